@@ -1,0 +1,92 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle checks.
+
+This module draws random numbers and assembles the workload parameters; it holds
+none of the orthogonalisation, Krylov or operator arithmetic.  All generators
+use NumPy's PCG64 (``numpy.random.default_rng(seed)``).
+
+Workloads (the paper's experiments run on synthetic tall-skinny matrices and on
+convection-diffusion operators; the sizes below are the project's workloads):
+
+* ``tall_skinny``: B = G diag(logspace(0, -e, n)) V with G ~ N(0,1) (m x n) and V
+  Haar-orthogonal (QR of an n x n N(0,1) matrix, columns sign-fixed), so that
+  kappa(B) ~ 10^e.  Returned column-major.
+* ``cd2d`` / ``cd3d``: grid and coefficients of -D Lap + v.grad on the unit
+  square / cube (Dirichlet, central differences) plus seeded vectors.
+* ``ks_instances``: a family of 2-D convection-diffusion instances with
+  n_x ~ U[48, 256] and v ~ U(0, 50)^2.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.default_rng(seed)
+
+
+def haar_orthogonal(n: int, seed: int) -> np.ndarray:
+    """Haar-distributed orthogonal n x n matrix (QR of a Gaussian, columns sign-fixed)."""
+    X = rng(seed).standard_normal((n, n))
+    Qh, Rh = np.linalg.qr(X)
+    return Qh * np.sign(np.diag(Rh))[None, :]
+
+
+def tall_skinny(m: int, n: int, cond_exp: float = 8.0, seed_g: int = 1, seed_v: int = 2,
+                dtype=np.float64) -> np.ndarray:
+    """B = G diag(logspace(0, -cond_exp, n)) V, column-major (Fortran order), m x n."""
+    Gt = rng(seed_g).standard_normal((n, m))           # G^T, row-major n x m
+    V = haar_orthogonal(n, seed_v)
+    M = np.logspace(0.0, -cond_exp, n)[:, None] * V    # diag(s) V
+    B = (M.T @ Gt).T                                    # = G M, Fortran-ordered m x n
+    return B.astype(dtype, copy=False)
+
+
+def normal_vector(m: int, seed: int) -> np.ndarray:
+    return rng(seed).standard_normal(m)
+
+
+def uniform_vector(m: int, seed: int) -> np.ndarray:
+    return rng(seed).uniform(0.0, 1.0, m)
+
+
+@dataclass(frozen=True)
+class CDProblem:
+    """-D Lap(u) + v.grad(u) on (0,1)^d, Dirichlet, h_i = 1/(n_i+1)."""
+    grid: tuple
+    D: float
+    vel: tuple
+
+    @property
+    def m(self) -> int:
+        return int(np.prod(self.grid))
+
+
+def cd2d(nx: int = 32, ny: int | None = None, D: float = 1.0, vel=(10.0, 10.0)) -> CDProblem:
+    return CDProblem((nx, nx if ny is None else ny), float(D), tuple(float(v) for v in vel))
+
+
+def cd3d(n: int = 128, D: float = 1.0, vel=(10.0, 10.0, 10.0)) -> CDProblem:
+    return CDProblem((n, n, n), float(D), tuple(float(v) for v in vel))
+
+
+def ks_instances(count: int, seed: int = 4, nmin: int = 48, nmax: int = 256, vmax: float = 50.0):
+    """Batched Krylov-Schur family: n_x ~ U{nmin..nmax} (square grids), v ~ U(0, vmax)^2."""
+    g = rng(seed)
+    nx = g.integers(nmin, nmax + 1, size=count)
+    vel = g.uniform(0.0, vmax, size=(count, 2))
+    return [CDProblem((int(n), int(n)), 1.0, (float(v[0]), float(v[1]))) for n, v in zip(nx, vel)]
+
+
+# Named workloads ------------------------------------------------------------------
+def config1():
+    """FP64 DCGS2 Arnoldi, 50 steps, 2-D convection-diffusion 32x32, v=(10,10), r0 ~ N(0,1) seed 0."""
+    prob = cd2d(32, vel=(10.0, 10.0))
+    return prob, normal_vector(prob.m, 0), 50
+
+
+def config3(n: int = 128):
+    """GMRES(50) on 3-D convection-diffusion n^3, v=(10,10,10), b ~ U(0,1) seed 3, rtol 1e-8."""
+    prob = cd3d(n, vel=(10.0, 10.0, 10.0))
+    return prob, uniform_vector(prob.m, 3)
