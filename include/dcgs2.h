@@ -1,0 +1,180 @@
+/*
+ * dcgs2.h -- C ABI of libdcgs2.so: the one-reduction DCGS2 Arnoldi-QR expansion
+ * on AMD Instinct MI355X (gfx950), and the GMRES and Krylov-Schur drivers on top.
+ *
+ * Method: Bielich, Langou, Thomas, Swirydowicz, Yamazaki, Boman, "Low-Synch
+ * Gram-Schmidt with Delayed Reorthogonalization for Krylov Solvers"
+ * (arXiv 2104.01253).  Section/equation/algorithm labels below are the paper's.
+ *
+ * Conventions for every entry point
+ *   - Matrices are column-major (FP64).  "device" pointers are HIP device
+ *     memory on the context's device; "host" pointers are ordinary host memory.
+ *   - The caller owns every array passed in; the library never frees caller
+ *     memory and keeps no pointer to it after the call returns.
+ *   - Work is enqueued on the context's stream; every call returns after that
+ *     stream has synchronised.  Use one context per host thread.
+ *   - Arguments are validated before any device work is enqueued: a violation
+ *     returns DCGS2_EINVAL and leaves every output untouched.
+ *   - Negative return codes are errors; positive codes are numerical outcomes
+ *     whose valid prefix stays usable (see dcgs2_stats.breakdown_step).
+ */
+#ifndef DCGS2_H
+#define DCGS2_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum {
+  DCGS2_OK = 0,
+  DCGS2_EINVAL = -1,        /* invalid argument (nothing was done)               */
+  DCGS2_EDEVICE = -2,       /* a HIP runtime call failed                          */
+  DCGS2_ENOMEM = -3,        /* device workspace allocation failed                 */
+  DCGS2_BREAKDOWN = 1,      /* alpha_{j} <= eta * rho_j: invariant subspace/rank
+                               deficiency; the first k columns are valid          */
+  DCGS2_NOT_CONVERGED = 2,  /* iteration budget exhausted; best result returned   */
+  DCGS2_NONFINITE = 3       /* NaN/Inf in a reduced scalar; valid prefix returned  */
+};
+
+/* Largest basis size (columns) accepted by the expansion entry points. */
+#define DCGS2_MAX_N 1024
+
+/* Opaque context: binds a device and a HIP stream, owns the device workspace
+ * (reduction partials, coefficient buffers, arrival counters, the Hessenberg
+ * matrix, internal Krylov bases).  The workspace grows on demand and is freed
+ * by dcgs2_destroy. */
+typedef struct dcgs2_ctx_s* dcgs2_ctx;
+
+/* Sparse operator A (m x m).  All array pointers are DEVICE pointers.
+ *  CSR:      rowptr[m+1], colind[nnz] (int32, column indices in [0, m)), val[nnz].
+ *  STENCIL5: 2-D grid nx*ny (m = nx*ny), lexicographic with x fastest; row of
+ *            point (ix,iy): c0*u + cxm*u(ix-1) + cxp*u(ix+1) + cym*u(iy-1) + cyp*u(iy+1),
+ *            neighbours outside the grid are zero (homogeneous Dirichlet).
+ *  STENCIL7: 3-D grid nx*ny*nz likewise, plus czm*u(iz-1) + czp*u(iz+1).
+ * This is the central-difference convection-diffusion operator of Sec. 6.1
+ * (Manteuffel's matrix) and of the workloads. */
+typedef enum { DCGS2_OP_CSR = 0, DCGS2_OP_STENCIL5 = 1, DCGS2_OP_STENCIL7 = 2 } dcgs2_op_kind;
+
+typedef struct {
+  int32_t kind;                 /* dcgs2_op_kind                                   */
+  int64_t m;                    /* rows = columns                                  */
+  const int32_t* rowptr;        /* CSR only (device)                               */
+  const int32_t* colind;        /* CSR only (device)                               */
+  const double* val;            /* CSR only (device)                               */
+  int64_t nnz;                  /* CSR only                                        */
+  int32_t nx, ny, nz;           /* stencils: grid extents (nz = 1 for STENCIL5)    */
+  double c0, cxm, cxp, cym, cyp, czm, czp;   /* stencil coefficients               */
+} dcgs2_op;
+
+/* Per-call statistics. */
+typedef struct {
+  int32_t reductions;       /* global reductions performed (one per step, Tab. full) */
+  int32_t pyth_fallbacks;   /* steps whose Pythagorean norm was replaced by an
+                               explicit norm (one extra reduction each)              */
+  int32_t breakdown_step;   /* number k of valid columns when status != OK, else -1  */
+  int32_t kernels;          /* kernel launches enqueued                             */
+} dcgs2_stats;
+
+typedef struct {
+  int32_t iters;            /* Arnoldi steps (matvecs) over all cycles              */
+  int32_t cycles;           /* restart cycles                                       */
+  int32_t status;           /* same as the return value                              */
+  int32_t pad;
+  double relres_true;       /* ||b - A x|| / ||b|| at return                          */
+  double relres_est;        /* least-squares residual estimate of the last cycle    */
+  dcgs2_stats st;
+} dcgs2_gmres_info;
+
+typedef struct {
+  int32_t restarts;         /* Krylov-Schur truncations performed                   */
+  int32_t nconv;            /* size of the converged leading Schur block (>= nev)   */
+  int32_t matvecs;
+  int32_t status;
+  double resid;             /* ||b_{1:nconv}|| / min |theta| of the last test        */
+  dcgs2_stats st;
+} dcgs2_ks_info;
+
+/* Create a context on `device` (HIP ordinal).  `hip_stream` is a hipStream_t to
+ * enqueue on, or NULL for a stream the context creates and owns.
+ * Returns DCGS2_OK, DCGS2_EINVAL (out == NULL or bad device), DCGS2_EDEVICE. */
+int dcgs2_create(dcgs2_ctx* out, int device, void* hip_stream);
+
+/* Free the workspace (and the owned stream).  NULL is accepted. */
+int dcgs2_destroy(dcgs2_ctx ctx);
+
+/* Tolerances of the two readings where the paper is silent (defaults 1e-8, 1e-12):
+ *  tau -- Pythagorean guard: the delayed norm alpha^2 = beta - C^T C (Sec. 3) is
+ *         used only when beta - C^T C > tau * beta; otherwise alpha is recomputed
+ *         explicitly as ||w - Q C|| with one extra reduction (tau >= 1 forces it).
+ *  eta -- breakdown: alpha_j <= eta * rho_j, rho_j the norm of the vector that w_j
+ *         was projected from.
+ * Returns DCGS2_EINVAL unless 0 <= tau and 0 <= eta < 1. */
+int dcgs2_set_tolerances(dcgs2_ctx ctx, double tau, double eta);
+
+/* Left-looking DCGS2 QR, Alg. qr (Sec. 3): B = Q R with one global reduction per
+ * column, the last column finished by CGS2 (two reductions; end of Sec. 3).
+ *  m, n    : 1 <= n <= min(m, DCGS2_MAX_N).
+ *  B       : device, m x n, leading dimension ldb >= m; read only.
+ *  Q       : device, m x n output, ldq >= m; must not overlap B.
+ *  R_host  : host, n x n output (upper triangular, R_jj > 0), ldr >= n.
+ *  st      : host, optional (NULL allowed).
+ * Returns DCGS2_OK, DCGS2_BREAKDOWN (first st->breakdown_step columns of Q and R
+ * valid), DCGS2_NONFINITE, or an error. */
+int dcgs2_qr(dcgs2_ctx ctx, int64_t m, int32_t n, const double* B, int64_t ldb,
+             double* Q, int64_t ldq, double* R_host, int32_t ldr, dcgs2_stats* st);
+
+/* DCGS2 Arnoldi-QR expansion, Alg. arnoldi (Sec. 4): n steps from r0, giving
+ * A Q_{1:n} = Q_{1:n+1} H_{1:n+1,1:n} (eq. eq:arnoldi) with q_1 = r0/||r0||.
+ * Each step is one matvec A w_{j-1} on the unnormalised vector and one global
+ * reduction; H column j-2 is completed at step j through the buffer K
+ * (eqs. (41)-(52)); column n is finished by CGS2 (two reductions).
+ *  A       : host struct describing a device operator.
+ *  r0      : device, m; read only.
+ *  Q       : device, m x (n+1) output, ldq >= m.
+ *  H_host  : host, (n+1) x n output, ldh >= n+1.
+ * 1 <= n <= min(m-1, DCGS2_MAX_N).  Returns as dcgs2_qr; on DCGS2_BREAKDOWN the
+ * first k = st->breakdown_step columns of Q and H_{1:k+1,1:k} are valid. */
+int dcgs2_arnoldi(dcgs2_ctx ctx, const dcgs2_op* A, const double* r0, int32_t n,
+                  double* Q, int64_t ldq, double* H_host, int32_t ldh, dcgs2_stats* st);
+
+/* Restarted GMRES(restart) (Sec. 1, Saad & Schultz) on the DCGS2 basis.
+ *  b       : device, m; read only.
+ *  x       : device, m; in: initial guess x0, out: solution.
+ * Stops when ||b - A x|| / ||b|| <= rtol (true residual) or after max_iters
+ * Arnoldi steps.  Givens rotations are applied on the device as each Hessenberg
+ * column completes; a cycle ends early once the least-squares residual estimate
+ * reaches rtol*||b||.  b = 0 gives x = 0 and DCGS2_OK.
+ * 1 <= restart <= min(m-1, DCGS2_MAX_N), rtol > 0, max_iters >= 0.
+ * Returns DCGS2_OK, DCGS2_NOT_CONVERGED, DCGS2_NONFINITE or an error. */
+int gmres_solve(dcgs2_ctx ctx, const dcgs2_op* A, const double* b, double* x,
+                int32_t restart, double rtol, int32_t max_iters, dcgs2_gmres_info* info);
+
+/* Krylov-Schur (Sec. 6.1, Stewart) for the nev largest-magnitude eigenvalues.
+ * Expands to ncv columns with DCGS2, computes a real Schur form of H on the host
+ * with the largest-magnitude Ritz values leading, accepts when
+ * ||b_{1:nev}|| <= tol * min|theta| (b = h_{p+1,p} times the last row of the
+ * Schur vectors), else keeps `keep` Schur vectors (a cut never splits Ritz values
+ * of equal magnitude) and resumes the expansion.
+ *  v0      : device, m start vector; read only.
+ *  eig_re_host, eig_im_host : host, nev outputs, by decreasing magnitude.
+ * 1 <= nev < keep < ncv <= min(m-1, DCGS2_MAX_N), tol > 0, max_restarts >= 0.
+ * Returns DCGS2_OK, DCGS2_NOT_CONVERGED (current Ritz values returned),
+ * DCGS2_BREAKDOWN, DCGS2_NONFINITE or an error. */
+int krylov_schur_eigs(dcgs2_ctx ctx, const dcgs2_op* A, int32_t nev, int32_t ncv, int32_t keep,
+                      double tol, int32_t max_restarts, const double* v0,
+                      double* eig_re_host, double* eig_im_host, dcgs2_ks_info* info);
+
+/* y = A x (device vectors of length A->m).  The matvec of step a1; exported so
+ * the operator can be checked on its own. */
+int dcgs2_apply(dcgs2_ctx ctx, const dcgs2_op* A, const double* x, double* y);
+
+/* Static description of a status code. */
+const char* dcgs2_status_str(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DCGS2_H */

@@ -1,0 +1,286 @@
+"""Thin ctypes binding of libdcgs2.so (argument marshalling only).
+
+Every step of the expansion runs in the HIP library; this module only turns
+torch device tensors into pointers, sizes and the context's stream, and the
+library's status codes into Python values.  Column-major matrices are torch
+tensors of shape (m, ncols) with stride (1, ld) -- see ``colmajor_empty``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int, c_int32, c_int64, c_void_p
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdcgs2.so")
+
+OK, EINVAL, EDEVICE, ENOMEM = 0, -1, -2, -3
+BREAKDOWN, NOT_CONVERGED, NONFINITE = 1, 2, 3
+OP_CSR, OP_STENCIL5, OP_STENCIL7 = 0, 1, 2
+MAX_N = 1024
+
+EXPORTS = ("dcgs2_create", "dcgs2_destroy", "dcgs2_set_tolerances", "dcgs2_qr", "dcgs2_arnoldi",
+           "gmres_solve", "krylov_schur_eigs", "dcgs2_apply", "dcgs2_status_str")
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("reductions", c_int32), ("pyth_fallbacks", c_int32),
+                ("breakdown_step", c_int32), ("kernels", c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Op(ctypes.Structure):
+    _fields_ = [("kind", c_int32), ("m", c_int64), ("rowptr", c_void_p), ("colind", c_void_p),
+                ("val", c_void_p), ("nnz", c_int64), ("nx", c_int32), ("ny", c_int32),
+                ("nz", c_int32), ("c0", c_double), ("cxm", c_double), ("cxp", c_double),
+                ("cym", c_double), ("cyp", c_double), ("czm", c_double), ("czp", c_double)]
+
+
+class GmresInfo(ctypes.Structure):
+    _fields_ = [("iters", c_int32), ("cycles", c_int32), ("status", c_int32), ("pad", c_int32),
+                ("relres_true", c_double), ("relres_est", c_double), ("st", Stats)]
+
+
+class KsInfo(ctypes.Structure):
+    _fields_ = [("restarts", c_int32), ("nconv", c_int32), ("matvecs", c_int32),
+                ("status", c_int32), ("resid", c_double), ("st", Stats)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libdcgs2.so; raises if it is not built (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run `python -m paper_2104_01253_amd.build`")
+    lib = ctypes.CDLL(path)
+    lib.dcgs2_create.argtypes = [POINTER(c_void_p), c_int, c_void_p]
+    lib.dcgs2_destroy.argtypes = [c_void_p]
+    lib.dcgs2_set_tolerances.argtypes = [c_void_p, c_double, c_double]
+    lib.dcgs2_qr.argtypes = [c_void_p, c_int64, c_int32, c_void_p, c_int64, c_void_p, c_int64,
+                             c_void_p, c_int32, POINTER(Stats)]
+    lib.dcgs2_arnoldi.argtypes = [c_void_p, POINTER(Op), c_void_p, c_int32, c_void_p, c_int64,
+                                  c_void_p, c_int32, POINTER(Stats)]
+    lib.gmres_solve.argtypes = [c_void_p, POINTER(Op), c_void_p, c_void_p, c_int32, c_double,
+                                c_int32, POINTER(GmresInfo)]
+    lib.krylov_schur_eigs.argtypes = [c_void_p, POINTER(Op), c_int32, c_int32, c_int32, c_double,
+                                      c_int32, c_void_p, c_void_p, c_void_p, POINTER(KsInfo)]
+    lib.dcgs2_apply.argtypes = [c_void_p, POINTER(Op), c_void_p, c_void_p]
+    lib.dcgs2_status_str.argtypes = [c_int]
+    lib.dcgs2_status_str.restype = ctypes.c_char_p
+    for name in ("dcgs2_create", "dcgs2_destroy", "dcgs2_set_tolerances", "dcgs2_qr",
+                 "dcgs2_arnoldi", "gmres_solve", "krylov_schur_eigs", "dcgs2_apply"):
+        getattr(lib, name).restype = c_int
+    _lib = lib
+    return lib
+
+
+def status_str(code: int) -> str:
+    return load().dcgs2_status_str(code).decode()
+
+
+class DCGS2Error(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {status_str(code)} ({code})")
+        self.code = code
+
+
+# ---- tensors ----------------------------------------------------------------------
+def colmajor_empty(m: int, ncols: int, ld: int | None = None, device="cuda", dtype=None):
+    """Uninitialised column-major m x ncols device matrix with leading dimension ld."""
+    import torch
+    ld = ((m + 63) // 64) * 64 if ld is None else ld
+    buf = torch.empty((ncols, ld), dtype=dtype or torch.float64, device=device)
+    return buf.t()[:m]
+
+
+def colmajor_from_numpy(A: np.ndarray, device="cuda", ld: int | None = None):
+    import torch
+    m, n = A.shape
+    out = colmajor_empty(m, n, ld, device)
+    out.copy_(torch.from_numpy(np.ascontiguousarray(A)).to(device))
+    return out
+
+
+def _colmajor_args(T, name):
+    if T.dim() != 2 or T.dtype != _f64() or not T.is_cuda:
+        raise ValueError(f"{name}: expected a 2-D float64 CUDA tensor")
+    if T.stride(0) != 1:
+        raise ValueError(f"{name}: expected column-major layout (stride(0) == 1)")
+    ld = T.stride(1) if T.shape[1] > 1 else max(T.shape[0], 1)
+    return T.data_ptr(), ld
+
+
+def _vec_ptr(t, name, m=None):
+    if t.dim() != 1 or t.dtype != _f64() or not t.is_cuda or t.stride(0) != 1:
+        raise ValueError(f"{name}: expected a contiguous 1-D float64 CUDA tensor")
+    if m is not None and t.numel() != m:
+        raise ValueError(f"{name}: expected length {m}")
+    return t.data_ptr()
+
+
+def _f64():
+    import torch
+    return torch.float64
+
+
+# ---- operators --------------------------------------------------------------------
+def stencil_coefficients(grid, D=1.0, vel=None, h=None):
+    """Central-difference coefficients of -D Lap(u) + v.grad(u) (Dirichlet, h = 1/(n+1))."""
+    d = len(grid)
+    vel = (0.0,) * d if vel is None else tuple(vel)
+    if h is None:
+        hs = tuple(1.0 / (n + 1) for n in grid)
+    else:
+        hs = (float(h),) * d if np.isscalar(h) else tuple(h)
+    c0 = 0.0
+    lo, hi = [], []
+    for n, v, hh in zip(grid, vel, hs):
+        dif = D / (hh * hh)
+        adv = v / (2.0 * hh)
+        c0 += 2.0 * dif
+        lo.append(-dif - adv)    # coefficient of the neighbour at i - 1 along this axis
+        hi.append(-dif + adv)    # coefficient of the neighbour at i + 1
+    while len(lo) < 3:
+        lo.append(0.0)
+        hi.append(0.0)
+    return c0, lo, hi
+
+
+def stencil_op(grid, D=1.0, vel=None, h=None) -> Op:
+    grid = tuple(int(g) for g in grid)
+    c0, lo, hi = stencil_coefficients(grid, D, vel, h)
+    op = Op()
+    op.kind = OP_STENCIL5 if len(grid) == 2 else OP_STENCIL7
+    if len(grid) == 1:
+        grid = (grid[0], 1)
+        op.kind = OP_STENCIL5
+    op.m = int(np.prod(grid))
+    op.nx, op.ny = grid[0], grid[1]
+    op.nz = grid[2] if len(grid) == 3 else 1
+    op.c0 = c0
+    op.cxm, op.cxp, op.cym, op.cyp, op.czm, op.czp = lo[0], hi[0], lo[1], hi[1], lo[2], hi[2]
+    return op
+
+
+def csr_op(rowptr, colind, val) -> Op:
+    """rowptr/colind: int32 CUDA tensors, val: float64 CUDA tensor (kept alive by the caller)."""
+    import torch
+    if rowptr.dtype != torch.int32 or colind.dtype != torch.int32 or val.dtype != torch.float64:
+        raise ValueError("csr_op: rowptr/colind int32, val float64")
+    op = Op()
+    op.kind = OP_CSR
+    op.m = rowptr.numel() - 1
+    op.rowptr, op.colind, op.val = rowptr.data_ptr(), colind.data_ptr(), val.data_ptr()
+    op.nnz = val.numel()
+    return op
+
+
+# ---- context ----------------------------------------------------------------------
+class Context:
+    """A libdcgs2 context bound to one device and one HIP stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        lib = load()
+        handle = c_void_p()
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        rc = lib.dcgs2_create(ctypes.byref(handle), device, c_void_p(stream))
+        if rc != OK:
+            raise DCGS2Error(rc, "dcgs2_create")
+        self._h = handle
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.dcgs2_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_tolerances(self, tau=1e-8, eta=1e-12):
+        rc = self._lib.dcgs2_set_tolerances(self._h, tau, eta)
+        if rc != OK:
+            raise DCGS2Error(rc, "dcgs2_set_tolerances")
+
+    # -- entry points -------------------------------------------------------------
+    def qr(self, B, Q):
+        """DCGS2 QR of column-major B into Q; returns (R (numpy n x n), status, stats)."""
+        m, n = B.shape
+        pb, ldb = _colmajor_args(B, "B")
+        pq, ldq = _colmajor_args(Q, "Q")
+        if Q.shape != (m, n):
+            raise ValueError("Q must have B's shape")
+        R = np.zeros((n, n), order="F")
+        st = Stats()
+        rc = self._lib.dcgs2_qr(self._h, m, n, pb, ldb, pq, ldq,
+                                R.ctypes.data_as(c_void_p), n, ctypes.byref(st))
+        if rc < 0:
+            raise DCGS2Error(rc, "dcgs2_qr")
+        return R, rc, st.as_dict()
+
+    def arnoldi(self, op: Op, r0, n: int, Q):
+        """n DCGS2 Arnoldi steps from r0 into Q (m x (n+1)); returns (H, status, stats)."""
+        pr = _vec_ptr(r0, "r0", op.m)
+        pq, ldq = _colmajor_args(Q, "Q")
+        if Q.shape[0] != op.m or Q.shape[1] < n + 1:
+            raise ValueError("Q must be m x (n+1)")
+        H = np.zeros((n + 1, n), order="F")
+        st = Stats()
+        rc = self._lib.dcgs2_arnoldi(self._h, ctypes.byref(op), pr, n, pq, ldq,
+                                     H.ctypes.data_as(c_void_p), n + 1, ctypes.byref(st))
+        if rc < 0:
+            raise DCGS2Error(rc, "dcgs2_arnoldi")
+        return H, rc, st.as_dict()
+
+    def gmres(self, op: Op, b, x, restart=50, rtol=1e-8, max_iters=100000):
+        """Restarted GMRES(restart); x holds x0 on entry and the solution on return."""
+        pb = _vec_ptr(b, "b", op.m)
+        px = _vec_ptr(x, "x", op.m)
+        info = GmresInfo()
+        rc = self._lib.gmres_solve(self._h, ctypes.byref(op), pb, px, restart, rtol, max_iters,
+                                   ctypes.byref(info))
+        if rc < 0:
+            raise DCGS2Error(rc, "gmres_solve")
+        out = {k: getattr(info, k) for k, _ in GmresInfo._fields_ if k not in ("st", "pad")}
+        out["stats"] = info.st.as_dict()
+        return rc, out
+
+    def krylov_schur(self, op: Op, v0, nev=10, ncv=60, keep=20, tol=1e-8, max_restarts=500):
+        """Largest-magnitude eigenvalues; returns (eigs complex numpy, status, info)."""
+        pv = _vec_ptr(v0, "v0", op.m)
+        re = np.zeros(nev)
+        im = np.zeros(nev)
+        info = KsInfo()
+        rc = self._lib.krylov_schur_eigs(self._h, ctypes.byref(op), nev, ncv, keep, tol,
+                                         max_restarts, pv, re.ctypes.data_as(c_void_p),
+                                         im.ctypes.data_as(c_void_p), ctypes.byref(info))
+        if rc < 0:
+            raise DCGS2Error(rc, "krylov_schur_eigs")
+        out = {k: getattr(info, k) for k, _ in KsInfo._fields_ if k != "st"}
+        out["stats"] = info.st.as_dict()
+        return re + 1j * im, rc, out
+
+    def apply(self, op: Op, x, y):
+        rc = self._lib.dcgs2_apply(self._h, ctypes.byref(op), _vec_ptr(x, "x", op.m),
+                                   _vec_ptr(y, "y", op.m))
+        if rc != OK:
+            raise DCGS2Error(rc, "dcgs2_apply")

@@ -1,0 +1,585 @@
+// Host driver of libdcgs2.so: argument validation, device workspace, the step
+// schedule of the DCGS2 expansion (Alg. qr / Alg. arnoldi of arXiv 2104.01253),
+// and the GMRES and Krylov-Schur drivers built on it.
+//
+// Schedule of one expansion (all launches are asynchronous on the context
+// stream; the host synchronises once at the end, or once per restart cycle):
+//   step j = 2..n+1 : [A w_{j-1} -> v]  reduce(j) + finalise  update(j)
+//   last column     : reduce(c = Q^T w)  project + norm  scale    (CGS2 finish)
+// Every kernel first reads the device control block and returns at once unless
+// the expansion is still RUNNING, so a breakdown, a non-finite value, GMRES
+// convergence or a Pythagorean-guard failure stops the remaining launches
+// without a host round trip.  The guard failure is then resolved here: the
+// explicit-norm fallback of that step is enqueued and the schedule resumes.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+using namespace dcgs2;
+
+namespace {
+
+constexpr int LDC = DCGS2_MAX_N + 2;              // coef block stride
+constexpr int LDP = 2 * (DCGS2_MAX_N + 2) + 8;    // partials stride
+constexpr int LDH_MAX = DCGS2_MAX_N + 1;          // square small-matrix buffers
+
+}  // namespace
+
+struct dcgs2_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool ready = false;
+  double tau = 1e-8, eta = 1e-12;
+  int64_t cap_m = 0;
+  int64_t cap_qa = 0, cap_qb = 0;
+  double *w = nullptr, *v = nullptr, *r = nullptr;
+  double *P1 = nullptr, *P2 = nullptr;
+  unsigned* cnt = nullptr;
+  double *coef = nullptr, *pend = nullptr;
+  double *H = nullptr, *K = nullptr, *Rg = nullptr, *R = nullptr, *Z = nullptr;
+  double *Sprev = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
+  double *Qa = nullptr, *Qb = nullptr;
+  Ctrl* ctrl = nullptr;
+  Ctrl* ctrl_host = nullptr;       // pinned
+  int kernels = 0;
+};
+
+namespace {
+
+#define CK(call)                                   \
+  do {                                             \
+    hipError_t e_ = (call);                        \
+    if (e_ != hipSuccess) return DCGS2_EDEVICE;    \
+  } while (0)
+
+#define CKL(call)                                  \
+  do {                                             \
+    hipError_t e_ = (call);                        \
+    if (e_ != hipSuccess) return DCGS2_EDEVICE;    \
+    ++c->kernels;                                  \
+  } while (0)
+
+int dalloc(void** p, size_t bytes) {
+  if (hipMalloc(p, bytes) != hipSuccess) { *p = nullptr; return DCGS2_ENOMEM; }
+  return DCGS2_OK;
+}
+
+void dfree(void* p) { if (p) (void)hipFree(p); }
+
+// First device use of a context: bind the device, create the stream, allocate
+// the size-independent workspace.
+int ctx_ready(dcgs2_ctx c) {
+  if (c->ready) {
+    CK(hipSetDevice(c->device));
+    return DCGS2_OK;
+  }
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || c->device < 0 || c->device >= count)
+    return DCGS2_EDEVICE;
+  CK(hipSetDevice(c->device));
+  if (!c->stream) {
+    CK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+  }
+  int rc;
+  if ((rc = dalloc((void**)&c->P1, sizeof(double) * (size_t)REDUCE_GMAX * LDP))) return rc;
+  if ((rc = dalloc((void**)&c->P2, sizeof(double) * (size_t)REDUCE_GSMAX * LDP))) return rc;
+  if ((rc = dalloc((void**)&c->cnt, sizeof(unsigned) * 64))) return rc;
+  if ((rc = dalloc((void**)&c->coef, sizeof(double) * (2 * LDC + 8)))) return rc;
+  if ((rc = dalloc((void**)&c->pend, sizeof(double) * (2 * LDC + 8)))) return rc;
+  const size_t sq = sizeof(double) * (size_t)LDH_MAX * (LDH_MAX + 1);
+  if ((rc = dalloc((void**)&c->H, sq))) return rc;
+  if ((rc = dalloc((void**)&c->K, sq))) return rc;
+  if ((rc = dalloc((void**)&c->Rg, sq))) return rc;
+  if ((rc = dalloc((void**)&c->R, sq))) return rc;
+  if ((rc = dalloc((void**)&c->Z, sq))) return rc;
+  if ((rc = dalloc((void**)&c->Sprev, sizeof(double) * (LDH_MAX + 2)))) return rc;
+  if ((rc = dalloc((void**)&c->cs, sizeof(double) * (LDH_MAX + 2)))) return rc;
+  if ((rc = dalloc((void**)&c->sn, sizeof(double) * (LDH_MAX + 2)))) return rc;
+  if ((rc = dalloc((void**)&c->g, sizeof(double) * (LDH_MAX + 2)))) return rc;
+  if ((rc = dalloc((void**)&c->ctrl, sizeof(Ctrl)))) return rc;
+  if (hipHostMalloc((void**)&c->ctrl_host, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess)
+    return DCGS2_ENOMEM;
+  CK(launch_zero_u32(c->cnt, 64, c->stream));
+  c->ready = true;
+  return DCGS2_OK;
+}
+
+// Length-m work vectors (w, v, r), grown on demand.
+int ensure_vectors(dcgs2_ctx c, int64_t m) {
+  if (m <= c->cap_m) return DCGS2_OK;
+  CK(hipStreamSynchronize(c->stream));
+  dfree(c->w); dfree(c->v); dfree(c->r);
+  c->w = c->v = c->r = nullptr;
+  c->cap_m = 0;
+  const int64_t mm = (m + 63) / 64 * 64;
+  int rc;
+  if ((rc = dalloc((void**)&c->w, sizeof(double) * mm))) return rc;
+  if ((rc = dalloc((void**)&c->v, sizeof(double) * mm))) return rc;
+  if ((rc = dalloc((void**)&c->r, sizeof(double) * mm))) return rc;
+  c->cap_m = mm;
+  return DCGS2_OK;
+}
+
+int ensure_basis(dcgs2_ctx c, double** buf, int64_t* cap, int64_t elems) {
+  if (elems <= *cap) return DCGS2_OK;
+  CK(hipStreamSynchronize(c->stream));
+  dfree(*buf);
+  *buf = nullptr;
+  *cap = 0;
+  int rc = dalloc((void**)buf, sizeof(double) * (size_t)elems);
+  if (rc) return rc;
+  *cap = elems;
+  return DCGS2_OK;
+}
+
+int64_t pad_ld(int64_t m) { return (m + 63) / 64 * 64; }
+
+int read_ctrl(dcgs2_ctx c, Ctrl* out) {
+  CK(hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
+  CK(hipStreamSynchronize(c->stream));
+  *out = *c->ctrl_host;
+  return DCGS2_OK;
+}
+
+int status_of(const Ctrl& s) {
+  switch (s.state) {
+    case ST_BREAKDOWN: return DCGS2_BREAKDOWN;
+    case ST_NONFINITE: return DCGS2_NONFINITE;
+    default: return DCGS2_OK;
+  }
+}
+
+bool valid_op(const dcgs2_op* A) {
+  if (!A || A->m < 2) return false;
+  switch (A->kind) {
+    case DCGS2_OP_CSR:
+      return A->rowptr && A->colind && A->val && A->nnz >= 0 && A->m < INT32_MAX;
+    case DCGS2_OP_STENCIL5:
+      return A->nx >= 1 && A->ny >= 1 && (int64_t)A->nx * A->ny == A->m && A->m < INT32_MAX;
+    case DCGS2_OP_STENCIL7:
+      return A->nx >= 1 && A->ny >= 1 && A->nz >= 1 &&
+             (int64_t)A->nx * A->ny * A->nz == A->m && A->m < INT32_MAX;
+    default:
+      return false;
+  }
+}
+
+OpDev to_dev(const dcgs2_op* A) {
+  OpDev o;
+  o.kind = A->kind;
+  o.m = A->m;
+  o.rowptr = A->rowptr; o.colind = A->colind; o.val = A->val;
+  o.nx = A->nx; o.ny = A->ny; o.nz = A->kind == DCGS2_OP_STENCIL7 ? A->nz : 1;
+  o.c0 = A->c0; o.cxm = A->cxm; o.cxp = A->cxp; o.cym = A->cym; o.cyp = A->cyp;
+  o.czm = A->czm; o.czp = A->czp;
+  return o;
+}
+
+// One expansion (QR or Arnoldi) over a basis Q.
+struct Expansion {
+  dcgs2_ctx c;
+  bool qr = false;
+  bool gmres = false;
+  int64_t m = 0;
+  double* Q = nullptr;
+  int64_t ldq = 0;
+  const double* B = nullptr;    // QR input columns
+  int64_t ldb = 0;
+  OpDev op{};                   // Arnoldi operator
+  int ldh = 0;                  // leading dimension of H/K/Rg (Arnoldi) or R (QR)
+  GridRed gr{};
+
+  FinArgs fin(int kind, int j, int J) const {
+    FinArgs f{};
+    f.kind = kind; f.qr = qr; f.j = j; f.J = J; f.gmres = gmres; f.ldc = LDC;
+    f.ctrl = c->ctrl; f.coef = c->coef; f.pend = c->pend;
+    f.H = c->H; f.K = c->K; f.ldh = ldh;
+    f.R = c->R; f.ldr = ldh; f.Sprev = c->Sprev;
+    f.Rg = c->Rg; f.cs = c->cs; f.sn = c->sn; f.g = c->g;
+    return f;
+  }
+  const double* ycol(int j) const { return qr ? B + (int64_t)(j - 1) * ldb : c->v; }
+
+  int enqueue_step(int j, int kind) {
+    const int J = j - 2;
+    hipStream_t s = c->stream;
+    if (!qr) CKL(launch_spmv(op, c->w, nullptr, c->v, c->ctrl, s));
+    CKL(launch_reduce(Q, ldq, J, c->w, ycol(j), m, gr, fin(kind, j, J), s));
+    CKL(launch_update(Q, ldq, J, c->w, ycol(j), m, c->coef, LDC, !qr, 0, c->ctrl, s));
+    return DCGS2_OK;
+  }
+  int enqueue_fallback(int j) {
+    const int J = j - 2;
+    hipStream_t s = c->stream;
+    CKL(launch_project_norm(Q, ldq, J, c->w, m, gr, fin(FIN_FALLBACK, j, J), s));
+    CKL(launch_update(Q, ldq, J, c->w, ycol(j), m, c->coef, LDC, !qr, 1, c->ctrl, s));
+    return DCGS2_OK;
+  }
+  // CGS2 finish of the last column: J final columns already in Q.
+  int enqueue_last(int J, int jvirt) {
+    hipStream_t s = c->stream;
+    CKL(launch_reduce(Q, ldq, J, c->w, nullptr, m, gr, fin(FIN_LAST1, jvirt, J), s));
+    CKL(launch_project_norm(Q, ldq, J, c->w, m, gr, fin(FIN_LAST2, jvirt, J), s));
+    CKL(launch_scale_col(Q, ldq, J, m, c->coef, LDC, c->ctrl, s));
+    return DCGS2_OK;
+  }
+  // Steps j_from..j_to (the first one of kind first_kind), then the last-column
+  // finish with J_last columns when J_last >= 0.  Resolves guard fallbacks.
+  int run(int j_from, int j_to, int first_kind, int J_last, Ctrl* out) {
+    int rc;
+    int j0 = j_from;
+    int kind0 = first_kind;
+    bool pending_fallback = false;
+    for (;;) {
+      if (pending_fallback) {
+        CKL(launch_set_state(c->ctrl, ST_RUNNING, c->stream));
+        if ((rc = enqueue_fallback(j0))) return rc;
+        ++j0;
+        kind0 = FIN_STEP;
+      }
+      for (int j = j0; j <= j_to; ++j) {
+        if ((rc = enqueue_step(j, j == j0 ? kind0 : FIN_STEP))) return rc;
+      }
+      if (J_last >= 0 && (rc = enqueue_last(J_last, j_to + 1))) return rc;
+      if ((rc = read_ctrl(c, out))) return rc;
+      if (out->state != ST_FALLBACK) return DCGS2_OK;
+      j0 = out->stop_step;
+      pending_fallback = true;
+    }
+  }
+};
+
+int setup_expansion(dcgs2_ctx c, Expansion& e, double thresh) {
+  e.c = c;
+  reduce_grid(e.m, &e.gr.G, &e.gr.GS, &e.gr.NG);
+  e.gr.P1 = c->P1;
+  e.gr.P2 = c->P2;
+  e.gr.cnt = c->cnt;
+  e.gr.ldp = LDP;
+  CK(launch_init_ctrl(c->ctrl, c->tau, c->eta, thresh, c->stream));
+  CK(launch_zero_u32(c->cnt, 64, c->stream));
+  c->kernels += 2;
+  return DCGS2_OK;
+}
+
+void fill_stats(dcgs2_stats* st, const Ctrl& s, int kernels, int status) {
+  if (!st) return;
+  st->reductions = s.reductions;
+  st->pyth_fallbacks = s.fallbacks;
+  st->breakdown_step = status == DCGS2_OK ? -1 : s.k;
+  st->kernels = kernels;
+}
+
+// Copy a device (rows x cols, ld ldd) block to host (ld ldh).
+int copy_to_host(dcgs2_ctx c, const double* dev, int ldd, int rows, int cols, double* host,
+                 int ldhost) {
+  std::vector<double> tmp((size_t)ldd * cols);
+  CK(hipMemcpyAsync(tmp.data(), dev, sizeof(double) * tmp.size(), hipMemcpyDeviceToHost,
+                    c->stream));
+  CK(hipStreamSynchronize(c->stream));
+  for (int jj = 0; jj < cols; ++jj)
+    for (int i = 0; i < rows; ++i) host[(size_t)jj * ldhost + i] = tmp[(size_t)jj * ldd + i];
+  return DCGS2_OK;
+}
+
+}  // namespace
+
+// =====================================================================================
+extern "C" {
+
+const char* dcgs2_status_str(int status) {
+  switch (status) {
+    case DCGS2_OK: return "ok";
+    case DCGS2_EINVAL: return "invalid argument";
+    case DCGS2_EDEVICE: return "HIP runtime error";
+    case DCGS2_ENOMEM: return "device allocation failed";
+    case DCGS2_BREAKDOWN: return "breakdown (invariant subspace or rank deficiency)";
+    case DCGS2_NOT_CONVERGED: return "not converged";
+    case DCGS2_NONFINITE: return "non-finite value in a reduction";
+    default: return "unknown status";
+  }
+}
+
+int dcgs2_create(dcgs2_ctx* out, int device, void* hip_stream) {
+  if (!out || device < 0) return DCGS2_EINVAL;
+  dcgs2_ctx c = new (std::nothrow) dcgs2_ctx_s();
+  if (!c) return DCGS2_ENOMEM;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  *out = c;
+  return DCGS2_OK;
+}
+
+int dcgs2_destroy(dcgs2_ctx c) {
+  if (!c) return DCGS2_OK;
+  if (c->ready) {
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    double* bufs[] = {c->w, c->v, c->r, c->P1, c->P2, c->coef, c->pend, c->H, c->K, c->Rg,
+                      c->R, c->Z, c->Sprev, c->cs, c->sn, c->g, c->Qa, c->Qb};
+    for (double* b : bufs) dfree(b);
+    dfree(c->cnt);
+    dfree(c->ctrl);
+    if (c->ctrl_host) (void)hipHostFree(c->ctrl_host);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  }
+  delete c;
+  return DCGS2_OK;
+}
+
+int dcgs2_set_tolerances(dcgs2_ctx c, double tau, double eta) {
+  if (!c || !(tau >= 0.0) || !(eta >= 0.0) || !(eta < 1.0)) return DCGS2_EINVAL;
+  c->tau = tau;
+  c->eta = eta;
+  return DCGS2_OK;
+}
+
+int dcgs2_apply(dcgs2_ctx c, const dcgs2_op* A, const double* x, double* y) {
+  if (!c || !valid_op(A) || !x || !y) return DCGS2_EINVAL;
+  int rc;
+  if ((rc = ctx_ready(c))) return rc;
+  CK(launch_spmv(to_dev(A), x, nullptr, y, nullptr, c->stream));
+  CK(hipStreamSynchronize(c->stream));
+  return DCGS2_OK;
+}
+
+int dcgs2_qr(dcgs2_ctx c, int64_t m, int32_t n, const double* B, int64_t ldb, double* Q,
+             int64_t ldq, double* R_host, int32_t ldr, dcgs2_stats* st) {
+  if (!c || m < 1 || n < 1 || n > DCGS2_MAX_N || (int64_t)n > m || !B || !Q || !R_host ||
+      ldb < m || ldq < m || ldr < n)
+    return DCGS2_EINVAL;
+  int rc;
+  if ((rc = ctx_ready(c))) return rc;
+  if ((rc = ensure_vectors(c, m))) return rc;
+  c->kernels = 0;
+  Expansion e;
+  e.qr = true;
+  e.m = m;
+  e.Q = Q; e.ldq = ldq; e.B = B; e.ldb = ldb;
+  e.ldh = n;
+  if ((rc = setup_expansion(c, e, 0.0))) return rc;
+  CKL(launch_fill(c->R, (int64_t)n * n, 0.0, c->stream));
+  CKL(launch_copy(c->w, B, m, c->stream));               // w_1 = a_1
+  Ctrl s{};
+  if ((rc = e.run(2, n, FIN_STEP, n - 1, &s))) return rc;
+  const int status = status_of(s);
+  if ((rc = copy_to_host(c, c->R, n, n, n, R_host, ldr))) return rc;
+  fill_stats(st, s, c->kernels, status);
+  return status;
+}
+
+int dcgs2_arnoldi(dcgs2_ctx c, const dcgs2_op* A, const double* r0, int32_t n, double* Q,
+                  int64_t ldq, double* H_host, int32_t ldh, dcgs2_stats* st) {
+  if (!c || !valid_op(A) || !r0 || !Q || !H_host || n < 1 || n > DCGS2_MAX_N ||
+      (int64_t)n >= A->m || ldq < A->m || ldh < n + 1)
+    return DCGS2_EINVAL;
+  int rc;
+  if ((rc = ctx_ready(c))) return rc;
+  const int64_t m = A->m;
+  if ((rc = ensure_vectors(c, m))) return rc;
+  c->kernels = 0;
+  Expansion e;
+  e.qr = false;
+  e.m = m;
+  e.Q = Q; e.ldq = ldq;
+  e.op = to_dev(A);
+  e.ldh = n + 1;
+  if ((rc = setup_expansion(c, e, 0.0))) return rc;
+  CKL(launch_fill(c->H, (int64_t)(n + 1) * (n + 1), 0.0, c->stream));
+  CKL(launch_fill(c->K, (int64_t)(n + 1) * (n + 1), 0.0, c->stream));
+  CKL(launch_copy(c->w, r0, m, c->stream));              // w_1 = r0 (unnormalised)
+  Ctrl s{};
+  if ((rc = e.run(2, n + 1, FIN_STEP, n, &s))) return rc;
+  const int status = status_of(s);
+  if ((rc = copy_to_host(c, c->H, n + 1, n + 1, n, H_host, ldh))) return rc;
+  fill_stats(st, s, c->kernels, status);
+  return status;
+}
+
+int gmres_solve(dcgs2_ctx c, const dcgs2_op* A, const double* b, double* x, int32_t restart,
+                double rtol, int32_t max_iters, dcgs2_gmres_info* info) {
+  if (!c || !valid_op(A) || !b || !x || restart < 1 || restart > DCGS2_MAX_N ||
+      (int64_t)restart >= A->m || !(rtol > 0.0) || max_iters < 0)
+    return DCGS2_EINVAL;
+  int rc;
+  if ((rc = ctx_ready(c))) return rc;
+  const int64_t m = A->m;
+  if ((rc = ensure_vectors(c, m))) return rc;
+  const int64_t ldq = pad_ld(m);
+  if ((rc = ensure_basis(c, &c->Qa, &c->cap_qa, ldq * (restart + 1)))) return rc;
+  c->kernels = 0;
+  dcgs2_gmres_info inf{};
+  Expansion e;
+  e.qr = false;
+  e.gmres = true;
+  e.m = m;
+  e.Q = c->Qa; e.ldq = ldq;
+  e.op = to_dev(A);
+  e.ldh = restart + 1;
+  // ||b||
+  if ((rc = setup_expansion(c, e, 0.0))) return rc;
+  Ctrl s{};
+  CKL(launch_reduce(nullptr, ldq, 0, b, nullptr, m, e.gr, e.fin(FIN_NORM, 0, 0), c->stream));
+  if ((rc = read_ctrl(c, &s))) return rc;
+  const double bnorm = std::sqrt(s.norm2);
+  int status = DCGS2_OK;
+  if (!std::isfinite(bnorm)) {
+    status = DCGS2_NONFINITE;
+  } else if (bnorm == 0.0) {
+    CKL(launch_fill(x, m, 0.0, c->stream));
+    CK(hipStreamSynchronize(c->stream));
+  } else {
+    std::vector<double> Rh, gh, y;
+    for (;;) {
+      // r = b - A x into w (w_1 of the cycle), then ||r||
+      if ((rc = setup_expansion(c, e, rtol * bnorm))) return rc;
+      CKL(launch_spmv(e.op, x, b, c->w, nullptr, c->stream));
+      CKL(launch_reduce(nullptr, ldq, 0, c->w, nullptr, m, e.gr, e.fin(FIN_NORM, 0, 0),
+                        c->stream));
+      if ((rc = read_ctrl(c, &s))) return rc;
+      inf.relres_true = std::sqrt(s.norm2) / bnorm;
+      if (!std::isfinite(inf.relres_true)) { status = DCGS2_NONFINITE; break; }
+      if (inf.relres_true <= rtol) { status = DCGS2_OK; break; }
+      if (inf.iters >= max_iters) { status = DCGS2_NOT_CONVERGED; break; }
+      const int nc = std::min(restart, max_iters - inf.iters);
+      inf.cycles += 1;
+      if ((rc = setup_expansion(c, e, rtol * bnorm))) return rc;
+      e.ldh = nc + 1;
+      CKL(launch_fill(c->H, (int64_t)(nc + 1) * (nc + 1), 0.0, c->stream));
+      CKL(launch_fill(c->K, (int64_t)(nc + 1) * (nc + 1), 0.0, c->stream));
+      CKL(launch_fill(c->g, nc + 2, 0.0, c->stream));
+      if ((rc = e.run(2, nc + 1, FIN_STEP, nc, &s))) return rc;
+      inf.st.reductions += s.reductions;
+      inf.st.pyth_fallbacks += s.fallbacks;
+      if (s.state == ST_NONFINITE) { status = DCGS2_NONFINITE; break; }
+      const int steps = (s.state == ST_RUNNING) ? nc : std::min(s.stop_step - 1, nc);
+      inf.iters += steps;
+      const int k = s.k;
+      inf.relres_est = s.resid_est / bnorm;
+      if (k <= 0) { status = DCGS2_BREAKDOWN; break; }
+      // y = R_k^{-1} g_{1:k} (back substitution on the rotated Hessenberg matrix)
+      const int ld = nc + 1;
+      Rh.assign((size_t)ld * k, 0.0);
+      gh.assign(k, 0.0);
+      CK(hipMemcpyAsync(Rh.data(), c->Rg, sizeof(double) * Rh.size(), hipMemcpyDeviceToHost,
+                        c->stream));
+      CK(hipMemcpyAsync(gh.data(), c->g, sizeof(double) * k, hipMemcpyDeviceToHost, c->stream));
+      CK(hipStreamSynchronize(c->stream));
+      y.assign(k, 0.0);
+      for (int i = k - 1; i >= 0; --i) {
+        double sum = gh[i];
+        for (int jj = i + 1; jj < k; ++jj) sum -= Rh[(size_t)jj * ld + i] * y[jj];
+        y[i] = sum / Rh[(size_t)i * ld + i];
+      }
+      CK(hipMemcpyAsync(c->Z, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, c->stream));
+      CKL(launch_tsgemm(c->Qa, ldq, k, c->Z, k, 1, x, m, m, 1, c->stream));
+    }
+  }
+  inf.status = status;
+  inf.st.kernels = c->kernels;
+  inf.st.breakdown_step = -1;
+  if (info) *info = inf;
+  return status;
+}
+
+int krylov_schur_eigs(dcgs2_ctx c, const dcgs2_op* A, int32_t nev, int32_t ncv, int32_t keep,
+                      double tol, int32_t max_restarts, const double* v0, double* eig_re,
+                      double* eig_im, dcgs2_ks_info* info) {
+  if (!c || !valid_op(A) || !v0 || !eig_re || !eig_im || nev < 1 || keep <= nev ||
+      ncv <= keep || ncv > DCGS2_MAX_N || (int64_t)ncv >= A->m || !(tol > 0.0) ||
+      max_restarts < 0)
+    return DCGS2_EINVAL;
+  int rc;
+  if ((rc = ctx_ready(c))) return rc;
+  const int64_t m = A->m;
+  if ((rc = ensure_vectors(c, m))) return rc;
+  const int64_t ldq = pad_ld(m);
+  const int p = ncv;
+  if ((rc = ensure_basis(c, &c->Qa, &c->cap_qa, ldq * (p + 1)))) return rc;
+  if ((rc = ensure_basis(c, &c->Qb, &c->cap_qb, ldq * (p + 1)))) return rc;
+  c->kernels = 0;
+  dcgs2_ks_info inf{};
+  Expansion e;
+  e.qr = false;
+  e.m = m;
+  e.Q = c->Qa; e.ldq = ldq;
+  e.op = to_dev(A);
+  e.ldh = p + 1;
+  const int ld = p + 1;
+  if ((rc = setup_expansion(c, e, 0.0))) return rc;
+  CKL(launch_fill(c->H, (int64_t)ld * ld, 0.0, c->stream));
+  CKL(launch_fill(c->K, (int64_t)ld * ld, 0.0, c->stream));
+  CKL(launch_copy(c->w, v0, m, c->stream));
+  Ctrl s{};
+  if ((rc = e.run(2, p + 1, FIN_STEP, p, &s))) return rc;
+  inf.matvecs = p;
+  inf.st.reductions = s.reductions;
+  inf.st.pyth_fallbacks = s.fallbacks;
+  int status = status_of(s);
+  std::vector<double> Hh((size_t)ld * p), T((size_t)p * p), Zm((size_t)p * p), Hn((size_t)ld * p);
+  std::vector<double> ere(p), eim(p);
+  const double CUT_GAP = 1e-8;
+  while (status == DCGS2_OK) {
+    if ((rc = copy_to_host(c, c->H, ld, ld, p, Hh.data(), ld))) return rc;
+    const double h = Hh[(size_t)(p - 1) * ld + p];
+    for (int jj = 0; jj < p; ++jj)
+      for (int i = 0; i < p; ++i) T[(size_t)jj * p + i] = Hh[(size_t)jj * ld + i];
+    if (real_schur(p, T.data(), p, Zm.data(), p) != 0) { status = DCGS2_NOT_CONVERGED; break; }
+    // convergence test on the leading nev (cut-adjusted) Schur vectors
+    const int kn = reorder_schur_by_magnitude(p, T.data(), p, Zm.data(), p, nev, CUT_GAP);
+    if (kn < 0) { status = DCGS2_NOT_CONVERGED; break; }
+    schur_eigenvalues(p, T.data(), p, ere.data(), eim.data());
+    double bn = 0.0, tmin = INFINITY;
+    for (int i = 0; i < kn; ++i) {
+      const double bi = h * Zm[(size_t)i * p + (p - 1)];
+      bn += bi * bi;
+      tmin = std::min(tmin, std::hypot(ere[i], eim[i]));
+    }
+    inf.resid = std::sqrt(bn) / tmin;
+    for (int i = 0; i < nev; ++i) { eig_re[i] = ere[i]; eig_im[i] = eim[i]; }
+    if (inf.resid <= tol) { inf.nconv = kn; break; }
+    if (inf.restarts >= max_restarts) { status = DCGS2_NOT_CONVERGED; break; }
+    // truncate to the leading `keep` Schur vectors
+    const int k = reorder_schur_by_magnitude(p, T.data(), p, Zm.data(), p, keep, CUT_GAP);
+    if (k < 0 || k >= p) { status = DCGS2_NOT_CONVERGED; break; }
+    CK(hipMemcpyAsync(c->Z, Zm.data(), sizeof(double) * (size_t)p * k, hipMemcpyHostToDevice,
+                      c->stream));
+    CKL(launch_tsgemm(c->Qa, ldq, p, c->Z, p, k, c->Qb, ldq, m, 0, c->stream));   // Q_p Z_k
+    CKL(launch_copy(c->Qb + (int64_t)k * ldq, c->Qa + (int64_t)p * ldq, m, c->stream));
+    CKL(launch_copy(c->w, c->Qa + (int64_t)p * ldq, m, c->stream));          // w = q_{k+1}
+    std::fill(Hn.begin(), Hn.end(), 0.0);
+    for (int jj = 0; jj < k; ++jj) {
+      for (int i = 0; i < k; ++i) Hn[(size_t)jj * ld + i] = T[(size_t)jj * p + i];
+      Hn[(size_t)jj * ld + k] = h * Zm[(size_t)jj * p + (p - 1)];
+    }
+    CKL(launch_fill(c->K, (int64_t)ld * ld, 0.0, c->stream));
+    CK(hipMemcpyAsync(c->H, Hn.data(), sizeof(double) * Hn.size(), hipMemcpyHostToDevice,
+                      c->stream));
+    std::swap(c->Qa, c->Qb);
+    std::swap(c->cap_qa, c->cap_qb);
+    e.Q = c->Qa;
+    inf.restarts += 1;
+    if ((rc = setup_expansion(c, e, 0.0))) return rc;
+    if ((rc = e.run(k + 2, p + 1, FIN_RESTART, p, &s))) return rc;
+    inf.matvecs += p - k;
+    inf.st.reductions += s.reductions;
+    inf.st.pyth_fallbacks += s.fallbacks;
+    status = status_of(s);
+  }
+  inf.status = status;
+  inf.st.kernels = c->kernels;
+  inf.st.breakdown_step = status == DCGS2_OK ? -1 : s.k;
+  if (info) *info = inf;
+  return status;
+}
+
+}  // extern "C"

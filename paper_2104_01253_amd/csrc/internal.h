@@ -1,0 +1,116 @@
+// Internal declarations shared by the host driver (api.cpp) and the kernels
+// (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include "dcgs2.h"
+#include "schur.h"
+
+namespace dcgs2 {
+
+// Device-resident control block, one per context.  Written by the finalising
+// workgroup of each reduction, read by every later kernel of the same call.
+enum : int {
+  ST_RUNNING = 0,
+  ST_BREAKDOWN = 1,
+  ST_FALLBACK = 2,     // stopped: the host must run the explicit-norm fallback
+  ST_NONFINITE = 3,
+  ST_DONE = 4,         // GMRES: least-squares residual reached the threshold
+};
+
+struct Ctrl {
+  int state;
+  int stop_step;       // paper's step j at which the state left RUNNING
+  int k;               // number of final Hessenberg (or R) columns
+  int reductions;
+  int fallbacks;
+  int pad0;
+  double rho_next;     // breakdown scale of the vector currently held in w
+  double tau, eta;
+  double gmres_thresh; // rtol * ||b||
+  double resid_est;    // |g_{k+1}|, least-squares residual estimate
+  double norm2;        // result of a plain squared-norm reduction
+};
+
+// What the finalising workgroup does with the reduced scalars.
+enum FinKind : int {
+  FIN_STEP = 0,        // DCGS2 step: Pythagorean alpha, T, H/K (or R) updates
+  FIN_FALLBACK = 1,    // same step after the explicit norm ||w - Q C||
+  FIN_RESTART = 2,     // first step after a Krylov-Schur truncation (C = 0, alpha = 1)
+  FIN_LAST1 = 3,       // last column, reduction 1: c = Q^T w
+  FIN_LAST2 = 4,       // last column, reduction 2: alpha = ||w - Q c||
+  FIN_NORM = 5,        // plain squared norm into ctrl->norm2
+};
+
+struct FinArgs {
+  int kind;            // FinKind
+  int qr;              // 1: QR (Alg. qr), 0: Arnoldi (Alg. arnoldi)
+  int j;               // paper's step index (1-based)
+  int J;               // number of basis columns dotted (j-2 for a step)
+  int gmres;           // apply Givens rotations to each completed H column
+  int ldc;             // stride between the C and T blocks of coef
+  Ctrl* ctrl;
+  double* coef;        // [0,ldc): C ; [ldc, 2ldc): T ; [2ldc]: alpha
+  double* pend;        // fallback hand-over: C, S, sigma, gamma
+  double* H; double* K; int ldh;           // Arnoldi (device, column-major)
+  double* R; int ldr; double* Sprev;       // QR     (device, column-major)
+  double* Rg; double* cs; double* sn; double* g;   // GMRES Givens state
+};
+
+// Two-level deterministic grid reduction bookkeeping.
+struct GridRed {
+  double* P1;          // [G][ldp] per-block partials
+  double* P2;          // [NG][ldp] per-group partials
+  unsigned* cnt;       // [NG + 1] arrival counters (zero between launches)
+  int G, GS, NG, ldp;
+};
+
+struct OpDev {
+  int kind;
+  int64_t m;
+  const int32_t* rowptr; const int32_t* colind; const double* val;
+  int nx, ny, nz;
+  double c0, cxm, cxp, cym, cyp, czm, czp;
+};
+
+// ---- launchers (kernels.hip) -------------------------------------------------------
+// Every launcher returns the hipError_t of its launch.
+hipError_t launch_init_ctrl(Ctrl* ctrl, double tau, double eta, double thresh, hipStream_t s);
+hipError_t launch_fill(double* p, int64_t n, double val, hipStream_t s);
+hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s);
+hipError_t launch_set_state(Ctrl* ctrl, int state, hipStream_t s);
+hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
+hipError_t launch_copy_cols(double* dst, int64_t ldd, const double* src, int64_t lds,
+                            int64_t m, int ncols, hipStream_t s);
+// y = A x, or y = b - A x when b != nullptr; skipped unless ctrl->state == RUNNING
+// (ctrl may be nullptr: always runs).
+hipError_t launch_spmv(const OpDev& op, const double* x, const double* b, double* y,
+                       const Ctrl* ctrl, hipStream_t s);
+// One DCGS2 reduction: [Q_{0..J-1}, x, (y)]^T [x, (y)] over m rows, grid-reduced,
+// then finalised by the last workgroup according to fin.
+hipError_t launch_reduce(const double* Q, int64_t ldq, int J, const double* x,
+                         const double* y, int64_t m, const GridRed& gr, const FinArgs& fin,
+                         hipStream_t s);
+// u = x - Q_{0..J-1} C  written to Q[:, J]; ||u||^2 grid-reduced and finalised.
+hipError_t launch_project_norm(double* Q, int64_t ldq, int J, const double* x, int64_t m,
+                               const GridRed& gr, const FinArgs& fin, hipStream_t s);
+// q_{j-1} = (x - Q C)/alpha (or Q[:,J]/alpha when qcol), Q[:,J] = q,
+// x <- yscale(y) - Q_{0..J-1} T - q T_J, with yscale(y) = y/alpha (Arnoldi) or y (QR).
+hipError_t launch_update(double* Q, int64_t ldq, int J, double* x, const double* y,
+                         int64_t m, const double* coef, int ldc, int arnoldi, int qcol,
+                         const Ctrl* ctrl, hipStream_t s);
+// Q[:, J] /= alpha (coef[2 ldc]) when ctrl->state == RUNNING.
+hipError_t launch_scale_col(double* Q, int64_t ldq, int J, int64_t m, const double* coef,
+                            int ldc, const Ctrl* ctrl, hipStream_t s);
+// Out[:, 0..k) = (acc ? Out : 0) + Q[:, 0..p) Z[0..p, 0..k)   (Z device, ldz)
+hipError_t launch_tsgemm(const double* Q, int64_t ldq, int p, const double* Z, int ldz,
+                         int k, double* Out, int64_t ldo, int64_t m, int acc, hipStream_t s);
+
+// Grid sizing for the reductions (number of workgroups for m rows).
+void reduce_grid(int64_t m, int* G, int* GS, int* NG);
+constexpr int REDUCE_GMAX = 1024;
+constexpr int REDUCE_GSMAX = 32;
+
+}  // namespace dcgs2

@@ -1,0 +1,813 @@
+// HIP kernels for the DCGS2 Arnoldi-QR expansion on gfx950 (MI355X).
+//
+// Method: Bielich et al., "Low-Synch Gram-Schmidt with Delayed
+// Reorthogonalization for Krylov Solvers" (arXiv 2104.01253), Sec. 3 (Alg. qr),
+// Sec. 4 (Alg. arnoldi and eqs. (08)-(52)).
+//
+// One DCGS2 step j is two streaming passes over the tall-skinny basis Q plus a
+// scalar tail that a single workgroup runs:
+//   reduce   [Q_{1:j-2}, w_{j-1}, y]^T [w_{j-1}, y]   (y = A w_{j-1} or a_j)
+//            -> per-workgroup partials -> two-level fixed-order grid sum;
+//            the last workgroup to arrive finalises the step (alpha by the
+//            Pythagorean trick, Stephen's trick, T, and the H/K or R updates).
+//   update   q_{j-1} = (w - Q C)/alpha into Q[:, j-1] and
+//            w_j = y/alpha - Q_{1:j-1} T (Arnoldi) or a_j - Q_{1:j-1} S (QR).
+// Both passes are bound by HBM bandwidth (about 0.5 flop per byte, far below
+// the fp64 ridge of the chip), so they are written as coalesced 16-byte
+// streams over rows with the per-column coefficients held uniform (scalar
+// registers), not as matrix-core tiles.  The grid sum is deterministic: the
+// partials of a fixed set of workgroups are added in a fixed order no matter
+// which workgroup arrives last, so repeated runs are bitwise identical.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "internal.h"
+
+namespace dcgs2 {
+namespace {
+
+constexpr int BS = 256;          // threads per workgroup (4 wavefronts of 64)
+constexpr int NW = BS / 64;
+constexpr int NT = 8;            // basis columns per reduction tile
+
+// ---------------------------------------------------------------------------------
+// Row vectors: a "unit" is VW consecutive rows; VW = 2 uses 16-byte loads and
+// requires every column start to be 16-byte aligned (checked by the host).
+template <int VW>
+struct RowVec {
+  double e[VW];
+  __device__ static RowVec load(const double* p, int64_t u) {
+    RowVec r;
+    if constexpr (VW == 2) {
+      const double2 t = reinterpret_cast<const double2*>(p)[u];
+      r.e[0] = t.x;
+      r.e[1] = t.y;
+    } else {
+      r.e[0] = p[u];
+    }
+    return r;
+  }
+  __device__ void store(double* p, int64_t u) const {
+    if constexpr (VW == 2) reinterpret_cast<double2*>(p)[u] = make_double2(e[0], e[1]);
+    else p[u] = e[0];
+  }
+  __device__ static RowVec zero() {
+    RowVec r;
+#pragma unroll
+    for (int i = 0; i < VW; ++i) r.e[i] = 0.0;
+    return r;
+  }
+  __device__ double dot(const RowVec& o) const {
+    double s = e[0] * o.e[0];
+#pragma unroll
+    for (int i = 1; i < VW; ++i) s = fma(e[i], o.e[i], s);
+    return s;
+  }
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Deterministic workgroup sum of NV per-thread values; results land in out[0..NV)
+// (global or shared), written by threads 0..NV-1.  sh: NW*NV doubles of LDS.
+template <int NV>
+__device__ void block_sum(const double (&acc)[NV], double* sh, double* out, int nvalid) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    const double v = wave_sum(acc[c]);
+    if (lane == 0) sh[wid * NV + c] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV && (int)threadIdx.x < nvalid) {
+    double s = sh[threadIdx.x];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) s += sh[w * NV + threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// Two-level grid reduction of V partial values per workgroup (already stored in
+// gr.P1[blockIdx.x]).  Returns true in exactly one workgroup, the last to arrive,
+// with the V totals in red[] (LDS).  Workgroups are grouped by consecutive index;
+// each group is summed in index order by its last arrival, then the group sums
+// are summed in group order by the last group to finish.
+__device__ bool grid_reduce(const GridRed& gr, int V, double* red) {
+  __shared__ int s_last;
+  __threadfence();               // every thread: release this workgroup's partial stores
+  __syncthreads();
+  const int grp = blockIdx.x / gr.GS;
+  const int g0 = grp * gr.GS;
+  const int gsz = min(gr.GS, gr.G - g0);
+  if (threadIdx.x == 0) {
+    const unsigned prev = atomicAdd(&gr.cnt[grp], 1u);
+    s_last = (prev == (unsigned)(gsz - 1));
+  }
+  __syncthreads();
+  if (!s_last) return false;
+  __threadfence();
+  for (int v = threadIdx.x; v < V; v += BS) {
+    double s = 0.0;
+    for (int b = 0; b < gsz; ++b) s += gr.P1[(int64_t)(g0 + b) * gr.ldp + v];
+    if (gr.NG == 1) red[v] = s;
+    else gr.P2[(int64_t)grp * gr.ldp + v] = s;
+  }
+  if (threadIdx.x == 0) gr.cnt[grp] = 0u;
+  if (gr.NG == 1) { __syncthreads(); return true; }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev = atomicAdd(&gr.cnt[gr.NG], 1u);
+    s_last = (prev == (unsigned)(gr.NG - 1));
+  }
+  __syncthreads();
+  if (!s_last) return false;
+  __threadfence();
+  for (int v = threadIdx.x; v < V; v += BS) {
+    double s = 0.0;
+    for (int g = 0; g < gr.NG; ++g) s += gr.P2[(int64_t)g * gr.ldp + v];
+    red[v] = s;
+  }
+  if (threadIdx.x == 0) gr.cnt[gr.NG] = 0u;
+  __syncthreads();
+  return true;
+}
+
+__device__ __forceinline__ bool finite(double v) { return isfinite(v); }
+
+// Deterministic dot product of two LDS/global vectors of length n by wavefront 0;
+// the result is broadcast through *out (LDS).  Call from all threads.
+__device__ void small_dot(const double* a, const double* b, int n, double* out) {
+  if (threadIdx.x < 64) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 64) s = fma(a[i], b[i], s);
+    s = wave_sum(s);
+    if (threadIdx.x == 0) *out = s;
+  }
+  __syncthreads();
+}
+
+// Any non-finite value among v[0..n)?  Result broadcast through *flag (LDS).
+__device__ void any_nonfinite(const double* v, int n, int* flag) {
+  if (threadIdx.x == 0) *flag = 0;
+  __syncthreads();
+  int bad = 0;
+  for (int i = threadIdx.x; i < n; i += BS) bad |= !finite(v[i]);
+  if (bad) atomicOr(flag, 1);
+  __syncthreads();
+}
+
+// GMRES: apply the stored Givens rotations to the just-completed Hessenberg column
+// c (rows 0..c+1), form rotation c, update g and test the least-squares residual
+// |g_{c+1}| against ctrl->gmres_thresh.  Thread 0 runs the recurrence; sh holds
+// at least 3(c+2) doubles of LDS scratch.
+__device__ void gmres_givens(const FinArgs& f, int c, int j, double* sh) {
+  double* h = sh;
+  double* cs = sh + (c + 2);
+  double* sn = cs + (c + 1);
+  for (int i = threadIdx.x; i <= c + 1; i += BS) h[i] = f.H[(int64_t)c * f.ldh + i];
+  for (int i = threadIdx.x; i < c; i += BS) { cs[i] = f.cs[i]; sn[i] = f.sn[i]; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < c; ++i) {
+      const double a = h[i], b = h[i + 1];
+      h[i] = cs[i] * a + sn[i] * b;
+      h[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = h[c], b = h[c + 1];
+    const double r = hypot(a, b);
+    const double cc = r > 0.0 ? a / r : 1.0;
+    const double ss = r > 0.0 ? b / r : 0.0;
+    f.cs[c] = cc;
+    f.sn[c] = ss;
+    h[c] = r;
+    const double gc = f.g[c];
+    f.g[c] = cc * gc;
+    f.g[c + 1] = -ss * gc;
+    const double est = fabs(ss * gc);
+    f.ctrl->resid_est = est;
+    if (est <= f.ctrl->gmres_thresh && f.ctrl->state == ST_RUNNING) {
+      f.ctrl->state = ST_DONE;
+      f.ctrl->stop_step = j;
+      f.ctrl->k = c + 1;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= c; i += BS) f.Rg[(int64_t)c * f.ldh + i] = h[i];
+  __syncthreads();
+}
+
+// Complete the Hessenberg column J-1 with the reorthogonalisation coefficients:
+// H_{1:J, J-1} = K_{1:J, J-1} + C,  H_{J+1, J-1} = alpha  (Alg. arnoldi, columns
+// completed one step late).  Then GMRES rotations when enabled.
+__device__ void complete_h_column(const FinArgs& f, const double* C, int J, double alpha,
+                                  double* scratch) {
+  const int col = J - 1;
+  for (int i = threadIdx.x; i < J; i += BS)
+    f.H[(int64_t)col * f.ldh + i] = f.K[(int64_t)col * f.ldh + i] + C[i];
+  if (threadIdx.x == 0) f.H[(int64_t)col * f.ldh + J] = alpha;
+  __syncthreads();
+  if (threadIdx.x == 0 && f.ctrl->state == ST_RUNNING) f.ctrl->k = J;
+  if (f.gmres) gmres_givens(f, col, f.j, scratch);
+}
+
+// Scalar tail of a DCGS2 step once alpha_{j-1} is known (Alg. arnoldi lines 4-12
+// with lines 10 -> 12 -> 11, or Alg. qr lines 3-8).
+//   C, S : LDS vectors of length J; sigma, gamma, cs = C^T S; rho = breakdown scale.
+__device__ void step_tail(const FinArgs& f, const double* C, const double* S, double sigma,
+                          double gamma, double csum, double alpha, double rho, double* T,
+                          double* scratch) {
+  Ctrl* ctrl = f.ctrl;
+  const int J = f.J, j = f.j;
+  if (!finite(alpha)) {
+    if (threadIdx.x == 0) { ctrl->state = ST_NONFINITE; ctrl->stop_step = j; }
+    return;
+  }
+  if (alpha <= ctrl->eta * rho) {                 // breakdown: close column j-2 and stop
+    if (f.qr) {
+      for (int i = threadIdx.x; i < J; i += BS) f.R[(int64_t)J * f.ldr + i] = f.Sprev[i] + C[i];
+      if (threadIdx.x == 0) f.R[(int64_t)J * f.ldr + J] = alpha;
+      __syncthreads();
+      if (threadIdx.x == 0) ctrl->k = J;
+    } else if (j >= 3) {
+      complete_h_column(f, C, J, alpha, scratch);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && (ctrl->state == ST_RUNNING || ctrl->state == ST_DONE)) {
+      if (ctrl->state == ST_RUNNING) { ctrl->state = ST_BREAKDOWN; ctrl->stop_step = j; }
+    }
+    return;
+  }
+  // T_{1:j-2} = S/alpha, T_{j-1} = (sigma - C^T S)/alpha^2 (Arnoldi);
+  // S_{j-1,j} = (sigma - C^T S)/alpha (QR, Stephen's trick)
+  for (int i = threadIdx.x; i < J; i += BS) T[i] = f.qr ? S[i] : S[i] / alpha;
+  if (threadIdx.x == 0) T[J] = f.qr ? (sigma - csum) / alpha : (sigma - csum) / (alpha * alpha);
+  __syncthreads();
+  for (int i = threadIdx.x; i < J; i += BS) f.coef[i] = C[i];
+  for (int i = threadIdx.x; i <= J; i += BS) f.coef[f.ldc + i] = T[i];
+  if (threadIdx.x == 0) f.coef[2 * f.ldc] = alpha;
+  if (f.qr) {
+    // R_{1:j-2, j-1} = S_{1:j-2, j-1} + C ; R_{j-1,j-1} = alpha ; keep S_{1:j-1, j}
+    for (int i = threadIdx.x; i < J; i += BS) f.R[(int64_t)J * f.ldr + i] = f.Sprev[i] + C[i];
+    if (threadIdx.x == 0) f.R[(int64_t)J * f.ldr + J] = alpha;
+    __syncthreads();
+    for (int i = threadIdx.x; i <= J; i += BS) f.Sprev[i] = T[i];
+    if (threadIdx.x == 0) { ctrl->k = J + 1; ctrl->rho_next = sqrt(gamma); }
+  } else {
+    if (f.gmres && j == 2 && threadIdx.x == 0) f.g[0] = alpha;   // beta e_1 of the cycle
+    if (j >= 3) complete_h_column(f, C, J, alpha, scratch);      // lines 10 and 12
+    __syncthreads();
+    // line 11: K_{1:j-1, j-1} = T - (1/alpha) H_{1:j-1, 1:j-2} C   (dense product)
+    for (int i = threadIdx.x; i <= J; i += BS) {
+      double hc = 0.0;
+      for (int c = 0; c < J; ++c) hc = fma(f.H[(int64_t)c * f.ldh + i], C[c], hc);
+      f.K[(int64_t)J * f.ldh + i] = T[i] - hc / alpha;
+    }
+    if (threadIdx.x == 0) ctrl->rho_next = sqrt(gamma) / alpha;
+  }
+  __syncthreads();
+}
+
+// The finalising workgroup: red[] holds the grid-reduced values of this kernel.
+__device__ void finalize(const FinArgs& f, double* red, double* T, double* scratch) {
+  Ctrl* ctrl = f.ctrl;
+  const int J = f.J, j = f.j;
+  __shared__ double s_dot[2];
+  __shared__ int s_flag;
+  switch (f.kind) {
+    case FIN_NORM:
+      if (threadIdx.x == 0) { ctrl->norm2 = red[0]; ctrl->reductions += 1; }
+      return;
+    case FIN_LAST1: {                      // c = Q^T w (and w^T w)
+      any_nonfinite(red, J + 1, &s_flag);
+      if (threadIdx.x == 0) {
+        ctrl->reductions += 1;
+        if (s_flag) { ctrl->state = ST_NONFINITE; ctrl->stop_step = j; }
+        if (J == 0) ctrl->rho_next = sqrt(red[0]);   // single-column QR: rho = ||a_1||
+      }
+      for (int i = threadIdx.x; i < J; i += BS) f.coef[i] = red[i];
+      return;
+    }
+    case FIN_LAST2: {                      // alpha = ||w - Q c||, close the last column
+      const double alpha = sqrt(red[0]);
+      const double* c = f.coef;
+      if (threadIdx.x == 0) ctrl->reductions += 1;
+      if (!finite(alpha)) {
+        if (threadIdx.x == 0) { ctrl->state = ST_NONFINITE; ctrl->stop_step = j; }
+        return;
+      }
+      for (int i = threadIdx.x; i < J; i += BS) T[i] = c[i];   // c into LDS
+      __syncthreads();
+      const bool brk = alpha <= ctrl->eta * ctrl->rho_next;
+      if (f.qr) {
+        for (int i = threadIdx.x; i < J; i += BS) f.R[(int64_t)J * f.ldr + i] = f.Sprev[i] + T[i];
+        if (threadIdx.x == 0) {
+          f.R[(int64_t)J * f.ldr + J] = alpha;
+          ctrl->k = brk ? J : J + 1;
+        }
+      } else {
+        complete_h_column(f, T, J, alpha, scratch);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        f.coef[2 * f.ldc] = alpha;
+        if (brk && ctrl->state == ST_RUNNING) { ctrl->state = ST_BREAKDOWN; ctrl->stop_step = j; }
+      }
+      return;
+    }
+    case FIN_RESTART: {                    // C = 0, alpha = 1: T = Q_{1:k+1}^T v
+      const int Jt = J + 2;
+      const double* S = red + Jt;
+      any_nonfinite(red, 2 * Jt, &s_flag);
+      if (s_flag) {
+        if (threadIdx.x == 0) { ctrl->state = ST_NONFINITE; ctrl->stop_step = j; ctrl->reductions += 1; }
+        return;
+      }
+      for (int i = threadIdx.x; i < J; i += BS) { T[i] = S[i]; f.coef[i] = 0.0; }
+      if (threadIdx.x == 0) T[J] = S[J];   // sigma = q_{k+1}^T v
+      __syncthreads();
+      for (int i = threadIdx.x; i <= J; i += BS) {
+        f.coef[f.ldc + i] = T[i];
+        f.K[(int64_t)J * f.ldh + i] = T[i];
+      }
+      if (threadIdx.x == 0) {
+        f.coef[2 * f.ldc] = 1.0;
+        ctrl->rho_next = sqrt(S[J + 1]);
+        ctrl->reductions += 1;
+      }
+      __syncthreads();
+      return;
+    }
+    case FIN_STEP: {
+      const int Jt = J + 2;
+      const double* C = red;
+      const double beta = red[J];
+      const double* S = red + Jt;
+      const double sigma = red[Jt + J];
+      const double gamma = red[Jt + J + 1];
+      any_nonfinite(red, 2 * Jt, &s_flag);
+      if (s_flag) {
+        if (threadIdx.x == 0) { ctrl->state = ST_NONFINITE; ctrl->stop_step = j; ctrl->reductions += 1; }
+        return;
+      }
+      small_dot(C, C, J, &s_dot[0]);
+      small_dot(C, S, J, &s_dot[1]);
+      const double rho = (j == 2) ? sqrt(beta) : ctrl->rho_next;
+      const double d = beta - s_dot[0];
+      if (threadIdx.x == 0) ctrl->reductions += 1;
+      if (!(finite(d) && d > ctrl->tau * beta)) {
+        // hand the reduced step over to the explicit-norm fallback (run by the host)
+        for (int i = threadIdx.x; i < J; i += BS) {
+          f.pend[i] = C[i];
+          f.pend[J + i] = S[i];
+          f.coef[i] = C[i];
+        }
+        if (threadIdx.x == 0) {
+          f.pend[2 * J] = sigma;
+          f.pend[2 * J + 1] = gamma;
+          f.pend[2 * J + 2] = beta;
+          ctrl->state = ST_FALLBACK;
+          ctrl->stop_step = j;
+        }
+        return;
+      }
+      step_tail(f, C, S, sigma, gamma, s_dot[1], sqrt(d), rho, T, scratch);
+      return;
+    }
+    case FIN_FALLBACK: {
+      const double alpha = sqrt(red[0]);
+      double* C = scratch;                 // pend -> LDS
+      double* S = scratch + J;
+      for (int i = threadIdx.x; i < J; i += BS) { C[i] = f.pend[i]; S[i] = f.pend[J + i]; }
+      __syncthreads();
+      const double sigma = f.pend[2 * J], gamma = f.pend[2 * J + 1], beta = f.pend[2 * J + 2];
+      small_dot(C, S, J, &s_dot[1]);
+      const double rho = (j == 2) ? sqrt(beta) : ctrl->rho_next;
+      if (threadIdx.x == 0) { ctrl->reductions += 1; ctrl->fallbacks += 1; }
+      step_tail(f, C, S, sigma, gamma, s_dot[1], alpha, rho, T, scratch + 2 * J);
+      return;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Reduction pass: per-workgroup partial dot products of [Q_{0..J-1}, x, (y)] with
+// [x, (y)] over a contiguous slab of rows, NT basis columns at a time.
+template <int VW, bool HASY>
+__global__ __launch_bounds__(BS) void reduce_kernel(const double* __restrict__ Q, int64_t ldq,
+                                                    int J, const double* __restrict__ x,
+                                                    const double* __restrict__ y, int64_t m,
+                                                    GridRed gr, FinArgs fin) {
+  extern __shared__ double smem[];
+  if (fin.ctrl->state != ST_RUNNING) return;
+  const int Jt = J + (HASY ? 2 : 1);
+  const int V = HASY ? 2 * Jt : Jt;
+  double* red = smem;                       // V
+  double* shb = red + V;                    // NW * 2 * NT
+  double* T = shb + NW * 2 * NT;            // J + 2
+  double* scratch = T + (J + 2);            // 3 (J + 2) + 64
+  const int64_t units = m / VW;
+  const int64_t per = (units + gr.G - 1) / gr.G;
+  const int64_t u0 = (int64_t)blockIdx.x * per;
+  const int64_t u1 = min(units, u0 + per);
+  const bool tail = (VW == 2) && (m & 1) && blockIdx.x == gr.G - 1 && threadIdx.x == 0;
+  double* P = gr.P1 + (int64_t)blockIdx.x * gr.ldp;
+  using RV = RowVec<VW>;
+
+  for (int k0 = 0; k0 < Jt; k0 += NT) {
+    double acc[2 * NT];
+#pragma unroll
+    for (int c = 0; c < 2 * NT; ++c) acc[c] = 0.0;
+    const double* colp[NT];
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+      const int k = k0 + c;
+      colp[c] = (k < J) ? Q + (int64_t)k * ldq : (k == J ? x : y);
+    }
+    for (int64_t u = u0 + threadIdx.x; u < u1; u += BS) {
+      const RV xv = RV::load(x, u);
+      const RV yv = HASY ? RV::load(y, u) : RV::zero();
+#pragma unroll
+      for (int c = 0; c < NT; ++c) {
+        if (k0 + c < Jt) {
+          const RV q = RV::load(colp[c], u);
+          acc[c] += q.dot(xv);
+          if (HASY) acc[NT + c] += q.dot(yv);
+        }
+      }
+    }
+    if (tail) {                              // odd m with 2-row units: last row
+      const int64_t r = m - 1;
+      const double xr = x[r], yr = HASY ? y[r] : 0.0;
+#pragma unroll
+      for (int c = 0; c < NT; ++c) {
+        if (k0 + c < Jt) {
+          const double q = colp[c][r];
+          acc[c] += q * xr;
+          if (HASY) acc[NT + c] += q * yr;
+        }
+      }
+    }
+    const int nvalid = min(NT, Jt - k0);
+    if (HASY) {
+      // partial layout: [0,Jt) = [Q,x,y]^T x ; [Jt, 2Jt) = [Q,x,y]^T y
+      double ax[NT], ay[NT];
+#pragma unroll
+      for (int c = 0; c < NT; ++c) { ax[c] = acc[c]; ay[c] = acc[NT + c]; }
+      block_sum<NT>(ax, shb, P + k0, nvalid);
+      block_sum<NT>(ay, shb, P + Jt + k0, nvalid);
+    } else {
+      double ax[NT];
+#pragma unroll
+      for (int c = 0; c < NT; ++c) ax[c] = acc[c];
+      block_sum<NT>(ax, shb, P + k0, nvalid);
+    }
+  }
+  if (grid_reduce(gr, V, red)) finalize(fin, red, T, scratch);
+}
+
+// u = x - Q_{0..J-1} C written to Q[:, J]; ||u||^2 grid-reduced and finalised.
+template <int VW>
+__global__ __launch_bounds__(BS) void project_norm_kernel(double* __restrict__ Q, int64_t ldq,
+                                                          int J, const double* __restrict__ x,
+                                                          int64_t m, GridRed gr, FinArgs fin) {
+  extern __shared__ double smem[];
+  if (fin.ctrl->state != ST_RUNNING) return;
+  double* red = smem;                       // 1
+  double* shb = red + 2;                    // NW
+  double* T = shb + NW;                     // J + 2
+  double* scratch = T + (J + 2);
+  const double* __restrict__ C = fin.coef;
+  const int64_t units = m / VW;
+  const int64_t per = (units + gr.G - 1) / gr.G;
+  const int64_t u0 = (int64_t)blockIdx.x * per;
+  const int64_t u1 = min(units, u0 + per);
+  using RV = RowVec<VW>;
+  double acc[1] = {0.0};
+  double* qout = Q + (int64_t)J * ldq;
+  for (int64_t u = u0 + threadIdx.x; u < u1; u += BS) {
+    RV sc = RV::zero();
+    for (int k = 0; k < J; ++k) {
+      const RV q = RV::load(Q + (int64_t)k * ldq, u);
+      const double ck = C[k];
+#pragma unroll
+      for (int e = 0; e < VW; ++e) sc.e[e] = fma(q.e[e], ck, sc.e[e]);
+    }
+    const RV xv = RV::load(x, u);
+    RV uu;
+#pragma unroll
+    for (int e = 0; e < VW; ++e) uu.e[e] = xv.e[e] - sc.e[e];
+    uu.store(qout, u);
+    acc[0] += uu.dot(uu);
+  }
+  if ((VW == 2) && (m & 1) && blockIdx.x == gr.G - 1 && threadIdx.x == 0) {
+    const int64_t r = m - 1;
+    double s = 0.0;
+    for (int k = 0; k < J; ++k) s = fma(Q[(int64_t)k * ldq + r], C[k], s);
+    const double uval = x[r] - s;
+    qout[r] = uval;
+    acc[0] += uval * uval;
+  }
+  block_sum<1>(acc, shb, gr.P1 + (int64_t)blockIdx.x * gr.ldp, 1);
+  if (grid_reduce(gr, 1, red)) finalize(fin, red, T, scratch);
+}
+
+// Update pass: q_{j-1} and w_j, one row unit per thread.
+template <int VW, bool ARN, bool QCOL>
+__global__ __launch_bounds__(BS) void update_kernel(double* __restrict__ Q, int64_t ldq, int J,
+                                                    double* __restrict__ x,
+                                                    const double* __restrict__ y, int64_t m,
+                                                    const double* __restrict__ coef, int ldc,
+                                                    const Ctrl* __restrict__ ctrl) {
+  if (ctrl->state != ST_RUNNING) return;
+  const double* __restrict__ C = coef;
+  const double* __restrict__ T = coef + ldc;
+  const double alpha = coef[2 * ldc];
+  const double tJ = T[J];
+  const int64_t units = m / VW;
+  const int64_t u = (int64_t)blockIdx.x * BS + threadIdx.x;
+  double* qout = Q + (int64_t)J * ldq;
+  if (u < units) {
+    RowVec<VW> sc = RowVec<VW>::zero(), st = RowVec<VW>::zero();
+#pragma unroll 8
+    for (int k = 0; k < J; ++k) {
+      const RowVec<VW> q = RowVec<VW>::load(Q + (int64_t)k * ldq, u);
+      const double ck = C[k], tk = T[k];
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+        sc.e[e] = fma(q.e[e], ck, sc.e[e]);
+        st.e[e] = fma(q.e[e], tk, st.e[e]);
+      }
+    }
+    const RowVec<VW> xv = RowVec<VW>::load(x, u);
+    const RowVec<VW> yv = RowVec<VW>::load(y, u);
+    RowVec<VW> qc = RowVec<VW>::zero();
+    if (QCOL) qc = RowVec<VW>::load(qout, u);
+    RowVec<VW> qn, wn;
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+      const double q = QCOL ? qc.e[e] / alpha : (xv.e[e] - sc.e[e]) / alpha;
+      const double yt = ARN ? yv.e[e] / alpha : yv.e[e];
+      qn.e[e] = q;
+      wn.e[e] = yt - fma(q, tJ, st.e[e]);
+    }
+    qn.store(qout, u);
+    wn.store(x, u);
+  } else if (VW == 2 && (m & 1) && u == units) {
+    const int64_t r = m - 1;
+    double sc = 0.0, st = 0.0;
+    for (int k = 0; k < J; ++k) {
+      const double q = Q[(int64_t)k * ldq + r];
+      sc = fma(q, C[k], sc);
+      st = fma(q, T[k], st);
+    }
+    const double q = QCOL ? qout[r] / alpha : (x[r] - sc) / alpha;
+    const double yt = ARN ? y[r] / alpha : y[r];
+    qout[r] = q;
+    x[r] = yt - fma(q, tJ, st);
+  }
+}
+
+__global__ void scale_col_kernel(double* Q, int64_t ldq, int J, int64_t m,
+                                 const double* coef, int ldc, const Ctrl* ctrl) {
+  if (ctrl->state != ST_RUNNING) return;
+  const double alpha = coef[2 * ldc];
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i < m) Q[(int64_t)J * ldq + i] = Q[(int64_t)J * ldq + i] / alpha;
+}
+
+// ---------------------------------------------------------------------------------
+// Matvec of step a1.  Stencils: one row per thread, neighbours summed in column
+// order; out-of-grid neighbours are zero (Dirichlet).
+__global__ __launch_bounds__(BS) void stencil_kernel(OpDev op, const double* __restrict__ x,
+                                                     const double* __restrict__ b,
+                                                     double* __restrict__ y,
+                                                     const Ctrl* __restrict__ ctrl) {
+  if (ctrl && ctrl->state != ST_RUNNING) return;
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= op.m) return;
+  const uint32_t nx = op.nx, ny = op.ny, nz = op.nz;
+  const uint32_t ii = (uint32_t)i;
+  const uint32_t ix = ii % nx;
+  const uint32_t r = ii / nx;
+  const uint32_t iy = r % ny;
+  const uint32_t iz = r / ny;
+  const int64_t sxy = (int64_t)nx * ny;
+  double s = 0.0;
+  if (nz > 1 && iz > 0) s += op.czm * x[i - sxy];
+  if (iy > 0) s += op.cym * x[i - nx];
+  if (ix > 0) s += op.cxm * x[i - 1];
+  s += op.c0 * x[i];
+  if (ix + 1 < nx) s += op.cxp * x[i + 1];
+  if (iy + 1 < ny) s += op.cyp * x[i + nx];
+  if (nz > 1 && iz + 1 < nz) s += op.czp * x[i + sxy];
+  y[i] = b ? b[i] - s : s;
+}
+
+__global__ __launch_bounds__(BS) void csr_kernel(OpDev op, const double* __restrict__ x,
+                                                 const double* __restrict__ b,
+                                                 double* __restrict__ y,
+                                                 const Ctrl* __restrict__ ctrl) {
+  if (ctrl && ctrl->state != ST_RUNNING) return;
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= op.m) return;
+  double s = 0.0;
+  for (int32_t p = op.rowptr[i]; p < op.rowptr[i + 1]; ++p) s += op.val[p] * x[op.colind[p]];
+  y[i] = b ? b[i] - s : s;
+}
+
+// Out[:, k0+o] = (acc ? Out : 0) + sum_c Q[:, c] Z[c, k0+o]   for o < NO (one row per thread)
+template <int NO>
+__global__ __launch_bounds__(BS) void tsgemm_kernel(const double* __restrict__ Q, int64_t ldq,
+                                                    int p, const double* __restrict__ Z, int ldz,
+                                                    int k, double* __restrict__ Out, int64_t ldo,
+                                                    int64_t m, int accum) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int k0 = blockIdx.y * NO;
+  if (i >= m) return;
+  double acc[NO];
+#pragma unroll
+  for (int o = 0; o < NO; ++o) acc[o] = 0.0;
+  for (int c = 0; c < p; ++c) {
+    const double q = Q[(int64_t)c * ldq + i];
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+      if (k0 + o < k) acc[o] = fma(q, Z[(int64_t)(k0 + o) * ldz + c], acc[o]);
+  }
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+    if (k0 + o < k) {
+      double* out = Out + (int64_t)(k0 + o) * ldo + i;
+      *out = accum ? *out + acc[o] : acc[o];
+    }
+  }
+}
+
+__global__ void init_ctrl_kernel(Ctrl* c, double tau, double eta, double thresh) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    c->state = ST_RUNNING;
+    c->stop_step = -1;
+    c->k = 0;
+    c->reductions = 0;
+    c->fallbacks = 0;
+    c->pad0 = 0;
+    c->rho_next = 0.0;
+    c->tau = tau;
+    c->eta = eta;
+    c->gmres_thresh = thresh;
+    c->resid_est = 0.0;
+    c->norm2 = 0.0;
+  }
+}
+
+__global__ void set_state_kernel(Ctrl* c, int state) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) c->state = state;
+}
+
+__global__ void zero_u32_kernel(unsigned* p, int n) {
+  const int i = blockIdx.x * BS + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+__global__ void fill_kernel(double* p, int64_t n, double val) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i < n) p[i] = val;
+}
+
+__global__ void copy_cols_kernel(double* dst, int64_t ldd, const double* src, int64_t lds,
+                                 int64_t m) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i < m) dst[(int64_t)c * ldd + i] = src[(int64_t)c * lds + i];
+}
+
+inline unsigned nblocks(int64_t n) { return (unsigned)((n + BS - 1) / BS); }
+
+template <typename P>
+inline bool aligned16(P p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+size_t reduce_smem(int J, bool hasy) {
+  const int Jt = J + (hasy ? 2 : 1);
+  const int V = hasy ? 2 * Jt : Jt;
+  return sizeof(double) * (size_t)(V + NW * 2 * NT + (J + 2) + 3 * (J + 2) + 64);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------
+void reduce_grid(int64_t m, int* G, int* GS, int* NG) {
+  const int64_t units = (m + 1) / 2;
+  int64_t g = (units + (int64_t)BS * 4 - 1) / ((int64_t)BS * 4);
+  if (g < 1) g = 1;
+  if (g > REDUCE_GMAX) g = REDUCE_GMAX;
+  *G = (int)g;
+  *GS = (int)(g < REDUCE_GSMAX ? g : REDUCE_GSMAX);
+  *NG = (int)((g + *GS - 1) / *GS);
+}
+
+hipError_t launch_init_ctrl(Ctrl* ctrl, double tau, double eta, double thresh, hipStream_t s) {
+  init_ctrl_kernel<<<1, 64, 0, s>>>(ctrl, tau, eta, thresh);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_state(Ctrl* ctrl, int state, hipStream_t s) {
+  set_state_kernel<<<1, 64, 0, s>>>(ctrl, state);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  zero_u32_kernel<<<nblocks(n), BS, 0, s>>>(p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, int64_t n, double val, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  fill_kernel<<<nblocks(n), BS, 0, s>>>(p, n, val);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  copy_cols_kernel<<<dim3(nblocks(n), 1), BS, 0, s>>>(dst, n, src, n, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_cols(double* dst, int64_t ldd, const double* src, int64_t lds, int64_t m,
+                            int ncols, hipStream_t s) {
+  if (m <= 0 || ncols <= 0) return hipSuccess;
+  copy_cols_kernel<<<dim3(nblocks(m), ncols), BS, 0, s>>>(dst, ldd, src, lds, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv(const OpDev& op, const double* x, const double* b, double* y,
+                       const Ctrl* ctrl, hipStream_t s) {
+  if (op.kind == DCGS2_OP_CSR)
+    csr_kernel<<<nblocks(op.m), BS, 0, s>>>(op, x, b, y, ctrl);
+  else
+    stencil_kernel<<<nblocks(op.m), BS, 0, s>>>(op, x, b, y, ctrl);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* Q, int64_t ldq, int J, const double* x, const double* y,
+                         int64_t m, const GridRed& gr, const FinArgs& fin, hipStream_t s) {
+  const bool vec = aligned16(Q) && (ldq % 2 == 0) && aligned16(x) && (!y || aligned16(y));
+  const size_t sm = reduce_smem(J, y != nullptr);
+  const dim3 grid(gr.G), block(BS);
+  if (y) {
+    if (vec) reduce_kernel<2, true><<<grid, block, sm, s>>>(Q, ldq, J, x, y, m, gr, fin);
+    else reduce_kernel<1, true><<<grid, block, sm, s>>>(Q, ldq, J, x, y, m, gr, fin);
+  } else {
+    if (vec) reduce_kernel<2, false><<<grid, block, sm, s>>>(Q, ldq, J, x, y, m, gr, fin);
+    else reduce_kernel<1, false><<<grid, block, sm, s>>>(Q, ldq, J, x, y, m, gr, fin);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_project_norm(double* Q, int64_t ldq, int J, const double* x, int64_t m,
+                               const GridRed& gr, const FinArgs& fin, hipStream_t s) {
+  const bool vec = aligned16(Q) && (ldq % 2 == 0) && aligned16(x);
+  const size_t sm = sizeof(double) * (size_t)(2 + NW + (J + 2) + 3 * (J + 2) + 2 * J + 64);
+  if (vec) project_norm_kernel<2><<<gr.G, BS, sm, s>>>(Q, ldq, J, x, m, gr, fin);
+  else project_norm_kernel<1><<<gr.G, BS, sm, s>>>(Q, ldq, J, x, m, gr, fin);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(double* Q, int64_t ldq, int J, double* x, const double* y, int64_t m,
+                         const double* coef, int ldc, int arnoldi, int qcol, const Ctrl* ctrl,
+                         hipStream_t s) {
+  const bool vec = aligned16(Q) && (ldq % 2 == 0) && aligned16(x) && aligned16(y);
+  const int64_t units = vec ? m / 2 : m;
+  const unsigned nb = nblocks(units + 1);
+#define DCGS2_UPD(VW, A, QC) update_kernel<VW, A, QC><<<nb, BS, 0, s>>>(Q, ldq, J, x, y, m, coef, ldc, ctrl)
+  if (vec) {
+    if (arnoldi) { if (qcol) DCGS2_UPD(2, true, true); else DCGS2_UPD(2, true, false); }
+    else { if (qcol) DCGS2_UPD(2, false, true); else DCGS2_UPD(2, false, false); }
+  } else {
+    if (arnoldi) { if (qcol) DCGS2_UPD(1, true, true); else DCGS2_UPD(1, true, false); }
+    else { if (qcol) DCGS2_UPD(1, false, true); else DCGS2_UPD(1, false, false); }
+  }
+#undef DCGS2_UPD
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_col(double* Q, int64_t ldq, int J, int64_t m, const double* coef, int ldc,
+                            const Ctrl* ctrl, hipStream_t s) {
+  scale_col_kernel<<<nblocks(m), BS, 0, s>>>(Q, ldq, J, m, coef, ldc, ctrl);
+  return hipGetLastError();
+}
+
+hipError_t launch_tsgemm(const double* Q, int64_t ldq, int p, const double* Z, int ldz, int k,
+                         double* Out, int64_t ldo, int64_t m, int acc, hipStream_t s) {
+  if (m <= 0 || k <= 0) return hipSuccess;
+  constexpr int NO = 8;
+  const dim3 grid(nblocks(m), (unsigned)((k + NO - 1) / NO));
+  tsgemm_kernel<NO><<<grid, BS, 0, s>>>(Q, ldq, p, Z, ldz, k, Out, ldo, m, acc);
+  return hipGetLastError();
+}
+
+}  // namespace dcgs2

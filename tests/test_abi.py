@@ -1,0 +1,102 @@
+"""The C-ABI library: loads, exports every declared symbol, and validates
+arguments before any device work (CPU only; no compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2104_01253_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dcgs2.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "sizeof")))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("dcgs2_qr", "dcgs2_arnoldi", "gmres_solve", "krylov_schur_eigs"):
+        assert n in names
+    assert set(names) == set(binding.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.load()
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+
+
+@pytest.fixture()
+def ctx():
+    lib = binding.load()
+    h = ctypes.c_void_p()
+    assert lib.dcgs2_create(ctypes.byref(h), 0, None) == binding.OK   # lazy: no device call
+    yield lib, h
+    lib.dcgs2_destroy(h)
+
+
+FAKE = 4096          # never dereferenced: validation fails first
+
+
+def test_qr_argument_validation(ctx):
+    lib, h = ctx
+    st = binding.Stats()
+    E = binding.EINVAL
+    assert lib.dcgs2_qr(None, 100, 10, FAKE, 100, FAKE, 100, FAKE, 10, None) == E
+    assert lib.dcgs2_qr(h, 10, 20, FAKE, 10, FAKE, 10, FAKE, 20, None) == E      # n > m
+    assert lib.dcgs2_qr(h, 100, 0, FAKE, 100, FAKE, 100, FAKE, 10, None) == E    # n < 1
+    assert lib.dcgs2_qr(h, 100, 10, FAKE, 99, FAKE, 100, FAKE, 10, None) == E    # ldb < m
+    assert lib.dcgs2_qr(h, 100, 10, FAKE, 100, FAKE, 99, FAKE, 10, None) == E    # ldq < m
+    assert lib.dcgs2_qr(h, 100, 10, FAKE, 100, FAKE, 100, FAKE, 9, None) == E    # ldr < n
+    assert lib.dcgs2_qr(h, 100, 10, None, 100, FAKE, 100, FAKE, 10, None) == E   # null B
+    assert lib.dcgs2_qr(h, 5000, 2000, FAKE, 5000, FAKE, 5000, FAKE, 2000, ctypes.byref(st)) == E
+
+
+def test_arnoldi_gmres_ks_argument_validation(ctx):
+    lib, h = ctx
+    E = binding.EINVAL
+    op = binding.stencil_op((8, 8), 1.0, (1.0, 1.0))
+    bad = binding.stencil_op((8, 8), 1.0, (1.0, 1.0))
+    bad.m = 63                                                    # nx*ny != m
+    H = (ctypes.c_double * 100)()
+    assert lib.dcgs2_arnoldi(h, ctypes.byref(bad), FAKE, 5, FAKE, 64, H, 6, None) == E
+    assert lib.dcgs2_arnoldi(h, ctypes.byref(op), FAKE, 64, FAKE, 64, H, 65, None) == E  # n >= m
+    assert lib.dcgs2_arnoldi(h, ctypes.byref(op), FAKE, 5, FAKE, 64, H, 5, None) == E    # ldh
+    assert lib.dcgs2_arnoldi(h, None, FAKE, 5, FAKE, 64, H, 6, None) == E
+    assert lib.gmres_solve(h, ctypes.byref(op), FAKE, FAKE, 0, 1e-8, 10, None) == E      # restart
+    assert lib.gmres_solve(h, ctypes.byref(op), FAKE, FAKE, 10, 0.0, 10, None) == E      # rtol
+    assert lib.gmres_solve(h, ctypes.byref(op), FAKE, FAKE, 10, 1e-8, -1, None) == E
+    re_, im_ = (ctypes.c_double * 10)(), (ctypes.c_double * 10)()
+    assert lib.krylov_schur_eigs(h, ctypes.byref(op), 10, 30, 10, 1e-8, 5, FAKE, re_, im_, None) == E
+    assert lib.krylov_schur_eigs(h, ctypes.byref(op), 5, 64, 10, 1e-8, 5, FAKE, re_, im_, None) == E
+    assert lib.krylov_schur_eigs(h, ctypes.byref(op), 5, 30, 10, -1.0, 5, FAKE, re_, im_, None) == E
+    csr = binding.Op()
+    csr.kind = binding.OP_CSR
+    csr.m = 10
+    assert lib.dcgs2_apply(h, ctypes.byref(csr), FAKE, FAKE) == E                     # null arrays
+
+
+def test_tolerance_validation_and_status_strings(ctx):
+    lib, h = ctx
+    assert lib.dcgs2_set_tolerances(h, 1e-8, 1e-12) == binding.OK
+    assert lib.dcgs2_set_tolerances(h, -1.0, 1e-12) == binding.EINVAL
+    assert lib.dcgs2_set_tolerances(h, 1e-8, 1.0) == binding.EINVAL
+    assert lib.dcgs2_set_tolerances(None, 1e-8, 1e-12) == binding.EINVAL
+    for code in (0, -1, -2, -3, 1, 2, 3):
+        assert binding.status_str(code) != "unknown status"
+    assert lib.dcgs2_destroy(None) == binding.OK
+
+
+def test_stencil_coefficients_match_definition():
+    c0, lo, hi = binding.stencil_coefficients((32, 32), 1.0, (10.0, 10.0))
+    h = 1 / 33
+    assert c0 == pytest.approx(4 / h**2)
+    assert lo[0] == pytest.approx(-1 / h**2 - 10 / (2 * h))
+    assert hi[1] == pytest.approx(-1 / h**2 + 10 / (2 * h))

@@ -1,0 +1,167 @@
+"""GPU parity of dcgs2_arnoldi (Alg. arnoldi) and the matvec, through the C ABI."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import arnoldi as ar
+from oracle import operators as ops
+from oracle.metrics import loss_of_orthogonality, representation_error
+from paper_2104_01253_amd import binding, synth
+from tests._gpu import dev_vector, host, relnorm, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch_cuda()
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def run_arnoldi(ctx, op, r0, n, ld=None):
+    Q = binding.colmajor_empty(op.m, n + 1, ld)
+    H, rc, st = ctx.arnoldi(op, dev_vector(r0), n, Q)
+    return host(Q), H, rc, st
+
+
+@pytest.mark.parametrize("grid,vel", [((32, 32), (10.0, 10.0)), ((31, 29), (3.0, 40.0)),
+                                      ((7, 5, 3), (1.0, 2.0, 3.0)), ((40, 33, 17), (10., 10., 10.)),
+                                      ((1000, 1), (5.0, 0.0))])
+def test_matvec_parity(ctx, grid, vel):
+    torch = torch_cuda()
+    A = ops.convection_diffusion(grid, 1.0, vel)
+    op = binding.stencil_op(grid, 1.0, vel)
+    x = synth.normal_vector(A.shape[0], 3)
+    y = torch.empty(A.shape[0], dtype=torch.float64, device="cuda")
+    ctx.apply(op, dev_vector(x), y)
+    ref = A @ x
+    assert np.max(np.abs(host(y) - ref)) <= 1e-13 * np.max(np.abs(A).sum(axis=1)) * np.max(np.abs(x))
+
+
+def test_csr_matvec_parity(ctx):
+    torch = torch_cuda()
+    A = sp.random(3001, 3001, density=0.003, random_state=4, format="csr") + sp.eye(3001)
+    A = A.tocsr()
+    A.sort_indices()
+    rp = torch.from_numpy(A.indptr.astype(np.int32)).cuda()
+    ci = torch.from_numpy(A.indices.astype(np.int32)).cuda()
+    va = torch.from_numpy(A.data.astype(np.float64)).cuda()
+    op = binding.csr_op(rp, ci, va)
+    x = synth.normal_vector(3001, 5)
+    y = torch.empty(3001, dtype=torch.float64, device="cuda")
+    ctx.apply(op, dev_vector(x), y)
+    assert relnorm(host(y), A @ x) <= 1e-14
+
+
+def test_config1_parity():
+    """2-D convection-diffusion 32x32, v=(10,10), 50 steps, r0 ~ N(0,1) seed 0."""
+    torch_cuda()
+    prob, r0, n = synth.config1()
+    A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
+    with binding.Context(0) as c:
+        Q, H, rc, st = run_arnoldi(c, binding.stencil_op(prob.grid, prob.D, prob.vel), r0, n)
+    ref = ar.dcgs2_arnoldi(lambda x: A @ x, r0, n)
+    assert rc == 0 and st["reductions"] == ref["reductions"] == n + 2
+    say("H rel", relnorm(H, ref["H"]), "Q rel", relnorm(Q, ref["Q"]))
+    assert relnorm(H, ref["H"]) <= TOL
+    assert relnorm(Q, ref["Q"]) <= TOL
+    assert loss_of_orthogonality(Q) <= 1e-13
+    assert representation_error(A, Q, H, n) <= 1e-15
+
+
+@pytest.mark.parametrize("grid,n", [((5, 4), 1), ((5, 4), 2), ((9, 7), 3), ((33, 31), 17),
+                                    ((12, 11, 9), 40), ((64, 64, 3), 64)])
+def test_arnoldi_parity_shapes(ctx, grid, n):
+    vel = (10.0,) * len(grid)
+    A = ops.convection_diffusion(grid, 1.0, vel)
+    r0 = synth.normal_vector(A.shape[0], 11)
+    Q, H, rc, st = run_arnoldi(ctx, binding.stencil_op(grid, 1.0, vel), r0, n)
+    ref = ar.dcgs2_arnoldi(lambda x: A @ x, r0, n)
+    assert rc == 0
+    assert relnorm(H, ref["H"]) <= TOL
+    assert relnorm(Q, ref["Q"]) <= TOL
+    assert st["reductions"] == n + 2
+
+
+def test_arnoldi_csr_operator_and_odd_ld(ctx):
+    torch = torch_cuda()
+    g = np.random.default_rng(8)
+    A = (sp.random(2501, 2501, density=0.004, random_state=9, format="csr") + 4 * sp.eye(2501)).tocsr()
+    rp = torch.from_numpy(A.indptr.astype(np.int32)).cuda()
+    ci = torch.from_numpy(A.indices.astype(np.int32)).cuda()
+    va = torch.from_numpy(A.data.astype(np.float64)).cuda()
+    r0 = g.standard_normal(2501)
+    Q, H, rc, _ = run_arnoldi(ctx, binding.csr_op(rp, ci, va), r0, 30, ld=2503)
+    ref = ar.dcgs2_arnoldi(lambda x: A @ x, r0, 30)
+    assert rc == 0
+    assert relnorm(H, ref["H"]) <= TOL and relnorm(Q, ref["Q"]) <= TOL
+
+
+def test_arnoldi_forced_fallback(ctx):
+    prob, r0, _ = synth.config1()
+    A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
+    ctx.set_tolerances(1.0, 1e-12)
+    try:
+        Q, H, rc, st = run_arnoldi(ctx, binding.stencil_op(prob.grid, prob.D, prob.vel), r0, 20)
+    finally:
+        ctx.set_tolerances(1e-8, 1e-12)
+    ref = ar.dcgs2_arnoldi(lambda x: A @ x, r0, 20, tau=1.0)
+    assert rc == 0 and st["pyth_fallbacks"] == ref["fallbacks"] == 20
+    assert st["reductions"] == ref["reductions"]
+    assert relnorm(H, ref["H"]) <= TOL and relnorm(Q, ref["Q"]) <= TOL
+
+
+def test_arnoldi_breakdown_invariant_subspace(ctx):
+    torch = torch_cuda()
+    lam = np.arange(1.0, 201.0)
+    A = sp.diags(lam).tocsr()
+    rp = torch.from_numpy(A.indptr.astype(np.int32)).cuda()
+    ci = torch.from_numpy(A.indices.astype(np.int32)).cuda()
+    va = torch.from_numpy(A.data.astype(np.float64)).cuda()
+    r0 = np.zeros(200)
+    r0[[4, 50, 120]] = [1.0, -2.0, 0.5]
+    Q, H, rc, st = run_arnoldi(ctx, binding.csr_op(rp, ci, va), r0, 10)
+    ref = ar.dcgs2_arnoldi(lambda x: A @ x, r0, 10)
+    assert rc == binding.BREAKDOWN and st["breakdown_step"] == ref["k"] == 3
+    assert relnorm(H[:4, :3], ref["H"][:4, :3]) <= 1e-10
+    ritz = np.sort(np.linalg.eigvals(H[:3, :3]).real)
+    assert np.allclose(ritz, [5.0, 51.0, 121.0], rtol=1e-12)
+
+
+def test_arnoldi_nonfinite(ctx):
+    prob, r0, _ = synth.config1()
+    r0 = r0.copy()
+    r0[7] = np.nan
+    _, _, rc, st = run_arnoldi(ctx, binding.stencil_op(prob.grid, prob.D, prob.vel), r0, 5)
+    assert rc == binding.NONFINITE and st["breakdown_step"] == 0
+
+
+def test_arnoldi_deterministic(ctx):
+    prob = synth.cd3d(64)
+    r0 = synth.uniform_vector(prob.m, 3)
+    op = binding.stencil_op(prob.grid, prob.D, prob.vel)
+    Q1, H1, _, _ = run_arnoldi(ctx, op, r0, 30)
+    Q2, H2, _, _ = run_arnoldi(ctx, op, r0, 30)
+    assert np.array_equal(Q1, Q2) and np.array_equal(H1, H2)
+
+
+def test_arnoldi_full_size_128cube(ctx):
+    """The Arnoldi workload at full size: 3-D 128^3 (m = 2,097,152), n = 100 steps."""
+    prob, b = synth.config3(128)
+    A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
+    n = 100
+    say("gpu arnoldi 128^3 n=100")
+    Q, H, rc, st = run_arnoldi(ctx, binding.stencil_op(prob.grid, prob.D, prob.vel), b, n)
+    assert rc == 0 and st["reductions"] == n + 2
+    say("oracle arnoldi 128^3 n=100")
+    ref = ar.dcgs2_arnoldi(lambda x: A @ x, b, n)
+    dh = relnorm(H, ref["H"])
+    say("H rel", dh)
+    assert dh <= TOL
+    loo = loss_of_orthogonality(Q)
+    say("loo", loo)
+    assert loo <= 1e-13
+    assert representation_error(A, Q, H, n) <= 1e-15

@@ -1,0 +1,121 @@
+"""GPU parity of dcgs2_qr (Alg. qr) against the FP64 oracle, through the C ABI.
+
+Gate: 1e-12 relative, normwise on the quantities that are unique at the given
+conditioning -- R, (Q - Q_oracle) R_oracle / ||B||, and raw Q where kappa(B) is
+small (raw Q at kappa ~ 1e8 differs between any two correct implementations by
+~ eps * kappa).
+"""
+import numpy as np
+import pytest
+
+from oracle import gram_schmidt as gs
+from oracle.metrics import loss_of_orthogonality, qr_error
+from paper_2104_01253_amd import binding, synth
+from tests._gpu import dev_matrix, host, relnorm, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch_cuda()
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def run_qr(ctx, B, ld=None):
+    Bd = dev_matrix(B, ld)
+    Qd = binding.colmajor_empty(B.shape[0], B.shape[1], ld)
+    R, rc, st = ctx.qr(Bd, Qd)
+    return host(Qd), R, rc, st
+
+
+@pytest.mark.parametrize("m,n,ce", [(1000, 1, 2), (1000, 2, 2), (1023, 3, 2), (4097, 17, 2),
+                                    (4097, 17, 8), (20011, 64, 8), (3000, 100, 4)])
+def test_qr_parity_small(ctx, m, n, ce):
+    say(f"qr parity m={m} n={n} kappa=1e{ce}")
+    B = synth.tall_skinny(m, n, ce, seed_g=100 + m, seed_v=7)
+    Q, R, rc, st = run_qr(ctx, B)
+    ref = gs.dcgs2_qr(B)
+    assert rc == binding.OK and ref["status"] == 0
+    assert relnorm(R, ref["R"]) <= TOL
+    assert np.linalg.norm((Q - ref["Q"]) @ ref["R"]) / np.linalg.norm(B) <= TOL
+    if ce <= 2:
+        assert np.linalg.norm(Q - ref["Q"]) / np.sqrt(n) <= TOL
+    assert st["reductions"] == ref["reductions"] == n + 1
+    assert loss_of_orthogonality(Q) <= 1e-13
+    assert qr_error(B, Q, R) <= 1e-14
+
+
+def test_qr_unaligned_leading_dimension(ctx):
+    """Odd ldq/ldb: the one-row (8-byte) kernel path."""
+    m, n = 5001, 12
+    B = synth.tall_skinny(m, n, 3)
+    Q, R, rc, _ = run_qr(ctx, B, ld=5003)
+    ref = gs.dcgs2_qr(B)
+    assert rc == 0
+    assert relnorm(R, ref["R"]) <= TOL
+    assert np.linalg.norm(Q - ref["Q"]) / np.sqrt(n) <= TOL
+
+
+def test_qr_deterministic(ctx):
+    B = synth.tall_skinny(300007, 30, 8)
+    Q1, R1, _, _ = run_qr(ctx, B)
+    Q2, R2, _, _ = run_qr(ctx, B)
+    assert np.array_equal(Q1, Q2) and np.array_equal(R1, R2)
+
+
+def test_qr_forced_fallback(ctx):
+    """tau = 1 forces the explicit-norm branch at every step (host-resumed)."""
+    B = synth.tall_skinny(7000, 15, 4)
+    ctx.set_tolerances(1.0, 1e-12)
+    try:
+        Q, R, rc, st = run_qr(ctx, B)
+    finally:
+        ctx.set_tolerances(1e-8, 1e-12)
+    ref = gs.dcgs2_qr(B, tau=1.0)
+    assert rc == 0
+    assert st["pyth_fallbacks"] == ref["fallbacks"] == 14
+    assert st["reductions"] == ref["reductions"]
+    assert relnorm(R, ref["R"]) <= TOL
+    assert np.linalg.norm(Q - ref["Q"]) / np.sqrt(15) <= TOL
+
+
+def test_qr_breakdown(ctx):
+    B = synth.tall_skinny(2000, 8, 2)
+    B[:, 3] = B[:, 0] - 2.0 * B[:, 2]
+    Q, R, rc, st = run_qr(ctx, B)
+    ref = gs.dcgs2_qr(B)
+    assert rc == binding.BREAKDOWN and ref["status"] == gs.BREAKDOWN
+    assert st["breakdown_step"] == ref["k"] == 3
+    assert relnorm(R[:3, :4], ref["R"][:3, :4]) <= TOL
+    assert np.linalg.norm(Q[:, :3] - ref["Q"][:, :3]) <= TOL
+
+
+def test_qr_nonfinite(ctx):
+    B = synth.tall_skinny(500, 6, 2)
+    B[17, 4] = np.nan
+    _, _, rc, st = run_qr(ctx, B)
+    assert rc == binding.NONFINITE
+    assert st["breakdown_step"] == gs.dcgs2_qr(B)["k"] == 3
+
+
+def test_qr_full_size_kappa_1e8(ctx):
+    """The tall-skinny workload at full size: m = 2,000,000, n = 100, kappa ~ 1e8."""
+    m, n = 2_000_000, 100
+    say("generating B 2e6 x 100")
+    B = synth.tall_skinny(m, n, 8.0)
+    say("gpu qr")
+    Q, R, rc, st = run_qr(ctx, B)
+    assert rc == 0 and st["reductions"] == n + 1
+    say("oracle qr")
+    ref = gs.dcgs2_qr(B)
+    assert relnorm(R, ref["R"]) <= TOL
+    dq = np.linalg.norm((Q - ref["Q"]) @ ref["R"]) / np.linalg.norm(B)
+    say("dQ R", dq)
+    assert dq <= TOL
+    loo = loss_of_orthogonality(Q)
+    say("loo", loo)
+    assert loo <= 1e-13

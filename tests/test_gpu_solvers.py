@@ -1,0 +1,120 @@
+"""GPU GMRES and Krylov-Schur against the oracle (through the C ABI)."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import operators as ops
+from oracle.gmres import gmres_dcgs2
+from oracle.krylov_schur import krylov_schur
+from paper_2104_01253_amd import binding, synth
+from tests._gpu import dev_vector, host, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def sigma_min(A, theta, iters=12):
+    import scipy.sparse as sp
+    M = (A.astype(complex) - theta * sp.identity(A.shape[0], dtype=complex, format="csr")).tocsc()
+    lu = spla.splu(M)
+    x = np.random.default_rng(0).standard_normal(A.shape[0]).astype(complex)
+    s = 0.0
+    for _ in range(iters):
+        x /= np.linalg.norm(x)
+        y = lu.solve(lu.solve(x), trans="H")
+        s = np.linalg.norm(y)
+        x = y
+    return 1.0 / np.sqrt(s)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch_cuda()
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("n,restart", [(16, 50), (32, 50), (24, 7)])
+def test_gmres_vs_oracle(ctx, n, restart):
+    torch = torch_cuda()
+    prob, b = synth.config3(n)
+    A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
+    op = binding.stencil_op(prob.grid, prob.D, prob.vel)
+    x = torch.zeros(prob.m, dtype=torch.float64, device="cuda")
+    rc, info = ctx.gmres(op, dev_vector(b), x, restart=restart, rtol=1e-8)
+    xr, iref = gmres_dcgs2(A, b, restart=restart, rtol=1e-8)
+    xg = host(x)
+    relres = np.linalg.norm(b - A @ xg) / np.linalg.norm(b)
+    say(f"gmres n={n}: gpu iters {info['iters']} cycles {info['cycles']} relres {relres:.3e};"
+        f" oracle iters {iref['iters']}")
+    assert rc == binding.OK
+    assert relres <= 1e-8
+    assert abs(info["relres_true"] - relres) <= 1e-12
+    assert abs(info["iters"] - iref["iters"]) <= 1
+    assert info["cycles"] == iref["cycles"]
+    assert np.linalg.norm(xg - xr) / np.linalg.norm(xr) <= 1e-6
+
+
+def test_gmres_zero_rhs_warm_start_and_budget(ctx):
+    torch = torch_cuda()
+    prob, b = synth.config3(12)
+    A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
+    op = binding.stencil_op(prob.grid, prob.D, prob.vel)
+    x = torch.full((prob.m,), 3.0, dtype=torch.float64, device="cuda")
+    rc, info = ctx.gmres(op, torch.zeros_like(x), x)
+    assert rc == 0 and info["iters"] == 0 and float(x.abs().max()) == 0.0
+    xs = spla.spsolve(A.tocsc(), b)
+    x = dev_vector(xs)
+    rc, info = ctx.gmres(op, dev_vector(b), x, restart=10)
+    assert rc == 0 and info["iters"] == 0
+    x = torch.zeros(prob.m, dtype=torch.float64, device="cuda")
+    rc, info = ctx.gmres(op, dev_vector(b), x, restart=20, rtol=1e-14, max_iters=30)
+    assert rc == binding.NOT_CONVERGED and info["iters"] == 30 and info["cycles"] == 2
+
+
+def test_gmres_full_size_128cube(ctx):
+    """GMRES(50) to 1e-8 on 3-D 128^3 (m = 2,097,152), v = (10,10,10), b ~ U(0,1)."""
+    torch = torch_cuda()
+    prob, b = synth.config3(128)
+    A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
+    op = binding.stencil_op(prob.grid, prob.D, prob.vel)
+    x = torch.zeros(prob.m, dtype=torch.float64, device="cuda")
+    rc, info = ctx.gmres(op, dev_vector(b), x, restart=50, rtol=1e-8)
+    relres = np.linalg.norm(b - A @ host(x)) / np.linalg.norm(b)
+    say("gmres 128^3", info, relres)
+    assert rc == 0 and relres <= 1e-8
+    assert 500 <= info["iters"] <= 800
+
+
+def test_krylov_schur_closed_form(ctx):
+    prob = synth.cd2d(24, vel=(4.0, 6.0))
+    A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
+    ref = ops.closed_form_eigenvalues(prob.grid, prob.D, prob.vel)[::-1][:10]
+    v0 = synth.normal_vector(prob.m, 5)
+    ev, rc, info = ctx.krylov_schur(binding.stencil_op(prob.grid, prob.D, prob.vel),
+                                    dev_vector(v0), nev=10, ncv=40, keep=16, tol=1e-10)
+    evo, io = krylov_schur(A, v0, nev=10, ncv=40, keep=16, tol=1e-10)
+    say("ks gpu", info, "oracle", io)
+    assert rc == 0
+    got = np.sort(ev.real)[::-1]
+    assert np.max(np.abs(ev.imag)) <= 1e-6 * ref[0]
+    assert np.max(np.abs(got - ref)) / ref[0] <= 1e-8
+    assert abs(info["restarts"] - io["restarts"]) <= 1
+
+
+def test_krylov_schur_config1_and_nonnormal(ctx):
+    for grid, vel, seed in [((32, 32), (10.0, 10.0), 0), ((48, 48), (50.0, 50.0), 1)]:
+        prob = synth.cd2d(grid[0], vel=vel)
+        A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
+        v0 = synth.normal_vector(prob.m, seed)
+        ev, rc, info = ctx.krylov_schur(binding.stencil_op(prob.grid, prob.D, prob.vel),
+                                        dev_vector(v0), nev=10, ncv=60, keep=20, tol=1e-8)
+        say("ks", grid, vel, info)
+        assert rc == 0 and info["resid"] <= 1e-8
+        # backward error of each Ritz value: smallest singular value of A - theta I,
+        # by inverse iteration on (A - theta I)^H (A - theta I) with a sparse LU
+        for th in ev:
+            assert sigma_min(A, th) <= 1e-6 * abs(th), th
+        if vel == (10.0, 10.0):
+            ref = ops.closed_form_eigenvalues(prob.grid, prob.D, prob.vel)[::-1][:10]
+            assert np.max(np.abs(np.sort(ev.real)[::-1] - ref)) / ref[0] <= 1e-8
