@@ -1,0 +1,224 @@
+"""Benchmark of the DCGS2 hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-legs]
+
+Headline workload (one bench "step"): the left-looking DCGS2 QR of the
+tall-skinny B = G diag(logspace(0,-8,100)) V, m = 2,000,000 x n = 100, FP64,
+resident in HBM -- 100 DCGS2 columns (steps) per factorisation.  `value` is DCGS2
+steps (columns) per second over the K timed factorisations.
+
+Also reported (not `value`): the DCGS2 Arnoldi expansion at m = 128^3 = 2,097,152
+with n = 100 (3-D convection-diffusion matvec), restarted GMRES(50) on the same
+operator to a 1e-8 true relative residual (time-to-solution), one Krylov-Schur
+solve, the per-kernel roofline figures measured with HIP events around each
+launch, and the FP64 oracle timed on the host on a bounded row sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published
+METRIC = "DCGS2 Arnoldi steps/s + HBM GB/s (m=2M,n=100); GMRES time-to-1e-8 vs FP64"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2104_01253_amd", "csrc", "kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+    when the kernels changed since the counters were taken."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t.get("kernels", {}).get(kernel, {}).get("bytes_per_launch")
+
+
+def timed(torch, fn, steps):
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1000.0
+
+
+def roofline(prof, wall_s=None):
+    dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
+    name, st = dom
+    avg_ms = st["total_ms"] / max(st["launches"], 1)
+    bytes_per_launch = st["bytes"] / max(st["launches"], 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    tr = measured_traffic(name)
+    return name, {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+        "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": tr,
+        "kernel": name, "launches": st["launches"], "avg_launch_us": round(avg_ms * 1e3, 2),
+        "alg_bytes_per_launch": bytes_per_launch,
+    }
+
+
+def cpu_baseline(B, n):
+    """The FP64 oracle (oracle.gram_schmidt.dcgs2_qr, unmodified) on the first rows of B."""
+    from oracle import gram_schmidt as gs
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    m = B.shape[0]
+    ms = min(m, 250_000)
+    sample = np.asfortranarray(B[:ms])
+    t0 = time.perf_counter()
+    gs.dcgs2_qr(sample)
+    dt = time.perf_counter() - t0
+    # the oracle's cost is linear in the number of rows: scale to the full m
+    t_full = dt * (m / ms)
+    return {"value": round(n / t_full, 3), "unit": "steps/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": f"dcgs2_qr of the first {ms} of {m} rows (all {n} columns), "
+                      f"{dt:.2f} s, scaled linearly in rows to m={m}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--m", type=int, default=2_000_000)
+    ap.add_argument("--n", type=int, default=100)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-legs", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the row-partitioned design is described in DESIGN.md); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2104_01253_amd import binding, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    m, n = args.m, args.n
+    log(f"[bench] generating B {m} x {n}, kappa ~ 1e8")
+    B = synth.tall_skinny(m, n, 8.0)
+    Bd = binding.colmajor_from_numpy(B)
+    Qd = binding.colmajor_empty(m, n)
+    ctx = binding.Context(0)
+
+    def qr_once():
+        _, rc, _ = ctx.qr(Bd, Qd)
+        assert rc == binding.OK, rc
+
+    log(f"[bench] warmup {args.warmup}")
+    for _ in range(args.warmup):
+        qr_once()
+    log(f"[bench] timing {args.steps} factorizations")
+    T = timed(torch, qr_once, args.steps)
+    ms_per_step = T / args.steps * 1e3
+    value = n * args.steps / T
+    # kernel durations: the same K factorizations again with HIP events around each launch
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    T_prof = timed(torch, qr_once, args.steps)
+    prof = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    prof = {k: v for k, v in prof.items() if v["launches"] > 0}
+    dom, roof = roofline(prof)
+    alg_bytes_step = sum(v["bytes"] for v in prof.values()) / args.steps
+    log(f"[bench] qr {ms_per_step:.3f} ms/factorization, {value:.1f} steps/s; "
+        f"dominant {dom} {roof['achieved']} GB/s")
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"dcgs2_qr: B = G diag(logspace(0,-8,{n})) V, m={m}, n={n}, "
+                               "fp64, resident in HBM; one step = one factorization",
+                   "m": m, "n": n, "cond": 1e8},
+        "hbm_gbps_step": round(alg_bytes_step / (ms_per_step * 1e-3) / 1e9, 1),
+        "alg_bytes_per_step": alg_bytes_step,
+        "profiled_ms_per_step": round(T_prof / args.steps * 1e3, 4),
+        "kernels": {k: {"launches": v["launches"], "avg_us": round(v["total_ms"] / v["launches"] * 1e3, 2),
+                        "gbps": round(v["bytes"] / (v["total_ms"] * 1e-3) / 1e9, 1) if v["total_ms"] > 0 else None}
+                    for k, v in prof.items()},
+        "roofline": roof,
+    }
+    del Bd, Qd
+    torch.cuda.empty_cache()
+
+    if not args.no_legs:
+        prob, b = synth.config3(128)
+        op = binding.stencil_op(prob.grid, prob.D, prob.vel)
+        bd = torch.from_numpy(b).cuda()
+        Qa = binding.colmajor_empty(prob.m, n + 1)
+
+        def arn_once():
+            _, rc, _ = ctx.arnoldi(op, bd, n, Qa)
+            assert rc == binding.OK, rc
+        arn_once()
+        Ta = timed(torch, arn_once, 3) / 3
+        ctx.profile(True)
+        ctx.profile_read(reset=True)
+        arn_once()
+        pa = ctx.profile_read(reset=True)
+        ctx.profile(False)
+        abytes = sum(v["bytes"] for v in pa.values())
+        out["arnoldi_128cube_n100"] = {"steps_per_s": round(n / Ta, 1), "ms": round(Ta * 1e3, 3),
+                                       "hbm_gbps": round(abytes / Ta / 1e9, 1)}
+        del Qa
+        x = torch.zeros(prob.m, dtype=torch.float64, device="cuda")
+
+        def gm_once():
+            x.zero_()
+            return ctx.gmres(op, bd, x, restart=50, rtol=1e-8)
+        gm_once()
+        t0 = time.perf_counter()
+        rc, info = gm_once()
+        tg = time.perf_counter() - t0
+        out["gmres50_128cube_fp64"] = {"time_to_1e-8_s": round(tg, 4), "iters": info["iters"],
+                                       "cycles": info["cycles"], "relres_true": info["relres_true"],
+                                       "status": rc}
+        ks = synth.cd2d(128, vel=(25.0, 40.0))
+        kop = binding.stencil_op(ks.grid, ks.D, ks.vel)
+        v0 = torch.from_numpy(synth.normal_vector(ks.m, 1)).cuda()
+        t0 = time.perf_counter()
+        ev, rc, kinfo = ctx.krylov_schur(kop, v0, nev=10, ncv=60, keep=20, tol=1e-8)
+        out["krylov_schur_128sq"] = {"time_s": round(time.perf_counter() - t0, 4),
+                                     "restarts": kinfo["restarts"], "matvecs": kinfo["matvecs"],
+                                     "status": rc}
+        log(f"[bench] legs: arnoldi {out['arnoldi_128cube_n100']}, gmres {out['gmres50_128cube_fp64']}")
+
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(B, n)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -97,12 +97,14 @@ typedef struct {
   dcgs2_stats st;
 } dcgs2_ks_info;
 
-/* Create a context on `device` (HIP ordinal).  `hip_stream` is a hipStream_t to
- * enqueue on, or NULL for a stream the context creates and owns.
+/* Create a context on `device` (HIP ordinal).  `hip_stream` is the hipStream_t to
+ * enqueue on; NULL selects the device's null (legacy default) stream, which is
+ * ordered with the other blocking streams of the process.  No device call is
+ * made here: the device is bound and the workspace allocated on first use.
  * Returns DCGS2_OK, DCGS2_EINVAL (out == NULL or bad device), DCGS2_EDEVICE. */
 int dcgs2_create(dcgs2_ctx* out, int device, void* hip_stream);
 
-/* Free the workspace (and the owned stream).  NULL is accepted. */
+/* Free the workspace.  NULL is accepted. */
 int dcgs2_destroy(dcgs2_ctx ctx);
 
 /* Tolerances of the two readings where the paper is silent (defaults 1e-8, 1e-12):
@@ -113,6 +115,14 @@ int dcgs2_destroy(dcgs2_ctx ctx);
  *         was projected from.
  * Returns DCGS2_EINVAL unless 0 <= tau and 0 <= eta < 1. */
 int dcgs2_set_tolerances(dcgs2_ctx ctx, double tau, double eta);
+
+/* Pass schedule of dcgs2_qr.  one_pass = 1 (default): the update of step j and the
+ * reduction of step j+1 share one read of Q (the next column a_{j+1} is already
+ * known in QR, so both use the same Q rows); the arithmetic and the one reduction
+ * per column are those of Alg. qr.  one_pass = 0: separate reduction and update
+ * passes, as for Arnoldi.  The one-pass schedule is used when n <= 502.
+ * Returns DCGS2_EINVAL unless one_pass is 0 or 1. */
+int dcgs2_set_qr_schedule(dcgs2_ctx ctx, int one_pass);
 
 /* Left-looking DCGS2 QR, Alg. qr (Sec. 3): B = Q R with one global reduction per
  * column, the last column finished by CGS2 (two reductions; end of Sec. 3).
@@ -166,6 +176,25 @@ int gmres_solve(dcgs2_ctx ctx, const dcgs2_op* A, const double* b, double* x,
 int krylov_schur_eigs(dcgs2_ctx ctx, const dcgs2_op* A, int32_t nev, int32_t ncv, int32_t keep,
                       double tol, int32_t max_restarts, const double* v0,
                       double* eig_re_host, double* eig_im_host, dcgs2_ks_info* info);
+
+/* Kernel timing.  While enabled, every kernel launch of the context is
+ * bracketed by two HIP events on the context stream; the device duration of
+ * each launch and its algorithmic HBM bytes (the bytes the method must move:
+ * basis columns read once, vectors read/written once) accumulate per kernel
+ * class ("spmv", "reduce", "update", "project_norm", "scale", "tsgemm",
+ * "fused_qr", "aux").
+ * dcgs2_profile_read synchronises the stream, writes up to max_entries records
+ * and returns the number of classes (>= 0), or DCGS2_EINVAL; reset != 0 clears
+ * the accumulators afterwards. */
+typedef struct {
+  char name[24];
+  int64_t launches;
+  double total_ms;          /* summed device time of the launches               */
+  double bytes;             /* summed algorithmic HBM bytes of the launches     */
+} dcgs2_kernel_stat;
+
+int dcgs2_profile_enable(dcgs2_ctx ctx, int enable);
+int dcgs2_profile_read(dcgs2_ctx ctx, dcgs2_kernel_stat* out, int32_t max_entries, int32_t reset);
 
 /* y = A x (device vectors of length A->m).  The matvec of step a1; exported so
  * the operator can be checked on its own. */

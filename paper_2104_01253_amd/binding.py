@@ -22,7 +22,8 @@ OP_CSR, OP_STENCIL5, OP_STENCIL7 = 0, 1, 2
 MAX_N = 1024
 
 EXPORTS = ("dcgs2_create", "dcgs2_destroy", "dcgs2_set_tolerances", "dcgs2_qr", "dcgs2_arnoldi",
-           "gmres_solve", "krylov_schur_eigs", "dcgs2_apply", "dcgs2_status_str")
+           "gmres_solve", "krylov_schur_eigs", "dcgs2_apply", "dcgs2_status_str",
+           "dcgs2_profile_enable", "dcgs2_profile_read", "dcgs2_set_qr_schedule")
 
 
 class Stats(ctypes.Structure):
@@ -38,6 +39,11 @@ class Op(ctypes.Structure):
                 ("val", c_void_p), ("nnz", c_int64), ("nx", c_int32), ("ny", c_int32),
                 ("nz", c_int32), ("c0", c_double), ("cxm", c_double), ("cxp", c_double),
                 ("cym", c_double), ("cyp", c_double), ("czm", c_double), ("czp", c_double)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", c_int64), ("total_ms", c_double),
+                ("bytes", c_double)]
 
 
 class GmresInfo(ctypes.Structure):
@@ -73,10 +79,14 @@ def load(path: str = LIB_PATH):
     lib.krylov_schur_eigs.argtypes = [c_void_p, POINTER(Op), c_int32, c_int32, c_int32, c_double,
                                       c_int32, c_void_p, c_void_p, c_void_p, POINTER(KsInfo)]
     lib.dcgs2_apply.argtypes = [c_void_p, POINTER(Op), c_void_p, c_void_p]
+    lib.dcgs2_profile_enable.argtypes = [c_void_p, c_int]
+    lib.dcgs2_set_qr_schedule.argtypes = [c_void_p, c_int]
+    lib.dcgs2_profile_read.argtypes = [c_void_p, POINTER(KernelStat), c_int32, c_int32]
     lib.dcgs2_status_str.argtypes = [c_int]
     lib.dcgs2_status_str.restype = ctypes.c_char_p
     for name in ("dcgs2_create", "dcgs2_destroy", "dcgs2_set_tolerances", "dcgs2_qr",
-                 "dcgs2_arnoldi", "gmres_solve", "krylov_schur_eigs", "dcgs2_apply"):
+                 "dcgs2_arnoldi", "gmres_solve", "krylov_schur_eigs", "dcgs2_apply",
+                 "dcgs2_profile_enable", "dcgs2_profile_read", "dcgs2_set_qr_schedule"):
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -278,6 +288,25 @@ class Context:
         out = {k: getattr(info, k) for k, _ in KsInfo._fields_ if k != "st"}
         out["stats"] = info.st.as_dict()
         return re + 1j * im, rc, out
+
+    def set_qr_schedule(self, one_pass: bool):
+        rc = self._lib.dcgs2_set_qr_schedule(self._h, 1 if one_pass else 0)
+        if rc != OK:
+            raise DCGS2Error(rc, "dcgs2_set_qr_schedule")
+
+    def profile(self, enable: bool = True):
+        rc = self._lib.dcgs2_profile_enable(self._h, 1 if enable else 0)
+        if rc != OK:
+            raise DCGS2Error(rc, "dcgs2_profile_enable")
+
+    def profile_read(self, reset: bool = True):
+        """Per-kernel-class {launches, total_ms, bytes} accumulated since the last reset."""
+        arr = (KernelStat * 16)()
+        n = self._lib.dcgs2_profile_read(self._h, arr, 16, 1 if reset else 0)
+        if n < 0:
+            raise DCGS2Error(n, "dcgs2_profile_read")
+        return {arr[i].name.decode(): dict(launches=arr[i].launches, total_ms=arr[i].total_ms,
+                                          bytes=arr[i].bytes) for i in range(n)}
 
     def apply(self, op: Op, x, y):
         rc = self._lib.dcgs2_apply(self._h, ctypes.byref(op), _vec_ptr(x, "x", op.m),

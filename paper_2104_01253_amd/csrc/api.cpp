@@ -38,6 +38,7 @@ struct dcgs2_ctx_s {
   bool own_stream = false;
   bool ready = false;
   double tau = 1e-8, eta = 1e-12;
+  bool qr_one_pass = true;
   int64_t cap_m = 0;
   int64_t cap_qa = 0, cap_qb = 0;
   double *w = nullptr, *v = nullptr, *r = nullptr;
@@ -50,6 +51,13 @@ struct dcgs2_ctx_s {
   Ctrl* ctrl = nullptr;
   Ctrl* ctrl_host = nullptr;       // pinned
   int kernels = 0;
+  // kernel timing (dcgs2_profile_enable): HIP events bracket each launch
+  struct ProfRec { int cls; hipEvent_t a, b; double bytes; };
+  struct ProfAcc { int64_t launches = 0; double ms = 0.0, bytes = 0.0; };
+  bool prof = false;
+  std::vector<hipEvent_t> evpool;
+  std::vector<ProfRec> pending;
+  ProfAcc acc[16];
 };
 
 namespace {
@@ -65,6 +73,56 @@ namespace {
     hipError_t e_ = (call);                        \
     if (e_ != hipSuccess) return DCGS2_EDEVICE;    \
     ++c->kernels;                                  \
+  } while (0)
+
+// Kernel classes reported by dcgs2_profile_read.
+enum KClass { K_SPMV = 0, K_REDUCE, K_UPDATE, K_PROJNORM, K_SCALE, K_TSGEMM, K_FUSED, K_AUX,
+              K_NCLASS };
+const char* const kClassName[K_NCLASS] = {"spmv", "reduce", "update", "project_norm",
+                                          "scale", "tsgemm", "fused_qr", "aux"};
+
+hipEvent_t prof_event(dcgs2_ctx c) {
+  if (!c->evpool.empty()) {
+    hipEvent_t e = c->evpool.back();
+    c->evpool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Fold completed launch timings into the accumulators (call after a stream sync).
+void prof_resolve(dcgs2_ctx c) {
+  for (auto& r : c->pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      c->acc[r.cls].launches += 1;
+      c->acc[r.cls].ms += ms;
+      c->acc[r.cls].bytes += r.bytes;
+    }
+    c->evpool.push_back(r.a);
+    c->evpool.push_back(r.b);
+  }
+  c->pending.clear();
+}
+
+// Launch with optional timing: KL(class, algorithmic HBM bytes, launcher call).
+#define KL(cls, nbytes, call)                                            \
+  do {                                                                   \
+    hipEvent_t ea_ = nullptr, eb_ = nullptr;                             \
+    if (c->prof) {                                                       \
+      ea_ = prof_event(c);                                               \
+      eb_ = prof_event(c);                                               \
+      if (ea_) (void)hipEventRecord(ea_, c->stream);                     \
+    }                                                                    \
+    hipError_t e_ = (call);                                              \
+    if (e_ != hipSuccess) return DCGS2_EDEVICE;                          \
+    ++c->kernels;                                                        \
+    if (c->prof && ea_ && eb_) {                                         \
+      (void)hipEventRecord(eb_, c->stream);                              \
+      c->pending.push_back({(int)(cls), ea_, eb_, (double)(nbytes)});    \
+    }                                                                    \
   } while (0)
 
 int dalloc(void** p, size_t bytes) {
@@ -85,10 +143,6 @@ int ctx_ready(dcgs2_ctx c) {
   if (hipGetDeviceCount(&count) != hipSuccess || c->device < 0 || c->device >= count)
     return DCGS2_EDEVICE;
   CK(hipSetDevice(c->device));
-  if (!c->stream) {
-    CK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
-    c->own_stream = true;
-  }
   int rc;
   if ((rc = dalloc((void**)&c->P1, sizeof(double) * (size_t)REDUCE_GMAX * LDP))) return rc;
   if ((rc = dalloc((void**)&c->P2, sizeof(double) * (size_t)REDUCE_GSMAX * LDP))) return rc;
@@ -147,6 +201,7 @@ int read_ctrl(dcgs2_ctx c, Ctrl* out) {
   CK(hipMemcpyAsync(c->ctrl_host, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
   CK(hipStreamSynchronize(c->stream));
   *out = *c->ctrl_host;
+  if (c->prof) prof_resolve(c);
   return DCGS2_OK;
 }
 
@@ -177,11 +232,19 @@ OpDev to_dev(const dcgs2_op* A) {
   OpDev o;
   o.kind = A->kind;
   o.m = A->m;
-  o.rowptr = A->rowptr; o.colind = A->colind; o.val = A->val;
+  o.rowptr = A->rowptr; o.colind = A->colind; o.val = A->val; o.nnz = A->nnz;
   o.nx = A->nx; o.ny = A->ny; o.nz = A->kind == DCGS2_OP_STENCIL7 ? A->nz : 1;
   o.c0 = A->c0; o.cxm = A->cxm; o.cxp = A->cxp; o.cym = A->cym; o.cyp = A->cyp;
   o.czm = A->czm; o.czp = A->czp;
   return o;
+}
+
+// Algorithmic HBM bytes of one matvec: a stencil reads x once (neighbours come
+// from cache) and writes y; CSR also streams its arrays.
+double op_bytes(const OpDev& op) {
+  const double m = (double)op.m;
+  if (op.kind == DCGS2_OP_CSR) return 16.0 * m + 4.0 * (m + 1) + 12.0 * (double)op.nnz;
+  return 16.0 * m;
 }
 
 // One expansion (QR or Arnoldi) over a basis Q.
@@ -195,6 +258,7 @@ struct Expansion {
   const double* B = nullptr;    // QR input columns
   int64_t ldb = 0;
   OpDev op{};                   // Arnoldi operator
+  bool one_pass = false;        // QR: fuse update(j) with the reduction of step j+1
   int ldh = 0;                  // leading dimension of H/K/Rg (Arnoldi) or R (QR)
   GridRed gr{};
 
@@ -208,28 +272,75 @@ struct Expansion {
     return f;
   }
   const double* ycol(int j) const { return qr ? B + (int64_t)(j - 1) * ldb : c->v; }
+  double spmv_bytes() const { return op_bytes(op); }
 
   int enqueue_step(int j, int kind) {
     const int J = j - 2;
     hipStream_t s = c->stream;
-    if (!qr) CKL(launch_spmv(op, c->w, nullptr, c->v, c->ctrl, s));
-    CKL(launch_reduce(Q, ldq, J, c->w, ycol(j), m, gr, fin(kind, j, J), s));
-    CKL(launch_update(Q, ldq, J, c->w, ycol(j), m, c->coef, LDC, !qr, 0, c->ctrl, s));
+    const double vm = 8.0 * (double)m;
+    if (!qr) KL(K_SPMV, spmv_bytes(), launch_spmv(op, c->w, nullptr, c->v, c->ctrl, s));
+    KL(K_REDUCE, vm * (J + 2), launch_reduce(Q, ldq, J, c->w, ycol(j), m, gr, fin(kind, j, J), s));
+    KL(K_UPDATE, vm * (J + 4),
+       launch_update(Q, ldq, J, c->w, ycol(j), m, c->coef, LDC, !qr, 0, c->ctrl, s));
     return DCGS2_OK;
   }
   int enqueue_fallback(int j) {
     const int J = j - 2;
     hipStream_t s = c->stream;
-    CKL(launch_project_norm(Q, ldq, J, c->w, m, gr, fin(FIN_FALLBACK, j, J), s));
-    CKL(launch_update(Q, ldq, J, c->w, ycol(j), m, c->coef, LDC, !qr, 1, c->ctrl, s));
+    const double vm = 8.0 * (double)m;
+    KL(K_PROJNORM, vm * (J + 2),
+       launch_project_norm(Q, ldq, J, c->w, m, gr, fin(FIN_FALLBACK, j, J), s));
+    KL(K_UPDATE, vm * (J + 5),
+       launch_update(Q, ldq, J, c->w, ycol(j), m, c->coef, LDC, !qr, 1, c->ctrl, s));
     return DCGS2_OK;
   }
   // CGS2 finish of the last column: J final columns already in Q.
   int enqueue_last(int J, int jvirt) {
     hipStream_t s = c->stream;
-    CKL(launch_reduce(Q, ldq, J, c->w, nullptr, m, gr, fin(FIN_LAST1, jvirt, J), s));
-    CKL(launch_project_norm(Q, ldq, J, c->w, m, gr, fin(FIN_LAST2, jvirt, J), s));
-    CKL(launch_scale_col(Q, ldq, J, m, c->coef, LDC, c->ctrl, s));
+    const double vm = 8.0 * (double)m;
+    KL(K_REDUCE, vm * (J + 1),
+       launch_reduce(Q, ldq, J, c->w, nullptr, m, gr, fin(FIN_LAST1, jvirt, J), s));
+    KL(K_PROJNORM, vm * (J + 2),
+       launch_project_norm(Q, ldq, J, c->w, m, gr, fin(FIN_LAST2, jvirt, J), s));
+    KL(K_SCALE, vm * 2, launch_scale_col(Q, ldq, J, m, c->coef, LDC, c->ctrl, s));
+    return DCGS2_OK;
+  }
+  GridRed fused_grid(int J, int last) const {
+    GridRed g = gr;
+    g.G = fused_qr_grid(m, J, last);
+    g.GS = g.G < REDUCE_GSMAX ? g.G : REDUCE_GSMAX;
+    g.NG = (g.G + g.GS - 1) / g.GS;
+    return g;
+  }
+  // One-pass QR schedule for steps j0..j_to: reduce(j0), then fused(j) =
+  // update(j) + reduction(j+1) for j < j_to, then update(j_to) fused with the
+  // first reduction of the last-column finish.
+  int enqueue_one_pass(int j0, int kind0, int j_to, int J_last) {
+    hipStream_t s = c->stream;
+    const double vm = 8.0 * (double)m;
+    if (j0 > j_to) return J_last >= 0 ? enqueue_last(J_last, j_to + 1) : DCGS2_OK;
+    KL(K_REDUCE, vm * (j0 - 2 + 2),
+       launch_reduce(Q, ldq, j0 - 2, c->w, ycol(j0), m, gr, fin(kind0, j0, j0 - 2), s));
+    for (int j = j0; j <= j_to; ++j) {
+      const int J = j - 2;
+      const bool last = (j == j_to);
+      if (last && J_last < 0) {
+        KL(K_UPDATE, vm * (J + 4),
+           launch_update(Q, ldq, J, c->w, ycol(j), m, c->coef, LDC, 0, 0, c->ctrl, s));
+        break;
+      }
+      const GridRed g = fused_grid(J, last ? 1 : 0);
+      const FinArgs f = last ? fin(FIN_LAST1, j + 1, J + 1) : fin(FIN_STEP, j + 1, J + 1);
+      // bytes: Q_{0..J-1}, w, a_j, a_{j+1} read; q, w written
+      KL(K_FUSED, vm * (J + (last ? 4 : 5)),
+         launch_fused_qr(Q, ldq, J, c->w, ycol(j), last ? nullptr : ycol(j + 1), m, c->coef,
+                         LDC, last ? 1 : 0, g, f, s));
+    }
+    if (J_last >= 0) {
+      KL(K_PROJNORM, vm * (J_last + 2),
+         launch_project_norm(Q, ldq, J_last, c->w, m, gr, fin(FIN_LAST2, j_to + 1, J_last), s));
+      KL(K_SCALE, vm * 2, launch_scale_col(Q, ldq, J_last, m, c->coef, LDC, c->ctrl, s));
+    }
     return DCGS2_OK;
   }
   // Steps j_from..j_to (the first one of kind first_kind), then the last-column
@@ -246,10 +357,14 @@ struct Expansion {
         ++j0;
         kind0 = FIN_STEP;
       }
-      for (int j = j0; j <= j_to; ++j) {
-        if ((rc = enqueue_step(j, j == j0 ? kind0 : FIN_STEP))) return rc;
+      if (one_pass) {
+        if ((rc = enqueue_one_pass(j0, kind0, j_to, J_last))) return rc;
+      } else {
+        for (int j = j0; j <= j_to; ++j) {
+          if ((rc = enqueue_step(j, j == j0 ? kind0 : FIN_STEP))) return rc;
+        }
+        if (J_last >= 0 && (rc = enqueue_last(J_last, j_to + 1))) return rc;
       }
-      if (J_last >= 0 && (rc = enqueue_last(J_last, j_to + 1))) return rc;
       if ((rc = read_ctrl(c, out))) return rc;
       if (out->state != ST_FALLBACK) return DCGS2_OK;
       j0 = out->stop_step;
@@ -329,6 +444,8 @@ int dcgs2_destroy(dcgs2_ctx c) {
     for (double* b : bufs) dfree(b);
     dfree(c->cnt);
     dfree(c->ctrl);
+    prof_resolve(c);
+    for (hipEvent_t ev : c->evpool) (void)hipEventDestroy(ev);
     if (c->ctrl_host) (void)hipHostFree(c->ctrl_host);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   }
@@ -341,6 +458,38 @@ int dcgs2_set_tolerances(dcgs2_ctx c, double tau, double eta) {
   c->tau = tau;
   c->eta = eta;
   return DCGS2_OK;
+}
+
+int dcgs2_set_qr_schedule(dcgs2_ctx c, int one_pass) {
+  if (!c || (one_pass != 0 && one_pass != 1)) return DCGS2_EINVAL;
+  c->qr_one_pass = one_pass == 1;
+  return DCGS2_OK;
+}
+
+int dcgs2_profile_enable(dcgs2_ctx c, int enable) {
+  if (!c) return DCGS2_EINVAL;
+  c->prof = enable != 0;
+  return DCGS2_OK;
+}
+
+int dcgs2_profile_read(dcgs2_ctx c, dcgs2_kernel_stat* out, int32_t max_entries, int32_t reset) {
+  if (!c || (max_entries > 0 && !out) || max_entries < 0) return DCGS2_EINVAL;
+  if (c->ready) {
+    CK(hipSetDevice(c->device));
+    CK(hipStreamSynchronize(c->stream));
+    prof_resolve(c);
+  }
+  const int n = std::min<int>(max_entries, K_NCLASS);
+  for (int i = 0; i < n; ++i) {
+    std::memset(&out[i], 0, sizeof(out[i]));
+    std::snprintf(out[i].name, sizeof(out[i].name), "%s", kClassName[i]);
+    out[i].launches = c->acc[i].launches;
+    out[i].total_ms = c->acc[i].ms;
+    out[i].bytes = c->acc[i].bytes;
+  }
+  if (reset)
+    for (auto& a : c->acc) a = dcgs2_ctx_s::ProfAcc();
+  return K_NCLASS;
 }
 
 int dcgs2_apply(dcgs2_ctx c, const dcgs2_op* A, const double* x, double* y) {
@@ -366,6 +515,7 @@ int dcgs2_qr(dcgs2_ctx c, int64_t m, int32_t n, const double* B, int64_t ldb, do
   e.m = m;
   e.Q = Q; e.ldq = ldq; e.B = B; e.ldb = ldb;
   e.ldh = n;
+  e.one_pass = c->qr_one_pass && n - 2 <= FUSED_QR_MAX_J;
   if ((rc = setup_expansion(c, e, 0.0))) return rc;
   CKL(launch_fill(c->R, (int64_t)n * n, 0.0, c->stream));
   CKL(launch_copy(c->w, B, m, c->stream));               // w_1 = a_1
@@ -442,7 +592,7 @@ int gmres_solve(dcgs2_ctx c, const dcgs2_op* A, const double* b, double* x, int3
     for (;;) {
       // r = b - A x into w (w_1 of the cycle), then ||r||
       if ((rc = setup_expansion(c, e, rtol * bnorm))) return rc;
-      CKL(launch_spmv(e.op, x, b, c->w, nullptr, c->stream));
+      KL(K_SPMV, op_bytes(e.op) + 8.0 * m, launch_spmv(e.op, x, b, c->w, nullptr, c->stream));
       CKL(launch_reduce(nullptr, ldq, 0, c->w, nullptr, m, e.gr, e.fin(FIN_NORM, 0, 0),
                         c->stream));
       if ((rc = read_ctrl(c, &s))) return rc;
@@ -481,7 +631,7 @@ int gmres_solve(dcgs2_ctx c, const dcgs2_op* A, const double* b, double* x, int3
         y[i] = sum / Rh[(size_t)i * ld + i];
       }
       CK(hipMemcpyAsync(c->Z, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, c->stream));
-      CKL(launch_tsgemm(c->Qa, ldq, k, c->Z, k, 1, x, m, m, 1, c->stream));
+      KL(K_TSGEMM, 8.0 * m * (k + 2), launch_tsgemm(c->Qa, ldq, k, c->Z, k, 1, x, m, m, 1, c->stream));
     }
   }
   inf.status = status;
@@ -553,7 +703,8 @@ int krylov_schur_eigs(dcgs2_ctx c, const dcgs2_op* A, int32_t nev, int32_t ncv, 
     if (k < 0 || k >= p) { status = DCGS2_NOT_CONVERGED; break; }
     CK(hipMemcpyAsync(c->Z, Zm.data(), sizeof(double) * (size_t)p * k, hipMemcpyHostToDevice,
                       c->stream));
-    CKL(launch_tsgemm(c->Qa, ldq, p, c->Z, p, k, c->Qb, ldq, m, 0, c->stream));   // Q_p Z_k
+    KL(K_TSGEMM, 8.0 * m * (p + k),
+       launch_tsgemm(c->Qa, ldq, p, c->Z, p, k, c->Qb, ldq, m, 0, c->stream));   // Q_p Z_k
     CKL(launch_copy(c->Qb + (int64_t)k * ldq, c->Qa + (int64_t)p * ldq, m, c->stream));
     CKL(launch_copy(c->w, c->Qa + (int64_t)p * ldq, m, c->stream));          // w = q_{k+1}
     std::fill(Hn.begin(), Hn.end(), 0.0);

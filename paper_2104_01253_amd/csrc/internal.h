@@ -71,6 +71,7 @@ struct OpDev {
   int kind;
   int64_t m;
   const int32_t* rowptr; const int32_t* colind; const double* val;
+  int64_t nnz;
   int nx, ny, nz;
   double c0, cxm, cxp, cym, cyp, czm, czp;
 };
@@ -101,6 +102,14 @@ hipError_t launch_project_norm(double* Q, int64_t ldq, int J, const double* x, i
 hipError_t launch_update(double* Q, int64_t ldq, int J, double* x, const double* y,
                          int64_t m, const double* coef, int ldc, int arnoldi, int qcol,
                          const Ctrl* ctrl, hipStream_t s);
+// One-pass QR step: update of step j (q into Q[:, J], w <- w_j) fused with the
+// reduction of step j+1 over [Q_{0..J}, w_j, a_next]; last != 0 reduces only
+// [Q_{0..J}, w_j]^T w_j (a_next unused).  gr.G must equal fused_qr_grid(m, J, last).
+hipError_t launch_fused_qr(double* Q, int64_t ldq, int J, double* w, const double* a_cur,
+                           const double* a_next, int64_t m, const double* coef, int ldc, int last,
+                           const GridRed& gr, const FinArgs& fin, hipStream_t s);
+int fused_qr_grid(int64_t m, int J, int last);
+constexpr int FUSED_QR_MAX_J = 500;       // columns owned one per thread (512 per workgroup)
 // Q[:, J] /= alpha (coef[2 ldc]) when ctrl->state == RUNNING.
 hipError_t launch_scale_col(double* Q, int64_t ldq, int J, int64_t m, const double* coef,
                             int ldc, const Ctrl* ctrl, hipStream_t s);

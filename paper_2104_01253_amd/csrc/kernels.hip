@@ -110,7 +110,7 @@ __device__ bool grid_reduce(const GridRed& gr, int V, double* red) {
   __syncthreads();
   if (!s_last) return false;
   __threadfence();
-  for (int v = threadIdx.x; v < V; v += BS) {
+  for (int v = threadIdx.x; v < V; v += (int)blockDim.x) {
     double s = 0.0;
     for (int b = 0; b < gsz; ++b) s += gr.P1[(int64_t)(g0 + b) * gr.ldp + v];
     if (gr.NG == 1) red[v] = s;
@@ -127,7 +127,7 @@ __device__ bool grid_reduce(const GridRed& gr, int V, double* red) {
   __syncthreads();
   if (!s_last) return false;
   __threadfence();
-  for (int v = threadIdx.x; v < V; v += BS) {
+  for (int v = threadIdx.x; v < V; v += (int)blockDim.x) {
     double s = 0.0;
     for (int g = 0; g < gr.NG; ++g) s += gr.P2[(int64_t)g * gr.ldp + v];
     red[v] = s;
@@ -156,7 +156,7 @@ __device__ void any_nonfinite(const double* v, int n, int* flag) {
   if (threadIdx.x == 0) *flag = 0;
   __syncthreads();
   int bad = 0;
-  for (int i = threadIdx.x; i < n; i += BS) bad |= !finite(v[i]);
+  for (int i = threadIdx.x; i < n; i += (int)blockDim.x) bad |= !finite(v[i]);
   if (bad) atomicOr(flag, 1);
   __syncthreads();
 }
@@ -169,8 +169,8 @@ __device__ void gmres_givens(const FinArgs& f, int c, int j, double* sh) {
   double* h = sh;
   double* cs = sh + (c + 2);
   double* sn = cs + (c + 1);
-  for (int i = threadIdx.x; i <= c + 1; i += BS) h[i] = f.H[(int64_t)c * f.ldh + i];
-  for (int i = threadIdx.x; i < c; i += BS) { cs[i] = f.cs[i]; sn[i] = f.sn[i]; }
+  for (int i = threadIdx.x; i <= c + 1; i += (int)blockDim.x) h[i] = f.H[(int64_t)c * f.ldh + i];
+  for (int i = threadIdx.x; i < c; i += (int)blockDim.x) { cs[i] = f.cs[i]; sn[i] = f.sn[i]; }
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int i = 0; i < c; ++i) {
@@ -197,7 +197,7 @@ __device__ void gmres_givens(const FinArgs& f, int c, int j, double* sh) {
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i <= c; i += BS) f.Rg[(int64_t)c * f.ldh + i] = h[i];
+  for (int i = threadIdx.x; i <= c; i += (int)blockDim.x) f.Rg[(int64_t)c * f.ldh + i] = h[i];
   __syncthreads();
 }
 
@@ -207,7 +207,7 @@ __device__ void gmres_givens(const FinArgs& f, int c, int j, double* sh) {
 __device__ void complete_h_column(const FinArgs& f, const double* C, int J, double alpha,
                                   double* scratch) {
   const int col = J - 1;
-  for (int i = threadIdx.x; i < J; i += BS)
+  for (int i = threadIdx.x; i < J; i += (int)blockDim.x)
     f.H[(int64_t)col * f.ldh + i] = f.K[(int64_t)col * f.ldh + i] + C[i];
   if (threadIdx.x == 0) f.H[(int64_t)col * f.ldh + J] = alpha;
   __syncthreads();
@@ -229,7 +229,7 @@ __device__ void step_tail(const FinArgs& f, const double* C, const double* S, do
   }
   if (alpha <= ctrl->eta * rho) {                 // breakdown: close column j-2 and stop
     if (f.qr) {
-      for (int i = threadIdx.x; i < J; i += BS) f.R[(int64_t)J * f.ldr + i] = f.Sprev[i] + C[i];
+      for (int i = threadIdx.x; i < J; i += (int)blockDim.x) f.R[(int64_t)J * f.ldr + i] = f.Sprev[i] + C[i];
       if (threadIdx.x == 0) f.R[(int64_t)J * f.ldr + J] = alpha;
       __syncthreads();
       if (threadIdx.x == 0) ctrl->k = J;
@@ -244,25 +244,25 @@ __device__ void step_tail(const FinArgs& f, const double* C, const double* S, do
   }
   // T_{1:j-2} = S/alpha, T_{j-1} = (sigma - C^T S)/alpha^2 (Arnoldi);
   // S_{j-1,j} = (sigma - C^T S)/alpha (QR, Stephen's trick)
-  for (int i = threadIdx.x; i < J; i += BS) T[i] = f.qr ? S[i] : S[i] / alpha;
+  for (int i = threadIdx.x; i < J; i += (int)blockDim.x) T[i] = f.qr ? S[i] : S[i] / alpha;
   if (threadIdx.x == 0) T[J] = f.qr ? (sigma - csum) / alpha : (sigma - csum) / (alpha * alpha);
   __syncthreads();
-  for (int i = threadIdx.x; i < J; i += BS) f.coef[i] = C[i];
-  for (int i = threadIdx.x; i <= J; i += BS) f.coef[f.ldc + i] = T[i];
+  for (int i = threadIdx.x; i < J; i += (int)blockDim.x) f.coef[i] = C[i];
+  for (int i = threadIdx.x; i <= J; i += (int)blockDim.x) f.coef[f.ldc + i] = T[i];
   if (threadIdx.x == 0) f.coef[2 * f.ldc] = alpha;
   if (f.qr) {
     // R_{1:j-2, j-1} = S_{1:j-2, j-1} + C ; R_{j-1,j-1} = alpha ; keep S_{1:j-1, j}
-    for (int i = threadIdx.x; i < J; i += BS) f.R[(int64_t)J * f.ldr + i] = f.Sprev[i] + C[i];
+    for (int i = threadIdx.x; i < J; i += (int)blockDim.x) f.R[(int64_t)J * f.ldr + i] = f.Sprev[i] + C[i];
     if (threadIdx.x == 0) f.R[(int64_t)J * f.ldr + J] = alpha;
     __syncthreads();
-    for (int i = threadIdx.x; i <= J; i += BS) f.Sprev[i] = T[i];
+    for (int i = threadIdx.x; i <= J; i += (int)blockDim.x) f.Sprev[i] = T[i];
     if (threadIdx.x == 0) { ctrl->k = J + 1; ctrl->rho_next = sqrt(gamma); }
   } else {
     if (f.gmres && j == 2 && threadIdx.x == 0) f.g[0] = alpha;   // beta e_1 of the cycle
     if (j >= 3) complete_h_column(f, C, J, alpha, scratch);      // lines 10 and 12
     __syncthreads();
     // line 11: K_{1:j-1, j-1} = T - (1/alpha) H_{1:j-1, 1:j-2} C   (dense product)
-    for (int i = threadIdx.x; i <= J; i += BS) {
+    for (int i = threadIdx.x; i <= J; i += (int)blockDim.x) {
       double hc = 0.0;
       for (int c = 0; c < J; ++c) hc = fma(f.H[(int64_t)c * f.ldh + i], C[c], hc);
       f.K[(int64_t)J * f.ldh + i] = T[i] - hc / alpha;
@@ -289,7 +289,7 @@ __device__ void finalize(const FinArgs& f, double* red, double* T, double* scrat
         if (s_flag) { ctrl->state = ST_NONFINITE; ctrl->stop_step = j; }
         if (J == 0) ctrl->rho_next = sqrt(red[0]);   // single-column QR: rho = ||a_1||
       }
-      for (int i = threadIdx.x; i < J; i += BS) f.coef[i] = red[i];
+      for (int i = threadIdx.x; i < J; i += (int)blockDim.x) f.coef[i] = red[i];
       return;
     }
     case FIN_LAST2: {                      // alpha = ||w - Q c||, close the last column
@@ -300,11 +300,11 @@ __device__ void finalize(const FinArgs& f, double* red, double* T, double* scrat
         if (threadIdx.x == 0) { ctrl->state = ST_NONFINITE; ctrl->stop_step = j; }
         return;
       }
-      for (int i = threadIdx.x; i < J; i += BS) T[i] = c[i];   // c into LDS
+      for (int i = threadIdx.x; i < J; i += (int)blockDim.x) T[i] = c[i];   // c into LDS
       __syncthreads();
       const bool brk = alpha <= ctrl->eta * ctrl->rho_next;
       if (f.qr) {
-        for (int i = threadIdx.x; i < J; i += BS) f.R[(int64_t)J * f.ldr + i] = f.Sprev[i] + T[i];
+        for (int i = threadIdx.x; i < J; i += (int)blockDim.x) f.R[(int64_t)J * f.ldr + i] = f.Sprev[i] + T[i];
         if (threadIdx.x == 0) {
           f.R[(int64_t)J * f.ldr + J] = alpha;
           ctrl->k = brk ? J : J + 1;
@@ -327,10 +327,10 @@ __device__ void finalize(const FinArgs& f, double* red, double* T, double* scrat
         if (threadIdx.x == 0) { ctrl->state = ST_NONFINITE; ctrl->stop_step = j; ctrl->reductions += 1; }
         return;
       }
-      for (int i = threadIdx.x; i < J; i += BS) { T[i] = S[i]; f.coef[i] = 0.0; }
+      for (int i = threadIdx.x; i < J; i += (int)blockDim.x) { T[i] = S[i]; f.coef[i] = 0.0; }
       if (threadIdx.x == 0) T[J] = S[J];   // sigma = q_{k+1}^T v
       __syncthreads();
-      for (int i = threadIdx.x; i <= J; i += BS) {
+      for (int i = threadIdx.x; i <= J; i += (int)blockDim.x) {
         f.coef[f.ldc + i] = T[i];
         f.K[(int64_t)J * f.ldh + i] = T[i];
       }
@@ -361,7 +361,7 @@ __device__ void finalize(const FinArgs& f, double* red, double* T, double* scrat
       if (threadIdx.x == 0) ctrl->reductions += 1;
       if (!(finite(d) && d > ctrl->tau * beta)) {
         // hand the reduced step over to the explicit-norm fallback (run by the host)
-        for (int i = threadIdx.x; i < J; i += BS) {
+        for (int i = threadIdx.x; i < J; i += (int)blockDim.x) {
           f.pend[i] = C[i];
           f.pend[J + i] = S[i];
           f.coef[i] = C[i];
@@ -382,7 +382,7 @@ __device__ void finalize(const FinArgs& f, double* red, double* T, double* scrat
       const double alpha = sqrt(red[0]);
       double* C = scratch;                 // pend -> LDS
       double* S = scratch + J;
-      for (int i = threadIdx.x; i < J; i += BS) { C[i] = f.pend[i]; S[i] = f.pend[J + i]; }
+      for (int i = threadIdx.x; i < J; i += (int)blockDim.x) { C[i] = f.pend[i]; S[i] = f.pend[J + i]; }
       __syncthreads();
       const double sigma = f.pend[2 * J], gamma = f.pend[2 * J + 1], beta = f.pend[2 * J + 2];
       small_dot(C, S, J, &s_dot[1]);
@@ -570,6 +570,122 @@ __global__ __launch_bounds__(BS) void update_kernel(double* __restrict__ Q, int6
     qout[r] = q;
     x[r] = yt - fma(q, tJ, st);
   }
+}
+
+// One-pass QR step (Alg. qr): the update of step j and the reduction of step j+1
+// share a single read of Q.  The next column a_{j+1} is known in advance, so
+// the rows of q_{j-1} and w_j produced by the update can be dotted immediately:
+//   q = (w - Q C)/alpha,  w' = a_j - Q T_{1:J} - q T_J          (update, step j)
+//   [Q_{0..J-1}, q, w', a_{j+1}]^T [w', a_{j+1}]                 (reduction, step j+1)
+// Rows are processed in tiles of FT rows.  Phase A: the FW wavefronts split the
+// basis columns (lane = row, 512-byte loads per column), keep the tile in LDS
+// and form partial Q C and Q T; wavefront 0 combines them in a fixed order and
+// writes q and w'.  Phase B: thread t owns column t of [Q, q, w', a_{j+1}] and
+// accumulates its two dot products over the tile from LDS, so the per-workgroup
+// partials need no cross-lane reduction.  last != 0: a_{j+1} does not exist
+// (the CGS2 finish of the last column), only [Q, q, w']^T w' is reduced.
+constexpr int FT = 64;           // rows per tile
+constexpr int FW = 8;            // wavefronts per workgroup
+constexpr int FBS = FW * 64;
+
+__global__ __launch_bounds__(FBS) void fused_qr_kernel(double* __restrict__ Q, int64_t ldq,
+                                                       int J, double* __restrict__ w,
+                                                       const double* __restrict__ a_cur,
+                                                       const double* __restrict__ a_next,
+                                                       int64_t m, const double* __restrict__ coef,
+                                                       int ldc, int last, GridRed gr,
+                                                       FinArgs fin) {
+  extern __shared__ double smem[];
+  if (fin.ctrl->state != ST_RUNNING) return;
+  const int Jt = J + (last ? 2 : 3);       // columns of [Q, q, w', (a_{j+1})]
+  const int V = last ? Jt : 2 * Jt;
+  constexpr int LDT = FT + 1;               // padded tile column stride
+  double* tile = smem;                      // Jt * LDT
+  double* part = tile + (size_t)Jt * LDT;   // FW * FT * 2
+  const double* __restrict__ C = coef;
+  const double* __restrict__ T = coef + ldc;
+  const double alpha = coef[2 * ldc];
+  const double tJ = T[J];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t ntiles = (m + FT - 1) / FT;
+  double accx = 0.0, accy = 0.0;
+  double* colq = tile + (size_t)J * LDT;
+  double* colw = colq + LDT;
+  double* cola = colw + LDT;
+  for (int64_t tix = blockIdx.x; tix < ntiles; tix += gr.G) {
+    const int64_t r0 = tix * FT;
+    const int rows = (int)min((int64_t)FT, m - r0);
+    // phase A: partial Q C and Q T over this wavefront's columns, tile into LDS
+    double sc = 0.0, st = 0.0;
+    if (lane < rows) {
+      const double* qrow = Q + r0 + lane;
+      int k = wv;
+      for (; k + 3 * FW < J; k += 4 * FW) {
+        const double q0 = qrow[(int64_t)k * ldq];
+        const double q1 = qrow[(int64_t)(k + FW) * ldq];
+        const double q2 = qrow[(int64_t)(k + 2 * FW) * ldq];
+        const double q3 = qrow[(int64_t)(k + 3 * FW) * ldq];
+        tile[(size_t)k * LDT + lane] = q0;
+        tile[(size_t)(k + FW) * LDT + lane] = q1;
+        tile[(size_t)(k + 2 * FW) * LDT + lane] = q2;
+        tile[(size_t)(k + 3 * FW) * LDT + lane] = q3;
+        sc = fma(q0, C[k], sc); st = fma(q0, T[k], st);
+        sc = fma(q1, C[k + FW], sc); st = fma(q1, T[k + FW], st);
+        sc = fma(q2, C[k + 2 * FW], sc); st = fma(q2, T[k + 2 * FW], st);
+        sc = fma(q3, C[k + 3 * FW], sc); st = fma(q3, T[k + 3 * FW], st);
+      }
+      for (; k < J; k += FW) {
+        const double q0 = qrow[(int64_t)k * ldq];
+        tile[(size_t)k * LDT + lane] = q0;
+        sc = fma(q0, C[k], sc);
+        st = fma(q0, T[k], st);
+      }
+    }
+    part[(wv * FT + lane) * 2] = sc;
+    part[(wv * FT + lane) * 2 + 1] = st;
+    __syncthreads();
+    // combine (fixed order) and form q_{j-1}, w_j for the tile rows
+    if (wv == 0 && lane < rows) {
+      double SC = part[lane * 2], ST = part[lane * 2 + 1];
+#pragma unroll
+      for (int u = 1; u < FW; ++u) {
+        SC += part[(u * FT + lane) * 2];
+        ST += part[(u * FT + lane) * 2 + 1];
+      }
+      const int64_t i = r0 + lane;
+      const double q = (w[i] - SC) / alpha;
+      const double wn = a_cur[i] - fma(q, tJ, ST);
+      Q[(int64_t)J * ldq + i] = q;
+      w[i] = wn;
+      colq[lane] = q;
+      colw[lane] = wn;
+      if (!last) cola[lane] = a_next[i];
+    }
+    __syncthreads();
+    // phase B: thread t owns column t of [Q, q, w', a_{j+1}]
+    if ((int)threadIdx.x < Jt) {
+      const double* col = tile + (size_t)threadIdx.x * LDT;
+      if (last) {
+        for (int r = 0; r < rows; ++r) accx = fma(col[r], colw[r], accx);
+      } else {
+        for (int r = 0; r < rows; ++r) {
+          const double qv = col[r];
+          accx = fma(qv, colw[r], accx);
+          accy = fma(qv, cola[r], accy);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double* P = gr.P1 + (int64_t)blockIdx.x * gr.ldp;
+  if ((int)threadIdx.x < Jt) {
+    P[threadIdx.x] = accx;
+    if (!last) P[Jt + threadIdx.x] = accy;
+  }
+  double* red = smem;                       // the tile is dead after the last tile's barrier
+  double* Tf = red + V;
+  double* scratch = Tf + (J + 3);
+  if (grid_reduce(gr, V, red)) finalize(fin, red, Tf, scratch);
 }
 
 __global__ void scale_col_kernel(double* Q, int64_t ldq, int J, int64_t m,
@@ -792,6 +908,32 @@ hipError_t launch_update(double* Q, int64_t ldq, int J, double* x, const double*
     else { if (qcol) DCGS2_UPD(1, false, true); else DCGS2_UPD(1, false, false); }
   }
 #undef DCGS2_UPD
+  return hipGetLastError();
+}
+
+size_t fused_qr_smem(int J, int last) {
+  const int Jt = J + (last ? 2 : 3);
+  const size_t tile = (size_t)Jt * (FT + 1) + (size_t)FW * FT * 2;
+  const size_t fin = (size_t)2 * Jt + (J + 3) + 3 * (J + 3) + 64;
+  return sizeof(double) * (tile > fin ? tile : fin) + sizeof(double) * 8;
+}
+
+int fused_qr_grid(int64_t m, int J, int last) {
+  const int64_t ntiles = (m + FT - 1) / FT;
+  const size_t lds = fused_qr_smem(J, last);
+  int per_cu = (int)((150u * 1024u) / lds);
+  per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
+  int64_t g = (int64_t)per_cu * 256;
+  if (g > REDUCE_GMAX) g = REDUCE_GMAX;
+  if (g > ntiles) g = ntiles;
+  return (int)(g < 1 ? 1 : g);
+}
+
+hipError_t launch_fused_qr(double* Q, int64_t ldq, int J, double* w, const double* a_cur,
+                           const double* a_next, int64_t m, const double* coef, int ldc, int last,
+                           const GridRed& gr, const FinArgs& fin, hipStream_t s) {
+  fused_qr_kernel<<<gr.G, FBS, fused_qr_smem(J, last), s>>>(Q, ldq, J, w, a_cur, a_next, m, coef,
+                                                             ldc, last, gr, fin);
   return hipGetLastError();
 }
 

@@ -32,12 +32,17 @@ def run_qr(ctx, B, ld=None):
     return host(Qd), R, rc, st
 
 
+@pytest.mark.parametrize("one_pass", [True, False])
 @pytest.mark.parametrize("m,n,ce", [(1000, 1, 2), (1000, 2, 2), (1023, 3, 2), (4097, 17, 2),
-                                    (4097, 17, 8), (20011, 64, 8), (3000, 100, 4)])
-def test_qr_parity_small(ctx, m, n, ce):
-    say(f"qr parity m={m} n={n} kappa=1e{ce}")
+                                    (4097, 17, 8), (20011, 64, 8), (3000, 100, 4), (130, 120, 2)])
+def test_qr_parity_small(ctx, m, n, ce, one_pass):
+    say(f"qr parity m={m} n={n} kappa=1e{ce} one_pass={one_pass}")
     B = synth.tall_skinny(m, n, ce, seed_g=100 + m, seed_v=7)
-    Q, R, rc, st = run_qr(ctx, B)
+    ctx.set_qr_schedule(one_pass)
+    try:
+        Q, R, rc, st = run_qr(ctx, B)
+    finally:
+        ctx.set_qr_schedule(True)
     ref = gs.dcgs2_qr(B)
     assert rc == binding.OK and ref["status"] == 0
     assert relnorm(R, ref["R"]) <= TOL
@@ -67,14 +72,17 @@ def test_qr_deterministic(ctx):
     assert np.array_equal(Q1, Q2) and np.array_equal(R1, R2)
 
 
-def test_qr_forced_fallback(ctx):
+@pytest.mark.parametrize("one_pass", [True, False])
+def test_qr_forced_fallback(ctx, one_pass):
     """tau = 1 forces the explicit-norm branch at every step (host-resumed)."""
     B = synth.tall_skinny(7000, 15, 4)
     ctx.set_tolerances(1.0, 1e-12)
+    ctx.set_qr_schedule(one_pass)
     try:
         Q, R, rc, st = run_qr(ctx, B)
     finally:
         ctx.set_tolerances(1e-8, 1e-12)
+        ctx.set_qr_schedule(True)
     ref = gs.dcgs2_qr(B, tau=1.0)
     assert rc == 0
     assert st["pyth_fallbacks"] == ref["fallbacks"] == 14
