@@ -150,6 +150,23 @@ int dcgs2_qr(dcgs2_ctx ctx, int64_t m, int32_t n, const double* B, int64_t ldb,
 int dcgs2_arnoldi(dcgs2_ctx ctx, const dcgs2_op* A, const double* r0, int32_t n,
                   double* Q, int64_t ldq, double* H_host, int32_t ldh, dcgs2_stats* st);
 
+/* FP32-stored basis.  Same algorithms and arguments as dcgs2_qr / dcgs2_arnoldi,
+ * but Q is a float array: each basis column is rounded once to FP32 when it is
+ * written, and every product with Q, every reduction (accumulated in FP64), the
+ * Pythagorean norm, R, H and K stay FP64; the projections use the stored
+ * columns.  Halves the bytes of the dominant basis streams.  Q (device, float)
+ * must be 8-byte aligned with an even ldq for the two-row loads (otherwise
+ * one-row loads are used). */
+int dcgs2_qr_q32(dcgs2_ctx ctx, int64_t m, int32_t n, const double* B, int64_t ldb,
+                 float* Q, int64_t ldq, double* R_host, int32_t ldr, dcgs2_stats* st);
+int dcgs2_arnoldi_q32(dcgs2_ctx ctx, const dcgs2_op* A, const double* r0, int32_t n,
+                      float* Q, int64_t ldq, double* H_host, int32_t ldh, dcgs2_stats* st);
+
+/* Storage precision (64 = FP64, default; 32 = FP32) of the internal Krylov bases
+ * of gmres_solve and krylov_schur_eigs; x, r, H, the Givens and Schur work and
+ * all reductions stay FP64.  Returns DCGS2_EINVAL for other values. */
+int dcgs2_set_basis_precision(dcgs2_ctx ctx, int bits);
+
 /* Restarted GMRES(restart) (Sec. 1, Saad & Schultz) on the DCGS2 basis.
  *  b       : device, m; read only.
  *  x       : device, m; in: initial guess x0, out: solution.

@@ -13,6 +13,11 @@ import numpy as np
 OK, BREAKDOWN, NONFINITE = 0, 1, 3
 
 
+def _f64(x):
+    """FP64 view of stored basis columns (exact widening when Q is stored in FP32)."""
+    return np.asarray(x, dtype=np.float64)
+
+
 def cgs2_arnoldi(matvec, r0, n):
     """Alg. cgs2_arnoldi: v = A q_{j-1}; two projections; normalisation (3 reductions/step)."""
     m = r0.size
@@ -87,15 +92,19 @@ class DCGS2Arnoldi:
         w_{j-1} was projected from: ||r0|| for j-1 = 1, else sqrt(gamma_{j-1})/alpha_{j-2}.
         Then H column j-2 is completed, k = j-2, status BREAKDOWN.
       * Any non-finite reduced scalar: status NONFINITE.
+
+    qdtype=np.float32 stores the basis in single precision (each column rounded
+    once when written); all products with Q, reductions, H, K and scalars stay
+    FP64 and the projections use the stored columns.
     """
 
-    def __init__(self, matvec, r0, n, tau=1e-8, eta=1e-12):
+    def __init__(self, matvec, r0, n, tau=1e-8, eta=1e-12, qdtype=np.float64):
         r0 = np.asarray(r0, dtype=np.float64)
         self.matvec = matvec
         self.m = r0.size
         self.n = n
         self.tau, self.eta = tau, eta
-        self.Q = np.zeros((self.m, n + 1), order="F")
+        self.Q = np.zeros((self.m, n + 1), order="F", dtype=qdtype)
         self.H = np.zeros((n + 1, n))
         self.K = np.zeros((n + 1, n + 1))
         self.w = r0.copy()                      # w_1 = r0 (unnormalised)
@@ -112,7 +121,7 @@ class DCGS2Arnoldi:
 
     # -- Krylov-Schur continuation -------------------------------------------------
     @classmethod
-    def resume(cls, matvec, Q, H, k, n, tau=1e-8, eta=1e-12):
+    def resume(cls, matvec, Q, H, k, n, tau=1e-8, eta=1e-12, qdtype=np.float64):
         """Continue an expansion from a truncated Krylov-Schur decomposition.
 
         Given orthonormal Q_{1:k+1} and H_{1:k+1,1:k} = [S_k; b^T] with
@@ -121,10 +130,10 @@ class DCGS2Arnoldi:
         it reduces only S = Q_{1:k+1}^T v, sets T = S, w_{k+2} = v - Q_{1:k+1} T,
         K_{:,k+1} = T, and leaves H column k alone (it is already final).
         """
-        self = cls(matvec, Q[:, k], n, tau, eta)
+        self = cls(matvec, _f64(Q[:, k]), n, tau, eta, qdtype)
         self.Q[:, :k + 1] = Q[:, :k + 1]
         self.H[:k + 1, :k] = H[:k + 1, :k]
-        self.w = Q[:, k].copy()
+        self.w = _f64(Q[:, k]).copy()
         self.j = k + 2
         self.k = k
         self.restart_step = True
@@ -139,16 +148,16 @@ class DCGS2Arnoldi:
         w = self.w
         v = self.matvec(w)
         self.matvecs += 1
-        Qk = Q[:, :J]
+        Qk = _f64(Q[:, :J])
         if self.restart_step:
             # Krylov-Schur continuation: q_{k+1} is final; one reduction of Q_{1:k+1}^T v
-            T = Q[:, :J + 1].T @ v
+            T = _f64(Q[:, :J + 1]).T @ v
             gamma = v @ v
             self.reductions += 1
             if not (np.all(np.isfinite(T)) and np.isfinite(gamma)):
                 self.status = NONFINITE
                 return self.status
-            self.w = v - Q[:, :J + 1] @ T
+            self.w = v - _f64(Q[:, :J + 1]) @ T
             K[:J + 1, J] = T
             self.alphas.append(1.0)
             self.rho_next = np.sqrt(gamma)
@@ -190,7 +199,7 @@ class DCGS2Arnoldi:
         T[:J] = S / alpha
         # --- projection
         Q[:, J] = (w - Qk @ C) / alpha
-        self.w = v / alpha - Q[:, :J + 1] @ T
+        self.w = v / alpha - _f64(Q[:, :J + 1]) @ T
         # --- representation: complete H column j-2, then the partial column K_{:, j-1}
         if j >= 3:
             H[:J, J - 1] = K[:J, J - 1] + C
@@ -210,7 +219,7 @@ class DCGS2Arnoldi:
         n = self.n
         Q, H, K = self.Q, self.H, self.K
         w = self.w
-        Qk = Q[:, :n]
+        Qk = _f64(Q[:, :n])
         c = Qk.T @ w
         u = w - Qk @ c
         alpha = np.linalg.norm(u)
@@ -238,8 +247,8 @@ class DCGS2Arnoldi:
         return self
 
 
-def dcgs2_arnoldi(matvec, r0, n, tau=1e-8, eta=1e-12):
+def dcgs2_arnoldi(matvec, r0, n, tau=1e-8, eta=1e-12, qdtype=np.float64):
     """Full DCGS2 Arnoldi-QR expansion of n steps: returns dict(Q, H, status, k, ...)."""
-    a = DCGS2Arnoldi(matvec, r0, n, tau, eta).run()
+    a = DCGS2Arnoldi(matvec, r0, n, tau, eta, qdtype).run()
     return dict(Q=a.Q, H=a.H, status=a.status, k=a.k, reductions=a.reductions,
                 fallbacks=a.fallbacks, matvecs=a.matvecs)

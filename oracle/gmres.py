@@ -13,6 +13,8 @@ Readings (the GPU path implements the same):
   * A cycle runs min(restart, max_iters - iters) steps, then the CGS2 last-column
     finish; ``iters`` counts Arnoldi matvecs.
   * b = 0 gives x = 0 and status OK.
+  * qdtype=np.float32 stores the basis in single precision; x, r, H, the
+    least-squares solve and every reduction stay FP64.
 """
 from __future__ import annotations
 
@@ -32,7 +34,7 @@ def _lsq(H, k, beta):
 
 
 def gmres_dcgs2(A, b, x0=None, restart=50, rtol=1e-8, max_iters=10000,
-                tau=1e-8, eta=1e-12):
+                tau=1e-8, eta=1e-12, qdtype=np.float64):
     """Restarted GMRES(restart) with DCGS2 Arnoldi.  A: scipy sparse matrix or callable."""
     matvec = A if callable(A) else (lambda x: A @ x)
     b = np.asarray(b, dtype=np.float64)
@@ -54,7 +56,7 @@ def gmres_dcgs2(A, b, x0=None, restart=50, rtol=1e-8, max_iters=10000,
             info["status"] = NOT_CONVERGED
             return x, info
         n = min(restart, max_iters - info["iters"])
-        arn = DCGS2Arnoldi(matvec, r, n, tau, eta)
+        arn = DCGS2Arnoldi(matvec, r, n, tau, eta, qdtype)
         info["cycles"] += 1
         k = None
         while arn.j <= n + 1:
@@ -79,4 +81,4 @@ def gmres_dcgs2(A, b, x0=None, restart=50, rtol=1e-8, max_iters=10000,
             return x, info
         y, est = _lsq(arn.H, k, arn.alphas[0])
         info["relres_est"] = est / bnorm
-        x = x + arn.Q[:, :k] @ y
+        x = x + np.asarray(arn.Q[:, :k], dtype=np.float64) @ y

@@ -76,7 +76,12 @@ def mgs_qr(B):
     return Q, R, red
 
 
-def dcgs2_qr(B, tau=1e-8, eta=1e-12):
+def _f64(x):
+    """FP64 view of stored basis columns (exact widening when Q is stored in FP32)."""
+    return np.asarray(x, dtype=np.float64)
+
+
+def dcgs2_qr(B, tau=1e-8, eta=1e-12, qdtype=np.float64):
     """Delayed CGS2 QR, Alg. qr, with the last column finished by CGS2 (end of Sec. 3).
 
     Step j (paper's 1-based j = 2..n) finalises q_{j-1} and forms w_j with ONE
@@ -97,11 +102,15 @@ def dcgs2_qr(B, tau=1e-8, eta=1e-12):
       first k = j-2 columns of Q and R are the valid prefix.
     * Any non-finite reduced scalar -> status NONFINITE.
 
+    qdtype=np.float32 stores Q in single precision (each q_j rounded once when it
+    is written); every product with Q, every reduction, R and the scalars stay
+    FP64, and the update uses the stored (rounded) column.
+
     Returns dict(Q, R, status, k, reductions, fallbacks).
     """
     B = np.asarray(B, dtype=np.float64)
     m, n = B.shape
-    Q = np.zeros((m, n), order="F")
+    Q = np.zeros((m, n), order="F", dtype=qdtype)
     R = np.zeros((n, n))
     red = 0
     fallbacks = 0
@@ -115,7 +124,7 @@ def dcgs2_qr(B, tau=1e-8, eta=1e-12):
     for j in range(2, n + 1):
         J = j - 2                           # columns q_1..q_{j-2} are final
         a = B[:, j - 1]                     # a_j
-        Qk = Q[:, :J]
+        Qk = _f64(Q[:, :J])
         # --- the one global reduction of step j
         C = Qk.T @ w
         beta = w @ w
@@ -146,7 +155,7 @@ def dcgs2_qr(B, tau=1e-8, eta=1e-12):
         # --- projection of a_j, with Stephen's trick for q_{j-1}^T a_j
         s_last = (sigma - C @ S) / alpha
         S_full = np.concatenate([S, [s_last]])
-        w = a - Q[:, :J + 1] @ S_full
+        w = a - _f64(Q[:, :J + 1]) @ S_full
         # --- representation R_{:, j-1}
         R[:J, J] = S_prev + C
         R[J, J] = alpha
@@ -155,7 +164,7 @@ def dcgs2_qr(B, tau=1e-8, eta=1e-12):
 
     # --- last column: CGS2 finish, two reductions (end of Sec. 3)
     J = n - 1
-    Qk = Q[:, :J]
+    Qk = _f64(Q[:, :J])
     c = Qk.T @ w
     u = w - Qk @ c
     alpha = np.linalg.norm(u)

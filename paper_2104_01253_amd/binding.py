@@ -23,7 +23,8 @@ MAX_N = 1024
 
 EXPORTS = ("dcgs2_create", "dcgs2_destroy", "dcgs2_set_tolerances", "dcgs2_qr", "dcgs2_arnoldi",
            "gmres_solve", "krylov_schur_eigs", "dcgs2_apply", "dcgs2_status_str",
-           "dcgs2_profile_enable", "dcgs2_profile_read", "dcgs2_set_qr_schedule")
+           "dcgs2_profile_enable", "dcgs2_profile_read", "dcgs2_set_qr_schedule",
+           "dcgs2_qr_q32", "dcgs2_arnoldi_q32", "dcgs2_set_basis_precision")
 
 
 class Stats(ctypes.Structure):
@@ -81,12 +82,16 @@ def load(path: str = LIB_PATH):
     lib.dcgs2_apply.argtypes = [c_void_p, POINTER(Op), c_void_p, c_void_p]
     lib.dcgs2_profile_enable.argtypes = [c_void_p, c_int]
     lib.dcgs2_set_qr_schedule.argtypes = [c_void_p, c_int]
+    lib.dcgs2_set_basis_precision.argtypes = [c_void_p, c_int]
+    lib.dcgs2_qr_q32.argtypes = lib.dcgs2_qr.argtypes
+    lib.dcgs2_arnoldi_q32.argtypes = lib.dcgs2_arnoldi.argtypes
     lib.dcgs2_profile_read.argtypes = [c_void_p, POINTER(KernelStat), c_int32, c_int32]
     lib.dcgs2_status_str.argtypes = [c_int]
     lib.dcgs2_status_str.restype = ctypes.c_char_p
     for name in ("dcgs2_create", "dcgs2_destroy", "dcgs2_set_tolerances", "dcgs2_qr",
                  "dcgs2_arnoldi", "gmres_solve", "krylov_schur_eigs", "dcgs2_apply",
-                 "dcgs2_profile_enable", "dcgs2_profile_read", "dcgs2_set_qr_schedule"):
+                 "dcgs2_profile_enable", "dcgs2_profile_read", "dcgs2_set_qr_schedule",
+           "dcgs2_qr_q32", "dcgs2_arnoldi_q32", "dcgs2_set_basis_precision"):
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -119,9 +124,11 @@ def colmajor_from_numpy(A: np.ndarray, device="cuda", ld: int | None = None):
     return out
 
 
-def _colmajor_args(T, name):
-    if T.dim() != 2 or T.dtype != _f64() or not T.is_cuda:
-        raise ValueError(f"{name}: expected a 2-D float64 CUDA tensor")
+def _colmajor_args(T, name, allow32=False):
+    import torch
+    ok = (torch.float64, torch.float32) if allow32 else (torch.float64,)
+    if T.dim() != 2 or T.dtype not in ok or not T.is_cuda:
+        raise ValueError(f"{name}: expected a 2-D {'float32/' if allow32 else ''}float64 CUDA tensor")
     if T.stride(0) != 1:
         raise ValueError(f"{name}: expected column-major layout (stride(0) == 1)")
     ld = T.stride(1) if T.shape[1] > 1 else max(T.shape[0], 1)
@@ -233,30 +240,34 @@ class Context:
 
     # -- entry points -------------------------------------------------------------
     def qr(self, B, Q):
-        """DCGS2 QR of column-major B into Q; returns (R (numpy n x n), status, stats)."""
+        """DCGS2 QR of column-major B into Q (float64, or float32 for the FP32-stored
+        basis); returns (R (numpy n x n), status, stats)."""
+        import torch
         m, n = B.shape
         pb, ldb = _colmajor_args(B, "B")
-        pq, ldq = _colmajor_args(Q, "Q")
+        pq, ldq = _colmajor_args(Q, "Q", allow32=True)
         if Q.shape != (m, n):
             raise ValueError("Q must have B's shape")
         R = np.zeros((n, n), order="F")
         st = Stats()
-        rc = self._lib.dcgs2_qr(self._h, m, n, pb, ldb, pq, ldq,
-                                R.ctypes.data_as(c_void_p), n, ctypes.byref(st))
+        fn = self._lib.dcgs2_qr_q32 if Q.dtype == torch.float32 else self._lib.dcgs2_qr
+        rc = fn(self._h, m, n, pb, ldb, pq, ldq, R.ctypes.data_as(c_void_p), n, ctypes.byref(st))
         if rc < 0:
             raise DCGS2Error(rc, "dcgs2_qr")
         return R, rc, st.as_dict()
 
     def arnoldi(self, op: Op, r0, n: int, Q):
         """n DCGS2 Arnoldi steps from r0 into Q (m x (n+1)); returns (H, status, stats)."""
+        import torch
         pr = _vec_ptr(r0, "r0", op.m)
-        pq, ldq = _colmajor_args(Q, "Q")
+        pq, ldq = _colmajor_args(Q, "Q", allow32=True)
         if Q.shape[0] != op.m or Q.shape[1] < n + 1:
             raise ValueError("Q must be m x (n+1)")
         H = np.zeros((n + 1, n), order="F")
         st = Stats()
-        rc = self._lib.dcgs2_arnoldi(self._h, ctypes.byref(op), pr, n, pq, ldq,
-                                     H.ctypes.data_as(c_void_p), n + 1, ctypes.byref(st))
+        fn = self._lib.dcgs2_arnoldi_q32 if Q.dtype == torch.float32 else self._lib.dcgs2_arnoldi
+        rc = fn(self._h, ctypes.byref(op), pr, n, pq, ldq, H.ctypes.data_as(c_void_p), n + 1,
+                ctypes.byref(st))
         if rc < 0:
             raise DCGS2Error(rc, "dcgs2_arnoldi")
         return H, rc, st.as_dict()
@@ -288,6 +299,12 @@ class Context:
         out = {k: getattr(info, k) for k, _ in KsInfo._fields_ if k != "st"}
         out["stats"] = info.st.as_dict()
         return re + 1j * im, rc, out
+
+    def set_basis_precision(self, bits: int):
+        """Storage precision (32 or 64) of the internal bases of gmres / krylov_schur."""
+        rc = self._lib.dcgs2_set_basis_precision(self._h, int(bits))
+        if rc != OK:
+            raise DCGS2Error(rc, "dcgs2_set_basis_precision")
 
     def set_qr_schedule(self, one_pass: bool):
         rc = self._lib.dcgs2_set_qr_schedule(self._h, 1 if one_pass else 0)

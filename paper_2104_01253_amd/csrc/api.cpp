@@ -47,7 +47,8 @@ struct dcgs2_ctx_s {
   double *coef = nullptr, *pend = nullptr;
   double *H = nullptr, *K = nullptr, *Rg = nullptr, *R = nullptr, *Z = nullptr;
   double *Sprev = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
-  double *Qa = nullptr, *Qb = nullptr;
+  double *Qa = nullptr, *Qb = nullptr;    // internal bases (GMRES, Krylov-Schur)
+  int basis_q32 = 0;                         // internal bases stored in FP32
   Ctrl* ctrl = nullptr;
   Ctrl* ctrl_host = nullptr;       // pinned
   int kernels = 0;
@@ -253,7 +254,8 @@ struct Expansion {
   bool qr = false;
   bool gmres = false;
   int64_t m = 0;
-  double* Q = nullptr;
+  void* Q = nullptr;            // basis (double, or float when q32)
+  int q32 = 0;
   int64_t ldq = 0;
   const double* B = nullptr;    // QR input columns
   int64_t ldb = 0;
@@ -278,31 +280,36 @@ struct Expansion {
     const int J = j - 2;
     hipStream_t s = c->stream;
     const double vm = 8.0 * (double)m;
+    const double qb = q32 ? 4.0 * (double)m : vm;      // bytes of one basis column
     if (!qr) KL(K_SPMV, spmv_bytes(), launch_spmv(op, c->w, nullptr, c->v, c->ctrl, s));
-    KL(K_REDUCE, vm * (J + 2), launch_reduce(Q, ldq, J, c->w, ycol(j), m, gr, fin(kind, j, J), s));
-    KL(K_UPDATE, vm * (J + 4),
-       launch_update(Q, ldq, J, c->w, ycol(j), m, c->coef, LDC, !qr, 0, c->ctrl, s));
+    KL(K_REDUCE, qb * J + 2 * vm,
+       launch_reduce(Q, q32, ldq, J, c->w, ycol(j), m, gr, fin(kind, j, J), s));
+    KL(K_UPDATE, qb * (J + 1) + 3 * vm,
+       launch_update(Q, q32, ldq, J, c->w, ycol(j), nullptr, m, c->coef, LDC, !qr, 0, c->ctrl, s));
     return DCGS2_OK;
   }
   int enqueue_fallback(int j) {
     const int J = j - 2;
     hipStream_t s = c->stream;
     const double vm = 8.0 * (double)m;
-    KL(K_PROJNORM, vm * (J + 2),
-       launch_project_norm(Q, ldq, J, c->w, m, gr, fin(FIN_FALLBACK, j, J), s));
-    KL(K_UPDATE, vm * (J + 5),
-       launch_update(Q, ldq, J, c->w, ycol(j), m, c->coef, LDC, !qr, 1, c->ctrl, s));
+    const double qb = q32 ? 4.0 * (double)m : vm;
+    KL(K_PROJNORM, qb * J + 2 * vm,
+       launch_project_norm(Q, q32, ldq, J, c->w, c->r, m, gr, fin(FIN_FALLBACK, j, J), s));
+    KL(K_UPDATE, qb * (J + 1) + 4 * vm,
+       launch_update(Q, q32, ldq, J, c->w, ycol(j), c->r, m, c->coef, LDC, !qr, 1, c->ctrl, s));
     return DCGS2_OK;
   }
   // CGS2 finish of the last column: J final columns already in Q.
   int enqueue_last(int J, int jvirt) {
     hipStream_t s = c->stream;
     const double vm = 8.0 * (double)m;
-    KL(K_REDUCE, vm * (J + 1),
-       launch_reduce(Q, ldq, J, c->w, nullptr, m, gr, fin(FIN_LAST1, jvirt, J), s));
-    KL(K_PROJNORM, vm * (J + 2),
-       launch_project_norm(Q, ldq, J, c->w, m, gr, fin(FIN_LAST2, jvirt, J), s));
-    KL(K_SCALE, vm * 2, launch_scale_col(Q, ldq, J, m, c->coef, LDC, c->ctrl, s));
+    const double qb = q32 ? 4.0 * (double)m : vm;
+    KL(K_REDUCE, qb * J + vm,
+       launch_reduce(Q, q32, ldq, J, c->w, nullptr, m, gr, fin(FIN_LAST1, jvirt, J), s));
+    KL(K_PROJNORM, qb * J + 2 * vm,
+       launch_project_norm(Q, q32, ldq, J, c->w, c->r, m, gr, fin(FIN_LAST2, jvirt, J), s));
+    KL(K_SCALE, vm + qb,
+       launch_scale_col(Q, q32, ldq, J, c->r, m, c->coef, LDC, c->ctrl, s));
     return DCGS2_OK;
   }
   GridRed fused_grid(int J, int last) const {
@@ -319,27 +326,31 @@ struct Expansion {
     hipStream_t s = c->stream;
     const double vm = 8.0 * (double)m;
     if (j0 > j_to) return J_last >= 0 ? enqueue_last(J_last, j_to + 1) : DCGS2_OK;
-    KL(K_REDUCE, vm * (j0 - 2 + 2),
-       launch_reduce(Q, ldq, j0 - 2, c->w, ycol(j0), m, gr, fin(kind0, j0, j0 - 2), s));
+    const double qb = q32 ? 4.0 * (double)m : vm;
+    KL(K_REDUCE, qb * (j0 - 2) + 2 * vm,
+       launch_reduce(Q, q32, ldq, j0 - 2, c->w, ycol(j0), m, gr, fin(kind0, j0, j0 - 2), s));
     for (int j = j0; j <= j_to; ++j) {
       const int J = j - 2;
       const bool last = (j == j_to);
       if (last && J_last < 0) {
-        KL(K_UPDATE, vm * (J + 4),
-           launch_update(Q, ldq, J, c->w, ycol(j), m, c->coef, LDC, 0, 0, c->ctrl, s));
+        KL(K_UPDATE, qb * (J + 1) + 3 * vm,
+           launch_update(Q, q32, ldq, J, c->w, ycol(j), nullptr, m, c->coef, LDC, 0, 0, c->ctrl,
+                         s));
         break;
       }
       const GridRed g = fused_grid(J, last ? 1 : 0);
       const FinArgs f = last ? fin(FIN_LAST1, j + 1, J + 1) : fin(FIN_STEP, j + 1, J + 1);
       // bytes: Q_{0..J-1}, w, a_j, a_{j+1} read; q, w written
-      KL(K_FUSED, vm * (J + (last ? 4 : 5)),
-         launch_fused_qr(Q, ldq, J, c->w, ycol(j), last ? nullptr : ycol(j + 1), m, c->coef,
-                         LDC, last ? 1 : 0, g, f, s));
+      KL(K_FUSED, qb * (J + 1) + vm * (last ? 3 : 4),
+         launch_fused_qr(Q, q32, ldq, J, c->w, ycol(j), last ? nullptr : ycol(j + 1), m,
+                         c->coef, LDC, last ? 1 : 0, g, f, s));
     }
     if (J_last >= 0) {
-      KL(K_PROJNORM, vm * (J_last + 2),
-         launch_project_norm(Q, ldq, J_last, c->w, m, gr, fin(FIN_LAST2, j_to + 1, J_last), s));
-      KL(K_SCALE, vm * 2, launch_scale_col(Q, ldq, J_last, m, c->coef, LDC, c->ctrl, s));
+      KL(K_PROJNORM, qb * J_last + 2 * vm,
+         launch_project_norm(Q, q32, ldq, J_last, c->w, c->r, m, gr,
+                             fin(FIN_LAST2, j_to + 1, J_last), s));
+      KL(K_SCALE, vm + qb,
+         launch_scale_col(Q, q32, ldq, J_last, c->r, m, c->coef, LDC, c->ctrl, s));
     }
     return DCGS2_OK;
   }
@@ -501,8 +512,8 @@ int dcgs2_apply(dcgs2_ctx c, const dcgs2_op* A, const double* x, double* y) {
   return DCGS2_OK;
 }
 
-int dcgs2_qr(dcgs2_ctx c, int64_t m, int32_t n, const double* B, int64_t ldb, double* Q,
-             int64_t ldq, double* R_host, int32_t ldr, dcgs2_stats* st) {
+static int qr_impl(dcgs2_ctx c, int64_t m, int32_t n, const double* B, int64_t ldb, void* Q,
+                   int q32, int64_t ldq, double* R_host, int32_t ldr, dcgs2_stats* st) {
   if (!c || m < 1 || n < 1 || n > DCGS2_MAX_N || (int64_t)n > m || !B || !Q || !R_host ||
       ldb < m || ldq < m || ldr < n)
     return DCGS2_EINVAL;
@@ -513,7 +524,7 @@ int dcgs2_qr(dcgs2_ctx c, int64_t m, int32_t n, const double* B, int64_t ldb, do
   Expansion e;
   e.qr = true;
   e.m = m;
-  e.Q = Q; e.ldq = ldq; e.B = B; e.ldb = ldb;
+  e.Q = Q; e.q32 = q32; e.ldq = ldq; e.B = B; e.ldb = ldb;
   e.ldh = n;
   e.one_pass = c->qr_one_pass && n - 2 <= FUSED_QR_MAX_J;
   if ((rc = setup_expansion(c, e, 0.0))) return rc;
@@ -527,8 +538,8 @@ int dcgs2_qr(dcgs2_ctx c, int64_t m, int32_t n, const double* B, int64_t ldb, do
   return status;
 }
 
-int dcgs2_arnoldi(dcgs2_ctx c, const dcgs2_op* A, const double* r0, int32_t n, double* Q,
-                  int64_t ldq, double* H_host, int32_t ldh, dcgs2_stats* st) {
+static int arnoldi_impl(dcgs2_ctx c, const dcgs2_op* A, const double* r0, int32_t n, void* Q,
+                        int q32, int64_t ldq, double* H_host, int32_t ldh, dcgs2_stats* st) {
   if (!c || !valid_op(A) || !r0 || !Q || !H_host || n < 1 || n > DCGS2_MAX_N ||
       (int64_t)n >= A->m || ldq < A->m || ldh < n + 1)
     return DCGS2_EINVAL;
@@ -540,7 +551,7 @@ int dcgs2_arnoldi(dcgs2_ctx c, const dcgs2_op* A, const double* r0, int32_t n, d
   Expansion e;
   e.qr = false;
   e.m = m;
-  e.Q = Q; e.ldq = ldq;
+  e.Q = Q; e.q32 = q32; e.ldq = ldq;
   e.op = to_dev(A);
   e.ldh = n + 1;
   if ((rc = setup_expansion(c, e, 0.0))) return rc;
@@ -553,6 +564,32 @@ int dcgs2_arnoldi(dcgs2_ctx c, const dcgs2_op* A, const double* r0, int32_t n, d
   if ((rc = copy_to_host(c, c->H, n + 1, n + 1, n, H_host, ldh))) return rc;
   fill_stats(st, s, c->kernels, status);
   return status;
+}
+
+int dcgs2_qr(dcgs2_ctx c, int64_t m, int32_t n, const double* B, int64_t ldb, double* Q,
+             int64_t ldq, double* R_host, int32_t ldr, dcgs2_stats* st) {
+  return qr_impl(c, m, n, B, ldb, Q, 0, ldq, R_host, ldr, st);
+}
+
+int dcgs2_qr_q32(dcgs2_ctx c, int64_t m, int32_t n, const double* B, int64_t ldb, float* Q,
+                 int64_t ldq, double* R_host, int32_t ldr, dcgs2_stats* st) {
+  return qr_impl(c, m, n, B, ldb, Q, 1, ldq, R_host, ldr, st);
+}
+
+int dcgs2_arnoldi(dcgs2_ctx c, const dcgs2_op* A, const double* r0, int32_t n, double* Q,
+                  int64_t ldq, double* H_host, int32_t ldh, dcgs2_stats* st) {
+  return arnoldi_impl(c, A, r0, n, Q, 0, ldq, H_host, ldh, st);
+}
+
+int dcgs2_arnoldi_q32(dcgs2_ctx c, const dcgs2_op* A, const double* r0, int32_t n, float* Q,
+                      int64_t ldq, double* H_host, int32_t ldh, dcgs2_stats* st) {
+  return arnoldi_impl(c, A, r0, n, Q, 1, ldq, H_host, ldh, st);
+}
+
+int dcgs2_set_basis_precision(dcgs2_ctx c, int bits) {
+  if (!c || (bits != 32 && bits != 64)) return DCGS2_EINVAL;
+  c->basis_q32 = bits == 32;
+  return DCGS2_OK;
 }
 
 int gmres_solve(dcgs2_ctx c, const dcgs2_op* A, const double* b, double* x, int32_t restart,
@@ -572,13 +609,13 @@ int gmres_solve(dcgs2_ctx c, const dcgs2_op* A, const double* b, double* x, int3
   e.qr = false;
   e.gmres = true;
   e.m = m;
-  e.Q = c->Qa; e.ldq = ldq;
+  e.Q = c->Qa; e.q32 = c->basis_q32; e.ldq = ldq;
   e.op = to_dev(A);
   e.ldh = restart + 1;
   // ||b||
   if ((rc = setup_expansion(c, e, 0.0))) return rc;
   Ctrl s{};
-  CKL(launch_reduce(nullptr, ldq, 0, b, nullptr, m, e.gr, e.fin(FIN_NORM, 0, 0), c->stream));
+  CKL(launch_reduce(nullptr, 0, ldq, 0, b, nullptr, m, e.gr, e.fin(FIN_NORM, 0, 0), c->stream));
   if ((rc = read_ctrl(c, &s))) return rc;
   const double bnorm = std::sqrt(s.norm2);
   int status = DCGS2_OK;
@@ -593,7 +630,7 @@ int gmres_solve(dcgs2_ctx c, const dcgs2_op* A, const double* b, double* x, int3
       // r = b - A x into w (w_1 of the cycle), then ||r||
       if ((rc = setup_expansion(c, e, rtol * bnorm))) return rc;
       KL(K_SPMV, op_bytes(e.op) + 8.0 * m, launch_spmv(e.op, x, b, c->w, nullptr, c->stream));
-      CKL(launch_reduce(nullptr, ldq, 0, c->w, nullptr, m, e.gr, e.fin(FIN_NORM, 0, 0),
+      CKL(launch_reduce(nullptr, 0, ldq, 0, c->w, nullptr, m, e.gr, e.fin(FIN_NORM, 0, 0),
                         c->stream));
       if ((rc = read_ctrl(c, &s))) return rc;
       inf.relres_true = std::sqrt(s.norm2) / bnorm;
@@ -631,7 +668,8 @@ int gmres_solve(dcgs2_ctx c, const dcgs2_op* A, const double* b, double* x, int3
         y[i] = sum / Rh[(size_t)i * ld + i];
       }
       CK(hipMemcpyAsync(c->Z, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, c->stream));
-      KL(K_TSGEMM, 8.0 * m * (k + 2), launch_tsgemm(c->Qa, ldq, k, c->Z, k, 1, x, m, m, 1, c->stream));
+      KL(K_TSGEMM, (e.q32 ? 4.0 : 8.0) * m * k + 16.0 * m,
+         launch_tsgemm(c->Qa, e.q32, ldq, k, c->Z, k, 1, x, 0, m, m, 1, c->stream));
     }
   }
   inf.status = status;
@@ -661,7 +699,7 @@ int krylov_schur_eigs(dcgs2_ctx c, const dcgs2_op* A, int32_t nev, int32_t ncv, 
   Expansion e;
   e.qr = false;
   e.m = m;
-  e.Q = c->Qa; e.ldq = ldq;
+  e.Q = c->Qa; e.q32 = c->basis_q32; e.ldq = ldq;
   e.op = to_dev(A);
   e.ldh = p + 1;
   const int ld = p + 1;
@@ -703,10 +741,13 @@ int krylov_schur_eigs(dcgs2_ctx c, const dcgs2_op* A, int32_t nev, int32_t ncv, 
     if (k < 0 || k >= p) { status = DCGS2_NOT_CONVERGED; break; }
     CK(hipMemcpyAsync(c->Z, Zm.data(), sizeof(double) * (size_t)p * k, hipMemcpyHostToDevice,
                       c->stream));
-    KL(K_TSGEMM, 8.0 * m * (p + k),
-       launch_tsgemm(c->Qa, ldq, p, c->Z, p, k, c->Qb, ldq, m, 0, c->stream));   // Q_p Z_k
-    CKL(launch_copy(c->Qb + (int64_t)k * ldq, c->Qa + (int64_t)p * ldq, m, c->stream));
-    CKL(launch_copy(c->w, c->Qa + (int64_t)p * ldq, m, c->stream));          // w = q_{k+1}
+    const int64_t es = e.q32 ? 4 : 8;                                         // element bytes
+    char* qa = reinterpret_cast<char*>(c->Qa);
+    char* qbuf = reinterpret_cast<char*>(c->Qb);
+    KL(K_TSGEMM, (double)es * m * (p + k),
+       launch_tsgemm(c->Qa, e.q32, ldq, p, c->Z, p, k, c->Qb, e.q32, ldq, m, 0, c->stream));
+    CKL(launch_convert(qbuf + es * k * ldq, e.q32, qa + es * p * ldq, e.q32, m, c->stream));
+    CKL(launch_convert(c->w, 0, qa + es * p * ldq, e.q32, m, c->stream));    // w = q_{k+1}
     std::fill(Hn.begin(), Hn.end(), 0.0);
     for (int jj = 0; jj < k; ++jj) {
       for (int i = 0; i < k; ++i) Hn[(size_t)jj * ld + i] = T[(size_t)jj * p + i];

@@ -89,33 +89,41 @@ hipError_t launch_copy_cols(double* dst, int64_t ldd, const double* src, int64_t
 // (ctrl may be nullptr: always runs).
 hipError_t launch_spmv(const OpDev& op, const double* x, const double* b, double* y,
                        const Ctrl* ctrl, hipStream_t s);
+// Basis pointers are `const void*` / `void*` with q32 selecting float (FP32
+// storage, FP64 arithmetic) or double elements.
 // One DCGS2 reduction: [Q_{0..J-1}, x, (y)]^T [x, (y)] over m rows, grid-reduced,
 // then finalised by the last workgroup according to fin.
-hipError_t launch_reduce(const double* Q, int64_t ldq, int J, const double* x,
+hipError_t launch_reduce(const void* Q, int q32, int64_t ldq, int J, const double* x,
                          const double* y, int64_t m, const GridRed& gr, const FinArgs& fin,
                          hipStream_t s);
-// u = x - Q_{0..J-1} C  written to Q[:, J]; ||u||^2 grid-reduced and finalised.
-hipError_t launch_project_norm(double* Q, int64_t ldq, int J, const double* x, int64_t m,
-                               const GridRed& gr, const FinArgs& fin, hipStream_t s);
-// q_{j-1} = (x - Q C)/alpha (or Q[:,J]/alpha when qcol), Q[:,J] = q,
-// x <- yscale(y) - Q_{0..J-1} T - q T_J, with yscale(y) = y/alpha (Arnoldi) or y (QR).
-hipError_t launch_update(double* Q, int64_t ldq, int J, double* x, const double* y,
-                         int64_t m, const double* coef, int ldc, int arnoldi, int qcol,
-                         const Ctrl* ctrl, hipStream_t s);
+// u = x - Q_{0..J-1} C written to ubuf; ||u||^2 grid-reduced and finalised.
+hipError_t launch_project_norm(const void* Q, int q32, int64_t ldq, int J, const double* x,
+                               double* ubuf, int64_t m, const GridRed& gr, const FinArgs& fin,
+                               hipStream_t s);
+// q_{j-1} = (x - Q C)/alpha (or ubuf/alpha when qcol) into Q[:, J] (rounded to the
+// basis type), x <- yscale(y) - Q_{0..J-1} T - q T_J with the stored q,
+// yscale(y) = y/alpha (Arnoldi) or y (QR).
+hipError_t launch_update(void* Q, int q32, int64_t ldq, int J, double* x, const double* y,
+                         const double* ubuf, int64_t m, const double* coef, int ldc, int arnoldi,
+                         int qcol, const Ctrl* ctrl, hipStream_t s);
 // One-pass QR step: update of step j (q into Q[:, J], w <- w_j) fused with the
 // reduction of step j+1 over [Q_{0..J}, w_j, a_next]; last != 0 reduces only
 // [Q_{0..J}, w_j]^T w_j (a_next unused).  gr.G must equal fused_qr_grid(m, J, last).
-hipError_t launch_fused_qr(double* Q, int64_t ldq, int J, double* w, const double* a_cur,
+hipError_t launch_fused_qr(void* Q, int q32, int64_t ldq, int J, double* w, const double* a_cur,
                            const double* a_next, int64_t m, const double* coef, int ldc, int last,
                            const GridRed& gr, const FinArgs& fin, hipStream_t s);
 int fused_qr_grid(int64_t m, int J, int last);
 constexpr int FUSED_QR_MAX_J = 500;       // columns owned one per thread (512 per workgroup)
-// Q[:, J] /= alpha (coef[2 ldc]) when ctrl->state == RUNNING.
-hipError_t launch_scale_col(double* Q, int64_t ldq, int J, int64_t m, const double* coef,
-                            int ldc, const Ctrl* ctrl, hipStream_t s);
+// Q[:, J] = ubuf / alpha (coef[2 ldc]) when ctrl->state == RUNNING.
+hipError_t launch_scale_col(void* Q, int q32, int64_t ldq, int J, const double* ubuf, int64_t m,
+                            const double* coef, int ldc, const Ctrl* ctrl, hipStream_t s);
 // Out[:, 0..k) = (acc ? Out : 0) + Q[:, 0..p) Z[0..p, 0..k)   (Z device, ldz)
-hipError_t launch_tsgemm(const double* Q, int64_t ldq, int p, const double* Z, int ldz,
-                         int k, double* Out, int64_t ldo, int64_t m, int acc, hipStream_t s);
+hipError_t launch_tsgemm(const void* Q, int q32, int64_t ldq, int p, const double* Z, int ldz,
+                         int k, void* Out, int o32, int64_t ldo, int64_t m, int acc,
+                         hipStream_t s);
+// dst[0..m) = src[0..m) with element-type conversion.
+hipError_t launch_convert(void* dst, int d32, const void* src, int s32, int64_t m,
+                          hipStream_t s);
 
 // Grid sizing for the reductions (number of workgroups for m rows).
 void reduce_grid(int64_t m, int* G, int* GS, int* NG);

@@ -36,20 +36,33 @@ constexpr int NT = 8;            // basis columns per reduction tile
 template <int VW>
 struct RowVec {
   double e[VW];
-  __device__ static RowVec load(const double* p, int64_t u) {
+  // Loads VW consecutive elements (unit u) of a double or float array, widened
+  // to double; stores round to the array's element type.
+  template <typename T>
+  __device__ static RowVec load(const T* p, int64_t u) {
     RowVec r;
-    if constexpr (VW == 2) {
+    if constexpr (VW == 2 && sizeof(T) == 8) {
       const double2 t = reinterpret_cast<const double2*>(p)[u];
       r.e[0] = t.x;
       r.e[1] = t.y;
+    } else if constexpr (VW == 2) {
+      const float2 t = reinterpret_cast<const float2*>(p)[u];
+      r.e[0] = (double)t.x;
+      r.e[1] = (double)t.y;
     } else {
-      r.e[0] = p[u];
+      r.e[0] = (double)p[u];
     }
     return r;
   }
-  __device__ void store(double* p, int64_t u) const {
-    if constexpr (VW == 2) reinterpret_cast<double2*>(p)[u] = make_double2(e[0], e[1]);
-    else p[u] = e[0];
+  template <typename T>
+  __device__ void store(T* p, int64_t u) const {
+    if constexpr (VW == 2 && sizeof(T) == 8) {
+      reinterpret_cast<double2*>(p)[u] = make_double2(e[0], e[1]);
+    } else if constexpr (VW == 2) {
+      reinterpret_cast<float2*>(p)[u] = make_float2((float)e[0], (float)e[1]);
+    } else {
+      p[u] = (T)e[0];
+    }
   }
   __device__ static RowVec zero() {
     RowVec r;
@@ -64,6 +77,10 @@ struct RowVec {
     return s;
   }
 };
+
+// Value of x as stored in an array of T (rounded once when T is float).
+template <typename T>
+__device__ __forceinline__ double stored(double x) { return (double)(T)x; }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -397,8 +414,8 @@ __device__ void finalize(const FinArgs& f, double* red, double* T, double* scrat
 // ---------------------------------------------------------------------------------
 // Reduction pass: per-workgroup partial dot products of [Q_{0..J-1}, x, (y)] with
 // [x, (y)] over a contiguous slab of rows, NT basis columns at a time.
-template <int VW, bool HASY>
-__global__ __launch_bounds__(BS) void reduce_kernel(const double* __restrict__ Q, int64_t ldq,
+template <int VW, bool HASY, typename TQ>
+__global__ __launch_bounds__(BS) void reduce_kernel(const TQ* __restrict__ Q, int64_t ldq,
                                                     int J, const double* __restrict__ x,
                                                     const double* __restrict__ y, int64_t m,
                                                     GridRed gr, FinArgs fin) {
@@ -422,11 +439,13 @@ __global__ __launch_bounds__(BS) void reduce_kernel(const double* __restrict__ Q
     double acc[2 * NT];
 #pragma unroll
     for (int c = 0; c < 2 * NT; ++c) acc[c] = 0.0;
-    const double* colp[NT];
+    const TQ* colq[NT];        // basis columns (k < J)
+    const double* colv[NT];    // the vectors x, y appended as columns J, J+1
 #pragma unroll
     for (int c = 0; c < NT; ++c) {
       const int k = k0 + c;
-      colp[c] = (k < J) ? Q + (int64_t)k * ldq : (k == J ? x : y);
+      colq[c] = Q + (int64_t)(k < J ? k : 0) * ldq;
+      colv[c] = (k == J) ? x : y;
     }
     for (int64_t u = u0 + threadIdx.x; u < u1; u += BS) {
       const RV xv = RV::load(x, u);
@@ -434,7 +453,7 @@ __global__ __launch_bounds__(BS) void reduce_kernel(const double* __restrict__ Q
 #pragma unroll
       for (int c = 0; c < NT; ++c) {
         if (k0 + c < Jt) {
-          const RV q = RV::load(colp[c], u);
+          const RV q = (k0 + c < J) ? RV::load(colq[c], u) : RV::load(colv[c], u);
           acc[c] += q.dot(xv);
           if (HASY) acc[NT + c] += q.dot(yv);
         }
@@ -446,7 +465,7 @@ __global__ __launch_bounds__(BS) void reduce_kernel(const double* __restrict__ Q
 #pragma unroll
       for (int c = 0; c < NT; ++c) {
         if (k0 + c < Jt) {
-          const double q = colp[c][r];
+          const double q = (k0 + c < J) ? (double)colq[c][r] : colv[c][r];
           acc[c] += q * xr;
           if (HASY) acc[NT + c] += q * yr;
         }
@@ -471,10 +490,11 @@ __global__ __launch_bounds__(BS) void reduce_kernel(const double* __restrict__ Q
 }
 
 // u = x - Q_{0..J-1} C written to Q[:, J]; ||u||^2 grid-reduced and finalised.
-template <int VW>
-__global__ __launch_bounds__(BS) void project_norm_kernel(double* __restrict__ Q, int64_t ldq,
+template <int VW, typename TQ>
+__global__ __launch_bounds__(BS) void project_norm_kernel(const TQ* __restrict__ Q, int64_t ldq,
                                                           int J, const double* __restrict__ x,
-                                                          int64_t m, GridRed gr, FinArgs fin) {
+                                                          double* __restrict__ ubuf, int64_t m,
+                                                          GridRed gr, FinArgs fin) {
   extern __shared__ double smem[];
   if (fin.ctrl->state != ST_RUNNING) return;
   double* red = smem;                       // 1
@@ -488,7 +508,6 @@ __global__ __launch_bounds__(BS) void project_norm_kernel(double* __restrict__ Q
   const int64_t u1 = min(units, u0 + per);
   using RV = RowVec<VW>;
   double acc[1] = {0.0};
-  double* qout = Q + (int64_t)J * ldq;
   for (int64_t u = u0 + threadIdx.x; u < u1; u += BS) {
     RV sc = RV::zero();
     for (int k = 0; k < J; ++k) {
@@ -501,15 +520,15 @@ __global__ __launch_bounds__(BS) void project_norm_kernel(double* __restrict__ Q
     RV uu;
 #pragma unroll
     for (int e = 0; e < VW; ++e) uu.e[e] = xv.e[e] - sc.e[e];
-    uu.store(qout, u);
+    uu.store(ubuf, u);
     acc[0] += uu.dot(uu);
   }
   if ((VW == 2) && (m & 1) && blockIdx.x == gr.G - 1 && threadIdx.x == 0) {
     const int64_t r = m - 1;
     double s = 0.0;
-    for (int k = 0; k < J; ++k) s = fma(Q[(int64_t)k * ldq + r], C[k], s);
+    for (int k = 0; k < J; ++k) s = fma((double)Q[(int64_t)k * ldq + r], C[k], s);
     const double uval = x[r] - s;
-    qout[r] = uval;
+    ubuf[r] = uval;
     acc[0] += uval * uval;
   }
   block_sum<1>(acc, shb, gr.P1 + (int64_t)blockIdx.x * gr.ldp, 1);
@@ -517,10 +536,11 @@ __global__ __launch_bounds__(BS) void project_norm_kernel(double* __restrict__ Q
 }
 
 // Update pass: q_{j-1} and w_j, one row unit per thread.
-template <int VW, bool ARN, bool QCOL>
-__global__ __launch_bounds__(BS) void update_kernel(double* __restrict__ Q, int64_t ldq, int J,
+template <int VW, bool ARN, bool QCOL, typename TQ>
+__global__ __launch_bounds__(BS) void update_kernel(TQ* __restrict__ Q, int64_t ldq, int J,
                                                     double* __restrict__ x,
-                                                    const double* __restrict__ y, int64_t m,
+                                                    const double* __restrict__ y,
+                                                    const double* __restrict__ ubuf, int64_t m,
                                                     const double* __restrict__ coef, int ldc,
                                                     const Ctrl* __restrict__ ctrl) {
   if (ctrl->state != ST_RUNNING) return;
@@ -530,7 +550,7 @@ __global__ __launch_bounds__(BS) void update_kernel(double* __restrict__ Q, int6
   const double tJ = T[J];
   const int64_t units = m / VW;
   const int64_t u = (int64_t)blockIdx.x * BS + threadIdx.x;
-  double* qout = Q + (int64_t)J * ldq;
+  TQ* qout = Q + (int64_t)J * ldq;
   if (u < units) {
     RowVec<VW> sc = RowVec<VW>::zero(), st = RowVec<VW>::zero();
 #pragma unroll 8
@@ -546,11 +566,11 @@ __global__ __launch_bounds__(BS) void update_kernel(double* __restrict__ Q, int6
     const RowVec<VW> xv = RowVec<VW>::load(x, u);
     const RowVec<VW> yv = RowVec<VW>::load(y, u);
     RowVec<VW> qc = RowVec<VW>::zero();
-    if (QCOL) qc = RowVec<VW>::load(qout, u);
+    if (QCOL) qc = RowVec<VW>::load(ubuf, u);
     RowVec<VW> qn, wn;
 #pragma unroll
     for (int e = 0; e < VW; ++e) {
-      const double q = QCOL ? qc.e[e] / alpha : (xv.e[e] - sc.e[e]) / alpha;
+      const double q = stored<TQ>(QCOL ? qc.e[e] / alpha : (xv.e[e] - sc.e[e]) / alpha);
       const double yt = ARN ? yv.e[e] / alpha : yv.e[e];
       qn.e[e] = q;
       wn.e[e] = yt - fma(q, tJ, st.e[e]);
@@ -561,13 +581,13 @@ __global__ __launch_bounds__(BS) void update_kernel(double* __restrict__ Q, int6
     const int64_t r = m - 1;
     double sc = 0.0, st = 0.0;
     for (int k = 0; k < J; ++k) {
-      const double q = Q[(int64_t)k * ldq + r];
+      const double q = (double)Q[(int64_t)k * ldq + r];
       sc = fma(q, C[k], sc);
       st = fma(q, T[k], st);
     }
-    const double q = QCOL ? qout[r] / alpha : (x[r] - sc) / alpha;
+    const double q = stored<TQ>(QCOL ? ubuf[r] / alpha : (x[r] - sc) / alpha);
     const double yt = ARN ? y[r] / alpha : y[r];
-    qout[r] = q;
+    qout[r] = (TQ)q;
     x[r] = yt - fma(q, tJ, st);
   }
 }
@@ -588,7 +608,8 @@ constexpr int FT = 64;           // rows per tile
 constexpr int FW = 8;            // wavefronts per workgroup
 constexpr int FBS = FW * 64;
 
-__global__ __launch_bounds__(FBS) void fused_qr_kernel(double* __restrict__ Q, int64_t ldq,
+template <typename TQ>
+__global__ __launch_bounds__(FBS) void fused_qr_kernel(TQ* __restrict__ Q, int64_t ldq,
                                                        int J, double* __restrict__ w,
                                                        const double* __restrict__ a_cur,
                                                        const double* __restrict__ a_next,
@@ -618,13 +639,13 @@ __global__ __launch_bounds__(FBS) void fused_qr_kernel(double* __restrict__ Q, i
     // phase A: partial Q C and Q T over this wavefront's columns, tile into LDS
     double sc = 0.0, st = 0.0;
     if (lane < rows) {
-      const double* qrow = Q + r0 + lane;
+      const TQ* qrow = Q + r0 + lane;
       int k = wv;
       for (; k + 3 * FW < J; k += 4 * FW) {
-        const double q0 = qrow[(int64_t)k * ldq];
-        const double q1 = qrow[(int64_t)(k + FW) * ldq];
-        const double q2 = qrow[(int64_t)(k + 2 * FW) * ldq];
-        const double q3 = qrow[(int64_t)(k + 3 * FW) * ldq];
+        const double q0 = (double)qrow[(int64_t)k * ldq];
+        const double q1 = (double)qrow[(int64_t)(k + FW) * ldq];
+        const double q2 = (double)qrow[(int64_t)(k + 2 * FW) * ldq];
+        const double q3 = (double)qrow[(int64_t)(k + 3 * FW) * ldq];
         tile[(size_t)k * LDT + lane] = q0;
         tile[(size_t)(k + FW) * LDT + lane] = q1;
         tile[(size_t)(k + 2 * FW) * LDT + lane] = q2;
@@ -635,7 +656,7 @@ __global__ __launch_bounds__(FBS) void fused_qr_kernel(double* __restrict__ Q, i
         sc = fma(q3, C[k + 3 * FW], sc); st = fma(q3, T[k + 3 * FW], st);
       }
       for (; k < J; k += FW) {
-        const double q0 = qrow[(int64_t)k * ldq];
+        const double q0 = (double)qrow[(int64_t)k * ldq];
         tile[(size_t)k * LDT + lane] = q0;
         sc = fma(q0, C[k], sc);
         st = fma(q0, T[k], st);
@@ -653,9 +674,9 @@ __global__ __launch_bounds__(FBS) void fused_qr_kernel(double* __restrict__ Q, i
         ST += part[(u * FT + lane) * 2 + 1];
       }
       const int64_t i = r0 + lane;
-      const double q = (w[i] - SC) / alpha;
+      const double q = stored<TQ>((w[i] - SC) / alpha);
       const double wn = a_cur[i] - fma(q, tJ, ST);
-      Q[(int64_t)J * ldq + i] = q;
+      Q[(int64_t)J * ldq + i] = (TQ)q;
       w[i] = wn;
       colq[lane] = q;
       colw[lane] = wn;
@@ -688,12 +709,14 @@ __global__ __launch_bounds__(FBS) void fused_qr_kernel(double* __restrict__ Q, i
   if (grid_reduce(gr, V, red)) finalize(fin, red, Tf, scratch);
 }
 
-__global__ void scale_col_kernel(double* Q, int64_t ldq, int J, int64_t m,
+// q = u / alpha into Q[:, J] (rounded once to the basis type).
+template <typename TQ>
+__global__ void scale_col_kernel(TQ* Q, int64_t ldq, int J, const double* ubuf, int64_t m,
                                  const double* coef, int ldc, const Ctrl* ctrl) {
   if (ctrl->state != ST_RUNNING) return;
   const double alpha = coef[2 * ldc];
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if (i < m) Q[(int64_t)J * ldq + i] = Q[(int64_t)J * ldq + i] / alpha;
+  if (i < m) Q[(int64_t)J * ldq + i] = (TQ)(ubuf[i] / alpha);
 }
 
 // ---------------------------------------------------------------------------------
@@ -737,10 +760,10 @@ __global__ __launch_bounds__(BS) void csr_kernel(OpDev op, const double* __restr
 }
 
 // Out[:, k0+o] = (acc ? Out : 0) + sum_c Q[:, c] Z[c, k0+o]   for o < NO (one row per thread)
-template <int NO>
-__global__ __launch_bounds__(BS) void tsgemm_kernel(const double* __restrict__ Q, int64_t ldq,
+template <int NO, typename TQ, typename TO>
+__global__ __launch_bounds__(BS) void tsgemm_kernel(const TQ* __restrict__ Q, int64_t ldq,
                                                     int p, const double* __restrict__ Z, int ldz,
-                                                    int k, double* __restrict__ Out, int64_t ldo,
+                                                    int k, TO* __restrict__ Out, int64_t ldo,
                                                     int64_t m, int accum) {
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
   const int k0 = blockIdx.y * NO;
@@ -749,7 +772,7 @@ __global__ __launch_bounds__(BS) void tsgemm_kernel(const double* __restrict__ Q
 #pragma unroll
   for (int o = 0; o < NO; ++o) acc[o] = 0.0;
   for (int c = 0; c < p; ++c) {
-    const double q = Q[(int64_t)c * ldq + i];
+    const double q = (double)Q[(int64_t)c * ldq + i];
 #pragma unroll
     for (int o = 0; o < NO; ++o)
       if (k0 + o < k) acc[o] = fma(q, Z[(int64_t)(k0 + o) * ldz + c], acc[o]);
@@ -757,8 +780,8 @@ __global__ __launch_bounds__(BS) void tsgemm_kernel(const double* __restrict__ Q
 #pragma unroll
   for (int o = 0; o < NO; ++o) {
     if (k0 + o < k) {
-      double* out = Out + (int64_t)(k0 + o) * ldo + i;
-      *out = accum ? *out + acc[o] : acc[o];
+      TO* out = Out + (int64_t)(k0 + o) * ldo + i;
+      *out = (TO)(accum ? (double)*out + acc[o] : acc[o]);
     }
   }
 }
@@ -794,6 +817,12 @@ __global__ void fill_kernel(double* p, int64_t n, double val) {
   if (i < n) p[i] = val;
 }
 
+template <typename TD, typename TS>
+__global__ void convert_col_kernel(TD* dst, const TS* src, int64_t m) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i < m) dst[i] = (TD)src[i];
+}
+
 __global__ void copy_cols_kernel(double* dst, int64_t ldd, const double* src, int64_t lds,
                                  int64_t m) {
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
@@ -805,6 +834,9 @@ inline unsigned nblocks(int64_t n) { return (unsigned)((n + BS - 1) / BS); }
 
 template <typename P>
 inline bool aligned16(P p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+inline bool aligned_to(const void* p, unsigned a) {
+  return (reinterpret_cast<uintptr_t>(p) & (uintptr_t)(a - 1)) == 0;
+}
 
 size_t reduce_smem(int J, bool hasy) {
   const int Jt = J + (hasy ? 2 : 1);
@@ -869,44 +901,57 @@ hipError_t launch_spmv(const OpDev& op, const double* x, const double* b, double
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(const double* Q, int64_t ldq, int J, const double* x, const double* y,
-                         int64_t m, const GridRed& gr, const FinArgs& fin, hipStream_t s) {
-  const bool vec = aligned16(Q) && (ldq % 2 == 0) && aligned16(x) && (!y || aligned16(y));
+hipError_t launch_reduce(const void* Q, int q32, int64_t ldq, int J, const double* x,
+                         const double* y, int64_t m, const GridRed& gr, const FinArgs& fin,
+                         hipStream_t s) {
+  const bool vec = aligned_to(Q, q32 ? 8 : 16) && (ldq % 2 == 0) && aligned16(x) &&
+                   (!y || aligned16(y));
   const size_t sm = reduce_smem(J, y != nullptr);
   const dim3 grid(gr.G), block(BS);
-  if (y) {
-    if (vec) reduce_kernel<2, true><<<grid, block, sm, s>>>(Q, ldq, J, x, y, m, gr, fin);
-    else reduce_kernel<1, true><<<grid, block, sm, s>>>(Q, ldq, J, x, y, m, gr, fin);
+#define DCGS2_RED(VW, HY, T) \
+  reduce_kernel<VW, HY, T><<<grid, block, sm, s>>>((const T*)Q, ldq, J, x, y, m, gr, fin)
+  if (q32) {
+    if (y) { if (vec) DCGS2_RED(2, true, float); else DCGS2_RED(1, true, float); }
+    else { if (vec) DCGS2_RED(2, false, float); else DCGS2_RED(1, false, float); }
   } else {
-    if (vec) reduce_kernel<2, false><<<grid, block, sm, s>>>(Q, ldq, J, x, y, m, gr, fin);
-    else reduce_kernel<1, false><<<grid, block, sm, s>>>(Q, ldq, J, x, y, m, gr, fin);
+    if (y) { if (vec) DCGS2_RED(2, true, double); else DCGS2_RED(1, true, double); }
+    else { if (vec) DCGS2_RED(2, false, double); else DCGS2_RED(1, false, double); }
   }
+#undef DCGS2_RED
   return hipGetLastError();
 }
 
-hipError_t launch_project_norm(double* Q, int64_t ldq, int J, const double* x, int64_t m,
-                               const GridRed& gr, const FinArgs& fin, hipStream_t s) {
-  const bool vec = aligned16(Q) && (ldq % 2 == 0) && aligned16(x);
+hipError_t launch_project_norm(const void* Q, int q32, int64_t ldq, int J, const double* x,
+                               double* ubuf, int64_t m, const GridRed& gr, const FinArgs& fin,
+                               hipStream_t s) {
+  const bool vec = aligned_to(Q, q32 ? 8 : 16) && (ldq % 2 == 0) && aligned16(x) &&
+                   aligned16(ubuf);
   const size_t sm = sizeof(double) * (size_t)(2 + NW + (J + 2) + 3 * (J + 2) + 2 * J + 64);
-  if (vec) project_norm_kernel<2><<<gr.G, BS, sm, s>>>(Q, ldq, J, x, m, gr, fin);
-  else project_norm_kernel<1><<<gr.G, BS, sm, s>>>(Q, ldq, J, x, m, gr, fin);
+#define DCGS2_PN(VW, T) \
+  project_norm_kernel<VW, T><<<gr.G, BS, sm, s>>>((const T*)Q, ldq, J, x, ubuf, m, gr, fin)
+  if (q32) { if (vec) DCGS2_PN(2, float); else DCGS2_PN(1, float); }
+  else { if (vec) DCGS2_PN(2, double); else DCGS2_PN(1, double); }
+#undef DCGS2_PN
   return hipGetLastError();
 }
 
-hipError_t launch_update(double* Q, int64_t ldq, int J, double* x, const double* y, int64_t m,
-                         const double* coef, int ldc, int arnoldi, int qcol, const Ctrl* ctrl,
-                         hipStream_t s) {
-  const bool vec = aligned16(Q) && (ldq % 2 == 0) && aligned16(x) && aligned16(y);
+hipError_t launch_update(void* Q, int q32, int64_t ldq, int J, double* x, const double* y,
+                         const double* ubuf, int64_t m, const double* coef, int ldc, int arnoldi,
+                         int qcol, const Ctrl* ctrl, hipStream_t s) {
+  const bool vec = aligned_to(Q, q32 ? 8 : 16) && (ldq % 2 == 0) && aligned16(x) &&
+                   aligned16(y) && (!ubuf || aligned16(ubuf));
   const int64_t units = vec ? m / 2 : m;
   const unsigned nb = nblocks(units + 1);
-#define DCGS2_UPD(VW, A, QC) update_kernel<VW, A, QC><<<nb, BS, 0, s>>>(Q, ldq, J, x, y, m, coef, ldc, ctrl)
-  if (vec) {
-    if (arnoldi) { if (qcol) DCGS2_UPD(2, true, true); else DCGS2_UPD(2, true, false); }
-    else { if (qcol) DCGS2_UPD(2, false, true); else DCGS2_UPD(2, false, false); }
-  } else {
-    if (arnoldi) { if (qcol) DCGS2_UPD(1, true, true); else DCGS2_UPD(1, true, false); }
-    else { if (qcol) DCGS2_UPD(1, false, true); else DCGS2_UPD(1, false, false); }
-  }
+#define DCGS2_UPD(VW, A, QC, T) \
+  update_kernel<VW, A, QC, T><<<nb, BS, 0, s>>>((T*)Q, ldq, J, x, y, ubuf, m, coef, ldc, ctrl)
+#define DCGS2_UPD_T(VW, T)                                                   \
+  do {                                                                       \
+    if (arnoldi) { if (qcol) DCGS2_UPD(VW, true, true, T); else DCGS2_UPD(VW, true, false, T); } \
+    else { if (qcol) DCGS2_UPD(VW, false, true, T); else DCGS2_UPD(VW, false, false, T); }       \
+  } while (0)
+  if (q32) { if (vec) DCGS2_UPD_T(2, float); else DCGS2_UPD_T(1, float); }
+  else { if (vec) DCGS2_UPD_T(2, double); else DCGS2_UPD_T(1, double); }
+#undef DCGS2_UPD_T
 #undef DCGS2_UPD
   return hipGetLastError();
 }
@@ -929,26 +974,50 @@ int fused_qr_grid(int64_t m, int J, int last) {
   return (int)(g < 1 ? 1 : g);
 }
 
-hipError_t launch_fused_qr(double* Q, int64_t ldq, int J, double* w, const double* a_cur,
+hipError_t launch_fused_qr(void* Q, int q32, int64_t ldq, int J, double* w, const double* a_cur,
                            const double* a_next, int64_t m, const double* coef, int ldc, int last,
                            const GridRed& gr, const FinArgs& fin, hipStream_t s) {
-  fused_qr_kernel<<<gr.G, FBS, fused_qr_smem(J, last), s>>>(Q, ldq, J, w, a_cur, a_next, m, coef,
-                                                             ldc, last, gr, fin);
+  const size_t sm = fused_qr_smem(J, last);
+  if (q32)
+    fused_qr_kernel<float><<<gr.G, FBS, sm, s>>>((float*)Q, ldq, J, w, a_cur, a_next, m, coef,
+                                                 ldc, last, gr, fin);
+  else
+    fused_qr_kernel<double><<<gr.G, FBS, sm, s>>>((double*)Q, ldq, J, w, a_cur, a_next, m, coef,
+                                                  ldc, last, gr, fin);
   return hipGetLastError();
 }
 
-hipError_t launch_scale_col(double* Q, int64_t ldq, int J, int64_t m, const double* coef, int ldc,
-                            const Ctrl* ctrl, hipStream_t s) {
-  scale_col_kernel<<<nblocks(m), BS, 0, s>>>(Q, ldq, J, m, coef, ldc, ctrl);
+hipError_t launch_scale_col(void* Q, int q32, int64_t ldq, int J, const double* ubuf, int64_t m,
+                            const double* coef, int ldc, const Ctrl* ctrl, hipStream_t s) {
+  if (q32)
+    scale_col_kernel<float><<<nblocks(m), BS, 0, s>>>((float*)Q, ldq, J, ubuf, m, coef, ldc, ctrl);
+  else
+    scale_col_kernel<double><<<nblocks(m), BS, 0, s>>>((double*)Q, ldq, J, ubuf, m, coef, ldc,
+                                                       ctrl);
   return hipGetLastError();
 }
 
-hipError_t launch_tsgemm(const double* Q, int64_t ldq, int p, const double* Z, int ldz, int k,
-                         double* Out, int64_t ldo, int64_t m, int acc, hipStream_t s) {
+hipError_t launch_tsgemm(const void* Q, int q32, int64_t ldq, int p, const double* Z, int ldz,
+                         int k, void* Out, int o32, int64_t ldo, int64_t m, int acc,
+                         hipStream_t s) {
   if (m <= 0 || k <= 0) return hipSuccess;
   constexpr int NO = 8;
   const dim3 grid(nblocks(m), (unsigned)((k + NO - 1) / NO));
-  tsgemm_kernel<NO><<<grid, BS, 0, s>>>(Q, ldq, p, Z, ldz, k, Out, ldo, m, acc);
+#define DCGS2_TS(TQ, TO) \
+  tsgemm_kernel<NO, TQ, TO><<<grid, BS, 0, s>>>((const TQ*)Q, ldq, p, Z, ldz, k, (TO*)Out, ldo, m, acc)
+  if (q32) { if (o32) DCGS2_TS(float, float); else DCGS2_TS(float, double); }
+  else { if (o32) DCGS2_TS(double, float); else DCGS2_TS(double, double); }
+#undef DCGS2_TS
+  return hipGetLastError();
+}
+
+hipError_t launch_convert(void* dst, int d32, const void* src, int s32, int64_t m,
+                          hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  if (d32 && s32) convert_col_kernel<float, float><<<nblocks(m), BS, 0, s>>>((float*)dst, (const float*)src, m);
+  else if (d32) convert_col_kernel<float, double><<<nblocks(m), BS, 0, s>>>((float*)dst, (const double*)src, m);
+  else if (s32) convert_col_kernel<double, float><<<nblocks(m), BS, 0, s>>>((double*)dst, (const float*)src, m);
+  else convert_col_kernel<double, double><<<nblocks(m), BS, 0, s>>>((double*)dst, (const double*)src, m);
   return hipGetLastError();
 }
 
