@@ -1,0 +1,80 @@
+"""GPU parity of the FP32-stored basis (dcgs2_qr_q32 / dcgs2_arnoldi_q32 and the
+GMRES option) against the oracle's FP32-basis variant.
+
+Both sides compute every q in FP64 and round it once to FP32; the FP64 values
+differ only by summation order (~1e-16 relative), so a stored column differs at
+most by one FP32 ulp in rare entries.  Gate: R/H within 1e-10 relative (they are
+FP64 quantities computed from nearly identical inputs), Q within 4 eps_32 entrywise.
+"""
+import numpy as np
+import pytest
+
+from oracle import arnoldi as ar
+from oracle import gram_schmidt as gs
+from oracle import operators as ops
+from oracle.gmres import gmres_dcgs2
+from oracle.metrics import loss_of_orthogonality
+from paper_2104_01253_amd import binding, synth
+from tests._gpu import dev_matrix, dev_vector, host, relnorm, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+EPS32 = float(np.finfo(np.float32).eps)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch_cuda()
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("one_pass", [True, False])
+@pytest.mark.parametrize("m,n,ce", [(1023, 3, 2), (20011, 64, 8), (300001, 100, 8)])
+def test_qr_q32_parity(ctx, m, n, ce, one_pass):
+    torch = torch_cuda()
+    B = synth.tall_skinny(m, n, ce, seed_g=200 + m, seed_v=9)
+    Bd = dev_matrix(B)
+    Q = binding.colmajor_empty(m, n, dtype=torch.float32)
+    ctx.set_qr_schedule(one_pass)
+    try:
+        R, rc, st = ctx.qr(Bd, Q)
+    finally:
+        ctx.set_qr_schedule(True)
+    ref = gs.dcgs2_qr(B, qdtype=np.float32)
+    Qh = host(Q).astype(np.float64)
+    assert rc == 0 and st["reductions"] == n + 1
+    say("q32 R rel", relnorm(R, ref["R"]), "Q max", np.max(np.abs(Qh - ref["Q"])))
+    assert relnorm(R, ref["R"]) <= 1e-10
+    assert np.max(np.abs(Qh - ref["Q"].astype(np.float64))) <= 4 * EPS32
+    assert loss_of_orthogonality(Qh) <= 60 * EPS32
+
+
+def test_arnoldi_q32_parity(ctx):
+    torch = torch_cuda()
+    prob, r0, n = synth.config1()
+    A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
+    Q = binding.colmajor_empty(prob.m, n + 1, dtype=torch.float32)
+    H, rc, st = ctx.arnoldi(binding.stencil_op(prob.grid, prob.D, prob.vel), dev_vector(r0), n, Q)
+    ref = ar.dcgs2_arnoldi(lambda x: A @ x, r0, n, qdtype=np.float32)
+    assert rc == 0
+    assert relnorm(H, ref["H"]) <= 1e-10
+    assert np.max(np.abs(host(Q).astype(np.float64) - ref["Q"])) <= 4 * EPS32
+
+
+def test_gmres_q32(ctx):
+    torch = torch_cuda()
+    prob, b = synth.config3(32)
+    A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
+    op = binding.stencil_op(prob.grid, prob.D, prob.vel)
+    x = torch.zeros(prob.m, dtype=torch.float64, device="cuda")
+    ctx.set_basis_precision(32)
+    try:
+        rc, info = ctx.gmres(op, dev_vector(b), x, restart=50, rtol=1e-8)
+    finally:
+        ctx.set_basis_precision(64)
+    _, iref = gmres_dcgs2(A, b, restart=50, rtol=1e-8, qdtype=np.float32)
+    relres = np.linalg.norm(b - A @ host(x)) / np.linalg.norm(b)
+    say("gmres q32", info, iref["iters"])
+    assert rc == 0 and relres <= 1e-8
+    assert abs(info["iters"] - iref["iters"]) <= 1
