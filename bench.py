@@ -164,6 +164,26 @@ def main():
                     for k, v in prof.items()},
         "roofline": roof,
     }
+    if not args.no_legs:
+        # the comparator (Alg. cgs2, three reductions per column) on the same B
+        def cgs2_once():
+            _, rc, _ = ctx.cgs2_qr(Bd, Qd)
+            assert rc == binding.OK, rc
+        cgs2_once()
+        Tc = timed(torch, cgs2_once, 3) / 3
+        out["cgs2_qr"] = {"steps_per_s": round(n / Tc, 1), "ms": round(Tc * 1e3, 3),
+                          "dcgs2_speedup": round(Tc / (ms_per_step * 1e-3), 3)}
+        # FP32-stored basis, FP64 reductions (same B)
+        Q32 = binding.colmajor_empty(m, n, dtype=torch.float32)
+
+        def q32_once():
+            _, rc, _ = ctx.qr(Bd, Q32)
+            assert rc == binding.OK, rc
+        q32_once()
+        T32 = timed(torch, q32_once, 3) / 3
+        out["qr_fp32_basis"] = {"steps_per_s": round(n / T32, 1), "ms": round(T32 * 1e3, 3)}
+        del Q32
+        log(f"[bench] cgs2 {out['cgs2_qr']}, fp32 basis {out['qr_fp32_basis']}")
     del Bd, Qd
     torch.cuda.empty_cache()
 
@@ -199,6 +219,15 @@ def main():
         out["gmres50_128cube_fp64"] = {"time_to_1e-8_s": round(tg, 4), "iters": info["iters"],
                                        "cycles": info["cycles"], "relres_true": info["relres_true"],
                                        "status": rc}
+        ctx.set_basis_precision(32)
+        gm_once()
+        t0 = time.perf_counter()
+        rc, info = gm_once()
+        tg32 = time.perf_counter() - t0
+        ctx.set_basis_precision(64)
+        out["gmres50_128cube_fp32_basis"] = {"time_to_1e-8_s": round(tg32, 4), "iters": info["iters"],
+                                             "relres_true": info["relres_true"], "status": rc,
+                                             "speedup_vs_fp64": round(tg / tg32, 3)}
         ks = synth.cd2d(128, vel=(25.0, 40.0))
         kop = binding.stencil_op(ks.grid, ks.D, ks.vel)
         v0 = torch.from_numpy(synth.normal_vector(ks.m, 1)).cuda()

@@ -162,6 +162,14 @@ int dcgs2_qr_q32(dcgs2_ctx ctx, int64_t m, int32_t n, const double* B, int64_t l
 int dcgs2_arnoldi_q32(dcgs2_ctx ctx, const dcgs2_op* A, const double* r0, int32_t n,
                       float* Q, int64_t ldq, double* H_host, int32_t ldh, dcgs2_stats* st);
 
+/* Comparator: classical Gram-Schmidt with reorthogonalisation, Alg. cgs2 (Sec. 3):
+ * per column S = Q^T a_j, w = a_j - Q S, C = Q^T w, u = w - Q C, alpha = ||u||,
+ * q_j = u/alpha, R_{1:j-1,j} = S + C -- three global reductions and four passes
+ * over Q per column (the method DCGS2 is measured against).  Same arguments,
+ * layout, ownership and status codes as dcgs2_qr (FP64 basis only). */
+int cgs2_qr(dcgs2_ctx ctx, int64_t m, int32_t n, const double* B, int64_t ldb, double* Q,
+            int64_t ldq, double* R_host, int32_t ldr, dcgs2_stats* st);
+
 /* Storage precision (64 = FP64, default; 32 = FP32) of the internal Krylov bases
  * of gmres_solve and krylov_schur_eigs; x, r, H, the Givens and Schur work and
  * all reductions stay FP64.  Returns DCGS2_EINVAL for other values. */

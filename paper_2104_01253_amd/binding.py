@@ -24,7 +24,7 @@ MAX_N = 1024
 EXPORTS = ("dcgs2_create", "dcgs2_destroy", "dcgs2_set_tolerances", "dcgs2_qr", "dcgs2_arnoldi",
            "gmres_solve", "krylov_schur_eigs", "dcgs2_apply", "dcgs2_status_str",
            "dcgs2_profile_enable", "dcgs2_profile_read", "dcgs2_set_qr_schedule",
-           "dcgs2_qr_q32", "dcgs2_arnoldi_q32", "dcgs2_set_basis_precision")
+           "dcgs2_qr_q32", "dcgs2_arnoldi_q32", "dcgs2_set_basis_precision", "cgs2_qr")
 
 
 class Stats(ctypes.Structure):
@@ -84,6 +84,7 @@ def load(path: str = LIB_PATH):
     lib.dcgs2_set_qr_schedule.argtypes = [c_void_p, c_int]
     lib.dcgs2_set_basis_precision.argtypes = [c_void_p, c_int]
     lib.dcgs2_qr_q32.argtypes = lib.dcgs2_qr.argtypes
+    lib.cgs2_qr.argtypes = lib.dcgs2_qr.argtypes
     lib.dcgs2_arnoldi_q32.argtypes = lib.dcgs2_arnoldi.argtypes
     lib.dcgs2_profile_read.argtypes = [c_void_p, POINTER(KernelStat), c_int32, c_int32]
     lib.dcgs2_status_str.argtypes = [c_int]
@@ -91,7 +92,7 @@ def load(path: str = LIB_PATH):
     for name in ("dcgs2_create", "dcgs2_destroy", "dcgs2_set_tolerances", "dcgs2_qr",
                  "dcgs2_arnoldi", "gmres_solve", "krylov_schur_eigs", "dcgs2_apply",
                  "dcgs2_profile_enable", "dcgs2_profile_read", "dcgs2_set_qr_schedule",
-           "dcgs2_qr_q32", "dcgs2_arnoldi_q32", "dcgs2_set_basis_precision"):
+           "dcgs2_qr_q32", "dcgs2_arnoldi_q32", "dcgs2_set_basis_precision", "cgs2_qr"):
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -254,6 +255,21 @@ class Context:
         rc = fn(self._h, m, n, pb, ldb, pq, ldq, R.ctypes.data_as(c_void_p), n, ctypes.byref(st))
         if rc < 0:
             raise DCGS2Error(rc, "dcgs2_qr")
+        return R, rc, st.as_dict()
+
+    def cgs2_qr(self, B, Q):
+        """Comparator: CGS2 QR (three reductions per column); returns (R, status, stats)."""
+        m, n = B.shape
+        pb, ldb = _colmajor_args(B, "B")
+        pq, ldq = _colmajor_args(Q, "Q")
+        if Q.shape != (m, n):
+            raise ValueError("Q must have B's shape")
+        R = np.zeros((n, n), order="F")
+        st = Stats()
+        rc = self._lib.cgs2_qr(self._h, m, n, pb, ldb, pq, ldq, R.ctypes.data_as(c_void_p), n,
+                               ctypes.byref(st))
+        if rc < 0:
+            raise DCGS2Error(rc, "cgs2_qr")
         return R, rc, st.as_dict()
 
     def arnoldi(self, op: Op, r0, n: int, Q):

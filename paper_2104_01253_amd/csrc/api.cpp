@@ -586,6 +586,50 @@ int dcgs2_arnoldi_q32(dcgs2_ctx c, const dcgs2_op* A, const double* r0, int32_t 
   return arnoldi_impl(c, A, r0, n, Q, 1, ldq, H_host, ldh, st);
 }
 
+int cgs2_qr(dcgs2_ctx c, int64_t m, int32_t n, const double* B, int64_t ldb, double* Q,
+            int64_t ldq, double* R_host, int32_t ldr, dcgs2_stats* st) {
+  if (!c || m < 1 || n < 1 || n > DCGS2_MAX_N || (int64_t)n > m || !B || !Q || !R_host ||
+      ldb < m || ldq < m || ldr < n)
+    return DCGS2_EINVAL;
+  int rc;
+  if ((rc = ctx_ready(c))) return rc;
+  if ((rc = ensure_vectors(c, m))) return rc;
+  c->kernels = 0;
+  Expansion e;
+  e.qr = true;
+  e.m = m;
+  e.Q = Q; e.q32 = 0; e.ldq = ldq; e.B = B; e.ldb = ldb;
+  e.ldh = n;
+  if ((rc = setup_expansion(c, e, 0.0))) return rc;
+  CKL(launch_fill(c->R, (int64_t)n * n, 0.0, c->stream));
+  hipStream_t s = c->stream;
+  const double vm = 8.0 * (double)m;
+  // Alg. cgs2, column j (0-based): S = Q^T a; w = a - Q S; C = Q^T w; u = w - Q C;
+  // alpha = ||u||; q = u/alpha; R_{:,j} = [S + C; alpha] -- three reductions.
+  for (int j = 0; j < n; ++j) {
+    const double* a = B + (int64_t)j * ldb;
+    const double* x = a;
+    if (j > 0) {
+      KL(K_REDUCE, vm * (j + 1),
+         launch_reduce(Q, 0, ldq, j, a, nullptr, m, e.gr, e.fin(FIN_CGS2_S, j + 2, j), s));
+      KL(K_PROJNORM, vm * (j + 2),
+         launch_project_norm(Q, 0, ldq, j, a, c->w, m, e.gr, e.fin(FIN_NONE, j + 2, j), s));
+      KL(K_REDUCE, vm * (j + 1),
+         launch_reduce(Q, 0, ldq, j, c->w, nullptr, m, e.gr, e.fin(FIN_LAST1, j + 2, j), s));
+      x = c->w;
+    }
+    KL(K_PROJNORM, vm * (j + 2),
+       launch_project_norm(Q, 0, ldq, j, x, c->r, m, e.gr, e.fin(FIN_LAST2, j + 2, j), s));
+    KL(K_SCALE, vm * 2, launch_scale_col(Q, 0, ldq, j, c->r, m, c->coef, LDC, c->ctrl, s));
+  }
+  Ctrl sc{};
+  if ((rc = read_ctrl(c, &sc))) return rc;
+  const int status = status_of(sc);
+  if ((rc = copy_to_host(c, c->R, n, n, n, R_host, ldr))) return rc;
+  fill_stats(st, sc, c->kernels, status);
+  return status;
+}
+
 int dcgs2_set_basis_precision(dcgs2_ctx c, int bits) {
   if (!c || (bits != 32 && bits != 64)) return DCGS2_EINVAL;
   c->basis_q32 = bits == 32;

@@ -42,6 +42,8 @@ enum FinKind : int {
   FIN_LAST1 = 3,       // last column, reduction 1: c = Q^T w
   FIN_LAST2 = 4,       // last column, reduction 2: alpha = ||w - Q c||
   FIN_NORM = 5,        // plain squared norm into ctrl->norm2
+  FIN_NONE = 6,        // no scalar work (a projection whose norm is not needed)
+  FIN_CGS2_S = 7,      // CGS2 first projection: S = Q^T a into coef and Sprev, rho = ||a||
 };
 
 struct FinArgs {

@@ -299,6 +299,21 @@ __device__ void finalize(const FinArgs& f, double* red, double* T, double* scrat
     case FIN_NORM:
       if (threadIdx.x == 0) { ctrl->norm2 = red[0]; ctrl->reductions += 1; }
       return;
+    case FIN_NONE:
+      return;
+    case FIN_CGS2_S: {                     // S = Q^T a (and a^T a): first CGS2 projection
+      any_nonfinite(red, J + 1, &s_flag);
+      if (threadIdx.x == 0) {
+        ctrl->reductions += 1;
+        if (s_flag) { ctrl->state = ST_NONFINITE; ctrl->stop_step = j; }
+        ctrl->rho_next = sqrt(red[J]);
+      }
+      for (int i = threadIdx.x; i < J; i += (int)blockDim.x) {
+        f.coef[i] = red[i];
+        f.Sprev[i] = red[i];
+      }
+      return;
+    }
     case FIN_LAST1: {                      // c = Q^T w (and w^T w)
       any_nonfinite(red, J + 1, &s_flag);
       if (threadIdx.x == 0) {

@@ -127,3 +127,17 @@ def test_qr_full_size_kappa_1e8(ctx):
     loo = loss_of_orthogonality(Q)
     say("loo", loo)
     assert loo <= 1e-13
+
+
+@pytest.mark.parametrize("m,n,ce", [(4097, 17, 2), (20011, 64, 8)])
+def test_cgs2_comparator_parity(ctx, m, n, ce):
+    """The CGS2 comparator against the oracle's Alg. cgs2 (three reductions per column)."""
+    B = synth.tall_skinny(m, n, ce, seed_g=300 + m, seed_v=5)
+    Bd = dev_matrix(B)
+    Qd = binding.colmajor_empty(m, n)
+    R, rc, st = ctx.cgs2_qr(Bd, Qd)
+    Qr, Rr, red = gs.cgs2_qr(B)
+    assert rc == 0 and st["reductions"] == red == 3 * (n - 1) + 1
+    assert relnorm(R, Rr) <= TOL
+    assert np.linalg.norm((host(Qd) - Qr) @ Rr) / np.linalg.norm(B) <= TOL
+    assert loss_of_orthogonality(host(Qd)) <= 1e-13
