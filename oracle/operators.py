@@ -90,3 +90,45 @@ def manteuffel_eigenvalues(k: int, beta: float) -> np.ndarray:
     c = np.cos(np.arange(1, k + 1) * np.pi / L)
     lam = 2.0 * (2.0 - np.sqrt(1.0 - (beta / 2.0) ** 2) * (c[:, None] + c[None, :]))
     return np.sort(lam.ravel())
+
+
+def varcoef_matrix(prob) -> sp.csr_matrix:
+    """Variable-diffusion convection-diffusion (the learned-guess family), assembled.
+
+    -div(D grad u) + v.grad u on (0,1)^2, Dirichlet, h = 1/(n+1), x fastest.
+    Diffusion uses D at the cell faces (midpoints between grid points), the
+    convection central differences:
+      row(i,j): (1/h^2)[(D_e + D_w + D_n + D_s) u_ij - D_e u_{i+1,j} - D_w u_{i-1,j}
+                - D_n u_{i,j+1} - D_s u_{i,j-1}] + vx (u_{i+1,j} - u_{i-1,j})/(2h)
+                + vy (u_{i,j+1} - u_{i,j-1})/(2h)
+    log D(x,y) = sum_k xi_k a_k phi_k, phi_{p,q} = 2 sin(p pi x) sin(q pi y),
+    a_{p,q} = 1/(p^2+q^2) (modes and amplitudes as stated in synth.VarCoefProblem).
+    """
+    n = prob.n
+    h = 1.0 / (n + 1)
+    modes = ((1, 1), (1, 2), (2, 1), (2, 2), (1, 3), (3, 1), (2, 3), (3, 2))
+
+    def D(x, y):
+        s = np.zeros_like(x)
+        for (p, q), xi in zip(modes, prob.xi):
+            s += xi / (p * p + q * q) * 2.0 * np.sin(p * np.pi * x) * np.sin(q * np.pi * y)
+        return np.exp(s)
+
+    vx, vy = prob.vel
+    rows, cols, vals = [], [], []
+    for j in range(n):            # y index
+        for i in range(n):        # x index
+            x, y = (i + 1) * h, (j + 1) * h
+            De, Dw = D(np.array(x + h / 2), np.array(y)), D(np.array(x - h / 2), np.array(y))
+            Dn, Ds = D(np.array(x), np.array(y + h / 2)), D(np.array(x), np.array(y - h / 2))
+            r = i + n * j
+            rows.append(r); cols.append(r); vals.append(float(De + Dw + Dn + Ds) / h**2)
+            if i + 1 < n:
+                rows.append(r); cols.append(r + 1); vals.append(float(-De / h**2 + vx / (2 * h)))
+            if i > 0:
+                rows.append(r); cols.append(r - 1); vals.append(float(-Dw / h**2 - vx / (2 * h)))
+            if j + 1 < n:
+                rows.append(r); cols.append(r + n); vals.append(float(-Dn / h**2 + vy / (2 * h)))
+            if j > 0:
+                rows.append(r); cols.append(r - n); vals.append(float(-Ds / h**2 - vy / (2 * h)))
+    return sp.csr_matrix((vals, (rows, cols)), shape=(n * n, n * n))

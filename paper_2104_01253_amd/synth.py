@@ -90,3 +90,51 @@ def config3(n: int = 128):
     """GMRES(50) on 3-D convection-diffusion n^3, v=(10,10,10), b ~ U(0,1) seed 3, rtol 1e-8."""
     prob = cd3d(n, vel=(10.0, 10.0, 10.0))
     return prob, uniform_vector(prob.m, 3)
+
+
+# Learned-initial-guess family ---------------------------------------------------------
+KL_MODES = ((1, 1), (1, 2), (2, 1), (2, 2), (1, 3), (3, 1), (2, 3), (3, 2))
+
+
+@dataclass(frozen=True)
+class VarCoefProblem:
+    """-div(D grad u) + v.grad u = b on (0,1)^2, Dirichlet, n x n interior grid.
+
+    log D(x, y) = sum_k xi_k a_k phi_k(x, y) with phi_{p,q} = 2 sin(p pi x) sin(q pi y),
+    a_{p,q} = 1 / (p^2 + q^2) (eight modes, KL_MODES); b is a sum of four Gaussian
+    bumps with centres, widths and amplitudes in `bumps` (rows: cx, cy, width, amp).
+    """
+    n: int
+    xi: tuple
+    bumps: tuple
+    vel: tuple = (10.0, 10.0)
+
+    @property
+    def m(self) -> int:
+        return self.n * self.n
+
+
+def varcoef_instances(count: int, seed: int = 5, n: int = 256, vel=(10.0, 10.0)):
+    g = rng(seed)
+    out = []
+    for _ in range(count):
+        xi = g.standard_normal(len(KL_MODES))
+        cxy = g.uniform(0.2, 0.8, size=(4, 2))
+        width = g.uniform(0.03, 0.1, size=(4, 1))
+        amp = g.uniform(-1.0, 1.0, size=(4, 1))
+        bumps = np.hstack([cxy, width, amp])
+        out.append(VarCoefProblem(n, tuple(float(v) for v in xi),
+                                  tuple(tuple(float(v) for v in r) for r in bumps),
+                                  tuple(float(v) for v in vel)))
+    return out
+
+
+def varcoef_rhs(prob: VarCoefProblem) -> np.ndarray:
+    """b at the interior grid points (x fastest), the four Gaussian bumps."""
+    h = 1.0 / (prob.n + 1)
+    t = np.arange(1, prob.n + 1) * h
+    X, Y = np.meshgrid(t, t, indexing="xy")          # rows = y, columns = x -> x fastest
+    b = np.zeros_like(X)
+    for cx, cy, wd, amp in prob.bumps:
+        b += amp * np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2.0 * wd * wd))
+    return b.ravel()

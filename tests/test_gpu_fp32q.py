@@ -46,7 +46,13 @@ def test_qr_q32_parity(ctx, m, n, ce, one_pass):
     assert rc == 0 and st["reductions"] == n + 1
     say("q32 R rel", relnorm(R, ref["R"]), "Q max", np.max(np.abs(Qh - ref["Q"])))
     assert relnorm(R, ref["R"]) <= 1e-10
-    assert np.max(np.abs(Qh - ref["Q"].astype(np.float64))) <= 4 * EPS32
+    Qr = ref["Q"].astype(np.float64)
+    # a one-ulp difference in an early stored column is amplified by kappa(B_{1:j}) in
+    # the later columns, so raw Q is compared only where kappa is small; (dQ) R is
+    # meaningful at any conditioning
+    assert np.linalg.norm((Qh - Qr) @ ref["R"]) / np.linalg.norm(B) <= 10 * EPS32
+    if ce <= 2:
+        assert np.max(np.abs(Qh - Qr)) <= 4 * EPS32
     assert loss_of_orthogonality(Qh) <= 60 * EPS32
 
 
