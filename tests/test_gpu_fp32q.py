@@ -2,9 +2,10 @@
 GMRES option) against the oracle's FP32-basis variant.
 
 Both sides compute every q in FP64 and round it once to FP32; the FP64 values
-differ only by summation order (~1e-16 relative), so a stored column differs at
-most by one FP32 ulp in rare entries.  Gate: R/H within 1e-10 relative (they are
-FP64 quantities computed from nearly identical inputs), Q within 4 eps_32 entrywise.
+differ only by summation order (~1e-16 relative), so a stored entry differs by at
+most one FP32 ulp, rarely.  QR: R within 1e-10 relative, (dQ)R within 10 eps_32,
+raw Q within 4 eps_32 at low kappa.  Arnoldi: H within 20 eps_32 (a flip propagates
+through the matvec), plus the representation error and orthogonality.
 """
 import numpy as np
 import pytest
@@ -13,7 +14,7 @@ from oracle import arnoldi as ar
 from oracle import gram_schmidt as gs
 from oracle import operators as ops
 from oracle.gmres import gmres_dcgs2
-from oracle.metrics import loss_of_orthogonality
+from oracle.metrics import loss_of_orthogonality, representation_error
 from paper_2104_01253_amd import binding, synth
 from tests._gpu import dev_matrix, dev_vector, host, relnorm, say, torch_cuda
 
@@ -64,8 +65,14 @@ def test_arnoldi_q32_parity(ctx):
     H, rc, st = ctx.arnoldi(binding.stencil_op(prob.grid, prob.D, prob.vel), dev_vector(r0), n, Q)
     ref = ar.dcgs2_arnoldi(lambda x: A @ x, r0, n, qdtype=np.float32)
     assert rc == 0
-    assert relnorm(H, ref["H"]) <= 1e-10
-    assert np.max(np.abs(host(Q).astype(np.float64) - ref["Q"])) <= 4 * EPS32
+    # The FP32-stored Arnoldi is defined only to O(eps_32): one rounding flip in an
+    # early column feeds every later column through the matvec (on the CPU oracle, a
+    # 1e-16 relative change of r0 moves H by 1.4e-8 relative).  Gate at 20 eps_32 and
+    # check the decomposition itself.
+    Qh = host(Q).astype(np.float64)
+    assert relnorm(H, ref["H"]) <= 20 * EPS32
+    assert representation_error(A, Qh, H, n) <= EPS32
+    assert loss_of_orthogonality(Qh) <= 60 * EPS32
 
 
 def test_gmres_q32(ctx):
