@@ -120,9 +120,21 @@ int dcgs2_set_tolerances(dcgs2_ctx ctx, double tau, double eta);
  * reduction of step j+1 share one read of Q (the next column a_{j+1} is already
  * known in QR, so both use the same Q rows); the arithmetic and the one reduction
  * per column are those of Alg. qr.  one_pass = 0: separate reduction and update
- * passes, as for Arnoldi.  The one-pass schedule is used when n <= 502.
+ * passes, as for Arnoldi.  The one-pass schedule is used when n <= 127.
  * Returns DCGS2_EINVAL unless one_pass is 0 or 1. */
 int dcgs2_set_qr_schedule(dcgs2_ctx ctx, int one_pass);
+
+/* Kernel shape knobs (chosen by the autotuner in paper_2104_01253_amd/autotune.py,
+ * or left at their defaults).  They change launch shapes only, never the
+ * arithmetic or the summation order within a workgroup.
+ *  DCGS2_TUNE_FUSED_WAVES : wavefronts per workgroup of the one-pass QR kernel,
+ *                           8 or 16 (default 16).
+ *  DCGS2_TUNE_REDUCE_GRID : upper bound on the workgroups of a reduction pass,
+ *                           1..1024, or 0 for automatic (default).
+ * Returns DCGS2_EINVAL for an unknown key or value. */
+enum { DCGS2_TUNE_FUSED_WAVES = 0, DCGS2_TUNE_REDUCE_GRID = 1 };
+int dcgs2_set_tuning(dcgs2_ctx ctx, int32_t key, int32_t value);
+int dcgs2_get_tuning(dcgs2_ctx ctx, int32_t key, int32_t* value);
 
 /* Left-looking DCGS2 QR, Alg. qr (Sec. 3): B = Q R with one global reduction per
  * column, the last column finished by CGS2 (two reductions; end of Sec. 3).

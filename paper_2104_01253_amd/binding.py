@@ -24,7 +24,9 @@ MAX_N = 1024
 EXPORTS = ("dcgs2_create", "dcgs2_destroy", "dcgs2_set_tolerances", "dcgs2_qr", "dcgs2_arnoldi",
            "gmres_solve", "krylov_schur_eigs", "dcgs2_apply", "dcgs2_status_str",
            "dcgs2_profile_enable", "dcgs2_profile_read", "dcgs2_set_qr_schedule",
-           "dcgs2_qr_q32", "dcgs2_arnoldi_q32", "dcgs2_set_basis_precision", "cgs2_qr")
+           "dcgs2_qr_q32", "dcgs2_arnoldi_q32", "dcgs2_set_basis_precision", "cgs2_qr",
+           "dcgs2_set_tuning", "dcgs2_get_tuning")
+TUNE_FUSED_WAVES, TUNE_REDUCE_GRID = 0, 1
 
 
 class Stats(ctypes.Structure):
@@ -85,6 +87,8 @@ def load(path: str = LIB_PATH):
     lib.dcgs2_set_basis_precision.argtypes = [c_void_p, c_int]
     lib.dcgs2_qr_q32.argtypes = lib.dcgs2_qr.argtypes
     lib.cgs2_qr.argtypes = lib.dcgs2_qr.argtypes
+    lib.dcgs2_set_tuning.argtypes = [c_void_p, c_int32, c_int32]
+    lib.dcgs2_get_tuning.argtypes = [c_void_p, c_int32, POINTER(c_int32)]
     lib.dcgs2_arnoldi_q32.argtypes = lib.dcgs2_arnoldi.argtypes
     lib.dcgs2_profile_read.argtypes = [c_void_p, POINTER(KernelStat), c_int32, c_int32]
     lib.dcgs2_status_str.argtypes = [c_int]
@@ -92,7 +96,8 @@ def load(path: str = LIB_PATH):
     for name in ("dcgs2_create", "dcgs2_destroy", "dcgs2_set_tolerances", "dcgs2_qr",
                  "dcgs2_arnoldi", "gmres_solve", "krylov_schur_eigs", "dcgs2_apply",
                  "dcgs2_profile_enable", "dcgs2_profile_read", "dcgs2_set_qr_schedule",
-           "dcgs2_qr_q32", "dcgs2_arnoldi_q32", "dcgs2_set_basis_precision", "cgs2_qr"):
+                 "dcgs2_qr_q32", "dcgs2_arnoldi_q32", "dcgs2_set_basis_precision", "cgs2_qr",
+                 "dcgs2_set_tuning", "dcgs2_get_tuning"):
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -315,6 +320,18 @@ class Context:
         out = {k: getattr(info, k) for k, _ in KsInfo._fields_ if k != "st"}
         out["stats"] = info.st.as_dict()
         return re + 1j * im, rc, out
+
+    def set_tuning(self, key: int, value: int):
+        rc = self._lib.dcgs2_set_tuning(self._h, int(key), int(value))
+        if rc != OK:
+            raise DCGS2Error(rc, "dcgs2_set_tuning")
+
+    def get_tuning(self, key: int) -> int:
+        v = c_int32()
+        rc = self._lib.dcgs2_get_tuning(self._h, int(key), ctypes.byref(v))
+        if rc != OK:
+            raise DCGS2Error(rc, "dcgs2_get_tuning")
+        return v.value
 
     def set_basis_precision(self, bits: int):
         """Storage precision (32 or 64) of the internal bases of gmres / krylov_schur."""

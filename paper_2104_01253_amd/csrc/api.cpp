@@ -39,6 +39,8 @@ struct dcgs2_ctx_s {
   bool ready = false;
   double tau = 1e-8, eta = 1e-12;
   bool qr_one_pass = true;
+  int tune_fused_waves = 16;     // DCGS2_TUNE_FUSED_WAVES
+  int tune_reduce_gmax = 0;      // DCGS2_TUNE_REDUCE_GRID (0: automatic)
   int64_t cap_m = 0;
   int64_t cap_qa = 0, cap_qb = 0;
   double *w = nullptr, *v = nullptr, *r = nullptr;
@@ -314,7 +316,7 @@ struct Expansion {
   }
   GridRed fused_grid(int J, int last) const {
     GridRed g = gr;
-    g.G = fused_qr_grid(m, J, last);
+    g.G = fused_qr_grid(m, J, last, c->tune_fused_waves, c->tune_reduce_gmax);
     g.GS = g.G < REDUCE_GSMAX ? g.G : REDUCE_GSMAX;
     g.NG = (g.G + g.GS - 1) / g.GS;
     return g;
@@ -343,7 +345,7 @@ struct Expansion {
       // bytes: Q_{0..J-1}, w, a_j, a_{j+1} read; q, w written
       KL(K_FUSED, qb * (J + 1) + vm * (last ? 3 : 4),
          launch_fused_qr(Q, q32, ldq, J, c->w, ycol(j), last ? nullptr : ycol(j + 1), m,
-                         c->coef, LDC, last ? 1 : 0, g, f, s));
+                         c->coef, LDC, last ? 1 : 0, c->tune_fused_waves, g, f, s));
     }
     if (J_last >= 0) {
       KL(K_PROJNORM, qb * J_last + 2 * vm,
@@ -386,7 +388,7 @@ struct Expansion {
 
 int setup_expansion(dcgs2_ctx c, Expansion& e, double thresh) {
   e.c = c;
-  reduce_grid(e.m, &e.gr.G, &e.gr.GS, &e.gr.NG);
+  reduce_grid(e.m, c->tune_reduce_gmax, &e.gr.G, &e.gr.GS, &e.gr.NG);
   e.gr.P1 = c->P1;
   e.gr.P2 = c->P2;
   e.gr.cnt = c->cnt;
@@ -469,6 +471,31 @@ int dcgs2_set_tolerances(dcgs2_ctx c, double tau, double eta) {
   c->tau = tau;
   c->eta = eta;
   return DCGS2_OK;
+}
+
+int dcgs2_set_tuning(dcgs2_ctx c, int32_t key, int32_t value) {
+  if (!c) return DCGS2_EINVAL;
+  switch (key) {
+    case DCGS2_TUNE_FUSED_WAVES:
+      if (value != 8 && value != 16) return DCGS2_EINVAL;
+      c->tune_fused_waves = value;
+      return DCGS2_OK;
+    case DCGS2_TUNE_REDUCE_GRID:
+      if (value != 0 && (value < 1 || value > REDUCE_GMAX)) return DCGS2_EINVAL;
+      c->tune_reduce_gmax = value;
+      return DCGS2_OK;
+    default:
+      return DCGS2_EINVAL;
+  }
+}
+
+int dcgs2_get_tuning(dcgs2_ctx c, int32_t key, int32_t* value) {
+  if (!c || !value) return DCGS2_EINVAL;
+  switch (key) {
+    case DCGS2_TUNE_FUSED_WAVES: *value = c->tune_fused_waves; return DCGS2_OK;
+    case DCGS2_TUNE_REDUCE_GRID: *value = c->tune_reduce_gmax; return DCGS2_OK;
+    default: return DCGS2_EINVAL;
+  }
 }
 
 int dcgs2_set_qr_schedule(dcgs2_ctx c, int one_pass) {

@@ -113,9 +113,10 @@ hipError_t launch_update(void* Q, int q32, int64_t ldq, int J, double* x, const 
 // [Q_{0..J}, w_j]^T w_j (a_next unused).  gr.G must equal fused_qr_grid(m, J, last).
 hipError_t launch_fused_qr(void* Q, int q32, int64_t ldq, int J, double* w, const double* a_cur,
                            const double* a_next, int64_t m, const double* coef, int ldc, int last,
-                           const GridRed& gr, const FinArgs& fin, hipStream_t s);
-int fused_qr_grid(int64_t m, int J, int last);
-constexpr int FUSED_QR_MAX_J = 500;       // columns owned one per thread (512 per workgroup)
+                           int fw, const GridRed& gr, const FinArgs& fin, hipStream_t s);
+// fw: wavefronts per workgroup (8 or 16); gmax > 0 caps the number of workgroups.
+int fused_qr_grid(int64_t m, int J, int last, int fw, int gmax);
+constexpr int FUSED_QR_MAX_J = 125;       // J + 3 basis and vector columns <= 128
 // Q[:, J] = ubuf / alpha (coef[2 ldc]) when ctrl->state == RUNNING.
 hipError_t launch_scale_col(void* Q, int q32, int64_t ldq, int J, const double* ubuf, int64_t m,
                             const double* coef, int ldc, const Ctrl* ctrl, hipStream_t s);
@@ -128,7 +129,7 @@ hipError_t launch_convert(void* dst, int d32, const void* src, int s32, int64_t 
                           hipStream_t s);
 
 // Grid sizing for the reductions (number of workgroups for m rows).
-void reduce_grid(int64_t m, int* G, int* GS, int* NG);
+void reduce_grid(int64_t m, int gmax, int* G, int* GS, int* NG);
 constexpr int REDUCE_GMAX = 1024;
 constexpr int REDUCE_GSMAX = 32;
 

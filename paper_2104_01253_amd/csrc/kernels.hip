@@ -28,7 +28,7 @@ namespace {
 
 constexpr int BS = 256;          // threads per workgroup (4 wavefronts of 64)
 constexpr int NW = BS / 64;
-constexpr int NT = 8;            // basis columns per reduction tile
+constexpr int NT = 16;           // basis columns per reduction tile
 
 // ---------------------------------------------------------------------------------
 // Row vectors: a "unit" is VW consecutive rows; VW = 2 uses 16-byte loads and
@@ -86,6 +86,73 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
+}
+
+// Transposed butterfly: reduce NV (a power of two <= 32) per-lane values over the
+// 64 lanes of a wavefront with NV + log2(64/NV) - 1 exchanges instead of
+// 6 NV.  At each of the first log2(NV) steps a lane keeps half of its values
+// (the half selected by its lane bit), swaps the other half with the partner lane
+// and adds; the remaining steps are plain butterflies.  Afterwards v[0] of lane l
+// holds the wavefront total of value index transpose_index<NV>(l).  The order of
+// additions is fixed, so the result is deterministic.
+template <int CNT, int OFF>
+struct TransposeStep {
+  template <int NV>
+  __device__ static void run(double (&v)[NV], int lane) {
+    if constexpr (OFF >= 1) {
+      if constexpr (CNT > 1) {
+        constexpr int H = CNT / 2;
+        const bool up = (lane & OFF) != 0;
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+          const double keep = up ? v[H + i] : v[i];
+          const double give = up ? v[i] : v[H + i];
+          v[i] = keep + __shfl_xor(give, OFF, 64);
+        }
+        TransposeStep<H, OFF / 2>::run(v, lane);
+      } else {
+        v[0] += __shfl_xor(v[0], OFF, 64);
+        TransposeStep<1, OFF / 2>::run(v, lane);
+      }
+    }
+  }
+};
+
+template <int NV>
+__device__ __forceinline__ int transpose_index(int lane) {
+  int idx = 0, cnt = NV;
+#pragma unroll
+  for (int off = 32; off >= 1 && cnt > 1; off >>= 1) {
+    cnt >>= 1;
+    if (lane & off) idx += cnt;
+  }
+  return idx;
+}
+
+template <int NV>
+__device__ __forceinline__ void wave_transpose_sum(double (&v)[NV], int lane) {
+  TransposeStep<NV, 32>::run(v, lane);
+}
+
+// Deterministic workgroup sum of NV (power of two <= 32) per-thread values by the
+// transposed butterfly; value c lands in out_lo[c] for c < NLO, else out_hi[c - NLO],
+// for c < nvalid_lo / nvalid_hi.  sh: NW*NV doubles of LDS.
+template <int NV, int NLO>
+__device__ void block_sum_t(double (&acc)[NV], double* sh, double* out_lo, int nvalid_lo,
+                            double* out_hi, int nvalid_hi) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  wave_transpose_sum(acc, lane);
+  sh[wid * NV + transpose_index<NV>(lane)] = acc[0];   // lanes sharing an index agree
+  __syncthreads();
+  const int c = threadIdx.x;
+  if (c < NV) {
+    double s = sh[c];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) s += sh[w * NV + c];
+    if (c < NLO) { if (c < nvalid_lo) out_lo[c] = s; }
+    else if (c - NLO < nvalid_hi) out_hi[c - NLO] = s;
+  }
+  __syncthreads();
 }
 
 // Deterministic workgroup sum of NV per-thread values; results land in out[0..NV)
@@ -454,21 +521,17 @@ __global__ __launch_bounds__(BS) void reduce_kernel(const TQ* __restrict__ Q, in
     double acc[2 * NT];
 #pragma unroll
     for (int c = 0; c < 2 * NT; ++c) acc[c] = 0.0;
-    const TQ* colq[NT];        // basis columns (k < J)
-    const double* colv[NT];    // the vectors x, y appended as columns J, J+1
-#pragma unroll
-    for (int c = 0; c < NT; ++c) {
-      const int k = k0 + c;
-      colq[c] = Q + (int64_t)(k < J ? k : 0) * ldq;
-      colv[c] = (k == J) ? x : y;
-    }
+    // column k0 + c is basis column k (k < J), x (k == J) or y (k == J + 1)
+    const TQ* qbase = Q + (int64_t)k0 * ldq;
+#pragma unroll 2
     for (int64_t u = u0 + threadIdx.x; u < u1; u += BS) {
       const RV xv = RV::load(x, u);
       const RV yv = HASY ? RV::load(y, u) : RV::zero();
 #pragma unroll
       for (int c = 0; c < NT; ++c) {
         if (k0 + c < Jt) {
-          const RV q = (k0 + c < J) ? RV::load(colq[c], u) : RV::load(colv[c], u);
+          const RV q = (k0 + c < J) ? RV::load(qbase + (int64_t)c * ldq, u)
+                                    : (k0 + c == J ? xv : yv);
           acc[c] += q.dot(xv);
           if (HASY) acc[NT + c] += q.dot(yv);
         }
@@ -480,7 +543,8 @@ __global__ __launch_bounds__(BS) void reduce_kernel(const TQ* __restrict__ Q, in
 #pragma unroll
       for (int c = 0; c < NT; ++c) {
         if (k0 + c < Jt) {
-          const double q = (k0 + c < J) ? (double)colq[c][r] : colv[c][r];
+          const double q = (k0 + c < J) ? (double)qbase[(int64_t)c * ldq + r]
+                                        : (k0 + c == J ? xr : yr);
           acc[c] += q * xr;
           if (HASY) acc[NT + c] += q * yr;
         }
@@ -489,16 +553,12 @@ __global__ __launch_bounds__(BS) void reduce_kernel(const TQ* __restrict__ Q, in
     const int nvalid = min(NT, Jt - k0);
     if (HASY) {
       // partial layout: [0,Jt) = [Q,x,y]^T x ; [Jt, 2Jt) = [Q,x,y]^T y
-      double ax[NT], ay[NT];
-#pragma unroll
-      for (int c = 0; c < NT; ++c) { ax[c] = acc[c]; ay[c] = acc[NT + c]; }
-      block_sum<NT>(ax, shb, P + k0, nvalid);
-      block_sum<NT>(ay, shb, P + Jt + k0, nvalid);
+      block_sum_t<2 * NT, NT>(acc, shb, P + k0, nvalid, P + Jt + k0, nvalid);
     } else {
       double ax[NT];
 #pragma unroll
       for (int c = 0; c < NT; ++c) ax[c] = acc[c];
-      block_sum<NT>(ax, shb, P + k0, nvalid);
+      block_sum_t<NT, NT>(ax, shb, P + k0, nvalid, nullptr, 0);
     }
   }
   if (grid_reduce(gr, V, red)) finalize(fin, red, T, scratch);
@@ -608,117 +668,116 @@ __global__ __launch_bounds__(BS) void update_kernel(TQ* __restrict__ Q, int64_t 
 }
 
 // One-pass QR step (Alg. qr): the update of step j and the reduction of step j+1
-// share a single read of Q.  The next column a_{j+1} is known in advance, so
-// the rows of q_{j-1} and w_j produced by the update can be dotted immediately:
+// share a single read of Q.  The next column a_{j+1} is known in advance, so the
+// rows of q_{j-1} and w_j produced by the update can be dotted at once:
 //   q = (w - Q C)/alpha,  w' = a_j - Q T_{1:J} - q T_J          (update, step j)
 //   [Q_{0..J-1}, q, w', a_{j+1}]^T [w', a_{j+1}]                 (reduction, step j+1)
-// Rows are processed in tiles of FT rows.  Phase A: the FW wavefronts split the
-// basis columns (lane = row, 512-byte loads per column), keep the tile in LDS
-// and form partial Q C and Q T; wavefront 0 combines them in a fixed order and
-// writes q and w'.  Phase B: thread t owns column t of [Q, q, w', a_{j+1}] and
-// accumulates its two dot products over the tile from LDS, so the per-workgroup
-// partials need no cross-lane reduction.  last != 0: a_{j+1} does not exist
-// (the CGS2 finish of the last column), only [Q, q, w']^T w' is reduced.
-constexpr int FT = 64;           // rows per tile
-constexpr int FW = 8;            // wavefronts per workgroup
-constexpr int FBS = FW * 64;
+// A workgroup of FW wavefronts walks tiles of 64 rows (lane = row).  Basis column
+// k belongs to wavefront k mod FW, slot k / FW, and stays in that wavefront's
+// registers for the whole tile: the wavefronts form partial Q C and Q T, one
+// combines them in a fixed order and publishes q, w', a_{j+1} for the tile through
+// LDS, and every wavefront then multiplies its columns by w' and a_{j+1} and
+// reduces the 2*FS products over the 64 rows with one transposed butterfly.  Each
+// lane thus owns one (column, right-hand side) total, accumulated over the tiles in
+// a register -- no LDS staging of the tile and no per-column reductions.
+// LAST: a_{j+1} does not exist (the CGS2 finish of the last column); only
+// [Q_{0..J-1}, q, w']^T w' is reduced.
+constexpr int FMAXCOL = 128;             // J + 3 <= FMAXCOL basis + vector columns
 
-template <typename TQ>
-__global__ __launch_bounds__(FBS) void fused_qr_kernel(TQ* __restrict__ Q, int64_t ldq,
-                                                       int J, double* __restrict__ w,
-                                                       const double* __restrict__ a_cur,
-                                                       const double* __restrict__ a_next,
-                                                       int64_t m, const double* __restrict__ coef,
-                                                       int ldc, int last, GridRed gr,
-                                                       FinArgs fin) {
+template <typename TQ, bool LAST, int FW>
+__global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, int64_t ldq,
+                                                           int J, double* __restrict__ w,
+                                                           const double* __restrict__ a_cur,
+                                                           const double* __restrict__ a_next,
+                                                           int64_t m,
+                                                           const double* __restrict__ coef,
+                                                           int ldc, GridRed gr, FinArgs fin) {
+  constexpr int FS = FMAXCOL / FW;        // column slots per wavefront
+  constexpr int NV = LAST ? FS : 2 * FS;  // products reduced per tile per wavefront
   extern __shared__ double smem[];
   if (fin.ctrl->state != ST_RUNNING) return;
-  const int Jt = J + (last ? 2 : 3);       // columns of [Q, q, w', (a_{j+1})]
-  const int V = last ? Jt : 2 * Jt;
-  constexpr int LDT = FT + 1;               // padded tile column stride
-  double* tile = smem;                      // Jt * LDT
-  double* part = tile + (size_t)Jt * LDT;   // FW * FT * 2
+  const int Jt = J + (LAST ? 2 : 3);
+  const int V = LAST ? Jt : 2 * Jt;
+  double* part = smem;                    // FW * 64 * 2 partial (Q C, Q T)
+  double* vq = part + FW * 128;           // q, w', a_{j+1} of the tile rows
+  double* vw = vq + 64;
+  double* va = vw + 64;
   const double* __restrict__ C = coef;
   const double* __restrict__ T = coef + ldc;
   const double alpha = coef[2 * ldc];
   const double tJ = T[J];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t ntiles = (m + FT - 1) / FT;
-  double accx = 0.0, accy = 0.0;
-  double* colq = tile + (size_t)J * LDT;
-  double* colw = colq + LDT;
-  double* cola = colw + LDT;
+  const int64_t ntiles = (m + 63) / 64;
+  double acc = 0.0;
   for (int64_t tix = blockIdx.x; tix < ntiles; tix += gr.G) {
-    const int64_t r0 = tix * FT;
-    const int rows = (int)min((int64_t)FT, m - r0);
-    // phase A: partial Q C and Q T over this wavefront's columns, tile into LDS
+    const int64_t i = tix * 64 + lane;
+    const bool live = i < m;
+    double qv[FS];
+#pragma unroll
+    for (int sl = 0; sl < FS; ++sl) {
+      const int k = wv + FW * sl;
+      qv[sl] = (k < J && live) ? (double)Q[(int64_t)k * ldq + i] : 0.0;
+    }
+    double wi = 0.0, ai = 0.0, an = 0.0;
+    if (wv == 0 && live) {
+      wi = w[i];
+      ai = a_cur[i];
+      if (!LAST) an = a_next[i];
+    }
     double sc = 0.0, st = 0.0;
-    if (lane < rows) {
-      const TQ* qrow = Q + r0 + lane;
-      int k = wv;
-      for (; k + 3 * FW < J; k += 4 * FW) {
-        const double q0 = (double)qrow[(int64_t)k * ldq];
-        const double q1 = (double)qrow[(int64_t)(k + FW) * ldq];
-        const double q2 = (double)qrow[(int64_t)(k + 2 * FW) * ldq];
-        const double q3 = (double)qrow[(int64_t)(k + 3 * FW) * ldq];
-        tile[(size_t)k * LDT + lane] = q0;
-        tile[(size_t)(k + FW) * LDT + lane] = q1;
-        tile[(size_t)(k + 2 * FW) * LDT + lane] = q2;
-        tile[(size_t)(k + 3 * FW) * LDT + lane] = q3;
-        sc = fma(q0, C[k], sc); st = fma(q0, T[k], st);
-        sc = fma(q1, C[k + FW], sc); st = fma(q1, T[k + FW], st);
-        sc = fma(q2, C[k + 2 * FW], sc); st = fma(q2, T[k + 2 * FW], st);
-        sc = fma(q3, C[k + 3 * FW], sc); st = fma(q3, T[k + 3 * FW], st);
-      }
-      for (; k < J; k += FW) {
-        const double q0 = (double)qrow[(int64_t)k * ldq];
-        tile[(size_t)k * LDT + lane] = q0;
-        sc = fma(q0, C[k], sc);
-        st = fma(q0, T[k], st);
+#pragma unroll
+    for (int sl = 0; sl < FS; ++sl) {
+      const int k = wv + FW * sl;
+      if (k < J) {
+        sc = fma(qv[sl], C[k], sc);
+        st = fma(qv[sl], T[k], st);
       }
     }
-    part[(wv * FT + lane) * 2] = sc;
-    part[(wv * FT + lane) * 2 + 1] = st;
+    part[(wv * 64 + lane) * 2] = sc;
+    part[(wv * 64 + lane) * 2 + 1] = st;
     __syncthreads();
-    // combine (fixed order) and form q_{j-1}, w_j for the tile rows
-    if (wv == 0 && lane < rows) {
+    if (wv == 0) {
       double SC = part[lane * 2], ST = part[lane * 2 + 1];
 #pragma unroll
       for (int u = 1; u < FW; ++u) {
-        SC += part[(u * FT + lane) * 2];
-        ST += part[(u * FT + lane) * 2 + 1];
+        SC += part[(u * 64 + lane) * 2];
+        ST += part[(u * 64 + lane) * 2 + 1];
       }
-      const int64_t i = r0 + lane;
-      const double q = stored<TQ>((w[i] - SC) / alpha);
-      const double wn = a_cur[i] - fma(q, tJ, ST);
-      Q[(int64_t)J * ldq + i] = (TQ)q;
-      w[i] = wn;
-      colq[lane] = q;
-      colw[lane] = wn;
-      if (!last) cola[lane] = a_next[i];
+      double q = 0.0, wn = 0.0;
+      if (live) {
+        q = stored<TQ>((wi - SC) / alpha);
+        wn = ai - fma(q, tJ, ST);
+        Q[(int64_t)J * ldq + i] = (TQ)q;
+        w[i] = wn;
+      }
+      vq[lane] = q;
+      vw[lane] = wn;
+      va[lane] = an;
     }
     __syncthreads();
-    // phase B: thread t owns column t of [Q, q, w', a_{j+1}]
-    if ((int)threadIdx.x < Jt) {
-      const double* col = tile + (size_t)threadIdx.x * LDT;
-      if (last) {
-        for (int r = 0; r < rows; ++r) accx = fma(col[r], colw[r], accx);
-      } else {
-        for (int r = 0; r < rows; ++r) {
-          const double qv = col[r];
-          accx = fma(qv, colw[r], accx);
-          accy = fma(qv, cola[r], accy);
-        }
-      }
+    const double qq = vq[lane], ww = vw[lane], aa = va[lane];
+    double pv[NV];
+#pragma unroll
+    for (int sl = 0; sl < FS; ++sl) {
+      const int k = wv + FW * sl;
+      const double val = (k < J) ? qv[sl]
+                         : (k == J) ? qq
+                         : (k == J + 1) ? ww
+                         : (!LAST && k == J + 2) ? aa : 0.0;
+      pv[sl] = val * ww;
+      if constexpr (!LAST) pv[FS + sl] = val * aa;
     }
-    __syncthreads();
+    wave_transpose_sum(pv, lane);
+    acc += pv[0];
   }
-  double* P = gr.P1 + (int64_t)blockIdx.x * gr.ldp;
-  if ((int)threadIdx.x < Jt) {
-    P[threadIdx.x] = accx;
-    if (!last) P[Jt + threadIdx.x] = accy;
+  {
+    const int idx = transpose_index<NV>(lane);
+    const int k = wv + FW * (idx % FS);
+    const int rhs = idx / FS;
+    if (k < Jt) gr.P1[(int64_t)blockIdx.x * gr.ldp + rhs * Jt + k] = acc;
   }
-  double* red = smem;                       // the tile is dead after the last tile's barrier
+  __syncthreads();                        // LDS is reused by the finaliser below
+  double* red = smem;
   double* Tf = red + V;
   double* scratch = Tf + (J + 3);
   if (grid_reduce(gr, V, red)) finalize(fin, red, Tf, scratch);
@@ -862,11 +921,12 @@ size_t reduce_smem(int J, bool hasy) {
 }  // namespace
 
 // ---------------------------------------------------------------------------------
-void reduce_grid(int64_t m, int* G, int* GS, int* NG) {
+void reduce_grid(int64_t m, int gmax, int* G, int* GS, int* NG) {
   const int64_t units = (m + 1) / 2;
   int64_t g = (units + (int64_t)BS * 4 - 1) / ((int64_t)BS * 4);
   if (g < 1) g = 1;
   if (g > REDUCE_GMAX) g = REDUCE_GMAX;
+  if (gmax > 0 && g > gmax) g = gmax;
   *G = (int)g;
   *GS = (int)(g < REDUCE_GSMAX ? g : REDUCE_GSMAX);
   *NG = (int)((g + *GS - 1) / *GS);
@@ -971,19 +1031,18 @@ hipError_t launch_update(void* Q, int q32, int64_t ldq, int J, double* x, const 
   return hipGetLastError();
 }
 
-size_t fused_qr_smem(int J, int last) {
+size_t fused_qr_smem(int J, int last, int fw) {
+  const size_t work = (size_t)fw * 128 + 3 * 64;
   const int Jt = J + (last ? 2 : 3);
-  const size_t tile = (size_t)Jt * (FT + 1) + (size_t)FW * FT * 2;
   const size_t fin = (size_t)2 * Jt + (J + 3) + 3 * (J + 3) + 64;
-  return sizeof(double) * (tile > fin ? tile : fin) + sizeof(double) * 8;
+  return sizeof(double) * (work > fin ? work : fin) + sizeof(double) * 8;
 }
 
-int fused_qr_grid(int64_t m, int J, int last) {
-  const int64_t ntiles = (m + FT - 1) / FT;
-  const size_t lds = fused_qr_smem(J, last);
-  int per_cu = (int)((150u * 1024u) / lds);
-  per_cu = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
-  int64_t g = (int64_t)per_cu * 256;
+int fused_qr_grid(int64_t m, int J, int last, int fw, int gmax) {
+  (void)J; (void)last;
+  const int64_t ntiles = (m + 63) / 64;
+  int64_t g = (fw == 8 ? 3 : 2) * 256;    // workgroups resident per CU at ~100 VGPRs
+  if (gmax > 0 && g > gmax) g = gmax;
   if (g > REDUCE_GMAX) g = REDUCE_GMAX;
   if (g > ntiles) g = ntiles;
   return (int)(g < 1 ? 1 : g);
@@ -991,14 +1050,18 @@ int fused_qr_grid(int64_t m, int J, int last) {
 
 hipError_t launch_fused_qr(void* Q, int q32, int64_t ldq, int J, double* w, const double* a_cur,
                            const double* a_next, int64_t m, const double* coef, int ldc, int last,
-                           const GridRed& gr, const FinArgs& fin, hipStream_t s) {
-  const size_t sm = fused_qr_smem(J, last);
-  if (q32)
-    fused_qr_kernel<float><<<gr.G, FBS, sm, s>>>((float*)Q, ldq, J, w, a_cur, a_next, m, coef,
-                                                 ldc, last, gr, fin);
-  else
-    fused_qr_kernel<double><<<gr.G, FBS, sm, s>>>((double*)Q, ldq, J, w, a_cur, a_next, m, coef,
-                                                  ldc, last, gr, fin);
+                           int fw, const GridRed& gr, const FinArgs& fin, hipStream_t s) {
+  const size_t sm = fused_qr_smem(J, last, fw);
+#define DCGS2_FQ(T, L, F) \
+  fused_qr_kernel<T, L, F><<<gr.G, F * 64, sm, s>>>((T*)Q, ldq, J, w, a_cur, a_next, m, coef, ldc, gr, fin)
+#define DCGS2_FQ_W(F)                                                                    \
+  do {                                                                                   \
+    if (q32) { if (last) DCGS2_FQ(float, true, F); else DCGS2_FQ(float, false, F); }     \
+    else { if (last) DCGS2_FQ(double, true, F); else DCGS2_FQ(double, false, F); }       \
+  } while (0)
+  if (fw == 8) DCGS2_FQ_W(8); else DCGS2_FQ_W(16);
+#undef DCGS2_FQ_W
+#undef DCGS2_FQ
   return hipGetLastError();
 }
 
