@@ -306,8 +306,12 @@ struct Expansion {
     hipStream_t s = c->stream;
     const double vm = 8.0 * (double)m;
     const double qb = q32 ? 4.0 * (double)m : vm;
-    KL(K_REDUCE, qb * J + vm,
-       launch_reduce(Q, q32, ldq, J, c->w, nullptr, m, gr, fin(FIN_LAST1, jvirt, J), s));
+    // with no earlier columns (single-column QR) c is empty: only the norm is reduced,
+    // and the breakdown test alpha <= eta * ||a_1|| = eta * alpha reduces to alpha == 0
+    // (rho_next keeps its initial 0)
+    if (J > 0)
+      KL(K_REDUCE, qb * J + vm,
+         launch_reduce(Q, q32, ldq, J, c->w, nullptr, m, gr, fin(FIN_LAST1, jvirt, J), s));
     KL(K_PROJNORM, qb * J + 2 * vm,
        launch_project_norm(Q, q32, ldq, J, c->w, c->r, m, gr, fin(FIN_LAST2, jvirt, J), s));
     KL(K_SCALE, vm + qb,
