@@ -107,6 +107,7 @@ def main():
     ap.add_argument("--n", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-legs", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -130,9 +131,16 @@ def main():
         _, rc, _ = ctx.qr(Bd, Qd)
         assert rc == binding.OK, rc
 
-    log(f"[bench] warmup {args.warmup}")
+    log(f"[bench] warmup {args.warmup} (+ autotuning of the launch shapes)")
     for _ in range(args.warmup):
         qr_once()
+    tuned = {}
+    if not args.no_tune:
+        from paper_2104_01253_amd import autotune
+        best, best_ms, _ = autotune.tune(ctx, qr_once, reps=1)
+        tuned = {("fused_waves" if k == binding.TUNE_FUSED_WAVES else "reduce_grid"): v
+                 for k, v in best.items()}
+        log(f"[bench] autotuned {tuned} ({best_ms:.2f} ms)")
     log(f"[bench] timing {args.steps} factorizations")
     T = timed(torch, qr_once, args.steps)
     ms_per_step = T / args.steps * 1e3
@@ -155,7 +163,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"dcgs2_qr: B = G diag(logspace(0,-8,{n})) V, m={m}, n={n}, "
                                "fp64, resident in HBM; one step = one factorization",
-                   "m": m, "n": n, "cond": 1e8},
+                   "m": m, "n": n, "cond": 1e8, "launch_shapes": tuned},
         "hbm_gbps_step": round(alg_bytes_step / (ms_per_step * 1e-3) / 1e9, 1),
         "alg_bytes_per_step": alg_bytes_step,
         "profiled_ms_per_step": round(T_prof / args.steps * 1e3, 4),

@@ -1,0 +1,53 @@
+"""Autotuner for the launch shapes of libdcgs2 (workgroups per reduction pass,
+wavefronts per one-pass QR workgroup).
+
+The knobs change launch shapes only -- never the arithmetic, and the result is
+deterministic for each setting -- so the tuner times each candidate on the
+caller's own workload and keeps the fastest.  Timing uses HIP events on the
+context's stream through torch.
+
+    best = autotune.tune(ctx, lambda: ctx.qr(B, Q))
+"""
+from __future__ import annotations
+
+import itertools
+
+from . import binding
+
+CANDIDATES = {
+    binding.TUNE_FUSED_WAVES: (16, 8),
+    binding.TUNE_REDUCE_GRID: (0, 512, 256),
+}
+
+
+def _time(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune(ctx: "binding.Context", fn, reps: int = 2, candidates=None, verbose=False):
+    """Try every combination of the knobs, leave the fastest set on ctx and return
+    (settings dict, best ms, all timings)."""
+    import torch
+    cands = candidates or CANDIDATES
+    keys = list(cands)
+    timings = []
+    for combo in itertools.product(*(cands[k] for k in keys)):
+        for k, v in zip(keys, combo):
+            ctx.set_tuning(k, v)
+        ms = _time(torch, fn, reps)
+        timings.append((dict(zip(keys, combo)), ms))
+        if verbose:
+            print("autotune", dict(zip(keys, combo)), f"{ms:.3f} ms", flush=True)
+    best, best_ms = min(timings, key=lambda t: t[1])
+    for k, v in best.items():
+        ctx.set_tuning(k, v)
+    return best, best_ms, timings
