@@ -26,472 +26,7 @@
 namespace dcgs2 {
 namespace {
 
-constexpr int BS = 256;          // threads per workgroup (4 wavefronts of 64)
-constexpr int NW = BS / 64;
-constexpr int NT = 16;           // basis columns per reduction tile
-
-// ---------------------------------------------------------------------------------
-// Row vectors: a "unit" is VW consecutive rows; VW = 2 uses 16-byte loads and
-// requires every column start to be 16-byte aligned (checked by the host).
-template <int VW>
-struct RowVec {
-  double e[VW];
-  // Loads VW consecutive elements (unit u) of a double or float array, widened
-  // to double; stores round to the array's element type.
-  template <typename T>
-  __device__ static RowVec load(const T* p, int64_t u) {
-    RowVec r;
-    if constexpr (VW == 2 && sizeof(T) == 8) {
-      const double2 t = reinterpret_cast<const double2*>(p)[u];
-      r.e[0] = t.x;
-      r.e[1] = t.y;
-    } else if constexpr (VW == 2) {
-      const float2 t = reinterpret_cast<const float2*>(p)[u];
-      r.e[0] = (double)t.x;
-      r.e[1] = (double)t.y;
-    } else {
-      r.e[0] = (double)p[u];
-    }
-    return r;
-  }
-  template <typename T>
-  __device__ void store(T* p, int64_t u) const {
-    if constexpr (VW == 2 && sizeof(T) == 8) {
-      reinterpret_cast<double2*>(p)[u] = make_double2(e[0], e[1]);
-    } else if constexpr (VW == 2) {
-      reinterpret_cast<float2*>(p)[u] = make_float2((float)e[0], (float)e[1]);
-    } else {
-      p[u] = (T)e[0];
-    }
-  }
-  __device__ static RowVec zero() {
-    RowVec r;
-#pragma unroll
-    for (int i = 0; i < VW; ++i) r.e[i] = 0.0;
-    return r;
-  }
-  __device__ double dot(const RowVec& o) const {
-    double s = e[0] * o.e[0];
-#pragma unroll
-    for (int i = 1; i < VW; ++i) s = fma(e[i], o.e[i], s);
-    return s;
-  }
-};
-
-// Value of x as stored in an array of T (rounded once when T is float).
-template <typename T>
-__device__ __forceinline__ double stored(double x) { return (double)(T)x; }
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// Transposed butterfly: reduce NV (a power of two <= 32) per-lane values over the
-// 64 lanes of a wavefront with NV + log2(64/NV) - 1 exchanges instead of
-// 6 NV.  At each of the first log2(NV) steps a lane keeps half of its values
-// (the half selected by its lane bit), swaps the other half with the partner lane
-// and adds; the remaining steps are plain butterflies.  Afterwards v[0] of lane l
-// holds the wavefront total of value index transpose_index<NV>(l).  The order of
-// additions is fixed, so the result is deterministic.
-template <int CNT, int OFF>
-struct TransposeStep {
-  template <int NV>
-  __device__ static void run(double (&v)[NV], int lane) {
-    if constexpr (OFF >= 1) {
-      if constexpr (CNT > 1) {
-        constexpr int H = CNT / 2;
-        const bool up = (lane & OFF) != 0;
-#pragma unroll
-        for (int i = 0; i < H; ++i) {
-          const double keep = up ? v[H + i] : v[i];
-          const double give = up ? v[i] : v[H + i];
-          v[i] = keep + __shfl_xor(give, OFF, 64);
-        }
-        TransposeStep<H, OFF / 2>::run(v, lane);
-      } else {
-        v[0] += __shfl_xor(v[0], OFF, 64);
-        TransposeStep<1, OFF / 2>::run(v, lane);
-      }
-    }
-  }
-};
-
-template <int NV>
-__device__ __forceinline__ int transpose_index(int lane) {
-  int idx = 0, cnt = NV;
-#pragma unroll
-  for (int off = 32; off >= 1 && cnt > 1; off >>= 1) {
-    cnt >>= 1;
-    if (lane & off) idx += cnt;
-  }
-  return idx;
-}
-
-template <int NV>
-__device__ __forceinline__ void wave_transpose_sum(double (&v)[NV], int lane) {
-  TransposeStep<NV, 32>::run(v, lane);
-}
-
-// Deterministic workgroup sum of NV (power of two <= 32) per-thread values by the
-// transposed butterfly; value c lands in out_lo[c] for c < NLO, else out_hi[c - NLO],
-// for c < nvalid_lo / nvalid_hi.  sh: NW*NV doubles of LDS.
-template <int NV, int NLO>
-__device__ void block_sum_t(double (&acc)[NV], double* sh, double* out_lo, int nvalid_lo,
-                            double* out_hi, int nvalid_hi) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  wave_transpose_sum(acc, lane);
-  sh[wid * NV + transpose_index<NV>(lane)] = acc[0];   // lanes sharing an index agree
-  __syncthreads();
-  const int c = threadIdx.x;
-  if (c < NV) {
-    double s = sh[c];
-#pragma unroll
-    for (int w = 1; w < NW; ++w) s += sh[w * NV + c];
-    if (c < NLO) { if (c < nvalid_lo) out_lo[c] = s; }
-    else if (c - NLO < nvalid_hi) out_hi[c - NLO] = s;
-  }
-  __syncthreads();
-}
-
-// Deterministic workgroup sum of NV per-thread values; results land in out[0..NV)
-// (global or shared), written by threads 0..NV-1.  sh: NW*NV doubles of LDS.
-template <int NV>
-__device__ void block_sum(const double (&acc)[NV], double* sh, double* out, int nvalid) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int c = 0; c < NV; ++c) {
-    const double v = wave_sum(acc[c]);
-    if (lane == 0) sh[wid * NV + c] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < NV && (int)threadIdx.x < nvalid) {
-    double s = sh[threadIdx.x];
-#pragma unroll
-    for (int w = 1; w < NW; ++w) s += sh[w * NV + threadIdx.x];
-    out[threadIdx.x] = s;
-  }
-  __syncthreads();
-}
-
-// Two-level grid reduction of V partial values per workgroup (already stored in
-// gr.P1[blockIdx.x]).  Returns true in exactly one workgroup, the last to arrive,
-// with the V totals in red[] (LDS).  Workgroups are grouped by consecutive index;
-// each group is summed in index order by its last arrival, then the group sums
-// are summed in group order by the last group to finish.
-__device__ bool grid_reduce(const GridRed& gr, int V, double* red) {
-  __shared__ int s_last;
-  __threadfence();               // every thread: release this workgroup's partial stores
-  __syncthreads();
-  const int grp = blockIdx.x / gr.GS;
-  const int g0 = grp * gr.GS;
-  const int gsz = min(gr.GS, gr.G - g0);
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(&gr.cnt[grp], 1u);
-    s_last = (prev == (unsigned)(gsz - 1));
-  }
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-  for (int v = threadIdx.x; v < V; v += (int)blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < gsz; ++b) s += gr.P1[(int64_t)(g0 + b) * gr.ldp + v];
-    if (gr.NG == 1) red[v] = s;
-    else gr.P2[(int64_t)grp * gr.ldp + v] = s;
-  }
-  if (threadIdx.x == 0) gr.cnt[grp] = 0u;
-  if (gr.NG == 1) { __syncthreads(); return true; }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(&gr.cnt[gr.NG], 1u);
-    s_last = (prev == (unsigned)(gr.NG - 1));
-  }
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-  for (int v = threadIdx.x; v < V; v += (int)blockDim.x) {
-    double s = 0.0;
-    for (int g = 0; g < gr.NG; ++g) s += gr.P2[(int64_t)g * gr.ldp + v];
-    red[v] = s;
-  }
-  if (threadIdx.x == 0) gr.cnt[gr.NG] = 0u;
-  __syncthreads();
-  return true;
-}
-
-__device__ __forceinline__ bool finite(double v) { return isfinite(v); }
-
-// Deterministic dot product of two LDS/global vectors of length n by wavefront 0;
-// the result is broadcast through *out (LDS).  Call from all threads.
-__device__ void small_dot(const double* a, const double* b, int n, double* out) {
-  if (threadIdx.x < 64) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += 64) s = fma(a[i], b[i], s);
-    s = wave_sum(s);
-    if (threadIdx.x == 0) *out = s;
-  }
-  __syncthreads();
-}
-
-// Any non-finite value among v[0..n)?  Result broadcast through *flag (LDS).
-__device__ void any_nonfinite(const double* v, int n, int* flag) {
-  if (threadIdx.x == 0) *flag = 0;
-  __syncthreads();
-  int bad = 0;
-  for (int i = threadIdx.x; i < n; i += (int)blockDim.x) bad |= !finite(v[i]);
-  if (bad) atomicOr(flag, 1);
-  __syncthreads();
-}
-
-// GMRES: apply the stored Givens rotations to the just-completed Hessenberg column
-// c (rows 0..c+1), form rotation c, update g and test the least-squares residual
-// |g_{c+1}| against ctrl->gmres_thresh.  Thread 0 runs the recurrence; sh holds
-// at least 3(c+2) doubles of LDS scratch.
-__device__ void gmres_givens(const FinArgs& f, int c, int j, double* sh) {
-  double* h = sh;
-  double* cs = sh + (c + 2);
-  double* sn = cs + (c + 1);
-  for (int i = threadIdx.x; i <= c + 1; i += (int)blockDim.x) h[i] = f.H[(int64_t)c * f.ldh + i];
-  for (int i = threadIdx.x; i < c; i += (int)blockDim.x) { cs[i] = f.cs[i]; sn[i] = f.sn[i]; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < c; ++i) {
-      const double a = h[i], b = h[i + 1];
-      h[i] = cs[i] * a + sn[i] * b;
-      h[i + 1] = -sn[i] * a + cs[i] * b;
-    }
-    const double a = h[c], b = h[c + 1];
-    const double r = hypot(a, b);
-    const double cc = r > 0.0 ? a / r : 1.0;
-    const double ss = r > 0.0 ? b / r : 0.0;
-    f.cs[c] = cc;
-    f.sn[c] = ss;
-    h[c] = r;
-    const double gc = f.g[c];
-    f.g[c] = cc * gc;
-    f.g[c + 1] = -ss * gc;
-    const double est = fabs(ss * gc);
-    f.ctrl->resid_est = est;
-    if (est <= f.ctrl->gmres_thresh && f.ctrl->state == ST_RUNNING) {
-      f.ctrl->state = ST_DONE;
-      f.ctrl->stop_step = j;
-      f.ctrl->k = c + 1;
-    }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i <= c; i += (int)blockDim.x) f.Rg[(int64_t)c * f.ldh + i] = h[i];
-  __syncthreads();
-}
-
-// Complete the Hessenberg column J-1 with the reorthogonalisation coefficients:
-// H_{1:J, J-1} = K_{1:J, J-1} + C,  H_{J+1, J-1} = alpha  (Alg. arnoldi, columns
-// completed one step late).  Then GMRES rotations when enabled.
-__device__ void complete_h_column(const FinArgs& f, const double* C, int J, double alpha,
-                                  double* scratch) {
-  const int col = J - 1;
-  for (int i = threadIdx.x; i < J; i += (int)blockDim.x)
-    f.H[(int64_t)col * f.ldh + i] = f.K[(int64_t)col * f.ldh + i] + C[i];
-  if (threadIdx.x == 0) f.H[(int64_t)col * f.ldh + J] = alpha;
-  __syncthreads();
-  if (threadIdx.x == 0 && f.ctrl->state == ST_RUNNING) f.ctrl->k = J;
-  if (f.gmres) gmres_givens(f, col, f.j, scratch);
-}
-
-// Scalar tail of a DCGS2 step once alpha_{j-1} is known (Alg. arnoldi lines 4-12
-// with lines 10 -> 12 -> 11, or Alg. qr lines 3-8).
-//   C, S : LDS vectors of length J; sigma, gamma, cs = C^T S; rho = breakdown scale.
-__device__ void step_tail(const FinArgs& f, const double* C, const double* S, double sigma,
-                          double gamma, double csum, double alpha, double rho, double* T,
-                          double* scratch) {
-  Ctrl* ctrl = f.ctrl;
-  const int J = f.J, j = f.j;
-  if (!finite(alpha)) {
-    if (threadIdx.x == 0) { ctrl->state = ST_NONFINITE; ctrl->stop_step = j; }
-    return;
-  }
-  if (alpha <= ctrl->eta * rho) {                 // breakdown: close column j-2 and stop
-    if (f.qr) {
-      for (int i = threadIdx.x; i < J; i += (int)blockDim.x) f.R[(int64_t)J * f.ldr + i] = f.Sprev[i] + C[i];
-      if (threadIdx.x == 0) f.R[(int64_t)J * f.ldr + J] = alpha;
-      __syncthreads();
-      if (threadIdx.x == 0) ctrl->k = J;
-    } else if (j >= 3) {
-      complete_h_column(f, C, J, alpha, scratch);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0 && (ctrl->state == ST_RUNNING || ctrl->state == ST_DONE)) {
-      if (ctrl->state == ST_RUNNING) { ctrl->state = ST_BREAKDOWN; ctrl->stop_step = j; }
-    }
-    return;
-  }
-  // T_{1:j-2} = S/alpha, T_{j-1} = (sigma - C^T S)/alpha^2 (Arnoldi);
-  // S_{j-1,j} = (sigma - C^T S)/alpha (QR, Stephen's trick)
-  for (int i = threadIdx.x; i < J; i += (int)blockDim.x) T[i] = f.qr ? S[i] : S[i] / alpha;
-  if (threadIdx.x == 0) T[J] = f.qr ? (sigma - csum) / alpha : (sigma - csum) / (alpha * alpha);
-  __syncthreads();
-  for (int i = threadIdx.x; i < J; i += (int)blockDim.x) f.coef[i] = C[i];
-  for (int i = threadIdx.x; i <= J; i += (int)blockDim.x) f.coef[f.ldc + i] = T[i];
-  if (threadIdx.x == 0) f.coef[2 * f.ldc] = alpha;
-  if (f.qr) {
-    // R_{1:j-2, j-1} = S_{1:j-2, j-1} + C ; R_{j-1,j-1} = alpha ; keep S_{1:j-1, j}
-    for (int i = threadIdx.x; i < J; i += (int)blockDim.x) f.R[(int64_t)J * f.ldr + i] = f.Sprev[i] + C[i];
-    if (threadIdx.x == 0) f.R[(int64_t)J * f.ldr + J] = alpha;
-    __syncthreads();
-    for (int i = threadIdx.x; i <= J; i += (int)blockDim.x) f.Sprev[i] = T[i];
-    if (threadIdx.x == 0) { ctrl->k = J + 1; ctrl->rho_next = sqrt(gamma); }
-  } else {
-    if (f.gmres && j == 2 && threadIdx.x == 0) f.g[0] = alpha;   // beta e_1 of the cycle
-    if (j >= 3) complete_h_column(f, C, J, alpha, scratch);      // lines 10 and 12
-    __syncthreads();
-    // line 11: K_{1:j-1, j-1} = T - (1/alpha) H_{1:j-1, 1:j-2} C   (dense product)
-    for (int i = threadIdx.x; i <= J; i += (int)blockDim.x) {
-      double hc = 0.0;
-      for (int c = 0; c < J; ++c) hc = fma(f.H[(int64_t)c * f.ldh + i], C[c], hc);
-      f.K[(int64_t)J * f.ldh + i] = T[i] - hc / alpha;
-    }
-    if (threadIdx.x == 0) ctrl->rho_next = sqrt(gamma) / alpha;
-  }
-  __syncthreads();
-}
-
-// The finalising workgroup: red[] holds the grid-reduced values of this kernel.
-__device__ void finalize(const FinArgs& f, double* red, double* T, double* scratch) {
-  Ctrl* ctrl = f.ctrl;
-  const int J = f.J, j = f.j;
-  __shared__ double s_dot[2];
-  __shared__ int s_flag;
-  switch (f.kind) {
-    case FIN_NORM:
-      if (threadIdx.x == 0) { ctrl->norm2 = red[0]; ctrl->reductions += 1; }
-      return;
-    case FIN_NONE:
-      return;
-    case FIN_CGS2_S: {                     // S = Q^T a (and a^T a): first CGS2 projection
-      any_nonfinite(red, J + 1, &s_flag);
-      if (threadIdx.x == 0) {
-        ctrl->reductions += 1;
-        if (s_flag) { ctrl->state = ST_NONFINITE; ctrl->stop_step = j; }
-        ctrl->rho_next = sqrt(red[J]);
-      }
-      for (int i = threadIdx.x; i < J; i += (int)blockDim.x) {
-        f.coef[i] = red[i];
-        f.Sprev[i] = red[i];
-      }
-      return;
-    }
-    case FIN_LAST1: {                      // c = Q^T w (and w^T w)
-      any_nonfinite(red, J + 1, &s_flag);
-      if (threadIdx.x == 0) {
-        ctrl->reductions += 1;
-        if (s_flag) { ctrl->state = ST_NONFINITE; ctrl->stop_step = j; }
-        if (J == 0) ctrl->rho_next = sqrt(red[0]);   // single-column QR: rho = ||a_1||
-      }
-      for (int i = threadIdx.x; i < J; i += (int)blockDim.x) f.coef[i] = red[i];
-      return;
-    }
-    case FIN_LAST2: {                      // alpha = ||w - Q c||, close the last column
-      const double alpha = sqrt(red[0]);
-      const double* c = f.coef;
-      if (threadIdx.x == 0) ctrl->reductions += 1;
-      if (!finite(alpha)) {
-        if (threadIdx.x == 0) { ctrl->state = ST_NONFINITE; ctrl->stop_step = j; }
-        return;
-      }
-      for (int i = threadIdx.x; i < J; i += (int)blockDim.x) T[i] = c[i];   // c into LDS
-      __syncthreads();
-      const bool brk = alpha <= ctrl->eta * ctrl->rho_next;
-      if (f.qr) {
-        for (int i = threadIdx.x; i < J; i += (int)blockDim.x) f.R[(int64_t)J * f.ldr + i] = f.Sprev[i] + T[i];
-        if (threadIdx.x == 0) {
-          f.R[(int64_t)J * f.ldr + J] = alpha;
-          ctrl->k = brk ? J : J + 1;
-        }
-      } else {
-        complete_h_column(f, T, J, alpha, scratch);
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        f.coef[2 * f.ldc] = alpha;
-        if (brk && ctrl->state == ST_RUNNING) { ctrl->state = ST_BREAKDOWN; ctrl->stop_step = j; }
-      }
-      return;
-    }
-    case FIN_RESTART: {                    // C = 0, alpha = 1: T = Q_{1:k+1}^T v
-      const int Jt = J + 2;
-      const double* S = red + Jt;
-      any_nonfinite(red, 2 * Jt, &s_flag);
-      if (s_flag) {
-        if (threadIdx.x == 0) { ctrl->state = ST_NONFINITE; ctrl->stop_step = j; ctrl->reductions += 1; }
-        return;
-      }
-      for (int i = threadIdx.x; i < J; i += (int)blockDim.x) { T[i] = S[i]; f.coef[i] = 0.0; }
-      if (threadIdx.x == 0) T[J] = S[J];   // sigma = q_{k+1}^T v
-      __syncthreads();
-      for (int i = threadIdx.x; i <= J; i += (int)blockDim.x) {
-        f.coef[f.ldc + i] = T[i];
-        f.K[(int64_t)J * f.ldh + i] = T[i];
-      }
-      if (threadIdx.x == 0) {
-        f.coef[2 * f.ldc] = 1.0;
-        ctrl->rho_next = sqrt(S[J + 1]);
-        ctrl->reductions += 1;
-      }
-      __syncthreads();
-      return;
-    }
-    case FIN_STEP: {
-      const int Jt = J + 2;
-      const double* C = red;
-      const double beta = red[J];
-      const double* S = red + Jt;
-      const double sigma = red[Jt + J];
-      const double gamma = red[Jt + J + 1];
-      any_nonfinite(red, 2 * Jt, &s_flag);
-      if (s_flag) {
-        if (threadIdx.x == 0) { ctrl->state = ST_NONFINITE; ctrl->stop_step = j; ctrl->reductions += 1; }
-        return;
-      }
-      small_dot(C, C, J, &s_dot[0]);
-      small_dot(C, S, J, &s_dot[1]);
-      const double rho = (j == 2) ? sqrt(beta) : ctrl->rho_next;
-      const double d = beta - s_dot[0];
-      if (threadIdx.x == 0) ctrl->reductions += 1;
-      if (!(finite(d) && d > ctrl->tau * beta)) {
-        // hand the reduced step over to the explicit-norm fallback (run by the host)
-        for (int i = threadIdx.x; i < J; i += (int)blockDim.x) {
-          f.pend[i] = C[i];
-          f.pend[J + i] = S[i];
-          f.coef[i] = C[i];
-        }
-        if (threadIdx.x == 0) {
-          f.pend[2 * J] = sigma;
-          f.pend[2 * J + 1] = gamma;
-          f.pend[2 * J + 2] = beta;
-          ctrl->state = ST_FALLBACK;
-          ctrl->stop_step = j;
-        }
-        return;
-      }
-      step_tail(f, C, S, sigma, gamma, s_dot[1], sqrt(d), rho, T, scratch);
-      return;
-    }
-    case FIN_FALLBACK: {
-      const double alpha = sqrt(red[0]);
-      double* C = scratch;                 // pend -> LDS
-      double* S = scratch + J;
-      for (int i = threadIdx.x; i < J; i += (int)blockDim.x) { C[i] = f.pend[i]; S[i] = f.pend[J + i]; }
-      __syncthreads();
-      const double sigma = f.pend[2 * J], gamma = f.pend[2 * J + 1], beta = f.pend[2 * J + 2];
-      small_dot(C, S, J, &s_dot[1]);
-      const double rho = (j == 2) ? sqrt(beta) : ctrl->rho_next;
-      if (threadIdx.x == 0) { ctrl->reductions += 1; ctrl->fallbacks += 1; }
-      step_tail(f, C, S, sigma, gamma, s_dot[1], alpha, rho, T, scratch + 2 * J);
-      return;
-    }
-  }
-}
+#include "device_common.h"
 
 // ---------------------------------------------------------------------------------
 // Reduction pass: per-workgroup partial dot products of [Q_{0..J-1}, x, (y)] with
