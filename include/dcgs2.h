@@ -233,6 +233,31 @@ typedef struct {
 int dcgs2_profile_enable(dcgs2_ctx ctx, int enable);
 int dcgs2_profile_read(dcgs2_ctx ctx, dcgs2_kernel_stat* out, int32_t max_entries, int32_t reset);
 
+/* Batched Krylov-Schur over `count` independent 2-D convection-diffusion operators
+ * (5-point stencils with constant coefficients, grids of different sizes).  Every
+ * DCGS2 expansion step is ONE launch of each step kernel covering all instances
+ * (workgroups mapped to instances by prefix sums; a per-instance grid reduction
+ * and finaliser); converged instances drop out.  A restart cycle's launches are
+ * captured into a HIP graph (use_graph != 0) and replayed.  The per-instance
+ * Schur work runs on host threads between cycles.  Algorithm and readings as
+ * krylov_schur_eigs, with shared nev, ncv, keep, tol, max_restarts.
+ *  ops         : host, count descriptors (m_b = nx*ny > ncv).
+ *  v0          : device, the count start vectors concatenated in instance order.
+ *  eig_re_host, eig_im_host : host, count x nev (instance-major).
+ *  info_host   : host, count records (status per instance).
+ * An instance whose Pythagorean guard fails stops with DCGS2_NOT_CONVERGED and
+ * st.pyth_fallbacks = 1 (krylov_schur_eigs runs the fallback).  Returns DCGS2_OK
+ * when every instance converged, DCGS2_NOT_CONVERGED otherwise, or an error. */
+typedef struct {
+  int32_t nx, ny;
+  double c0, cxm, cxp, cym, cyp;
+} dcgs2_stencil2d;
+
+int krylov_schur_batched(dcgs2_ctx ctx, int32_t count, const dcgs2_stencil2d* ops,
+                         int32_t nev, int32_t ncv, int32_t keep, double tol,
+                         int32_t max_restarts, const double* v0, double* eig_re_host,
+                         double* eig_im_host, dcgs2_ks_info* info_host, int32_t use_graph);
+
 /* y = A x (device vectors of length A->m).  The matvec of step a1; exported so
  * the operator can be checked on its own. */
 int dcgs2_apply(dcgs2_ctx ctx, const dcgs2_op* A, const double* x, double* y);

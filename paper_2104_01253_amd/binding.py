@@ -25,7 +25,7 @@ EXPORTS = ("dcgs2_create", "dcgs2_destroy", "dcgs2_set_tolerances", "dcgs2_qr", 
            "gmres_solve", "krylov_schur_eigs", "dcgs2_apply", "dcgs2_status_str",
            "dcgs2_profile_enable", "dcgs2_profile_read", "dcgs2_set_qr_schedule",
            "dcgs2_qr_q32", "dcgs2_arnoldi_q32", "dcgs2_set_basis_precision", "cgs2_qr",
-           "dcgs2_set_tuning", "dcgs2_get_tuning")
+           "dcgs2_set_tuning", "dcgs2_get_tuning", "krylov_schur_batched")
 TUNE_FUSED_WAVES, TUNE_REDUCE_GRID = 0, 1
 
 
@@ -59,6 +59,11 @@ class KsInfo(ctypes.Structure):
                 ("status", c_int32), ("resid", c_double), ("st", Stats)]
 
 
+class Stencil2d(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("c0", c_double), ("cxm", c_double),
+                ("cxp", c_double), ("cym", c_double), ("cyp", c_double)]
+
+
 _lib = None
 
 
@@ -81,6 +86,9 @@ def load(path: str = LIB_PATH):
                                 c_int32, POINTER(GmresInfo)]
     lib.krylov_schur_eigs.argtypes = [c_void_p, POINTER(Op), c_int32, c_int32, c_int32, c_double,
                                       c_int32, c_void_p, c_void_p, c_void_p, POINTER(KsInfo)]
+    lib.krylov_schur_batched.argtypes = [c_void_p, c_int32, POINTER(Stencil2d), c_int32, c_int32,
+                                         c_int32, c_double, c_int32, c_void_p, c_void_p,
+                                         c_void_p, POINTER(KsInfo), c_int32]
     lib.dcgs2_apply.argtypes = [c_void_p, POINTER(Op), c_void_p, c_void_p]
     lib.dcgs2_profile_enable.argtypes = [c_void_p, c_int]
     lib.dcgs2_set_qr_schedule.argtypes = [c_void_p, c_int]
@@ -97,7 +105,7 @@ def load(path: str = LIB_PATH):
                  "dcgs2_arnoldi", "gmres_solve", "krylov_schur_eigs", "dcgs2_apply",
                  "dcgs2_profile_enable", "dcgs2_profile_read", "dcgs2_set_qr_schedule",
                  "dcgs2_qr_q32", "dcgs2_arnoldi_q32", "dcgs2_set_basis_precision", "cgs2_qr",
-                 "dcgs2_set_tuning", "dcgs2_get_tuning"):
+                 "dcgs2_set_tuning", "dcgs2_get_tuning", "krylov_schur_batched"):
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -191,6 +199,16 @@ def stencil_op(grid, D=1.0, vel=None, h=None) -> Op:
     op.c0 = c0
     op.cxm, op.cxp, op.cym, op.cyp, op.czm, op.czp = lo[0], hi[0], lo[1], hi[1], lo[2], hi[2]
     return op
+
+
+def stencil2d(grid, D=1.0, vel=None, h=None) -> Stencil2d:
+    """Batched-solver descriptor of a 2-D convection-diffusion stencil."""
+    nx, ny = (int(g) for g in grid)
+    c0, lo, hi = stencil_coefficients((nx, ny), D, vel, h)
+    d = Stencil2d()
+    d.nx, d.ny, d.c0 = nx, ny, c0
+    d.cxm, d.cxp, d.cym, d.cyp = lo[0], hi[0], lo[1], hi[1]
+    return d
 
 
 def csr_op(rowptr, colind, val) -> Op:
@@ -319,6 +337,31 @@ class Context:
             raise DCGS2Error(rc, "krylov_schur_eigs")
         out = {k: getattr(info, k) for k, _ in KsInfo._fields_ if k != "st"}
         out["stats"] = info.st.as_dict()
+        return re + 1j * im, rc, out
+
+    def krylov_schur_batched(self, ops, v0, nev=10, ncv=60, keep=20, tol=1e-8,
+                             max_restarts=500, use_graph=True):
+        """Krylov-Schur on len(ops) stencil operators at once (Stencil2d descriptors).
+        v0: CUDA float64 tensor, the start vectors concatenated in instance order.
+        Returns (eigs complex numpy [count, nev], status, list of info dicts)."""
+        count = len(ops)
+        arr = (Stencil2d * count)(*ops)
+        total = sum(o.nx * o.ny for o in ops)
+        pv = _vec_ptr(v0, "v0", total)
+        re = np.zeros((count, nev))
+        im = np.zeros((count, nev))
+        infos = (KsInfo * count)()
+        rc = self._lib.krylov_schur_batched(self._h, count, arr, nev, ncv, keep, tol,
+                                            max_restarts, pv, re.ctypes.data_as(c_void_p),
+                                            im.ctypes.data_as(c_void_p), infos,
+                                            1 if use_graph else 0)
+        if rc < 0:
+            raise DCGS2Error(rc, "krylov_schur_batched")
+        out = []
+        for inf in infos:
+            d = {k: getattr(inf, k) for k, _ in KsInfo._fields_ if k != "st"}
+            d["stats"] = inf.st.as_dict()
+            out.append(d)
         return re + 1j * im, rc, out
 
     def set_tuning(self, key: int, value: int):

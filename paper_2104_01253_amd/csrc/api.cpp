@@ -17,7 +17,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
@@ -850,3 +852,293 @@ int krylov_schur_eigs(dcgs2_ctx c, const dcgs2_op* A, int32_t nev, int32_t ncv, 
 }
 
 }  // extern "C"
+
+// =====================================================================================
+// Batched Krylov-Schur: every expansion step is one launch of each batched kernel
+// over all instances (batched.hip); the per-instance dense work (real Schur form,
+// reordering, convergence test, truncation matrices) runs on host threads between
+// cycles.  A cycle's launch sequence depends only on its first step index, so it is
+// captured once per first index into a HIP graph and replayed.
+namespace {
+
+struct BatchedState {
+  int count = 0, p = 0, ld = 0, ldc = 0, ldp = 0;
+  std::vector<dcgs2::BInst> tab;
+  std::vector<int> pre_rows, pre_red;
+  int nb_rows = 0, nb_red = 0;
+  dcgs2::BInst* d_tab = nullptr;
+  int* d_pre_rows = nullptr;
+  int* d_pre_red = nullptr;
+  double *Qa = nullptr, *Qb = nullptr, *vec = nullptr, *coef = nullptr, *pend = nullptr;
+  double *H = nullptr, *K = nullptr, *Z = nullptr, *P1 = nullptr, *P2 = nullptr;
+  Ctrl* ctrl = nullptr;
+  unsigned* cnt = nullptr;
+  hipStream_t s = nullptr;
+  std::vector<std::pair<int, hipGraphExec_t>> graphs;
+  std::vector<hipGraph_t> graph_defs;
+  ~BatchedState() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    for (auto& g : graph_defs) (void)hipGraphDestroy(g);
+    void* bufs[] = {d_tab, d_pre_rows, d_pre_red, Qa, Qb, vec, coef, pend, H, K, Z, P1, P2,
+                    ctrl, cnt};
+    for (void* b : bufs) if (b) (void)hipFree(b);
+    if (s) (void)hipStreamDestroy(s);
+  }
+};
+
+int batched_cycle(BatchedState& B, int jmin, double tau, double eta, int* kernels) {
+  hipStream_t s = B.s;
+  const int p = B.p;
+  CK(launch_breset(B.d_tab, B.count, tau, eta, s));
+  for (int j = jmin; j <= p + 1; ++j) {
+    CK(launch_bstencil(B.d_tab, B.d_pre_rows, B.count, B.nb_rows, j, s));
+    CK(launch_breduce(B.d_tab, B.d_pre_red, B.count, B.nb_red, j, 0, B.ldp, B.ldc, B.ld, s));
+    CK(launch_bupdate(B.d_tab, B.d_pre_rows, B.count, B.nb_rows, j, B.ldc, s));
+    *kernels += 3;
+  }
+  const int jl = p + 2;                     // last column: J = p
+  CK(launch_breduce(B.d_tab, B.d_pre_red, B.count, B.nb_red, jl, 1, B.ldp, B.ldc, B.ld, s));
+  CK(launch_bproject_norm(B.d_tab, B.d_pre_red, B.count, B.nb_red, jl, B.ldp, B.ldc, B.ld, s));
+  CK(launch_bscale(B.d_tab, B.d_pre_rows, B.count, B.nb_rows, jl, B.ldc, s));
+  *kernels += 4;
+  return DCGS2_OK;
+}
+
+int batched_run_cycle(BatchedState& B, int jmin, double tau, double eta, bool use_graph,
+                      int* kernels) {
+  if (!use_graph) return batched_cycle(B, jmin, tau, eta, kernels);
+  for (auto& g : B.graphs) {
+    if (g.first == jmin) {
+      CK(hipGraphLaunch(g.second, B.s));
+      *kernels += 3 * (B.p + 2 - jmin) + 4;
+      return DCGS2_OK;
+    }
+  }
+  hipGraph_t graph = nullptr;
+  CK(hipStreamBeginCapture(B.s, hipStreamCaptureModeThreadLocal));
+  int k0 = 0;
+  const int rc = batched_cycle(B, jmin, tau, eta, &k0);
+  hipGraph_t captured = nullptr;
+  const hipError_t ec = hipStreamEndCapture(B.s, &captured);
+  if (rc != DCGS2_OK) return rc;
+  if (ec != hipSuccess) return DCGS2_EDEVICE;
+  graph = captured;
+  hipGraphExec_t exec = nullptr;
+  CK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  B.graph_defs.push_back(graph);
+  B.graphs.push_back({jmin, exec});
+  CK(hipGraphLaunch(exec, B.s));
+  *kernels += k0;
+  return DCGS2_OK;
+}
+
+}  // namespace
+
+extern "C" int krylov_schur_batched(dcgs2_ctx c, int32_t count, const dcgs2_stencil2d* ops,
+                                    int32_t nev, int32_t ncv, int32_t keep, double tol,
+                                    int32_t max_restarts, const double* v0, double* eig_re,
+                                    double* eig_im, dcgs2_ks_info* infos, int32_t use_graph) {
+  if (!c || count < 1 || count > 65536 || !ops || !v0 || !eig_re || !eig_im || !infos ||
+      nev < 1 || keep <= nev || ncv <= keep || ncv > DCGS2_MAX_N || !(tol > 0.0) ||
+      max_restarts < 0)
+    return DCGS2_EINVAL;
+  for (int b = 0; b < count; ++b) {
+    const int64_t mb = (int64_t)ops[b].nx * ops[b].ny;
+    if (ops[b].nx < 1 || ops[b].ny < 1 || mb <= ncv || mb >= INT32_MAX) return DCGS2_EINVAL;
+  }
+  int rc;
+  if ((rc = ctx_ready(c))) return rc;
+  BatchedState B;
+  B.count = count;
+  B.p = ncv;
+  B.ld = ncv + 1;
+  B.ldc = ncv + 2;
+  B.ldp = 2 * (ncv + 2) + 8;
+  const int p = B.p, ld = B.ld;
+  CK(hipStreamCreateWithFlags(&B.s, hipStreamNonBlocking));   // default priority
+  CK(hipStreamSynchronize(c->stream));      // inputs produced on the caller's stream
+  // layout: per instance, padded row counts; all buffers carved from a few allocations
+  std::vector<int64_t> ldq(count), qoff(count), voff(count), v0off(count);
+  int64_t qtot = 0, vtot = 0, v0tot = 0, gtot = 0;
+  B.pre_rows.assign(count + 1, 0);
+  B.pre_red.assign(count + 1, 0);
+  std::vector<int> G(count);
+  for (int b = 0; b < count; ++b) {
+    const int64_t mb = (int64_t)ops[b].nx * ops[b].ny;
+    ldq[b] = pad_ld(mb);
+    qoff[b] = qtot;
+    qtot += ldq[b] * (p + 1);
+    voff[b] = vtot;
+    vtot += 3 * ldq[b];
+    v0off[b] = v0tot;
+    v0tot += mb;
+    int64_t g = ((mb + 1) / 2 + 1023) / 1024;
+    G[b] = (int)std::max<int64_t>(1, std::min<int64_t>(g, REDUCE_GSMAX));
+    gtot += G[b];
+    B.pre_rows[b + 1] = B.pre_rows[b] + (int)((mb + BATCH_ROWS_PER_BLOCK - 1) / BATCH_ROWS_PER_BLOCK);
+    B.pre_red[b + 1] = B.pre_red[b] + G[b];
+  }
+  B.nb_rows = B.pre_rows[count];
+  B.nb_red = B.pre_red[count];
+  if ((rc = dalloc((void**)&B.Qa, sizeof(double) * qtot))) return rc;
+  if ((rc = dalloc((void**)&B.Qb, sizeof(double) * qtot))) return rc;
+  if ((rc = dalloc((void**)&B.vec, sizeof(double) * vtot))) return rc;
+  if ((rc = dalloc((void**)&B.coef, sizeof(double) * (size_t)count * (2 * B.ldc + 8)))) return rc;
+  if ((rc = dalloc((void**)&B.pend, sizeof(double) * (size_t)count * (2 * B.ldc + 8)))) return rc;
+  if ((rc = dalloc((void**)&B.H, sizeof(double) * (size_t)count * ld * ld))) return rc;
+  if ((rc = dalloc((void**)&B.K, sizeof(double) * (size_t)count * ld * ld))) return rc;
+  if ((rc = dalloc((void**)&B.Z, sizeof(double) * (size_t)count * p * p))) return rc;
+  if ((rc = dalloc((void**)&B.P1, sizeof(double) * (size_t)gtot * B.ldp))) return rc;
+  if ((rc = dalloc((void**)&B.P2, sizeof(double) * (size_t)count * B.ldp))) return rc;
+  if ((rc = dalloc((void**)&B.ctrl, sizeof(Ctrl) * (size_t)count))) return rc;
+  if ((rc = dalloc((void**)&B.cnt, sizeof(unsigned) * (size_t)count * 64))) return rc;
+  if ((rc = dalloc((void**)&B.d_tab, sizeof(dcgs2::BInst) * (size_t)count))) return rc;
+  if ((rc = dalloc((void**)&B.d_pre_rows, sizeof(int) * (size_t)(count + 1)))) return rc;
+  if ((rc = dalloc((void**)&B.d_pre_red, sizeof(int) * (size_t)(count + 1)))) return rc;
+  B.tab.resize(count);
+  int64_t goff = 0;
+  for (int b = 0; b < count; ++b) {
+    dcgs2::BInst& I = B.tab[b];
+    std::memset(&I, 0, sizeof(I));
+    I.m = (int64_t)ops[b].nx * ops[b].ny;
+    I.ldq = ldq[b];
+    I.Q = B.Qa + qoff[b];
+    I.Qn = B.Qb + qoff[b];
+    I.w = B.vec + voff[b];
+    I.v = I.w + ldq[b];
+    I.r = I.v + ldq[b];
+    I.coef = B.coef + (size_t)b * (2 * B.ldc + 8);
+    I.pend = B.pend + (size_t)b * (2 * B.ldc + 8);
+    I.H = B.H + (size_t)b * ld * ld;
+    I.K = B.K + (size_t)b * ld * ld;
+    I.Z = B.Z + (size_t)b * p * p;
+    I.ctrl = B.ctrl + b;
+    I.P1 = B.P1 + goff * B.ldp;
+    I.P2 = B.P2 + (size_t)b * B.ldp;
+    I.cnt = B.cnt + (size_t)b * 64;
+    I.G = G[b];
+    goff += G[b];
+    I.nx = ops[b].nx; I.ny = ops[b].ny;
+    I.c0 = ops[b].c0; I.cxm = ops[b].cxm; I.cxp = ops[b].cxp; I.cym = ops[b].cym;
+    I.cyp = ops[b].cyp;
+    I.first_j = 2;
+    I.restart = 0;
+    I.active = 1;
+    CK(hipMemcpyAsync(I.w, v0 + v0off[b], sizeof(double) * I.m, hipMemcpyDeviceToDevice, B.s));
+  }
+  CK(hipMemcpyAsync(B.d_pre_rows, B.pre_rows.data(), sizeof(int) * (count + 1),
+                    hipMemcpyHostToDevice, B.s));
+  CK(hipMemcpyAsync(B.d_pre_red, B.pre_red.data(), sizeof(int) * (count + 1),
+                    hipMemcpyHostToDevice, B.s));
+  CK(hipMemcpyAsync(B.d_tab, B.tab.data(), sizeof(dcgs2::BInst) * count, hipMemcpyHostToDevice,
+                    B.s));
+  CK(launch_fill(B.H, (int64_t)count * ld * ld, 0.0, B.s));
+  CK(launch_fill(B.K, (int64_t)count * ld * ld, 0.0, B.s));
+  CK(launch_zero_u32(B.cnt, count * 64, B.s));
+  int kernels = 0;
+  if ((rc = batched_run_cycle(B, 2, c->tau, c->eta, use_graph != 0, &kernels))) return rc;
+  for (int b = 0; b < count; ++b) {
+    std::memset(&infos[b], 0, sizeof(infos[b]));
+    infos[b].matvecs = p;
+    infos[b].status = DCGS2_NOT_CONVERGED;
+  }
+  std::vector<Ctrl> hctrl(count);
+  std::vector<dcgs2::BInst> tab_trunc;
+  std::vector<double> Hh((size_t)count * ld * ld), Zh((size_t)count * p * p);
+  int overall = DCGS2_OK;
+  const double CUT_GAP = 1e-8;
+  for (;;) {
+    CK(hipMemcpyAsync(hctrl.data(), B.ctrl, sizeof(Ctrl) * count, hipMemcpyDeviceToHost, B.s));
+    CK(hipMemcpyAsync(Hh.data(), B.H, sizeof(double) * Hh.size(), hipMemcpyDeviceToHost, B.s));
+    CK(hipStreamSynchronize(B.s));
+    // per-instance dense work on host threads
+    const int nthreads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    std::atomic<int> next{0};
+    auto worker = [&]() {
+      std::vector<double> T((size_t)p * p), Zm((size_t)p * p), ere(p), eim(p);
+      for (int b = next++; b < count; b = next++) {
+        dcgs2::BInst& I = B.tab[b];
+        if (!I.active) continue;
+        dcgs2_ks_info& inf = infos[b];
+        inf.st.reductions += hctrl[b].reductions;
+        I.truncate = 0;
+        if (hctrl[b].state != ST_RUNNING) {
+          inf.status = hctrl[b].state == ST_BREAKDOWN ? DCGS2_BREAKDOWN
+                       : hctrl[b].state == ST_NONFINITE ? DCGS2_NONFINITE : DCGS2_NOT_CONVERGED;
+          if (hctrl[b].state == ST_FALLBACK) inf.st.pyth_fallbacks += 1;
+          inf.st.breakdown_step = hctrl[b].k;
+          I.active = 0;
+          continue;
+        }
+        const double* Hb = Hh.data() + (size_t)b * ld * ld;
+        const double h = Hb[(size_t)(p - 1) * ld + p];
+        for (int jj = 0; jj < p; ++jj)
+          for (int i = 0; i < p; ++i) T[(size_t)jj * p + i] = Hb[(size_t)jj * ld + i];
+        if (real_schur(p, T.data(), p, Zm.data(), p) != 0) { I.active = 0; continue; }
+        const int kn = reorder_schur_by_magnitude(p, T.data(), p, Zm.data(), p, nev, CUT_GAP);
+        if (kn < 0) { I.active = 0; continue; }
+        schur_eigenvalues(p, T.data(), p, ere.data(), eim.data());
+        double bn = 0.0, tmin = INFINITY;
+        for (int i = 0; i < kn; ++i) {
+          const double bi = h * Zm[(size_t)i * p + (p - 1)];
+          bn += bi * bi;
+          tmin = std::min(tmin, std::hypot(ere[i], eim[i]));
+        }
+        inf.resid = std::sqrt(bn) / tmin;
+        for (int i = 0; i < nev; ++i) {
+          eig_re[(size_t)b * nev + i] = ere[i];
+          eig_im[(size_t)b * nev + i] = eim[i];
+        }
+        if (inf.resid <= tol) { inf.nconv = kn; inf.status = DCGS2_OK; I.active = 0; continue; }
+        if (inf.restarts >= max_restarts) { inf.status = DCGS2_NOT_CONVERGED; I.active = 0; continue; }
+        const int k = reorder_schur_by_magnitude(p, T.data(), p, Zm.data(), p, keep, CUT_GAP);
+        if (k < 0 || k >= p) { I.active = 0; continue; }
+        std::copy(Zm.begin(), Zm.end(), Zh.begin() + (size_t)b * p * p);
+        double* Hn = Hh.data() + (size_t)b * ld * ld;
+        std::fill(Hn, Hn + (size_t)ld * ld, 0.0);
+        for (int jj = 0; jj < k; ++jj) {
+          for (int i = 0; i < k; ++i) Hn[(size_t)jj * ld + i] = T[(size_t)jj * p + i];
+          Hn[(size_t)jj * ld + k] = h * Zm[(size_t)jj * p + (p - 1)];
+        }
+        I.k = k;
+        I.first_j = k + 2;
+        I.restart = 1;
+        I.truncate = 1;
+        inf.restarts += 1;
+        inf.matvecs += p - k;
+      }
+    };
+    for (int t = 0; t < nthreads; ++t) pool.emplace_back(worker);
+    for (auto& t : pool) t.join();
+    int jmin = INT32_MAX;
+    for (int b = 0; b < count; ++b)
+      if (B.tab[b].active) jmin = std::min(jmin, B.tab[b].first_j);
+    if (jmin == INT32_MAX) break;
+    // truncation: Qn = Q Z_k, q_{k+1} and w; then swap the bases of truncated instances
+    CK(hipMemcpyAsync(B.Z, Zh.data(), sizeof(double) * Zh.size(), hipMemcpyHostToDevice, B.s));
+    CK(hipMemcpyAsync(B.H, Hh.data(), sizeof(double) * Hh.size(), hipMemcpyHostToDevice, B.s));
+    CK(launch_fill(B.K, (int64_t)count * ld * ld, 0.0, B.s));
+    // the truncation reads this copy of the table; the swapped table below is uploaded
+    // from a different host buffer, and neither changes before the next synchronisation
+    tab_trunc = B.tab;
+    CK(hipMemcpyAsync(B.d_tab, tab_trunc.data(), sizeof(dcgs2::BInst) * count,
+                      hipMemcpyHostToDevice, B.s));
+    CK(launch_btruncate(B.d_tab, B.d_pre_rows, count, B.nb_rows, p, B.s));
+    kernels += 2;
+    for (int b = 0; b < count; ++b) {
+      dcgs2::BInst& I = B.tab[b];
+      if (I.active && I.truncate) { std::swap(I.Q, I.Qn); I.truncate = 0; }
+    }
+    CK(hipMemcpyAsync(B.d_tab, B.tab.data(), sizeof(dcgs2::BInst) * count, hipMemcpyHostToDevice,
+                      B.s));
+    if ((rc = batched_run_cycle(B, jmin, c->tau, c->eta, use_graph != 0, &kernels))) return rc;
+  }
+  for (int b = 0; b < count; ++b) {
+    infos[b].st.kernels = kernels;
+    if (infos[b].status != DCGS2_OK) overall = DCGS2_NOT_CONVERGED;
+    if (infos[b].status == DCGS2_OK) infos[b].st.breakdown_step = -1;
+  }
+  CK(hipStreamSynchronize(B.s));
+  return overall;
+}

@@ -128,6 +128,44 @@ hipError_t launch_tsgemm(const void* Q, int q32, int64_t ldq, int p, const doubl
 hipError_t launch_convert(void* dst, int d32, const void* src, int s32, int64_t m,
                           hipStream_t s);
 
+// ---- batched Krylov-Schur (batched.hip) ----------------------------------------------
+// One record per instance in a device table; see batched.hip.
+struct BInst {
+  int64_t m, ldq;
+  double* Q;           // basis of the current cycle, m x (p+1), leading dimension ldq
+  double* Qn;          // truncation target (swapped with Q after a truncation)
+  double *w, *v, *r;   // working vectors (length m)
+  double *coef, *pend; // per-instance coefficient and fallback hand-over blocks
+  double *H, *K;       // (p+1) x (p+1), leading dimension p+1
+  double* Z;           // p x p Schur vectors of the last truncation (leading dimension p)
+  Ctrl* ctrl;
+  double *P1, *P2;     // reduction partials (G x ldp) and group partials
+  unsigned* cnt;       // arrival counters (64)
+  int G;               // workgroups of the instance's reduction passes
+  int nx, ny;
+  double c0, cxm, cxp, cym, cyp;
+  int first_j;         // first step of the current cycle (2 for a fresh start)
+  int restart;         // the first step is the Krylov-Schur continuation step
+  int k;               // Schur vectors kept by the last truncation
+  int active;          // 0: converged or stopped -- every batched kernel skips it
+  int truncate;        // 1: btruncate acts on this instance
+  int pad;
+};
+hipError_t launch_bstencil(const BInst* tab, const int* pre_rows, int count, int nblocks, int j,
+                           hipStream_t s);
+hipError_t launch_breduce(const BInst* tab, const int* pre_red, int count, int nblocks, int j,
+                          int last, int ldp, int ldc, int ldh, hipStream_t s);
+hipError_t launch_bupdate(const BInst* tab, const int* pre_rows, int count, int nblocks, int j,
+                          int ldc, hipStream_t s);
+hipError_t launch_bproject_norm(const BInst* tab, const int* pre_red, int count, int nblocks,
+                                int j, int ldp, int ldc, int ldh, hipStream_t s);
+hipError_t launch_bscale(const BInst* tab, const int* pre_rows, int count, int nblocks, int j,
+                         int ldc, hipStream_t s);
+hipError_t launch_btruncate(const BInst* tab, const int* pre_rows, int count, int nblocks, int p,
+                            hipStream_t s);
+hipError_t launch_breset(const BInst* tab, int count, double tau, double eta, hipStream_t s);
+constexpr int BATCH_ROWS_PER_BLOCK = 512;  // rows per workgroup of the row-parallel kernels
+
 // Grid sizing for the reductions (number of workgroups for m rows).
 void reduce_grid(int64_t m, int gmax, int* G, int* GS, int* NG);
 constexpr int REDUCE_GMAX = 1024;

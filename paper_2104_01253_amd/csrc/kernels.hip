@@ -28,124 +28,22 @@ namespace {
 
 #include "device_common.h"
 
-// ---------------------------------------------------------------------------------
-// Reduction pass: per-workgroup partial dot products of [Q_{0..J-1}, x, (y)] with
-// [x, (y)] over a contiguous slab of rows, NT basis columns at a time.
 template <int VW, bool HASY, typename TQ>
 __global__ __launch_bounds__(BS) void reduce_kernel(const TQ* __restrict__ Q, int64_t ldq,
                                                     int J, const double* __restrict__ x,
                                                     const double* __restrict__ y, int64_t m,
                                                     GridRed gr, FinArgs fin) {
-  extern __shared__ double smem[];
-  if (fin.ctrl->state != ST_RUNNING) return;
-  const int Jt = J + (HASY ? 2 : 1);
-  const int V = HASY ? 2 * Jt : Jt;
-  double* red = smem;                       // V
-  double* shb = red + V;                    // NW * 2 * NT
-  double* T = shb + NW * 2 * NT;            // J + 2
-  double* scratch = T + (J + 2);            // 3 (J + 2) + 64
-  const int64_t units = m / VW;
-  const int64_t per = (units + gr.G - 1) / gr.G;
-  const int64_t u0 = (int64_t)blockIdx.x * per;
-  const int64_t u1 = min(units, u0 + per);
-  const bool tail = (VW == 2) && (m & 1) && blockIdx.x == gr.G - 1 && threadIdx.x == 0;
-  double* P = gr.P1 + (int64_t)blockIdx.x * gr.ldp;
-  using RV = RowVec<VW>;
-
-  for (int k0 = 0; k0 < Jt; k0 += NT) {
-    double acc[2 * NT];
-#pragma unroll
-    for (int c = 0; c < 2 * NT; ++c) acc[c] = 0.0;
-    // column k0 + c is basis column k (k < J), x (k == J) or y (k == J + 1)
-    const TQ* qbase = Q + (int64_t)k0 * ldq;
-#pragma unroll 2
-    for (int64_t u = u0 + threadIdx.x; u < u1; u += BS) {
-      const RV xv = RV::load(x, u);
-      const RV yv = HASY ? RV::load(y, u) : RV::zero();
-#pragma unroll
-      for (int c = 0; c < NT; ++c) {
-        if (k0 + c < Jt) {
-          const RV q = (k0 + c < J) ? RV::load(qbase + (int64_t)c * ldq, u)
-                                    : (k0 + c == J ? xv : yv);
-          acc[c] += q.dot(xv);
-          if (HASY) acc[NT + c] += q.dot(yv);
-        }
-      }
-    }
-    if (tail) {                              // odd m with 2-row units: last row
-      const int64_t r = m - 1;
-      const double xr = x[r], yr = HASY ? y[r] : 0.0;
-#pragma unroll
-      for (int c = 0; c < NT; ++c) {
-        if (k0 + c < Jt) {
-          const double q = (k0 + c < J) ? (double)qbase[(int64_t)c * ldq + r]
-                                        : (k0 + c == J ? xr : yr);
-          acc[c] += q * xr;
-          if (HASY) acc[NT + c] += q * yr;
-        }
-      }
-    }
-    const int nvalid = min(NT, Jt - k0);
-    if (HASY) {
-      // partial layout: [0,Jt) = [Q,x,y]^T x ; [Jt, 2Jt) = [Q,x,y]^T y
-      block_sum_t<2 * NT, NT>(acc, shb, P + k0, nvalid, P + Jt + k0, nvalid);
-    } else {
-      double ax[NT];
-#pragma unroll
-      for (int c = 0; c < NT; ++c) ax[c] = acc[c];
-      block_sum_t<NT, NT>(ax, shb, P + k0, nvalid, nullptr, 0);
-    }
-  }
-  if (grid_reduce(gr, V, red)) finalize(fin, red, T, scratch);
+  reduce_body<VW, HASY, TQ>(Q, ldq, J, x, y, m, gr, fin, blockIdx.x);
 }
 
-// u = x - Q_{0..J-1} C written to Q[:, J]; ||u||^2 grid-reduced and finalised.
 template <int VW, typename TQ>
 __global__ __launch_bounds__(BS) void project_norm_kernel(const TQ* __restrict__ Q, int64_t ldq,
                                                           int J, const double* __restrict__ x,
                                                           double* __restrict__ ubuf, int64_t m,
                                                           GridRed gr, FinArgs fin) {
-  extern __shared__ double smem[];
-  if (fin.ctrl->state != ST_RUNNING) return;
-  double* red = smem;                       // 1
-  double* shb = red + 2;                    // NW
-  double* T = shb + NW;                     // J + 2
-  double* scratch = T + (J + 2);
-  const double* __restrict__ C = fin.coef;
-  const int64_t units = m / VW;
-  const int64_t per = (units + gr.G - 1) / gr.G;
-  const int64_t u0 = (int64_t)blockIdx.x * per;
-  const int64_t u1 = min(units, u0 + per);
-  using RV = RowVec<VW>;
-  double acc[1] = {0.0};
-  for (int64_t u = u0 + threadIdx.x; u < u1; u += BS) {
-    RV sc = RV::zero();
-    for (int k = 0; k < J; ++k) {
-      const RV q = RV::load(Q + (int64_t)k * ldq, u);
-      const double ck = C[k];
-#pragma unroll
-      for (int e = 0; e < VW; ++e) sc.e[e] = fma(q.e[e], ck, sc.e[e]);
-    }
-    const RV xv = RV::load(x, u);
-    RV uu;
-#pragma unroll
-    for (int e = 0; e < VW; ++e) uu.e[e] = xv.e[e] - sc.e[e];
-    uu.store(ubuf, u);
-    acc[0] += uu.dot(uu);
-  }
-  if ((VW == 2) && (m & 1) && blockIdx.x == gr.G - 1 && threadIdx.x == 0) {
-    const int64_t r = m - 1;
-    double s = 0.0;
-    for (int k = 0; k < J; ++k) s = fma((double)Q[(int64_t)k * ldq + r], C[k], s);
-    const double uval = x[r] - s;
-    ubuf[r] = uval;
-    acc[0] += uval * uval;
-  }
-  block_sum<1>(acc, shb, gr.P1 + (int64_t)blockIdx.x * gr.ldp, 1);
-  if (grid_reduce(gr, 1, red)) finalize(fin, red, T, scratch);
+  project_norm_body<VW, TQ>(Q, ldq, J, x, ubuf, m, gr, fin, blockIdx.x);
 }
 
-// Update pass: q_{j-1} and w_j, one row unit per thread.
 template <int VW, bool ARN, bool QCOL, typename TQ>
 __global__ __launch_bounds__(BS) void update_kernel(TQ* __restrict__ Q, int64_t ldq, int J,
                                                     double* __restrict__ x,
@@ -153,53 +51,7 @@ __global__ __launch_bounds__(BS) void update_kernel(TQ* __restrict__ Q, int64_t 
                                                     const double* __restrict__ ubuf, int64_t m,
                                                     const double* __restrict__ coef, int ldc,
                                                     const Ctrl* __restrict__ ctrl) {
-  if (ctrl->state != ST_RUNNING) return;
-  const double* __restrict__ C = coef;
-  const double* __restrict__ T = coef + ldc;
-  const double alpha = coef[2 * ldc];
-  const double tJ = T[J];
-  const int64_t units = m / VW;
-  const int64_t u = (int64_t)blockIdx.x * BS + threadIdx.x;
-  TQ* qout = Q + (int64_t)J * ldq;
-  if (u < units) {
-    RowVec<VW> sc = RowVec<VW>::zero(), st = RowVec<VW>::zero();
-#pragma unroll 8
-    for (int k = 0; k < J; ++k) {
-      const RowVec<VW> q = RowVec<VW>::load(Q + (int64_t)k * ldq, u);
-      const double ck = C[k], tk = T[k];
-#pragma unroll
-      for (int e = 0; e < VW; ++e) {
-        sc.e[e] = fma(q.e[e], ck, sc.e[e]);
-        st.e[e] = fma(q.e[e], tk, st.e[e]);
-      }
-    }
-    const RowVec<VW> xv = RowVec<VW>::load(x, u);
-    const RowVec<VW> yv = RowVec<VW>::load(y, u);
-    RowVec<VW> qc = RowVec<VW>::zero();
-    if (QCOL) qc = RowVec<VW>::load(ubuf, u);
-    RowVec<VW> qn, wn;
-#pragma unroll
-    for (int e = 0; e < VW; ++e) {
-      const double q = stored<TQ>(QCOL ? qc.e[e] / alpha : (xv.e[e] - sc.e[e]) / alpha);
-      const double yt = ARN ? yv.e[e] / alpha : yv.e[e];
-      qn.e[e] = q;
-      wn.e[e] = yt - fma(q, tJ, st.e[e]);
-    }
-    qn.store(qout, u);
-    wn.store(x, u);
-  } else if (VW == 2 && (m & 1) && u == units) {
-    const int64_t r = m - 1;
-    double sc = 0.0, st = 0.0;
-    for (int k = 0; k < J; ++k) {
-      const double q = (double)Q[(int64_t)k * ldq + r];
-      sc = fma(q, C[k], sc);
-      st = fma(q, T[k], st);
-    }
-    const double q = stored<TQ>(QCOL ? ubuf[r] / alpha : (x[r] - sc) / alpha);
-    const double yt = ARN ? y[r] / alpha : y[r];
-    qout[r] = (TQ)q;
-    x[r] = yt - fma(q, tJ, st);
-  }
+  update_body<VW, ARN, QCOL, TQ>(Q, ldq, J, x, y, ubuf, m, coef, ldc, ctrl, blockIdx.x);
 }
 
 // One-pass QR step (Alg. qr): the update of step j and the reduction of step j+1
@@ -315,7 +167,7 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
   double* red = smem;
   double* Tf = red + V;
   double* scratch = Tf + (J + 3);
-  if (grid_reduce(gr, V, red)) finalize(fin, red, Tf, scratch);
+  if (grid_reduce(gr, V, red, blockIdx.x)) finalize(fin, red, Tf, scratch);
 }
 
 // q = u / alpha into Q[:, J] (rounded once to the basis type).

@@ -77,6 +77,15 @@ def test_arnoldi_gmres_ks_argument_validation(ctx):
     assert lib.krylov_schur_eigs(h, ctypes.byref(op), 10, 30, 10, 1e-8, 5, FAKE, re_, im_, None) == E
     assert lib.krylov_schur_eigs(h, ctypes.byref(op), 5, 64, 10, 1e-8, 5, FAKE, re_, im_, None) == E
     assert lib.krylov_schur_eigs(h, ctypes.byref(op), 5, 30, 10, -1.0, 5, FAKE, re_, im_, None) == E
+    ops = (binding.Stencil2d * 2)(binding.stencil2d((8, 8)), binding.stencil2d((6, 5)))
+    re2, im2 = (ctypes.c_double * 20)(), (ctypes.c_double * 20)()
+    infos = (binding.KsInfo * 2)()
+    ksb = lib.krylov_schur_batched
+    assert ksb(h, 2, ops, 2, 30, 8, 1e-8, 5, FAKE, re2, im2, infos, 1) == E     # ncv >= 6*5
+    assert ksb(h, 0, ops, 2, 20, 8, 1e-8, 5, FAKE, re2, im2, infos, 1) == E     # count < 1
+    assert ksb(h, 1, ops, 2, 20, 2, 1e-8, 5, FAKE, re2, im2, infos, 1) == E     # keep <= nev
+    assert ksb(h, 1, ops, 2, 20, 8, 0.0, 5, FAKE, re2, im2, infos, 1) == E      # tol
+    assert ksb(h, 1, None, 2, 20, 8, 1e-8, 5, FAKE, re2, im2, infos, 1) == E
     csr = binding.Op()
     csr.kind = binding.OP_CSR
     csr.m = 10

@@ -1,0 +1,98 @@
+"""Batched Krylov-Schur (one launch per DCGS2 step over all instances) against the
+oracle, against the single-instance path, and graph replay against eager launches.
+
+The instances are 2-D convection-diffusion operators of different grid sizes and
+velocities (the batched eigenvalue family), including a ragged odd-sized grid and a
+tiny instance whose first cycle already converges while the others restart.
+"""
+import numpy as np
+import pytest
+
+from oracle import operators as ops
+from oracle.krylov_schur import krylov_schur
+from paper_2104_01253_amd import binding, synth
+from tests._gpu import dev_vector, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+NEV, NCV, KEEP, TOL = 6, 30, 12, 1e-9
+
+# (grid, velocity, start-vector seed); grid 31 x 17 has odd m = 527, grid 7 x 6 has
+# m = 42, barely above ncv, so its first cycle is nearly exact
+CASES = [((24, 24), (4.0, 6.0), 11), ((31, 17), (10.0, 3.0), 12), ((40, 40), (30.0, 30.0), 13),
+         ((7, 6), (1.0, 2.0), 14), ((48, 20), (0.0, 20.0), 15)]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch_cuda()
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def _batch(cases):
+    import torch
+    descs = [binding.stencil2d(g, 1.0, v) for g, v, _ in cases]
+    v0s = [synth.normal_vector(g[0] * g[1], s) for g, _, s in cases]
+    v0 = dev_vector(np.concatenate(v0s))
+    torch.cuda.synchronize()
+    return descs, v0s, v0
+
+
+def _by_magnitude(ev):
+    return ev[np.lexsort((ev.imag, ev.real, -np.abs(ev)))]
+
+
+def test_batched_ks_vs_oracle(ctx):
+    descs, v0s, v0 = _batch(CASES)
+    ev, rc, infos = ctx.krylov_schur_batched(descs, v0, NEV, NCV, KEEP, TOL, 200)
+    say("batched rc", rc, [(i["status"], i["restarts"], i["resid"]) for i in infos])
+    assert rc == binding.OK
+    for b, (g, v, _) in enumerate(CASES):
+        A = ops.convection_diffusion(g, 1.0, v)
+        ref, io = krylov_schur(A, v0s[b], nev=NEV, ncv=NCV, keep=KEEP, tol=TOL)
+        say("instance", b, g, v, "gpu restarts", infos[b]["restarts"], "oracle", io["restarts"])
+        assert infos[b]["status"] == binding.OK and infos[b]["resid"] <= TOL
+        got, want = _by_magnitude(ev[b]), _by_magnitude(np.asarray(ref))
+        assert np.max(np.abs(got - want)) <= 1e-8 * abs(want[0]), (got, want)
+        assert abs(infos[b]["restarts"] - io["restarts"]) <= 1
+        if abs(v[0]) * 0.5 / (g[0] + 1) < 1 and abs(v[1]) * 0.5 / (g[1] + 1) < 1:
+            exact = ops.closed_form_eigenvalues(g, 1.0, v)[::-1][:NEV]
+            assert np.max(np.abs(np.sort(got.real)[::-1] - exact)) <= 1e-8 * exact[0]
+    assert infos[3]["restarts"] == 0            # the tiny instance converges in cycle 1
+    assert max(i["restarts"] for i in infos) >= 1
+
+
+def test_batched_matches_single_instance_path(ctx):
+    descs, v0s, v0 = _batch(CASES[:3])
+    ev, rc, infos = ctx.krylov_schur_batched(descs, v0, NEV, NCV, KEEP, TOL, 200)
+    assert rc == binding.OK
+    for b, (g, v, _) in enumerate(CASES[:3]):
+        e1, rc1, i1 = ctx.krylov_schur(binding.stencil_op(g, 1.0, v), dev_vector(v0s[b]),
+                                       nev=NEV, ncv=NCV, keep=KEEP, tol=TOL, max_restarts=200)
+        assert rc1 == binding.OK
+        assert np.max(np.abs(_by_magnitude(ev[b]) - _by_magnitude(e1))) <= 1e-10 * abs(e1[0])
+        assert abs(i1["restarts"] - infos[b]["restarts"]) <= 1
+
+
+def test_batched_graph_replay_is_bitwise_eager(ctx):
+    descs, _, v0 = _batch(CASES)
+    eg, rcg, ig = ctx.krylov_schur_batched(descs, v0, NEV, NCV, KEEP, TOL, 200, use_graph=True)
+    ee, rce, ie = ctx.krylov_schur_batched(descs, v0, NEV, NCV, KEEP, TOL, 200, use_graph=False)
+    assert rcg == rce == binding.OK
+    assert np.array_equal(eg, ee)
+    for a, b in zip(ig, ie):
+        assert a["restarts"] == b["restarts"] and a["resid"] == b["resid"]
+        assert a["stats"]["reductions"] == b["stats"]["reductions"]
+
+
+def test_batched_single_instance_and_budget(ctx):
+    descs, _, v0 = _batch(CASES[2:3])
+    ev, rc, infos = ctx.krylov_schur_batched(descs, v0, NEV, NCV, KEEP, TOL, 200)
+    assert rc == binding.OK and infos[0]["status"] == binding.OK
+    # a zero restart budget: the instance that needs restarts reports NOT_CONVERGED
+    descs, _, v0 = _batch(CASES[2:4])
+    ev, rc, infos = ctx.krylov_schur_batched(descs, v0, NEV, NCV, KEEP, TOL, 0)
+    assert rc == binding.NOT_CONVERGED
+    assert infos[0]["status"] == binding.NOT_CONVERGED and infos[1]["status"] == binding.OK

@@ -49,7 +49,7 @@ def test_qr_parity_small(ctx, m, n, ce, one_pass):
     assert np.linalg.norm((Q - ref["Q"]) @ ref["R"]) / np.linalg.norm(B) <= TOL
     if ce <= 2:
         assert np.linalg.norm(Q - ref["Q"]) / np.sqrt(n) <= TOL
-    assert st["reductions"] == ref["reductions"] == n + 1
+    assert st["reductions"] == ref["reductions"] == (n + 1 if n > 1 else 1)
     assert loss_of_orthogonality(Q) <= 1e-13
     assert qr_error(B, Q, R) <= 1e-14
 

@@ -81,6 +81,8 @@ def test_reduction_counts():
     assert gs.dcgs2_qr(B)["reductions"] == n + 1
     assert gs.cgs2_qr(B)[2] == 3 * (n - 1) + 1
     assert gs.mgs_qr(B)[2] == n * (n + 1) // 2
+    # one column: the last-column finish has nothing to project out, only a norm
+    assert gs.dcgs2_qr(B[:, :1])["reductions"] == 1
 
 
 def test_forced_pythagorean_fallback_gives_same_factorization():
