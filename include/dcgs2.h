@@ -258,8 +258,67 @@ int krylov_schur_batched(dcgs2_ctx ctx, int32_t count, const dcgs2_stencil2d* op
                          int32_t max_restarts, const double* v0, double* eig_re_host,
                          double* eig_im_host, dcgs2_ks_info* info_host, int32_t use_graph);
 
-/* y = A x (device vectors of length A->m).  The matvec of step a1; exported so
- * the operator can be checked on its own. */
+/* ------------------------------------------------------------------------------------
+ * Learned initial guess for GMRES (x0 of the minimisation over x0 + K_k, Sec. 1).
+ * Not part of the paper's method: a data-driven start vector for families of
+ * 2-D problems on an n x n interior grid (x fastest, h = 1/(n+1)).  A coarse
+ * nc x nc grid (n divisible by nc, r = n/nc) carries the learned part:
+ *   restriction   R : mean of each r x r block of fine values;
+ *   prolongation  P : tensor-product linear interpolation of the values at the
+ *                     coarse block centres, zero at the Dirichlet boundary;
+ *   features        : [R(b)/s, operator parameters, zero padding], s = RMS of R(b);
+ *   guess           : x0 = s * P(MLP(features)).
+ * The perceptron (FP32; Z_l = X_l W_l + b_l, ReLU on hidden layers, linear
+ * output) is trained with the mean squared error on targets R(x)/s of solved
+ * instances and Adam (Kingma & Ba, 2015).  Its products run on the matrix cores.
+ * Arrays marked device are caller-owned device memory; samples are rows
+ * (row-major, sample-major).  All calls synchronise the context's stream.
+ * ---------------------------------------------------------------------------------- */
+typedef struct dcgs2_mlp_s* dcgs2_mlp;
+
+/* Perceptron with nlayers layers of widths[0] -> ... -> widths[nlayers] (each
+ * 1..16384, 1 <= nlayers <= 16) for batches of up to max_batch (<= 65536) rows.
+ * Parameters start at zero; they are packed layer by layer as W_l (row-major,
+ * widths[l] x widths[l+1]) followed by b_l. */
+int dcgs2_mlp_create(dcgs2_ctx ctx, int32_t nlayers, const int32_t* widths, int32_t max_batch,
+                     dcgs2_mlp* out);
+int dcgs2_mlp_destroy(dcgs2_mlp mlp);
+int dcgs2_mlp_num_params(dcgs2_mlp mlp, int64_t* count);
+/* Host copy in (resets the Adam moments and step count) / out. */
+int dcgs2_mlp_set_params(dcgs2_mlp mlp, const float* params_host);
+int dcgs2_mlp_get_params(dcgs2_mlp mlp, float* params_host);
+/* Gradients of the last dcgs2_mlp_loss_grad, packed like the parameters. */
+int dcgs2_mlp_get_grads(dcgs2_mlp mlp, float* grads_host);
+/* Y (device, batch x widths[nlayers]) = MLP(X) (device, batch x widths[0]). */
+int dcgs2_mlp_forward(dcgs2_mlp mlp, int32_t batch, const float* X, float* Y);
+/* Forward pass, loss = mean((Y - T)^2) over all batch x widths[nlayers] entries
+ * (host, may be NULL) and its gradients into the gradient buffer. */
+int dcgs2_mlp_loss_grad(dcgs2_mlp mlp, int32_t batch, const float* X, const float* T,
+                        double* loss_host);
+/* One Adam step with the stored gradients (0 <= beta < 1, lr > 0, eps > 0). */
+int dcgs2_mlp_adam(dcgs2_mlp mlp, float lr, float beta1, float beta2, float eps);
+
+/* Features of `count` instances: b (device, count x n*n doubles), prm (device,
+ * count x np floats) -> feat (device, count x fdim floats, fdim >= nc*nc + np)
+ * and scale (device, count doubles).  nc <= 64. */
+int dcgs2_guess_features(dcgs2_ctx ctx, int32_t count, int32_t n, int32_t nc, const double* b,
+                         const float* prm, int32_t np, int32_t fdim, float* feat, double* scale);
+/* Training targets t = R(x)/scale (device, count x nc*nc floats; zero where scale = 0). */
+int dcgs2_guess_targets(dcgs2_ctx ctx, int32_t count, int32_t n, int32_t nc, const double* x,
+                        const double* scale, float* t);
+/* x0 = scale * P(y): y device count x nc*nc floats, x0 device count x n*n doubles. */
+int dcgs2_guess_prolong(dcgs2_ctx ctx, int32_t count, int32_t n, int32_t nc, const float* y,
+                        const double* scale, double* x0);
+/* Zero-guess fallback: ratio = ||b - A x0|| / ||b|| (host, may be NULL); keeps x0
+ * (kept = 1) when the ratio is finite and below max_ratio (> 0), otherwise sets
+ * x0 = 0 (kept = 0).  A coarse guess leaves interpolation kinks whose residual
+ * can exceed ||b|| while its error is small, so max_ratio is taken well above 1
+ * (the training driver uses 10).  b, x0: device vectors of length A->m. */
+int dcgs2_guess_guard(dcgs2_ctx ctx, const dcgs2_op* A, const double* b, double* x0,
+                      double max_ratio, int32_t* kept, double* ratio_host);
+
+/* y = A x (device vectors of length A->m).  The matvec of each expansion step;
+ * exported so the operator can be checked on its own. */
 int dcgs2_apply(dcgs2_ctx ctx, const dcgs2_op* A, const double* x, double* y);
 
 /* Static description of a status code. */

@@ -25,7 +25,12 @@ EXPORTS = ("dcgs2_create", "dcgs2_destroy", "dcgs2_set_tolerances", "dcgs2_qr", 
            "gmres_solve", "krylov_schur_eigs", "dcgs2_apply", "dcgs2_status_str",
            "dcgs2_profile_enable", "dcgs2_profile_read", "dcgs2_set_qr_schedule",
            "dcgs2_qr_q32", "dcgs2_arnoldi_q32", "dcgs2_set_basis_precision", "cgs2_qr",
-           "dcgs2_set_tuning", "dcgs2_get_tuning", "krylov_schur_batched")
+           "dcgs2_set_tuning", "dcgs2_get_tuning", "krylov_schur_batched",
+           "dcgs2_mlp_create", "dcgs2_mlp_destroy", "dcgs2_mlp_num_params",
+           "dcgs2_mlp_set_params", "dcgs2_mlp_get_params", "dcgs2_mlp_get_grads",
+           "dcgs2_mlp_forward", "dcgs2_mlp_loss_grad", "dcgs2_mlp_adam",
+           "dcgs2_guess_features", "dcgs2_guess_targets", "dcgs2_guess_prolong",
+           "dcgs2_guess_guard")
 TUNE_FUSED_WAVES, TUNE_REDUCE_GRID = 0, 1
 
 
@@ -101,12 +106,27 @@ def load(path: str = LIB_PATH):
     lib.dcgs2_profile_read.argtypes = [c_void_p, POINTER(KernelStat), c_int32, c_int32]
     lib.dcgs2_status_str.argtypes = [c_int]
     lib.dcgs2_status_str.restype = ctypes.c_char_p
-    for name in ("dcgs2_create", "dcgs2_destroy", "dcgs2_set_tolerances", "dcgs2_qr",
-                 "dcgs2_arnoldi", "gmres_solve", "krylov_schur_eigs", "dcgs2_apply",
-                 "dcgs2_profile_enable", "dcgs2_profile_read", "dcgs2_set_qr_schedule",
-                 "dcgs2_qr_q32", "dcgs2_arnoldi_q32", "dcgs2_set_basis_precision", "cgs2_qr",
-                 "dcgs2_set_tuning", "dcgs2_get_tuning", "krylov_schur_batched"):
-        getattr(lib, name).restype = c_int
+    c_i32p = POINTER(c_int32)
+    lib.dcgs2_mlp_create.argtypes = [c_void_p, c_int32, c_i32p, c_int32, POINTER(c_void_p)]
+    lib.dcgs2_mlp_destroy.argtypes = [c_void_p]
+    lib.dcgs2_mlp_num_params.argtypes = [c_void_p, POINTER(c_int64)]
+    lib.dcgs2_mlp_set_params.argtypes = [c_void_p, c_void_p]
+    lib.dcgs2_mlp_get_params.argtypes = [c_void_p, c_void_p]
+    lib.dcgs2_mlp_get_grads.argtypes = [c_void_p, c_void_p]
+    lib.dcgs2_mlp_forward.argtypes = [c_void_p, c_int32, c_void_p, c_void_p]
+    lib.dcgs2_mlp_loss_grad.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, POINTER(c_double)]
+    lib.dcgs2_mlp_adam.argtypes = [c_void_p, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                   ctypes.c_float]
+    lib.dcgs2_guess_features.argtypes = [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p,
+                                         c_int32, c_int32, c_void_p, c_void_p]
+    lib.dcgs2_guess_targets.argtypes = [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p,
+                                        c_void_p]
+    lib.dcgs2_guess_prolong.argtypes = lib.dcgs2_guess_targets.argtypes
+    lib.dcgs2_guess_guard.argtypes = [c_void_p, POINTER(Op), c_void_p, c_void_p, c_double,
+                                      c_i32p, POINTER(c_double)]
+    for name in EXPORTS:
+        if name != "dcgs2_status_str":
+            getattr(lib, name).restype = c_int
     _lib = lib
     return lib
 
@@ -160,6 +180,104 @@ def _vec_ptr(t, name, m=None):
 def _f64():
     import torch
     return torch.float64
+
+
+def _ptr(t, dtype):
+    """Device pointer of a contiguous CUDA tensor of the given dtype."""
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous CUDA tensor of {dtype}")
+    return t.data_ptr()
+
+
+class MLP:
+    """FP32 perceptron on the device (dcgs2_mlp_*): widths[0] -> ... -> widths[-1]."""
+
+    def __init__(self, ctx: "Context", widths, max_batch: int):
+        self._lib = ctx._lib
+        self.widths = [int(w) for w in widths]
+        self.max_batch = int(max_batch)
+        arr = (c_int32 * len(self.widths))(*self.widths)
+        h = c_void_p()
+        rc = self._lib.dcgs2_mlp_create(ctx._h, len(self.widths) - 1, arr, self.max_batch,
+                                        ctypes.byref(h))
+        if rc != OK:
+            raise DCGS2Error(rc, "dcgs2_mlp_create")
+        self._h = h
+        n = c_int64()
+        self._lib.dcgs2_mlp_num_params(h, ctypes.byref(n))
+        self.num_params = n.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.dcgs2_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pack(self, layers):
+        """[(W (K x N), b (N,)), ...] -> flat float32 parameter vector."""
+        return np.concatenate([np.concatenate([np.asarray(W, np.float32).ravel(),
+                                               np.asarray(b, np.float32).ravel()])
+                               for W, b in layers])
+
+    def unpack(self, flat):
+        out, o = [], 0
+        for K, N in zip(self.widths[:-1], self.widths[1:]):
+            W = flat[o:o + K * N].reshape(K, N)
+            o += K * N
+            out.append((W, flat[o:o + N]))
+            o += N
+        return out
+
+    def set_params(self, flat):
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        if flat.size != self.num_params:
+            raise ValueError("parameter count")
+        rc = self._lib.dcgs2_mlp_set_params(self._h, flat.ctypes.data_as(c_void_p))
+        if rc != OK:
+            raise DCGS2Error(rc, "dcgs2_mlp_set_params")
+
+    def get_params(self):
+        out = np.empty(self.num_params, dtype=np.float32)
+        rc = self._lib.dcgs2_mlp_get_params(self._h, out.ctypes.data_as(c_void_p))
+        if rc != OK:
+            raise DCGS2Error(rc, "dcgs2_mlp_get_params")
+        return out
+
+    def get_grads(self):
+        out = np.empty(self.num_params, dtype=np.float32)
+        rc = self._lib.dcgs2_mlp_get_grads(self._h, out.ctypes.data_as(c_void_p))
+        if rc != OK:
+            raise DCGS2Error(rc, "dcgs2_mlp_get_grads")
+        return out
+
+    def forward(self, X, out=None):
+        import torch
+        Y = out if out is not None else torch.empty((X.shape[0], self.widths[-1]),
+                                                    dtype=torch.float32, device=X.device)
+        rc = self._lib.dcgs2_mlp_forward(self._h, X.shape[0], _ptr(X, torch.float32),
+                                         _ptr(Y, torch.float32))
+        if rc != OK:
+            raise DCGS2Error(rc, "dcgs2_mlp_forward")
+        return Y
+
+    def loss_grad(self, X, T) -> float:
+        import torch
+        loss = c_double()
+        rc = self._lib.dcgs2_mlp_loss_grad(self._h, X.shape[0], _ptr(X, torch.float32),
+                                           _ptr(T, torch.float32), ctypes.byref(loss))
+        if rc != OK:
+            raise DCGS2Error(rc, "dcgs2_mlp_loss_grad")
+        return loss.value
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        rc = self._lib.dcgs2_mlp_adam(self._h, lr, beta1, beta2, eps)
+        if rc != OK:
+            raise DCGS2Error(rc, "dcgs2_mlp_adam")
 
 
 # ---- operators --------------------------------------------------------------------
@@ -363,6 +481,54 @@ class Context:
             d["stats"] = inf.st.as_dict()
             out.append(d)
         return re + 1j * im, rc, out
+
+    # ---- learned initial guess ------------------------------------------------------
+    def guess_features(self, b, prm, n: int, nc: int, fdim: int):
+        """b: CUDA float64 (count, n*n); prm: CUDA float32 (count, np).
+        Returns (feat float32 (count, fdim), scale float64 (count,))."""
+        import torch
+        count = b.shape[0]
+        np_ = prm.shape[1] if prm is not None else 0
+        feat = torch.empty((count, fdim), dtype=torch.float32, device=b.device)
+        scale = torch.empty(count, dtype=torch.float64, device=b.device)
+        rc = self._lib.dcgs2_guess_features(self._h, count, n, nc, _ptr(b, torch.float64),
+                                            _ptr(prm, torch.float32) if np_ else None, np_,
+                                            fdim, feat.data_ptr(), scale.data_ptr())
+        if rc != OK:
+            raise DCGS2Error(rc, "dcgs2_guess_features")
+        return feat, scale
+
+    def guess_targets(self, x, scale, n: int, nc: int):
+        import torch
+        count = x.shape[0]
+        t = torch.empty((count, nc * nc), dtype=torch.float32, device=x.device)
+        rc = self._lib.dcgs2_guess_targets(self._h, count, n, nc, _ptr(x, torch.float64),
+                                           _ptr(scale, torch.float64), t.data_ptr())
+        if rc != OK:
+            raise DCGS2Error(rc, "dcgs2_guess_targets")
+        return t
+
+    def guess_prolong(self, y, scale, n: int, nc: int, out=None):
+        import torch
+        count = y.shape[0]
+        x0 = out if out is not None else torch.empty((count, n * n), dtype=torch.float64,
+                                                     device=y.device)
+        rc = self._lib.dcgs2_guess_prolong(self._h, count, n, nc, _ptr(y, torch.float32),
+                                           _ptr(scale, torch.float64), _ptr(x0, torch.float64))
+        if rc != OK:
+            raise DCGS2Error(rc, "dcgs2_guess_prolong")
+        return x0
+
+    def guess_guard(self, op: Op, b, x0, max_ratio=10.0):
+        """Zero-guess fallback; returns (kept, ||b - A x0|| / ||b||)."""
+        kept = c_int32()
+        ratio = c_double()
+        rc = self._lib.dcgs2_guess_guard(self._h, ctypes.byref(op), _vec_ptr(b, "b", op.m),
+                                         _vec_ptr(x0, "x0", op.m), max_ratio,
+                                         ctypes.byref(kept), ctypes.byref(ratio))
+        if rc != OK:
+            raise DCGS2Error(rc, "dcgs2_guess_guard")
+        return bool(kept.value), ratio.value
 
     def set_tuning(self, key: int, value: int):
         rc = self._lib.dcgs2_set_tuning(self._h, int(key), int(value))

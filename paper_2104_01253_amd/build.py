@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdcgs2.so")
-SOURCES = ["kernels.hip", "batched.hip", "api.cpp", "schur.cpp"]
+SOURCES = ["kernels.hip", "batched.hip", "guess.hip", "api.cpp", "guess_api.cpp", "schur.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -427,6 +427,14 @@ int copy_to_host(dcgs2_ctx c, const double* dev, int ldd, int rows, int cols, do
 
 }  // namespace
 
+int dcgs2::ctx_prepare(dcgs2_ctx c, hipStream_t* stream) {
+  if (!c) return DCGS2_EINVAL;
+  const int rc = ctx_ready(c);
+  if (rc) return rc;
+  *stream = c->stream;
+  return DCGS2_OK;
+}
+
 // =====================================================================================
 extern "C" {
 
@@ -852,6 +860,38 @@ int krylov_schur_eigs(dcgs2_ctx c, const dcgs2_op* A, int32_t nev, int32_t ncv, 
 }
 
 }  // extern "C"
+
+extern "C" int dcgs2_guess_guard(dcgs2_ctx c, const dcgs2_op* A, const double* b, double* x0,
+                                 double max_ratio, int32_t* kept, double* ratio) {
+  if (!c || !valid_op(A) || !b || !x0 || !kept || !(max_ratio > 0.0)) return DCGS2_EINVAL;
+  int rc;
+  if ((rc = ctx_ready(c))) return rc;
+  const int64_t m = A->m;
+  if ((rc = ensure_vectors(c, m))) return rc;
+  Expansion e;
+  e.qr = false;
+  e.m = m;
+  e.op = to_dev(A);
+  Ctrl s{};
+  // ||b||^2, then ||b - A x0||^2 (r into w)
+  if ((rc = setup_expansion(c, e, 0.0))) return rc;
+  CKL(launch_reduce(nullptr, 0, m, 0, b, nullptr, m, e.gr, e.fin(FIN_NORM, 0, 0), c->stream));
+  if ((rc = read_ctrl(c, &s))) return rc;
+  const double bn2 = s.norm2;
+  if ((rc = setup_expansion(c, e, 0.0))) return rc;
+  CKL(launch_spmv(e.op, x0, b, c->w, nullptr, c->stream));
+  CKL(launch_reduce(nullptr, 0, m, 0, c->w, nullptr, m, e.gr, e.fin(FIN_NORM, 0, 0), c->stream));
+  if ((rc = read_ctrl(c, &s))) return rc;
+  const double rn2 = s.norm2;
+  const double q = bn2 > 0.0 ? std::sqrt(rn2 / bn2) : INFINITY;
+  if (ratio) *ratio = q;
+  *kept = (std::isfinite(q) && q < max_ratio) ? 1 : 0;
+  if (!*kept) {
+    CKL(launch_fill(x0, m, 0.0, c->stream));
+    CK(hipStreamSynchronize(c->stream));
+  }
+  return DCGS2_OK;
+}
 
 // =====================================================================================
 // Batched Krylov-Schur: every expansion step is one launch of each batched kernel

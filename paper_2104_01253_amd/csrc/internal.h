@@ -166,6 +166,28 @@ hipError_t launch_btruncate(const BInst* tab, const int* pre_rows, int count, in
 hipError_t launch_breset(const BInst* tab, int count, double tau, double eta, hipStream_t s);
 constexpr int BATCH_ROWS_PER_BLOCK = 512;  // rows per workgroup of the row-parallel kernels
 
+// Learned initial guess (guess.hip): FP32 MFMA products, loss, Adam, grid transfers.
+enum GemmEpilogue : int { GEMM_PLAIN = 0, GEMM_BIAS = 1, GEMM_BIAS_RELU = 2, GEMM_MASK = 3 };
+hipError_t launch_gemm_f32(int ta, int tb, int epi, int M, int N, int K, const float* A, int lda,
+                           const float* B, int ldb, float* C, int ldc, const float* bias,
+                           const float* mask, hipStream_t s);
+hipError_t launch_colsum(int rows, int cols, const float* dZ, int ld, float* out, hipStream_t s);
+int mse_parts(int64_t count);
+hipError_t launch_mse(int64_t count, const float* Y, const float* T, float* dY, double* part,
+                      double* loss, hipStream_t s);
+hipError_t launch_adam(int64_t n, float* theta, const float* g, float* m, float* v, float lr,
+                       float b1, float b2, float eps, float c1, float c2, hipStream_t s);
+hipError_t launch_features(int count, int n, int nc, const double* b, const float* prm, int np,
+                           int fdim, float* feat, double* scale, hipStream_t s);
+hipError_t launch_targets(int count, int n, int nc, const double* x, const double* scale,
+                          float* t, hipStream_t s);
+hipError_t launch_prolong(int count, int n, int nc, const float* y, const double* scale,
+                          double* x0, hipStream_t s);
+
+// Context access for the other host sources of the library: makes the context's
+// device current (allocating its workspace on first use) and returns its stream.
+int ctx_prepare(dcgs2_ctx c, hipStream_t* stream);
+
 // Grid sizing for the reductions (number of workgroups for m rows).
 void reduce_grid(int64_t m, int gmax, int* G, int* GS, int* NG);
 constexpr int REDUCE_GMAX = 1024;

@@ -1,0 +1,208 @@
+"""Learned initial guess for GMRES on the variable-coefficient convection-diffusion
+family: data generation, training and inference on the device.
+
+    python -m paper_2104_01253_amd.guess train --count 4096 --out <weights.npz>
+
+Pipeline for one instance (every numeric step is a libdcgs2 kernel; this module
+marshals arguments, assembles the operator's CSR arrays and batches samples):
+
+  features  f = [R(b)/s, xi, v/10, 0...]       (dcgs2_guess_features)
+  network   y = MLP(f)                          (dcgs2_mlp_forward, FP32 matrix cores)
+  guess     x0 = s P(y)                         (dcgs2_guess_prolong)
+  fallback  x0 = 0 unless ||b - A x0|| < 10 ||b||   (dcgs2_guess_guard)
+
+Training data are GMRES(50) solutions of seeded instances of the family
+(solved by this library); the targets are R(x)/s, the loss the mean squared
+error, the optimiser Adam.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import time
+
+import numpy as np
+
+from . import binding, synth
+
+N, NC = 256, 32
+NPARAM = len(synth.KL_MODES) + 2            # xi and the two velocity components
+FDIM = NC * NC + 16                         # features padded to a multiple of 16
+WIDTHS = (FDIM, 512, 512, NC * NC)
+DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data",
+                               "guess_mlp_256.npz")
+
+
+# ---- operator of the family -----------------------------------------------------------
+def diffusion(prob, x, y):
+    """D(x, y) = exp(sum_k xi_k a_k phi_k(x, y)) with the family's KL modes."""
+    s = np.zeros(np.broadcast(x, y).shape)
+    for (p, q), xi in zip(synth.KL_MODES, prob.xi):
+        s = s + xi / (p * p + q * q) * 2.0 * np.sin(p * np.pi * x) * np.sin(q * np.pi * y)
+    return np.exp(s)
+
+
+def varcoef_csr(prob):
+    """CSR arrays (rowptr int32, colind int32, val float64) of -div(D grad u) + v.grad u:
+    face-centred diffusion, central convection, Dirichlet, x fastest, columns sorted."""
+    n = prob.n
+    h = 1.0 / (n + 1)
+    t = np.arange(1, n + 1) * h
+    X, Y = np.meshgrid(t, t, indexing="xy")           # [iy, ix]
+    De = diffusion(prob, X + h / 2, Y)
+    Dw = diffusion(prob, X - h / 2, Y)
+    Dn = diffusion(prob, X, Y + h / 2)
+    Ds = diffusion(prob, X, Y - h / 2)
+    vx, vy = prob.vel
+    ih2 = 1.0 / (h * h)
+    cx = vx / (2.0 * h)
+    cy = vy / (2.0 * h)
+    # neighbour order by column index: south, west, centre, east, north
+    vals = np.stack([-Ds * ih2 - cy, -Dw * ih2 - cx, (De + Dw + Dn + Ds) * ih2,
+                     -De * ih2 + cx, -Dn * ih2 + cy], axis=-1)        # [iy, ix, 5]
+    iy, ix = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    r = iy * n + ix
+    cols = np.stack([r - n, r - 1, r, r + 1, r + n], axis=-1)
+    ok = np.stack([iy > 0, ix > 0, np.ones_like(ix, bool), ix < n - 1, iy < n - 1], axis=-1)
+    counts = ok.reshape(-1, 5).sum(axis=1)
+    rowptr = np.zeros(n * n + 1, dtype=np.int32)
+    rowptr[1:] = np.cumsum(counts)
+    return rowptr, cols.reshape(-1, 5)[ok.reshape(-1, 5)].astype(np.int32), \
+        vals.reshape(-1, 5)[ok.reshape(-1, 5)].astype(np.float64)
+
+
+def params_of(prob) -> np.ndarray:
+    return np.array(list(prob.xi) + [prob.vel[0] / 10.0, prob.vel[1] / 10.0], dtype=np.float32)
+
+
+class DeviceOp:
+    """CSR operator of one instance on the device (keeps its tensors alive)."""
+
+    def __init__(self, prob, device="cuda"):
+        import torch
+        rp, ci, va = varcoef_csr(prob)
+        self.rowptr = torch.from_numpy(rp).to(device)
+        self.colind = torch.from_numpy(ci).to(device)
+        self.val = torch.from_numpy(va).to(device)
+        self.op = binding.csr_op(self.rowptr, self.colind, self.val)
+
+
+# ---- model ----------------------------------------------------------------------------
+def he_init(widths, seed):
+    g = synth.rng(seed)
+    return [(g.standard_normal((a, b)) * np.sqrt(2.0 / a), np.zeros(b))
+            for a, b in zip(widths[:-1], widths[1:])]
+
+
+class GuessModel:
+    def __init__(self, ctx: binding.Context, max_batch=256, widths=WIDTHS, seed=0):
+        self.ctx = ctx
+        self.mlp = binding.MLP(ctx, widths, max_batch)
+        self.mlp.set_params(self.mlp.pack(he_init(widths, seed)))
+
+    def predict(self, b, prm):
+        """b: CUDA float64 (count, N*N); prm: CUDA float32 (count, NPARAM) -> x0 (count, N*N)."""
+        feat, scale = self.ctx.guess_features(b, prm, N, NC, FDIM)
+        y = self.mlp.forward(feat)
+        return self.ctx.guess_prolong(y, scale, N, NC)
+
+    def save(self, path, **meta):
+        os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+        np.savez(path, params=self.mlp.get_params(), widths=np.array(self.mlp.widths),
+                 **{k: np.asarray(v) for k, v in meta.items()})
+
+    def load(self, path):
+        with np.load(path, allow_pickle=False) as z:
+            if tuple(int(w) for w in z["widths"]) != tuple(self.mlp.widths):
+                raise ValueError("weights file has other layer widths")
+            self.mlp.set_params(z["params"])
+
+
+# ---- data and training ------------------------------------------------------------------
+def solve(ctx, prob, b_dev, x0=None, rtol=1e-8, restart=50, max_iters=20000):
+    """GMRES(restart) on one instance; returns (x, rc, info, seconds)."""
+    import torch
+    dop = DeviceOp(prob, b_dev.device)
+    x = torch.zeros_like(b_dev) if x0 is None else x0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, info = ctx.gmres(dop.op, b_dev, x, restart=restart, rtol=rtol, max_iters=max_iters)
+    return x, rc, info, time.perf_counter() - t0
+
+
+def generate(ctx, count, seed, rtol=1e-6, log=None):
+    """Features and targets of `count` solved instances (device tensors)."""
+    import torch
+    probs = synth.varcoef_instances(count, seed=seed, n=N)
+    feats = torch.empty((count, FDIM), dtype=torch.float32, device="cuda")
+    targs = torch.empty((count, NC * NC), dtype=torch.float32, device="cuda")
+    for i, p in enumerate(probs):
+        b = torch.from_numpy(synth.varcoef_rhs(p)).cuda()
+        prm = torch.from_numpy(params_of(p)).cuda()
+        x, rc, info, _ = solve(ctx, p, b, rtol=rtol)
+        if rc != binding.OK:
+            raise RuntimeError(f"training solve {i} did not converge: {info}")
+        f, s = ctx.guess_features(b[None], prm[None], N, NC, FDIM)
+        feats[i] = f[0]
+        targs[i] = ctx.guess_targets(x[None], s, N, NC)[0]
+        if log and (i + 1) % 256 == 0:
+            log(f"generated {i + 1}/{count} (last: {info['iters']} iterations)")
+    return feats, targs
+
+
+def train(model, feats, targs, epochs=60, batch=256, lr=1e-3, seed=0, log=None):
+    import torch
+    g = synth.rng(seed)
+    count = feats.shape[0]
+    hist = []
+    for ep in range(epochs):
+        perm = torch.from_numpy(g.permutation(count)).cuda()
+        tot, nb = 0.0, 0
+        for s in range(0, count - batch + 1, batch):
+            idx = perm[s:s + batch]
+            X = feats.index_select(0, idx).contiguous()
+            T = targs.index_select(0, idx).contiguous()
+            tot += model.mlp.loss_grad(X, T)
+            model.mlp.adam(lr)
+            nb += 1
+        hist.append(tot / max(nb, 1))
+        if log and (ep % 10 == 9 or ep == epochs - 1):
+            log(f"epoch {ep + 1}: train mse {hist[-1]:.4e}")
+    return hist
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--count", type=int, default=4096)
+    t.add_argument("--val", type=int, default=256)
+    t.add_argument("--epochs", type=int, default=60)
+    t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--seed", type=int, default=100)
+    t.add_argument("--out", default=DEFAULT_WEIGHTS)
+    a = ap.parse_args(argv)
+    import torch
+    torch.cuda.set_device(0)
+
+    def log(msg):
+        print(msg, flush=True)
+
+    ctx = binding.Context(0)
+    model = GuessModel(ctx)
+    t0 = time.perf_counter()
+    feats, targs = generate(ctx, a.count, a.seed, log=log)
+    vf, vt = generate(ctx, a.val, a.seed + 1, log=log)
+    log(f"data: {time.perf_counter() - t0:.1f} s")
+    hist = train(model, feats, targs, a.epochs, lr=a.lr, log=log)
+    y = model.mlp.forward(vf)
+    val = float(((y - vt) ** 2).mean())
+    rel = float(((y - vt) ** 2).sum().sqrt() / (vt ** 2).sum().sqrt())
+    log(f"validation mse {val:.4e}, relative error {rel:.4f}")
+    model.save(a.out, train_mse=hist[-1], val_mse=val, val_rel=rel, count=a.count,
+               seed=a.seed, epochs=a.epochs)
+    log(f"saved {a.out}")
+
+
+if __name__ == "__main__":
+    main()

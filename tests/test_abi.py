@@ -4,6 +4,8 @@ import ctypes
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 from paper_2104_01253_amd import binding
@@ -109,3 +111,38 @@ def test_stencil_coefficients_match_definition():
     assert c0 == pytest.approx(4 / h**2)
     assert lo[0] == pytest.approx(-1 / h**2 - 10 / (2 * h))
     assert hi[1] == pytest.approx(-1 / h**2 + 10 / (2 * h))
+
+
+def test_guess_argument_validation(ctx):
+    lib, h = ctx
+    E = binding.EINVAL
+    out = ctypes.c_void_p()
+    w = (ctypes.c_int32 * 3)(8, 0, 4)
+    assert lib.dcgs2_mlp_create(h, 2, w, 16, ctypes.byref(out)) == E            # width 0
+    w = (ctypes.c_int32 * 3)(8, 5, 4)
+    assert lib.dcgs2_mlp_create(h, 2, w, 0, ctypes.byref(out)) == E             # max_batch
+    assert lib.dcgs2_mlp_create(None, 2, w, 16, ctypes.byref(out)) == E
+    assert lib.dcgs2_mlp_create(h, 0, w, 16, ctypes.byref(out)) == E            # no layer
+    assert lib.dcgs2_mlp_forward(None, 1, FAKE, FAKE) == E
+    assert lib.dcgs2_mlp_adam(None, 1e-3, 0.9, 0.999, 1e-8) == E
+    assert lib.dcgs2_guess_features(h, 1, 30, 4, FAKE, FAKE, 2, 18, FAKE, FAKE) == E   # 30 % 4
+    assert lib.dcgs2_guess_features(h, 1, 32, 4, FAKE, FAKE, 2, 17, FAKE, FAKE) == E   # fdim
+    assert lib.dcgs2_guess_targets(h, 0, 32, 4, FAKE, FAKE, FAKE) == E                 # count
+    assert lib.dcgs2_guess_prolong(h, 1, 32, 1, FAKE, FAKE, FAKE) == E                 # nc < 2
+    op = binding.stencil_op((8, 8), 1.0, (1.0, 1.0))
+    kept = ctypes.c_int32()
+    assert lib.dcgs2_guess_guard(h, ctypes.byref(op), FAKE, FAKE, 0.0, ctypes.byref(kept),
+                                 None) == E                                       # max_ratio
+
+
+def test_varcoef_csr_matches_the_oracle_assembly():
+    import scipy.sparse as sp
+    from oracle.operators import varcoef_matrix
+    from paper_2104_01253_amd import guess, synth
+    for seed, n in [(3, 24), (4, 17)]:
+        p = synth.varcoef_instances(1, n=n, seed=seed, vel=(10.0, -4.0))[0]
+        rp, ci, va = guess.varcoef_csr(p)
+        A = sp.csr_matrix((va, ci, rp), shape=(p.m, p.m))
+        B = varcoef_matrix(p)
+        assert abs(A - B).max() <= 1e-15 * abs(B).max()
+        assert np.all(np.diff(ci.reshape(-1)[rp[0]:rp[1]]) > 0)

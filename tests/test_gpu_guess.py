@@ -1,0 +1,161 @@
+"""Learned initial guess on the GPU against the oracle (oracle.guess): the
+perceptron's forward pass, loss, gradients and Adam step (FP32 matrix-core
+products vs FP64), the grid transfers and features, and the zero-guess guard.
+
+Tolerances: FP32 products over K terms carry relative errors of order
+sqrt(K) * 6e-8; 2e-5 of the largest magnitude covers K <= 1040 with margin."""
+import numpy as np
+import pytest
+
+from oracle import guess as G
+from paper_2104_01253_amd import binding, guess, synth
+from tests._gpu import say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch_cuda()
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def _layers(widths, seed):
+    g = np.random.default_rng(seed)
+    return [((g.standard_normal((a, b)) * np.sqrt(2.0 / a)).astype(np.float32),
+             (0.1 * g.standard_normal(b)).astype(np.float32))
+            for a, b in zip(widths[:-1], widths[1:])]
+
+
+def _as64(layers):
+    return [(W.astype(np.float64), b.astype(np.float64)) for W, b in layers]
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(np.asarray(a, np.float64) - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+# ragged widths and batch (several 64 x 64 tiles plus partial ones) and the model's own
+CASES = [((37, 70, 45, 19), 83, 1), ((5, 3), 1, 2), (guess.WIDTHS, 256, 3), ((130, 64, 200), 129, 4)]
+
+
+@pytest.mark.parametrize("widths,batch,seed", CASES)
+def test_mlp_forward_loss_and_gradients(ctx, widths, batch, seed):
+    import torch
+    say("mlp", widths, batch)
+    layers = _layers(widths, seed)
+    g = np.random.default_rng(seed + 10)
+    X = g.standard_normal((batch, widths[0])).astype(np.float32)
+    T = g.standard_normal((batch, widths[-1])).astype(np.float32)
+    mlp = binding.MLP(ctx, widths, max_batch=max(batch, 8))
+    mlp.set_params(mlp.pack(layers))
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    Y = mlp.forward(Xd).cpu().numpy()
+    _, Yref = G.forward(_as64(layers), X.astype(np.float64))
+    assert _rel(Y, Yref) <= 2e-5
+    loss = mlp.loss_grad(Xd, Td)
+    lref, gref = G.gradients(_as64(layers), X.astype(np.float64), T.astype(np.float64))
+    assert abs(loss - lref) <= 2e-5 * lref
+    grads = mlp.unpack(mlp.get_grads())
+    for (dW, db), (rW, rb) in zip(grads, gref):
+        assert _rel(dW, rW) <= 2e-5 and _rel(db, rb) <= 2e-5
+    mlp.close()
+
+
+def test_adam_step_matches_oracle(ctx):
+    import torch
+    widths, batch = (37, 70, 45, 19), 83
+    layers = _layers(widths, 7)
+    g = np.random.default_rng(8)
+    X = g.standard_normal((batch, widths[0])).astype(np.float32)
+    T = g.standard_normal((batch, widths[-1])).astype(np.float32)
+    mlp = binding.MLP(ctx, widths, max_batch=batch)
+    mlp.set_params(mlp.pack(layers))
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    theta = _as64(layers)
+    flat = lambda ls: np.concatenate([np.concatenate([W.ravel(), b]) for W, b in ls])
+    opt = G.Adam([a.shape for pair in theta for a in pair], lr=1e-3)
+    for step in range(3):
+        mlp.loss_grad(Xd, Td)
+        mlp.adam(1e-3)
+        _, gr = G.gradients(theta, X.astype(np.float64), T.astype(np.float64))
+        new = opt.step([a for pair in theta for a in pair], [a for pair in gr for a in pair])
+        theta = [(new[2 * i], new[2 * i + 1]) for i in range(len(theta))]
+        got, want = mlp.get_params().astype(np.float64), flat(theta)
+        gmag = np.abs(flat(gr))
+        # where the gradient is well above FP32 noise the step is +-lr to a few ulps;
+        # elsewhere the sign of a noise-level gradient may differ (step within 2 lr)
+        big = gmag > 0.05 * gmag.max()
+        assert np.max(np.abs(got - want)[big]) <= 1e-6
+        assert np.max(np.abs(got - want)) <= 2e-3 * (step + 1) + 1e-6
+        say("adam step", step, "max diff (big)", np.max(np.abs(got - want)[big]))
+    mlp.close()
+
+
+@pytest.mark.parametrize("n,nc", [(256, 32), (16, 4), (30, 5), (27, 3)])
+def test_features_targets_and_prolongation(ctx, n, nc):
+    import torch
+    say("transfers", n, nc)
+    g = np.random.default_rng(n + nc)
+    count, npar, fdim = 3, 10, nc * nc + 13
+    b = g.standard_normal((count, n * n))
+    b[1] = 0.0                                        # a zero right-hand side: s = 0
+    prm = g.standard_normal((count, npar)).astype(np.float32)
+    x = g.standard_normal((count, n * n))
+    feat, scale = ctx.guess_features(torch.from_numpy(b).cuda(), torch.from_numpy(prm).cuda(),
+                                     n, nc, fdim)
+    feat, scale_h = feat.cpu().numpy(), scale.cpu().numpy()
+    for i in range(count):
+        f, s = G.features(b[i], prm[i].astype(np.float64), n, nc, fdim)
+        assert abs(scale_h[i] - s) <= 1e-14 * max(s, 1e-300)
+        assert np.max(np.abs(feat[i] - f)) <= 1e-6 * max(np.max(np.abs(f)), 1.0)
+    t = ctx.guess_targets(torch.from_numpy(x).cuda(), scale, n, nc).cpu().numpy()
+    for i in range(count):
+        want = G.restrict(x[i], n, nc) / scale_h[i] if scale_h[i] > 0 else np.zeros(nc * nc)
+        assert np.max(np.abs(t[i] - want)) <= 1e-6 * max(np.max(np.abs(want)), 1.0)
+    y = g.standard_normal((count, nc * nc)).astype(np.float32)
+    sc = torch.tensor([1.0, 2.5, 0.0], dtype=torch.float64, device="cuda")
+    x0 = ctx.guess_prolong(torch.from_numpy(y).cuda(), sc, n, nc).cpu().numpy()
+    for i in range(count):
+        want = float(sc[i]) * G.prolong(y[i].astype(np.float64), n, nc)
+        assert np.max(np.abs(x0[i] - want)) <= 1e-13 * max(np.max(np.abs(want)), 1.0)
+
+
+def test_guard_keeps_a_good_guess_and_rejects_garbage(ctx):
+    import torch
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    prob = synth.varcoef_instances(1, seed=21, n=64)[0]
+    rp, ci, va = guess.varcoef_csr(prob)
+    A = sp.csr_matrix((va, ci, rp), shape=(prob.m, prob.m))
+    b = synth.varcoef_rhs(prob)
+    dop = guess.DeviceOp(prob)
+    bd = torch.from_numpy(b).cuda()
+    x = spla.spsolve(A.tocsc(), b)
+    x0 = torch.from_numpy(G.prolong(G.restrict(x, 64, 8), 64, 8)).cuda()
+    kept, ratio = ctx.guess_guard(dop.op, bd, x0, 10.0)
+    want = np.linalg.norm(b - A @ x0.cpu().numpy()) / np.linalg.norm(b)
+    say("guard good guess ratio", ratio, want)
+    assert kept and abs(ratio - want) <= 1e-12 * want
+    bad = torch.from_numpy(1e3 * np.random.default_rng(0).standard_normal(prob.m)).cuda()
+    kept, ratio = ctx.guess_guard(dop.op, bd, bad, 10.0)
+    assert not kept and ratio > 10.0 and not bool(bad.abs().max() > 0)
+
+
+def test_guess_pipeline_and_gmres_from_the_guess(ctx):
+    import torch
+    model = guess.GuessModel(ctx, max_batch=4, seed=0)
+    probs = synth.varcoef_instances(2, seed=31, n=guess.N)
+    b = torch.stack([torch.from_numpy(synth.varcoef_rhs(p)) for p in probs]).cuda()
+    prm = torch.stack([torch.from_numpy(guess.params_of(p)) for p in probs]).cuda()
+    x0 = model.predict(b, prm)
+    assert x0.shape == (2, guess.N * guess.N) and bool(torch.isfinite(x0).all())
+    dop = guess.DeviceOp(probs[0])
+    xg = x0[0].contiguous()
+    ctx.guess_guard(dop.op, b[0].contiguous(), xg, 10.0)
+    x, rc, info, secs = guess.solve(ctx, probs[0], b[0].contiguous(), x0=xg, rtol=1e-6)
+    say("gmres from an untrained guess", info, f"{secs:.3f}s")
+    assert rc == binding.OK and info["relres_true"] <= 1e-6
+    model.mlp.close()
