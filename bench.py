@@ -111,7 +111,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the row-partitioned design is described in DESIGN.md); run with --gpus 1",
+              "(the path would shard by row blocks with one small all-reduce per step); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 
@@ -196,7 +196,7 @@ def main():
     torch.cuda.empty_cache()
 
     if not args.no_legs:
-        prob, b = synth.config3(128)
+        prob, b = synth.gmres_cd3d(128)
         op = binding.stencil_op(prob.grid, prob.D, prob.vel)
         bd = torch.from_numpy(b).cuda()
         Qa = binding.colmajor_empty(prob.m, n + 1)

@@ -181,7 +181,7 @@ __global__ void scale_col_kernel(TQ* Q, int64_t ldq, int J, const double* ubuf, 
 }
 
 // ---------------------------------------------------------------------------------
-// Matvec of step a1.  Stencils: one row per thread, neighbours summed in column
+// Matvec of each Arnoldi step.  Stencils: one row per thread, neighbours summed in column
 // order; out-of-grid neighbours are zero (Dirichlet).
 __global__ __launch_bounds__(BS) void stencil_kernel(OpDev op, const double* __restrict__ x,
                                                      const double* __restrict__ b,

@@ -48,7 +48,7 @@ def run(workload: str, reps: int):
             _, rc, _ = ctx.qr(B, Q)
             assert rc == 0
     elif workload == "arnoldi":
-        prob, b = synth.config3(128)
+        prob, b = synth.gmres_cd3d(128)
         op = binding.stencil_op(prob.grid, prob.D, prob.vel)
         bd = torch.from_numpy(b).cuda()
         Q = binding.colmajor_empty(prob.m, 101)
@@ -56,7 +56,7 @@ def run(workload: str, reps: int):
             _, rc, _ = ctx.arnoldi(op, bd, 100, Q)
             assert rc == 0
     elif workload == "gmres":
-        prob, b = synth.config3(128)
+        prob, b = synth.gmres_cd3d(128)
         op = binding.stencil_op(prob.grid, prob.D, prob.vel)
         bd = torch.from_numpy(b).cuda()
         x = torch.zeros(prob.m, dtype=torch.float64, device="cuda")

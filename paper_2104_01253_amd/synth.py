@@ -80,13 +80,13 @@ def ks_instances(count: int, seed: int = 4, nmin: int = 48, nmax: int = 256, vma
 
 
 # Named workloads ------------------------------------------------------------------
-def config1():
+def arnoldi_cd2d_32():
     """FP64 DCGS2 Arnoldi, 50 steps, 2-D convection-diffusion 32x32, v=(10,10), r0 ~ N(0,1) seed 0."""
     prob = cd2d(32, vel=(10.0, 10.0))
     return prob, normal_vector(prob.m, 0), 50
 
 
-def config3(n: int = 128):
+def gmres_cd3d(n: int = 128):
     """GMRES(50) on 3-D convection-diffusion n^3, v=(10,10,10), b ~ U(0,1) seed 3, rtol 1e-8."""
     prob = cd3d(n, vel=(10.0, 10.0, 10.0))
     return prob, uniform_vector(prob.m, 3)

@@ -59,7 +59,7 @@ def test_csr_matvec_parity(ctx):
 def test_config1_parity():
     """2-D convection-diffusion 32x32, v=(10,10), 50 steps, r0 ~ N(0,1) seed 0."""
     torch_cuda()
-    prob, r0, n = synth.config1()
+    prob, r0, n = synth.arnoldi_cd2d_32()
     A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
     with binding.Context(0) as c:
         Q, H, rc, st = run_arnoldi(c, binding.stencil_op(prob.grid, prob.D, prob.vel), r0, n)
@@ -101,7 +101,7 @@ def test_arnoldi_csr_operator_and_odd_ld(ctx):
 
 
 def test_arnoldi_forced_fallback(ctx):
-    prob, r0, _ = synth.config1()
+    prob, r0, _ = synth.arnoldi_cd2d_32()
     A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
     ctx.set_tolerances(1.0, 1e-12)
     try:
@@ -132,7 +132,7 @@ def test_arnoldi_breakdown_invariant_subspace(ctx):
 
 
 def test_arnoldi_nonfinite(ctx):
-    prob, r0, _ = synth.config1()
+    prob, r0, _ = synth.arnoldi_cd2d_32()
     r0 = r0.copy()
     r0[7] = np.nan
     _, _, rc, st = run_arnoldi(ctx, binding.stencil_op(prob.grid, prob.D, prob.vel), r0, 5)
@@ -150,7 +150,7 @@ def test_arnoldi_deterministic(ctx):
 
 def test_arnoldi_full_size_128cube(ctx):
     """The Arnoldi workload at full size: 3-D 128^3 (m = 2,097,152), n = 100 steps."""
-    prob, b = synth.config3(128)
+    prob, b = synth.gmres_cd3d(128)
     A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
     n = 100
     say("gpu arnoldi 128^3 n=100")

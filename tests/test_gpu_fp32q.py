@@ -59,7 +59,7 @@ def test_qr_q32_parity(ctx, m, n, ce, one_pass):
 
 def test_arnoldi_q32_parity(ctx):
     torch = torch_cuda()
-    prob, r0, n = synth.config1()
+    prob, r0, n = synth.arnoldi_cd2d_32()
     A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
     Q = binding.colmajor_empty(prob.m, n + 1, dtype=torch.float32)
     H, rc, st = ctx.arnoldi(binding.stencil_op(prob.grid, prob.D, prob.vel), dev_vector(r0), n, Q)
@@ -77,7 +77,7 @@ def test_arnoldi_q32_parity(ctx):
 
 def test_gmres_q32(ctx):
     torch = torch_cuda()
-    prob, b = synth.config3(32)
+    prob, b = synth.gmres_cd3d(32)
     A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
     op = binding.stencil_op(prob.grid, prob.D, prob.vel)
     x = torch.zeros(prob.m, dtype=torch.float64, device="cuda")

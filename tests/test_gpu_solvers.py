@@ -37,7 +37,7 @@ def ctx():
 @pytest.mark.parametrize("n,restart", [(16, 50), (32, 50), (24, 7)])
 def test_gmres_vs_oracle(ctx, n, restart):
     torch = torch_cuda()
-    prob, b = synth.config3(n)
+    prob, b = synth.gmres_cd3d(n)
     A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
     op = binding.stencil_op(prob.grid, prob.D, prob.vel)
     x = torch.zeros(prob.m, dtype=torch.float64, device="cuda")
@@ -57,7 +57,7 @@ def test_gmres_vs_oracle(ctx, n, restart):
 
 def test_gmres_zero_rhs_warm_start_and_budget(ctx):
     torch = torch_cuda()
-    prob, b = synth.config3(12)
+    prob, b = synth.gmres_cd3d(12)
     A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
     op = binding.stencil_op(prob.grid, prob.D, prob.vel)
     x = torch.full((prob.m,), 3.0, dtype=torch.float64, device="cuda")
@@ -75,7 +75,7 @@ def test_gmres_zero_rhs_warm_start_and_budget(ctx):
 def test_gmres_full_size_128cube(ctx):
     """GMRES(50) to 1e-8 on 3-D 128^3 (m = 2,097,152), v = (10,10,10), b ~ U(0,1)."""
     torch = torch_cuda()
-    prob, b = synth.config3(128)
+    prob, b = synth.gmres_cd3d(128)
     A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
     op = binding.stencil_op(prob.grid, prob.D, prob.vel)
     x = torch.zeros(prob.m, dtype=torch.float64, device="cuda")

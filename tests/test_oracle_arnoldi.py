@@ -94,7 +94,7 @@ def test_dcgs2_arnoldi_tiny_against_50_digit():
 
 
 def test_config1_dcgs2_vs_cgs2_mgs():
-    prob, r0, n = synth.config1()
+    prob, r0, n = synth.arnoldi_cd2d_32()
     A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
     mv = lambda x: A @ x
     d = ar.dcgs2_arnoldi(mv, r0, n)
@@ -115,7 +115,7 @@ def test_config1_dcgs2_vs_cgs2_mgs():
 
 def test_eq41_projection_identity():
     """eq. (41): A w_{j-1} = Q_{1:j-2} S + (1/alpha) q_{j-1} (sigma - C^T S) + alpha w_j."""
-    prob, r0, n = synth.config1()
+    prob, r0, n = synth.arnoldi_cd2d_32()
     A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
     arn = ar.DCGS2Arnoldi(lambda x: A @ x, r0, 20)
     arn.trace = []
@@ -132,7 +132,7 @@ def test_eq41_projection_identity():
 
 
 def test_forced_fallback_same_decomposition():
-    prob, r0, n = synth.config1()
+    prob, r0, n = synth.arnoldi_cd2d_32()
     A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
     a = ar.dcgs2_arnoldi(lambda x: A @ x, r0, 30)
     b = ar.dcgs2_arnoldi(lambda x: A @ x, r0, 30, tau=1.0)
@@ -165,7 +165,7 @@ def test_nonfinite_start():
 
 def test_krylov_schur_continuation_keeps_arnoldi_relation():
     """After a truncation-style restart, the resumed expansion keeps A Q_p = Q_{p+1} H."""
-    prob, r0, _ = synth.config1()
+    prob, r0, _ = synth.arnoldi_cd2d_32()
     A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
     mv = lambda x: A @ x
     p, k = 30, 10

@@ -32,7 +32,7 @@ def test_qr_fp32_basis_against_fp64():
 
 
 def test_arnoldi_fp32_basis_against_fp64():
-    prob, r0, n = synth.config1()
+    prob, r0, n = synth.arnoldi_cd2d_32()
     A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
     a = ar.dcgs2_arnoldi(lambda x: A @ x, r0, n)
     b = ar.dcgs2_arnoldi(lambda x: A @ x, r0, n, qdtype=np.float32)
@@ -43,7 +43,7 @@ def test_arnoldi_fp32_basis_against_fp64():
 
 
 def test_gmres_fp32_basis_same_convergence():
-    prob, bb = synth.config3(16)
+    prob, bb = synth.gmres_cd3d(16)
     A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
     x64, i64 = gmres_dcgs2(A, bb)
     x32, i32 = gmres_dcgs2(A, bb, qdtype=np.float32)

@@ -27,7 +27,7 @@ def _scipy_gmres_iters(A, b, restart, rtol):
 
 
 def test_gmres_matches_direct_solve_16cube():
-    prob, b = synth.config3(16)
+    prob, b = synth.gmres_cd3d(16)
     A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
     x, info = gmres_dcgs2(A, b, restart=50, rtol=1e-8)
     assert info["status"] == 0
@@ -41,7 +41,7 @@ def test_gmres_matches_direct_solve_16cube():
 
 
 def test_gmres_zero_rhs_and_warm_start():
-    prob, b = synth.config3(8)
+    prob, b = synth.gmres_cd3d(8)
     A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
     x, info = gmres_dcgs2(A, np.zeros_like(b), restart=10)
     assert np.all(x == 0) and info["status"] == 0 and info["iters"] == 0
@@ -51,7 +51,7 @@ def test_gmres_zero_rhs_and_warm_start():
 
 
 def test_gmres_max_iters_not_converged():
-    prob, b = synth.config3(16)
+    prob, b = synth.gmres_cd3d(16)
     A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
     x, info = gmres_dcgs2(A, b, restart=20, rtol=1e-12, max_iters=30)
     assert info["status"] == 2 and info["iters"] == 30 and info["cycles"] == 2
