@@ -474,7 +474,89 @@ __device__ void finalize(const FinArgs& f, double* red, double* T, double* scrat
 
 // ---------------------------------------------------------------------------------
 // Reduction pass: per-workgroup partial dot products of [Q_{0..J-1}, x, (y)] with
-// [x, (y)] over a contiguous slab of rows, NT basis columns at a time.
+// [x, (y)] over a contiguous slab of rows.
+//
+// The basis columns are taken in column groups of exactly NC = 16, 8, 4, 2 or 1
+// (J = 16 q + binary digits of the remainder), each group one sweep over the
+// slab, so no load in a sweep is conditional: every load of an unrolled
+// iteration is issued before the first one is waited for.  (A per-column bound
+// test inside the sweep would make each load wait for the previous one.)  A last
+// sweep forms x^T x, x^T y and y^T y.  Partial layout (V values per workgroup):
+//   [0, Jt)   = [Q, x, y]^T x,   [Jt, 2 Jt) = [Q, x, y]^T y   (HASY, Jt = J + 2)
+//   [0, Jt)   = [Q, x]^T x                                      (Jt = J + 1)
+template <int VW, bool HASY, int NC, typename TQ>
+__device__ __forceinline__ void reduce_sweep(const TQ* __restrict__ Q, int64_t ldq, int k0,
+                                             const double* __restrict__ x,
+                                             const double* __restrict__ y, int64_t u0,
+                                             int64_t u1, bool tail, int64_t m, double* shb,
+                                             double* P, int Jt) {
+  constexpr int NA = HASY ? 2 * NC : NC;
+  using RV = RowVec<VW>;
+  double acc[NA];
+#pragma unroll
+  for (int c = 0; c < NA; ++c) acc[c] = 0.0;
+  const TQ* __restrict__ qb = Q + (int64_t)k0 * ldq;
+#pragma unroll 2
+  for (int64_t u = u0 + threadIdx.x; u < u1; u += BS) {
+    const RV xv = RV::load(x, u);
+    const RV yv = HASY ? RV::load(y, u) : RV::zero();
+    RV q[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) q[c] = RV::load(qb + (int64_t)c * ldq, u);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      acc[c] += q[c].dot(xv);
+      if (HASY) acc[NC + c] += q[c].dot(yv);
+    }
+  }
+  if (tail) {                              // odd m with 2-row units: last row
+    const int64_t r = m - 1;
+    const double xr = x[r], yr = HASY ? y[r] : 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double q = (double)qb[(int64_t)c * ldq + r];
+      acc[c] += q * xr;
+      if (HASY) acc[NC + c] += q * yr;
+    }
+  }
+  block_sum_t<NA, NC>(acc, shb, P + k0, NC, P + Jt + k0, HASY ? NC : 0);
+}
+
+template <int VW, bool HASY>
+__device__ __forceinline__ void reduce_self(const double* __restrict__ x,
+                                            const double* __restrict__ y, int64_t u0, int64_t u1,
+                                            bool tail, int64_t m, double* shb, double* P, int J,
+                                            int Jt) {
+  using RV = RowVec<VW>;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};   // x.x, x.y, y.y, unused
+#pragma unroll 4
+  for (int64_t u = u0 + threadIdx.x; u < u1; u += BS) {
+    const RV xv = RV::load(x, u);
+    acc[0] += xv.dot(xv);
+    if (HASY) {
+      const RV yv = RV::load(y, u);
+      acc[1] += xv.dot(yv);
+      acc[2] += yv.dot(yv);
+    }
+  }
+  if (tail) {
+    const int64_t r = m - 1;
+    const double xr = x[r], yr = HASY ? y[r] : 0.0;
+    acc[0] += xr * xr;
+    if (HASY) { acc[1] += xr * yr; acc[2] += yr * yr; }
+  }
+  double* out = shb + NW * 4;
+  block_sum_t<4, 4>(acc, shb, out, 3, nullptr, 0);
+  if (threadIdx.x == 0) {
+    P[J] = out[0];
+    if (HASY) {
+      P[J + 1] = out[1];                     // y^T x
+      P[Jt + J] = out[1];                    // x^T y
+      P[Jt + J + 1] = out[2];
+    }
+  }
+}
+
 template <int VW, bool HASY, typename TQ>
 __device__ __forceinline__ void reduce_body(const TQ* __restrict__ Q, int64_t ldq,
                                                     int J, const double* __restrict__ x,
@@ -494,52 +576,23 @@ __device__ __forceinline__ void reduce_body(const TQ* __restrict__ Q, int64_t ld
   const int64_t u1 = min(units, u0 + per);
   const bool tail = (VW == 2) && (m & 1) && bid == gr.G - 1 && threadIdx.x == 0;
   double* P = gr.P1 + (int64_t)bid * gr.ldp;
-  using RV = RowVec<VW>;
-
-  for (int k0 = 0; k0 < Jt; k0 += NT) {
-    double acc[2 * NT];
-#pragma unroll
-    for (int c = 0; c < 2 * NT; ++c) acc[c] = 0.0;
-    // column k0 + c is basis column k (k < J), x (k == J) or y (k == J + 1)
-    const TQ* qbase = Q + (int64_t)k0 * ldq;
-#pragma unroll 2
-    for (int64_t u = u0 + threadIdx.x; u < u1; u += BS) {
-      const RV xv = RV::load(x, u);
-      const RV yv = HASY ? RV::load(y, u) : RV::zero();
-#pragma unroll
-      for (int c = 0; c < NT; ++c) {
-        if (k0 + c < Jt) {
-          const RV q = (k0 + c < J) ? RV::load(qbase + (int64_t)c * ldq, u)
-                                    : (k0 + c == J ? xv : yv);
-          acc[c] += q.dot(xv);
-          if (HASY) acc[NT + c] += q.dot(yv);
-        }
-      }
-    }
-    if (tail) {                              // odd m with 2-row units: last row
-      const int64_t r = m - 1;
-      const double xr = x[r], yr = HASY ? y[r] : 0.0;
-#pragma unroll
-      for (int c = 0; c < NT; ++c) {
-        if (k0 + c < Jt) {
-          const double q = (k0 + c < J) ? (double)qbase[(int64_t)c * ldq + r]
-                                        : (k0 + c == J ? xr : yr);
-          acc[c] += q * xr;
-          if (HASY) acc[NT + c] += q * yr;
-        }
-      }
-    }
-    const int nvalid = min(NT, Jt - k0);
-    if (HASY) {
-      // partial layout: [0,Jt) = [Q,x,y]^T x ; [Jt, 2Jt) = [Q,x,y]^T y
-      block_sum_t<2 * NT, NT>(acc, shb, P + k0, nvalid, P + Jt + k0, nvalid);
-    } else {
-      double ax[NT];
-#pragma unroll
-      for (int c = 0; c < NT; ++c) ax[c] = acc[c];
-      block_sum_t<NT, NT>(ax, shb, P + k0, nvalid, nullptr, 0);
-    }
+  int k0 = 0;
+  for (; k0 + 16 <= J; k0 += 16)
+    reduce_sweep<VW, HASY, 16, TQ>(Q, ldq, k0, x, y, u0, u1, tail, m, shb, P, Jt);
+  if (k0 + 8 <= J) {
+    reduce_sweep<VW, HASY, 8, TQ>(Q, ldq, k0, x, y, u0, u1, tail, m, shb, P, Jt);
+    k0 += 8;
   }
+  if (k0 + 4 <= J) {
+    reduce_sweep<VW, HASY, 4, TQ>(Q, ldq, k0, x, y, u0, u1, tail, m, shb, P, Jt);
+    k0 += 4;
+  }
+  if (k0 + 2 <= J) {
+    reduce_sweep<VW, HASY, 2, TQ>(Q, ldq, k0, x, y, u0, u1, tail, m, shb, P, Jt);
+    k0 += 2;
+  }
+  if (k0 + 1 <= J) reduce_sweep<VW, HASY, 1, TQ>(Q, ldq, k0, x, y, u0, u1, tail, m, shb, P, Jt);
+  reduce_self<VW, HASY>(x, y, u0, u1, tail, m, shb, P, J, Jt);
   if (grid_reduce(gr, V, red, bid)) finalize(fin, red, T, scratch);
 }
 
@@ -564,6 +617,7 @@ __device__ __forceinline__ void project_norm_body(const TQ* __restrict__ Q, int6
   double acc[1] = {0.0};
   for (int64_t u = u0 + threadIdx.x; u < u1; u += BS) {
     RV sc = RV::zero();
+#pragma unroll 8
     for (int k = 0; k < J; ++k) {
       const RV q = RV::load(Q + (int64_t)k * ldq, u);
       const double ck = C[k];

@@ -59,19 +59,20 @@ __global__ __launch_bounds__(BS) void update_kernel(TQ* __restrict__ Q, int64_t 
 // rows of q_{j-1} and w_j produced by the update can be dotted at once:
 //   q = (w - Q C)/alpha,  w' = a_j - Q T_{1:J} - q T_J          (update, step j)
 //   [Q_{0..J-1}, q, w', a_{j+1}]^T [w', a_{j+1}]                 (reduction, step j+1)
-// A workgroup of FW wavefronts walks tiles of 64 rows (lane = row).  Basis column
-// k belongs to wavefront k mod FW, slot k / FW, and stays in that wavefront's
-// registers for the whole tile: the wavefronts form partial Q C and Q T, one
-// combines them in a fixed order and publishes q, w', a_{j+1} for the tile through
-// LDS, and every wavefront then multiplies its columns by w' and a_{j+1} and
-// reduces the 2*FS products over the 64 rows with one transposed butterfly.  Each
-// lane thus owns one (column, right-hand side) total, accumulated over the tiles in
-// a register -- no LDS staging of the tile and no per-column reductions.
+// A workgroup of FW wavefronts walks tiles of 64 rows (lane = row).  Column k of
+// [Q, q, w', a_{j+1}] belongs to wavefront k mod FW, slot k / FW; NS = the number
+// of slots in use is a template parameter, so the tile's loads of a wavefront are
+// unconditional (slots past the basis read a valid column and discard it) and are
+// all in flight together.  The wavefronts form partial Q C and Q T from their
+// slots, wavefront 0 combines them in a fixed order and publishes q, w', a_{j+1}
+// of the tile through LDS, and every lane then accumulates its rows' products
+// for its slots in registers across all tiles; one transposed butterfly per
+// wavefront at the end yields the workgroup partials.
 // LAST: a_{j+1} does not exist (the CGS2 finish of the last column); only
 // [Q_{0..J-1}, q, w']^T w' is reduced.
 constexpr int FMAXCOL = 128;             // J + 3 <= FMAXCOL basis + vector columns
 
-template <typename TQ, bool LAST, int FW>
+template <typename TQ, bool LAST, int FW, int NS>
 __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, int64_t ldq,
                                                            int J, double* __restrict__ w,
                                                            const double* __restrict__ a_cur,
@@ -79,8 +80,9 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
                                                            int64_t m,
                                                            const double* __restrict__ coef,
                                                            int ldc, GridRed gr, FinArgs fin) {
-  constexpr int FS = FMAXCOL / FW;        // column slots per wavefront
-  constexpr int NV = LAST ? FS : 2 * FS;  // products reduced per tile per wavefront
+  constexpr int FS = FMAXCOL / FW;        // slot capacity per wavefront (power of two)
+  constexpr int NV = LAST ? FS : 2 * FS;  // products reduced per wavefront
+  static_assert(NS >= 1 && NS <= FS, "slot count");
   extern __shared__ double smem[];
   if (fin.ctrl->state != ST_RUNNING) return;
   const int Jt = J + (LAST ? 2 : 3);
@@ -89,35 +91,44 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
   double* vq = part + FW * 128;           // q, w', a_{j+1} of the tile rows
   double* vw = vq + 64;
   double* va = vw + 64;
-  const double* __restrict__ C = coef;
-  const double* __restrict__ T = coef + ldc;
   const double alpha = coef[2 * ldc];
-  const double tJ = T[J];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double tJ = coef[ldc + J];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // per-slot column pointers and coefficients (uniform per wavefront)
+  const TQ* colp[NS];
+  double cs[NS], ts[NS];
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const int k = wv + FW * sl;
+    const int kl = k < J ? k : (J > 0 ? J - 1 : 0);
+    colp[sl] = Q + (int64_t)kl * ldq;
+    cs[sl] = k < J ? coef[k] : 0.0;
+    ts[sl] = k < J ? coef[ldc + k] : 0.0;
+  }
   const int64_t ntiles = (m + 63) / 64;
-  double acc = 0.0;
+  double ax[NS], ay[NS];
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) { ax[sl] = 0.0; ay[sl] = 0.0; }
   for (int64_t tix = blockIdx.x; tix < ntiles; tix += gr.G) {
     const int64_t i = tix * 64 + lane;
     const bool live = i < m;
-    double qv[FS];
+    const int64_t il = live ? i : m - 1;
+    double qv[NS];
 #pragma unroll
-    for (int sl = 0; sl < FS; ++sl) {
-      const int k = wv + FW * sl;
-      qv[sl] = (k < J && live) ? (double)Q[(int64_t)k * ldq + i] : 0.0;
-    }
+    for (int sl = 0; sl < NS; ++sl) qv[sl] = (double)colp[sl][il];
     double wi = 0.0, ai = 0.0, an = 0.0;
-    if (wv == 0 && live) {
-      wi = w[i];
-      ai = a_cur[i];
-      if (!LAST) an = a_next[i];
+    if (wv == 0) {
+      wi = w[il];
+      ai = a_cur[il];
+      if (!LAST) an = a_next[il];
     }
     double sc = 0.0, st = 0.0;
 #pragma unroll
-    for (int sl = 0; sl < FS; ++sl) {
-      const int k = wv + FW * sl;
-      if (k < J) {
-        sc = fma(qv[sl], C[k], sc);
-        st = fma(qv[sl], T[k], st);
+    for (int sl = 0; sl < NS; ++sl) {
+      if (wv + FW * sl < J) {             // uniform: a discarded slot may hold anything
+        sc = fma(qv[sl], cs[sl], sc);
+        st = fma(qv[sl], ts[sl], st);
       }
     }
     part[(wv * 64 + lane) * 2] = sc;
@@ -136,6 +147,8 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
         wn = ai - fma(q, tJ, ST);
         Q[(int64_t)J * ldq + i] = (TQ)q;
         w[i] = wn;
+      } else {
+        an = 0.0;
       }
       vq[lane] = q;
       vw[lane] = wn;
@@ -143,25 +156,30 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
     }
     __syncthreads();
     const double qq = vq[lane], ww = vw[lane], aa = va[lane];
-    double pv[NV];
 #pragma unroll
-    for (int sl = 0; sl < FS; ++sl) {
+    for (int sl = 0; sl < NS; ++sl) {
       const int k = wv + FW * sl;
       const double val = (k < J) ? qv[sl]
                          : (k == J) ? qq
                          : (k == J + 1) ? ww
                          : (!LAST && k == J + 2) ? aa : 0.0;
-      pv[sl] = val * ww;
-      if constexpr (!LAST) pv[FS + sl] = val * aa;
+      ax[sl] = fma(val, ww, ax[sl]);
+      if constexpr (!LAST) ay[sl] = fma(val, aa, ay[sl]);
     }
-    wave_transpose_sum(pv, lane);
-    acc += pv[0];
   }
+  // dead rows contribute 0: q = w' = a = 0 there, and basis values only meet them
+  double pv[NV];
+#pragma unroll
+  for (int sl = 0; sl < FS; ++sl) {
+    pv[sl] = sl < NS ? ax[sl] : 0.0;
+    if constexpr (!LAST) pv[FS + sl] = sl < NS ? ay[sl] : 0.0;
+  }
+  wave_transpose_sum(pv, lane);
   {
     const int idx = transpose_index<NV>(lane);
     const int k = wv + FW * (idx % FS);
     const int rhs = idx / FS;
-    if (k < Jt) gr.P1[(int64_t)blockIdx.x * gr.ldp + rhs * Jt + k] = acc;
+    if (k < Jt) gr.P1[(int64_t)blockIdx.x * gr.ldp + rhs * Jt + k] = pv[0];
   }
   __syncthreads();                        // LDS is reused by the finaliser below
   double* red = smem;
@@ -230,13 +248,17 @@ __global__ __launch_bounds__(BS) void tsgemm_kernel(const TQ* __restrict__ Q, in
   const int k0 = blockIdx.y * NO;
   if (i >= m) return;
   double acc[NO];
+  const double* zc[NO];                   // output columns past k repeat column k-1 (not stored)
 #pragma unroll
-  for (int o = 0; o < NO; ++o) acc[o] = 0.0;
+  for (int o = 0; o < NO; ++o) {
+    acc[o] = 0.0;
+    zc[o] = Z + (int64_t)(k0 + o < k ? k0 + o : k - 1) * ldz;
+  }
+#pragma unroll 8
   for (int c = 0; c < p; ++c) {
     const double q = (double)Q[(int64_t)c * ldq + i];
 #pragma unroll
-    for (int o = 0; o < NO; ++o)
-      if (k0 + o < k) acc[o] = fma(q, Z[(int64_t)(k0 + o) * ldz + c], acc[o]);
+    for (int o = 0; o < NO; ++o) acc[o] = fma(q, zc[o][c], acc[o]);
   }
 #pragma unroll
   for (int o = 0; o < NO; ++o) {
@@ -435,21 +457,45 @@ int fused_qr_grid(int64_t m, int J, int last, int fw, int gmax) {
   return (int)(g < 1 ? 1 : g);
 }
 
+namespace {
+// Dispatch on the slot count NS = ceil(Jt / FW) (compile-time in the kernel).
+template <typename T, bool L, int F, int NS>
+hipError_t fused_qr_ns(int ns, T* Q, int64_t ldq, int J, double* w, const double* a_cur,
+                       const double* a_next, int64_t m, const double* coef, int ldc, size_t sm,
+                       const GridRed& gr, const FinArgs& fin, hipStream_t s) {
+  if constexpr (NS > FMAXCOL / F) {
+    return hipErrorInvalidValue;
+  } else {
+    if (ns == NS) {
+      fused_qr_kernel<T, L, F, NS><<<gr.G, F * 64, sm, s>>>(Q, ldq, J, w, a_cur, a_next, m, coef,
+                                                            ldc, gr, fin);
+      return hipGetLastError();
+    }
+    return fused_qr_ns<T, L, F, NS + 1>(ns, Q, ldq, J, w, a_cur, a_next, m, coef, ldc, sm, gr,
+                                        fin, s);
+  }
+}
+}  // namespace
+
 hipError_t launch_fused_qr(void* Q, int q32, int64_t ldq, int J, double* w, const double* a_cur,
                            const double* a_next, int64_t m, const double* coef, int ldc, int last,
                            int fw, const GridRed& gr, const FinArgs& fin, hipStream_t s) {
   const size_t sm = fused_qr_smem(J, last, fw);
-#define DCGS2_FQ(T, L, F) \
-  fused_qr_kernel<T, L, F><<<gr.G, F * 64, sm, s>>>((T*)Q, ldq, J, w, a_cur, a_next, m, coef, ldc, gr, fin)
-#define DCGS2_FQ_W(F)                                                                    \
-  do {                                                                                   \
-    if (q32) { if (last) DCGS2_FQ(float, true, F); else DCGS2_FQ(float, false, F); }     \
-    else { if (last) DCGS2_FQ(double, true, F); else DCGS2_FQ(double, false, F); }       \
-  } while (0)
-  if (fw == 8) DCGS2_FQ_W(8); else DCGS2_FQ_W(16);
-#undef DCGS2_FQ_W
+  const int F = fw == 8 ? 8 : 16;
+  const int Jt = J + (last ? 2 : 3);
+  const int ns = (Jt + F - 1) / F;
+  if (ns < 1 || ns > FMAXCOL / F) return hipErrorInvalidValue;
+#define DCGS2_FQ(T, L, FF)                                                                      \
+  return fused_qr_ns<T, L, FF, 1>(ns, (T*)Q, ldq, J, w, a_cur, a_next, m, coef, ldc, sm, gr, fin, s)
+  if (F == 8) {
+    if (q32) { if (last) DCGS2_FQ(float, true, 8); DCGS2_FQ(float, false, 8); }
+    if (last) DCGS2_FQ(double, true, 8);
+    DCGS2_FQ(double, false, 8);
+  }
+  if (q32) { if (last) DCGS2_FQ(float, true, 16); DCGS2_FQ(float, false, 16); }
+  if (last) DCGS2_FQ(double, true, 16);
+  DCGS2_FQ(double, false, 16);
 #undef DCGS2_FQ
-  return hipGetLastError();
 }
 
 hipError_t launch_scale_col(void* Q, int q32, int64_t ldq, int J, const double* ubuf, int64_t m,
