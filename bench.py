@@ -9,9 +9,11 @@ steps (columns) per second over the K timed factorisations.
 
 Also reported (not `value`): the DCGS2 Arnoldi expansion at m = 128^3 = 2,097,152
 with n = 100 (3-D convection-diffusion matvec), restarted GMRES(50) on the same
-operator to a 1e-8 true relative residual (time-to-solution), one Krylov-Schur
-solve, the per-kernel roofline figures measured with HIP events around each
-launch, and the FP64 oracle timed on the host on a bounded row sample.
+operator to a 1e-8 true relative residual (time-to-solution, FP64 and FP32-stored
+basis), one Krylov-Schur solve, batched Krylov-Schur over 512 operators, GMRES
+from the learned initial guess against x0 = 0, the per-kernel roofline figures
+measured with HIP events around each launch, and the FP64 oracle timed on the
+host on the same matrix.
 """
 from __future__ import annotations
 
@@ -96,6 +98,58 @@ def cpu_baseline(B, n):
             "kind": "oracle",
             "sample": f"one full factorization of the same B ({m} x {n}) by "
                       f"oracle.gram_schmidt.dcgs2_qr (NumPy/BLAS fp64), {dt:.2f} s"}
+
+
+def batched_ks_leg(torch, ctx, binding, synth, count=512):
+    """Batched Krylov-Schur: `count` 2-D convection-diffusion operators, n_x ~ U{48..256},
+    v ~ U(0,50)^2, 10 largest-magnitude eigenvalues, basis 60, keep 20, tol 1e-8."""
+    probs = synth.ks_instances(count, seed=4)
+    descs = [binding.stencil2d(p.grid, p.D, p.vel) for p in probs]
+    v0 = torch.from_numpy(np.concatenate([synth.normal_vector(p.m, 1000 + i)
+                                          for i, p in enumerate(probs)])).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, rc, infos = ctx.krylov_schur_batched(descs, v0, 10, 60, 20, 1e-8, 300, use_graph=True)
+    dt = time.perf_counter() - t0
+    st = [i["status"] for i in infos]
+    rs = [i["restarts"] for i in infos]
+    return {"instances": count, "time_s": round(dt, 3), "converged": st.count(0),
+            "restarts_max": max(rs), "restarts_mean": round(float(np.mean(rs)), 2),
+            "matvecs_total": int(sum(i["matvecs"] for i in infos)),
+            "instances_per_s": round(count / dt, 2), "status": rc}
+
+
+def learned_guess_leg(torch, ctx, binding, synth, count=8):
+    """GMRES(50) to 1e-8 on held-out instances of the 256 x 256 variable-coefficient
+    family, from x0 = 0 and from the trained network's guess (inference and the
+    guard included in the timed region)."""
+    from paper_2104_01253_amd import guess
+    if not os.path.exists(guess.DEFAULT_WEIGHTS):
+        return {"status": "no trained weights"}
+    model = guess.GuessModel(ctx, max_batch=count)
+    model.load(guess.DEFAULT_WEIGHTS)
+    probs = synth.varcoef_instances(count, seed=777, n=guess.N)
+    rows = []
+    for p in probs:
+        b = torch.from_numpy(synth.varcoef_rhs(p)).cuda()
+        prm = torch.from_numpy(guess.params_of(p)).cuda()
+        dop = guess.DeviceOp(p)
+        _, rc0, i0, t_zero = guess.solve(ctx, p, b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x0 = model.predict(b[None], prm[None])[0].contiguous()
+        kept, ratio = ctx.guess_guard(dop.op, b, x0, 10.0)
+        t_inf = time.perf_counter() - t0
+        _, rc1, i1, t_g = guess.solve(ctx, p, b, x0=x0)
+        rows.append((t_zero, t_inf + t_g, i0["iters"], i1["iters"], kept, ratio, rc0, rc1))
+    a = np.array([r[:4] for r in rows], dtype=float)
+    return {"instances": count, "zero_guess_s_mean": round(float(a[:, 0].mean()), 4),
+            "learned_guess_s_mean": round(float(a[:, 1].mean()), 4),
+            "speedup": round(float(a[:, 0].sum() / a[:, 1].sum()), 3),
+            "iters_zero_mean": float(a[:, 2].mean()), "iters_guess_mean": float(a[:, 3].mean()),
+            "guesses_kept": int(sum(r[4] for r in rows)),
+            "residual_ratio_mean": round(float(np.mean([r[5] for r in rows])), 3),
+            "status": [int(r[7]) for r in rows]}
 
 
 def main():
@@ -245,6 +299,10 @@ def main():
                                      "restarts": kinfo["restarts"], "matvecs": kinfo["matvecs"],
                                      "status": rc}
         log(f"[bench] legs: arnoldi {out['arnoldi_128cube_n100']}, gmres {out['gmres50_128cube_fp64']}")
+        out["krylov_schur_batched_512"] = batched_ks_leg(torch, ctx, binding, synth)
+        log(f"[bench] batched KS {out['krylov_schur_batched_512']}")
+        out["gmres50_learned_guess_256sq"] = learned_guess_leg(torch, ctx, binding, synth)
+        log(f"[bench] learned guess {out['gmres50_learned_guess_256sq']}")
 
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")

@@ -83,36 +83,50 @@ def _rows(d, pattern):
     return out
 
 
+# kernel name fragments -> the kernel classes of dcgs2_profile_read
+CLASSES = (("fused_qr_kernel", "fused_qr"), ("reduce_kernel", "reduce"), ("update_kernel", "update"),
+           ("project_norm_kernel", "project_norm"), ("scale_col_kernel", "scale"),
+           ("stencil_kernel", "spmv"), ("csr_kernel", "spmv"), ("tsgemm_kernel", "tsgemm"))
+
+
 def _short(name: str) -> str:
-    for key in ("fused_qr_kernel", "reduce_kernel", "update_kernel", "project_norm_kernel",
-                "scale_col_kernel", "stencil_kernel", "csr_kernel", "tsgemm_kernel"):
+    for key, cls in CLASSES:
         if key in name:
-            return key
-    if "copy" in name.lower() or "elementwise" in name.lower():
-        return "torch_copy"
-    return name[:60]
+            return cls
+    return "other"
 
 
-def _counter(d, counter):
-    """Sum of `counter` per short kernel name and dispatch count."""
-    per, disp = {}, {}
+def _dispatches(d, counter):
+    """[(dispatch id, kernel name, grid size, counter value in KiB)] of one counter run."""
+    out = []
     for r in _rows(d, "*counter_collection.csv"):
-        if r.get("Counter_Name") != counter:
+        if r.get("Counter_Name") == counter:
+            out.append((int(r["Dispatch_Id"]), r.get("Kernel_Name", ""), int(r.get("Grid_Size", 0)),
+                        float(r["Counter_Value"])))
+    return out
+
+
+def _calibrated(d, counter):
+    """Per kernel class: (dispatches, bytes per launch) with the counter scaled so that
+    the calibration copy (the largest copy-kernel dispatch, COPY_BYTES read and
+    written) reads exactly COPY_BYTES; and the scale itself."""
+    rows = _dispatches(d, counter)
+    copies = [r for r in rows if "copyBuffer" in r[1]]      # hipMemcpy device-to-device
+    cal = max(copies, key=lambda r: r[3]) if copies else None
+    scale = COPY_BYTES / (cal[3] * 1024.0) if cal and cal[3] > 0 else 1.0
+    per = {}
+    for _, name, _, v in rows:
+        k = _short(name)
+        if k == "other":
             continue
-        k = _short(r.get("Kernel_Name", ""))
-        per[k] = per.get(k, 0.0) + float(r["Counter_Value"])
-        disp.setdefault(k, set()).add(r.get("Dispatch_Id"))
-    return per, {k: len(v) for k, v in disp.items()}
+        n, tot = per.get(k, (0, 0.0))
+        per[k] = (n + 1, tot + v * 1024.0 * scale)
+    return {k: (n, tot / n) for k, (n, tot) in per.items()}, scale
 
 
 def summarize(fetch_dir, write_dir, trace_dir, out, command):
-    fetch, nf = _counter(fetch_dir, "FETCH_SIZE")
-    write, nw = _counter(write_dir, "WRITE_SIZE")
-    # copy calibration: the copy kernel moves COPY_BYTES in and COPY_BYTES out
-    cf = fetch.get("torch_copy", 0.0) * 1024.0
-    cw = write.get("torch_copy", 0.0) * 1024.0
-    fscale = COPY_BYTES / cf if cf > 0 else 1.0
-    wscale = COPY_BYTES / cw if cw > 0 else 1.0
+    fetch, fscale = _calibrated(fetch_dir, "FETCH_SIZE")
+    write, wscale = _calibrated(write_dir, "WRITE_SIZE")
     stats = {}
     for r in _rows(trace_dir, "*kernel_stats.csv"):
         k = _short(r["Name"])
@@ -121,14 +135,13 @@ def summarize(fetch_dir, write_dir, trace_dir, out, command):
         s[1] += float(r["TotalDurationNs"])
     kernels = {}
     for k in sorted(set(fetch) | set(write)):
-        if k == "torch_copy":
-            continue
-        n = max(nf.get(k, 0), nw.get(k, 0), 1)
-        fb = fetch.get(k, 0.0) * 1024.0 * fscale / n
-        wb = write.get(k, 0.0) * 1024.0 * wscale / n
+        n = max(fetch.get(k, (0, 0.0))[0], write.get(k, (0, 0.0))[0], 1)
+        fb = fetch.get(k, (0, 0.0))[1]
+        wb = write.get(k, (0, 0.0))[1]
         kernels[k] = {"dispatches": n, "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
                       "bytes_per_launch": fb + wb}
         if k in stats:
+            kernels[k]["trace_launches"] = stats[k][0]
             kernels[k]["avg_duration_us"] = stats[k][1] / max(stats[k][0], 1) / 1e3
     src = open(os.path.join(HERE, "csrc", "kernels.hip"), "rb").read()
     rec = {"kernel_source_sha256_16": hashlib.sha256(src).hexdigest()[:16],
@@ -138,12 +151,17 @@ def summarize(fetch_dir, write_dir, trace_dir, out, command):
     with open(out + ".json", "w") as fh:
         json.dump(rec, fh, indent=1)
     with open(out + ".md", "w") as fh:
-        fh.write(f"# {os.path.basename(out)}\n\ncommand: `{command}`\n\n")
-        fh.write(f"copy calibration: FETCH scale {fscale:.4f}, WRITE scale {wscale:.4f}\n\n")
-        fh.write("| kernel | dispatches | fetch MB/launch | write MB/launch | avg us |\n|---|---|---|---|---|\n")
+        fh.write(f"# {os.path.basename(out)}\n\n")
+        fh.write(f"commands:\n\n```\n{command}\n```\n\n")
+        fh.write(f"Counter calibration: a device copy of {COPY_BYTES} bytes read and written; "
+                 f"FETCH_SIZE scale {fscale:.4f}, WRITE_SIZE scale {wscale:.4f}.\n\n")
+        fh.write("| kernel class | dispatches | HBM read MB/launch | HBM write MB/launch | "
+                 "avg duration us (kernel trace) | measured GB/s |\n|---|---|---|---|---|---|\n")
         for k, v in kernels.items():
+            us = v.get("avg_duration_us", float("nan"))
+            gbs = v["bytes_per_launch"] / (us * 1e-6) / 1e9 if us == us and us > 0 else float("nan")
             fh.write(f"| {k} | {v['dispatches']} | {v['fetch_bytes_per_launch']/1e6:.2f} | "
-                     f"{v['write_bytes_per_launch']/1e6:.2f} | {v.get('avg_duration_us', float('nan')):.1f} |\n")
+                     f"{v['write_bytes_per_launch']/1e6:.2f} | {us:.1f} | {gbs:.0f} |\n")
     print(json.dumps(rec, indent=1))
 
 
