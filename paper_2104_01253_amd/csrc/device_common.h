@@ -158,6 +158,22 @@ __device__ void block_sum(const double (&acc)[NV], double* sh, double* out, int 
 // with the V totals in red[] (LDS).  Workgroups are grouped by consecutive index;
 // each group is summed in index order by its last arrival, then the group sums
 // are summed in group order by the last group to finish.
+// base[0], base[stride], ..., base[(n-1) stride] (n >= 1) summed in index order.
+// The loads are issued eight at a time (clamped indices, unconditional), so a
+// chain of n partials costs n/8 memory round trips instead of n; skipped entries
+// add an exact 0.0, which leaves the sum unchanged.
+__device__ __forceinline__ double ordered_sum(const double* base, int64_t stride, int n) {
+  double s = 0.0;
+  for (int b0 = 0; b0 < n; b0 += 8) {
+    double t[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) t[i] = base[(int64_t)min(b0 + i, n - 1) * stride];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s += (b0 + i < n) ? t[i] : 0.0;
+  }
+  return s;
+}
+
 __device__ bool grid_reduce(const GridRed& gr, int V, double* red, int bid) {
   __shared__ int s_last;
   __threadfence();               // every thread: release this workgroup's partial stores
@@ -173,8 +189,7 @@ __device__ bool grid_reduce(const GridRed& gr, int V, double* red, int bid) {
   if (!s_last) return false;
   __threadfence();
   for (int v = threadIdx.x; v < V; v += (int)blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < gsz; ++b) s += gr.P1[(int64_t)(g0 + b) * gr.ldp + v];
+    const double s = ordered_sum(gr.P1 + (int64_t)g0 * gr.ldp + v, gr.ldp, gsz);
     if (gr.NG == 1) red[v] = s;
     else gr.P2[(int64_t)grp * gr.ldp + v] = s;
   }
@@ -189,11 +204,8 @@ __device__ bool grid_reduce(const GridRed& gr, int V, double* red, int bid) {
   __syncthreads();
   if (!s_last) return false;
   __threadfence();
-  for (int v = threadIdx.x; v < V; v += (int)blockDim.x) {
-    double s = 0.0;
-    for (int g = 0; g < gr.NG; ++g) s += gr.P2[(int64_t)g * gr.ldp + v];
-    red[v] = s;
-  }
+  for (int v = threadIdx.x; v < V; v += (int)blockDim.x)
+    red[v] = ordered_sum(gr.P2 + v, gr.ldp, gr.NG);
   if (threadIdx.x == 0) gr.cnt[gr.NG] = 0u;
   __syncthreads();
   return true;
@@ -326,7 +338,14 @@ __device__ void step_tail(const FinArgs& f, const double* C, const double* S, do
     // line 11: K_{1:j-1, j-1} = T - (1/alpha) H_{1:j-1, 1:j-2} C   (dense product)
     for (int i = threadIdx.x; i <= J; i += (int)blockDim.x) {
       double hc = 0.0;
-      for (int c = 0; c < J; ++c) hc = fma(f.H[(int64_t)c * f.ldh + i], C[c], hc);
+      for (int c0 = 0; c0 < J; c0 += 8) {        // eight loads in flight, FMAs in order
+        double h[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) h[u] = f.H[(int64_t)min(c0 + u, J - 1) * f.ldh + i];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (c0 + u < J) hc = fma(h[u], C[c0 + u], hc);
+      }
       f.K[(int64_t)J * f.ldh + i] = T[i] - hc / alpha;
     }
     if (threadIdx.x == 0) ctrl->rho_next = sqrt(gamma) / alpha;

@@ -72,6 +72,14 @@ __global__ __launch_bounds__(BS) void update_kernel(TQ* __restrict__ Q, int64_t 
 // [Q_{0..J-1}, q, w']^T w' is reduced.
 constexpr int FMAXCOL = 128;             // J + 3 <= FMAXCOL basis + vector columns
 
+// Workgroup barrier for LDS hand-offs only: waits for this wavefront's LDS
+// traffic, not for its outstanding global loads, so the next tile's prefetch
+// stays in flight across the barrier.  (The generic barrier also waits for every
+// global access, which would expose the full memory latency once per tile.)
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 template <typename TQ, bool LAST, int FW, int NS>
 __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, int64_t ldq,
                                                            int J, double* __restrict__ w,
@@ -110,19 +118,24 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
   double ax[NS], ay[NS];
 #pragma unroll
   for (int sl = 0; sl < NS; ++sl) { ax[sl] = 0.0; ay[sl] = 0.0; }
-  for (int64_t tix = blockIdx.x; tix < ntiles; tix += gr.G) {
+  // software pipeline: the loads of the next tile are issued before the current
+  // tile's barriers and consumed one iteration later
+  double qv[NS], wi = 0.0, ai = 0.0, an = 0.0;
+  auto load_tile = [&](int64_t t, double (&q)[NS], double& x0, double& x1, double& x2) {
+    const int64_t il = min(t * 64 + lane, m - 1);
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) q[sl] = (double)colp[sl][il];
+    if (wv == 0) {
+      x0 = w[il];
+      x1 = a_cur[il];
+      if (!LAST) x2 = a_next[il];
+    }
+  };
+  int64_t tix = blockIdx.x;
+  if (tix < ntiles) load_tile(tix, qv, wi, ai, an);
+  for (; tix < ntiles; tix += gr.G) {
     const int64_t i = tix * 64 + lane;
     const bool live = i < m;
-    const int64_t il = live ? i : m - 1;
-    double qv[NS];
-#pragma unroll
-    for (int sl = 0; sl < NS; ++sl) qv[sl] = (double)colp[sl][il];
-    double wi = 0.0, ai = 0.0, an = 0.0;
-    if (wv == 0) {
-      wi = w[il];
-      ai = a_cur[il];
-      if (!LAST) an = a_next[il];
-    }
     double sc = 0.0, st = 0.0;
 #pragma unroll
     for (int sl = 0; sl < NS; ++sl) {
@@ -133,7 +146,9 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
     }
     part[(wv * 64 + lane) * 2] = sc;
     part[(wv * 64 + lane) * 2 + 1] = st;
-    __syncthreads();
+    double qn[NS], wn_ = 0.0, an_ = 0.0, ann = 0.0;
+    load_tile(min(tix + gr.G, ntiles - 1), qn, wn_, an_, ann);   // prefetch
+    lds_barrier();
     if (wv == 0) {
       double SC = part[lane * 2], ST = part[lane * 2 + 1];
 #pragma unroll
@@ -141,20 +156,19 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
         SC += part[(u * 64 + lane) * 2];
         ST += part[(u * 64 + lane) * 2 + 1];
       }
-      double q = 0.0, wn = 0.0;
+      double q = 0.0, wn = 0.0, av = 0.0;
       if (live) {
         q = stored<TQ>((wi - SC) / alpha);
         wn = ai - fma(q, tJ, ST);
+        av = an;
         Q[(int64_t)J * ldq + i] = (TQ)q;
         w[i] = wn;
-      } else {
-        an = 0.0;
       }
       vq[lane] = q;
       vw[lane] = wn;
-      va[lane] = an;
+      va[lane] = av;
     }
-    __syncthreads();
+    lds_barrier();
     const double qq = vq[lane], ww = vw[lane], aa = va[lane];
 #pragma unroll
     for (int sl = 0; sl < NS; ++sl) {
@@ -166,6 +180,13 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
       ax[sl] = fma(val, ww, ax[sl]);
       if constexpr (!LAST) ay[sl] = fma(val, aa, ay[sl]);
     }
+    // (the next tile's part writes follow the second barrier, and its vq writes
+    // its first one, so two barriers per tile suffice)
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) qv[sl] = qn[sl];
+    wi = wn_;
+    ai = an_;
+    an = ann;
   }
   // dead rows contribute 0: q = w' = a = 0 there, and basis values only meet them
   double pv[NV];
