@@ -130,7 +130,7 @@ int dcgs2_set_qr_schedule(dcgs2_ctx ctx, int one_pass);
  *  DCGS2_TUNE_FUSED_WAVES : wavefronts per workgroup of the one-pass QR kernel,
  *                           8 or 16 (default 16).
  *  DCGS2_TUNE_REDUCE_GRID : upper bound on the workgroups of a reduction pass,
- *                           1..1024, or 0 for automatic (default).
+ *                           1..1024, or 0 for automatic (default: at most 512).
  * Returns DCGS2_EINVAL for an unknown key or value. */
 enum { DCGS2_TUNE_FUSED_WAVES = 0, DCGS2_TUNE_REDUCE_GRID = 1 };
 int dcgs2_set_tuning(dcgs2_ctx ctx, int32_t key, int32_t value);

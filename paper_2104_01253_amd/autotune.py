@@ -16,7 +16,7 @@ from . import binding
 
 CANDIDATES = {
     binding.TUNE_FUSED_WAVES: (16, 8),
-    binding.TUNE_REDUCE_GRID: (0, 512, 256),
+    binding.TUNE_REDUCE_GRID: (0, 768, 256),
 }
 
 

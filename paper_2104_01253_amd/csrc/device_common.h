@@ -515,7 +515,6 @@ __device__ __forceinline__ void reduce_sweep(const TQ* __restrict__ Q, int64_t l
 #pragma unroll
   for (int c = 0; c < NA; ++c) acc[c] = 0.0;
   const TQ* __restrict__ qb = Q + (int64_t)k0 * ldq;
-#pragma unroll 2
   for (int64_t u = u0 + threadIdx.x; u < u1; u += BS) {
     const RV xv = RV::load(x, u);
     const RV yv = HASY ? RV::load(y, u) : RV::zero();
