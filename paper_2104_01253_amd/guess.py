@@ -163,12 +163,13 @@ def train(model, feats, targs, epochs=60, batch=256, lr=1e-3, seed=0, log=None):
     for ep in range(epochs):
         perm = torch.from_numpy(g.permutation(count)).cuda()
         tot, nb = 0.0, 0
+        step_lr = lr if ep < int(0.7 * epochs) else 0.1 * lr     # one decay step at 70 %
         for s in range(0, count - batch + 1, batch):
             idx = perm[s:s + batch]
             X = feats.index_select(0, idx).contiguous()
             T = targs.index_select(0, idx).contiguous()
             tot += model.mlp.loss_grad(X, T)
-            model.mlp.adam(lr)
+            model.mlp.adam(step_lr)
             nb += 1
         hist.append(tot / max(nb, 1))
         if log and (ep % 10 == 9 or ep == epochs - 1):
@@ -182,7 +183,7 @@ def main(argv=None):
     t = sub.add_parser("train")
     t.add_argument("--count", type=int, default=4096)
     t.add_argument("--val", type=int, default=256)
-    t.add_argument("--epochs", type=int, default=60)
+    t.add_argument("--epochs", type=int, default=150)
     t.add_argument("--lr", type=float, default=1e-3)
     t.add_argument("--seed", type=int, default=100)
     t.add_argument("--out", default=DEFAULT_WEIGHTS)
