@@ -80,7 +80,7 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-template <typename TQ, bool LAST, int FW, int NS>
+template <typename TQ, bool LAST, int FW, int NS, int VR>
 __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, int64_t ldq,
                                                            int J, double* __restrict__ w,
                                                            const double* __restrict__ a_cur,
@@ -88,17 +88,21 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
                                                            int64_t m,
                                                            const double* __restrict__ coef,
                                                            int ldc, GridRed gr, FinArgs fin) {
+  // VR rows per lane (1, or 2 with paired 16-byte loads; VR = 2 needs m even and
+  // every column 16-byte aligned), TR = 64 VR rows per tile.
   constexpr int FS = FMAXCOL / FW;        // slot capacity per wavefront (power of two)
   constexpr int NV = LAST ? FS : 2 * FS;  // products reduced per wavefront
+  constexpr int TR = 64 * VR;
   static_assert(NS >= 1 && NS <= FS, "slot count");
+  using RV = RowVec<VR>;
   extern __shared__ double smem[];
   if (fin.ctrl->state != ST_RUNNING) return;
   const int Jt = J + (LAST ? 2 : 3);
   const int V = LAST ? Jt : 2 * Jt;
-  double* part = smem;                    // FW * 64 * 2 partial (Q C, Q T)
-  double* vq = part + FW * 128;           // q, w', a_{j+1} of the tile rows
-  double* vw = vq + 64;
-  double* va = vw + 64;
+  double* part = smem;                    // FW * TR * 2 partial (Q C, Q T)
+  double* vq = part + FW * TR * 2;        // q, w', a_{j+1} of the tile rows
+  double* vw = vq + TR;
+  double* va = vw + TR;
   const double alpha = coef[2 * ldc];
   const double tJ = coef[ldc + J];
   const int lane = threadIdx.x & 63;
@@ -114,71 +118,95 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
     cs[sl] = k < J ? coef[k] : 0.0;
     ts[sl] = k < J ? coef[ldc + k] : 0.0;
   }
-  const int64_t ntiles = (m + 63) / 64;
+  const int64_t units = m / VR;           // row units of VR rows (m % VR == 0)
+  const int64_t ntiles = (units + 63) / 64;
   double ax[NS], ay[NS];
 #pragma unroll
   for (int sl = 0; sl < NS; ++sl) { ax[sl] = 0.0; ay[sl] = 0.0; }
   // software pipeline: the loads of the next tile are issued before the current
   // tile's barriers and consumed one iteration later
-  double qv[NS], wi = 0.0, ai = 0.0, an = 0.0;
-  auto load_tile = [&](int64_t t, double (&q)[NS], double& x0, double& x1, double& x2) {
-    const int64_t il = min(t * 64 + lane, m - 1);
+  RV qv[NS], wi = RV::zero(), ai = RV::zero(), an = RV::zero();
+  auto load_tile = [&](int64_t t, RV (&q)[NS], RV& x0, RV& x1, RV& x2) {
+    const int64_t ul = min(t * 64 + lane, units - 1);
 #pragma unroll
-    for (int sl = 0; sl < NS; ++sl) q[sl] = (double)colp[sl][il];
+    for (int sl = 0; sl < NS; ++sl) q[sl] = RV::load(colp[sl], ul);
     if (wv == 0) {
-      x0 = w[il];
-      x1 = a_cur[il];
-      if (!LAST) x2 = a_next[il];
+      x0 = RV::load(w, ul);
+      x1 = RV::load(a_cur, ul);
+      if (!LAST) x2 = RV::load(a_next, ul);
     }
   };
   int64_t tix = blockIdx.x;
   if (tix < ntiles) load_tile(tix, qv, wi, ai, an);
   for (; tix < ntiles; tix += gr.G) {
-    const int64_t i = tix * 64 + lane;
-    const bool live = i < m;
-    double sc = 0.0, st = 0.0;
+    const int64_t u = tix * 64 + lane;
+    const bool live = u < units;
+    double sc[VR], st[VR];
+#pragma unroll
+    for (int e = 0; e < VR; ++e) { sc[e] = 0.0; st[e] = 0.0; }
 #pragma unroll
     for (int sl = 0; sl < NS; ++sl) {
       if (wv + FW * sl < J) {             // uniform: a discarded slot may hold anything
-        sc = fma(qv[sl], cs[sl], sc);
-        st = fma(qv[sl], ts[sl], st);
+#pragma unroll
+        for (int e = 0; e < VR; ++e) {
+          sc[e] = fma(qv[sl].e[e], cs[sl], sc[e]);
+          st[e] = fma(qv[sl].e[e], ts[sl], st[e]);
+        }
       }
     }
-    part[(wv * 64 + lane) * 2] = sc;
-    part[(wv * 64 + lane) * 2 + 1] = st;
-    double qn[NS], wn_ = 0.0, an_ = 0.0, ann = 0.0;
+#pragma unroll
+    for (int e = 0; e < VR; ++e) {
+      part[((wv * 64 + lane) * VR + e) * 2] = sc[e];
+      part[((wv * 64 + lane) * VR + e) * 2 + 1] = st[e];
+    }
+    RV qn[NS], wn_ = RV::zero(), an_ = RV::zero(), ann = RV::zero();
     load_tile(min(tix + gr.G, ntiles - 1), qn, wn_, an_, ann);   // prefetch
     lds_barrier();
     if (wv == 0) {
-      double SC = part[lane * 2], ST = part[lane * 2 + 1];
+      RV qo = RV::zero(), wo = RV::zero(), ao = RV::zero();
 #pragma unroll
-      for (int u = 1; u < FW; ++u) {
-        SC += part[(u * 64 + lane) * 2];
-        ST += part[(u * 64 + lane) * 2 + 1];
+      for (int e = 0; e < VR; ++e) {
+        const int r = lane * VR + e;
+        double SC = part[r * 2], ST = part[r * 2 + 1];
+#pragma unroll
+        for (int v = 1; v < FW; ++v) {
+          SC += part[((v * 64 + lane) * VR + e) * 2];
+          ST += part[((v * 64 + lane) * VR + e) * 2 + 1];
+        }
+        if (live) {
+          qo.e[e] = stored<TQ>((wi.e[e] - SC) / alpha);
+          wo.e[e] = ai.e[e] - fma(qo.e[e], tJ, ST);
+          ao.e[e] = an.e[e];
+        }
+        vq[r] = qo.e[e];
+        vw[r] = wo.e[e];
+        va[r] = ao.e[e];
       }
-      double q = 0.0, wn = 0.0, av = 0.0;
       if (live) {
-        q = stored<TQ>((wi - SC) / alpha);
-        wn = ai - fma(q, tJ, ST);
-        av = an;
-        Q[(int64_t)J * ldq + i] = (TQ)q;
-        w[i] = wn;
+        qo.store(Q + (int64_t)J * ldq, u);
+        wo.store(w, u);
       }
-      vq[lane] = q;
-      vw[lane] = wn;
-      va[lane] = av;
     }
     lds_barrier();
-    const double qq = vq[lane], ww = vw[lane], aa = va[lane];
+    RV qq, ww, aa;
+#pragma unroll
+    for (int e = 0; e < VR; ++e) {
+      qq.e[e] = vq[lane * VR + e];
+      ww.e[e] = vw[lane * VR + e];
+      aa.e[e] = va[lane * VR + e];
+    }
 #pragma unroll
     for (int sl = 0; sl < NS; ++sl) {
       const int k = wv + FW * sl;
-      const double val = (k < J) ? qv[sl]
-                         : (k == J) ? qq
-                         : (k == J + 1) ? ww
-                         : (!LAST && k == J + 2) ? aa : 0.0;
-      ax[sl] = fma(val, ww, ax[sl]);
-      if constexpr (!LAST) ay[sl] = fma(val, aa, ay[sl]);
+#pragma unroll
+      for (int e = 0; e < VR; ++e) {
+        const double val = (k < J) ? qv[sl].e[e]
+                           : (k == J) ? qq.e[e]
+                           : (k == J + 1) ? ww.e[e]
+                           : (!LAST && k == J + 2) ? aa.e[e] : 0.0;
+        ax[sl] = fma(val, ww.e[e], ax[sl]);
+        if constexpr (!LAST) ay[sl] = fma(val, aa.e[e], ay[sl]);
+      }
     }
     // (the next tile's part writes follow the second barrier, and its vq writes
     // its first one, so two barriers per tile suffice)
@@ -463,8 +491,8 @@ hipError_t launch_update(void* Q, int q32, int64_t ldq, int J, double* x, const 
   return hipGetLastError();
 }
 
-size_t fused_qr_smem(int J, int last, int fw) {
-  const size_t work = (size_t)fw * 128 + 3 * 64;
+size_t fused_qr_smem(int J, int last, int fw, int vr) {
+  const size_t work = (size_t)fw * 128 * vr + 3 * 64 * vr;
   const int Jt = J + (last ? 2 : 3);
   const size_t fin = (size_t)2 * Jt + (J + 3) + 3 * (J + 3) + 64;
   return sizeof(double) * (work > fin ? work : fin) + sizeof(double) * 8;
@@ -473,7 +501,8 @@ size_t fused_qr_smem(int J, int last, int fw) {
 int fused_qr_grid(int64_t m, int J, int last, int fw, int gmax) {
   (void)J; (void)last;
   const int64_t ntiles = (m + 63) / 64;
-  int64_t g = (fw == 8 ? 3 : 2) * 256;    // workgroups resident per CU at ~100 VGPRs
+  (void)fw;
+  int64_t g = 256;                         // one workgroup per CU (measured best at m = 2e6)
   if (gmax > 0 && g > gmax) g = gmax;
   if (g > REDUCE_GMAX) g = REDUCE_GMAX;
   if (g > ntiles) g = ntiles;
@@ -482,7 +511,7 @@ int fused_qr_grid(int64_t m, int J, int last, int fw, int gmax) {
 
 namespace {
 // Dispatch on the slot count NS = ceil(Jt / FW) (compile-time in the kernel).
-template <typename T, bool L, int F, int NS>
+template <typename T, bool L, int F, int VR, int NS>
 hipError_t fused_qr_ns(int ns, T* Q, int64_t ldq, int J, double* w, const double* a_cur,
                        const double* a_next, int64_t m, const double* coef, int ldc, size_t sm,
                        const GridRed& gr, const FinArgs& fin, hipStream_t s) {
@@ -490,12 +519,12 @@ hipError_t fused_qr_ns(int ns, T* Q, int64_t ldq, int J, double* w, const double
     return hipErrorInvalidValue;
   } else {
     if (ns == NS) {
-      fused_qr_kernel<T, L, F, NS><<<gr.G, F * 64, sm, s>>>(Q, ldq, J, w, a_cur, a_next, m, coef,
-                                                            ldc, gr, fin);
+      fused_qr_kernel<T, L, F, NS, VR><<<gr.G, F * 64, sm, s>>>(Q, ldq, J, w, a_cur, a_next, m,
+                                                                coef, ldc, gr, fin);
       return hipGetLastError();
     }
-    return fused_qr_ns<T, L, F, NS + 1>(ns, Q, ldq, J, w, a_cur, a_next, m, coef, ldc, sm, gr,
-                                        fin, s);
+    return fused_qr_ns<T, L, F, VR, NS + 1>(ns, Q, ldq, J, w, a_cur, a_next, m, coef, ldc, sm, gr,
+                                            fin, s);
   }
 }
 }  // namespace
@@ -503,21 +532,30 @@ hipError_t fused_qr_ns(int ns, T* Q, int64_t ldq, int J, double* w, const double
 hipError_t launch_fused_qr(void* Q, int q32, int64_t ldq, int J, double* w, const double* a_cur,
                            const double* a_next, int64_t m, const double* coef, int ldc, int last,
                            int fw, const GridRed& gr, const FinArgs& fin, hipStream_t s) {
-  const size_t sm = fused_qr_smem(J, last, fw);
   const int F = fw == 8 ? 8 : 16;
   const int Jt = J + (last ? 2 : 3);
   const int ns = (Jt + F - 1) / F;
   if (ns < 1 || ns > FMAXCOL / F) return hipErrorInvalidValue;
-#define DCGS2_FQ(T, L, FF)                                                                      \
-  return fused_qr_ns<T, L, FF, 1>(ns, (T*)Q, ldq, J, w, a_cur, a_next, m, coef, ldc, sm, gr, fin, s)
+  // paired rows: m even, every column start 16-byte aligned (8 for an FP32 basis)
+  const bool pair = (m % 2 == 0) && aligned_to(Q, q32 ? 8 : 16) && (ldq % 2 == 0) &&
+                    aligned16(w) && aligned16(a_cur) && (last || aligned16(a_next));
+  const size_t sm = fused_qr_smem(J, last, F, pair ? 2 : 1);
+#define DCGS2_FQ(T, L, FF, VR)                                                                 \
+  return fused_qr_ns<T, L, FF, VR, 1>(ns, (T*)Q, ldq, J, w, a_cur, a_next, m, coef, ldc, sm, gr, \
+                                      fin, s)
+#define DCGS2_FQ_V(FF, VR)                                                                    \
+  do {                                                                                        \
+    if (q32) { if (last) DCGS2_FQ(float, true, FF, VR); DCGS2_FQ(float, false, FF, VR); }     \
+    if (last) DCGS2_FQ(double, true, FF, VR);                                                 \
+    DCGS2_FQ(double, false, FF, VR);                                                          \
+  } while (0)
   if (F == 8) {
-    if (q32) { if (last) DCGS2_FQ(float, true, 8); DCGS2_FQ(float, false, 8); }
-    if (last) DCGS2_FQ(double, true, 8);
-    DCGS2_FQ(double, false, 8);
+    if (pair) DCGS2_FQ_V(8, 2);
+    DCGS2_FQ_V(8, 1);
   }
-  if (q32) { if (last) DCGS2_FQ(float, true, 16); DCGS2_FQ(float, false, 16); }
-  if (last) DCGS2_FQ(double, true, 16);
-  DCGS2_FQ(double, false, 16);
+  if (pair) DCGS2_FQ_V(16, 2);
+  DCGS2_FQ_V(16, 1);
+#undef DCGS2_FQ_V
 #undef DCGS2_FQ
 }
 
