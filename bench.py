@@ -68,7 +68,8 @@ def timed(torch, fn, steps):
 
 
 def roofline(prof, wall_s=None):
-    dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
+    kern = {k: v for k, v in prof.items() if not k.startswith("phase_")}
+    dom = max(kern.items(), key=lambda kv: kv[1]["total_ms"])
     name, st = dom
     avg_ms = st["total_ms"] / max(st["launches"], 1)
     bytes_per_launch = st["bytes"] / max(st["launches"], 1)
@@ -192,8 +193,9 @@ def main():
     if not args.no_tune:
         from paper_2104_01253_amd import autotune
         best, best_ms, _ = autotune.tune(ctx, qr_once, reps=1)
-        tuned = {("fused_waves" if k == binding.TUNE_FUSED_WAVES else "reduce_grid"): v
-                 for k, v in best.items()}
+        names = {binding.TUNE_FUSED_WAVES: "fused_waves", binding.TUNE_REDUCE_GRID: "reduce_grid",
+                 binding.TUNE_FUSED_MIN_J: "fused_min_j"}
+        tuned = {names[k]: v for k, v in best.items()}
         log(f"[bench] autotuned {tuned} ({best_ms:.2f} ms)")
     log(f"[bench] timing {args.steps} factorizations")
     T = timed(torch, qr_once, args.steps)

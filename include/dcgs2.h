@@ -128,11 +128,15 @@ int dcgs2_set_qr_schedule(dcgs2_ctx ctx, int one_pass);
  * or left at their defaults).  They change launch shapes only, never the
  * arithmetic or the summation order within a workgroup.
  *  DCGS2_TUNE_FUSED_WAVES : wavefronts per workgroup of the one-pass QR kernel,
- *                           8 or 16 (default 16).
+ *                           8 or 16 (default 8).
  *  DCGS2_TUNE_REDUCE_GRID : upper bound on the workgroups of a reduction pass,
- *                           1..1024, or 0 for automatic (default: at most 512).
+ *                           1..1024, or 0 for automatic (default: at most 256).
+ *  DCGS2_TUNE_FUSED_MIN_J : one-pass QR schedule: steps whose basis has fewer
+ *                           than this many columns run as a separate update and
+ *                           reduction pass (same arithmetic per pass, another
+ *                           summation order), 0..DCGS2_MAX_N (default 0).
  * Returns DCGS2_EINVAL for an unknown key or value. */
-enum { DCGS2_TUNE_FUSED_WAVES = 0, DCGS2_TUNE_REDUCE_GRID = 1 };
+enum { DCGS2_TUNE_FUSED_WAVES = 0, DCGS2_TUNE_REDUCE_GRID = 1, DCGS2_TUNE_FUSED_MIN_J = 2 };
 int dcgs2_set_tuning(dcgs2_ctx ctx, int32_t key, int32_t value);
 int dcgs2_get_tuning(dcgs2_ctx ctx, int32_t key, int32_t* value);
 
@@ -219,7 +223,10 @@ int krylov_schur_eigs(dcgs2_ctx ctx, const dcgs2_op* A, int32_t nev, int32_t ncv
  * each launch and its algorithmic HBM bytes (the bytes the method must move:
  * basis columns read once, vectors read/written once) accumulate per kernel
  * class ("spmv", "reduce", "update", "project_norm", "scale", "tsgemm",
- * "fused_qr", "aux").
+ * "fused_qr", "aux").  Two further records are wall-clock phases of
+ * krylov_schur_batched, not kernels (bytes 0): "phase_batched_cycle" (from a
+ * cycle's launch to its completion) and "phase_host_dense" (the host Schur work
+ * between cycles).
  * dcgs2_profile_read synchronises the stream, writes up to max_entries records
  * and returns the number of classes (>= 0), or DCGS2_EINVAL; reset != 0 clears
  * the accumulators afterwards. */

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -41,8 +42,9 @@ struct dcgs2_ctx_s {
   bool ready = false;
   double tau = 1e-8, eta = 1e-12;
   bool qr_one_pass = true;
-  int tune_fused_waves = 16;     // DCGS2_TUNE_FUSED_WAVES
+  int tune_fused_waves = 8;      // DCGS2_TUNE_FUSED_WAVES
   int tune_reduce_gmax = 0;      // DCGS2_TUNE_REDUCE_GRID (0: automatic)
+  int tune_fused_min_j = 0;      // DCGS2_TUNE_FUSED_MIN_J
   int64_t cap_m = 0;
   int64_t cap_qa = 0, cap_qb = 0;
   double *w = nullptr, *v = nullptr, *r = nullptr;
@@ -81,10 +83,13 @@ namespace {
   } while (0)
 
 // Kernel classes reported by dcgs2_profile_read.
+// The last two are wall-clock phases of the batched solver, not kernels: device
+// time of an expansion cycle (launch to completion) and the host dense work.
 enum KClass { K_SPMV = 0, K_REDUCE, K_UPDATE, K_PROJNORM, K_SCALE, K_TSGEMM, K_FUSED, K_AUX,
-              K_NCLASS };
+              K_BATCH_CYCLE, K_HOST_DENSE, K_NCLASS };
 const char* const kClassName[K_NCLASS] = {"spmv", "reduce", "update", "project_norm",
-                                          "scale", "tsgemm", "fused_qr", "aux"};
+                                          "scale", "tsgemm", "fused_qr", "aux",
+                                          "phase_batched_cycle", "phase_host_dense"};
 
 hipEvent_t prof_event(dcgs2_ctx c) {
   if (!c->evpool.empty()) {
@@ -346,8 +351,17 @@ struct Expansion {
                          s));
         break;
       }
-      const GridRed g = fused_grid(J, last ? 1 : 0);
       const FinArgs f = last ? fin(FIN_LAST1, j + 1, J + 1) : fin(FIN_STEP, j + 1, J + 1);
+      if (J < c->tune_fused_min_j) {
+        // a short basis: the separate passes stream better than the tiled fused pass
+        KL(K_UPDATE, qb * (J + 1) + 3 * vm,
+           launch_update(Q, q32, ldq, J, c->w, ycol(j), nullptr, m, c->coef, LDC, 0, 0, c->ctrl,
+                         s));
+        KL(K_REDUCE, qb * (J + 1) + (last ? 1 : 2) * vm,
+           launch_reduce(Q, q32, ldq, J + 1, c->w, last ? nullptr : ycol(j + 1), m, gr, f, s));
+        continue;
+      }
+      const GridRed g = fused_grid(J, last ? 1 : 0);
       // bytes: Q_{0..J-1}, w, a_j, a_{j+1} read; q, w written
       KL(K_FUSED, qb * (J + 1) + vm * (last ? 3 : 4),
          launch_fused_qr(Q, q32, ldq, J, c->w, ycol(j), last ? nullptr : ycol(j + 1), m,
@@ -498,6 +512,10 @@ int dcgs2_set_tuning(dcgs2_ctx c, int32_t key, int32_t value) {
       if (value != 0 && (value < 1 || value > REDUCE_GMAX)) return DCGS2_EINVAL;
       c->tune_reduce_gmax = value;
       return DCGS2_OK;
+    case DCGS2_TUNE_FUSED_MIN_J:
+      if (value < 0 || value > DCGS2_MAX_N) return DCGS2_EINVAL;
+      c->tune_fused_min_j = value;
+      return DCGS2_OK;
     default:
       return DCGS2_EINVAL;
   }
@@ -508,6 +526,7 @@ int dcgs2_get_tuning(dcgs2_ctx c, int32_t key, int32_t* value) {
   switch (key) {
     case DCGS2_TUNE_FUSED_WAVES: *value = c->tune_fused_waves; return DCGS2_OK;
     case DCGS2_TUNE_REDUCE_GRID: *value = c->tune_reduce_gmax; return DCGS2_OK;
+    case DCGS2_TUNE_FUSED_MIN_J: *value = c->tune_fused_min_j; return DCGS2_OK;
     default: return DCGS2_EINVAL;
   }
 }
@@ -974,21 +993,26 @@ int batched_run_cycle(BatchedState& B, int jmin, double tau, double eta, bool us
 
 }  // namespace
 
-extern "C" int krylov_schur_batched(dcgs2_ctx c, int32_t count, const dcgs2_stencil2d* ops,
-                                    int32_t nev, int32_t ncv, int32_t keep, double tol,
-                                    int32_t max_restarts, const double* v0, double* eig_re,
-                                    double* eig_im, dcgs2_ks_info* infos, int32_t use_graph) {
-  if (!c || count < 1 || count > 65536 || !ops || !v0 || !eig_re || !eig_im || !infos ||
-      nev < 1 || keep <= nev || ncv <= keep || ncv > DCGS2_MAX_N || !(tol > 0.0) ||
-      max_restarts < 0)
-    return DCGS2_EINVAL;
-  for (int b = 0; b < count; ++b) {
-    const int64_t mb = (int64_t)ops[b].nx * ops[b].ny;
-    if (ops[b].nx < 1 || ops[b].ny < 1 || mb <= ncv || mb >= INT32_MAX) return DCGS2_EINVAL;
-  }
-  int rc;
-  if ((rc = ctx_ready(c))) return rc;
+namespace {
+
+// One group of instances of the batched solver: its own stream, buffers, table
+// and graphs.  Two groups alternate so that the host dense work of one overlaps
+// the device cycle of the other.
+struct BatchedGroup {
   BatchedState B;
+  std::vector<int> gid;                 // global index of each local instance
+  std::vector<Ctrl> hctrl;
+  std::vector<double> Hh, Zh;
+  std::vector<dcgs2::BInst> tab_trunc;
+  int kernels = 0;
+  bool done = false;
+  std::chrono::steady_clock::time_point t_cycle;
+};
+
+int group_setup(dcgs2_ctx c, BatchedGroup& g, const dcgs2_stencil2d* ops, const double* v0,
+                const std::vector<int64_t>& v0off, int ncv) {
+  BatchedState& B = g.B;
+  const int count = (int)g.gid.size();
   B.count = count;
   B.p = ncv;
   B.ld = ncv + 1;
@@ -996,30 +1020,29 @@ extern "C" int krylov_schur_batched(dcgs2_ctx c, int32_t count, const dcgs2_sten
   B.ldp = 2 * (ncv + 2) + 8;
   const int p = B.p, ld = B.ld;
   CK(hipStreamCreateWithFlags(&B.s, hipStreamNonBlocking));   // default priority
-  CK(hipStreamSynchronize(c->stream));      // inputs produced on the caller's stream
-  // layout: per instance, padded row counts; all buffers carved from a few allocations
-  std::vector<int64_t> ldq(count), qoff(count), voff(count), v0off(count);
-  int64_t qtot = 0, vtot = 0, v0tot = 0, gtot = 0;
+  std::vector<int64_t> ldq(count), qoff(count), voff(count);
+  int64_t qtot = 0, vtot = 0, gtot = 0;
   B.pre_rows.assign(count + 1, 0);
   B.pre_red.assign(count + 1, 0);
   std::vector<int> G(count);
   for (int b = 0; b < count; ++b) {
-    const int64_t mb = (int64_t)ops[b].nx * ops[b].ny;
+    const dcgs2_stencil2d& o = ops[g.gid[b]];
+    const int64_t mb = (int64_t)o.nx * o.ny;
     ldq[b] = pad_ld(mb);
     qoff[b] = qtot;
     qtot += ldq[b] * (p + 1);
     voff[b] = vtot;
     vtot += 3 * ldq[b];
-    v0off[b] = v0tot;
-    v0tot += mb;
-    int64_t g = ((mb + 1) / 2 + 1023) / 1024;
-    G[b] = (int)std::max<int64_t>(1, std::min<int64_t>(g, REDUCE_GSMAX));
+    const int64_t gg = ((mb + 1) / 2 + 1023) / 1024;
+    G[b] = (int)std::max<int64_t>(1, std::min<int64_t>(gg, REDUCE_GSMAX));
     gtot += G[b];
-    B.pre_rows[b + 1] = B.pre_rows[b] + (int)((mb + BATCH_ROWS_PER_BLOCK - 1) / BATCH_ROWS_PER_BLOCK);
+    B.pre_rows[b + 1] =
+        B.pre_rows[b] + (int)((mb + BATCH_ROWS_PER_BLOCK - 1) / BATCH_ROWS_PER_BLOCK);
     B.pre_red[b + 1] = B.pre_red[b] + G[b];
   }
   B.nb_rows = B.pre_rows[count];
   B.nb_red = B.pre_red[count];
+  int rc;
   if ((rc = dalloc((void**)&B.Qa, sizeof(double) * qtot))) return rc;
   if ((rc = dalloc((void**)&B.Qb, sizeof(double) * qtot))) return rc;
   if ((rc = dalloc((void**)&B.vec, sizeof(double) * vtot))) return rc;
@@ -1038,9 +1061,10 @@ extern "C" int krylov_schur_batched(dcgs2_ctx c, int32_t count, const dcgs2_sten
   B.tab.resize(count);
   int64_t goff = 0;
   for (int b = 0; b < count; ++b) {
+    const dcgs2_stencil2d& o = ops[g.gid[b]];
     dcgs2::BInst& I = B.tab[b];
     std::memset(&I, 0, sizeof(I));
-    I.m = (int64_t)ops[b].nx * ops[b].ny;
+    I.m = (int64_t)o.nx * o.ny;
     I.ldq = ldq[b];
     I.Q = B.Qa + qoff[b];
     I.Qn = B.Qb + qoff[b];
@@ -1058,13 +1082,13 @@ extern "C" int krylov_schur_batched(dcgs2_ctx c, int32_t count, const dcgs2_sten
     I.cnt = B.cnt + (size_t)b * 64;
     I.G = G[b];
     goff += G[b];
-    I.nx = ops[b].nx; I.ny = ops[b].ny;
-    I.c0 = ops[b].c0; I.cxm = ops[b].cxm; I.cxp = ops[b].cxp; I.cym = ops[b].cym;
-    I.cyp = ops[b].cyp;
+    I.nx = o.nx; I.ny = o.ny;
+    I.c0 = o.c0; I.cxm = o.cxm; I.cxp = o.cxp; I.cym = o.cym; I.cyp = o.cyp;
     I.first_j = 2;
     I.restart = 0;
     I.active = 1;
-    CK(hipMemcpyAsync(I.w, v0 + v0off[b], sizeof(double) * I.m, hipMemcpyDeviceToDevice, B.s));
+    CK(hipMemcpyAsync(I.w, v0 + v0off[g.gid[b]], sizeof(double) * I.m, hipMemcpyDeviceToDevice,
+                      B.s));
   }
   CK(hipMemcpyAsync(B.d_pre_rows, B.pre_rows.data(), sizeof(int) * (count + 1),
                     hipMemcpyHostToDevice, B.s));
@@ -1075,110 +1099,199 @@ extern "C" int krylov_schur_batched(dcgs2_ctx c, int32_t count, const dcgs2_sten
   CK(launch_fill(B.H, (int64_t)count * ld * ld, 0.0, B.s));
   CK(launch_fill(B.K, (int64_t)count * ld * ld, 0.0, B.s));
   CK(launch_zero_u32(B.cnt, count * 64, B.s));
-  int kernels = 0;
-  if ((rc = batched_run_cycle(B, 2, c->tau, c->eta, use_graph != 0, &kernels))) return rc;
+  g.hctrl.resize(count);
+  g.Hh.resize((size_t)count * ld * ld);
+  g.Zh.resize((size_t)count * p * p);
+  return DCGS2_OK;
+}
+
+// Enqueue the read-back of a finished cycle's control blocks and H.
+int group_readback(BatchedGroup& g) {
+  BatchedState& B = g.B;
+  CK(hipMemcpyAsync(g.hctrl.data(), B.ctrl, sizeof(Ctrl) * B.count, hipMemcpyDeviceToHost, B.s));
+  CK(hipMemcpyAsync(g.Hh.data(), B.H, sizeof(double) * g.Hh.size(), hipMemcpyDeviceToHost, B.s));
+  return DCGS2_OK;
+}
+
+// Host dense work of one finished cycle (threads), then the truncation and the
+// next cycle's launch for the instances still active.
+int group_step(dcgs2_ctx c, BatchedGroup& g, int nev, int keep, double tol, int max_restarts,
+               double* eig_re, double* eig_im, dcgs2_ks_info* infos, bool use_graph,
+               int nthreads) {
+  using clk = std::chrono::steady_clock;
+  BatchedState& B = g.B;
+  const int p = B.p, ld = B.ld, count = B.count;
+  CK(hipStreamSynchronize(B.s));
+  if (c->prof) {
+    c->acc[K_BATCH_CYCLE].launches += 1;
+    c->acc[K_BATCH_CYCLE].ms +=
+        std::chrono::duration<double, std::milli>(clk::now() - g.t_cycle).count();
+  }
+  const clk::time_point t_host = clk::now();
+  const double CUT_GAP = 1e-8;
+  std::vector<std::thread> pool;
+  std::atomic<int> next{0};
+  auto worker = [&]() {
+    std::vector<double> T((size_t)p * p), Zm((size_t)p * p), ere(p), eim(p);
+    for (int b = next++; b < count; b = next++) {
+      dcgs2::BInst& I = B.tab[b];
+      if (!I.active) continue;
+      const int gb = g.gid[b];
+      dcgs2_ks_info& inf = infos[gb];
+      const Ctrl& hc = g.hctrl[b];
+      inf.st.reductions += hc.reductions;
+      I.truncate = 0;
+      if (hc.state != ST_RUNNING) {
+        inf.status = hc.state == ST_BREAKDOWN ? DCGS2_BREAKDOWN
+                     : hc.state == ST_NONFINITE ? DCGS2_NONFINITE : DCGS2_NOT_CONVERGED;
+        if (hc.state == ST_FALLBACK) inf.st.pyth_fallbacks += 1;
+        inf.st.breakdown_step = hc.k;
+        I.active = 0;
+        continue;
+      }
+      const double* Hb = g.Hh.data() + (size_t)b * ld * ld;
+      const double h = Hb[(size_t)(p - 1) * ld + p];
+      for (int jj = 0; jj < p; ++jj)
+        for (int i = 0; i < p; ++i) T[(size_t)jj * p + i] = Hb[(size_t)jj * ld + i];
+      if (real_schur(p, T.data(), p, Zm.data(), p) != 0) { I.active = 0; continue; }
+      const int kn = reorder_schur_by_magnitude(p, T.data(), p, Zm.data(), p, nev, CUT_GAP);
+      if (kn < 0) { I.active = 0; continue; }
+      schur_eigenvalues(p, T.data(), p, ere.data(), eim.data());
+      double bn = 0.0, tmin = INFINITY;
+      for (int i = 0; i < kn; ++i) {
+        const double bi = h * Zm[(size_t)i * p + (p - 1)];
+        bn += bi * bi;
+        tmin = std::min(tmin, std::hypot(ere[i], eim[i]));
+      }
+      inf.resid = std::sqrt(bn) / tmin;
+      for (int i = 0; i < nev; ++i) {
+        eig_re[(size_t)gb * nev + i] = ere[i];
+        eig_im[(size_t)gb * nev + i] = eim[i];
+      }
+      if (inf.resid <= tol) { inf.nconv = kn; inf.status = DCGS2_OK; I.active = 0; continue; }
+      if (inf.restarts >= max_restarts) {
+        inf.status = DCGS2_NOT_CONVERGED;
+        I.active = 0;
+        continue;
+      }
+      const int k = reorder_schur_by_magnitude(p, T.data(), p, Zm.data(), p, keep, CUT_GAP);
+      if (k < 0 || k >= p) { I.active = 0; continue; }
+      std::copy(Zm.begin(), Zm.end(), g.Zh.begin() + (size_t)b * p * p);
+      double* Hn = g.Hh.data() + (size_t)b * ld * ld;
+      std::fill(Hn, Hn + (size_t)ld * ld, 0.0);
+      for (int jj = 0; jj < k; ++jj) {
+        for (int i = 0; i < k; ++i) Hn[(size_t)jj * ld + i] = T[(size_t)jj * p + i];
+        Hn[(size_t)jj * ld + k] = h * Zm[(size_t)jj * p + (p - 1)];
+      }
+      I.k = k;
+      I.first_j = k + 2;
+      I.restart = 1;
+      I.truncate = 1;
+      inf.restarts += 1;
+      inf.matvecs += p - k;
+    }
+  };
+  for (int t = 0; t < nthreads; ++t) pool.emplace_back(worker);
+  for (auto& t : pool) t.join();
+  if (c->prof) {
+    c->acc[K_HOST_DENSE].launches += 1;
+    c->acc[K_HOST_DENSE].ms +=
+        std::chrono::duration<double, std::milli>(clk::now() - t_host).count();
+  }
+  int jmin = INT32_MAX;
+  for (int b = 0; b < count; ++b)
+    if (B.tab[b].active) jmin = std::min(jmin, B.tab[b].first_j);
+  if (jmin == INT32_MAX) {
+    g.done = true;
+    return DCGS2_OK;
+  }
+  // truncation: Qn = Q Z_k, q_{k+1} and w; then swap the bases of truncated instances.
+  // The truncation reads g.tab_trunc and the next cycle the swapped g.B.tab: two host
+  // buffers, neither changed before this group's next synchronisation.
+  CK(hipMemcpyAsync(B.Z, g.Zh.data(), sizeof(double) * g.Zh.size(), hipMemcpyHostToDevice, B.s));
+  CK(hipMemcpyAsync(B.H, g.Hh.data(), sizeof(double) * g.Hh.size(), hipMemcpyHostToDevice, B.s));
+  CK(launch_fill(B.K, (int64_t)count * ld * ld, 0.0, B.s));
+  g.tab_trunc = B.tab;
+  CK(hipMemcpyAsync(B.d_tab, g.tab_trunc.data(), sizeof(dcgs2::BInst) * count,
+                    hipMemcpyHostToDevice, B.s));
+  CK(launch_btruncate(B.d_tab, B.d_pre_rows, count, B.nb_rows, p, B.s));
+  g.kernels += 2;
   for (int b = 0; b < count; ++b) {
+    dcgs2::BInst& I = B.tab[b];
+    if (I.active && I.truncate) { std::swap(I.Q, I.Qn); I.truncate = 0; }
+  }
+  CK(hipMemcpyAsync(B.d_tab, B.tab.data(), sizeof(dcgs2::BInst) * count, hipMemcpyHostToDevice,
+                    B.s));
+  g.t_cycle = clk::now();
+  int rc;
+  if ((rc = batched_run_cycle(B, jmin, c->tau, c->eta, use_graph, &g.kernels))) return rc;
+  return group_readback(g);
+}
+
+}  // namespace
+
+extern "C" int krylov_schur_batched(dcgs2_ctx c, int32_t count, const dcgs2_stencil2d* ops,
+                                    int32_t nev, int32_t ncv, int32_t keep, double tol,
+                                    int32_t max_restarts, const double* v0, double* eig_re,
+                                    double* eig_im, dcgs2_ks_info* infos, int32_t use_graph) {
+  if (!c || count < 1 || count > 65536 || !ops || !v0 || !eig_re || !eig_im || !infos ||
+      nev < 1 || keep <= nev || ncv <= keep || ncv > DCGS2_MAX_N || !(tol > 0.0) ||
+      max_restarts < 0)
+    return DCGS2_EINVAL;
+  for (int b = 0; b < count; ++b) {
+    const int64_t mb = (int64_t)ops[b].nx * ops[b].ny;
+    if (ops[b].nx < 1 || ops[b].ny < 1 || mb <= ncv || mb >= INT32_MAX) return DCGS2_EINVAL;
+  }
+  int rc;
+  if ((rc = ctx_ready(c))) return rc;
+  CK(hipStreamSynchronize(c->stream));      // inputs produced on the caller's stream
+  std::vector<int64_t> v0off(count);
+  int64_t v0tot = 0;
+  for (int b = 0; b < count; ++b) {
+    v0off[b] = v0tot;
+    v0tot += (int64_t)ops[b].nx * ops[b].ny;
     std::memset(&infos[b], 0, sizeof(infos[b]));
-    infos[b].matvecs = p;
+    infos[b].matvecs = ncv;
     infos[b].status = DCGS2_NOT_CONVERGED;
   }
-  std::vector<Ctrl> hctrl(count);
-  std::vector<dcgs2::BInst> tab_trunc;
-  std::vector<double> Hh((size_t)count * ld * ld), Zh((size_t)count * p * p);
-  int overall = DCGS2_OK;
-  const double CUT_GAP = 1e-8;
+  // two groups of similar total size: instances by decreasing m, dealt alternately
+  const int ngroups = count >= 2 ? 2 : 1;
+  std::vector<int> order(count);
+  for (int b = 0; b < count; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return (int64_t)ops[x].nx * ops[x].ny > (int64_t)ops[y].nx * ops[y].ny;
+  });
+  std::vector<BatchedGroup> groups(ngroups);
+  for (int i = 0; i < count; ++i) groups[i % ngroups].gid.push_back(order[i]);
+  for (auto& g : groups) std::sort(g.gid.begin(), g.gid.end());
+  for (auto& g : groups) {
+    if ((rc = group_setup(c, g, ops, v0, v0off, ncv))) return rc;
+    g.t_cycle = std::chrono::steady_clock::now();
+    if ((rc = batched_run_cycle(g.B, 2, c->tau, c->eta, use_graph != 0, &g.kernels))) return rc;
+    if ((rc = group_readback(g))) return rc;
+  }
+  const int nthreads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   for (;;) {
-    CK(hipMemcpyAsync(hctrl.data(), B.ctrl, sizeof(Ctrl) * count, hipMemcpyDeviceToHost, B.s));
-    CK(hipMemcpyAsync(Hh.data(), B.H, sizeof(double) * Hh.size(), hipMemcpyDeviceToHost, B.s));
-    CK(hipStreamSynchronize(B.s));
-    // per-instance dense work on host threads
-    const int nthreads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    std::vector<std::thread> pool;
-    std::atomic<int> next{0};
-    auto worker = [&]() {
-      std::vector<double> T((size_t)p * p), Zm((size_t)p * p), ere(p), eim(p);
-      for (int b = next++; b < count; b = next++) {
-        dcgs2::BInst& I = B.tab[b];
-        if (!I.active) continue;
-        dcgs2_ks_info& inf = infos[b];
-        inf.st.reductions += hctrl[b].reductions;
-        I.truncate = 0;
-        if (hctrl[b].state != ST_RUNNING) {
-          inf.status = hctrl[b].state == ST_BREAKDOWN ? DCGS2_BREAKDOWN
-                       : hctrl[b].state == ST_NONFINITE ? DCGS2_NONFINITE : DCGS2_NOT_CONVERGED;
-          if (hctrl[b].state == ST_FALLBACK) inf.st.pyth_fallbacks += 1;
-          inf.st.breakdown_step = hctrl[b].k;
-          I.active = 0;
-          continue;
-        }
-        const double* Hb = Hh.data() + (size_t)b * ld * ld;
-        const double h = Hb[(size_t)(p - 1) * ld + p];
-        for (int jj = 0; jj < p; ++jj)
-          for (int i = 0; i < p; ++i) T[(size_t)jj * p + i] = Hb[(size_t)jj * ld + i];
-        if (real_schur(p, T.data(), p, Zm.data(), p) != 0) { I.active = 0; continue; }
-        const int kn = reorder_schur_by_magnitude(p, T.data(), p, Zm.data(), p, nev, CUT_GAP);
-        if (kn < 0) { I.active = 0; continue; }
-        schur_eigenvalues(p, T.data(), p, ere.data(), eim.data());
-        double bn = 0.0, tmin = INFINITY;
-        for (int i = 0; i < kn; ++i) {
-          const double bi = h * Zm[(size_t)i * p + (p - 1)];
-          bn += bi * bi;
-          tmin = std::min(tmin, std::hypot(ere[i], eim[i]));
-        }
-        inf.resid = std::sqrt(bn) / tmin;
-        for (int i = 0; i < nev; ++i) {
-          eig_re[(size_t)b * nev + i] = ere[i];
-          eig_im[(size_t)b * nev + i] = eim[i];
-        }
-        if (inf.resid <= tol) { inf.nconv = kn; inf.status = DCGS2_OK; I.active = 0; continue; }
-        if (inf.restarts >= max_restarts) { inf.status = DCGS2_NOT_CONVERGED; I.active = 0; continue; }
-        const int k = reorder_schur_by_magnitude(p, T.data(), p, Zm.data(), p, keep, CUT_GAP);
-        if (k < 0 || k >= p) { I.active = 0; continue; }
-        std::copy(Zm.begin(), Zm.end(), Zh.begin() + (size_t)b * p * p);
-        double* Hn = Hh.data() + (size_t)b * ld * ld;
-        std::fill(Hn, Hn + (size_t)ld * ld, 0.0);
-        for (int jj = 0; jj < k; ++jj) {
-          for (int i = 0; i < k; ++i) Hn[(size_t)jj * ld + i] = T[(size_t)jj * p + i];
-          Hn[(size_t)jj * ld + k] = h * Zm[(size_t)jj * p + (p - 1)];
-        }
-        I.k = k;
-        I.first_j = k + 2;
-        I.restart = 1;
-        I.truncate = 1;
-        inf.restarts += 1;
-        inf.matvecs += p - k;
-      }
-    };
-    for (int t = 0; t < nthreads; ++t) pool.emplace_back(worker);
-    for (auto& t : pool) t.join();
-    int jmin = INT32_MAX;
-    for (int b = 0; b < count; ++b)
-      if (B.tab[b].active) jmin = std::min(jmin, B.tab[b].first_j);
-    if (jmin == INT32_MAX) break;
-    // truncation: Qn = Q Z_k, q_{k+1} and w; then swap the bases of truncated instances
-    CK(hipMemcpyAsync(B.Z, Zh.data(), sizeof(double) * Zh.size(), hipMemcpyHostToDevice, B.s));
-    CK(hipMemcpyAsync(B.H, Hh.data(), sizeof(double) * Hh.size(), hipMemcpyHostToDevice, B.s));
-    CK(launch_fill(B.K, (int64_t)count * ld * ld, 0.0, B.s));
-    // the truncation reads this copy of the table; the swapped table below is uploaded
-    // from a different host buffer, and neither changes before the next synchronisation
-    tab_trunc = B.tab;
-    CK(hipMemcpyAsync(B.d_tab, tab_trunc.data(), sizeof(dcgs2::BInst) * count,
-                      hipMemcpyHostToDevice, B.s));
-    CK(launch_btruncate(B.d_tab, B.d_pre_rows, count, B.nb_rows, p, B.s));
-    kernels += 2;
-    for (int b = 0; b < count; ++b) {
-      dcgs2::BInst& I = B.tab[b];
-      if (I.active && I.truncate) { std::swap(I.Q, I.Qn); I.truncate = 0; }
+    bool any = false;
+    for (auto& g : groups) {
+      if (g.done) continue;
+      any = true;
+      if ((rc = group_step(c, g, nev, keep, tol, max_restarts, eig_re, eig_im, infos,
+                           use_graph != 0, nthreads)))
+        return rc;
     }
-    CK(hipMemcpyAsync(B.d_tab, B.tab.data(), sizeof(dcgs2::BInst) * count, hipMemcpyHostToDevice,
-                      B.s));
-    if ((rc = batched_run_cycle(B, jmin, c->tau, c->eta, use_graph != 0, &kernels))) return rc;
+    if (!any) break;
+  }
+  int overall = DCGS2_OK;
+  int kernels = 0;
+  for (auto& g : groups) {
+    CK(hipStreamSynchronize(g.B.s));
+    kernels += g.kernels;
   }
   for (int b = 0; b < count; ++b) {
     infos[b].st.kernels = kernels;
     if (infos[b].status != DCGS2_OK) overall = DCGS2_NOT_CONVERGED;
     if (infos[b].status == DCGS2_OK) infos[b].st.breakdown_step = -1;
   }
-  CK(hipStreamSynchronize(B.s));
   return overall;
 }

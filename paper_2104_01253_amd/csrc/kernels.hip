@@ -383,9 +383,9 @@ void reduce_grid(int64_t m, int gmax, int* G, int* GS, int* NG) {
   const int64_t units = (m + 1) / 2;
   int64_t g = (units + (int64_t)BS * 4 - 1) / ((int64_t)BS * 4);
   if (g < 1) g = 1;
-  // default: at most 512 workgroups (two per CU); measured best for the
+  // default: at most 256 workgroups (one per CU); measured best for the
   // 16-column sweeps at m = 2e6 (the tuning knob overrides it)
-  if (g > (gmax > 0 ? gmax : 512)) g = gmax > 0 ? gmax : 512;
+  if (g > (gmax > 0 ? gmax : 256)) g = gmax > 0 ? gmax : 256;
   if (g > REDUCE_GMAX) g = REDUCE_GMAX;
   *G = (int)g;
   *GS = (int)(g < REDUCE_GSMAX ? g : REDUCE_GSMAX);

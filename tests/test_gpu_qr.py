@@ -141,3 +141,28 @@ def test_cgs2_comparator_parity(ctx, m, n, ce):
     assert relnorm(R, Rr) <= TOL
     assert np.linalg.norm((host(Qd) - Qr) @ Rr) / np.linalg.norm(B) <= TOL
     assert loss_of_orthogonality(host(Qd)) <= 1e-13
+
+
+@pytest.mark.parametrize("min_j", [8, 200])
+@pytest.mark.parametrize("m,n,ce", [(1000, 2, 2), (4097, 17, 8), (20011, 64, 8), (3000, 100, 4)])
+def test_qr_hybrid_schedule_parity(ctx, m, n, ce, min_j):
+    """One-pass schedule with the first min_j steps as separate update and
+    reduction passes (min_j beyond n: every step separate); the forced-fallback
+    path resumes inside the hybrid schedule too."""
+    say(f"qr hybrid m={m} n={n} min_j={min_j}")
+    B = synth.tall_skinny(m, n, ce, seed_g=300 + m, seed_v=9)
+    ref = gs.dcgs2_qr(B)
+    ctx.set_tuning(binding.TUNE_FUSED_MIN_J, min_j)
+    try:
+        Q, R, rc, st = run_qr(ctx, B)
+        ctx.set_tolerances(1.0, 1e-12)
+        Qf, Rf, rcf, stf = run_qr(ctx, B)
+    finally:
+        ctx.set_tolerances(1e-8, 1e-12)
+        ctx.set_tuning(binding.TUNE_FUSED_MIN_J, 0)
+    assert rc == 0 and st["reductions"] == ref["reductions"]
+    assert relnorm(R, ref["R"]) <= TOL
+    assert np.linalg.norm((Q - ref["Q"]) @ ref["R"]) / np.linalg.norm(B) <= TOL
+    reff = gs.dcgs2_qr(B, tau=1.0)
+    assert rcf == 0 and stf["pyth_fallbacks"] == reff["fallbacks"]
+    assert relnorm(Rf, reff["R"]) <= TOL
