@@ -26,12 +26,15 @@ ROOT = os.path.dirname(HERE)
 COPY_BYTES = 1 << 30     # 1 GiB read + 1 GiB written
 
 
-def run(workload: str, reps: int):
+def run(workload: str, reps: int, tuning=None):
     import torch
     sys.path.insert(0, ROOT)
     from paper_2104_01253_amd import binding, synth
     torch.cuda.set_device(0)
     ctx = binding.Context(0)
+    for key, value in (tuning or {}).items():
+        if value is not None:
+            ctx.set_tuning(getattr(binding, key), value)
     if workload == "qr":
         m, n = 2_000_000, 100
         B = binding.colmajor_from_numpy(synth.tall_skinny(m, n, 8.0))
@@ -171,6 +174,9 @@ def main():
     r = sub.add_parser("run")
     r.add_argument("--workload", default="qr")
     r.add_argument("--reps", type=int, default=1)
+    r.add_argument("--fused-waves", type=int, default=None)
+    r.add_argument("--reduce-grid", type=int, default=None)
+    r.add_argument("--fused-min-j", type=int, default=None)
     s = sub.add_parser("summarize")
     s.add_argument("--fetch", required=True)
     s.add_argument("--write", required=True)
@@ -179,7 +185,9 @@ def main():
     s.add_argument("--command", default="")
     a = ap.parse_args()
     if a.cmd == "run":
-        run(a.workload, a.reps)
+        run(a.workload, a.reps, {"TUNE_FUSED_WAVES": a.fused_waves,
+                                 "TUNE_REDUCE_GRID": a.reduce_grid,
+                                 "TUNE_FUSED_MIN_J": a.fused_min_j})
     else:
         summarize(a.fetch, a.write, a.trace, a.out, a.command)
 
