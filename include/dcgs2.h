@@ -186,6 +186,15 @@ int dcgs2_arnoldi_q32(dcgs2_ctx ctx, const dcgs2_op* A, const double* r0, int32_
 int cgs2_qr(dcgs2_ctx ctx, int64_t m, int32_t n, const double* B, int64_t ldb, double* Q,
             int64_t ldq, double* R_host, int32_t ldr, dcgs2_stats* st);
 
+/* Comparator: modified Gram-Schmidt, column by column (the classical sequential
+ * form the paper takes as its baseline, Sec. 2): for column j, w = a_j; for each
+ * k < j, r_kj = q_k^T w (one global reduction) and w -= r_kj q_k; alpha = ||w||
+ * (one reduction); q_j = w / alpha -- n(n+1)/2 reductions.  Same arguments,
+ * layout, ownership and status codes as dcgs2_qr (FP64 basis only); breakdown
+ * when alpha <= eta ||a_j||. */
+int mgs_qr(dcgs2_ctx ctx, int64_t m, int32_t n, const double* B, int64_t ldb, double* Q,
+           int64_t ldq, double* R_host, int32_t ldr, dcgs2_stats* st);
+
 /* Storage precision (64 = FP64, default; 32 = FP32) of the internal Krylov bases
  * of gmres_solve and krylov_schur_eigs; x, r, H, the Givens and Schur work and
  * all reductions stay FP64.  Returns DCGS2_EINVAL for other values. */

@@ -690,6 +690,49 @@ int cgs2_qr(dcgs2_ctx c, int64_t m, int32_t n, const double* B, int64_t ldb, dou
   return status;
 }
 
+int mgs_qr(dcgs2_ctx c, int64_t m, int32_t n, const double* B, int64_t ldb, double* Q,
+           int64_t ldq, double* R_host, int32_t ldr, dcgs2_stats* st) {
+  if (!c || m < 1 || n < 1 || n > DCGS2_MAX_N || (int64_t)n > m || !B || !Q || !R_host ||
+      ldb < m || ldq < m || ldr < n)
+    return DCGS2_EINVAL;
+  int rc;
+  if ((rc = ctx_ready(c))) return rc;
+  if ((rc = ensure_vectors(c, m))) return rc;
+  c->kernels = 0;
+  Expansion e;
+  e.qr = true;
+  e.m = m;
+  e.Q = Q; e.q32 = 0; e.ldq = ldq; e.B = B; e.ldb = ldb;
+  e.ldh = n;
+  if ((rc = setup_expansion(c, e, 0.0))) return rc;
+  CKL(launch_fill(c->R, (int64_t)n * n, 0.0, c->stream));
+  hipStream_t s = c->stream;
+  const double vm = 8.0 * (double)m;
+  // classical column-by-column MGS (the paper's Sec. 2 baseline): for column j,
+  // w = a_j; for k < j: r = q_k^T w (one reduction), w -= r q_k; alpha = ||w||
+  // (one reduction); q_j = w / alpha -- n(n+1)/2 reductions in all.
+  for (int j = 0; j < n; ++j) {
+    CKL(launch_copy(c->w, B + (int64_t)j * ldb, m, s));
+    for (int k = 0; k < j; ++k) {
+      const double* qk = Q + (int64_t)k * ldq;
+      KL(K_REDUCE, vm * 2,
+         launch_reduce(qk, 0, ldq, 1, c->w, nullptr, m, e.gr, e.fin(FIN_MGS_DOT, j, k), s));
+      // w -= r q_k in place (the pass also forms ||w||^2 partials, unused)
+      KL(K_PROJNORM, vm * 3,
+         launch_project_norm(qk, 0, ldq, 1, c->w, c->w, m, e.gr, e.fin(FIN_NONE, j, 1), s));
+    }
+    KL(K_REDUCE, vm,
+       launch_reduce(Q, 0, ldq, 0, c->w, nullptr, m, e.gr, e.fin(FIN_MGS_NORM, j, 0), s));
+    KL(K_SCALE, vm * 2, launch_scale_col(Q, 0, ldq, j, c->w, m, c->coef, LDC, c->ctrl, s));
+  }
+  Ctrl sc{};
+  if ((rc = read_ctrl(c, &sc))) return rc;
+  const int status = status_of(sc);
+  if ((rc = copy_to_host(c, c->R, n, n, n, R_host, ldr))) return rc;
+  fill_stats(st, sc, c->kernels, status);
+  return status;
+}
+
 int dcgs2_set_basis_precision(dcgs2_ctx c, int bits) {
   if (!c || (bits != 32 && bits != 64)) return DCGS2_EINVAL;
   c->basis_q32 = bits == 32;

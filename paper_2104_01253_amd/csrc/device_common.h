@@ -378,6 +378,43 @@ __device__ void finalize(const FinArgs& f, double* red, double* T, double* scrat
       }
       return;
     }
+    case FIN_MGS_DOT: {                    // r = q_k^T w, w^T w (k = J, column j)
+      if (threadIdx.x == 0) {
+        ctrl->reductions += 1;
+        const double r = red[0];
+        if (!finite(r) || !finite(red[1])) {
+          ctrl->state = ST_NONFINITE;
+          ctrl->stop_step = j;
+        } else {
+          f.R[(int64_t)j * f.ldr + J] = r;
+          f.coef[0] = r;
+          if (J == 0) ctrl->rho_next = sqrt(red[1]);    // ||a_j|| before any projection
+        }
+      }
+      return;
+    }
+    case FIN_MGS_NORM: {                   // alpha = ||w|| closes column j
+      if (threadIdx.x == 0) {
+        ctrl->reductions += 1;
+        const double alpha = sqrt(red[0]);
+        const double rho = j == 0 ? alpha : ctrl->rho_next;
+        if (!finite(alpha)) {
+          ctrl->state = ST_NONFINITE;
+          ctrl->stop_step = j;
+        } else {
+          f.R[(int64_t)j * f.ldr + j] = alpha;
+          f.coef[2 * f.ldc] = alpha;
+          if (alpha <= ctrl->eta * rho || alpha == 0.0) {
+            ctrl->state = ST_BREAKDOWN;
+            ctrl->stop_step = j;
+            ctrl->k = j;
+          } else {
+            ctrl->k = j + 1;
+          }
+        }
+      }
+      return;
+    }
     case FIN_LAST1: {                      // c = Q^T w (and w^T w)
       any_nonfinite(red, J + 1, &s_flag);
       if (threadIdx.x == 0) {

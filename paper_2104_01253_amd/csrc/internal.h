@@ -44,6 +44,8 @@ enum FinKind : int {
   FIN_NORM = 5,        // plain squared norm into ctrl->norm2
   FIN_NONE = 6,        // no scalar work (a projection whose norm is not needed)
   FIN_CGS2_S = 7,      // CGS2 first projection: S = Q^T a into coef and Sprev, rho = ||a||
+  FIN_MGS_DOT = 8,     // MGS: r = q_k^T w into R(k, j) and coef[0] (J = k, j = column)
+  FIN_MGS_NORM = 9,    // MGS: alpha = ||w|| into R(j, j) and the coefficient block
 };
 
 struct FinArgs {

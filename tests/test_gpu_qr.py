@@ -143,6 +143,28 @@ def test_cgs2_comparator_parity(ctx, m, n, ce):
     assert loss_of_orthogonality(host(Qd)) <= 1e-13
 
 
+@pytest.mark.parametrize("m,n,ce", [(4097, 17, 2), (20011, 40, 2), (3001, 12, 6)])
+def test_mgs_comparator_parity(ctx, m, n, ce):
+    """The MGS comparator against the oracle's MGS: n(n+1)/2 reductions; R and Q to
+    1e-12 at kappa ~ 1e2; at kappa ~ 1e6 both lose orthogonality at the MGS rate
+    O(eps kappa) (Tab. loss_of_orth) while R stays a backward-stable factor."""
+    B = synth.tall_skinny(m, n, ce, seed_g=500 + m, seed_v=5)
+    Bd = dev_matrix(B)
+    Qd = binding.colmajor_empty(m, n)
+    R, rc, st = ctx.mgs_qr(Bd, Qd)
+    Qr, Rr, red = gs.mgs_qr(B)
+    Q = host(Qd)
+    assert rc == 0 and st["reductions"] == red == n * (n + 1) // 2
+    assert relnorm(R, Rr) <= (TOL if ce <= 2 else 1e-9)
+    assert qr_error(B, Q, R) <= 1e-14
+    if ce <= 2:
+        assert np.linalg.norm(Q - Qr) / np.sqrt(n) <= TOL
+    else:
+        lo_gpu, lo_ref = loss_of_orthogonality(Q), loss_of_orthogonality(Qr)
+        say("mgs LOO gpu", lo_gpu, "oracle", lo_ref)
+        assert 1e-13 < lo_gpu < 1e-6 and 0.1 < lo_gpu / lo_ref < 10
+
+
 @pytest.mark.parametrize("min_j", [8, 200])
 @pytest.mark.parametrize("m,n,ce", [(1000, 2, 2), (4097, 17, 8), (20011, 64, 8), (3000, 100, 4)])
 def test_qr_hybrid_schedule_parity(ctx, m, n, ce, min_j):
