@@ -237,6 +237,11 @@ def main():
         Tc = timed(torch, cgs2_once, 3) / 3
         out["cgs2_qr"] = {"steps_per_s": round(n / Tc, 1), "ms": round(Tc * 1e3, 3),
                           "dcgs2_speedup": round(Tc / (ms_per_step * 1e-3), 3)}
+        # the column-by-column MGS comparator (n(n+1)/2 reductions), once
+        mgs_once = lambda: ctx.mgs_qr(Bd, Qd)
+        Tm = timed(torch, mgs_once, 1)
+        out["mgs_qr"] = {"steps_per_s": round(n / Tm, 1), "ms": round(Tm * 1e3, 3),
+                         "dcgs2_speedup": round(Tm / (ms_per_step * 1e-3), 3)}
         # FP32-stored basis, FP64 reductions (same B)
         Q32 = binding.colmajor_empty(m, n, dtype=torch.float32)
 
@@ -247,7 +252,7 @@ def main():
         T32 = timed(torch, q32_once, 3) / 3
         out["qr_fp32_basis"] = {"steps_per_s": round(n / T32, 1), "ms": round(T32 * 1e3, 3)}
         del Q32
-        log(f"[bench] cgs2 {out['cgs2_qr']}, fp32 basis {out['qr_fp32_basis']}")
+        log(f"[bench] cgs2 {out['cgs2_qr']}, mgs {out['mgs_qr']}, fp32 basis {out['qr_fp32_basis']}")
     del Bd, Qd
     torch.cuda.empty_cache()
 

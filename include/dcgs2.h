@@ -283,10 +283,11 @@ int krylov_schur_batched(dcgs2_ctx ctx, int32_t count, const dcgs2_stencil2d* op
  *   prolongation  P : tensor-product linear interpolation of the values at the
  *                     coarse block centres, zero at the Dirichlet boundary;
  *   features        : [R(b)/s, operator parameters, zero padding], s = RMS of R(b);
- *   guess           : x0 = s * P(MLP(features)).
+ *   guess           : x0 = (s / gain) * P(MLP(features)).
  * The perceptron (FP32; Z_l = X_l W_l + b_l, ReLU on hidden layers, linear
- * output) is trained with the mean squared error on targets R(x)/s of solved
- * instances and Adam (Kingma & Ba, 2015).  Its products run on the matrix cores.
+ * output) is trained with the mean squared error on targets gain * R(x)/s of
+ * solved instances and Adam (Kingma & Ba, 2015); gain > 0 brings the targets to
+ * order one.  Its products run on the matrix cores.
  * Arrays marked device are caller-owned device memory; samples are rows
  * (row-major, sample-major).  All calls synchronise the context's stream.
  * ---------------------------------------------------------------------------------- */
@@ -319,12 +320,14 @@ int dcgs2_mlp_adam(dcgs2_mlp mlp, float lr, float beta1, float beta2, float eps)
  * and scale (device, count doubles).  nc <= 64. */
 int dcgs2_guess_features(dcgs2_ctx ctx, int32_t count, int32_t n, int32_t nc, const double* b,
                          const float* prm, int32_t np, int32_t fdim, float* feat, double* scale);
-/* Training targets t = R(x)/scale (device, count x nc*nc floats; zero where scale = 0). */
+/* Training targets t = gain R(x)/scale (device, count x nc*nc floats; zero where
+ * scale = 0; gain finite and > 0). */
 int dcgs2_guess_targets(dcgs2_ctx ctx, int32_t count, int32_t n, int32_t nc, const double* x,
-                        const double* scale, float* t);
-/* x0 = scale * P(y): y device count x nc*nc floats, x0 device count x n*n doubles. */
+                        const double* scale, double gain, float* t);
+/* x0 = (scale / gain) P(y): y device count x nc*nc floats, x0 device count x n*n
+ * doubles. */
 int dcgs2_guess_prolong(dcgs2_ctx ctx, int32_t count, int32_t n, int32_t nc, const float* y,
-                        const double* scale, double* x0);
+                        const double* scale, double gain, double* x0);
 /* Zero-guess fallback: ratio = ||b - A x0|| / ||b|| (host, may be NULL); keeps x0
  * (kept = 1) when the ratio is finite and below max_ratio (> 0), otherwise sets
  * x0 = 0 (kept = 0).  A coarse guess leaves interpolation kinks whose residual

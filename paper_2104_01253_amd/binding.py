@@ -121,7 +121,7 @@ def load(path: str = LIB_PATH):
     lib.dcgs2_guess_features.argtypes = [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p,
                                          c_int32, c_int32, c_void_p, c_void_p]
     lib.dcgs2_guess_targets.argtypes = [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p,
-                                        c_void_p]
+                                        c_double, c_void_p]
     lib.dcgs2_guess_prolong.argtypes = lib.dcgs2_guess_targets.argtypes
     lib.dcgs2_guess_guard.argtypes = [c_void_p, POINTER(Op), c_void_p, c_void_p, c_double,
                                       c_i32p, POINTER(c_double)]
@@ -514,23 +514,24 @@ class Context:
             raise DCGS2Error(rc, "dcgs2_guess_features")
         return feat, scale
 
-    def guess_targets(self, x, scale, n: int, nc: int):
+    def guess_targets(self, x, scale, n: int, nc: int, gain: float = 1.0):
         import torch
         count = x.shape[0]
         t = torch.empty((count, nc * nc), dtype=torch.float32, device=x.device)
         rc = self._lib.dcgs2_guess_targets(self._h, count, n, nc, _ptr(x, torch.float64),
-                                           _ptr(scale, torch.float64), t.data_ptr())
+                                           _ptr(scale, torch.float64), gain, t.data_ptr())
         if rc != OK:
             raise DCGS2Error(rc, "dcgs2_guess_targets")
         return t
 
-    def guess_prolong(self, y, scale, n: int, nc: int, out=None):
+    def guess_prolong(self, y, scale, n: int, nc: int, gain: float = 1.0, out=None):
         import torch
         count = y.shape[0]
         x0 = out if out is not None else torch.empty((count, n * n), dtype=torch.float64,
                                                      device=y.device)
         rc = self._lib.dcgs2_guess_prolong(self._h, count, n, nc, _ptr(y, torch.float32),
-                                           _ptr(scale, torch.float64), _ptr(x0, torch.float64))
+                                           _ptr(scale, torch.float64), gain,
+                                           _ptr(x0, torch.float64))
         if rc != OK:
             raise DCGS2Error(rc, "dcgs2_guess_prolong")
         return x0

@@ -208,9 +208,10 @@ __global__ __launch_bounds__(256) void features_kernel(int n, int nc, const doub
   if (threadIdx.x == 0) scale[inst] = s;
 }
 
-// Training targets: t = R(x) / s (zero when s = 0); one thread per coarse point.
+// Training targets: t = gain R(x) / s (zero when s = 0); one thread per coarse point.
 __global__ void targets_kernel(int count, int n, int nc, const double* __restrict__ x,
-                               const double* __restrict__ scale, float* __restrict__ t) {
+                               const double* __restrict__ scale, double gain,
+                               float* __restrict__ t) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= (int64_t)count * nc * nc) return;
   const int inst = (int)(g / (nc * nc));
@@ -223,7 +224,7 @@ __global__ void targets_kernel(int count, int n, int nc, const double* __restric
     for (int xx = 0; xx < r; ++xx) s += xi[(int64_t)(J * r + y) * n + I * r + xx];
   s /= (double)(r * r);
   const double sc = scale[inst];
-  t[g] = sc > 0.0 ? (float)(s / sc) : 0.f;
+  t[g] = sc > 0.0 ? (float)(gain * s / sc) : 0.f;
 }
 
 // 1-D interpolation weights of fine point i: value = wl * c[kl] + wr * c[kl + 1],
@@ -255,9 +256,10 @@ __device__ __forceinline__ void interp_1d(int i, int n, int nc, int* kl, double*
   }
 }
 
-// x0 = s * P(y): one thread per fine point.
+// x0 = (s / gain) P(y): one thread per fine point.
 __global__ void prolong_kernel(int count, int n, int nc, const float* __restrict__ y,
-                               const double* __restrict__ scale, double* __restrict__ x0) {
+                               const double* __restrict__ scale, double gain,
+                               double* __restrict__ x0) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= (int64_t)count * n * n) return;
   const int inst = (int)(g / ((int64_t)n * n));
@@ -273,7 +275,7 @@ __global__ void prolong_kernel(int count, int n, int nc, const float* __restrict
   };
   const double v = wyl * (wxl * at(kx, ky) + wxr * at(kx + 1, ky)) +
                    wyr * (wxl * at(kx, ky + 1) + wxr * at(kx + 1, ky + 1));
-  x0[g] = scale[inst] * v;
+  x0[g] = (scale[inst] / gain) * v;
 }
 
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -335,16 +337,16 @@ hipError_t launch_features(int count, int n, int nc, const double* b, const floa
 }
 
 hipError_t launch_targets(int count, int n, int nc, const double* x, const double* scale,
-                          float* t, hipStream_t s) {
+                          double gain, float* t, hipStream_t s) {
   targets_kernel<<<blocks_for((int64_t)count * nc * nc, 256), 256, 0, s>>>(count, n, nc, x, scale,
-                                                                          t);
+                                                                          gain, t);
   return hipGetLastError();
 }
 
 hipError_t launch_prolong(int count, int n, int nc, const float* y, const double* scale,
-                          double* x0, hipStream_t s) {
+                          double gain, double* x0, hipStream_t s) {
   prolong_kernel<<<blocks_for((int64_t)count * n * n, 256), 256, 0, s>>>(count, n, nc, y, scale,
-                                                                         x0);
+                                                                         gain, x0);
   return hipGetLastError();
 }
 

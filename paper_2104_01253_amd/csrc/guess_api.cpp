@@ -229,25 +229,27 @@ int dcgs2_guess_features(dcgs2_ctx ctx, int32_t count, int32_t n, int32_t nc, co
 }
 
 int dcgs2_guess_targets(dcgs2_ctx ctx, int32_t count, int32_t n, int32_t nc, const double* x,
-                        const double* scale, float* t) {
-  if (!ctx || !x || !scale || !t || count < 1 || nc < 1 || n < nc || n % nc != 0)
+                        const double* scale, double gain, float* t) {
+  if (!ctx || !x || !scale || !t || count < 1 || nc < 1 || n < nc || n % nc != 0 ||
+      !(gain > 0.0) || !std::isfinite(gain))
     return DCGS2_EINVAL;
   hipStream_t s;
   int rc = ctx_prepare(ctx, &s);
   if (rc) return rc;
-  CK(launch_targets(count, n, nc, x, scale, t, s));
+  CK(launch_targets(count, n, nc, x, scale, gain, t, s));
   CK(hipStreamSynchronize(s));
   return DCGS2_OK;
 }
 
 int dcgs2_guess_prolong(dcgs2_ctx ctx, int32_t count, int32_t n, int32_t nc, const float* y,
-                        const double* scale, double* x0) {
-  if (!ctx || !y || !scale || !x0 || count < 1 || nc < 2 || n < nc || n % nc != 0)
+                        const double* scale, double gain, double* x0) {
+  if (!ctx || !y || !scale || !x0 || count < 1 || nc < 2 || n < nc || n % nc != 0 ||
+      !(gain > 0.0) || !std::isfinite(gain))
     return DCGS2_EINVAL;
   hipStream_t s;
   int rc = ctx_prepare(ctx, &s);
   if (rc) return rc;
-  CK(launch_prolong(count, n, nc, y, scale, x0, s));
+  CK(launch_prolong(count, n, nc, y, scale, gain, x0, s));
   CK(hipStreamSynchronize(s));
   return DCGS2_OK;
 }

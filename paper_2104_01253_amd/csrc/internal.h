@@ -182,9 +182,9 @@ hipError_t launch_adam(int64_t n, float* theta, const float* g, float* m, float*
 hipError_t launch_features(int count, int n, int nc, const double* b, const float* prm, int np,
                            int fdim, float* feat, double* scale, hipStream_t s);
 hipError_t launch_targets(int count, int n, int nc, const double* x, const double* scale,
-                          float* t, hipStream_t s);
+                          double gain, float* t, hipStream_t s);
 hipError_t launch_prolong(int count, int n, int nc, const float* y, const double* scale,
-                          double* x0, hipStream_t s);
+                          double gain, double* x0, hipStream_t s);
 
 // Context access for the other host sources of the library: makes the context's
 // device current (allocating its workspace on first use) and returns its stream.

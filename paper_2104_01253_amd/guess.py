@@ -8,7 +8,7 @@ marshals arguments, assembles the operator's CSR arrays and batches samples):
 
   features  f = [R(b)/s, xi, v/10, 0...]       (dcgs2_guess_features)
   network   y = MLP(f)                          (dcgs2_mlp_forward, FP32 matrix cores)
-  guess     x0 = s P(y)                         (dcgs2_guess_prolong)
+  guess     x0 = (s / gain) P(y)                (dcgs2_guess_prolong)
   fallback  x0 = 0 unless ||b - A x0|| < 10 ||b||   (dcgs2_guess_guard)
 
 Training data are GMRES(50) solutions of seeded instances of the family
@@ -29,6 +29,10 @@ N, NC = 256, 32
 NPARAM = len(synth.KL_MODES) + 2            # xi and the two velocity components
 FDIM = NC * NC + 16                         # features padded to a multiple of 16
 WIDTHS = (FDIM, 512, 512, NC * NC)
+# Targets are gain R(x)/s: with s the RMS of R(b) they have an RMS near 1/70 on this
+# family, so gain = 64 brings them to order one, the scale of a He-initialised
+# network's outputs (unscaled targets leave the network at its initial output).
+GAIN = 64.0
 DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data",
                                "guess_mlp_256.npz")
 
@@ -104,7 +108,7 @@ class GuessModel:
         """b: CUDA float64 (count, N*N); prm: CUDA float32 (count, NPARAM) -> x0 (count, N*N)."""
         feat, scale = self.ctx.guess_features(b, prm, N, NC, FDIM)
         y = self.mlp.forward(feat)
-        return self.ctx.guess_prolong(y, scale, N, NC)
+        return self.ctx.guess_prolong(y, scale, N, NC, GAIN)
 
     def save(self, path, **meta):
         os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
@@ -130,7 +134,7 @@ def solve(ctx, prob, b_dev, x0=None, rtol=1e-8, restart=50, max_iters=20000):
     return x, rc, info, time.perf_counter() - t0
 
 
-def generate(ctx, count, seed, rtol=1e-6, max_iters=8000, log=None):
+def generate(ctx, count, seed, rtol=1e-5, max_iters=6000, log=None):
     """Features and targets of the solved instances among `count` seeded ones
     (device tensors).  An instance whose GMRES(50) does not reach rtol within
     max_iters iterations is left out (restarted GMRES can stagnate on this family);
@@ -148,18 +152,32 @@ def generate(ctx, count, seed, rtol=1e-6, max_iters=8000, log=None):
         if rc == binding.OK:
             f, s = ctx.guess_features(b[None], prm[None], N, NC, FDIM)
             feats[kept] = f[0]
-            targs[kept] = ctx.guess_targets(x[None], s, N, NC)[0]
+            targs[kept] = ctx.guess_targets(x[None], s, N, NC, GAIN)[0]
             kept += 1
         if log and (i + 1) % 256 == 0:
             log(f"solved {i + 1}/{count}: kept {kept}, median {int(np.median(iters))} iterations")
     return feats[:kept].contiguous(), targs[:kept].contiguous()
 
 
-def train(model, feats, targs, epochs=60, batch=256, lr=1e-3, seed=0, log=None):
+def validate(model, vf, vt):
+    """Relative error ||MLP(vf) - vt|| / ||vt|| on a held-out set (chunks of max_batch)."""
+    num = den = 0.0
+    for s in range(0, vf.shape[0], model.mlp.max_batch):
+        y = model.mlp.forward(vf[s:s + model.mlp.max_batch].contiguous())
+        t = vt[s:s + model.mlp.max_batch]
+        num += float(((y - t) ** 2).sum())
+        den += float((t ** 2).sum())
+    return (num / max(den, 1e-300)) ** 0.5
+
+
+def train(model, feats, targs, epochs=60, batch=256, lr=1e-3, seed=0, log=None, val=None):
+    """Adam on minibatches; with val = (features, targets) the parameters with the
+    lowest validation error (checked every 10 epochs) are kept."""
     import torch
     g = synth.rng(seed)
     count = feats.shape[0]
     hist = []
+    best = (float("inf"), None)
     for ep in range(epochs):
         perm = torch.from_numpy(g.permutation(count)).cuda()
         tot, nb = 0.0, 0
@@ -172,8 +190,17 @@ def train(model, feats, targs, epochs=60, batch=256, lr=1e-3, seed=0, log=None):
             model.mlp.adam(step_lr)
             nb += 1
         hist.append(tot / max(nb, 1))
-        if log and (ep % 10 == 9 or ep == epochs - 1):
-            log(f"epoch {ep + 1}: train mse {hist[-1]:.4e}")
+        if ep % 10 == 9 or ep == epochs - 1:
+            msg = f"epoch {ep + 1}: train mse {hist[-1]:.4e}"
+            if val is not None:
+                err = validate(model, *val)
+                if err < best[0]:
+                    best = (err, model.mlp.get_params())
+                msg += f", validation relative error {err:.4f}"
+            if log:
+                log(msg)
+    if best[1] is not None:
+        model.mlp.set_params(best[1])
     return hist
 
 
@@ -200,13 +227,12 @@ def main(argv=None):
     feats, targs = generate(ctx, a.count, a.seed, log=log)
     vf, vt = generate(ctx, a.val, a.seed + 1, log=log)
     log(f"data: {time.perf_counter() - t0:.1f} s")
-    hist = train(model, feats, targs, a.epochs, lr=a.lr, log=log)
-    y = model.mlp.forward(vf)
-    val = float(((y - vt) ** 2).mean())
-    rel = float(((y - vt) ** 2).sum().sqrt() / (vt ** 2).sum().sqrt())
-    log(f"validation mse {val:.4e}, relative error {rel:.4f}")
-    model.save(a.out, train_mse=hist[-1], val_mse=val, val_rel=rel, count=a.count,
-               seed=a.seed, epochs=a.epochs)
+    hist = train(model, feats, targs, a.epochs, lr=a.lr, log=log, val=(vf, vt))
+    rel = validate(model, vf, vt)
+    log(f"kept parameters: validation relative error {rel:.4f} "
+        f"({feats.shape[0]} training and {vf.shape[0]} validation instances)")
+    model.save(a.out, train_mse=hist[-1], val_rel=rel, count=a.count, kept=feats.shape[0],
+               seed=a.seed, epochs=a.epochs, gain=GAIN)
     log(f"saved {a.out}")
 
 

@@ -143,8 +143,10 @@ def test_guess_argument_validation(ctx):
     assert lib.dcgs2_mlp_adam(None, 1e-3, 0.9, 0.999, 1e-8) == E
     assert lib.dcgs2_guess_features(h, 1, 30, 4, FAKE, FAKE, 2, 18, FAKE, FAKE) == E   # 30 % 4
     assert lib.dcgs2_guess_features(h, 1, 32, 4, FAKE, FAKE, 2, 17, FAKE, FAKE) == E   # fdim
-    assert lib.dcgs2_guess_targets(h, 0, 32, 4, FAKE, FAKE, FAKE) == E                 # count
-    assert lib.dcgs2_guess_prolong(h, 1, 32, 1, FAKE, FAKE, FAKE) == E                 # nc < 2
+    assert lib.dcgs2_guess_targets(h, 0, 32, 4, FAKE, FAKE, 1.0, FAKE) == E            # count
+    assert lib.dcgs2_guess_targets(h, 1, 32, 4, FAKE, FAKE, 0.0, FAKE) == E            # gain
+    assert lib.dcgs2_guess_prolong(h, 1, 32, 1, FAKE, FAKE, 1.0, FAKE) == E            # nc < 2
+    assert lib.dcgs2_guess_prolong(h, 1, 32, 4, FAKE, FAKE, -2.0, FAKE) == E           # gain
     op = binding.stencil_op((8, 8), 1.0, (1.0, 1.0))
     kept = ctypes.c_int32()
     assert lib.dcgs2_guess_guard(h, ctypes.byref(op), FAKE, FAKE, 0.0, ctypes.byref(kept),

@@ -111,15 +111,17 @@ def test_features_targets_and_prolongation(ctx, n, nc):
         f, s = G.features(b[i], prm[i].astype(np.float64), n, nc, fdim)
         assert abs(scale_h[i] - s) <= 1e-14 * max(s, 1e-300)
         assert np.max(np.abs(feat[i] - f)) <= 1e-6 * max(np.max(np.abs(f)), 1.0)
-    t = ctx.guess_targets(torch.from_numpy(x).cuda(), scale, n, nc).cpu().numpy()
+    gain = 64.0
+    t = ctx.guess_targets(torch.from_numpy(x).cuda(), scale, n, nc, gain).cpu().numpy()
     for i in range(count):
-        want = G.restrict(x[i], n, nc) / scale_h[i] if scale_h[i] > 0 else np.zeros(nc * nc)
+        want = (gain * G.restrict(x[i], n, nc) / scale_h[i] if scale_h[i] > 0
+                else np.zeros(nc * nc))
         assert np.max(np.abs(t[i] - want)) <= 1e-6 * max(np.max(np.abs(want)), 1.0)
     y = g.standard_normal((count, nc * nc)).astype(np.float32)
     sc = torch.tensor([1.0, 2.5, 0.0], dtype=torch.float64, device="cuda")
-    x0 = ctx.guess_prolong(torch.from_numpy(y).cuda(), sc, n, nc).cpu().numpy()
+    x0 = ctx.guess_prolong(torch.from_numpy(y).cuda(), sc, n, nc, gain).cpu().numpy()
     for i in range(count):
-        want = float(sc[i]) * G.prolong(y[i].astype(np.float64), n, nc)
+        want = float(sc[i]) / gain * G.prolong(y[i].astype(np.float64), n, nc)
         assert np.max(np.abs(x0[i] - want)) <= 1e-13 * max(np.max(np.abs(want)), 1.0)
 
 
