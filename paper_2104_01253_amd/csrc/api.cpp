@@ -45,6 +45,7 @@ struct dcgs2_ctx_s {
   int tune_fused_waves = 8;      // DCGS2_TUNE_FUSED_WAVES
   int tune_reduce_gmax = 0;      // DCGS2_TUNE_REDUCE_GRID (0: automatic)
   int tune_fused_min_j = 0;      // DCGS2_TUNE_FUSED_MIN_J
+  int tune_batch_units = 4096;   // DCGS2_TUNE_BATCH_REDUCE_ROWS / 2
   int64_t cap_m = 0;
   int64_t cap_qa = 0, cap_qb = 0;
   double *w = nullptr, *v = nullptr, *r = nullptr;
@@ -325,13 +326,6 @@ struct Expansion {
        launch_scale_col(Q, q32, ldq, J, c->r, m, c->coef, LDC, c->ctrl, s));
     return DCGS2_OK;
   }
-  GridRed fused_grid(int J, int last) const {
-    GridRed g = gr;
-    g.G = fused_qr_grid(m, J, last, c->tune_fused_waves, c->tune_reduce_gmax);
-    g.GS = g.G < REDUCE_GSMAX ? g.G : REDUCE_GSMAX;
-    g.NG = (g.G + g.GS - 1) / g.GS;
-    return g;
-  }
   // One-pass QR schedule for steps j0..j_to: reduce(j0), then fused(j) =
   // update(j) + reduction(j+1) for j < j_to, then update(j_to) fused with the
   // first reduction of the last-column finish.
@@ -361,11 +355,11 @@ struct Expansion {
            launch_reduce(Q, q32, ldq, J + 1, c->w, last ? nullptr : ycol(j + 1), m, gr, f, s));
         continue;
       }
-      const GridRed g = fused_grid(J, last ? 1 : 0);
-      // bytes: Q_{0..J-1}, w, a_j, a_{j+1} read; q, w written
+      // bytes: Q_{0..J-1}, w, a_j, a_{j+1} read; q, w written (grid sized inside)
       KL(K_FUSED, qb * (J + 1) + vm * (last ? 3 : 4),
          launch_fused_qr(Q, q32, ldq, J, c->w, ycol(j), last ? nullptr : ycol(j + 1), m,
-                         c->coef, LDC, last ? 1 : 0, c->tune_fused_waves, g, f, s));
+                         c->coef, LDC, last ? 1 : 0, c->tune_fused_waves,
+                         c->tune_reduce_gmax, gr, f, s));
     }
     if (J_last >= 0) {
       KL(K_PROJNORM, qb * J_last + 2 * vm,
@@ -516,6 +510,10 @@ int dcgs2_set_tuning(dcgs2_ctx c, int32_t key, int32_t value) {
       if (value < 0 || value > DCGS2_MAX_N) return DCGS2_EINVAL;
       c->tune_fused_min_j = value;
       return DCGS2_OK;
+    case DCGS2_TUNE_BATCH_REDUCE_ROWS:
+      if (value < 512 || value > 65536 || (value & (value - 1)) != 0) return DCGS2_EINVAL;
+      c->tune_batch_units = value / 2;
+      return DCGS2_OK;
     default:
       return DCGS2_EINVAL;
   }
@@ -527,6 +525,7 @@ int dcgs2_get_tuning(dcgs2_ctx c, int32_t key, int32_t* value) {
     case DCGS2_TUNE_FUSED_WAVES: *value = c->tune_fused_waves; return DCGS2_OK;
     case DCGS2_TUNE_REDUCE_GRID: *value = c->tune_reduce_gmax; return DCGS2_OK;
     case DCGS2_TUNE_FUSED_MIN_J: *value = c->tune_fused_min_j; return DCGS2_OK;
+    case DCGS2_TUNE_BATCH_REDUCE_ROWS: *value = 2 * c->tune_batch_units; return DCGS2_OK;
     default: return DCGS2_EINVAL;
   }
 }
@@ -1076,7 +1075,7 @@ int group_setup(dcgs2_ctx c, BatchedGroup& g, const dcgs2_stencil2d* ops, const 
     qtot += ldq[b] * (p + 1);
     voff[b] = vtot;
     vtot += 3 * ldq[b];
-    const int64_t gg = ((mb + 1) / 2 + 1023) / 1024;
+    const int64_t gg = ((mb + 1) / 2 + c->tune_batch_units - 1) / c->tune_batch_units;
     G[b] = (int)std::max<int64_t>(1, std::min<int64_t>(gg, REDUCE_GSMAX));
     gtot += G[b];
     B.pre_rows[b + 1] =

@@ -498,40 +498,64 @@ size_t fused_qr_smem(int J, int last, int fw, int vr) {
   return sizeof(double) * (work > fin ? work : fin) + sizeof(double) * 8;
 }
 
-int fused_qr_grid(int64_t m, int J, int last, int fw, int gmax) {
-  (void)J; (void)last;
-  const int64_t ntiles = (m + 63) / 64;
-  (void)fw;
-  int64_t g = 256;                         // one workgroup per CU (measured best at m = 2e6)
-  if (gmax > 0 && g > gmax) g = gmax;
-  if (g > REDUCE_GMAX) g = REDUCE_GMAX;
-  if (g > ntiles) g = ntiles;
-  return (int)(g < 1 ? 1 : g);
+// Multiprocessors of the current device (cached).
+int device_cus() {
+  static int ncu = 0;
+  if (ncu == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        v > 0)
+      ncu = v;
+    else
+      return 256;
+  }
+  return ncu;
 }
 
 namespace {
 // Dispatch on the slot count NS = ceil(Jt / FW) (compile-time in the kernel).
+// The grid is as many workgroups as fit on the device at once (the occupancy of
+// this instantiation: registers grow with NS), so short bases, whose tiles are
+// latency-bound, get several workgroups per CU and long ones one.
 template <typename T, bool L, int F, int VR, int NS>
 hipError_t fused_qr_ns(int ns, T* Q, int64_t ldq, int J, double* w, const double* a_cur,
                        const double* a_next, int64_t m, const double* coef, int ldc, size_t sm,
-                       const GridRed& gr, const FinArgs& fin, hipStream_t s) {
+                       GridRed gr, int gmax, const FinArgs& fin, hipStream_t s) {
   if constexpr (NS > FMAXCOL / F) {
     return hipErrorInvalidValue;
   } else {
     if (ns == NS) {
+      static int per_cu = 0;               // resident workgroups per CU (cached)
+      if (per_cu == 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, fused_qr_kernel<T, L, F, NS, VR>, F * 64, sm) != hipSuccess || nb < 1)
+          nb = 1;
+        per_cu = nb;
+      }
+      const int64_t ntiles = (m / VR + 63) / 64;
+      int64_t g = (int64_t)per_cu * device_cus();
+      if (gmax > 0 && g > gmax) g = gmax;
+      if (g > REDUCE_GMAX) g = REDUCE_GMAX;
+      if (g > ntiles) g = ntiles;
+      gr.G = (int)(g < 1 ? 1 : g);
+      gr.GS = gr.G < REDUCE_GSMAX ? gr.G : REDUCE_GSMAX;
+      gr.NG = (gr.G + gr.GS - 1) / gr.GS;
       fused_qr_kernel<T, L, F, NS, VR><<<gr.G, F * 64, sm, s>>>(Q, ldq, J, w, a_cur, a_next, m,
                                                                 coef, ldc, gr, fin);
       return hipGetLastError();
     }
     return fused_qr_ns<T, L, F, VR, NS + 1>(ns, Q, ldq, J, w, a_cur, a_next, m, coef, ldc, sm, gr,
-                                            fin, s);
+                                            gmax, fin, s);
   }
 }
 }  // namespace
 
 hipError_t launch_fused_qr(void* Q, int q32, int64_t ldq, int J, double* w, const double* a_cur,
                            const double* a_next, int64_t m, const double* coef, int ldc, int last,
-                           int fw, const GridRed& gr, const FinArgs& fin, hipStream_t s) {
+                           int fw, int gmax, const GridRed& gr, const FinArgs& fin,
+                           hipStream_t s) {
   const int F = fw == 8 ? 8 : 16;
   const int Jt = J + (last ? 2 : 3);
   const int ns = (Jt + F - 1) / F;
@@ -542,7 +566,7 @@ hipError_t launch_fused_qr(void* Q, int q32, int64_t ldq, int J, double* w, cons
   const size_t sm = fused_qr_smem(J, last, F, pair ? 2 : 1);
 #define DCGS2_FQ(T, L, FF, VR)                                                                 \
   return fused_qr_ns<T, L, FF, VR, 1>(ns, (T*)Q, ldq, J, w, a_cur, a_next, m, coef, ldc, sm, gr, \
-                                      fin, s)
+                                      gmax, fin, s)
 #define DCGS2_FQ_V(FF, VR)                                                                    \
   do {                                                                                        \
     if (q32) { if (last) DCGS2_FQ(float, true, FF, VR); DCGS2_FQ(float, false, FF, VR); }     \
