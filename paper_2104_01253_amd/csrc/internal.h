@@ -112,9 +112,9 @@ hipError_t launch_update(void* Q, int q32, int64_t ldq, int J, double* x, const 
                          int qcol, const Ctrl* ctrl, hipStream_t s);
 // One-pass QR step: update of step j (q into Q[:, J], w <- w_j) fused with the
 // reduction of step j+1 over [Q_{0..J}, w_j, a_next]; last != 0 reduces only
-// [Q_{0..J}, w_j]^T w_j (a_next unused).  The launcher sizes the grid itself (the
-// occupancy of the chosen instantiation, capped by gmax > 0 and the tile count);
-// gr supplies the partial buffers, counters and ldp.
+// [Q_{0..J}, w_j]^T w_j (a_next unused).  The launcher sizes the grid itself (one
+// workgroup per CU, capped by gmax > 0 and the tile count); gr supplies the
+// partial buffers, counters and ldp.
 hipError_t launch_fused_qr(void* Q, int q32, int64_t ldq, int J, double* w, const double* a_cur,
                            const double* a_next, int64_t m, const double* coef, int ldc, int last,
                            int fw, int gmax, const GridRed& gr, const FinArgs& fin,

@@ -80,7 +80,7 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-template <typename TQ, bool LAST, int FW, int NS, int VR>
+template <typename TQ, bool LAST, int FW, int NS, int VR, int PD>
 __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, int64_t ldq,
                                                            int J, double* __restrict__ w,
                                                            const double* __restrict__ a_cur,
@@ -123,8 +123,7 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
   double ax[NS], ay[NS];
 #pragma unroll
   for (int sl = 0; sl < NS; ++sl) { ax[sl] = 0.0; ay[sl] = 0.0; }
-  // software pipeline: the loads of the next tile are issued before the current
-  // tile's barriers and consumed one iteration later
+  // software pipeline: tile loads are issued PD iterations before their use
   RV qv[NS], wi = RV::zero(), ai = RV::zero(), an = RV::zero();
   auto load_tile = [&](int64_t t, RV (&q)[NS], RV& x0, RV& x1, RV& x2) {
     const int64_t ul = min(t * 64 + lane, units - 1);
@@ -136,9 +135,17 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
       if (!LAST) x2 = RV::load(a_next, ul);
     }
   };
+  // PD tiles in flight ahead of the one being processed: the loads of tile t + PD G
+  // are issued at the top of iteration t
   int64_t tix = blockIdx.x;
-  if (tix < ntiles) load_tile(tix, qv, wi, ai, an);
+  RV q1[NS], w1 = RV::zero(), a1 = RV::zero(), n1 = RV::zero();   // tile t + G (PD = 2)
+  if (tix < ntiles) {
+    load_tile(tix, qv, wi, ai, an);
+    if constexpr (PD == 2) load_tile(min(tix + gr.G, ntiles - 1), q1, w1, a1, n1);
+  }
   for (; tix < ntiles; tix += gr.G) {
+    RV qn[NS], wn_ = RV::zero(), an_ = RV::zero(), ann = RV::zero();
+    load_tile(min(tix + PD * gr.G, ntiles - 1), qn, wn_, an_, ann);   // prefetch
     const int64_t u = tix * 64 + lane;
     const bool live = u < units;
     double sc[VR], st[VR];
@@ -159,8 +166,6 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
       part[((wv * 64 + lane) * VR + e) * 2] = sc[e];
       part[((wv * 64 + lane) * VR + e) * 2 + 1] = st[e];
     }
-    RV qn[NS], wn_ = RV::zero(), an_ = RV::zero(), ann = RV::zero();
-    load_tile(min(tix + gr.G, ntiles - 1), qn, wn_, an_, ann);   // prefetch
     lds_barrier();
     if (wv == 0) {
       RV qo = RV::zero(), wo = RV::zero(), ao = RV::zero();
@@ -210,11 +215,16 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
     }
     // (the next tile's part writes follow the second barrier, and its vq writes
     // its first one, so two barriers per tile suffice)
+    if constexpr (PD == 2) {
 #pragma unroll
-    for (int sl = 0; sl < NS; ++sl) qv[sl] = qn[sl];
-    wi = wn_;
-    ai = an_;
-    an = ann;
+      for (int sl = 0; sl < NS; ++sl) { qv[sl] = q1[sl]; q1[sl] = qn[sl]; }
+      wi = w1; ai = a1; an = n1;
+      w1 = wn_; a1 = an_; n1 = ann;
+    } else {
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl) qv[sl] = qn[sl];
+      wi = wn_; ai = an_; an = ann;
+    }
   }
   // dead rows contribute 0: q = w' = a = 0 there, and basis values only meet them
   double pv[NV];
@@ -515,9 +525,8 @@ int device_cus() {
 
 namespace {
 // Dispatch on the slot count NS = ceil(Jt / FW) (compile-time in the kernel).
-// The grid is as many workgroups as fit on the device at once (the occupancy of
-// this instantiation: registers grow with NS), so short bases, whose tiles are
-// latency-bound, get several workgroups per CU and long ones one.
+// One workgroup per CU: measured faster at m = 2e6 than filling each CU to the
+// occupancy of the instantiation (several workgroups per CU for short bases).
 template <typename T, bool L, int F, int VR, int NS>
 hipError_t fused_qr_ns(int ns, T* Q, int64_t ldq, int J, double* w, const double* a_cur,
                        const double* a_next, int64_t m, const double* coef, int ldc, size_t sm,
@@ -526,24 +535,19 @@ hipError_t fused_qr_ns(int ns, T* Q, int64_t ldq, int J, double* w, const double
     return hipErrorInvalidValue;
   } else {
     if (ns == NS) {
-      static int per_cu = 0;               // resident workgroups per CU (cached)
-      if (per_cu == 0) {
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &nb, fused_qr_kernel<T, L, F, NS, VR>, F * 64, sm) != hipSuccess || nb < 1)
-          nb = 1;
-        per_cu = nb;
-      }
       const int64_t ntiles = (m / VR + 63) / 64;
-      int64_t g = (int64_t)per_cu * device_cus();
+      int64_t g = device_cus();
       if (gmax > 0 && g > gmax) g = gmax;
       if (g > REDUCE_GMAX) g = REDUCE_GMAX;
       if (g > ntiles) g = ntiles;
       gr.G = (int)(g < 1 ? 1 : g);
       gr.GS = gr.G < REDUCE_GSMAX ? gr.G : REDUCE_GSMAX;
       gr.NG = (gr.G + gr.GS - 1) / gr.GS;
-      fused_qr_kernel<T, L, F, NS, VR><<<gr.G, F * 64, sm, s>>>(Q, ldq, J, w, a_cur, a_next, m,
-                                                                coef, ldc, gr, fin);
+      // prefetch depth 2 while the three register sets of NS slots fit (VR NS <= 16;
+      // 16-wavefront workgroups are limited to 128 registers)
+      constexpr int PD = (F == 8 && VR * NS <= 16) ? 2 : 1;
+      fused_qr_kernel<T, L, F, NS, VR, PD><<<gr.G, F * 64, sm, s>>>(Q, ldq, J, w, a_cur, a_next,
+                                                                    m, coef, ldc, gr, fin);
       return hipGetLastError();
     }
     return fused_qr_ns<T, L, F, VR, NS + 1>(ns, Q, ldq, J, w, a_cur, a_next, m, coef, ldc, sm, gr,
@@ -560,8 +564,10 @@ hipError_t launch_fused_qr(void* Q, int q32, int64_t ldq, int J, double* w, cons
   const int Jt = J + (last ? 2 : 3);
   const int ns = (Jt + F - 1) / F;
   if (ns < 1 || ns > FMAXCOL / F) return hipErrorInvalidValue;
-  // paired rows: m even, every column start 16-byte aligned (8 for an FP32 basis)
-  const bool pair = (m % 2 == 0) && aligned_to(Q, q32 ? 8 : 16) && (ldq % 2 == 0) &&
+  // paired rows: m even, every column start 16-byte aligned (8 for an FP32 basis);
+  // 8-wavefront workgroups only (16 wavefronts leave 128 registers, which two-row
+  // slots overflow)
+  const bool pair = F == 8 && (m % 2 == 0) && aligned_to(Q, q32 ? 8 : 16) && (ldq % 2 == 0) &&
                     aligned16(w) && aligned16(a_cur) && (last || aligned16(a_next));
   const size_t sm = fused_qr_smem(J, last, F, pair ? 2 : 1);
 #define DCGS2_FQ(T, L, FF, VR)                                                                 \
@@ -577,7 +583,6 @@ hipError_t launch_fused_qr(void* Q, int q32, int64_t ldq, int J, double* w, cons
     if (pair) DCGS2_FQ_V(8, 2);
     DCGS2_FQ_V(8, 1);
   }
-  if (pair) DCGS2_FQ_V(16, 2);
   DCGS2_FQ_V(16, 1);
 #undef DCGS2_FQ_V
 #undef DCGS2_FQ
