@@ -120,7 +120,7 @@ def batched_ks_leg(torch, ctx, binding, synth, count=512):
             "instances_per_s": round(count / dt, 2), "status": rc}
 
 
-def learned_guess_leg(torch, ctx, binding, synth, count=8):
+def learned_guess_leg(torch, ctx, binding, synth, count=16):
     """GMRES(50) to 1e-8 on held-out instances of the 256 x 256 variable-coefficient
     family, from x0 = 0 and from the trained network's guess (inference and the
     guard included in the timed region)."""

@@ -289,8 +289,10 @@ __device__ void complete_h_column(const FinArgs& f, const double* C, int J, doub
   if (f.gmres) gmres_givens(f, col, f.j, scratch);
 }
 
-// Scalar tail of a DCGS2 step once alpha_{j-1} is known (Alg. arnoldi lines 4-12
-// with lines 10 -> 12 -> 11, or Alg. qr lines 3-8).
+// Scalar tail of a DCGS2 step once alpha_{j-1} is known (Alg. arnoldi: T, then the
+// Hessenberg column H_{:,j-2} = K + C with H_{j-1,j-2} = alpha, then the new K column
+// -- H is completed before K is formed, as the derivation after eq. (52) requires;
+// or Alg. qr: R column and Stephen's trick).
 //   C, S : LDS vectors of length J; sigma, gamma, cs = C^T S; rho = breakdown scale.
 __device__ void step_tail(const FinArgs& f, const double* C, const double* S, double sigma,
                           double gamma, double csum, double alpha, double rho, double* T,
@@ -333,20 +335,38 @@ __device__ void step_tail(const FinArgs& f, const double* C, const double* S, do
     if (threadIdx.x == 0) { ctrl->k = J + 1; ctrl->rho_next = sqrt(gamma); }
   } else {
     if (f.gmres && j == 2 && threadIdx.x == 0) f.g[0] = alpha;   // beta e_1 of the cycle
-    if (j >= 3) complete_h_column(f, C, J, alpha, scratch);      // lines 10 and 12
+    if (j >= 3) complete_h_column(f, C, J, alpha, scratch);      // H_{:,j-2}, H_{j-1,j-2}
     __syncthreads();
-    // line 11: K_{1:j-1, j-1} = T - (1/alpha) H_{1:j-1, 1:j-2} C   (dense product)
-    for (int i = threadIdx.x; i <= J; i += (int)blockDim.x) {
-      double hc = 0.0;
-      for (int c0 = 0; c0 < J; c0 += 8) {        // eight loads in flight, FMAs in order
-        double h[8];
+    // K_{1:j-1, j-1} = T - (1/alpha) H_{1:j-1, 1:j-2} C   (dense product).  Each row's
+    // dot product is split over CH threads (column chunks, then the chunk partials
+    // in order), so the chain of dependent global loads per thread stays short.
+    {
+      const int R = J + 1;
+      const int cap = 3 * (J + 2) + 64;         // doubles of scratch
+      int CH = (int)blockDim.x / R;
+      if (CH > cap / R) CH = cap / R;
+      if (CH < 1) CH = 1;
+      const int L = (J + CH - 1) / CH;          // columns per chunk
+      for (int t = threadIdx.x; t < R * CH; t += (int)blockDim.x) {
+        const int i = t / CH, part = t % CH;
+        const int c_lo = part * L, c_hi = min(J, c_lo + L);
+        double hc = 0.0;
+        for (int c0 = c_lo; c0 < c_hi; c0 += 8) {   // eight loads in flight, FMAs in order
+          double h[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) h[u] = f.H[(int64_t)min(c0 + u, J - 1) * f.ldh + i];
+          for (int u = 0; u < 8; ++u) h[u] = f.H[(int64_t)min(c0 + u, c_hi - 1) * f.ldh + i];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (c0 + u < J) hc = fma(h[u], C[c0 + u], hc);
+          for (int u = 0; u < 8; ++u)
+            if (c0 + u < c_hi) hc = fma(h[u], C[c0 + u], hc);
+        }
+        scratch[t] = hc;
       }
-      f.K[(int64_t)J * f.ldh + i] = T[i] - hc / alpha;
+      __syncthreads();
+      for (int i = threadIdx.x; i < R; i += (int)blockDim.x) {
+        double hc = 0.0;
+        for (int part = 0; part < CH; ++part) hc += scratch[i * CH + part];
+        f.K[(int64_t)J * f.ldh + i] = T[i] - hc / alpha;
+      }
     }
     if (threadIdx.x == 0) ctrl->rho_next = sqrt(gamma) / alpha;
   }

@@ -390,8 +390,10 @@ size_t reduce_smem(int J, bool hasy) {
 
 // ---------------------------------------------------------------------------------
 void reduce_grid(int64_t m, int gmax, int* G, int* GS, int* NG) {
+  // one two-row unit per thread and sweep until the cap: short slabs keep the
+  // latency chain of a sweep short when m is small
   const int64_t units = (m + 1) / 2;
-  int64_t g = (units + (int64_t)BS * 4 - 1) / ((int64_t)BS * 4);
+  int64_t g = (units + (int64_t)BS - 1) / (int64_t)BS;
   if (g < 1) g = 1;
   // default: at most 256 workgroups (one per CU); measured best for the
   // 16-column sweeps at m = 2e6 (the tuning knob overrides it)
