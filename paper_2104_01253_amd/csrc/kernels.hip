@@ -547,7 +547,7 @@ hipError_t fused_qr_ns(int ns, T* Q, int64_t ldq, int J, double* w, const double
       gr.NG = (gr.G + gr.GS - 1) / gr.GS;
       // prefetch depth 2 while the three register sets of NS slots fit (VR NS <= 16;
       // 16-wavefront workgroups are limited to 128 registers)
-      constexpr int PD = (F == 8 && VR * NS <= 16) ? 2 : 1;
+      constexpr int PD = ((F == 8 && VR * NS <= 16) || (F == 16 && VR == 1 && NS <= 5)) ? 2 : 1;
       fused_qr_kernel<T, L, F, NS, VR, PD><<<gr.G, F * 64, sm, s>>>(Q, ldq, J, w, a_cur, a_next,
                                                                     m, coef, ldc, gr, fin);
       return hipGetLastError();
