@@ -174,8 +174,37 @@ __device__ __forceinline__ double ordered_sum(const double* base, int64_t stride
   return s;
 }
 
+// out[v] = sum over i < n of base[i stride + v], for v < V, by the whole workgroup.
+// With few values each value's n partials are split into up to four chunks summed
+// by different threads (then the chunk sums in order), so the chain of dependent
+// loads per thread stays short; the order of additions is fixed either way.
+__device__ void group_sum(const double* base, int64_t stride, int n, int V, double* out,
+                          double* s_part /* 256 doubles of LDS */) {
+  int C = V <= 256 ? 256 / V : 1;
+  if (C > 4) C = 4;
+  if (C > n) C = n;
+  if (C <= 1) {
+    for (int v = threadIdx.x; v < V; v += (int)blockDim.x) out[v] = ordered_sum(base + v, stride, n);
+    return;
+  }
+  const int L = (n + C - 1) / C;
+  for (int t = threadIdx.x; t < V * C; t += (int)blockDim.x) {
+    const int v = t / C, c = t % C;
+    const int lo = c * L, hi = min(n, lo + L);
+    s_part[t] = lo < hi ? ordered_sum(base + (int64_t)lo * stride + v, stride, hi - lo) : 0.0;
+  }
+  __syncthreads();
+  for (int v = threadIdx.x; v < V; v += (int)blockDim.x) {
+    double s = 0.0;
+    for (int c = 0; c < C; ++c) s += s_part[v * C + c];
+    out[v] = s;
+  }
+  __syncthreads();
+}
+
 __device__ bool grid_reduce(const GridRed& gr, int V, double* red, int bid) {
   __shared__ int s_last;
+  __shared__ double s_part[256];
   __threadfence();               // every thread: release this workgroup's partial stores
   __syncthreads();
   const int grp = bid / gr.GS;
@@ -188,11 +217,8 @@ __device__ bool grid_reduce(const GridRed& gr, int V, double* red, int bid) {
   __syncthreads();
   if (!s_last) return false;
   __threadfence();
-  for (int v = threadIdx.x; v < V; v += (int)blockDim.x) {
-    const double s = ordered_sum(gr.P1 + (int64_t)g0 * gr.ldp + v, gr.ldp, gsz);
-    if (gr.NG == 1) red[v] = s;
-    else gr.P2[(int64_t)grp * gr.ldp + v] = s;
-  }
+  group_sum(gr.P1 + (int64_t)g0 * gr.ldp, gr.ldp, gsz, V,
+            gr.NG == 1 ? red : gr.P2 + (int64_t)grp * gr.ldp, s_part);
   if (threadIdx.x == 0) gr.cnt[grp] = 0u;
   if (gr.NG == 1) { __syncthreads(); return true; }
   __threadfence();
@@ -204,8 +230,7 @@ __device__ bool grid_reduce(const GridRed& gr, int V, double* red, int bid) {
   __syncthreads();
   if (!s_last) return false;
   __threadfence();
-  for (int v = threadIdx.x; v < V; v += (int)blockDim.x)
-    red[v] = ordered_sum(gr.P2 + v, gr.ldp, gr.NG);
+  group_sum(gr.P2, gr.ldp, gr.NG, V, red, s_part);
   if (threadIdx.x == 0) gr.cnt[gr.NG] = 0u;
   __syncthreads();
   return true;
