@@ -194,7 +194,8 @@ def main():
         from paper_2104_01253_amd import autotune
         best, best_ms, _ = autotune.tune(ctx, qr_once, reps=1)
         names = {binding.TUNE_FUSED_WAVES: "fused_waves", binding.TUNE_REDUCE_GRID: "reduce_grid",
-                 binding.TUNE_FUSED_MIN_J: "fused_min_j"}
+                 binding.TUNE_FUSED_MIN_J: "fused_min_j",
+                 binding.TUNE_FUSED_PAIR_SLOTS: "fused_pair_slots"}
         tuned = {names[k]: v for k, v in best.items()}
         log(f"[bench] autotuned {tuned} ({best_ms:.2f} ms)")
     log(f"[bench] timing {args.steps} factorizations")

@@ -138,9 +138,13 @@ int dcgs2_set_qr_schedule(dcgs2_ctx ctx, int one_pass);
  *  DCGS2_TUNE_BATCH_REDUCE_ROWS : krylov_schur_batched: rows per workgroup of an
  *                           instance's reduction passes (up to 32 workgroups per
  *                           instance), a power of two in 512..65536 (default 8192).
+ *  DCGS2_TUNE_FUSED_PAIR_SLOTS : one-pass QR kernel: two rows per lane (16-byte
+ *                           loads) while the basis needs at most this many column
+ *                           slots per wavefront, one row per lane (deeper
+ *                           prefetch) beyond, 0..16 (default 16).
  * Returns DCGS2_EINVAL for an unknown key or value. */
 enum { DCGS2_TUNE_FUSED_WAVES = 0, DCGS2_TUNE_REDUCE_GRID = 1, DCGS2_TUNE_FUSED_MIN_J = 2,
-       DCGS2_TUNE_BATCH_REDUCE_ROWS = 3 };
+       DCGS2_TUNE_BATCH_REDUCE_ROWS = 3, DCGS2_TUNE_FUSED_PAIR_SLOTS = 4 };
 int dcgs2_set_tuning(dcgs2_ctx ctx, int32_t key, int32_t value);
 int dcgs2_get_tuning(dcgs2_ctx ctx, int32_t key, int32_t* value);
 

@@ -46,6 +46,7 @@ struct dcgs2_ctx_s {
   int tune_reduce_gmax = 0;      // DCGS2_TUNE_REDUCE_GRID (0: automatic)
   int tune_fused_min_j = 0;      // DCGS2_TUNE_FUSED_MIN_J
   int tune_batch_units = 4096;   // DCGS2_TUNE_BATCH_REDUCE_ROWS / 2
+  int tune_pair_max_ns = 16;     // DCGS2_TUNE_FUSED_PAIR_SLOTS
   int64_t cap_m = 0;
   int64_t cap_qa = 0, cap_qb = 0;
   double *w = nullptr, *v = nullptr, *r = nullptr;
@@ -359,7 +360,7 @@ struct Expansion {
       KL(K_FUSED, qb * (J + 1) + vm * (last ? 3 : 4),
          launch_fused_qr(Q, q32, ldq, J, c->w, ycol(j), last ? nullptr : ycol(j + 1), m,
                          c->coef, LDC, last ? 1 : 0, c->tune_fused_waves,
-                         c->tune_reduce_gmax, gr, f, s));
+                         c->tune_reduce_gmax, c->tune_pair_max_ns, gr, f, s));
     }
     if (J_last >= 0) {
       KL(K_PROJNORM, qb * J_last + 2 * vm,
@@ -514,6 +515,10 @@ int dcgs2_set_tuning(dcgs2_ctx c, int32_t key, int32_t value) {
       if (value < 512 || value > 65536 || (value & (value - 1)) != 0) return DCGS2_EINVAL;
       c->tune_batch_units = value / 2;
       return DCGS2_OK;
+    case DCGS2_TUNE_FUSED_PAIR_SLOTS:
+      if (value < 0 || value > 16) return DCGS2_EINVAL;
+      c->tune_pair_max_ns = value;
+      return DCGS2_OK;
     default:
       return DCGS2_EINVAL;
   }
@@ -526,6 +531,7 @@ int dcgs2_get_tuning(dcgs2_ctx c, int32_t key, int32_t* value) {
     case DCGS2_TUNE_REDUCE_GRID: *value = c->tune_reduce_gmax; return DCGS2_OK;
     case DCGS2_TUNE_FUSED_MIN_J: *value = c->tune_fused_min_j; return DCGS2_OK;
     case DCGS2_TUNE_BATCH_REDUCE_ROWS: *value = 2 * c->tune_batch_units; return DCGS2_OK;
+    case DCGS2_TUNE_FUSED_PAIR_SLOTS: *value = c->tune_pair_max_ns; return DCGS2_OK;
     default: return DCGS2_EINVAL;
   }
 }

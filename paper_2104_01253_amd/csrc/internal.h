@@ -117,9 +117,10 @@ hipError_t launch_update(void* Q, int q32, int64_t ldq, int J, double* x, const 
 // partial buffers, counters and ldp.
 hipError_t launch_fused_qr(void* Q, int q32, int64_t ldq, int J, double* w, const double* a_cur,
                            const double* a_next, int64_t m, const double* coef, int ldc, int last,
-                           int fw, int gmax, const GridRed& gr, const FinArgs& fin,
-                           hipStream_t s);
-// fw: wavefronts per workgroup (8 or 16).
+                           int fw, int gmax, int pair_max_ns, const GridRed& gr,
+                           const FinArgs& fin, hipStream_t s);
+// fw: wavefronts per workgroup (8 or 16); two-row slots are used (when the data
+// allow them) only while the slot count NS <= pair_max_ns.
 int device_cus();                         // multiprocessors of the current device
 constexpr int FUSED_QR_MAX_J = 125;       // J + 3 basis and vector columns <= 128
 // Q[:, J] = ubuf / alpha (coef[2 ldc]) when ctrl->state == RUNNING.

@@ -135,17 +135,21 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
       if (!LAST) x2 = RV::load(a_next, ul);
     }
   };
-  // PD tiles in flight ahead of the one being processed: the loads of tile t + PD G
-  // are issued at the top of iteration t
+  // PD tiles in flight ahead of the one being processed (a ring of register sets):
+  // the loads of tile t + PD G are issued at the top of iteration t
   int64_t tix = blockIdx.x;
-  RV q1[NS], w1 = RV::zero(), a1 = RV::zero(), n1 = RV::zero();   // tile t + G (PD = 2)
+  RV rq[PD][NS], rw[PD], ra[PD], rn[PD];
+#pragma unroll
+  for (int d = 0; d < PD; ++d) { rw[d] = RV::zero(); ra[d] = RV::zero(); rn[d] = RV::zero(); }
   if (tix < ntiles) {
     load_tile(tix, qv, wi, ai, an);
-    if constexpr (PD == 2) load_tile(min(tix + gr.G, ntiles - 1), q1, w1, a1, n1);
+#pragma unroll
+    for (int d = 0; d + 1 < PD; ++d)
+      load_tile(min(tix + (d + 1) * gr.G, ntiles - 1), rq[d], rw[d], ra[d], rn[d]);
   }
   for (; tix < ntiles; tix += gr.G) {
-    RV qn[NS], wn_ = RV::zero(), an_ = RV::zero(), ann = RV::zero();
-    load_tile(min(tix + PD * gr.G, ntiles - 1), qn, wn_, an_, ann);   // prefetch
+    load_tile(min(tix + PD * gr.G, ntiles - 1), rq[PD - 1], rw[PD - 1], ra[PD - 1],
+              rn[PD - 1]);                                        // prefetch
     const int64_t u = tix * 64 + lane;
     const bool live = u < units;
     double sc[VR], st[VR];
@@ -215,15 +219,15 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
     }
     // (the next tile's part writes follow the second barrier, and its vq writes
     // its first one, so two barriers per tile suffice)
-    if constexpr (PD == 2) {
+    // rotate the ring: the next tile becomes current
 #pragma unroll
-      for (int sl = 0; sl < NS; ++sl) { qv[sl] = q1[sl]; q1[sl] = qn[sl]; }
-      wi = w1; ai = a1; an = n1;
-      w1 = wn_; a1 = an_; n1 = ann;
-    } else {
+    for (int sl = 0; sl < NS; ++sl) qv[sl] = rq[0][sl];
+    wi = rw[0]; ai = ra[0]; an = rn[0];
 #pragma unroll
-      for (int sl = 0; sl < NS; ++sl) qv[sl] = qn[sl];
-      wi = wn_; ai = an_; an = ann;
+    for (int d = 0; d + 1 < PD; ++d) {
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl) rq[d][sl] = rq[d + 1][sl];
+      rw[d] = rw[d + 1]; ra[d] = ra[d + 1]; rn[d] = rn[d + 1];
     }
   }
   // dead rows contribute 0: q = w' = a = 0 there, and basis values only meet them
@@ -545,9 +549,12 @@ hipError_t fused_qr_ns(int ns, T* Q, int64_t ldq, int J, double* w, const double
       gr.G = (int)(g < 1 ? 1 : g);
       gr.GS = gr.G < REDUCE_GSMAX ? gr.G : REDUCE_GSMAX;
       gr.NG = (gr.G + gr.GS - 1) / gr.GS;
-      // prefetch depth 2 while the three register sets of NS slots fit (VR NS <= 16;
-      // 16-wavefront workgroups are limited to 128 registers)
-      constexpr int PD = ((F == 8 && VR * NS <= 16) || (F == 16 && VR == 1 && NS <= 5)) ? 2 : 1;
+      // prefetch depth: as many tiles ahead as register sets of 2 (NS + 3) VR
+      // registers fit beside the accumulators (8-wavefront workgroups may use 256
+      // registers, 16-wavefront ones 128), between 1 and 8
+      constexpr int BUDGET = (F == 8 ? 196 : 60) - 4 * NS;
+      constexpr int SETS = BUDGET / (2 * (NS + 3) * VR);
+      constexpr int PD = SETS - 1 < 1 ? 1 : (SETS - 1 > 8 ? 8 : SETS - 1);
       fused_qr_kernel<T, L, F, NS, VR, PD><<<gr.G, F * 64, sm, s>>>(Q, ldq, J, w, a_cur, a_next,
                                                                     m, coef, ldc, gr, fin);
       return hipGetLastError();
@@ -560,8 +567,8 @@ hipError_t fused_qr_ns(int ns, T* Q, int64_t ldq, int J, double* w, const double
 
 hipError_t launch_fused_qr(void* Q, int q32, int64_t ldq, int J, double* w, const double* a_cur,
                            const double* a_next, int64_t m, const double* coef, int ldc, int last,
-                           int fw, int gmax, const GridRed& gr, const FinArgs& fin,
-                           hipStream_t s) {
+                           int fw, int gmax, int pair_max_ns, const GridRed& gr,
+                           const FinArgs& fin, hipStream_t s) {
   const int F = fw == 8 ? 8 : 16;
   const int Jt = J + (last ? 2 : 3);
   const int ns = (Jt + F - 1) / F;
@@ -569,8 +576,9 @@ hipError_t launch_fused_qr(void* Q, int q32, int64_t ldq, int J, double* w, cons
   // paired rows: m even, every column start 16-byte aligned (8 for an FP32 basis);
   // 8-wavefront workgroups only (16 wavefronts leave 128 registers, which two-row
   // slots overflow)
-  const bool pair = F == 8 && (m % 2 == 0) && aligned_to(Q, q32 ? 8 : 16) && (ldq % 2 == 0) &&
-                    aligned16(w) && aligned16(a_cur) && (last || aligned16(a_next));
+  const bool pair = F == 8 && ns <= pair_max_ns && (m % 2 == 0) && aligned_to(Q, q32 ? 8 : 16) &&
+                    (ldq % 2 == 0) && aligned16(w) && aligned16(a_cur) &&
+                    (last || aligned16(a_next));
   const size_t sm = fused_qr_smem(J, last, F, pair ? 2 : 1);
 #define DCGS2_FQ(T, L, FF, VR)                                                                 \
   return fused_qr_ns<T, L, FF, VR, 1>(ns, (T*)Q, ldq, J, w, a_cur, a_next, m, coef, ldc, sm, gr, \

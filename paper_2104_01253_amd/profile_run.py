@@ -177,6 +177,7 @@ def main():
     r.add_argument("--fused-waves", type=int, default=None)
     r.add_argument("--reduce-grid", type=int, default=None)
     r.add_argument("--fused-min-j", type=int, default=None)
+    r.add_argument("--fused-pair-slots", type=int, default=None)
     s = sub.add_parser("summarize")
     s.add_argument("--fetch", required=True)
     s.add_argument("--write", required=True)
@@ -187,7 +188,8 @@ def main():
     if a.cmd == "run":
         run(a.workload, a.reps, {"TUNE_FUSED_WAVES": a.fused_waves,
                                  "TUNE_REDUCE_GRID": a.reduce_grid,
-                                 "TUNE_FUSED_MIN_J": a.fused_min_j})
+                                 "TUNE_FUSED_MIN_J": a.fused_min_j,
+                                 "TUNE_FUSED_PAIR_SLOTS": a.fused_pair_slots})
     else:
         summarize(a.fetch, a.write, a.trace, a.out, a.command)
 
