@@ -21,6 +21,9 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <type_traits>
+#include <utility>
+
 #include "internal.h"
 
 namespace dcgs2 {
@@ -80,6 +83,16 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// f(std::integral_constant<int, i>) for i = 0 .. N-1, unrolled at compile time.
+template <int N, typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
+}
+
 template <typename TQ, bool LAST, int FW, int NS, int VR, int PD>
 __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, int64_t ldq,
                                                            int J, double* __restrict__ w,
@@ -123,8 +136,11 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
   double ax[NS], ay[NS];
 #pragma unroll
   for (int sl = 0; sl < NS; ++sl) { ax[sl] = 0.0; ay[sl] = 0.0; }
-  // software pipeline: tile loads are issued PD iterations before their use
-  RV qv[NS], wi = RV::zero(), ai = RV::zero(), an = RV::zero();
+  // Software pipeline over a ring of PD + 1 register sets: while tile t is processed
+  // the loads of tiles t + G .. t + PD G are in flight.  The loop is unrolled PD + 1
+  // times so that every ring slot keeps its registers (a register move of data still
+  // in flight would make the compiler wait for it, which serialises the pipeline).
+  RV buf[PD + 1][NS], bw[PD + 1], ba[PD + 1], bn[PD + 1];
   auto load_tile = [&](int64_t t, RV (&q)[NS], RV& x0, RV& x1, RV& x2) {
     const int64_t ul = min(t * 64 + lane, units - 1);
 #pragma unroll
@@ -133,23 +149,15 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
       x0 = RV::load(w, ul);
       x1 = RV::load(a_cur, ul);
       if (!LAST) x2 = RV::load(a_next, ul);
+      else x2 = RV::zero();
+    } else {
+      x0 = RV::zero();
+      x1 = RV::zero();
+      x2 = RV::zero();
     }
   };
-  // PD tiles in flight ahead of the one being processed (a ring of register sets):
-  // the loads of tile t + PD G are issued at the top of iteration t
-  int64_t tix = blockIdx.x;
-  RV rq[PD][NS], rw[PD], ra[PD], rn[PD];
-#pragma unroll
-  for (int d = 0; d < PD; ++d) { rw[d] = RV::zero(); ra[d] = RV::zero(); rn[d] = RV::zero(); }
-  if (tix < ntiles) {
-    load_tile(tix, qv, wi, ai, an);
-#pragma unroll
-    for (int d = 0; d + 1 < PD; ++d)
-      load_tile(min(tix + (d + 1) * gr.G, ntiles - 1), rq[d], rw[d], ra[d], rn[d]);
-  }
-  for (; tix < ntiles; tix += gr.G) {
-    load_tile(min(tix + PD * gr.G, ntiles - 1), rq[PD - 1], rw[PD - 1], ra[PD - 1],
-              rn[PD - 1]);                                        // prefetch
+  auto process = [&](int64_t tix, const RV (&qv)[NS], const RV& wi, const RV& ai,
+                     const RV& an) {
     const int64_t u = tix * 64 + lane;
     const bool live = u < units;
     double sc[VR], st[VR];
@@ -219,16 +227,25 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
     }
     // (the next tile's part writes follow the second barrier, and its vq writes
     // its first one, so two barriers per tile suffice)
-    // rotate the ring: the next tile becomes current
-#pragma unroll
-    for (int sl = 0; sl < NS; ++sl) qv[sl] = rq[0][sl];
-    wi = rw[0]; ai = ra[0]; an = rn[0];
-#pragma unroll
-    for (int d = 0; d + 1 < PD; ++d) {
-#pragma unroll
-      for (int sl = 0; sl < NS; ++sl) rq[d][sl] = rq[d + 1][sl];
-      rw[d] = rw[d + 1]; ra[d] = ra[d + 1]; rn[d] = rn[d + 1];
-    }
+  };
+  int64_t tix = blockIdx.x;
+  if (tix < ntiles) {
+    static_for<PD>([&](auto d) {
+      constexpr int D = decltype(d)::value;
+      load_tile(min(tix + D * gr.G, ntiles - 1), buf[D], bw[D], ba[D], bn[D]);
+    });
+  }
+  bool more = tix < ntiles;
+  while (more) {
+    static_for<PD + 1>([&](auto c) {
+      constexpr int C = decltype(c)::value;            // ring slot of the current tile
+      constexpr int L = (C + PD) % (PD + 1);            // ring slot being refilled
+      if (!more) return;
+      load_tile(min(tix + PD * gr.G, ntiles - 1), buf[L], bw[L], ba[L], bn[L]);
+      process(tix, buf[C], bw[C], ba[C], bn[C]);
+      tix += gr.G;
+      more = tix < ntiles;
+    });
   }
   // dead rows contribute 0: q = w' = a = 0 there, and basis values only meet them
   double pv[NV];
