@@ -21,9 +21,6 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
-#include <type_traits>
-#include <utility>
-
 #include "internal.h"
 
 namespace dcgs2 {
@@ -83,16 +80,6 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-// f(std::integral_constant<int, i>) for i = 0 .. N-1, unrolled at compile time.
-template <int N, typename F, int... I>
-__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
-  (f(std::integral_constant<int, I>{}), ...);
-}
-template <int N, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-  static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
-}
-
 template <typename TQ, bool LAST, int FW, int NS, int VR, int PD>
 __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, int64_t ldq,
                                                            int J, double* __restrict__ w,
@@ -136,11 +123,8 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
   double ax[NS], ay[NS];
 #pragma unroll
   for (int sl = 0; sl < NS; ++sl) { ax[sl] = 0.0; ay[sl] = 0.0; }
-  // Software pipeline over a ring of PD + 1 register sets: while tile t is processed
-  // the loads of tiles t + G .. t + PD G are in flight.  The loop is unrolled PD + 1
-  // times so that every ring slot keeps its registers (a register move of data still
-  // in flight would make the compiler wait for it, which serialises the pipeline).
-  RV buf[PD + 1][NS], bw[PD + 1], ba[PD + 1], bn[PD + 1];
+  // software pipeline: tile loads are issued PD iterations before their use
+  RV qv[NS], wi = RV::zero(), ai = RV::zero(), an = RV::zero();
   auto load_tile = [&](int64_t t, RV (&q)[NS], RV& x0, RV& x1, RV& x2) {
     const int64_t ul = min(t * 64 + lane, units - 1);
 #pragma unroll
@@ -149,15 +133,19 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
       x0 = RV::load(w, ul);
       x1 = RV::load(a_cur, ul);
       if (!LAST) x2 = RV::load(a_next, ul);
-      else x2 = RV::zero();
-    } else {
-      x0 = RV::zero();
-      x1 = RV::zero();
-      x2 = RV::zero();
     }
   };
-  auto process = [&](int64_t tix, const RV (&qv)[NS], const RV& wi, const RV& ai,
-                     const RV& an) {
+  // PD tiles in flight ahead of the one being processed: the loads of tile t + PD G
+  // are issued at the top of iteration t
+  int64_t tix = blockIdx.x;
+  RV q1[NS], w1 = RV::zero(), a1 = RV::zero(), n1 = RV::zero();   // tile t + G (PD = 2)
+  if (tix < ntiles) {
+    load_tile(tix, qv, wi, ai, an);
+    if constexpr (PD == 2) load_tile(min(tix + gr.G, ntiles - 1), q1, w1, a1, n1);
+  }
+  for (; tix < ntiles; tix += gr.G) {
+    RV qn[NS], wn_ = RV::zero(), an_ = RV::zero(), ann = RV::zero();
+    load_tile(min(tix + PD * gr.G, ntiles - 1), qn, wn_, an_, ann);   // prefetch
     const int64_t u = tix * 64 + lane;
     const bool live = u < units;
     double sc[VR], st[VR];
@@ -227,25 +215,16 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
     }
     // (the next tile's part writes follow the second barrier, and its vq writes
     // its first one, so two barriers per tile suffice)
-  };
-  int64_t tix = blockIdx.x;
-  if (tix < ntiles) {
-    static_for<PD>([&](auto d) {
-      constexpr int D = decltype(d)::value;
-      load_tile(min(tix + D * gr.G, ntiles - 1), buf[D], bw[D], ba[D], bn[D]);
-    });
-  }
-  bool more = tix < ntiles;
-  while (more) {
-    static_for<PD + 1>([&](auto c) {
-      constexpr int C = decltype(c)::value;            // ring slot of the current tile
-      constexpr int L = (C + PD) % (PD + 1);            // ring slot being refilled
-      if (!more) return;
-      load_tile(min(tix + PD * gr.G, ntiles - 1), buf[L], bw[L], ba[L], bn[L]);
-      process(tix, buf[C], bw[C], ba[C], bn[C]);
-      tix += gr.G;
-      more = tix < ntiles;
-    });
+    if constexpr (PD == 2) {
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl) { qv[sl] = q1[sl]; q1[sl] = qn[sl]; }
+      wi = w1; ai = a1; an = n1;
+      w1 = wn_; a1 = an_; n1 = ann;
+    } else {
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl) qv[sl] = qn[sl];
+      wi = wn_; ai = an_; an = ann;
+    }
   }
   // dead rows contribute 0: q = w' = a = 0 there, and basis values only meet them
   double pv[NV];
@@ -566,12 +545,9 @@ hipError_t fused_qr_ns(int ns, T* Q, int64_t ldq, int J, double* w, const double
       gr.G = (int)(g < 1 ? 1 : g);
       gr.GS = gr.G < REDUCE_GSMAX ? gr.G : REDUCE_GSMAX;
       gr.NG = (gr.G + gr.GS - 1) / gr.GS;
-      // prefetch depth: as many tiles ahead as register sets of 2 (NS + 3) VR
-      // registers fit beside the accumulators (8-wavefront workgroups may use 256
-      // registers, 16-wavefront ones 128), between 1 and 8
-      constexpr int BUDGET = (F == 8 ? 196 : 60) - 4 * NS;
-      constexpr int SETS = BUDGET / (2 * (NS + 3) * VR);
-      constexpr int PD = SETS - 1 < 1 ? 1 : (SETS - 1 > 8 ? 8 : SETS - 1);
+      // prefetch depth 2 while the three register sets of NS slots fit (VR NS <= 16;
+      // 16-wavefront workgroups are limited to 128 registers)
+      constexpr int PD = ((F == 8 && VR * NS <= 16) || (F == 16 && VR == 1 && NS <= 5)) ? 2 : 1;
       fused_qr_kernel<T, L, F, NS, VR, PD><<<gr.G, F * 64, sm, s>>>(Q, ldq, J, w, a_cur, a_next,
                                                                     m, coef, ldc, gr, fin);
       return hipGetLastError();
