@@ -32,7 +32,8 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published
 METRIC = "DCGS2 Arnoldi steps/s + HBM GB/s (m=2M,n=100); GMRES time-to-1e-8 vs FP64"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2104_01253_amd", "csrc", "kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2104_01253_amd", "csrc", f)
+               for f in ("kernels.hip", "device_common.h")]
 
 
 def log(*a):
@@ -40,7 +41,12 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the sources of the path's kernels (a counter record is only used when
+    it was taken with exactly these sources)."""
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel: str):

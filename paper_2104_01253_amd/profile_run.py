@@ -146,8 +146,10 @@ def summarize(fetch_dir, write_dir, trace_dir, out, command):
         if k in stats:
             kernels[k]["trace_launches"] = stats[k][0]
             kernels[k]["avg_duration_us"] = stats[k][1] / max(stats[k][0], 1) / 1e3
-    src = open(os.path.join(HERE, "csrc", "kernels.hip"), "rb").read()
-    rec = {"kernel_source_sha256_16": hashlib.sha256(src).hexdigest()[:16],
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "device_common.h"):
+        h.update(open(os.path.join(HERE, "csrc", f), "rb").read())
+    rec = {"kernel_source_sha256_16": h.hexdigest()[:16],
            "calibration": {"copy_bytes": COPY_BYTES, "fetch_scale": fscale, "write_scale": wscale},
            "command": command, "kernels": kernels}
     os.makedirs(os.path.dirname(out) or ".", exist_ok=True)
