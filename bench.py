@@ -107,6 +107,21 @@ def cpu_baseline(B, n):
                       f"oracle.gram_schmidt.dcgs2_qr (NumPy/BLAS fp64), {dt:.2f} s"}
 
 
+def calibration(torch, nbytes=1_600_000_000):
+    """Achievable HBM rates on this device for the roofline's context: a device copy
+    (read + write) and a streaming read (sum) over nbytes of FP64."""
+    x = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    t_copy = timed(torch, lambda: y.copy_(x), 5) / 5
+    x.sum()
+    t_read = timed(torch, lambda: x.sum(), 5) / 5
+    del x, y
+    torch.cuda.empty_cache()
+    return {"copy_gbps": round(2 * nbytes / t_copy / 1e9, 1),
+            "read_gbps": round(nbytes / t_read / 1e9, 1), "bytes": nbytes}
+
+
 def batched_ks_leg(torch, ctx, binding, synth, count=512):
     """Batched Krylov-Schur: `count` 2-D convection-diffusion operators, n_x ~ U{48..256},
     v ~ U(0,50)^2, 10 largest-magnitude eigenvalues, basis 60, keep 20, tol 1e-8."""
@@ -318,6 +333,8 @@ def main():
         out["gmres50_learned_guess_256sq"] = learned_guess_leg(torch, ctx, binding, synth)
         log(f"[bench] learned guess {out['gmres50_learned_guess_256sq']}")
 
+    out["roofline"]["achievable"] = calibration(torch)
+    log(f"[bench] calibration {out['roofline']['achievable']}")
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(B, n)

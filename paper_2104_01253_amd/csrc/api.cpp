@@ -591,7 +591,9 @@ static int qr_impl(dcgs2_ctx c, int64_t m, int32_t n, const double* B, int64_t l
   e.m = m;
   e.Q = Q; e.q32 = q32; e.ldq = ldq; e.B = B; e.ldb = ldb;
   e.ldh = n;
-  e.one_pass = c->qr_one_pass && n - 2 <= FUSED_QR_MAX_J;
+  // the one-pass kernel addresses a column with 32-bit byte offsets
+  e.one_pass = c->qr_one_pass && n - 2 <= FUSED_QR_MAX_J &&
+               (double)m * (q32 ? 4.0 : 8.0) < 2147483648.0;
   if ((rc = setup_expansion(c, e, 0.0))) return rc;
   CKL(launch_fill(c->R, (int64_t)n * n, 0.0, c->stream));
   CKL(launch_copy(c->w, B, m, c->stream));               // w_1 = a_1

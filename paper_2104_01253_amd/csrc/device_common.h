@@ -32,6 +32,26 @@ struct RowVec {
     }
     return r;
   }
+  // Same as load(p, u) with the byte offset of unit u given as a 32-bit value, so
+  // that the address is a uniform base plus a 32-bit lane offset (one offset
+  // register can serve many columns).
+  template <typename T>
+  __device__ static RowVec load_off32(const T* p, uint32_t off) {
+    const char* b = reinterpret_cast<const char*>(p) + off;
+    RowVec r;
+    if constexpr (VW == 2 && sizeof(T) == 8) {
+      const double2 t = *reinterpret_cast<const double2*>(b);
+      r.e[0] = t.x;
+      r.e[1] = t.y;
+    } else if constexpr (VW == 2) {
+      const float2 t = *reinterpret_cast<const float2*>(b);
+      r.e[0] = (double)t.x;
+      r.e[1] = (double)t.y;
+    } else {
+      r.e[0] = (double)*reinterpret_cast<const T*>(b);
+    }
+    return r;
+  }
   template <typename T>
   __device__ void store(T* p, int64_t u) const {
     if constexpr (VW == 2 && sizeof(T) == 8) {

@@ -127,8 +127,11 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
   RV qv[NS], wi = RV::zero(), ai = RV::zero(), an = RV::zero();
   auto load_tile = [&](int64_t t, RV (&q)[NS], RV& x0, RV& x1, RV& x2) {
     const int64_t ul = min(t * 64 + lane, units - 1);
+    // columns hold fewer than 2^31 bytes (checked by the launcher): one 32-bit
+    // offset register serves every slot's column base
+    const uint32_t off = (uint32_t)ul * (uint32_t)(VR * sizeof(TQ));
 #pragma unroll
-    for (int sl = 0; sl < NS; ++sl) q[sl] = RV::load(colp[sl], ul);
+    for (int sl = 0; sl < NS; ++sl) q[sl] = RV::load_off32(colp[sl], off);
     if (wv == 0) {
       x0 = RV::load(w, ul);
       x1 = RV::load(a_cur, ul);
@@ -566,6 +569,7 @@ hipError_t launch_fused_qr(void* Q, int q32, int64_t ldq, int J, double* w, cons
   const int Jt = J + (last ? 2 : 3);
   const int ns = (Jt + F - 1) / F;
   if (ns < 1 || ns > FMAXCOL / F) return hipErrorInvalidValue;
+  if ((double)m * (q32 ? 4.0 : 8.0) >= 2147483648.0) return hipErrorInvalidValue;  // 32-bit offsets
   // paired rows: m even, every column start 16-byte aligned (8 for an FP32 basis);
   // 8-wavefront workgroups only (16 wavefronts leave 128 registers, which two-row
   // slots overflow)
