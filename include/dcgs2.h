@@ -120,8 +120,8 @@ int dcgs2_set_tolerances(dcgs2_ctx ctx, double tau, double eta);
  * reduction of step j+1 share one read of Q (the next column a_{j+1} is already
  * known in QR, so both use the same Q rows); the arithmetic and the one reduction
  * per column are those of Alg. qr.  one_pass = 0: separate reduction and update
- * passes, as for Arnoldi.  The one-pass schedule is used when n <= 127 and a
- * column of Q holds fewer than 2^31 bytes (otherwise two passes).
+ * passes, as for Arnoldi.  The one-pass schedule is used when n <= 127 and
+ * m < 2^28 (an FP64 column of fewer than 2^31 bytes; otherwise two passes).
  * Returns DCGS2_EINVAL unless one_pass is 0 or 1. */
 int dcgs2_set_qr_schedule(dcgs2_ctx ctx, int one_pass);
 

@@ -50,8 +50,7 @@ struct dcgs2_ctx_s {
   int64_t cap_m = 0;
   int64_t cap_qa = 0, cap_qb = 0;
   double *w = nullptr, *v = nullptr, *r = nullptr;
-  double *P1 = nullptr, *P2 = nullptr;
-  unsigned* cnt = nullptr;
+  double* P1 = nullptr;
   double *coef = nullptr, *pend = nullptr;
   double *H = nullptr, *K = nullptr, *Rg = nullptr, *R = nullptr, *Z = nullptr;
   double *Sprev = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
@@ -119,7 +118,12 @@ void prof_resolve(dcgs2_ctx c) {
   c->pending.clear();
 }
 
-// Launch with optional timing: KL(class, algorithmic HBM bytes, launcher call).
+// Reducing launchers enqueue a streaming kernel and its one-workgroup finishing
+// kernel; they take the event `mid_` (recorded between the two) as last argument.
+constexpr bool reducing(int cls) { return cls == K_REDUCE || cls == K_PROJNORM || cls == K_FUSED; }
+
+// Launch with optional timing: KL(class, algorithmic HBM bytes, launcher call).  The
+// timed interval is the streaming kernel (for a reducing class, up to `mid_`).
 #define KL(cls, nbytes, call)                                            \
   do {                                                                   \
     hipEvent_t ea_ = nullptr, eb_ = nullptr;                             \
@@ -128,13 +132,23 @@ void prof_resolve(dcgs2_ctx c) {
       eb_ = prof_event(c);                                               \
       if (ea_) (void)hipEventRecord(ea_, c->stream);                     \
     }                                                                    \
+    hipEvent_t mid_ = (ea_ && eb_) ? eb_ : nullptr;                      \
+    (void)mid_;                                                          \
     hipError_t e_ = (call);                                              \
     if (e_ != hipSuccess) return DCGS2_EDEVICE;                          \
-    ++c->kernels;                                                        \
+    c->kernels += reducing(cls) ? 2 : 1;                                 \
     if (c->prof && ea_ && eb_) {                                         \
-      (void)hipEventRecord(eb_, c->stream);                              \
+      if (!reducing(cls)) (void)hipEventRecord(eb_, c->stream);          \
       c->pending.push_back({(int)(cls), ea_, eb_, (double)(nbytes)});    \
     }                                                                    \
+  } while (0)
+
+// A reducing launch without timing (two kernels).
+#define CKR(call)                                  \
+  do {                                             \
+    hipError_t e_ = (call);                        \
+    if (e_ != hipSuccess) return DCGS2_EDEVICE;    \
+    c->kernels += 2;                               \
   } while (0)
 
 int dalloc(void** p, size_t bytes) {
@@ -157,8 +171,6 @@ int ctx_ready(dcgs2_ctx c) {
   CK(hipSetDevice(c->device));
   int rc;
   if ((rc = dalloc((void**)&c->P1, sizeof(double) * (size_t)REDUCE_GMAX * LDP))) return rc;
-  if ((rc = dalloc((void**)&c->P2, sizeof(double) * (size_t)REDUCE_GSMAX * LDP))) return rc;
-  if ((rc = dalloc((void**)&c->cnt, sizeof(unsigned) * 64))) return rc;
   if ((rc = dalloc((void**)&c->coef, sizeof(double) * (2 * LDC + 8)))) return rc;
   if ((rc = dalloc((void**)&c->pend, sizeof(double) * (2 * LDC + 8)))) return rc;
   const size_t sq = sizeof(double) * (size_t)LDH_MAX * (LDH_MAX + 1);
@@ -174,7 +186,6 @@ int ctx_ready(dcgs2_ctx c) {
   if ((rc = dalloc((void**)&c->ctrl, sizeof(Ctrl)))) return rc;
   if (hipHostMalloc((void**)&c->ctrl_host, sizeof(Ctrl), hipHostMallocDefault) != hipSuccess)
     return DCGS2_ENOMEM;
-  CK(launch_zero_u32(c->cnt, 64, c->stream));
   c->ready = true;
   return DCGS2_OK;
 }
@@ -294,7 +305,7 @@ struct Expansion {
     const double qb = q32 ? 4.0 * (double)m : vm;      // bytes of one basis column
     if (!qr) KL(K_SPMV, spmv_bytes(), launch_spmv(op, c->w, nullptr, c->v, c->ctrl, s));
     KL(K_REDUCE, qb * J + 2 * vm,
-       launch_reduce(Q, q32, ldq, J, c->w, ycol(j), m, gr, fin(kind, j, J), s));
+       launch_reduce(Q, q32, ldq, J, c->w, ycol(j), m, gr, fin(kind, j, J), s, mid_));
     KL(K_UPDATE, qb * (J + 1) + 3 * vm,
        launch_update(Q, q32, ldq, J, c->w, ycol(j), nullptr, m, c->coef, LDC, !qr, 0, c->ctrl, s));
     return DCGS2_OK;
@@ -305,7 +316,7 @@ struct Expansion {
     const double vm = 8.0 * (double)m;
     const double qb = q32 ? 4.0 * (double)m : vm;
     KL(K_PROJNORM, qb * J + 2 * vm,
-       launch_project_norm(Q, q32, ldq, J, c->w, c->r, m, gr, fin(FIN_FALLBACK, j, J), s));
+       launch_project_norm(Q, q32, ldq, J, c->w, c->r, m, gr, fin(FIN_FALLBACK, j, J), s, mid_));
     KL(K_UPDATE, qb * (J + 1) + 4 * vm,
        launch_update(Q, q32, ldq, J, c->w, ycol(j), c->r, m, c->coef, LDC, !qr, 1, c->ctrl, s));
     return DCGS2_OK;
@@ -320,9 +331,9 @@ struct Expansion {
     // (rho_next keeps its initial 0)
     if (J > 0)
       KL(K_REDUCE, qb * J + vm,
-         launch_reduce(Q, q32, ldq, J, c->w, nullptr, m, gr, fin(FIN_LAST1, jvirt, J), s));
+         launch_reduce(Q, q32, ldq, J, c->w, nullptr, m, gr, fin(FIN_LAST1, jvirt, J), s, mid_));
     KL(K_PROJNORM, qb * J + 2 * vm,
-       launch_project_norm(Q, q32, ldq, J, c->w, c->r, m, gr, fin(FIN_LAST2, jvirt, J), s));
+       launch_project_norm(Q, q32, ldq, J, c->w, c->r, m, gr, fin(FIN_LAST2, jvirt, J), s, mid_));
     KL(K_SCALE, vm + qb,
        launch_scale_col(Q, q32, ldq, J, c->r, m, c->coef, LDC, c->ctrl, s));
     return DCGS2_OK;
@@ -336,7 +347,7 @@ struct Expansion {
     if (j0 > j_to) return J_last >= 0 ? enqueue_last(J_last, j_to + 1) : DCGS2_OK;
     const double qb = q32 ? 4.0 * (double)m : vm;
     KL(K_REDUCE, qb * (j0 - 2) + 2 * vm,
-       launch_reduce(Q, q32, ldq, j0 - 2, c->w, ycol(j0), m, gr, fin(kind0, j0, j0 - 2), s));
+       launch_reduce(Q, q32, ldq, j0 - 2, c->w, ycol(j0), m, gr, fin(kind0, j0, j0 - 2), s, mid_));
     for (int j = j0; j <= j_to; ++j) {
       const int J = j - 2;
       const bool last = (j == j_to);
@@ -353,19 +364,19 @@ struct Expansion {
            launch_update(Q, q32, ldq, J, c->w, ycol(j), nullptr, m, c->coef, LDC, 0, 0, c->ctrl,
                          s));
         KL(K_REDUCE, qb * (J + 1) + (last ? 1 : 2) * vm,
-           launch_reduce(Q, q32, ldq, J + 1, c->w, last ? nullptr : ycol(j + 1), m, gr, f, s));
+           launch_reduce(Q, q32, ldq, J + 1, c->w, last ? nullptr : ycol(j + 1), m, gr, f, s, mid_));
         continue;
       }
       // bytes: Q_{0..J-1}, w, a_j, a_{j+1} read; q, w written (grid sized inside)
       KL(K_FUSED, qb * (J + 1) + vm * (last ? 3 : 4),
          launch_fused_qr(Q, q32, ldq, J, c->w, ycol(j), last ? nullptr : ycol(j + 1), m,
                          c->coef, LDC, last ? 1 : 0, c->tune_fused_waves,
-                         c->tune_reduce_gmax, c->tune_pair_max_ns, gr, f, s));
+                         c->tune_reduce_gmax, c->tune_pair_max_ns, gr, f, s, mid_));
     }
     if (J_last >= 0) {
       KL(K_PROJNORM, qb * J_last + 2 * vm,
          launch_project_norm(Q, q32, ldq, J_last, c->w, c->r, m, gr,
-                             fin(FIN_LAST2, j_to + 1, J_last), s));
+                             fin(FIN_LAST2, j_to + 1, J_last), s, mid_));
       KL(K_SCALE, vm + qb,
          launch_scale_col(Q, q32, ldq, J_last, c->r, m, c->coef, LDC, c->ctrl, s));
     }
@@ -403,14 +414,11 @@ struct Expansion {
 
 int setup_expansion(dcgs2_ctx c, Expansion& e, double thresh) {
   e.c = c;
-  reduce_grid(e.m, c->tune_reduce_gmax, &e.gr.G, &e.gr.GS, &e.gr.NG);
+  reduce_grid(e.m, c->tune_reduce_gmax, &e.gr.G);
   e.gr.P1 = c->P1;
-  e.gr.P2 = c->P2;
-  e.gr.cnt = c->cnt;
   e.gr.ldp = LDP;
   CK(launch_init_ctrl(c->ctrl, c->tau, c->eta, thresh, c->stream));
-  CK(launch_zero_u32(c->cnt, 64, c->stream));
-  c->kernels += 2;
+  c->kernels += 1;
   return DCGS2_OK;
 }
 
@@ -475,10 +483,9 @@ int dcgs2_destroy(dcgs2_ctx c) {
   if (c->ready) {
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    double* bufs[] = {c->w, c->v, c->r, c->P1, c->P2, c->coef, c->pend, c->H, c->K, c->Rg,
+    double* bufs[] = {c->w, c->v, c->r, c->P1, c->coef, c->pend, c->H, c->K, c->Rg,
                       c->R, c->Z, c->Sprev, c->cs, c->sn, c->g, c->Qa, c->Qb};
     for (double* b : bufs) dfree(b);
-    dfree(c->cnt);
     dfree(c->ctrl);
     prof_resolve(c);
     for (hipEvent_t ev : c->evpool) (void)hipEventDestroy(ev);
@@ -593,7 +600,7 @@ static int qr_impl(dcgs2_ctx c, int64_t m, int32_t n, const double* B, int64_t l
   e.ldh = n;
   // the one-pass kernel addresses a column with 32-bit byte offsets
   e.one_pass = c->qr_one_pass && n - 2 <= FUSED_QR_MAX_J &&
-               (double)m * (q32 ? 4.0 : 8.0) < 2147483648.0;
+               (double)m * 8.0 < 2147483648.0;
   if ((rc = setup_expansion(c, e, 0.0))) return rc;
   CKL(launch_fill(c->R, (int64_t)n * n, 0.0, c->stream));
   CKL(launch_copy(c->w, B, m, c->stream));               // w_1 = a_1
@@ -678,15 +685,15 @@ int cgs2_qr(dcgs2_ctx c, int64_t m, int32_t n, const double* B, int64_t ldb, dou
     const double* x = a;
     if (j > 0) {
       KL(K_REDUCE, vm * (j + 1),
-         launch_reduce(Q, 0, ldq, j, a, nullptr, m, e.gr, e.fin(FIN_CGS2_S, j + 2, j), s));
+         launch_reduce(Q, 0, ldq, j, a, nullptr, m, e.gr, e.fin(FIN_CGS2_S, j + 2, j), s, mid_));
       KL(K_PROJNORM, vm * (j + 2),
-         launch_project_norm(Q, 0, ldq, j, a, c->w, m, e.gr, e.fin(FIN_NONE, j + 2, j), s));
+         launch_project_norm(Q, 0, ldq, j, a, c->w, m, e.gr, e.fin(FIN_NONE, j + 2, j), s, mid_));
       KL(K_REDUCE, vm * (j + 1),
-         launch_reduce(Q, 0, ldq, j, c->w, nullptr, m, e.gr, e.fin(FIN_LAST1, j + 2, j), s));
+         launch_reduce(Q, 0, ldq, j, c->w, nullptr, m, e.gr, e.fin(FIN_LAST1, j + 2, j), s, mid_));
       x = c->w;
     }
     KL(K_PROJNORM, vm * (j + 2),
-       launch_project_norm(Q, 0, ldq, j, x, c->r, m, e.gr, e.fin(FIN_LAST2, j + 2, j), s));
+       launch_project_norm(Q, 0, ldq, j, x, c->r, m, e.gr, e.fin(FIN_LAST2, j + 2, j), s, mid_));
     KL(K_SCALE, vm * 2, launch_scale_col(Q, 0, ldq, j, c->r, m, c->coef, LDC, c->ctrl, s));
   }
   Ctrl sc{};
@@ -723,13 +730,13 @@ int mgs_qr(dcgs2_ctx c, int64_t m, int32_t n, const double* B, int64_t ldb, doub
     for (int k = 0; k < j; ++k) {
       const double* qk = Q + (int64_t)k * ldq;
       KL(K_REDUCE, vm * 2,
-         launch_reduce(qk, 0, ldq, 1, c->w, nullptr, m, e.gr, e.fin(FIN_MGS_DOT, j, k), s));
+         launch_reduce(qk, 0, ldq, 1, c->w, nullptr, m, e.gr, e.fin(FIN_MGS_DOT, j, k), s, mid_));
       // w -= r q_k in place (the pass also forms ||w||^2 partials, unused)
       KL(K_PROJNORM, vm * 3,
-         launch_project_norm(qk, 0, ldq, 1, c->w, c->w, m, e.gr, e.fin(FIN_NONE, j, 1), s));
+         launch_project_norm(qk, 0, ldq, 1, c->w, c->w, m, e.gr, e.fin(FIN_NONE, j, 1), s, mid_));
     }
     KL(K_REDUCE, vm,
-       launch_reduce(Q, 0, ldq, 0, c->w, nullptr, m, e.gr, e.fin(FIN_MGS_NORM, j, 0), s));
+       launch_reduce(Q, 0, ldq, 0, c->w, nullptr, m, e.gr, e.fin(FIN_MGS_NORM, j, 0), s, mid_));
     KL(K_SCALE, vm * 2, launch_scale_col(Q, 0, ldq, j, c->w, m, c->coef, LDC, c->ctrl, s));
   }
   Ctrl sc{};
@@ -769,7 +776,7 @@ int gmres_solve(dcgs2_ctx c, const dcgs2_op* A, const double* b, double* x, int3
   // ||b||
   if ((rc = setup_expansion(c, e, 0.0))) return rc;
   Ctrl s{};
-  CKL(launch_reduce(nullptr, 0, ldq, 0, b, nullptr, m, e.gr, e.fin(FIN_NORM, 0, 0), c->stream));
+  CKR(launch_reduce(nullptr, 0, ldq, 0, b, nullptr, m, e.gr, e.fin(FIN_NORM, 0, 0), c->stream));
   if ((rc = read_ctrl(c, &s))) return rc;
   const double bnorm = std::sqrt(s.norm2);
   int status = DCGS2_OK;
@@ -784,7 +791,7 @@ int gmres_solve(dcgs2_ctx c, const dcgs2_op* A, const double* b, double* x, int3
       // r = b - A x into w (w_1 of the cycle), then ||r||
       if ((rc = setup_expansion(c, e, rtol * bnorm))) return rc;
       KL(K_SPMV, op_bytes(e.op) + 8.0 * m, launch_spmv(e.op, x, b, c->w, nullptr, c->stream));
-      CKL(launch_reduce(nullptr, 0, ldq, 0, c->w, nullptr, m, e.gr, e.fin(FIN_NORM, 0, 0),
+      CKR(launch_reduce(nullptr, 0, ldq, 0, c->w, nullptr, m, e.gr, e.fin(FIN_NORM, 0, 0),
                         c->stream));
       if ((rc = read_ctrl(c, &s))) return rc;
       inf.relres_true = std::sqrt(s.norm2) / bnorm;
@@ -944,12 +951,12 @@ extern "C" int dcgs2_guess_guard(dcgs2_ctx c, const dcgs2_op* A, const double* b
   Ctrl s{};
   // ||b||^2, then ||b - A x0||^2 (r into w)
   if ((rc = setup_expansion(c, e, 0.0))) return rc;
-  CKL(launch_reduce(nullptr, 0, m, 0, b, nullptr, m, e.gr, e.fin(FIN_NORM, 0, 0), c->stream));
+  CKR(launch_reduce(nullptr, 0, m, 0, b, nullptr, m, e.gr, e.fin(FIN_NORM, 0, 0), c->stream));
   if ((rc = read_ctrl(c, &s))) return rc;
   const double bn2 = s.norm2;
   if ((rc = setup_expansion(c, e, 0.0))) return rc;
   CKL(launch_spmv(e.op, x0, b, c->w, nullptr, c->stream));
-  CKL(launch_reduce(nullptr, 0, m, 0, c->w, nullptr, m, e.gr, e.fin(FIN_NORM, 0, 0), c->stream));
+  CKR(launch_reduce(nullptr, 0, m, 0, c->w, nullptr, m, e.gr, e.fin(FIN_NORM, 0, 0), c->stream));
   if ((rc = read_ctrl(c, &s))) return rc;
   const double rn2 = s.norm2;
   const double q = bn2 > 0.0 ? std::sqrt(rn2 / bn2) : INFINITY;
@@ -979,17 +986,15 @@ struct BatchedState {
   int* d_pre_rows = nullptr;
   int* d_pre_red = nullptr;
   double *Qa = nullptr, *Qb = nullptr, *vec = nullptr, *coef = nullptr, *pend = nullptr;
-  double *H = nullptr, *K = nullptr, *Z = nullptr, *P1 = nullptr, *P2 = nullptr;
+  double *H = nullptr, *K = nullptr, *Z = nullptr, *P1 = nullptr;
   Ctrl* ctrl = nullptr;
-  unsigned* cnt = nullptr;
   hipStream_t s = nullptr;
   std::vector<std::pair<int, hipGraphExec_t>> graphs;
   std::vector<hipGraph_t> graph_defs;
   ~BatchedState() {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
     for (auto& g : graph_defs) (void)hipGraphDestroy(g);
-    void* bufs[] = {d_tab, d_pre_rows, d_pre_red, Qa, Qb, vec, coef, pend, H, K, Z, P1, P2,
-                    ctrl, cnt};
+    void* bufs[] = {d_tab, d_pre_rows, d_pre_red, Qa, Qb, vec, coef, pend, H, K, Z, P1, ctrl};
     for (void* b : bufs) if (b) (void)hipFree(b);
     if (s) (void)hipStreamDestroy(s);
   }
@@ -1003,13 +1008,13 @@ int batched_cycle(BatchedState& B, int jmin, double tau, double eta, int* kernel
     CK(launch_bstencil(B.d_tab, B.d_pre_rows, B.count, B.nb_rows, j, s));
     CK(launch_breduce(B.d_tab, B.d_pre_red, B.count, B.nb_red, j, 0, B.ldp, B.ldc, B.ld, s));
     CK(launch_bupdate(B.d_tab, B.d_pre_rows, B.count, B.nb_rows, j, B.ldc, s));
-    *kernels += 3;
+    *kernels += 4;
   }
   const int jl = p + 2;                     // last column: J = p
   CK(launch_breduce(B.d_tab, B.d_pre_red, B.count, B.nb_red, jl, 1, B.ldp, B.ldc, B.ld, s));
   CK(launch_bproject_norm(B.d_tab, B.d_pre_red, B.count, B.nb_red, jl, B.ldp, B.ldc, B.ld, s));
   CK(launch_bscale(B.d_tab, B.d_pre_rows, B.count, B.nb_rows, jl, B.ldc, s));
-  *kernels += 4;
+  *kernels += 6;
   return DCGS2_OK;
 }
 
@@ -1019,7 +1024,7 @@ int batched_run_cycle(BatchedState& B, int jmin, double tau, double eta, bool us
   for (auto& g : B.graphs) {
     if (g.first == jmin) {
       CK(hipGraphLaunch(g.second, B.s));
-      *kernels += 3 * (B.p + 2 - jmin) + 4;
+      *kernels += 4 * (B.p + 2 - jmin) + 6;
       return DCGS2_OK;
     }
   }
@@ -1084,7 +1089,7 @@ int group_setup(dcgs2_ctx c, BatchedGroup& g, const dcgs2_stencil2d* ops, const 
     voff[b] = vtot;
     vtot += 3 * ldq[b];
     const int64_t gg = ((mb + 1) / 2 + c->tune_batch_units - 1) / c->tune_batch_units;
-    G[b] = (int)std::max<int64_t>(1, std::min<int64_t>(gg, REDUCE_GSMAX));
+    G[b] = (int)std::max<int64_t>(1, std::min<int64_t>(gg, BATCH_GMAX));
     gtot += G[b];
     B.pre_rows[b + 1] =
         B.pre_rows[b] + (int)((mb + BATCH_ROWS_PER_BLOCK - 1) / BATCH_ROWS_PER_BLOCK);
@@ -1102,9 +1107,7 @@ int group_setup(dcgs2_ctx c, BatchedGroup& g, const dcgs2_stencil2d* ops, const 
   if ((rc = dalloc((void**)&B.K, sizeof(double) * (size_t)count * ld * ld))) return rc;
   if ((rc = dalloc((void**)&B.Z, sizeof(double) * (size_t)count * p * p))) return rc;
   if ((rc = dalloc((void**)&B.P1, sizeof(double) * (size_t)gtot * B.ldp))) return rc;
-  if ((rc = dalloc((void**)&B.P2, sizeof(double) * (size_t)count * B.ldp))) return rc;
   if ((rc = dalloc((void**)&B.ctrl, sizeof(Ctrl) * (size_t)count))) return rc;
-  if ((rc = dalloc((void**)&B.cnt, sizeof(unsigned) * (size_t)count * 64))) return rc;
   if ((rc = dalloc((void**)&B.d_tab, sizeof(dcgs2::BInst) * (size_t)count))) return rc;
   if ((rc = dalloc((void**)&B.d_pre_rows, sizeof(int) * (size_t)(count + 1)))) return rc;
   if ((rc = dalloc((void**)&B.d_pre_red, sizeof(int) * (size_t)(count + 1)))) return rc;
@@ -1128,8 +1131,6 @@ int group_setup(dcgs2_ctx c, BatchedGroup& g, const dcgs2_stencil2d* ops, const 
     I.Z = B.Z + (size_t)b * p * p;
     I.ctrl = B.ctrl + b;
     I.P1 = B.P1 + goff * B.ldp;
-    I.P2 = B.P2 + (size_t)b * B.ldp;
-    I.cnt = B.cnt + (size_t)b * 64;
     I.G = G[b];
     goff += G[b];
     I.nx = o.nx; I.ny = o.ny;
@@ -1148,7 +1149,6 @@ int group_setup(dcgs2_ctx c, BatchedGroup& g, const dcgs2_stencil2d* ops, const 
                     B.s));
   CK(launch_fill(B.H, (int64_t)count * ld * ld, 0.0, B.s));
   CK(launch_fill(B.K, (int64_t)count * ld * ld, 0.0, B.s));
-  CK(launch_zero_u32(B.cnt, count * 64, B.s));
   g.hctrl.resize(count);
   g.Hh.resize((size_t)count * ld * ld);
   g.Zh.resize((size_t)count * p * p);

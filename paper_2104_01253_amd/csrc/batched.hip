@@ -4,10 +4,10 @@
 // basis, vectors, Hessenberg matrix and control block) is described by a BInst
 // record in a device table.  A launch's workgroups are mapped to (instance,
 // slab) pairs through prefix sums of the per-instance workgroup counts, so small
-// and large instances share one grid without idle workgroups.  Each instance has
-// its own arrival counters, so its reduction is finalised by the last of *its*
-// workgroups, with exactly the arithmetic of the single-instance kernels
-// (device_common.h and the *_body functions are shared).
+// and large instances share one grid without idle workgroups.  Each instance's
+// reduction partials are summed and finalised by a finishing kernel with one
+// workgroup per instance, with exactly the arithmetic of the single-instance
+// kernels (device_common.h and the *_body functions are shared).
 //
 // All instances advance the same step index j.  After a Krylov-Schur truncation
 // instance b keeps k_b Schur vectors and starts at j = k_b + 2 with the
@@ -38,9 +38,8 @@ __device__ __forceinline__ int find_instance(const int* __restrict__ pre, int co
 
 __device__ __forceinline__ GridRed inst_grid(const BInst& I, int ldp) {
   GridRed g;
-  g.P1 = I.P1; g.P2 = I.P2; g.cnt = I.cnt;
-  g.G = I.G; g.GS = I.G < REDUCE_GSMAX ? I.G : REDUCE_GSMAX;
-  g.NG = (I.G + g.GS - 1) / g.GS;
+  g.P1 = I.P1;
+  g.G = I.G;
   g.ldp = ldp;
   return g;
 }
@@ -187,6 +186,26 @@ __global__ __launch_bounds__(BS) void btruncate_kernel(const BInst* __restrict__
   }
 }
 
+// Second half of the reductions of step j, one workgroup per instance (see
+// finish_body): mode 0 the step's reduction, 1 and 2 the two reductions of the
+// last-column finish.
+__global__ __launch_bounds__(FINISH_BS) void bfinish_kernel(const BInst* __restrict__ tab, int j,
+                                                            int mode, int ldp, int ldc, int ldh) {
+  const BInst I = tab[blockIdx.x];
+  if (!inst_active(I, j)) return;
+  const int J = j - 2;
+  const int kind = mode == 1 ? FIN_LAST1
+                 : mode == 2 ? FIN_LAST2
+                 : (I.restart && j == I.first_j) ? FIN_RESTART : FIN_STEP;
+  const int V = mode == 1 ? J + 1 : mode == 2 ? 1 : 2 * (J + 2);
+  finish_body(inst_grid(I, ldp), V, inst_fin(I, kind, j, J, ldc, ldh), J);
+}
+
+inline size_t bfinish_smem(int j, int mode) {
+  const int J = j - 2;
+  return finish_smem(mode == 1 ? J + 1 : mode == 2 ? 1 : 2 * (J + 2), J);
+}
+
 // Per-instance control reset at the start of a cycle (one thread per instance).
 __global__ void breset_kernel(const BInst* __restrict__ tab, int count, double tau, double eta) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -211,11 +230,6 @@ inline unsigned bnb(int n) { return (unsigned)((n + BS - 1) / BS); }
 
 }  // namespace
 
-size_t batched_reduce_smem(int J, bool last) {
-  const int Jt = J + (last ? 1 : 2);
-  const int V = last ? Jt : 2 * Jt;
-  return sizeof(double) * (size_t)(V + NW * 2 * NT + (J + 2) + 3 * (J + 2) + 64);
-}
 
 hipError_t launch_bstencil(const BInst* tab, const int* pre_rows, int count, int nblocks, int j,
                            hipStream_t s) {
@@ -225,8 +239,12 @@ hipError_t launch_bstencil(const BInst* tab, const int* pre_rows, int count, int
 
 hipError_t launch_breduce(const BInst* tab, const int* pre_red, int count, int nblocks, int j,
                           int last, int ldp, int ldc, int ldh, hipStream_t s) {
-  breduce_kernel<<<nblocks, BS, batched_reduce_smem(j - 2, last != 0), s>>>(
-      tab, pre_red, count, j, last, ldp, ldc, ldh);
+  breduce_kernel<<<nblocks, BS, sizeof(double) * NW * 2 * NT, s>>>(tab, pre_red, count, j, last,
+                                                                  ldp, ldc, ldh);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int mode = last ? 1 : 0;
+  bfinish_kernel<<<count, FINISH_BS, bfinish_smem(j, mode), s>>>(tab, j, mode, ldp, ldc, ldh);
   return hipGetLastError();
 }
 
@@ -238,9 +256,11 @@ hipError_t launch_bupdate(const BInst* tab, const int* pre_rows, int count, int 
 
 hipError_t launch_bproject_norm(const BInst* tab, const int* pre_red, int count, int nblocks,
                                 int j, int ldp, int ldc, int ldh, hipStream_t s) {
-  const int J = j - 2;
-  const size_t sm = sizeof(double) * (size_t)(2 + NW + (J + 2) + 3 * (J + 2) + 2 * J + 64);
-  bproject_norm_kernel<<<nblocks, BS, sm, s>>>(tab, pre_red, count, j, ldp, ldc, ldh);
+  bproject_norm_kernel<<<nblocks, BS, sizeof(double) * NW, s>>>(tab, pre_red, count, j, ldp, ldc,
+                                                               ldh);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  bfinish_kernel<<<count, FINISH_BS, bfinish_smem(j, 2), s>>>(tab, j, 2, ldp, ldc, ldh);
   return hipGetLastError();
 }
 

@@ -173,87 +173,38 @@ __device__ void block_sum(const double (&acc)[NV], double* sh, double* out, int 
   __syncthreads();
 }
 
-// Two-level grid reduction of V partial values per workgroup (already stored in
-// gr.P1[blockIdx.x]).  Returns true in exactly one workgroup, the last to arrive,
-// with the V totals in red[] (LDS).  Workgroups are grouped by consecutive index;
-// each group is summed in index order by its last arrival, then the group sums
-// are summed in group order by the last group to finish.
-// base[0], base[stride], ..., base[(n-1) stride] (n >= 1) summed in index order.
-// The loads are issued eight at a time (clamped indices, unconditional), so a
-// chain of n partials costs n/8 memory round trips instead of n; skipped entries
-// add an exact 0.0, which leaves the sum unchanged.
-__device__ __forceinline__ double ordered_sum(const double* base, int64_t stride, int n) {
-  double s = 0.0;
-  for (int b0 = 0; b0 < n; b0 += 8) {
-    double t[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) t[i] = base[(int64_t)min(b0 + i, n - 1) * stride];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) s += (b0 + i < n) ? t[i] : 0.0;
-  }
-  return s;
-}
-
-// out[v] = sum over i < n of base[i stride + v], for v < V, by the whole workgroup.
-// With few values each value's n partials are split into up to four chunks summed
-// by different threads (then the chunk sums in order), so the chain of dependent
-// loads per thread stays short; the order of additions is fixed either way.
-__device__ void group_sum(const double* base, int64_t stride, int n, int V, double* out,
-                          double* s_part /* 256 doubles of LDS */) {
-  int C = V <= 256 ? 256 / V : 1;
-  if (C > 4) C = 4;
-  if (C > n) C = n;
-  if (C <= 1) {
-    for (int v = threadIdx.x; v < V; v += (int)blockDim.x) out[v] = ordered_sum(base + v, stride, n);
-    return;
-  }
-  const int L = (n + C - 1) / C;
-  for (int t = threadIdx.x; t < V * C; t += (int)blockDim.x) {
-    const int v = t / C, c = t % C;
-    const int lo = c * L, hi = min(n, lo + L);
-    s_part[t] = lo < hi ? ordered_sum(base + (int64_t)lo * stride + v, stride, hi - lo) : 0.0;
-  }
-  __syncthreads();
-  for (int v = threadIdx.x; v < V; v += (int)blockDim.x) {
+// red[v] = sum over g < G of P[g ldp + v] for v < V, by the whole workgroup, in a
+// fixed order: the G partials of each value are split into C chunks of consecutive
+// workgroups (C depends on V and the block size only), each chunk is summed in
+// workgroup order by one thread with 16 loads in flight, then the chunk sums are
+// added in chunk order.  sp: LDS scratch of max(V, blockDim.x) doubles.
+__device__ void partial_sum(const double* __restrict__ P, int64_t ldp, int G, int V,
+                            double* red, double* sp) {
+  const int nt = (int)blockDim.x;
+  int C = V >= nt ? 1 : nt / V;
+  if (C > 32) C = 32;
+  if (C > G) C = G;
+  const int L = (G + C - 1) / C;
+  for (int t = threadIdx.x; t < V * C; t += nt) {
+    const int v = t % V, c = t / V;     // neighbouring threads read neighbouring values
+    const int lo = c * L, hi = min(G, lo + L);
     double s = 0.0;
-    for (int c = 0; c < C; ++c) s += s_part[v * C + c];
-    out[v] = s;
+    for (int g0 = lo; g0 < hi; g0 += 16) {
+      double x[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) x[i] = P[(int64_t)min(g0 + i, hi - 1) * ldp + v];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) s += (g0 + i < hi) ? x[i] : 0.0;
+    }
+    sp[t] = s;                          // t = c V + v
   }
   __syncthreads();
-}
-
-__device__ bool grid_reduce(const GridRed& gr, int V, double* red, int bid) {
-  __shared__ int s_last;
-  __shared__ double s_part[256];
-  __threadfence();               // every thread: release this workgroup's partial stores
-  __syncthreads();
-  const int grp = bid / gr.GS;
-  const int g0 = grp * gr.GS;
-  const int gsz = min(gr.GS, gr.G - g0);
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(&gr.cnt[grp], 1u);
-    s_last = (prev == (unsigned)(gsz - 1));
+  for (int v = threadIdx.x; v < V; v += nt) {
+    double s = 0.0;
+    for (int c = 0; c < C; ++c) s += sp[c * V + v];
+    red[v] = s;
   }
   __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-  group_sum(gr.P1 + (int64_t)g0 * gr.ldp, gr.ldp, gsz, V,
-            gr.NG == 1 ? red : gr.P2 + (int64_t)grp * gr.ldp, s_part);
-  if (threadIdx.x == 0) gr.cnt[grp] = 0u;
-  if (gr.NG == 1) { __syncthreads(); return true; }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(&gr.cnt[gr.NG], 1u);
-    s_last = (prev == (unsigned)(gr.NG - 1));
-  }
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-  group_sum(gr.P2, gr.ldp, gr.NG, V, red, s_part);
-  if (threadIdx.x == 0) gr.cnt[gr.NG] = 0u;
-  __syncthreads();
-  return true;
 }
 
 __device__ __forceinline__ bool finite(double v) { return isfinite(v); }
@@ -592,6 +543,35 @@ __device__ void finalize(const FinArgs& f, double* red, double* T, double* scrat
   }
 }
 
+// Threads of the finishing workgroup (one per reduction).
+constexpr int FINISH_BS = 1024;
+
+// LDS of finish_body for V reduced values and J basis columns: the sums (V), the
+// finaliser's T (J + 3) and scratch (5 (J + 3) + 64), and the chunk sums of
+// partial_sum (max(V, FINISH_BS)).
+__host__ __device__ inline size_t finish_smem(int V, int J) {
+  const int Jp = J + 3;
+  return sizeof(double) * (size_t)(V + Jp + 5 * Jp + 64 + (V > FINISH_BS ? V : FINISH_BS));
+}
+
+// Second half of every DCGS2 reduction, run by a single workgroup after the
+// streaming kernel has stored its per-workgroup partials: the G partials of each
+// of the V values are summed in a fixed order and the step is finalised.  Running
+// it as a kernel of its own (instead of letting the last workgroup to arrive do
+// it) needs no device-scope fence in the streaming kernel: on this chip such a
+// fence writes back the L2 of the workgroup's XCD, which measured tens of
+// microseconds per launch; the kernel boundary makes the partials visible.
+__device__ void finish_body(const GridRed& gr, int V, const FinArgs& fin, int J) {
+  extern __shared__ double smem[];
+  if (fin.ctrl->state != ST_RUNNING) return;
+  double* red = smem;                     // V
+  double* T = red + V;                    // J + 3
+  double* scratch = T + (J + 3);          // 5 (J + 3) + 64
+  double* sp = scratch + 5 * (J + 3) + 64;
+  partial_sum(gr.P1, gr.ldp, gr.G, V, red, sp);
+  finalize(fin, red, T, scratch);
+}
+
 
 // ---------------------------------------------------------------------------------
 // Reduction pass: per-workgroup partial dot products of [Q_{0..J-1}, x, (y)] with
@@ -685,11 +665,7 @@ __device__ __forceinline__ void reduce_body(const TQ* __restrict__ Q, int64_t ld
   extern __shared__ double smem[];
   if (fin.ctrl->state != ST_RUNNING) return;
   const int Jt = J + (HASY ? 2 : 1);
-  const int V = HASY ? 2 * Jt : Jt;
-  double* red = smem;                       // V
-  double* shb = red + V;                    // NW * 2 * NT
-  double* T = shb + NW * 2 * NT;            // J + 2
-  double* scratch = T + (J + 2);            // 3 (J + 2) + 64
+  double* shb = smem;                       // NW * 2 * NT
   const int64_t units = m / VW;
   const int64_t per = (units + gr.G - 1) / gr.G;
   const int64_t u0 = (int64_t)bid * per;
@@ -713,7 +689,6 @@ __device__ __forceinline__ void reduce_body(const TQ* __restrict__ Q, int64_t ld
   }
   if (k0 + 1 <= J) reduce_sweep<VW, HASY, 1, TQ>(Q, ldq, k0, x, y, u0, u1, tail, m, shb, P, Jt);
   reduce_self<VW, HASY>(x, y, u0, u1, tail, m, shb, P, J, Jt);
-  if (grid_reduce(gr, V, red, bid)) finalize(fin, red, T, scratch);
 }
 
 // u = x - Q_{0..J-1} C written to ubuf; ||u||^2 grid-reduced and finalised.
@@ -724,10 +699,7 @@ __device__ __forceinline__ void project_norm_body(const TQ* __restrict__ Q, int6
                                                           const GridRed& gr, const FinArgs& fin, int bid) {
   extern __shared__ double smem[];
   if (fin.ctrl->state != ST_RUNNING) return;
-  double* red = smem;                       // 1
-  double* shb = red + 2;                    // NW
-  double* T = shb + NW;                     // J + 2
-  double* scratch = T + (J + 2);
+  double* shb = smem;                       // NW
   const double* __restrict__ C = fin.coef;
   const int64_t units = m / VW;
   const int64_t per = (units + gr.G - 1) / gr.G;
@@ -760,7 +732,6 @@ __device__ __forceinline__ void project_norm_body(const TQ* __restrict__ Q, int6
     acc[0] += uval * uval;
   }
   block_sum<1>(acc, shb, gr.P1 + (int64_t)bid * gr.ldp, 1);
-  if (grid_reduce(gr, 1, red, bid)) finalize(fin, red, T, scratch);
 }
 
 // Update pass: q_{j-1} and w_j, one row unit per thread.

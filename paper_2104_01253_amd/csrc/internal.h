@@ -63,12 +63,12 @@ struct FinArgs {
   double* Rg; double* cs; double* sn; double* g;   // GMRES Givens state
 };
 
-// Two-level deterministic grid reduction bookkeeping.
+// Deterministic grid reduction: each of the G workgroups of a streaming kernel
+// stores its partials in row bid of P1; a one-workgroup finishing kernel sums them
+// in a fixed order and finalises the step.
 struct GridRed {
-  double* P1;          // [G][ldp] per-block partials
-  double* P2;          // [NG][ldp] per-group partials
-  unsigned* cnt;       // [NG + 1] arrival counters (zero between launches)
-  int G, GS, NG, ldp;
+  double* P1;          // [G][ldp] per-workgroup partials
+  int G, ldp;
 };
 
 struct OpDev {
@@ -84,7 +84,6 @@ struct OpDev {
 // Every launcher returns the hipError_t of its launch.
 hipError_t launch_init_ctrl(Ctrl* ctrl, double tau, double eta, double thresh, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t n, double val, hipStream_t s);
-hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s);
 hipError_t launch_set_state(Ctrl* ctrl, int state, hipStream_t s);
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
 hipError_t launch_copy_cols(double* dst, int64_t ldd, const double* src, int64_t lds,
@@ -95,15 +94,17 @@ hipError_t launch_spmv(const OpDev& op, const double* x, const double* b, double
                        const Ctrl* ctrl, hipStream_t s);
 // Basis pointers are `const void*` / `void*` with q32 selecting float (FP32
 // storage, FP64 arithmetic) or double elements.
-// One DCGS2 reduction: [Q_{0..J-1}, x, (y)]^T [x, (y)] over m rows, grid-reduced,
-// then finalised by the last workgroup according to fin.
+// One DCGS2 reduction: [Q_{0..J-1}, x, (y)]^T [x, (y)] over m rows into per-workgroup
+// partials, then a finishing kernel sums them and finalises according to fin.
+// The reducing launchers enqueue both kernels; `mid`, when given, is recorded
+// between them (so that HIP events can time the streaming kernel alone).
 hipError_t launch_reduce(const void* Q, int q32, int64_t ldq, int J, const double* x,
                          const double* y, int64_t m, const GridRed& gr, const FinArgs& fin,
-                         hipStream_t s);
+                         hipStream_t s, hipEvent_t mid = nullptr);
 // u = x - Q_{0..J-1} C written to ubuf; ||u||^2 grid-reduced and finalised.
 hipError_t launch_project_norm(const void* Q, int q32, int64_t ldq, int J, const double* x,
                                double* ubuf, int64_t m, const GridRed& gr, const FinArgs& fin,
-                               hipStream_t s);
+                               hipStream_t s, hipEvent_t mid = nullptr);
 // q_{j-1} = (x - Q C)/alpha (or ubuf/alpha when qcol) into Q[:, J] (rounded to the
 // basis type), x <- yscale(y) - Q_{0..J-1} T - q T_J with the stored q,
 // yscale(y) = y/alpha (Arnoldi) or y (QR).
@@ -114,11 +115,11 @@ hipError_t launch_update(void* Q, int q32, int64_t ldq, int J, double* x, const 
 // reduction of step j+1 over [Q_{0..J}, w_j, a_next]; last != 0 reduces only
 // [Q_{0..J}, w_j]^T w_j (a_next unused).  The launcher sizes the grid itself (one
 // workgroup per CU, capped by gmax > 0 and the tile count); gr supplies the
-// partial buffers, counters and ldp.
+// partial buffer and ldp.
 hipError_t launch_fused_qr(void* Q, int q32, int64_t ldq, int J, double* w, const double* a_cur,
                            const double* a_next, int64_t m, const double* coef, int ldc, int last,
                            int fw, int gmax, int pair_max_ns, const GridRed& gr,
-                           const FinArgs& fin, hipStream_t s);
+                           const FinArgs& fin, hipStream_t s, hipEvent_t mid = nullptr);
 // fw: wavefronts per workgroup (8 or 16); two-row slots are used (when the data
 // allow them) only while the slot count NS <= pair_max_ns.
 int device_cus();                         // multiprocessors of the current device
@@ -145,8 +146,7 @@ struct BInst {
   double *H, *K;       // (p+1) x (p+1), leading dimension p+1
   double* Z;           // p x p Schur vectors of the last truncation (leading dimension p)
   Ctrl* ctrl;
-  double *P1, *P2;     // reduction partials (G x ldp) and group partials
-  unsigned* cnt;       // arrival counters (64)
+  double* P1;          // reduction partials (G x ldp)
   int G;               // workgroups of the instance's reduction passes
   int nx, ny;
   double c0, cxm, cxp, cym, cyp;
@@ -195,8 +195,8 @@ hipError_t launch_prolong(int count, int n, int nc, const float* y, const double
 int ctx_prepare(dcgs2_ctx c, hipStream_t* stream);
 
 // Grid sizing for the reductions (number of workgroups for m rows).
-void reduce_grid(int64_t m, int gmax, int* G, int* GS, int* NG);
+void reduce_grid(int64_t m, int gmax, int* G);
 constexpr int REDUCE_GMAX = 1024;
-constexpr int REDUCE_GSMAX = 32;
+constexpr int BATCH_GMAX = 32;            // reduction workgroups per batched instance
 
 }  // namespace dcgs2

@@ -21,6 +21,9 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <type_traits>
+#include <utility>
+
 #include "internal.h"
 
 namespace dcgs2 {
@@ -80,6 +83,37 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// Calls f(std::integral_constant<int, I>) for I = 0, 1, ... in order, so that
+// every index f derives from I is a compile-time constant.
+template <int... I, class F>
+__device__ __forceinline__ void static_for(std::integer_sequence<int, I...>, F&& f) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+
+// VR consecutive basis elements as loaded (converted to double where used).
+template <int VR, typename T>
+struct RawVec {
+  T e[VR];
+};
+
+template <int VR, typename T>
+__device__ __forceinline__ RawVec<VR, T> load_raw(const T* p, uint32_t off) {
+  const char* b = reinterpret_cast<const char*>(p) + off;
+  RawVec<VR, T> r;
+  if constexpr (VR == 2 && sizeof(T) == 8) {
+    const double2 t = *reinterpret_cast<const double2*>(b);
+    r.e[0] = t.x;
+    r.e[1] = t.y;
+  } else if constexpr (VR == 2) {
+    const float2 t = *reinterpret_cast<const float2*>(b);
+    r.e[0] = t.x;
+    r.e[1] = t.y;
+  } else {
+    r.e[0] = *reinterpret_cast<const T*>(b);
+  }
+  return r;
+}
+
 template <typename TQ, bool LAST, int FW, int NS, int VR, int PD>
 __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, int64_t ldq,
                                                            int J, double* __restrict__ w,
@@ -94,11 +128,11 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
   constexpr int NV = LAST ? FS : 2 * FS;  // products reduced per wavefront
   constexpr int TR = 64 * VR;
   static_assert(NS >= 1 && NS <= FS, "slot count");
+  static_assert(PD >= 1, "prefetch depth");
   using RV = RowVec<VR>;
   extern __shared__ double smem[];
   if (fin.ctrl->state != ST_RUNNING) return;
   const int Jt = J + (LAST ? 2 : 3);
-  const int V = LAST ? Jt : 2 * Jt;
   double* part = smem;                    // FW * TR * 2 partial (Q C, Q T)
   double* vq = part + FW * TR * 2;        // q, w', a_{j+1} of the tile rows
   double* vw = vq + TR;
@@ -123,32 +157,34 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
   double ax[NS], ay[NS];
 #pragma unroll
   for (int sl = 0; sl < NS; ++sl) { ax[sl] = 0.0; ay[sl] = 0.0; }
-  // software pipeline: tile loads are issued PD iterations before their use
-  RV qv[NS], wi = RV::zero(), ai = RV::zero(), an = RV::zero();
-  auto load_tile = [&](int64_t t, RV (&q)[NS], RV& x0, RV& x1, RV& x2) {
-    const int64_t ul = min(t * 64 + lane, units - 1);
-    // columns hold fewer than 2^31 bytes (checked by the launcher): one 32-bit
-    // offset register serves every slot's column base
-    const uint32_t off = (uint32_t)ul * (uint32_t)(VR * sizeof(TQ));
-#pragma unroll
-    for (int sl = 0; sl < NS; ++sl) q[sl] = RV::load_off32(colp[sl], off);
-    if (wv == 0) {
-      x0 = RV::load(w, ul);
-      x1 = RV::load(a_cur, ul);
-      if (!LAST) x2 = RV::load(a_next, ul);
-    }
+
+  // Prefetch ring: PD + 1 register stages, tile t + PD G is loaded while tile t is
+  // processed.  The ring is walked by a loop unrolled PD + 1 times, so each stage
+  // keeps fixed registers: no register copies between iterations, which would make
+  // the compiler wait for every outstanding load (the whole prefetch) once per tile.
+  struct Stage {
+    RawVec<VR, TQ> q[NS];
+    RV x0, x1, x2;                        // w, a_j, a_{j+1} (used by wavefront 0)
   };
-  // PD tiles in flight ahead of the one being processed: the loads of tile t + PD G
-  // are issued at the top of iteration t
-  int64_t tix = blockIdx.x;
-  RV q1[NS], w1 = RV::zero(), a1 = RV::zero(), n1 = RV::zero();   // tile t + G (PD = 2)
-  if (tix < ntiles) {
-    load_tile(tix, qv, wi, ai, an);
-    if constexpr (PD == 2) load_tile(min(tix + gr.G, ntiles - 1), q1, w1, a1, n1);
-  }
-  for (; tix < ntiles; tix += gr.G) {
-    RV qn[NS], wn_ = RV::zero(), an_ = RV::zero(), ann = RV::zero();
-    load_tile(min(tix + PD * gr.G, ntiles - 1), qn, wn_, an_, ann);   // prefetch
+  Stage ring[PD + 1];
+  auto issue = [&](int64_t t, Stage& S) __attribute__((always_inline)) {
+    const int64_t ul = min(t * 64 + lane, units - 1);
+    // columns hold fewer than 2^31 bytes, also in FP64 (checked by the launcher):
+    // one 32-bit offset register serves every slot's column base
+    const uint32_t off = (uint32_t)ul * (uint32_t)(VR * sizeof(TQ));
+    // Every wavefront issues the same loads, so that all of them have the same
+    // number in flight and the waits for a stage are exact.  Loads whose values are
+    // not used (slots past the basis, the vectors outside wavefront 0) read the
+    // first element of their array in every lane: one cache line, not a tile.
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl)
+      S.q[sl] = load_raw<VR>(colp[sl], wv + FW * sl < J ? off : 0u);
+    const uint32_t offv = wv == 0 ? (uint32_t)ul * (uint32_t)(VR * sizeof(double)) : 0u;
+    S.x0 = RV::load_off32(w, offv);
+    S.x1 = RV::load_off32(a_cur, offv);
+    if (!LAST) S.x2 = RV::load_off32(a_next, offv);
+  };
+  auto process = [&](int64_t tix, const Stage& S) __attribute__((always_inline)) {
     const int64_t u = tix * 64 + lane;
     const bool live = u < units;
     double sc[VR], st[VR];
@@ -159,8 +195,9 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
       if (wv + FW * sl < J) {             // uniform: a discarded slot may hold anything
 #pragma unroll
         for (int e = 0; e < VR; ++e) {
-          sc[e] = fma(qv[sl].e[e], cs[sl], sc[e]);
-          st[e] = fma(qv[sl].e[e], ts[sl], st[e]);
+          const double qx = (double)S.q[sl].e[e];
+          sc[e] = fma(qx, cs[sl], sc[e]);
+          st[e] = fma(qx, ts[sl], st[e]);
         }
       }
     }
@@ -182,9 +219,9 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
           ST += part[((v * 64 + lane) * VR + e) * 2 + 1];
         }
         if (live) {
-          qo.e[e] = stored<TQ>((wi.e[e] - SC) / alpha);
-          wo.e[e] = ai.e[e] - fma(qo.e[e], tJ, ST);
-          ao.e[e] = an.e[e];
+          qo.e[e] = stored<TQ>((S.x0.e[e] - SC) / alpha);
+          wo.e[e] = S.x1.e[e] - fma(qo.e[e], tJ, ST);
+          ao.e[e] = S.x2.e[e];
         }
         vq[r] = qo.e[e];
         vw[r] = wo.e[e];
@@ -208,7 +245,7 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
       const int k = wv + FW * sl;
 #pragma unroll
       for (int e = 0; e < VR; ++e) {
-        const double val = (k < J) ? qv[sl].e[e]
+        const double val = (k < J) ? (double)S.q[sl].e[e]
                            : (k == J) ? qq.e[e]
                            : (k == J + 1) ? ww.e[e]
                            : (!LAST && k == J + 2) ? aa.e[e] : 0.0;
@@ -218,17 +255,34 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
     }
     // (the next tile's part writes follow the second barrier, and its vq writes
     // its first one, so two barriers per tile suffice)
-    if constexpr (PD == 2) {
-#pragma unroll
-      for (int sl = 0; sl < NS; ++sl) { qv[sl] = q1[sl]; q1[sl] = qn[sl]; }
-      wi = w1; ai = a1; an = n1;
-      w1 = wn_; a1 = an_; n1 = ann;
-    } else {
-#pragma unroll
-      for (int sl = 0; sl < NS; ++sl) qv[sl] = qn[sl];
-      wi = wn_; ai = an_; an = ann;
-    }
+  };
+  // Stage s holds tile tix + s G (s < PD) at the top of every round.  A round of
+  // PD + 1 tiles runs only when all of them exist, so the loop body has no exits
+  // and the waits at its back edge are those of the steady state; the last (at
+  // most PD) tiles, already in the ring, are processed after the loop.
+  int64_t tix = blockIdx.x;
+  if (tix < ntiles) {
+    static_for(std::make_integer_sequence<int, PD>{}, [&](auto R) __attribute__((always_inline)) {
+      constexpr int r = decltype(R)::value;
+      issue(min(tix + (int64_t)r * gr.G, ntiles - 1), ring[r]);
+    });
   }
+  while (tix + (int64_t)PD * gr.G < ntiles) {
+    static_for(std::make_integer_sequence<int, PD + 1>{}, [&](auto R) __attribute__((always_inline)) {
+      constexpr int r = decltype(R)::value;
+      // tile tix + PD G goes to the stage of the tile processed last
+      issue(min(tix + (int64_t)PD * gr.G, ntiles - 1), ring[(r + PD) % (PD + 1)]);
+      process(tix, ring[r]);
+      tix += gr.G;
+    });
+  }
+  static_for(std::make_integer_sequence<int, PD>{}, [&](auto R) __attribute__((always_inline)) {
+    constexpr int r = decltype(R)::value;
+    if (tix < ntiles) {
+      process(tix, ring[r]);
+      tix += gr.G;
+    }
+  });
   // dead rows contribute 0: q = w' = a = 0 there, and basis values only meet them
   double pv[NV];
 #pragma unroll
@@ -243,11 +297,6 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
     const int rhs = idx / FS;
     if (k < Jt) gr.P1[(int64_t)blockIdx.x * gr.ldp + rhs * Jt + k] = pv[0];
   }
-  __syncthreads();                        // LDS is reused by the finaliser below
-  double* red = smem;
-  double* Tf = red + V;
-  double* scratch = Tf + (J + 3);
-  if (grid_reduce(gr, V, red, blockIdx.x)) finalize(fin, red, Tf, scratch);
 }
 
 // q = u / alpha into Q[:, J] (rounded once to the basis type).
@@ -352,11 +401,6 @@ __global__ void set_state_kernel(Ctrl* c, int state) {
   if (threadIdx.x == 0 && blockIdx.x == 0) c->state = state;
 }
 
-__global__ void zero_u32_kernel(unsigned* p, int n) {
-  const int i = blockIdx.x * BS + threadIdx.x;
-  if (i < n) p[i] = 0u;
-}
-
 __global__ void fill_kernel(double* p, int64_t n, double val) {
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
   if (i < n) p[i] = val;
@@ -383,16 +427,12 @@ inline bool aligned_to(const void* p, unsigned a) {
   return (reinterpret_cast<uintptr_t>(p) & (uintptr_t)(a - 1)) == 0;
 }
 
-size_t reduce_smem(int J, bool hasy) {
-  const int Jt = J + (hasy ? 2 : 1);
-  const int V = hasy ? 2 * Jt : Jt;
-  return sizeof(double) * (size_t)(V + NW * 2 * NT + (J + 2) + 3 * (J + 2) + 64);
-}
+size_t reduce_smem() { return sizeof(double) * (size_t)(NW * 2 * NT); }
 
 }  // namespace
 
 // ---------------------------------------------------------------------------------
-void reduce_grid(int64_t m, int gmax, int* G, int* GS, int* NG) {
+void reduce_grid(int64_t m, int gmax, int* G) {
   // one two-row unit per thread and sweep until the cap: short slabs keep the
   // latency chain of a sweep short when m is small
   const int64_t units = (m + 1) / 2;
@@ -403,8 +443,6 @@ void reduce_grid(int64_t m, int gmax, int* G, int* GS, int* NG) {
   if (g > (gmax > 0 ? gmax : 256)) g = gmax > 0 ? gmax : 256;
   if (g > REDUCE_GMAX) g = REDUCE_GMAX;
   *G = (int)g;
-  *GS = (int)(g < REDUCE_GSMAX ? g : REDUCE_GSMAX);
-  *NG = (int)((g + *GS - 1) / *GS);
 }
 
 hipError_t launch_init_ctrl(Ctrl* ctrl, double tau, double eta, double thresh, hipStream_t s) {
@@ -414,12 +452,6 @@ hipError_t launch_init_ctrl(Ctrl* ctrl, double tau, double eta, double thresh, h
 
 hipError_t launch_set_state(Ctrl* ctrl, int state, hipStream_t s) {
   set_state_kernel<<<1, 64, 0, s>>>(ctrl, state);
-  return hipGetLastError();
-}
-
-hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  zero_u32_kernel<<<nblocks(n), BS, 0, s>>>(p, n);
   return hipGetLastError();
 }
 
@@ -451,12 +483,31 @@ hipError_t launch_spmv(const OpDev& op, const double* x, const double* b, double
   return hipGetLastError();
 }
 
+namespace {
+__global__ __launch_bounds__(FINISH_BS) void finish_kernel(GridRed gr, int V, int J,
+                                                           FinArgs fin) {
+  finish_body(gr, V, fin, J);
+}
+
+// Enqueues the finishing kernel of a reduction over J basis columns with V values
+// per workgroup; records `mid` (when given) between the streaming kernel and it.
+hipError_t launch_finish(const GridRed& gr, int V, int J, const FinArgs& fin, hipEvent_t mid,
+                         hipStream_t s) {
+  hipError_t e = hipGetLastError();      // the streaming kernel's launch status
+  if (e != hipSuccess) return e;
+  if (mid && (e = hipEventRecord(mid, s)) != hipSuccess) return e;
+  const int Jf = J > fin.J ? J : fin.J;
+  finish_kernel<<<1, FINISH_BS, finish_smem(V, Jf), s>>>(gr, V, Jf, fin);
+  return hipGetLastError();
+}
+}  // namespace
+
 hipError_t launch_reduce(const void* Q, int q32, int64_t ldq, int J, const double* x,
                          const double* y, int64_t m, const GridRed& gr, const FinArgs& fin,
-                         hipStream_t s) {
+                         hipStream_t s, hipEvent_t mid) {
   const bool vec = aligned_to(Q, q32 ? 8 : 16) && (ldq % 2 == 0) && aligned16(x) &&
                    (!y || aligned16(y));
-  const size_t sm = reduce_smem(J, y != nullptr);
+  const size_t sm = reduce_smem();
   const dim3 grid(gr.G), block(BS);
 #define DCGS2_RED(VW, HY, T) \
   reduce_kernel<VW, HY, T><<<grid, block, sm, s>>>((const T*)Q, ldq, J, x, y, m, gr, fin)
@@ -468,21 +519,22 @@ hipError_t launch_reduce(const void* Q, int q32, int64_t ldq, int J, const doubl
     else { if (vec) DCGS2_RED(2, false, double); else DCGS2_RED(1, false, double); }
   }
 #undef DCGS2_RED
-  return hipGetLastError();
+  const int Jt = J + (y ? 2 : 1);
+  return launch_finish(gr, y ? 2 * Jt : Jt, J, fin, mid, s);
 }
 
 hipError_t launch_project_norm(const void* Q, int q32, int64_t ldq, int J, const double* x,
                                double* ubuf, int64_t m, const GridRed& gr, const FinArgs& fin,
-                               hipStream_t s) {
+                               hipStream_t s, hipEvent_t mid) {
   const bool vec = aligned_to(Q, q32 ? 8 : 16) && (ldq % 2 == 0) && aligned16(x) &&
                    aligned16(ubuf);
-  const size_t sm = sizeof(double) * (size_t)(2 + NW + (J + 2) + 3 * (J + 2) + 2 * J + 64);
+  const size_t sm = sizeof(double) * (size_t)NW;
 #define DCGS2_PN(VW, T) \
   project_norm_kernel<VW, T><<<gr.G, BS, sm, s>>>((const T*)Q, ldq, J, x, ubuf, m, gr, fin)
   if (q32) { if (vec) DCGS2_PN(2, float); else DCGS2_PN(1, float); }
   else { if (vec) DCGS2_PN(2, double); else DCGS2_PN(1, double); }
 #undef DCGS2_PN
-  return hipGetLastError();
+  return launch_finish(gr, 1, J, fin, mid, s);
 }
 
 hipError_t launch_update(void* Q, int q32, int64_t ldq, int J, double* x, const double* y,
@@ -506,11 +558,8 @@ hipError_t launch_update(void* Q, int q32, int64_t ldq, int J, double* x, const 
   return hipGetLastError();
 }
 
-size_t fused_qr_smem(int J, int last, int fw, int vr) {
-  const size_t work = (size_t)fw * 128 * vr + 3 * 64 * vr;
-  const int Jt = J + (last ? 2 : 3);
-  const size_t fin = (size_t)2 * Jt + (J + 3) + 3 * (J + 3) + 64;
-  return sizeof(double) * (work > fin ? work : fin) + sizeof(double) * 8;
+size_t fused_qr_smem(int fw, int vr) {
+  return sizeof(double) * ((size_t)fw * 128 * vr + 3 * 64 * vr);
 }
 
 // Multiprocessors of the current device (cached).
@@ -529,15 +578,37 @@ int device_cus() {
 }
 
 namespace {
+// Prefetch depth of the one-pass kernel: the deepest ring (PD <= 4) whose PD + 1
+// register stages of NS slots fit, with the accumulators, in the registers of a
+// wavefront (256 with 8 wavefronts per workgroup, 128 with 16) without spilling.
+// The limits are the largest NS per depth found free of scratch use by compiling
+// every instantiation for gfx950; slot_limit is the largest NS that fits at PD = 1.
+struct RingLimits {
+  int pd4, pd3, pd2, pd1;
+};
+template <typename T, bool L, int F, int VR>
+constexpr RingLimits ring_limits() {
+  if constexpr (F == 16) return RingLimits{0, 0, 0, 5};
+  if constexpr (sizeof(T) == 8 && VR == 2) return L ? RingLimits{2, 3, 7, 13} : RingLimits{2, 3, 5, 11};
+  if constexpr (sizeof(T) == 8) return L ? RingLimits{8, 11, 15, 16} : RingLimits{6, 8, 12, 16};
+  if constexpr (VR == 2) return L ? RingLimits{4, 5, 8, 14} : RingLimits{2, 4, 6, 11};
+  return L ? RingLimits{10, 12, 16, 16} : RingLimits{8, 10, 13, 16};
+}
+template <typename T, bool L, int F, int VR, int NS>
+constexpr int ring_depth() {
+  constexpr RingLimits r = ring_limits<T, L, F, VR>();
+  return NS <= r.pd4 ? 4 : NS <= r.pd3 ? 3 : NS <= r.pd2 ? 2 : 1;
+}
+
 // Dispatch on the slot count NS = ceil(Jt / FW) (compile-time in the kernel).
 // One workgroup per CU: measured faster at m = 2e6 than filling each CU to the
 // occupancy of the instantiation (several workgroups per CU for short bases).
 template <typename T, bool L, int F, int VR, int NS>
 hipError_t fused_qr_ns(int ns, T* Q, int64_t ldq, int J, double* w, const double* a_cur,
                        const double* a_next, int64_t m, const double* coef, int ldc, size_t sm,
-                       GridRed gr, int gmax, const FinArgs& fin, hipStream_t s) {
-  if constexpr (NS > FMAXCOL / F) {
-    return hipErrorInvalidValue;
+                       GridRed gr, int gmax, const FinArgs& fin, hipStream_t s, hipEvent_t mid) {
+  if constexpr (NS > FMAXCOL / F || NS > ring_limits<T, L, F, VR>().pd1) {
+    return hipErrorInvalidValue;          // not dispatched (the launcher checks the fit)
   } else {
     if (ns == NS) {
       const int64_t ntiles = (m / VR + 63) / 64;
@@ -546,17 +617,14 @@ hipError_t fused_qr_ns(int ns, T* Q, int64_t ldq, int J, double* w, const double
       if (g > REDUCE_GMAX) g = REDUCE_GMAX;
       if (g > ntiles) g = ntiles;
       gr.G = (int)(g < 1 ? 1 : g);
-      gr.GS = gr.G < REDUCE_GSMAX ? gr.G : REDUCE_GSMAX;
-      gr.NG = (gr.G + gr.GS - 1) / gr.GS;
-      // prefetch depth 2 while the three register sets of NS slots fit (VR NS <= 16;
-      // 16-wavefront workgroups are limited to 128 registers)
-      constexpr int PD = ((F == 8 && VR * NS <= 16) || (F == 16 && VR == 1 && NS <= 5)) ? 2 : 1;
+      constexpr int PD = ring_depth<T, L, F, VR, NS>();
       fused_qr_kernel<T, L, F, NS, VR, PD><<<gr.G, F * 64, sm, s>>>(Q, ldq, J, w, a_cur, a_next,
                                                                     m, coef, ldc, gr, fin);
-      return hipGetLastError();
+      const int Jt = J + (L ? 2 : 3);
+      return launch_finish(gr, L ? Jt : 2 * Jt, J, fin, mid, s);
     }
     return fused_qr_ns<T, L, F, VR, NS + 1>(ns, Q, ldq, J, w, a_cur, a_next, m, coef, ldc, sm, gr,
-                                            gmax, fin, s);
+                                            gmax, fin, s, mid);
   }
 }
 }  // namespace
@@ -564,22 +632,27 @@ hipError_t fused_qr_ns(int ns, T* Q, int64_t ldq, int J, double* w, const double
 hipError_t launch_fused_qr(void* Q, int q32, int64_t ldq, int J, double* w, const double* a_cur,
                            const double* a_next, int64_t m, const double* coef, int ldc, int last,
                            int fw, int gmax, int pair_max_ns, const GridRed& gr,
-                           const FinArgs& fin, hipStream_t s) {
-  const int F = fw == 8 ? 8 : 16;
+                           const FinArgs& fin, hipStream_t s, hipEvent_t mid) {
   const int Jt = J + (last ? 2 : 3);
+  // 16-wavefront workgroups hold at most 5 slots per wavefront without spilling
+  const int F = (fw == 16 && (Jt + 15) / 16 <= ring_limits<double, false, 16, 1>().pd1) ? 16 : 8;
   const int ns = (Jt + F - 1) / F;
   if (ns < 1 || ns > FMAXCOL / F) return hipErrorInvalidValue;
-  if ((double)m * (q32 ? 4.0 : 8.0) >= 2147483648.0) return hipErrorInvalidValue;  // 32-bit offsets
+  if ((double)m * 8.0 >= 2147483648.0) return hipErrorInvalidValue;  // 32-bit offsets
   // paired rows: m even, every column start 16-byte aligned (8 for an FP32 basis);
-  // 8-wavefront workgroups only (16 wavefronts leave 128 registers, which two-row
-  // slots overflow)
-  const bool pair = F == 8 && ns <= pair_max_ns && (m % 2 == 0) && aligned_to(Q, q32 ? 8 : 16) &&
-                    (ldq % 2 == 0) && aligned16(w) && aligned16(a_cur) &&
-                    (last || aligned16(a_next));
-  const size_t sm = fused_qr_smem(J, last, F, pair ? 2 : 1);
+  // 8-wavefront workgroups only, and only up to the slot count whose two register
+  // stages of two-row slots fit without spilling
+  const int pair_fit = q32 ? (last ? ring_limits<float, true, 8, 2>().pd1
+                                   : ring_limits<float, false, 8, 2>().pd1)
+                           : (last ? ring_limits<double, true, 8, 2>().pd1
+                                   : ring_limits<double, false, 8, 2>().pd1);
+  const bool pair = F == 8 && ns <= pair_max_ns && ns <= pair_fit && (m % 2 == 0) &&
+                    aligned_to(Q, q32 ? 8 : 16) && (ldq % 2 == 0) && aligned16(w) &&
+                    aligned16(a_cur) && (last || aligned16(a_next));
+  const size_t sm = fused_qr_smem(F, pair ? 2 : 1);
 #define DCGS2_FQ(T, L, FF, VR)                                                                 \
   return fused_qr_ns<T, L, FF, VR, 1>(ns, (T*)Q, ldq, J, w, a_cur, a_next, m, coef, ldc, sm, gr, \
-                                      gmax, fin, s)
+                                      gmax, fin, s, mid)
 #define DCGS2_FQ_V(FF, VR)                                                                    \
   do {                                                                                        \
     if (q32) { if (last) DCGS2_FQ(float, true, FF, VR); DCGS2_FQ(float, false, FF, VR); }     \
