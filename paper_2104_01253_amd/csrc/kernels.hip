@@ -133,8 +133,11 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
   extern __shared__ double smem[];
   if (fin.ctrl->state != ST_RUNNING) return;
   const int Jt = J + (LAST ? 2 : 3);
-  double* part = smem;                    // FW * TR * 2 partial (Q C, Q T)
-  double* vq = part + FW * TR * 2;        // q, w', a_{j+1} of the tile rows
+  // LDS is laid out value-major, so that neighbouring lanes touch neighbouring
+  // doubles (no bank conflicts): part[((e 2 + c) FW + wavefront) 64 + lane] holds
+  // the partial (Q C for c = 0, Q T for c = 1) of row element e of the lane
+  double* part = smem;                    // FW * TR * 2 partials
+  double* vq = part + FW * TR * 2;        // q, w', a_{j+1} of the tile rows: [e 64 + lane]
   double* vw = vq + TR;
   double* va = vw + TR;
   const double alpha = coef[2 * ldc];
@@ -203,20 +206,20 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
     }
 #pragma unroll
     for (int e = 0; e < VR; ++e) {
-      part[((wv * 64 + lane) * VR + e) * 2] = sc[e];
-      part[((wv * 64 + lane) * VR + e) * 2 + 1] = st[e];
+      part[((e * 2) * FW + wv) * 64 + lane] = sc[e];
+      part[((e * 2 + 1) * FW + wv) * 64 + lane] = st[e];
     }
     lds_barrier();
     if (wv == 0) {
       RV qo = RV::zero(), wo = RV::zero(), ao = RV::zero();
 #pragma unroll
       for (int e = 0; e < VR; ++e) {
-        const int r = lane * VR + e;
-        double SC = part[r * 2], ST = part[r * 2 + 1];
+        const int r = e * 64 + lane;
+        double SC = part[((e * 2) * FW) * 64 + lane], ST = part[((e * 2 + 1) * FW) * 64 + lane];
 #pragma unroll
         for (int v = 1; v < FW; ++v) {
-          SC += part[((v * 64 + lane) * VR + e) * 2];
-          ST += part[((v * 64 + lane) * VR + e) * 2 + 1];
+          SC += part[((e * 2) * FW + v) * 64 + lane];
+          ST += part[((e * 2 + 1) * FW + v) * 64 + lane];
         }
         if (live) {
           qo.e[e] = stored<TQ>((S.x0.e[e] - SC) / alpha);
@@ -236,9 +239,9 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
     RV qq, ww, aa;
 #pragma unroll
     for (int e = 0; e < VR; ++e) {
-      qq.e[e] = vq[lane * VR + e];
-      ww.e[e] = vw[lane * VR + e];
-      aa.e[e] = va[lane * VR + e];
+      qq.e[e] = vq[e * 64 + lane];
+      ww.e[e] = vw[e * 64 + lane];
+      aa.e[e] = va[e * 64 + lane];
     }
 #pragma unroll
     for (int sl = 0; sl < NS; ++sl) {
