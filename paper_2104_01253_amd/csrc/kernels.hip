@@ -131,7 +131,6 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
   static_assert(PD >= 1, "prefetch depth");
   using RV = RowVec<VR>;
   extern __shared__ double smem[];
-  if (fin.ctrl->state != ST_RUNNING) return;
   const int Jt = J + (LAST ? 2 : 3);
   // LDS is laid out value-major, so that neighbouring lanes touch neighbouring
   // doubles (no bank conflicts): part[((e 2 + c) FW + wavefront) 64 + lane] holds
@@ -140,20 +139,17 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
   double* vq = part + FW * TR * 2;        // q, w', a_{j+1} of the tile rows: [e 64 + lane]
   double* vw = vq + TR;
   double* va = vw + TR;
-  const double alpha = coef[2 * ldc];
-  const double tJ = coef[ldc + J];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  // per-slot column pointers and coefficients (uniform per wavefront)
+  // per-slot column pointers and coefficients (uniform per wavefront; the
+  // coefficients are read once the first tiles' loads are in flight)
   const TQ* colp[NS];
-  double cs[NS], ts[NS];
+  double alpha = 0.0, tJ = 0.0, cs[NS], ts[NS];
 #pragma unroll
   for (int sl = 0; sl < NS; ++sl) {
     const int k = wv + FW * sl;
     const int kl = k < J ? k : (J > 0 ? J - 1 : 0);
     colp[sl] = Q + (int64_t)kl * ldq;
-    cs[sl] = k < J ? coef[k] : 0.0;
-    ts[sl] = k < J ? coef[ldc + k] : 0.0;
   }
   const int64_t units = m / VR;           // row units of VR rows (m % VR == 0)
   const int64_t ntiles = (units + 63) / 64;
@@ -269,6 +265,19 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
       constexpr int r = decltype(R)::value;
       issue(min(tix + (int64_t)r * gr.G, ntiles - 1), ring[r]);
     });
+  }
+  // The control block and the coefficients are read while the first tiles load
+  // (their latencies overlap); a stopped expansion still exits before any store.
+  if (fin.ctrl->state != ST_RUNNING) return;
+  alpha = coef[2 * ldc];
+  tJ = coef[ldc + J];
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {       // unconditional loads (clamped index): one wait
+    const int k = wv + FW * sl;
+    const int kc = k < J ? k : 0;
+    const double c = coef[kc], t = coef[ldc + kc];
+    cs[sl] = k < J ? c : 0.0;
+    ts[sl] = k < J ? t : 0.0;
   }
   while (tix + (int64_t)PD * gr.G < ntiles) {
     static_for(std::make_integer_sequence<int, PD + 1>{}, [&](auto R) __attribute__((always_inline)) {
