@@ -563,12 +563,14 @@ __host__ __device__ inline size_t finish_smem(int V, int J) {
 // microseconds per launch; the kernel boundary makes the partials visible.
 __device__ void finish_body(const GridRed& gr, int V, const FinArgs& fin, int J) {
   extern __shared__ double smem[];
-  if (fin.ctrl->state != ST_RUNNING) return;
   double* red = smem;                     // V
   double* T = red + V;                    // J + 3
   double* scratch = T + (J + 3);          // 5 (J + 3) + 64
   double* sp = scratch + 5 * (J + 3) + 64;
+  // the sums only touch LDS: they are formed before the control block is read, so
+  // that the two memory latencies overlap (a stopped expansion still returns here)
   partial_sum(gr.P1, gr.ldp, gr.G, V, red, sp);
+  if (fin.ctrl->state != ST_RUNNING) return;
   finalize(fin, red, T, scratch);
 }
 
