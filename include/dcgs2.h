@@ -43,7 +43,7 @@ enum {
 #define DCGS2_MAX_N 1024
 
 /* Opaque context: binds a device and a HIP stream, owns the device workspace
- * (reduction partials, coefficient buffers, arrival counters, the Hessenberg
+ * (reduction partials, coefficient buffers, the control block, the Hessenberg
  * matrix, internal Krylov bases).  The workspace grows on demand and is freed
  * by dcgs2_destroy. */
 typedef struct dcgs2_ctx_s* dcgs2_ctx;

@@ -1,7 +1,7 @@
 // Device code shared by the single-instance kernels (kernels.hip) and the
 // batched kernels (batched.hip): row vectors, wavefront and workgroup reductions,
-// the deterministic two-level grid reduction and the scalar finaliser of a DCGS2
-// step.  Included inside namespace dcgs2 { namespace { ... } } of each file.
+// the fixed-order sum of the per-workgroup partials and the scalar finaliser of a
+// DCGS2 step.  Included inside namespace dcgs2 { namespace { ... } } of each file.
 #pragma once
 
 constexpr int BS = 256;          // threads per workgroup (4 wavefronts of 64)

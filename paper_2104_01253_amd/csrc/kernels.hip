@@ -7,8 +7,8 @@
 // One DCGS2 step j is two streaming passes over the tall-skinny basis Q plus a
 // scalar tail that a single workgroup runs:
 //   reduce   [Q_{1:j-2}, w_{j-1}, y]^T [w_{j-1}, y]   (y = A w_{j-1} or a_j)
-//            -> per-workgroup partials -> two-level fixed-order grid sum;
-//            the last workgroup to arrive finalises the step (alpha by the
+//            -> per-workgroup partials; a one-workgroup finishing kernel sums
+//            them in a fixed order and finalises the step (alpha by the
 //            Pythagorean trick, Stephen's trick, T, and the H/K or R updates).
 //   update   q_{j-1} = (w - Q C)/alpha into Q[:, j-1] and
 //            w_j = y/alpha - Q_{1:j-1} T (Arnoldi) or a_j - Q_{1:j-1} S (QR).
@@ -16,8 +16,7 @@
 // the fp64 ridge of the chip), so they are written as coalesced 16-byte
 // streams over rows with the per-column coefficients held uniform (scalar
 // registers), not as matrix-core tiles.  The grid sum is deterministic: the
-// partials of a fixed set of workgroups are added in a fixed order no matter
-// which workgroup arrives last, so repeated runs are bitwise identical.
+// partials are added in a fixed order, so repeated runs are bitwise identical.
 #include <hip/hip_runtime.h>
 #include <math.h>
 

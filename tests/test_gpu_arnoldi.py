@@ -165,3 +165,23 @@ def test_arnoldi_full_size_128cube(ctx):
     say("loo", loo)
     assert loo <= 1e-13
     assert representation_error(A, Q, H, n) <= 1e-15
+
+
+@pytest.mark.parametrize("gmax", [1, 37, 1024])
+def test_arnoldi_reduction_grid_parity(ctx, gmax):
+    """Arnoldi with 1, 37 and (at this size) 1024 reduction workgroups against the
+    oracle: the finishing kernel's fixed-order sums for every grid shape."""
+    prob = synth.cd3d(84)                  # m = 592,704: the default sizing reaches 1024
+    A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
+    r0 = synth.uniform_vector(prob.m, 5)
+    n = 12
+    say(f"arnoldi reduction grid gmax={gmax}")
+    ctx.set_tuning(binding.TUNE_REDUCE_GRID, gmax)
+    try:
+        Q, H, rc, st = run_arnoldi(ctx, binding.stencil_op(prob.grid, prob.D, prob.vel), r0, n)
+    finally:
+        ctx.set_tuning(binding.TUNE_REDUCE_GRID, 0)
+    ref = ar.dcgs2_arnoldi(lambda x: A @ x, r0, n)
+    assert rc == 0 and st["reductions"] == n + 2
+    assert relnorm(H, ref["H"]) <= TOL
+    assert relnorm(Q, ref["Q"]) <= TOL

@@ -188,3 +188,27 @@ def test_qr_hybrid_schedule_parity(ctx, m, n, ce, min_j):
     reff = gs.dcgs2_qr(B, tau=1.0)
     assert rcf == 0 and stf["pyth_fallbacks"] == reff["fallbacks"]
     assert relnorm(Rf, reff["R"]) <= TOL
+
+
+@pytest.mark.parametrize("one_pass", [True, False])
+@pytest.mark.parametrize("gmax,m,n", [(1, 20011, 40), (3, 20011, 40), (37, 4097, 17),
+                                      (1024, 600000, 12)])
+def test_qr_reduction_grid_parity(ctx, gmax, m, n, one_pass):
+    """The fixed-order sum of the per-workgroup partials for grids of 1 to 1024
+    workgroups (a single chunk, chunks of unequal length, more workgroups than
+    threads per value): parity with the oracle, and the same result twice."""
+    say(f"qr reduction grid gmax={gmax} m={m} n={n} one_pass={one_pass}")
+    B = synth.tall_skinny(m, n, 6, seed_g=500 + gmax, seed_v=11)
+    ref = gs.dcgs2_qr(B)
+    ctx.set_tuning(binding.TUNE_REDUCE_GRID, gmax)
+    ctx.set_qr_schedule(one_pass)
+    try:
+        Q, R, rc, st = run_qr(ctx, B)
+        Q2, R2, _, _ = run_qr(ctx, B)
+    finally:
+        ctx.set_tuning(binding.TUNE_REDUCE_GRID, 0)
+        ctx.set_qr_schedule(True)
+    assert rc == 0 and st["reductions"] == ref["reductions"]
+    assert relnorm(R, ref["R"]) <= TOL
+    assert np.linalg.norm((Q - ref["Q"]) @ ref["R"]) / np.linalg.norm(B) <= TOL
+    assert np.array_equal(Q, Q2) and np.array_equal(R, R2)
