@@ -110,16 +110,24 @@ def test_qr_nonfinite(ctx):
     assert st["breakdown_step"] == gs.dcgs2_qr(B)["k"] == 3
 
 
-def test_qr_full_size_kappa_1e8(ctx):
-    """The tall-skinny workload at full size: m = 2,000,000, n = 100, kappa ~ 1e8."""
+@pytest.fixture(scope="module")
+def full_size():
+    """The tall-skinny workload at full size (m = 2,000,000, n = 100, kappa ~ 1e8) and
+    the oracle's factorisation of it, computed once for the tests below."""
     m, n = 2_000_000, 100
     say("generating B 2e6 x 100")
     B = synth.tall_skinny(m, n, 8.0)
+    say("oracle qr")
+    return B, gs.dcgs2_qr(B)
+
+
+def test_qr_full_size_kappa_1e8(ctx, full_size):
+    """Full size with the default launch shapes."""
+    B, ref = full_size
+    n = B.shape[1]
     say("gpu qr")
     Q, R, rc, st = run_qr(ctx, B)
     assert rc == 0 and st["reductions"] == n + 1
-    say("oracle qr")
-    ref = gs.dcgs2_qr(B)
     assert relnorm(R, ref["R"]) <= TOL
     dq = np.linalg.norm((Q - ref["Q"]) @ ref["R"]) / np.linalg.norm(B)
     say("dQ R", dq)
@@ -127,6 +135,31 @@ def test_qr_full_size_kappa_1e8(ctx):
     loo = loss_of_orthogonality(Q)
     say("loo", loo)
     assert loo <= 1e-13
+
+
+def test_qr_full_size_every_tuned_shape(ctx, full_size):
+    """Full size under every launch-shape combination the autotuner can choose, so
+    the configuration the benchmark times is among those checked."""
+    from paper_2104_01253_amd import autotune
+    import itertools
+    B, ref = full_size
+    n = B.shape[1]
+    Bd = dev_matrix(B)
+    Qd = binding.colmajor_empty(B.shape[0], n)
+    keys = list(autotune.CANDIDATES)
+    try:
+        for combo in itertools.product(*(autotune.CANDIDATES[k] for k in keys)):
+            for k, v in zip(keys, combo):
+                ctx.set_tuning(k, v)
+            R, rc, st = ctx.qr(Bd, Qd)
+            Q = host(Qd)
+            dq = np.linalg.norm((Q - ref["Q"]) @ ref["R"]) / np.linalg.norm(B)
+            say("shape", dict(zip(keys, combo)), "R rel", relnorm(R, ref["R"]), "dQ R", dq)
+            assert rc == 0 and st["reductions"] == n + 1
+            assert relnorm(R, ref["R"]) <= TOL and dq <= TOL
+    finally:
+        for k in keys:
+            ctx.set_tuning(k, {binding.TUNE_FUSED_PAIR_SLOTS: 16}.get(k, 0))
 
 
 @pytest.mark.parametrize("m,n,ce", [(4097, 17, 2), (20011, 64, 8)])
