@@ -76,12 +76,17 @@ __global__ __launch_bounds__(BS) void bstencil_kernel(const BInst* __restrict__ 
     const uint32_t ii = (uint32_t)i;
     const uint32_t ix = ii % nx, iy = ii / nx;
     const double* x = I.w;
+    const bool ym = iy > 0, yp = iy + 1 < ny, xm = ix > 0, xp = ix + 1 < nx;
+    // unconditional loads (an absent neighbour reads the row itself); an absent
+    // term adds an exact zero
+    const double vym = x[ym ? i - nx : i], vxm = x[xm ? i - 1 : i], vc = x[i];
+    const double vxp = x[xp ? i + 1 : i], vyp = x[yp ? i + nx : i];
     double s = 0.0;
-    if (iy > 0) s += I.cym * x[i - nx];
-    if (ix > 0) s += I.cxm * x[i - 1];
-    s += I.c0 * x[i];
-    if (ix + 1 < nx) s += I.cxp * x[i + 1];
-    if (iy + 1 < ny) s += I.cyp * x[i + nx];
+    s = fma(ym ? I.cym : 0.0, vym, s);
+    s = fma(xm ? I.cxm : 0.0, vxm, s);
+    s = fma(I.c0, vc, s);
+    s = fma(xp ? I.cxp : 0.0, vxp, s);
+    s = fma(yp ? I.cyp : 0.0, vyp, s);
     I.v[i] = s;
   }
 }

@@ -323,29 +323,65 @@ __global__ void scale_col_kernel(TQ* Q, int64_t ldq, int J, const double* ubuf, 
 // ---------------------------------------------------------------------------------
 // Matvec of each Arnoldi step.  Stencils: one row per thread, neighbours summed in column
 // order; out-of-grid neighbours are zero (Dirichlet).
+// Block index for rows with XCD-local neighbours.  Workgroup b of a launch runs on
+// XCD b mod 8 (the chip's round-robin dispatch over its 8 XCDs, each with its own
+// L2).  Mapping the blocks of XCD x to one contiguous range of rows (the k-th of
+// them to range start + k) keeps a row's far stencil neighbours (a plane away) in
+// the L2 that has just read them.  The map is a bijection of [0, gridDim.x).
+__device__ __forceinline__ unsigned xcd_local_block() {
+  const unsigned nb = gridDim.x, b = blockIdx.x;
+  const unsigned q = nb / 8, r = nb % 8, x = b % 8, k = b / 8;
+  return x * q + (x < r ? x : r) + k;
+}
+
+// Rows per thread of the stencil matvec: two, a block width apart (coalesced), so
+// that fourteen loads are in flight per thread.
+constexpr int STENCIL_ROWS = 2;
+
 __global__ __launch_bounds__(BS) void stencil_kernel(OpDev op, const double* __restrict__ x,
                                                      const double* __restrict__ b,
                                                      double* __restrict__ y,
                                                      const Ctrl* __restrict__ ctrl) {
-  if (ctrl && ctrl->state != ST_RUNNING) return;
-  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if (i >= op.m) return;
   const uint32_t nx = op.nx, ny = op.ny, nz = op.nz;
-  const uint32_t ii = (uint32_t)i;
-  const uint32_t ix = ii % nx;
-  const uint32_t r = ii / nx;
-  const uint32_t iy = r % ny;
-  const uint32_t iz = r / ny;
   const int64_t sxy = (int64_t)nx * ny;
-  double s = 0.0;
-  if (nz > 1 && iz > 0) s += op.czm * x[i - sxy];
-  if (iy > 0) s += op.cym * x[i - nx];
-  if (ix > 0) s += op.cxm * x[i - 1];
-  s += op.c0 * x[i];
-  if (ix + 1 < nx) s += op.cxp * x[i + 1];
-  if (iy + 1 < ny) s += op.cyp * x[i + nx];
-  if (nz > 1 && iz + 1 < nz) s += op.czp * x[i + sxy];
-  y[i] = b ? b[i] - s : s;
+  const int64_t base = (int64_t)xcd_local_block() * (BS * STENCIL_ROWS) + threadIdx.x;
+  double v[STENCIL_ROWS][7];
+  bool in[STENCIL_ROWS][7];
+  // all loads first: an absent neighbour (or a row past m) reads a valid row
+#pragma unroll
+  for (int h = 0; h < STENCIL_ROWS; ++h) {
+    const int64_t i0 = base + h * BS;
+    const int64_t i = i0 < op.m ? i0 : op.m - 1;
+    const uint32_t ii = (uint32_t)i;
+    const uint32_t ix = ii % nx;
+    const uint32_t r = ii / nx;
+    const uint32_t iy = r % ny;
+    const uint32_t iz = r / ny;
+    in[h][0] = nz > 1 && iz > 0;
+    in[h][1] = iy > 0;
+    in[h][2] = ix > 0;
+    in[h][3] = true;
+    in[h][4] = ix + 1 < nx;
+    in[h][5] = iy + 1 < ny;
+    in[h][6] = nz > 1 && iz + 1 < nz;
+    const int64_t off[7] = {-sxy, -(int64_t)nx, -1, 0, 1, (int64_t)nx, sxy};
+#pragma unroll
+    for (int t = 0; t < 7; ++t) v[h][t] = x[in[h][t] ? i + off[t] : i];
+  }
+  // the control block is read while the loads are in flight; a stopped expansion
+  // still exits before any store
+  if (ctrl && ctrl->state != ST_RUNNING) return;
+  const double c[7] = {op.czm, op.cym, op.cxm, op.c0, op.cxp, op.cyp, op.czp};
+#pragma unroll
+  for (int h = 0; h < STENCIL_ROWS; ++h) {
+    const int64_t i = base + h * BS;
+    if (i >= op.m) continue;
+    // terms in neighbour order; an absent term adds an exact zero
+    double s = 0.0;
+#pragma unroll
+    for (int t = 0; t < 7; ++t) s = fma(in[h][t] ? c[t] : 0.0, v[h][t], s);
+    y[i] = b ? b[i] - s : s;
+  }
 }
 
 __global__ __launch_bounds__(BS) void csr_kernel(OpDev op, const double* __restrict__ x,
@@ -490,7 +526,8 @@ hipError_t launch_spmv(const OpDev& op, const double* x, const double* b, double
   if (op.kind == DCGS2_OP_CSR)
     csr_kernel<<<nblocks(op.m), BS, 0, s>>>(op, x, b, y, ctrl);
   else
-    stencil_kernel<<<nblocks(op.m), BS, 0, s>>>(op, x, b, y, ctrl);
+    stencil_kernel<<<(unsigned)((op.m + BS * STENCIL_ROWS - 1) / (BS * STENCIL_ROWS)), BS, 0, s>>>(
+        op, x, b, y, ctrl);
   return hipGetLastError();
 }
 
