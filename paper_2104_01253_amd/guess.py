@@ -46,17 +46,26 @@ def diffusion(prob, x, y):
     return np.exp(s)
 
 
+def diffusion_grid(prob, tx, ty):
+    """diffusion() on the tensor grid [iy, ix] = (tx[ix], ty[iy]) (the same values,
+    element by element: the modes are separable, so the sines are taken on the axes)."""
+    s = np.zeros((ty.shape[0], tx.shape[0]))
+    for (p, q), xi in zip(synth.KL_MODES, prob.xi):
+        s = s + (xi / (p * p + q * q) * 2.0 * np.sin(p * np.pi * tx))[None, :] \
+            * np.sin(q * np.pi * ty)[:, None]
+    return np.exp(s)
+
+
 def varcoef_csr(prob):
     """CSR arrays (rowptr int32, colind int32, val float64) of -div(D grad u) + v.grad u:
     face-centred diffusion, central convection, Dirichlet, x fastest, columns sorted."""
     n = prob.n
     h = 1.0 / (n + 1)
     t = np.arange(1, n + 1) * h
-    X, Y = np.meshgrid(t, t, indexing="xy")           # [iy, ix]
-    De = diffusion(prob, X + h / 2, Y)
-    Dw = diffusion(prob, X - h / 2, Y)
-    Dn = diffusion(prob, X, Y + h / 2)
-    Ds = diffusion(prob, X, Y - h / 2)
+    De = diffusion_grid(prob, t + h / 2, t)            # [iy, ix]
+    Dw = diffusion_grid(prob, t - h / 2, t)
+    Dn = diffusion_grid(prob, t, t + h / 2)
+    Ds = diffusion_grid(prob, t, t - h / 2)
     vx, vy = prob.vel
     ih2 = 1.0 / (h * h)
     cx = vx / (2.0 * h)
@@ -128,35 +137,90 @@ def solve(ctx, prob, b_dev, x0=None, rtol=1e-8, restart=50, max_iters=20000):
     import torch
     dop = DeviceOp(prob, b_dev.device)
     x = torch.zeros_like(b_dev) if x0 is None else x0.clone()
-    torch.cuda.synchronize()
+    # the inputs are ready on torch's stream (the library runs on its own); other
+    # threads' solver streams are not waited for
+    torch.cuda.current_stream().synchronize()
     t0 = time.perf_counter()
     rc, info = ctx.gmres(dop.op, b_dev, x, restart=restart, rtol=rtol, max_iters=max_iters)
     return x, rc, info, time.perf_counter() - t0
 
 
-def generate(ctx, count, seed, rtol=1e-5, max_iters=6000, log=None):
+def generate(ctx, count, seed, rtol=1e-5, max_iters=6000, log=None, workers=1):
     """Features and targets of the solved instances among `count` seeded ones
-    (device tensors).  An instance whose GMRES(50) does not reach rtol within
-    max_iters iterations is left out (restarted GMRES can stagnate on this family);
-    the coarse targets need far less accuracy than rtol."""
+    (device tensors, in instance order).  An instance whose GMRES(50) does not reach
+    rtol within max_iters iterations is left out (restarted GMRES can stagnate on
+    this family); the coarse targets need far less accuracy than rtol.
+
+    workers > 1 solves contiguous slices of the instances concurrently, each in a host
+    thread of its own with a context on a stream of its own (default priority; the
+    thread's torch work runs on the same stream): one 256 x 256 solve fills only a
+    small part of the GPU.  The result does not depend on the number of workers."""
+    import threading
     import torch
     probs = synth.varcoef_instances(count, seed=seed, n=N)
-    feats = torch.empty((count, FDIM), dtype=torch.float32, device="cuda")
-    targs = torch.empty((count, NC * NC), dtype=torch.float32, device="cuda")
-    kept, iters = 0, []
-    for i, p in enumerate(probs):
-        b = torch.from_numpy(synth.varcoef_rhs(p)).cuda()
-        prm = torch.from_numpy(params_of(p)).cuda()
-        x, rc, info, _ = solve(ctx, p, b, rtol=rtol, max_iters=max_iters)
-        iters.append(info["iters"])
-        if rc == binding.OK:
-            f, s = ctx.guess_features(b[None], prm[None], N, NC, FDIM)
-            feats[kept] = f[0]
-            targs[kept] = ctx.guess_targets(x[None], s, N, NC, GAIN)[0]
-            kept += 1
-        if log and (i + 1) % 256 == 0:
-            log(f"solved {i + 1}/{count}: kept {kept}, median {int(np.median(iters))} iterations")
-    return feats[:kept].contiguous(), targs[:kept].contiguous()
+    workers = max(1, min(int(workers), count))
+    rows = [None] * count                   # (features, targets) or None, per instance
+    iters = [0] * count
+    done = [0]
+    lock = threading.Lock()
+    errors = []
+
+    def run(lo, hi, c, stream=None):
+        try:
+            torch.cuda.set_device(0)
+            if stream is not None:
+                with torch.cuda.stream(stream):
+                    solve_range(lo, hi, c)
+            else:
+                solve_range(lo, hi, c)
+        except Exception as e:              # re-raised in the calling thread
+            errors.append(e)
+
+    def solve_range(lo, hi, c):
+        for i in range(lo, hi):
+            p = probs[i]
+            b = torch.from_numpy(synth.varcoef_rhs(p)).cuda()
+            prm = torch.from_numpy(params_of(p)).cuda()
+            x, rc, info, _ = solve(c, p, b, rtol=rtol, max_iters=max_iters)
+            iters[i] = info["iters"]
+            if rc == binding.OK:
+                f, sc = c.guess_features(b[None], prm[None], N, NC, FDIM)
+                rows[i] = (f[0].clone(), c.guess_targets(x[None], sc, N, NC, GAIN)[0].clone())
+            with lock:
+                done[0] += 1
+                if log and done[0] % 256 == 0:
+                    kept = sum(r is not None for r in rows)
+                    log(f"solved {done[0]}/{count}: kept {kept}, median "
+                        f"{int(np.median([t for t in iters if t]))} iterations")
+
+    if workers == 1:
+        run(0, count, ctx)
+    else:
+        bounds = [count * w // workers for w in range(workers + 1)]
+        streams = [torch.cuda.Stream() for _ in range(workers)]
+        ctxs = [binding.Context(0, stream=st.cuda_stream) for st in streams]
+        try:
+            ts = [threading.Thread(target=run, args=(bounds[w], bounds[w + 1], ctxs[w],
+                                                     streams[w]))
+                  for w in range(workers)]
+            for t in ts:
+                t.start()
+            for t in ts:
+                t.join()
+            torch.cuda.synchronize()
+        finally:
+            for c in ctxs:
+                c.close()
+    if errors:
+        raise errors[0]
+    keep = [r for r in rows if r is not None]
+    if not keep:
+        return (torch.empty((0, FDIM), dtype=torch.float32, device="cuda"),
+                torch.empty((0, NC * NC), dtype=torch.float32, device="cuda"))
+    out = (torch.stack([r[0] for r in keep]).contiguous(),
+           torch.stack([r[1] for r in keep]).contiguous())
+    torch.cuda.synchronize()                # before the per-stream rows are freed
+    return out
 
 
 def validate(model, vf, vt):
@@ -214,6 +278,7 @@ def main(argv=None):
     t.add_argument("--lr", type=float, default=1e-3)
     t.add_argument("--seed", type=int, default=100)
     t.add_argument("--out", default=DEFAULT_WEIGHTS)
+    t.add_argument("--workers", type=int, default=4, help="concurrent solver threads")
     a = ap.parse_args(argv)
     import torch
     torch.cuda.set_device(0)
@@ -224,8 +289,8 @@ def main(argv=None):
     ctx = binding.Context(0)
     model = GuessModel(ctx)
     t0 = time.perf_counter()
-    feats, targs = generate(ctx, a.count, a.seed, log=log)
-    vf, vt = generate(ctx, a.val, a.seed + 1, log=log)
+    feats, targs = generate(ctx, a.count, a.seed, log=log, workers=a.workers)
+    vf, vt = generate(ctx, a.val, a.seed + 1, log=log, workers=a.workers)
     log(f"data: {time.perf_counter() - t0:.1f} s")
     hist = train(model, feats, targs, a.epochs, lr=a.lr, log=log, val=(vf, vt))
     rel = validate(model, vf, vt)
