@@ -245,3 +245,34 @@ def test_qr_reduction_grid_parity(ctx, gmax, m, n, one_pass):
     assert relnorm(R, ref["R"]) <= TOL
     assert np.linalg.norm((Q - ref["Q"]) @ ref["R"]) / np.linalg.norm(B) <= TOL
     assert np.array_equal(Q, Q2) and np.array_equal(R, R2)
+
+
+@pytest.mark.parametrize("m,n", [(6000, 126), (6000, 127), (3001, 127), (6000, 128), (2600, 200)])
+def test_qr_one_pass_size_limits(ctx, m, n):
+    """Around the one-pass limit: n = 127 fills all 16 slots of every wavefront (J + 3 =
+    128 columns, one-row slots where two-row ones would spill; odd m), n >= 128 runs the
+    two-pass schedule."""
+    say(f"qr size limits m={m} n={n}")
+    B = synth.tall_skinny(m, n, 4, seed_g=700 + n, seed_v=13)
+    ref = gs.dcgs2_qr(B)
+    Q, R, rc, st = run_qr(ctx, B)
+    assert rc == 0 and st["reductions"] == ref["reductions"] == n + 1
+    assert relnorm(R, ref["R"]) <= TOL
+    assert np.linalg.norm((Q - ref["Q"]) @ ref["R"]) / np.linalg.norm(B) <= TOL
+    assert loss_of_orthogonality(Q) <= 1e-13
+
+
+@pytest.mark.parametrize("m,n", [(20011, 40), (20011, 100), (4097, 17)])
+def test_qr_sixteen_wavefront_workgroups(ctx, m, n):
+    """FUSED_WAVES = 16: 16-wavefront workgroups while every wavefront holds at most five
+    slots (J + 3 <= 80), 8-wavefront ones beyond."""
+    B = synth.tall_skinny(m, n, 6, seed_g=800 + n, seed_v=17)
+    ref = gs.dcgs2_qr(B)
+    ctx.set_tuning(binding.TUNE_FUSED_WAVES, 16)
+    try:
+        Q, R, rc, st = run_qr(ctx, B)
+    finally:
+        ctx.set_tuning(binding.TUNE_FUSED_WAVES, 8)
+    assert rc == 0 and st["reductions"] == ref["reductions"]
+    assert relnorm(R, ref["R"]) <= TOL
+    assert np.linalg.norm((Q - ref["Q"]) @ ref["R"]) / np.linalg.norm(B) <= TOL
