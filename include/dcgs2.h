@@ -143,9 +143,17 @@ int dcgs2_set_qr_schedule(dcgs2_ctx ctx, int one_pass);
  *                           loads) while the basis needs at most this many column
  *                           slots per wavefront, one row per lane (deeper
  *                           prefetch) beyond, 0..16 (default 16).
+ *  DCGS2_TUNE_BATCH_DENSE : krylov_schur_batched: where the dense restart work
+ *                           (Schur form, reordering, residual test, truncated H)
+ *                           runs: 0 on the GPU, one wavefront per instance (used
+ *                           while ncv <= 96), 1 on host threads (default: faster,
+ *                           as the host work of one group of instances overlaps
+ *                           the other group's expansion on the GPU).  Both follow
+ *                           the same algorithms; results agree to rounding.
  * Returns DCGS2_EINVAL for an unknown key or value. */
 enum { DCGS2_TUNE_FUSED_WAVES = 0, DCGS2_TUNE_REDUCE_GRID = 1, DCGS2_TUNE_FUSED_MIN_J = 2,
-       DCGS2_TUNE_BATCH_REDUCE_ROWS = 3, DCGS2_TUNE_FUSED_PAIR_SLOTS = 4 };
+       DCGS2_TUNE_BATCH_REDUCE_ROWS = 3, DCGS2_TUNE_FUSED_PAIR_SLOTS = 4,
+       DCGS2_TUNE_BATCH_DENSE = 5 };
 int dcgs2_set_tuning(dcgs2_ctx ctx, int32_t key, int32_t value);
 int dcgs2_get_tuning(dcgs2_ctx ctx, int32_t key, int32_t* value);
 

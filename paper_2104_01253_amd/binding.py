@@ -32,7 +32,7 @@ EXPORTS = ("dcgs2_create", "dcgs2_destroy", "dcgs2_set_tolerances", "dcgs2_qr", 
            "dcgs2_guess_features", "dcgs2_guess_targets", "dcgs2_guess_prolong",
            "dcgs2_guess_guard", "mgs_qr")
 (TUNE_FUSED_WAVES, TUNE_REDUCE_GRID, TUNE_FUSED_MIN_J, TUNE_BATCH_REDUCE_ROWS,
- TUNE_FUSED_PAIR_SLOTS) = 0, 1, 2, 3, 4
+ TUNE_FUSED_PAIR_SLOTS, TUNE_BATCH_DENSE) = 0, 1, 2, 3, 4, 5
 
 
 class Stats(ctypes.Structure):

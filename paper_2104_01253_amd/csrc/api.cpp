@@ -47,6 +47,7 @@ struct dcgs2_ctx_s {
   int tune_fused_min_j = 0;      // DCGS2_TUNE_FUSED_MIN_J
   int tune_batch_units = 4096;   // DCGS2_TUNE_BATCH_REDUCE_ROWS / 2
   int tune_pair_max_ns = 16;     // DCGS2_TUNE_FUSED_PAIR_SLOTS
+  int tune_batch_host_dense = 1; // DCGS2_TUNE_BATCH_DENSE
   int64_t cap_m = 0;
   int64_t cap_qa = 0, cap_qb = 0;
   double *w = nullptr, *v = nullptr, *r = nullptr;
@@ -526,6 +527,10 @@ int dcgs2_set_tuning(dcgs2_ctx c, int32_t key, int32_t value) {
       if (value < 0 || value > 16) return DCGS2_EINVAL;
       c->tune_pair_max_ns = value;
       return DCGS2_OK;
+    case DCGS2_TUNE_BATCH_DENSE:
+      if (value != 0 && value != 1) return DCGS2_EINVAL;
+      c->tune_batch_host_dense = value;
+      return DCGS2_OK;
     default:
       return DCGS2_EINVAL;
   }
@@ -539,6 +544,7 @@ int dcgs2_get_tuning(dcgs2_ctx c, int32_t key, int32_t* value) {
     case DCGS2_TUNE_FUSED_MIN_J: *value = c->tune_fused_min_j; return DCGS2_OK;
     case DCGS2_TUNE_BATCH_REDUCE_ROWS: *value = 2 * c->tune_batch_units; return DCGS2_OK;
     case DCGS2_TUNE_FUSED_PAIR_SLOTS: *value = c->tune_pair_max_ns; return DCGS2_OK;
+    case DCGS2_TUNE_BATCH_DENSE: *value = c->tune_batch_host_dense; return DCGS2_OK;
     default: return DCGS2_EINVAL;
   }
 }
@@ -987,6 +993,8 @@ struct BatchedState {
   int* d_pre_red = nullptr;
   double *Qa = nullptr, *Qb = nullptr, *vec = nullptr, *coef = nullptr, *pend = nullptr;
   double *H = nullptr, *K = nullptr, *Z = nullptr, *P1 = nullptr;
+  double *resid = nullptr, *ere = nullptr, *eim = nullptr;   // dense results on the GPU
+  int* ires = nullptr;
   Ctrl* ctrl = nullptr;
   hipStream_t s = nullptr;
   std::vector<std::pair<int, hipGraphExec_t>> graphs;
@@ -994,7 +1002,8 @@ struct BatchedState {
   ~BatchedState() {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
     for (auto& g : graph_defs) (void)hipGraphDestroy(g);
-    void* bufs[] = {d_tab, d_pre_rows, d_pre_red, Qa, Qb, vec, coef, pend, H, K, Z, P1, ctrl};
+    void* bufs[] = {d_tab, d_pre_rows, d_pre_red, Qa, Qb, vec, coef, pend, H, K, Z, P1, ctrl,
+                    resid, ere, eim, ires};
     for (void* b : bufs) if (b) (void)hipFree(b);
     if (s) (void)hipStreamDestroy(s);
   }
@@ -1058,6 +1067,12 @@ struct BatchedGroup {
   std::vector<int> gid;                 // global index of each local instance
   std::vector<Ctrl> hctrl;
   std::vector<double> Hh, Zh;
+  // dense restart work on the GPU (device_dense): its parameters and host copies of
+  // its per-instance results
+  bool device_dense = false;
+  int nev = 0, keep = 0;
+  std::vector<int> hres;
+  std::vector<double> hresid, here, heim;
   std::vector<dcgs2::BInst> tab_trunc;
   int kernels = 0;
   bool done = false;
@@ -1150,16 +1165,46 @@ int group_setup(dcgs2_ctx c, BatchedGroup& g, const dcgs2_stencil2d* ops, const 
   CK(launch_fill(B.H, (int64_t)count * ld * ld, 0.0, B.s));
   CK(launch_fill(B.K, (int64_t)count * ld * ld, 0.0, B.s));
   g.hctrl.resize(count);
-  g.Hh.resize((size_t)count * ld * ld);
-  g.Zh.resize((size_t)count * p * p);
+  if (g.device_dense) {
+    if ((rc = dalloc((void**)&B.ires, sizeof(int) * (size_t)count * 4))) return rc;
+    if ((rc = dalloc((void**)&B.resid, sizeof(double) * (size_t)count))) return rc;
+    if ((rc = dalloc((void**)&B.ere, sizeof(double) * (size_t)count * g.nev))) return rc;
+    if ((rc = dalloc((void**)&B.eim, sizeof(double) * (size_t)count * g.nev))) return rc;
+    g.hres.resize((size_t)count * 4);
+    g.hresid.resize(count);
+    g.here.resize((size_t)count * g.nev);
+    g.heim.resize((size_t)count * g.nev);
+  } else {
+    g.Hh.resize((size_t)count * ld * ld);
+    g.Zh.resize((size_t)count * p * p);
+  }
   return DCGS2_OK;
 }
 
 // Enqueue the read-back of a finished cycle's control blocks and H.
+constexpr double BATCH_CUT_GAP = 1e-8;   // a complex pair is never split by the cut
+
+// Enqueued behind a cycle: the control blocks, and either the projected matrices (dense
+// work on the host) or the dense work on the GPU and its per-instance results.
 int group_readback(BatchedGroup& g) {
   BatchedState& B = g.B;
   CK(hipMemcpyAsync(g.hctrl.data(), B.ctrl, sizeof(Ctrl) * B.count, hipMemcpyDeviceToHost, B.s));
-  CK(hipMemcpyAsync(g.Hh.data(), B.H, sizeof(double) * g.Hh.size(), hipMemcpyDeviceToHost, B.s));
+  if (!g.device_dense) {
+    CK(hipMemcpyAsync(g.Hh.data(), B.H, sizeof(double) * g.Hh.size(), hipMemcpyDeviceToHost,
+                      B.s));
+    return DCGS2_OK;
+  }
+  CK(launch_bschur(B.d_tab, B.count, B.p, B.ld, g.nev, g.keep, BATCH_CUT_GAP, B.H, B.Z, B.ires,
+                   B.resid, B.ere, B.eim, B.s));
+  g.kernels += 1;
+  CK(hipMemcpyAsync(g.hres.data(), B.ires, sizeof(int) * g.hres.size(), hipMemcpyDeviceToHost,
+                    B.s));
+  CK(hipMemcpyAsync(g.hresid.data(), B.resid, sizeof(double) * g.hresid.size(),
+                    hipMemcpyDeviceToHost, B.s));
+  CK(hipMemcpyAsync(g.here.data(), B.ere, sizeof(double) * g.here.size(), hipMemcpyDeviceToHost,
+                    B.s));
+  CK(hipMemcpyAsync(g.heim.data(), B.eim, sizeof(double) * g.heim.size(), hipMemcpyDeviceToHost,
+                    B.s));
   return DCGS2_OK;
 }
 
@@ -1178,7 +1223,7 @@ int group_step(dcgs2_ctx c, BatchedGroup& g, int nev, int keep, double tol, int 
         std::chrono::duration<double, std::milli>(clk::now() - g.t_cycle).count();
   }
   const clk::time_point t_host = clk::now();
-  const double CUT_GAP = 1e-8;
+  const double CUT_GAP = BATCH_CUT_GAP;
   std::vector<std::thread> pool;
   std::atomic<int> next{0};
   auto worker = [&]() {
@@ -1241,8 +1286,53 @@ int group_step(dcgs2_ctx c, BatchedGroup& g, int nev, int keep, double tol, int 
       inf.matvecs += p - k;
     }
   };
-  for (int t = 0; t < nthreads; ++t) pool.emplace_back(worker);
-  for (auto& t : pool) t.join();
+  // dense work done on the GPU: the same decisions from its per-instance results
+  auto settle = [&]() {
+    for (int b = 0; b < count; ++b) {
+      dcgs2::BInst& I = B.tab[b];
+      if (!I.active) continue;
+      const int gb = g.gid[b];
+      dcgs2_ks_info& inf = infos[gb];
+      const Ctrl& hc = g.hctrl[b];
+      inf.st.reductions += hc.reductions;
+      I.truncate = 0;
+      if (hc.state != ST_RUNNING) {
+        inf.status = hc.state == ST_BREAKDOWN ? DCGS2_BREAKDOWN
+                     : hc.state == ST_NONFINITE ? DCGS2_NONFINITE : DCGS2_NOT_CONVERGED;
+        if (hc.state == ST_FALLBACK) inf.st.pyth_fallbacks += 1;
+        inf.st.breakdown_step = hc.k;
+        I.active = 0;
+        continue;
+      }
+      const int* r = &g.hres[(size_t)4 * b];
+      if (r[0] != 1 && r[0] != -2) { I.active = 0; continue; }   // no Ritz values
+      inf.resid = g.hresid[b];
+      for (int i = 0; i < nev; ++i) {
+        eig_re[(size_t)gb * nev + i] = g.here[(size_t)b * nev + i];
+        eig_im[(size_t)gb * nev + i] = g.heim[(size_t)b * nev + i];
+      }
+      if (inf.resid <= tol) { inf.nconv = r[1]; inf.status = DCGS2_OK; I.active = 0; continue; }
+      if (inf.restarts >= max_restarts) {
+        inf.status = DCGS2_NOT_CONVERGED;
+        I.active = 0;
+        continue;
+      }
+      if (r[0] != 1) { I.active = 0; continue; }
+      const int k = r[2];
+      I.k = k;
+      I.first_j = k + 2;
+      I.restart = 1;
+      I.truncate = 1;
+      inf.restarts += 1;
+      inf.matvecs += p - k;
+    }
+  };
+  if (g.device_dense) {
+    settle();
+  } else {
+    for (int t = 0; t < nthreads; ++t) pool.emplace_back(worker);
+    for (auto& t : pool) t.join();
+  }
   if (c->prof) {
     c->acc[K_HOST_DENSE].launches += 1;
     c->acc[K_HOST_DENSE].ms +=
@@ -1258,8 +1348,12 @@ int group_step(dcgs2_ctx c, BatchedGroup& g, int nev, int keep, double tol, int 
   // truncation: Qn = Q Z_k, q_{k+1} and w; then swap the bases of truncated instances.
   // The truncation reads g.tab_trunc and the next cycle the swapped g.B.tab: two host
   // buffers, neither changed before this group's next synchronisation.
-  CK(hipMemcpyAsync(B.Z, g.Zh.data(), sizeof(double) * g.Zh.size(), hipMemcpyHostToDevice, B.s));
-  CK(hipMemcpyAsync(B.H, g.Hh.data(), sizeof(double) * g.Hh.size(), hipMemcpyHostToDevice, B.s));
+  if (!g.device_dense) {                 // on the GPU, Z and H are already in place
+    CK(hipMemcpyAsync(B.Z, g.Zh.data(), sizeof(double) * g.Zh.size(), hipMemcpyHostToDevice,
+                      B.s));
+    CK(hipMemcpyAsync(B.H, g.Hh.data(), sizeof(double) * g.Hh.size(), hipMemcpyHostToDevice,
+                      B.s));
+  }
   CK(launch_fill(B.K, (int64_t)count * ld * ld, 0.0, B.s));
   g.tab_trunc = B.tab;
   CK(hipMemcpyAsync(B.d_tab, g.tab_trunc.data(), sizeof(dcgs2::BInst) * count,
@@ -1315,6 +1409,9 @@ extern "C" int krylov_schur_batched(dcgs2_ctx c, int32_t count, const dcgs2_sten
   for (int i = 0; i < count; ++i) groups[i % ngroups].gid.push_back(order[i]);
   for (auto& g : groups) std::sort(g.gid.begin(), g.gid.end());
   for (auto& g : groups) {
+    g.device_dense = c->tune_batch_host_dense == 0 && ncv <= BSCHUR_MAX_P;
+    g.nev = nev;
+    g.keep = keep;
     if ((rc = group_setup(c, g, ops, v0, v0off, ncv))) return rc;
     g.t_cycle = std::chrono::steady_clock::now();
     if ((rc = batched_run_cycle(g.B, 2, c->tau, c->eta, use_graph != 0, &g.kernels))) return rc;

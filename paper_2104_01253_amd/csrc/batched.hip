@@ -233,6 +233,508 @@ __global__ void breset_kernel(const BInst* __restrict__ tab, int count, double t
 
 inline unsigned bnb(int n) { return (unsigned)((n + BS - 1) / BS); }
 
+// ---------------------------------------------------------------------------------
+// Dense work of the Krylov-Schur restart on the GPU, one wavefront per instance:
+// real Schur form of the p x p projected matrix, reordering by eigenvalue magnitude,
+// the residual test, and the truncated Hessenberg matrix of the next cycle.
+//
+// The algorithms are those of the host implementation (schur.cpp): Householder
+// reduction to Hessenberg form, the implicit Francis double-shift QR step (Golub &
+// Van Loan, Alg. 7.5.1) with EISPACK's exceptional shifts, the 2x2 normal form of
+// LAPACK's lanv2, and adjacent block swaps through the Sylvester equation (Bai &
+// Demmel).  T and Z live in LDS.  Scalar decisions (deflation, shifts, reflectors,
+// rotations) are taken identically by every lane; each update of rows or columns
+// gives one row or column to a lane, with the per-element arithmetic of the host
+// code, so both paths agree up to the rounding of hypot.
+constexpr int SCHUR_THREADS = 64;
+constexpr double SEPS = 2.220446049250313e-16;
+
+struct LMat {
+  double* a;
+  int ld;
+  __device__ double& operator()(int i, int j) const { return a[j * ld + i]; }
+};
+
+__device__ __forceinline__ void wsync() { __syncthreads(); }
+
+// Householder vector of x[0..n) (x, v: LDS or thread-private); every lane computes
+// the same tau; lane-parallel writes when v is shared.
+__device__ double s_make_house(const double* x, int n, double* v, bool shared_v) {
+  double sigma = 0.0;
+  for (int i = 1; i < n; ++i) sigma += x[i] * x[i];
+  const double x0 = x[0];
+  double v0 = 1.0, tau = 0.0;
+  if (sigma != 0.0) {
+    const double mu = sqrt(x0 * x0 + sigma);
+    v0 = (x0 <= 0.0) ? x0 - mu : -sigma / (x0 + mu);
+    tau = 2.0 * v0 * v0 / (sigma + v0 * v0);
+  }
+  if (shared_v) {
+    wsync();                              // every lane has read x before v is written
+    for (int i = threadIdx.x; i < n; i += SCHUR_THREADS)
+      v[i] = i == 0 ? 1.0 : (sigma == 0.0 ? x[i] : x[i] / v0);
+    wsync();
+  } else {
+    v[0] = 1.0;
+    for (int i = 1; i < n; ++i) v[i] = sigma == 0.0 ? x[i] : x[i] / v0;
+  }
+  return tau;
+}
+
+// rows r0..r0+n-1, columns c0..c1: A <- (I - tau v v^T) A   (a column per lane)
+__device__ void s_house_left(const LMat& A, const double* v, int n, double tau, int r0, int c0,
+                             int c1) {
+  for (int j = c0 + threadIdx.x; j <= c1; j += SCHUR_THREADS) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += v[i] * A(r0 + i, j);
+    s *= tau;
+    for (int i = 0; i < n; ++i) A(r0 + i, j) -= s * v[i];
+  }
+  wsync();
+}
+
+// columns c0..c0+n-1, rows r0..r1: A <- A (I - tau v v^T)   (a row per lane)
+__device__ void s_house_right(const LMat& A, const double* v, int n, double tau, int c0, int r0,
+                              int r1) {
+  for (int i = r0 + threadIdx.x; i <= r1; i += SCHUR_THREADS) {
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) s += A(i, c0 + k) * v[k];
+    s *= tau;
+    for (int k = 0; k < n; ++k) A(i, c0 + k) -= s * v[k];
+  }
+  wsync();
+}
+
+__device__ void s_rot_rows(const LMat& A, int i, int c0, int c1, double cs, double sn) {
+  for (int j = c0 + threadIdx.x; j <= c1; j += SCHUR_THREADS) {
+    const double x = A(i, j), y = A(i + 1, j);
+    A(i, j) = cs * x + sn * y;
+    A(i + 1, j) = -sn * x + cs * y;
+  }
+  wsync();
+}
+
+__device__ void s_rot_cols(const LMat& A, int i, int r0, int r1, double cs, double sn) {
+  for (int r = r0 + threadIdx.x; r <= r1; r += SCHUR_THREADS) {
+    const double x = A(r, i), y = A(r, i + 1);
+    A(r, i) = cs * x + sn * y;
+    A(r, i + 1) = -sn * x + cs * y;
+  }
+  wsync();
+}
+
+__device__ __forceinline__ void dswap(double& a, double& b) { const double t = a; a = b; b = t; }
+
+// Normal form of a real 2x2 block (scalar; see schur.cpp)
+__device__ void s_std2x2(double& a, double& b, double& c, double& d, double& cs, double& sn) {
+  if (c == 0.0) { cs = 1.0; sn = 0.0; return; }
+  if (b == 0.0) { cs = 0.0; sn = 1.0; dswap(a, d); b = -c; c = 0.0; return; }
+  if (a - d == 0.0 && signbit(b) != signbit(c)) { cs = 1.0; sn = 0.0; return; }
+  const double temp0 = a - d;
+  double p = 0.5 * temp0;
+  const double bcmax = fmax(fabs(b), fabs(c));
+  const double bcmis = fmin(fabs(b), fabs(c)) * copysign(1.0, b) * copysign(1.0, c);
+  const double scale = fmax(fabs(p), bcmax);
+  double z = (p / scale) * p + (bcmax / scale) * bcmis;
+  if (z >= 4.0 * SEPS) {
+    z = p + copysign(sqrt(scale) * sqrt(z), p);
+    a = d + z;
+    d = d - (bcmax / z) * bcmis;
+    const double tau = hypot(c, z);
+    cs = z / tau;
+    sn = c / tau;
+    b = b - c;
+    c = 0.0;
+    return;
+  }
+  const double sigma = b + c;
+  const double tau = hypot(sigma, temp0);
+  cs = sqrt(0.5 * (1.0 + fabs(sigma) / tau));
+  sn = -(p / (tau * cs)) * copysign(1.0, sigma);
+  const double aa = a * cs + b * sn, bb = -a * sn + b * cs;
+  const double cc = c * cs + d * sn, dd = -c * sn + d * cs;
+  a = aa * cs + cc * sn;
+  b = bb * cs + dd * sn;
+  c = -aa * sn + cc * cs;
+  d = -bb * sn + dd * cs;
+  const double mid = 0.5 * (a + d);
+  a = mid;
+  d = mid;
+  if (c != 0.0) {
+    if (b != 0.0) {
+      if (signbit(b) == signbit(c)) {
+        const double sab = sqrt(fabs(b)), sac = sqrt(fabs(c));
+        p = copysign(sab * sac, c);
+        const double t = 1.0 / sqrt(fabs(b + c));
+        a = mid + p;
+        d = mid - p;
+        b = b - c;
+        c = 0.0;
+        const double cs1 = sab * t, sn1 = sac * t;
+        const double ncs = cs * cs1 - sn * sn1;
+        sn = cs * sn1 + sn * cs1;
+        cs = ncs;
+      }
+    } else {
+      b = -c;
+      c = 0.0;
+      const double t = cs;
+      cs = -sn;
+      sn = t;
+    }
+  }
+}
+
+__device__ void s_standardize(int p, const LMat& T, const LMat& Z, int i) {
+  double a = T(i, i), b = T(i, i + 1), c = T(i + 1, i), d = T(i + 1, i + 1), cs, sn;
+  s_std2x2(a, b, c, d, cs, sn);
+  wsync();
+  if (i + 2 <= p - 1) s_rot_rows(T, i, i + 2, p - 1, cs, sn);
+  if (i >= 1) s_rot_cols(T, i, 0, i - 1, cs, sn);
+  s_rot_cols(Z, i, 0, p - 1, cs, sn);
+  if (threadIdx.x == 0) { T(i, i) = a; T(i, i + 1) = b; T(i + 1, i) = c; T(i + 1, i + 1) = d; }
+  wsync();
+}
+
+__device__ __forceinline__ int s_block_size(const LMat& T, int p, int i) {
+  return (i + 1 < p && T(i + 1, i) != 0.0) ? 2 : 1;
+}
+
+__device__ __forceinline__ double s_block_mag(const LMat& T, int i, int sz) {
+  if (sz == 1) return fabs(T(i, i));
+  return sqrt(T(i, i) * T(i, i) + fabs(T(i, i + 1) * T(i + 1, i)));
+}
+
+// Gaussian elimination with partial pivoting, N <= 4 (scalar)
+__device__ bool s_small_solve(int N, double* M, double* rhs) {
+  for (int k = 0; k < N; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < N; ++i)
+      if (fabs(M[k * N + i]) > fabs(M[k * N + piv])) piv = i;
+    if (M[k * N + piv] == 0.0) return false;
+    if (piv != k) {
+      for (int j = 0; j < N; ++j) dswap(M[j * N + k], M[j * N + piv]);
+      dswap(rhs[k], rhs[piv]);
+    }
+    for (int i = k + 1; i < N; ++i) {
+      const double f = M[k * N + i] / M[k * N + k];
+      for (int j = k; j < N; ++j) M[j * N + i] -= f * M[j * N + k];
+      rhs[i] -= f * rhs[k];
+    }
+  }
+  for (int i = N - 1; i >= 0; --i) {
+    double s = rhs[i];
+    for (int j = i + 1; j < N; ++j) s -= M[j * N + i] * rhs[j];
+    rhs[i] = s / M[i * N + i];
+  }
+  return true;
+}
+
+// Swap the adjacent diagonal blocks at j (sizes n1, n2); returns 0 on success.
+__device__ int s_swap_blocks(int p, const LMat& T, const LMat& Z, int j, int n1, int n2) {
+  if (n1 == 1 && n2 == 1) {
+    const double t11 = T(j, j), t22 = T(j + 1, j + 1), t12 = T(j, j + 1);
+    const double r = hypot(t12, t22 - t11);
+    if (r == 0.0) return 0;
+    const double cs = t12 / r, sn = (t22 - t11) / r;
+    wsync();
+    s_rot_rows(T, j, j, p - 1, cs, sn);
+    s_rot_cols(T, j, 0, j + 1, cs, sn);
+    s_rot_cols(Z, j, 0, p - 1, cs, sn);
+    if (threadIdx.x == 0) { T(j, j) = t22; T(j + 1, j + 1) = t11; T(j + 1, j) = 0.0; }
+    wsync();
+    return 0;
+  }
+  const int n = n1 + n2;
+  const int N = n1 * n2;
+  double M[16], x[4];
+  for (int i = 0; i < 16; ++i) M[i] = 0.0;
+  for (int jj = 0; jj < n2; ++jj)
+    for (int ii = 0; ii < n1; ++ii) {
+      const int row = ii + jj * n1;
+      for (int k = 0; k < n1; ++k) M[(k + jj * n1) * N + row] += T(j + ii, j + k);
+      for (int k = 0; k < n2; ++k) M[(ii + k * n1) * N + row] -= T(j + n1 + k, j + n1 + jj);
+      x[row] = T(j + ii, j + n1 + jj);
+    }
+  if (!s_small_solve(N, M, x)) return 1;
+  double W[16], Qh[16];
+  for (int i = 0; i < 16; ++i) { W[i] = 0.0; Qh[i] = 0.0; }
+  for (int jj = 0; jj < n2; ++jj) {
+    for (int ii = 0; ii < n1; ++ii) W[jj * n + ii] = -x[ii + jj * n1];
+    W[jj * n + n1 + jj] = 1.0;
+  }
+  for (int i = 0; i < n; ++i) Qh[i * n + i] = 1.0;
+  for (int c = 0; c < n2; ++c) {          // thread-private 4 x 4 Householder QR
+    double v[4], col[4];
+    const int len = n - c;
+    for (int i = 0; i < len; ++i) col[i] = W[c * n + c + i];
+    const double tau = s_make_house(col, len, v, false);
+    if (tau == 0.0) continue;
+    for (int jc = c; jc <= n2 - 1; ++jc) {
+      double s = 0.0;
+      for (int i = 0; i < len; ++i) s += v[i] * W[jc * n + c + i];
+      s *= tau;
+      for (int i = 0; i < len; ++i) W[jc * n + c + i] -= s * v[i];
+    }
+    for (int r = 0; r <= n - 1; ++r) {
+      double s = 0.0;
+      for (int k = 0; k < len; ++k) s += Qh[(c + k) * n + r] * v[k];
+      s *= tau;
+      for (int k = 0; k < len; ++k) Qh[(c + k) * n + r] -= s * v[k];
+    }
+  }
+  wsync();
+  // T <- Qh^T T Qh on the affected rows and columns, Z <- Z Qh
+  for (int col = j + threadIdx.x; col < p; col += SCHUR_THREADS) {   // rows j..j+n-1
+    double tmp[4];
+    for (int i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (int k = 0; k < n; ++k) s += Qh[i * n + k] * T(j + k, col);
+      tmp[i] = s;
+    }
+    for (int i = 0; i < n; ++i) T(j + i, col) = tmp[i];
+  }
+  wsync();
+  for (int r = threadIdx.x; r <= j + n - 1; r += SCHUR_THREADS) {
+    double tmp[4];
+    for (int i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (int k = 0; k < n; ++k) s += T(r, j + k) * Qh[i * n + k];
+      tmp[i] = s;
+    }
+    for (int i = 0; i < n; ++i) T(r, j + i) = tmp[i];
+  }
+  for (int r = threadIdx.x; r <= p - 1; r += SCHUR_THREADS) {
+    double tmp[4];
+    for (int i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (int k = 0; k < n; ++k) s += Z(r, j + k) * Qh[i * n + k];
+      tmp[i] = s;
+    }
+    for (int i = 0; i < n; ++i) Z(r, j + i) = tmp[i];
+  }
+  wsync();
+  if (threadIdx.x == 0) {
+    for (int cc = 0; cc < n2; ++cc)
+      for (int rr = n2; rr < n; ++rr) T(j + rr, j + cc) = 0.0;
+    if (n2 != 2) T(j + 1, j) = 0.0;
+  }
+  wsync();
+  if (n2 == 2) s_standardize(p, T, Z, j);
+  if (n1 == 2) s_standardize(p, T, Z, j + n2);
+  return 0;
+}
+
+// Real Schur form of A (p x p, LDS) in place, Z accumulated; 0 on success.
+__device__ int s_real_schur(int p, const LMat& A, const LMat& Z, double* vbuf) {
+  for (int t = threadIdx.x; t < p * p; t += SCHUR_THREADS)
+    Z(t % p, t / p) = (t % p == t / p) ? 1.0 : 0.0;
+  wsync();
+  if (p <= 1) return 0;
+  for (int k = 0; k + 2 < p; ++k) {        // Hessenberg reduction
+    const int n = p - k - 1;
+    for (int i = threadIdx.x; i < n; i += SCHUR_THREADS) vbuf[p + i] = A(k + 1 + i, k);
+    wsync();
+    const double tau = s_make_house(vbuf + p, n, vbuf, true);
+    if (tau != 0.0) {
+      s_house_left(A, vbuf, n, tau, k + 1, k, p - 1);
+      s_house_right(A, vbuf, n, tau, k + 1, 0, p - 1);
+      s_house_right(Z, vbuf, n, tau, k + 1, 0, p - 1);
+    }
+    for (int i = k + 2 + threadIdx.x; i < p; i += SCHUR_THREADS) A(i, k) = 0.0;
+    wsync();
+  }
+  double anorm = 0.0;
+  for (int j = 0; j < p; ++j)
+    for (int i = 0; i <= min(j + 1, p - 1); ++i) anorm = fmax(anorm, fabs(A(i, j)));
+  int hi = p - 1, its = 0, total = 0;
+  const int max_total = 60 * p + 100;
+  while (hi >= 0) {
+    int l = hi;
+    for (; l > 0; --l) {
+      double s = fabs(A(l - 1, l - 1)) + fabs(A(l, l));
+      if (s == 0.0) s = anorm;
+      if (fabs(A(l, l - 1)) <= SEPS * s) break;
+    }
+    wsync();
+    if (l > 0) {
+      if (threadIdx.x == 0) A(l, l - 1) = 0.0;
+      wsync();
+    }
+    if (l == hi) { hi -= 1; its = 0; continue; }
+    if (l == hi - 1) { s_standardize(p, A, Z, hi - 1); hi -= 2; its = 0; continue; }
+    if (++total > max_total) return 1;
+    ++its;
+    double s, t;
+    if (its == 10 || its == 20) {
+      const double ex = fabs(A(hi, hi - 1)) + fabs(A(hi - 1, hi - 2));
+      s = 1.5 * ex;
+      t = ex * ex;
+    } else {
+      s = A(hi - 1, hi - 1) + A(hi, hi);
+      t = A(hi - 1, hi - 1) * A(hi, hi) - A(hi - 1, hi) * A(hi, hi - 1);
+    }
+    double xx = A(l, l) * A(l, l) + A(l, l + 1) * A(l + 1, l) - s * A(l, l) + t;
+    double yy = A(l + 1, l) * (A(l, l) + A(l + 1, l + 1) - s);
+    double zz = A(l + 1, l) * A(l + 2, l + 1);
+    for (int k = l; k <= hi - 2; ++k) {
+      const double xv[3] = {xx, yy, zz};
+      double hv[3];
+      const double tau = s_make_house(xv, 3, hv, false);
+      wsync();
+      if (tau != 0.0) {
+        s_house_left(A, hv, 3, tau, k, max(l, k - 1), p - 1);
+        s_house_right(A, hv, 3, tau, k, 0, min(k + 3, hi));
+        s_house_right(Z, hv, 3, tau, k, 0, p - 1);
+      }
+      if (k > l && threadIdx.x == 0) { A(k + 1, k - 1) = 0.0; A(k + 2, k - 1) = 0.0; }
+      wsync();
+      xx = A(k + 1, k);
+      yy = A(k + 2, k);
+      if (k < hi - 2) zz = A(k + 3, k);
+    }
+    const double xv[2] = {xx, yy};
+    double hv[2];
+    const double tau = s_make_house(xv, 2, hv, false);
+    wsync();
+    if (tau != 0.0) {
+      s_house_left(A, hv, 2, tau, hi - 1, hi - 2, p - 1);
+      s_house_right(A, hv, 2, tau, hi - 1, 0, hi);
+      s_house_right(Z, hv, 2, tau, hi - 1, 0, p - 1);
+    }
+    if (threadIdx.x == 0) A(hi, hi - 2) = 0.0;
+    wsync();
+  }
+  return 0;
+}
+
+// Eigenvalues of the standardised quasi-triangular T (every lane, same values).
+__device__ void s_eigen(int p, const LMat& T, double* re, double* im) {
+  wsync();
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < p;) {
+      if (s_block_size(T, p, i) == 2) {
+        const double a = 0.5 * (T(i, i) + T(i + 1, i + 1));
+        const double w = sqrt(fabs(T(i, i + 1))) * sqrt(fabs(T(i + 1, i)));
+        re[i] = a; im[i] = w; re[i + 1] = a; im[i + 1] = -w;
+        i += 2;
+      } else {
+        re[i] = T(i, i); im[i] = 0.0;
+        i += 1;
+      }
+    }
+  }
+  wsync();
+}
+
+// Leading `count` eigenvalues by magnitude (see schur.cpp); -1 on failure.
+__device__ int s_reorder(int p, const LMat& T, const LMat& Z, int count, double cut_gap,
+                         double* re, double* im, double* mags) {
+  if (count >= p) count = p;
+  s_eigen(p, T, re, im);
+  if (threadIdx.x == 0) {                  // magnitudes, sorted descending (insertion)
+    for (int i = 0; i < p; ++i) {
+      const double v = hypot(re[i], im[i]);
+      int k = i;
+      while (k > 0 && mags[k - 1] < v) { mags[k] = mags[k - 1]; --k; }
+      mags[k] = v;
+    }
+  }
+  wsync();
+  int cnt = count > 1 ? count : 1;
+  while (cnt < p && mags[cnt - 1] - mags[cnt] <= cut_gap * mags[0]) ++cnt;
+  int filled = 0, guard = 0;
+  while (filled < cnt) {
+    if (++guard > 4 * p + 4) return -1;
+    int best = -1;
+    double bmag = -1.0;
+    for (int i = filled; i < p;) {
+      const int sz = s_block_size(T, p, i);
+      const double mg = s_block_mag(T, i, sz);
+      if (mg > bmag) { bmag = mg; best = i; }
+      i += sz;
+    }
+    int pos = best;
+    while (pos > filled) {
+      int i = filled, prev = filled;
+      while (i < pos) { prev = i; i += s_block_size(T, p, i); }
+      if (i != pos) return -1;
+      const int above = pos - prev;
+      const int cur = s_block_size(T, p, pos);
+      wsync();
+      if (s_swap_blocks(p, T, Z, prev, above, cur) != 0) return -1;
+      pos = prev;
+    }
+    filled += s_block_size(T, p, filled);
+    wsync();
+  }
+  return filled;
+}
+
+// Restart work of every active, running instance: Schur form and reordering of its
+// p x p projected matrix H (ld x ld in B.H), the Ritz values (the first nev after
+// reordering) and residual estimate, then reordering for `keep` and the truncated
+// Hessenberg matrix and Schur vectors of the next cycle, written in place (H) and to
+// Zout (p x p per instance).  ires[b] = {state, kn, k, 0}: state 0 skipped (inactive
+// or stopped), 1 done, -1 the Schur form or the first reordering failed (no Ritz
+// values), -2 the reordering for keep failed (Ritz values and residual valid).
+__global__ __launch_bounds__(SCHUR_THREADS) void bschur_kernel(
+    const BInst* __restrict__ tab, int p, int ld, int nev, int keep, double cut_gap,
+    double* __restrict__ Hall, double* __restrict__ Zall, int* __restrict__ ires,
+    double* __restrict__ resid, double* __restrict__ ere, double* __restrict__ eim) {
+  extern __shared__ double sm[];
+  const int b = blockIdx.x;
+  const BInst I = tab[b];
+  int* out = ires + 4 * b;
+  if (!I.active || I.ctrl->state != ST_RUNNING) {
+    if (threadIdx.x == 0) { out[0] = 0; out[1] = 0; out[2] = 0; out[3] = 0; }
+    return;
+  }
+  double* Hb = Hall + (size_t)b * ld * ld;
+  double* Zb = Zall + (size_t)b * p * p;
+  const LMat T{sm, p}, Z{sm + p * p, p};
+  double* vbuf = sm + 2 * p * p;          // 2p
+  double* re = vbuf + 2 * p;
+  double* im = re + p;
+  double* mags = im + p;
+  const double h = Hb[(size_t)(p - 1) * ld + p];
+  for (int t = threadIdx.x; t < p * p; t += SCHUR_THREADS) T(t % p, t / p) = Hb[(t / p) * ld + t % p];
+  wsync();
+  int fail = s_real_schur(p, T, Z, vbuf);
+  int kn = fail ? -1 : s_reorder(p, T, Z, nev, cut_gap, re, im, mags);
+  if (kn < 0) {
+    if (threadIdx.x == 0) { out[0] = -1; out[1] = 0; out[2] = 0; out[3] = 0; }
+    return;
+  }
+  s_eigen(p, T, re, im);
+  if (threadIdx.x == 0) {
+    double bn = 0.0, tmin = INFINITY;
+    for (int i = 0; i < kn; ++i) {
+      const double bi = h * Z(p - 1, i);
+      bn += bi * bi;
+      tmin = fmin(tmin, hypot(re[i], im[i]));
+    }
+    resid[b] = sqrt(bn) / tmin;
+    for (int i = 0; i < nev; ++i) {
+      ere[(size_t)b * nev + i] = re[i];
+      eim[(size_t)b * nev + i] = im[i];
+    }
+  }
+  wsync();
+  const int k = s_reorder(p, T, Z, keep, cut_gap, re, im, mags);
+  if (threadIdx.x == 0) { out[0] = (k < 0 || k >= p) ? -2 : 1; out[1] = kn; out[2] = k; out[3] = 0; }
+  if (k < 0 || k >= p) return;
+  // next cycle: H = [T_k; h Z(p-1, 0:k)] in the leading (k+1) x k block, zero elsewhere
+  for (int t = threadIdx.x; t < ld * ld; t += SCHUR_THREADS) {
+    const int i = t % ld, jj = t / ld;
+    double v = 0.0;
+    if (jj < k && i < k) v = T(i, jj);
+    else if (jj < k && i == k) v = h * Z(p - 1, jj);
+    Hb[t] = v;
+  }
+  for (int t = threadIdx.x; t < p * p; t += SCHUR_THREADS) Zb[t] = Z(t % p, t / p);
+}
+
 }  // namespace
 
 
@@ -278,6 +780,18 @@ hipError_t launch_bscale(const BInst* tab, const int* pre_rows, int count, int n
 hipError_t launch_btruncate(const BInst* tab, const int* pre_rows, int count, int nblocks, int p,
                             hipStream_t s) {
   btruncate_kernel<8><<<nblocks, BS, 0, s>>>(tab, pre_rows, count, p);
+  return hipGetLastError();
+}
+
+size_t bschur_smem(int p) { return sizeof(double) * (size_t)(2 * p * p + 5 * p); }
+
+hipError_t launch_bschur(const BInst* tab, int count, int p, int ld, int nev, int keep,
+                         double cut_gap, double* H, double* Z, int* ires, double* resid,
+                         double* ere, double* eim, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (p < 2 || p > BSCHUR_MAX_P || nev < 1 || keep < 1) return hipErrorInvalidValue;
+  bschur_kernel<<<count, SCHUR_THREADS, bschur_smem(p), s>>>(tab, p, ld, nev, keep, cut_gap, H, Z,
+                                                             ires, resid, ere, eim);
   return hipGetLastError();
 }
 

@@ -170,6 +170,17 @@ hipError_t launch_bscale(const BInst* tab, const int* pre_rows, int count, int n
 hipError_t launch_btruncate(const BInst* tab, const int* pre_rows, int count, int nblocks, int p,
                             hipStream_t s);
 hipError_t launch_breset(const BInst* tab, int count, double tau, double eta, hipStream_t s);
+// Dense restart work of every active, running instance on the GPU (one wavefront per
+// instance, T and Z in LDS): real Schur form of the p x p H, reordering by magnitude
+// for nev (Ritz values into ere/eim, residual estimate into resid) and then for keep
+// (Schur vectors into Z, p x p per instance; the truncated H written back in place).
+// ires[4 b] = state (0 skipped, 1 done, -1 Schur form or first reordering failed,
+// -2 reordering for keep failed), ires[4 b + 1] = leading block for nev,
+// ires[4 b + 2] = kept block size.  p <= BSCHUR_MAX_P.
+constexpr int BSCHUR_MAX_P = 96;
+hipError_t launch_bschur(const BInst* tab, int count, int p, int ld, int nev, int keep,
+                         double cut_gap, double* H, double* Z, int* ires, double* resid,
+                         double* ere, double* eim, hipStream_t s);
 constexpr int BATCH_ROWS_PER_BLOCK = 512;  // rows per workgroup of the row-parallel kernels
 
 // Learned initial guess (guess.hip): FP32 MFMA products, loss, Adam, grid transfers.

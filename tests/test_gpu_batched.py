@@ -70,13 +70,19 @@ def _sigma_min(A, theta, iters=12):
     return 1.0 / np.sqrt(s)
 
 
-def test_batched_ks_vs_oracle(ctx):
+@pytest.mark.parametrize("host_dense", [1, 0])
+def test_batched_ks_vs_oracle(ctx, host_dense):
     """Each instance converges (backward error of the partial Schur form <= tol),
     each Ritz value is an eigenvalue of a nearby matrix (sigma_min check), lies
     within kappa(V) * tol * |theta_1| of the closed-form spectrum (Bauer-Fike), and
-    the restart count is close to the oracle's."""
+    the restart count is close to the oracle's -- with the restart's dense work on
+    host threads and on the GPU."""
     descs, v0s, v0 = _batch(CASES)
-    ev, rc, infos = ctx.krylov_schur_batched(descs, v0, NEV, NCV, KEEP, TOL, 200)
+    ctx.set_tuning(binding.TUNE_BATCH_DENSE, host_dense)
+    try:
+        ev, rc, infos = ctx.krylov_schur_batched(descs, v0, NEV, NCV, KEEP, TOL, 200)
+    finally:
+        ctx.set_tuning(binding.TUNE_BATCH_DENSE, 1)
     say("batched rc", rc, [(i["status"], i["restarts"], i["resid"]) for i in infos])
     assert rc == binding.OK
     for b, (g, v, _) in enumerate(CASES):
@@ -138,3 +144,35 @@ def test_batched_single_instance_and_budget(ctx):
     assert rc == binding.NOT_CONVERGED
     assert infos[0]["status"] == binding.NOT_CONVERGED and infos[0]["restarts"] == 1
     assert infos[1]["status"] == binding.OK and infos[1]["restarts"] <= 1
+
+
+def test_batched_dense_work_gpu_matches_host(ctx):
+    """The restart's dense work (Schur form, reordering, residual test, truncated H)
+    on the GPU, one wavefront per instance, against the same algorithms on host
+    threads: both converge, with Ritz values within 2 kappa(V) tol |theta_1| of each
+    other and restart counts as close as between the batched and single-instance
+    paths."""
+    descs, _, v0 = _batch(CASES)
+    ctx.set_tuning(binding.TUNE_BATCH_DENSE, 1)
+    try:
+        eh, rch, ih = ctx.krylov_schur_batched(descs, v0, NEV, NCV, KEEP, TOL, 200)
+    finally:
+        ctx.set_tuning(binding.TUNE_BATCH_DENSE, 0)
+    try:
+        eg, rcg, ig = ctx.krylov_schur_batched(descs, v0, NEV, NCV, KEEP, TOL, 200)
+    finally:
+        ctx.set_tuning(binding.TUNE_BATCH_DENSE, 1)
+    say("host", [(i["status"], i["restarts"]) for i in ih], "gpu",
+        [(i["status"], i["restarts"]) for i in ig])
+    assert rch == rcg == binding.OK
+    for b, (g, v, _) in enumerate(CASES):
+        assert ig[b]["status"] == binding.OK and ig[b]["resid"] <= TOL
+        # the paths round differently (fused multiply-adds on the GPU), which can
+        # move an instance's convergence by a few restarts, as between the batched
+        # and single-instance solvers
+        assert abs(ig[b]["restarts"] - ih[b]["restarts"]) <= max(3, ih[b]["restarts"] // 4)
+        kappa = _eigvec_condition(g, v)
+        if kappa < 1e6:
+            bound = 2.0 * kappa * TOL * abs(eh[b][0]) + 1e-12 * abs(eh[b][0])
+            diff = np.abs(_by_magnitude(eg[b])[:, None] - _by_magnitude(eh[b])[None, :]).min(axis=1)
+            assert np.max(diff) <= bound, (b, diff, bound)
