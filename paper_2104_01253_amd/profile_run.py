@@ -67,6 +67,18 @@ def run(workload: str, reps: int, tuning=None):
             x.zero_()
             rc, _ = ctx.gmres(op, bd, x, restart=50, rtol=1e-8)
             assert rc == 0
+    elif workload == "batched":
+        # the batched Krylov-Schur family (2-D grids n_x in 48..256, basis 60, keep 20,
+        # 10 eigenvalues), 128 instances so that the trace stays small
+        count = 128
+        probs = synth.ks_instances(count, seed=4)
+        descs = [binding.stencil2d(p.grid, p.D, p.vel) for p in probs]
+        import numpy as np
+        v0 = torch.from_numpy(np.concatenate([synth.normal_vector(p.m, 1000 + i)
+                                              for i, p in enumerate(probs)])).cuda()
+        for _ in range(reps):
+            _, rc, _ = ctx.krylov_schur_batched(descs, v0, 10, 60, 20, 1e-8, 300, use_graph=True)
+            assert rc == 0
     else:
         raise SystemExit(f"unknown workload {workload}")
     src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
@@ -90,7 +102,8 @@ def _rows(d, pattern):
 CLASSES = (("fused_qr_kernel", "fused_qr"), ("reduce_kernel", "reduce"), ("update_kernel", "update"),
            ("project_norm_kernel", "project_norm"), ("scale_col_kernel", "scale"),
            ("stencil_kernel", "spmv"), ("csr_kernel", "spmv"), ("tsgemm_kernel", "tsgemm"),
-           ("finish_kernel", "finish"))
+           ("finish_kernel", "finish"), ("bschur_kernel", "dense_schur"),
+           ("btruncate_kernel", "truncate"), ("bscale_kernel", "scale"))
 
 
 def _short(name: str) -> str:
@@ -181,6 +194,8 @@ def main():
     r.add_argument("--reduce-grid", type=int, default=None)
     r.add_argument("--fused-min-j", type=int, default=None)
     r.add_argument("--fused-pair-slots", type=int, default=None)
+    r.add_argument("--batch-dense", type=int, default=None,
+                   help="batched workload: 0 dense restart work on the GPU, 1 on the host")
     s = sub.add_parser("summarize")
     s.add_argument("--fetch", required=True)
     s.add_argument("--write", required=True)
@@ -192,7 +207,8 @@ def main():
         run(a.workload, a.reps, {"TUNE_FUSED_WAVES": a.fused_waves,
                                  "TUNE_REDUCE_GRID": a.reduce_grid,
                                  "TUNE_FUSED_MIN_J": a.fused_min_j,
-                                 "TUNE_FUSED_PAIR_SLOTS": a.fused_pair_slots})
+                                 "TUNE_FUSED_PAIR_SLOTS": a.fused_pair_slots,
+                                 "TUNE_BATCH_DENSE": a.batch_dense})
     else:
         summarize(a.fetch, a.write, a.trace, a.out, a.command)
 
