@@ -23,17 +23,40 @@ namespace {
 
 #include "device_common.h"
 
+// Device memory that no kernel writes while a reader of this view runs (the
+// instance table, the prefix sums, Z during the truncation), seen through the
+// constant address space: loads from it at a wavefront-uniform address become
+// scalar loads.
+template <class T>
+using ConstPtr = const __attribute__((address_space(4))) T*;
+template <class T>
+__device__ __forceinline__ ConstPtr<T> as_const(const T* p) {
+  return (ConstPtr<T>)p;
+}
+
+// Record b of the instance table, read through the constant view (the table is
+// written only by host copies).  Only the device pass compiles the copy out of
+// the constant address space; the host pass never runs this body.
+__device__ __forceinline__ BInst load_inst(const BInst* tab, int b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return as_const(tab)[b];
+#else
+  return tab[b];
+#endif
+}
+
 // Instance owning workgroup `blk` given the prefix sums pre[0..count] (pre[0] = 0);
 // returns the workgroup index within the instance in *local.
-__device__ __forceinline__ int find_instance(const int* __restrict__ pre, int count, int blk,
+__device__ __forceinline__ int find_instance(const int* __restrict__ pre_, int count, int blk,
                                              int* local) {
+  const ConstPtr<int> pre = as_const(pre_);
   int lo = 0, hi = count;                  // invariant: pre[lo] <= blk < pre[hi]
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
     if (pre[mid] <= blk) lo = mid; else hi = mid;
   }
   *local = blk - pre[lo];
-  return lo;
+  return __builtin_amdgcn_readfirstlane(lo);
 }
 
 __device__ __forceinline__ GridRed inst_grid(const BInst& I, int ldp) {
@@ -66,7 +89,7 @@ __global__ __launch_bounds__(BS) void bstencil_kernel(const BInst* __restrict__ 
                                                       int j) {
   int local;
   const int b = find_instance(pre, count, blockIdx.x, &local);
-  const BInst I = tab[b];
+  const BInst I = load_inst(tab, b);
   if (!inst_active(I, j)) return;
   const uint32_t nx = I.nx, ny = I.ny;
 #pragma unroll
@@ -98,7 +121,7 @@ __global__ __launch_bounds__(BS) void breduce_kernel(const BInst* __restrict__ t
                                                      int j, int last, int ldp, int ldc, int ldh) {
   int local;
   const int b = find_instance(pre, count, blockIdx.x, &local);
-  const BInst I = tab[b];
+  const BInst I = load_inst(tab, b);
   if (!inst_active(I, j)) return;
   const int J = j - 2;
   const GridRed g = inst_grid(I, ldp);
@@ -118,7 +141,7 @@ __global__ __launch_bounds__(BS) void bupdate_kernel(const BInst* __restrict__ t
                                                      int j, int ldc) {
   int local;
   const int b = find_instance(pre, count, blockIdx.x, &local);
-  const BInst I = tab[b];
+  const BInst I = load_inst(tab, b);
   if (!inst_active(I, j)) return;
   update_body<2, true, false, double>(I.Q, I.ldq, j - 2, I.w, I.v, nullptr, I.m, I.coef, ldc,
                                       I.ctrl, local);
@@ -131,7 +154,7 @@ __global__ __launch_bounds__(BS) void bproject_norm_kernel(const BInst* __restri
                                                            int ldh) {
   int local;
   const int b = find_instance(pre, count, blockIdx.x, &local);
-  const BInst I = tab[b];
+  const BInst I = load_inst(tab, b);
   if (!inst_active(I, j)) return;
   const int J = j - 2;
   project_norm_body<2, double>(I.Q, I.ldq, J, I.w, I.r, I.m, inst_grid(I, ldp),
@@ -144,7 +167,7 @@ __global__ __launch_bounds__(BS) void bscale_kernel(const BInst* __restrict__ ta
                                                     int j, int ldc) {
   int local;
   const int b = find_instance(pre, count, blockIdx.x, &local);
-  const BInst I = tab[b];
+  const BInst I = load_inst(tab, b);
   if (!inst_active(I, j)) return;
   const double alpha = I.coef[2 * ldc];
   const int J = j - 2;
@@ -157,29 +180,36 @@ __global__ __launch_bounds__(BS) void bscale_kernel(const BInst* __restrict__ ta
 
 // Krylov-Schur truncation for the instances with truncate != 0:
 //   Qn[:, 0..k) = Q[:, 0..p) Z[0..p, 0..k),  Qn[:, k] = Q[:, p],  w = Q[:, p].
-// One row per thread, NO output columns per pass.
+// One row per thread, NO output columns per pass over Q: with NO >= k (the kept
+// block, keep or keep + 1 when a complex pair is not split) Q is read once.
 template <int NO>
 __global__ __launch_bounds__(BS) void btruncate_kernel(const BInst* __restrict__ tab,
                                                        const int* __restrict__ pre, int count,
                                                        int p) {
   int local;
   const int b = find_instance(pre, count, blockIdx.x, &local);
-  const BInst I = tab[b];
+  const BInst I = load_inst(tab, b);
   if (!I.active || !I.truncate) return;
   const int k = I.k;
+  const ConstPtr<double> Z = as_const(I.Z);
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int64_t i = (int64_t)local * 2 * BS + h * BS + threadIdx.x;
     if (i >= I.m) continue;
     for (int o0 = 0; o0 < k; o0 += NO) {
+      // Columns past k read column k-1 of Z (always in bounds) and are not stored:
+      // no branch in the loop, so the loads of several c overlap.
+      ConstPtr<double> zc[NO];
+#pragma unroll
+      for (int o = 0; o < NO; ++o) zc[o] = Z + (int64_t)min(o0 + o, k - 1) * p;
       double acc[NO];
 #pragma unroll
       for (int o = 0; o < NO; ++o) acc[o] = 0.0;
+#pragma unroll 4
       for (int c = 0; c < p; ++c) {
         const double q = I.Q[(int64_t)c * I.ldq + i];
 #pragma unroll
-        for (int o = 0; o < NO; ++o)
-          if (o0 + o < k) acc[o] = fma(q, I.Z[(int64_t)(o0 + o) * p + c], acc[o]);
+        for (int o = 0; o < NO; ++o) acc[o] = fma(q, zc[o][c], acc[o]);
       }
 #pragma unroll
       for (int o = 0; o < NO; ++o)
@@ -196,7 +226,7 @@ __global__ __launch_bounds__(BS) void btruncate_kernel(const BInst* __restrict__
 // last-column finish.
 __global__ __launch_bounds__(FINISH_BS) void bfinish_kernel(const BInst* __restrict__ tab, int j,
                                                             int mode, int ldp, int ldc, int ldh) {
-  const BInst I = tab[blockIdx.x];
+  const BInst I = load_inst(tab, blockIdx.x);
   if (!inst_active(I, j)) return;
   const int J = j - 2;
   const int kind = mode == 1 ? FIN_LAST1
@@ -684,7 +714,7 @@ __global__ __launch_bounds__(SCHUR_THREADS) void bschur_kernel(
     double* __restrict__ resid, double* __restrict__ ere, double* __restrict__ eim) {
   extern __shared__ double sm[];
   const int b = blockIdx.x;
-  const BInst I = tab[b];
+  const BInst I = load_inst(tab, b);
   int* out = ires + 4 * b;
   if (!I.active || I.ctrl->state != ST_RUNNING) {
     if (threadIdx.x == 0) { out[0] = 0; out[1] = 0; out[2] = 0; out[3] = 0; }
@@ -779,7 +809,7 @@ hipError_t launch_bscale(const BInst* tab, const int* pre_rows, int count, int n
 
 hipError_t launch_btruncate(const BInst* tab, const int* pre_rows, int count, int nblocks, int p,
                             hipStream_t s) {
-  btruncate_kernel<8><<<nblocks, BS, 0, s>>>(tab, pre_rows, count, p);
+  btruncate_kernel<24><<<nblocks, BS, 0, s>>>(tab, pre_rows, count, p);
   return hipGetLastError();
 }
 

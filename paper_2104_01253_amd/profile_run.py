@@ -141,7 +141,8 @@ def _calibrated(d, counter):
     return {k: (n, tot / n) for k, (n, tot) in per.items()}, scale
 
 
-def summarize(fetch_dir, write_dir, trace_dir, out, command):
+def summarize(fetch_dir, write_dir, trace_dir, out, command,
+              sources=("kernels.hip", "device_common.h")):
     fetch, fscale = _calibrated(fetch_dir, "FETCH_SIZE")
     write, wscale = _calibrated(write_dir, "WRITE_SIZE")
     stats = {}
@@ -161,9 +162,9 @@ def summarize(fetch_dir, write_dir, trace_dir, out, command):
             kernels[k]["trace_launches"] = stats[k][0]
             kernels[k]["avg_duration_us"] = stats[k][1] / max(stats[k][0], 1) / 1e3
     h = hashlib.sha256()
-    for f in ("kernels.hip", "device_common.h"):
+    for f in sources:
         h.update(open(os.path.join(HERE, "csrc", f), "rb").read())
-    rec = {"kernel_source_sha256_16": h.hexdigest()[:16],
+    rec = {"kernel_source_sha256_16": h.hexdigest()[:16], "kernel_sources": list(sources),
            "calibration": {"copy_bytes": COPY_BYTES, "fetch_scale": fscale, "write_scale": wscale},
            "command": command, "kernels": kernels}
     os.makedirs(os.path.dirname(out) or ".", exist_ok=True)
@@ -202,6 +203,8 @@ def main():
     s.add_argument("--trace", required=True)
     s.add_argument("--out", required=True)
     s.add_argument("--command", default="")
+    s.add_argument("--sources", default="kernels.hip,device_common.h",
+                   help="comma-separated csrc files whose hash keys the record")
     a = ap.parse_args()
     if a.cmd == "run":
         run(a.workload, a.reps, {"TUNE_FUSED_WAVES": a.fused_waves,
@@ -210,7 +213,7 @@ def main():
                                  "TUNE_FUSED_PAIR_SLOTS": a.fused_pair_slots,
                                  "TUNE_BATCH_DENSE": a.batch_dense})
     else:
-        summarize(a.fetch, a.write, a.trace, a.out, a.command)
+        summarize(a.fetch, a.write, a.trace, a.out, a.command, tuple(a.sources.split(",")))
 
 
 if __name__ == "__main__":
