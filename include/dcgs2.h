@@ -138,7 +138,7 @@ int dcgs2_set_qr_schedule(dcgs2_ctx ctx, int one_pass);
  *                           summation order), 0..DCGS2_MAX_N (default 0).
  *  DCGS2_TUNE_BATCH_REDUCE_ROWS : krylov_schur_batched: rows per workgroup of an
  *                           instance's reduction passes (up to 32 workgroups per
- *                           instance), a power of two in 512..65536 (default 8192).
+ *                           instance), a power of two in 512..65536 (default 2048).
  *  DCGS2_TUNE_FUSED_PAIR_SLOTS : one-pass QR kernel: two rows per lane (16-byte
  *                           loads) while the basis needs at most this many column
  *                           slots per wavefront, one row per lane (deeper

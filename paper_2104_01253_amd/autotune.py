@@ -20,6 +20,13 @@ CANDIDATES = {
     binding.TUNE_FUSED_PAIR_SLOTS: (16, 8, 5, 0),
 }
 
+# Knobs of krylov_schur_batched: rows per workgroup of an instance's reduction
+# passes, and where the restart's dense work runs (1 host threads, 0 the GPU).
+BATCHED_CANDIDATES = {
+    binding.TUNE_BATCH_REDUCE_ROWS: (8192, 4096, 2048, 1024),
+    binding.TUNE_BATCH_DENSE: (1, 0),
+}
+
 
 def _time(torch, fn, reps):
     fn()

@@ -45,7 +45,7 @@ struct dcgs2_ctx_s {
   int tune_fused_waves = 8;      // DCGS2_TUNE_FUSED_WAVES
   int tune_reduce_gmax = 0;      // DCGS2_TUNE_REDUCE_GRID (0: automatic)
   int tune_fused_min_j = 0;      // DCGS2_TUNE_FUSED_MIN_J
-  int tune_batch_units = 4096;   // DCGS2_TUNE_BATCH_REDUCE_ROWS / 2
+  int tune_batch_units = 1024;   // DCGS2_TUNE_BATCH_REDUCE_ROWS / 2
   int tune_pair_max_ns = 16;     // DCGS2_TUNE_FUSED_PAIR_SLOTS
   int tune_batch_host_dense = 1; // DCGS2_TUNE_BATCH_DENSE
   int64_t cap_m = 0;

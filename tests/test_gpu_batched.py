@@ -176,3 +176,35 @@ def test_batched_dense_work_gpu_matches_host(ctx):
             bound = 2.0 * kappa * TOL * abs(eh[b][0]) + 1e-12 * abs(eh[b][0])
             diff = np.abs(_by_magnitude(eg[b])[:, None] - _by_magnitude(eh[b])[None, :]).min(axis=1)
             assert np.max(diff) <= bound, (b, diff, bound)
+
+
+def test_batched_every_tuned_reduce_shape(ctx):
+    """Rows per reduction workgroup change only the partial-sum grouping (1 to 32
+    workgroups per instance), so every value the autotuner can choose converges to
+    Ritz values within 2 kappa(V) tol |theta_1| of the default's.  Two instances
+    are large enough (m = 12,288 and 27,150) that their workgroup count changes
+    with the setting, up to the 32-workgroup cap."""
+    from paper_2104_01253_amd import autotune
+    cases = CASES[:2] + [((128, 96), (5.0, 8.0), 16), ((181, 150), (12.0, 2.0), 17)]
+    descs, _, v0 = _batch(cases)
+    key = binding.TUNE_BATCH_REDUCE_ROWS
+    default = ctx.get_tuning(key)
+    ref, rc0, i0 = ctx.krylov_schur_batched(descs, v0, NEV, NCV, KEEP, TOL, 300)
+    assert rc0 == binding.OK
+    try:
+        for rows in autotune.BATCHED_CANDIDATES[key] + (512,):
+            ctx.set_tuning(key, rows)
+            ev, rc, infos = ctx.krylov_schur_batched(descs, v0, NEV, NCV, KEEP, TOL, 300)
+            say("rows", rows, [(i["status"], i["restarts"]) for i in infos])
+            assert rc == binding.OK
+            for b, (g, v, _) in enumerate(cases):
+                assert infos[b]["status"] == binding.OK and infos[b]["resid"] <= TOL
+                assert abs(infos[b]["restarts"] - i0[b]["restarts"]) <= max(3, i0[b]["restarts"] // 4)
+                kappa = _eigvec_condition(g, v)
+                if kappa < 1e6:
+                    bound = 2.0 * kappa * TOL * abs(ref[b][0]) + 1e-12 * abs(ref[b][0])
+                    diff = np.abs(_by_magnitude(ev[b])[:, None]
+                                  - _by_magnitude(ref[b])[None, :]).min(axis=1)
+                    assert np.max(diff) <= bound, (rows, b, diff, bound)
+    finally:
+        ctx.set_tuning(key, default)
