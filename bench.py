@@ -122,6 +122,34 @@ def calibration(torch, nbytes=1_600_000_000):
             "read_gbps": round(nbytes / t_read / 1e9, 1), "bytes": nbytes}
 
 
+def row_block_leg(torch, ctx, binding, B, n, rows=250_000, steps=20):
+    """The same factorisation on the first `rows` rows of B: one GPU's row block when
+    the m = 2,000,000 problem is split eight ways (without the per-step all-reduce
+    such a split adds).  Reports the wall time, the time inside the streaming
+    kernels (HIP events) and the rest: finishing kernels and launch gaps, the fixed
+    per-step costs that grow in weight as the row block shrinks."""
+    Bs = binding.colmajor_from_numpy(np.ascontiguousarray(B[:rows]))
+    Qs = binding.colmajor_empty(rows, n)
+
+    def once():
+        _, rc, _ = ctx.qr(Bs, Qs)
+        assert rc == binding.OK, rc
+    for _ in range(3):
+        once()
+    T = timed(torch, once, steps) / steps
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    once()
+    prof = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    stream_ms = sum(v["total_ms"] for v in prof.values())
+    alg = sum(v["bytes"] for v in prof.values())
+    del Bs, Qs
+    return {"m": rows, "n": n, "ms": round(T * 1e3, 3), "steps_per_s": round(n / T, 1),
+            "hbm_gbps": round(alg / T / 1e9, 1), "streaming_kernels_ms": round(stream_ms, 3),
+            "finish_and_gaps_ms": round(T * 1e3 - stream_ms, 3)}
+
+
 def batched_ks_leg(torch, ctx, binding, synth, count=512):
     """Batched Krylov-Schur: `count` 2-D convection-diffusion operators, n_x ~ U{48..256},
     v ~ U(0,50)^2, 10 largest-magnitude eigenvalues, basis 60, keep 20, tol 1e-8."""
@@ -275,6 +303,8 @@ def main():
         out["qr_fp32_basis"] = {"steps_per_s": round(n / T32, 1), "ms": round(T32 * 1e3, 3)}
         del Q32
         log(f"[bench] cgs2 {out['cgs2_qr']}, mgs {out['mgs_qr']}, fp32 basis {out['qr_fp32_basis']}")
+        out["qr_row_block_250k"] = row_block_leg(torch, ctx, binding, B, n)
+        log(f"[bench] one GPU's row block of an 8-way split {out['qr_row_block_250k']}")
     del Bd, Qd
     torch.cuda.empty_cache()
 
