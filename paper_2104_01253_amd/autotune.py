@@ -7,6 +7,8 @@ caller's own workload and keeps the fastest.  Timing uses HIP events on the
 context's stream through torch.
 
     best = autotune.tune(ctx, lambda: ctx.qr(B, Q))
+    best = autotune.tune(ctx, lambda: ctx.krylov_schur_batched(descs, v0, 10, 60, 20, 1e-8, 300),
+                         reps=1, candidates=autotune.BATCHED_CANDIDATES)
 """
 from __future__ import annotations
 
