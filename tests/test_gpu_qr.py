@@ -137,6 +137,27 @@ def test_qr_full_size_kappa_1e8(ctx, full_size):
     assert loo <= 1e-13
 
 
+def test_qr_full_size_kappa_1e2(ctx):
+    """Full size on the well-conditioned matrix (singular values logspace(0, -2)):
+    against the oracle, with the orthogonality DCGS2 reaches there (the oracle's
+    own loss of orthogonality on this matrix is 1.9e-14, its representation error
+    3.1e-16)."""
+    m, n = 2_000_000, 100
+    say("generating B 2e6 x 100, kappa ~ 1e2")
+    B = synth.tall_skinny(m, n, 2.0)
+    say("oracle qr")
+    ref = gs.dcgs2_qr(B)
+    say("gpu qr")
+    Q, R, rc, st = run_qr(ctx, B)
+    assert rc == 0 and st["reductions"] == n + 1
+    assert relnorm(R, ref["R"]) <= TOL
+    dq = np.linalg.norm((Q - ref["Q"]) @ ref["R"]) / np.linalg.norm(B)
+    loo = loss_of_orthogonality(Q)
+    rre = np.linalg.norm(B - Q @ R) / np.linalg.norm(B)
+    say("dQ R", dq, "loo", loo, "rre", rre)
+    assert dq <= TOL and loo <= 1e-13 and rre <= 1e-15
+
+
 def test_qr_full_size_every_tuned_shape(ctx, full_size):
     """Full size under every launch-shape combination the autotuner can choose, so
     the configuration the benchmark times is among those checked."""
