@@ -89,6 +89,18 @@ def roofline(prof, wall_s=None):
     }
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (Linux), for the CPU baseline's context."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(B, n):
     """The FP64 oracle (oracle.gram_schmidt.dcgs2_qr, unmodified) on the first rows of B."""
     from oracle import gram_schmidt as gs
@@ -102,7 +114,7 @@ def cpu_baseline(B, n):
     gs.dcgs2_qr(B)
     dt = time.perf_counter() - t0
     return {"value": round(n / dt, 3), "unit": "steps/s", "cores": int(cores),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"one full factorization of the same B ({m} x {n}) by "
                       f"oracle.gram_schmidt.dcgs2_qr (NumPy/BLAS fp64), {dt:.2f} s"}
 
