@@ -349,8 +349,18 @@ def main():
         t0 = time.perf_counter()
         rc, info = gm_once()
         tg = time.perf_counter() - t0
+        # algorithmic bytes of the same solve's expansion kernels (the per-cycle solution
+        # update and residual, about 2 % more, are not counted), over the unprofiled
+        # wall time
+        ctx.profile(True)
+        ctx.profile_read(reset=True)
+        gm_once()
+        gbytes = sum(v["bytes"] for v in ctx.profile_read(reset=True).values())
+        ctx.profile(False)
         out["gmres50_128cube_fp64"] = {"time_to_1e-8_s": round(tg, 4), "iters": info["iters"],
                                        "cycles": info["cycles"], "relres_true": info["relres_true"],
+                                       "expansion_gbps": round(gbytes / tg / 1e9, 1),
+                                       "expansion_gb_per_iter": round(gbytes / max(info["iters"], 1) / 1e9, 3),
                                        "status": rc}
         ctx.set_basis_precision(32)
         gm_once()
