@@ -66,7 +66,7 @@ __global__ __launch_bounds__(BS) void update_kernel(TQ* __restrict__ Q, int64_t 
 // of slots in use is a template parameter, so the tile's loads of a wavefront are
 // unconditional (slots past the basis read a valid column and discard it) and are
 // all in flight together.  The wavefronts form partial Q C and Q T from their
-// slots, wavefront 0 combines them in a fixed order and publishes q, w', a_{j+1}
+// slots, wavefronts 0..VR-1 combine them in a fixed order and publish q, w', a_{j+1}
 // of the tile through LDS, and every lane then accumulates its rows' products
 // for its slots in registers across all tiles; one transposed butterfly per
 // wavefront at the end yields the workgroup partials.
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
   // the compiler wait for every outstanding load (the whole prefetch) once per tile.
   struct Stage {
     RawVec<VR, TQ> q[NS];
-    RV x0, x1, x2;                        // w, a_j, a_{j+1} (used by wavefront 0)
+    RV x0, x1, x2;                        // w, a_j, a_{j+1} (used by wavefronts 0..VR-1)
   };
   Stage ring[PD + 1];
   auto issue = [&](int64_t t, Stage& S) __attribute__((always_inline)) {
@@ -172,12 +172,12 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
     const uint32_t off = (uint32_t)ul * (uint32_t)(VR * sizeof(TQ));
     // Every wavefront issues the same loads, so that all of them have the same
     // number in flight and the waits for a stage are exact.  Loads whose values are
-    // not used (slots past the basis, the vectors outside wavefront 0) read the
+    // not used (slots past the basis, the vectors outside wavefronts 0..VR-1) read the
     // first element of their array in every lane: one cache line, not a tile.
 #pragma unroll
     for (int sl = 0; sl < NS; ++sl)
       S.q[sl] = load_raw<VR>(colp[sl], wv + FW * sl < J ? off : 0u);
-    const uint32_t offv = wv == 0 ? (uint32_t)ul * (uint32_t)(VR * sizeof(double)) : 0u;
+    const uint32_t offv = wv < VR ? (uint32_t)ul * (uint32_t)(VR * sizeof(double)) : 0u;
     S.x0 = RV::load_off32(w, offv);
     S.x1 = RV::load_off32(a_cur, offv);
     if (!LAST) S.x2 = RV::load_off32(a_next, offv);
@@ -205,30 +205,32 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
       part[((e * 2 + 1) * FW + wv) * 64 + lane] = st[e];
     }
     lds_barrier();
-    if (wv == 0) {
-      RV qo = RV::zero(), wo = RV::zero(), ao = RV::zero();
+    if (wv < VR) {
+      // wavefront e combines row element e of every lane's VR rows (for VR = 2 the
+      // two halves of the tile at the same time), summing the wavefronts' partials
+      // in wavefront order
+      const int e = wv;
+      const int r = e * 64 + lane;
+      double SC = part[((e * 2) * FW) * 64 + lane], ST = part[((e * 2 + 1) * FW) * 64 + lane];
 #pragma unroll
-      for (int e = 0; e < VR; ++e) {
-        const int r = e * 64 + lane;
-        double SC = part[((e * 2) * FW) * 64 + lane], ST = part[((e * 2 + 1) * FW) * 64 + lane];
-#pragma unroll
-        for (int v = 1; v < FW; ++v) {
-          SC += part[((e * 2) * FW + v) * 64 + lane];
-          ST += part[((e * 2 + 1) * FW + v) * 64 + lane];
-        }
-        if (live) {
-          qo.e[e] = stored<TQ>((S.x0.e[e] - SC) / alpha);
-          wo.e[e] = S.x1.e[e] - fma(qo.e[e], tJ, ST);
-          ao.e[e] = S.x2.e[e];
-        }
-        vq[r] = qo.e[e];
-        vw[r] = wo.e[e];
-        va[r] = ao.e[e];
+      for (int v = 1; v < FW; ++v) {
+        SC += part[((e * 2) * FW + v) * 64 + lane];
+        ST += part[((e * 2 + 1) * FW + v) * 64 + lane];
       }
+      const double x0 = e == 0 ? S.x0.e[0] : S.x0.e[VR - 1];
+      const double x1 = e == 0 ? S.x1.e[0] : S.x1.e[VR - 1];
+      const double x2 = e == 0 ? S.x2.e[0] : S.x2.e[VR - 1];
+      double qo = 0.0, wo = 0.0, ao = 0.0;
       if (live) {
-        qo.store(Q + (int64_t)J * ldq, u);
-        wo.store(w, u);
+        qo = stored<TQ>((x0 - SC) / alpha);
+        wo = x1 - fma(qo, tJ, ST);
+        ao = x2;
+        Q[(int64_t)J * ldq + u * VR + e] = (TQ)qo;
+        w[u * VR + e] = wo;
       }
+      vq[r] = qo;
+      vw[r] = wo;
+      va[r] = ao;
     }
     lds_barrier();
     RV qq, ww, aa;

@@ -7,9 +7,11 @@
 `run` executes the named workload `reps` times plus one plain device copy of
 `COPY_BYTES` bytes (torch's copy kernel) that calibrates the FETCH_SIZE /
 WRITE_SIZE counters.  `summarize` reads rocprofv3's CSV output (counter
-collection and kernel stats) and writes a short text summary and
-profiles/traffic.json (per-kernel HBM bytes per launch, calibrated, keyed by a
-hash of kernels.hip so a stale measurement is not reused).
+collection and kernel stats) and writes <out>.md, a short text summary, and
+<out>.json, the per-kernel HBM bytes per launch (calibrated), keyed by a hash of
+the kernel sources so that a stale measurement is not reused.  bench.py reads
+the QR workload's record from profiles/traffic.json, a copy of that summary's
+JSON.
 """
 from __future__ import annotations
 
