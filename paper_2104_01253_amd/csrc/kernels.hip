@@ -138,12 +138,17 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
   double* vq = part + FW * TR * 2;        // q, w', a_{j+1} of the tile rows: [e 64 + lane]
   double* vw = vq + TR;
   double* va = vw + TR;
+  // With 12 two-row FP64 slots per wavefront (not the last column) the per-slot
+  // coefficients do not fit in registers beside the ring: they are kept in LDS as
+  // (c_k, t_k) pairs and read per tile (one broadcast address per wavefront).
+  constexpr bool CL = VR == 2 && NS > 11 && !LAST && sizeof(TQ) == 8;
+  double* cts = va + TR;                  // 2 FMAXCOL: (c_k, t_k), zero for k >= J
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // per-slot column pointers and coefficients (uniform per wavefront; the
   // coefficients are read once the first tiles' loads are in flight)
   const TQ* colp[NS];
-  double alpha = 0.0, tJ = 0.0, cs[NS], ts[NS];
+  double alpha = 0.0, tJ = 0.0, cs[CL ? 1 : NS], ts[CL ? 1 : NS];
 #pragma unroll
   for (int sl = 0; sl < NS; ++sl) {
     const int k = wv + FW * sl;
@@ -191,11 +196,19 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
 #pragma unroll
     for (int sl = 0; sl < NS; ++sl) {
       if (wv + FW * sl < J) {             // uniform: a discarded slot may hold anything
+        double c, t;
+        if constexpr (CL) {
+          c = cts[2 * (wv + FW * sl)];
+          t = cts[2 * (wv + FW * sl) + 1];
+        } else {
+          c = cs[sl];
+          t = ts[sl];
+        }
 #pragma unroll
         for (int e = 0; e < VR; ++e) {
           const double qx = (double)S.q[sl].e[e];
-          sc[e] = fma(qx, cs[sl], sc[e]);
-          st[e] = fma(qx, ts[sl], st[e]);
+          sc[e] = fma(qx, c, sc[e]);
+          st[e] = fma(qx, t, st[e]);
         }
       }
     }
@@ -272,13 +285,23 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
   if (fin.ctrl->state != ST_RUNNING) return;
   alpha = coef[2 * ldc];
   tJ = coef[ldc + J];
+  if constexpr (CL) {
+    for (int k = threadIdx.x; k < FW * NS; k += FW * 64) {
+      const int kc = k < J ? k : 0;
+      const double c = coef[kc], t = coef[ldc + kc];
+      cts[2 * k] = k < J ? c : 0.0;
+      cts[2 * k + 1] = k < J ? t : 0.0;
+    }
+    lds_barrier();
+  } else {
 #pragma unroll
-  for (int sl = 0; sl < NS; ++sl) {       // unconditional loads (clamped index): one wait
-    const int k = wv + FW * sl;
-    const int kc = k < J ? k : 0;
-    const double c = coef[kc], t = coef[ldc + kc];
-    cs[sl] = k < J ? c : 0.0;
-    ts[sl] = k < J ? t : 0.0;
+    for (int sl = 0; sl < NS; ++sl) {     // unconditional loads (clamped index): one wait
+      const int k = wv + FW * sl;
+      const int kc = k < J ? k : 0;
+      const double c = coef[kc], t = coef[ldc + kc];
+      cs[sl] = k < J ? c : 0.0;
+      ts[sl] = k < J ? t : 0.0;
+    }
   }
   while (tix + (int64_t)PD * gr.G < ntiles) {
     static_for(std::make_integer_sequence<int, PD + 1>{}, [&](auto R) __attribute__((always_inline)) {
@@ -609,7 +632,7 @@ hipError_t launch_update(void* Q, int q32, int64_t ldq, int J, double* x, const 
 }
 
 size_t fused_qr_smem(int fw, int vr) {
-  return sizeof(double) * ((size_t)fw * 128 * vr + 3 * 64 * vr);
+  return sizeof(double) * ((size_t)fw * 128 * vr + 3 * 64 * vr + 2 * FMAXCOL);
 }
 
 // Multiprocessors of the current device (cached).
@@ -639,7 +662,7 @@ struct RingLimits {
 template <typename T, bool L, int F, int VR>
 constexpr RingLimits ring_limits() {
   if constexpr (F == 16) return RingLimits{0, 0, 0, 5};
-  if constexpr (sizeof(T) == 8 && VR == 2) return L ? RingLimits{2, 3, 7, 13} : RingLimits{2, 3, 5, 11};
+  if constexpr (sizeof(T) == 8 && VR == 2) return L ? RingLimits{2, 3, 7, 13} : RingLimits{2, 3, 5, 12};
   if constexpr (sizeof(T) == 8) return L ? RingLimits{8, 11, 15, 16} : RingLimits{6, 8, 12, 16};
   if constexpr (VR == 2) return L ? RingLimits{4, 5, 8, 14} : RingLimits{2, 4, 6, 11};
   return L ? RingLimits{10, 12, 16, 16} : RingLimits{8, 10, 13, 16};
