@@ -138,10 +138,10 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
   double* vq = part + FW * TR * 2;        // q, w', a_{j+1} of the tile rows: [e 64 + lane]
   double* vw = vq + TR;
   double* va = vw + TR;
-  // With 12 two-row FP64 slots per wavefront (not the last column) the per-slot
+  // With more than 11 two-row slots per wavefront (not the last column) the per-slot
   // coefficients do not fit in registers beside the ring: they are kept in LDS as
   // (c_k, t_k) pairs and read per tile (one broadcast address per wavefront).
-  constexpr bool CL = VR == 2 && NS > 11 && !LAST && sizeof(TQ) == 8;
+  constexpr bool CL = VR == 2 && NS > 11 && !LAST;
   double* cts = va + TR;                  // 2 FMAXCOL: (c_k, t_k), zero for k >= J
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -664,7 +664,7 @@ constexpr RingLimits ring_limits() {
   if constexpr (F == 16) return RingLimits{0, 0, 0, 5};
   if constexpr (sizeof(T) == 8 && VR == 2) return L ? RingLimits{2, 3, 7, 13} : RingLimits{2, 3, 5, 12};
   if constexpr (sizeof(T) == 8) return L ? RingLimits{8, 11, 15, 16} : RingLimits{6, 8, 12, 16};
-  if constexpr (VR == 2) return L ? RingLimits{4, 5, 8, 14} : RingLimits{2, 4, 6, 11};
+  if constexpr (VR == 2) return L ? RingLimits{4, 5, 8, 14} : RingLimits{2, 4, 6, 13};
   return L ? RingLimits{10, 12, 16, 16} : RingLimits{8, 10, 13, 16};
 }
 template <typename T, bool L, int F, int VR, int NS>

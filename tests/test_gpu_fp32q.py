@@ -31,7 +31,9 @@ def ctx():
 
 
 @pytest.mark.parametrize("one_pass", [True, False])
-@pytest.mark.parametrize("m,n,ce", [(1023, 3, 2), (20011, 64, 8), (300001, 100, 8)])
+# odd m: one-row slots throughout; m = 300,000 (even, aligned columns): two-row slots
+@pytest.mark.parametrize("m,n,ce", [(1023, 3, 2), (20011, 64, 8), (300001, 100, 8),
+                                    (300000, 100, 8)])
 def test_qr_q32_parity(ctx, m, n, ce, one_pass):
     torch = torch_cuda()
     B = synth.tall_skinny(m, n, ce, seed_g=200 + m, seed_v=9)
