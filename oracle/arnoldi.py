@@ -210,7 +210,9 @@ class DCGS2Arnoldi:
         self.rho_next = np.sqrt(gamma) / alpha
         if self.trace is not None:
             self.trace.append(dict(j=j, C=C.copy(), beta=beta, S=S.copy(), sigma=sigma,
-                                   alpha=alpha, T=T.copy(), w=self.w.copy()))
+                                   gamma=gamma, alpha=alpha, T=T.copy(), w=self.w.copy(),
+                                   rho_next=self.rho_next, fallback=not (np.isfinite(d) and
+                                                                          d > self.tau * beta)))
         self.j += 1
         return self.status
 

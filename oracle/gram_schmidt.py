@@ -81,19 +81,66 @@ def _f64(x):
     return np.asarray(x, dtype=np.float64)
 
 
-def dcgs2_qr(B, tau=1e-8, eta=1e-12, qdtype=np.float64):
-    """Delayed CGS2 QR, Alg. qr, with the last column finished by CGS2 (end of Sec. 3).
+def dcgs2_qr_step(Q, J, w, a, S_prev, rho, tau=1e-8, eta=1e-12):
+    """Step j = J + 2 of Alg. qr from a given state (test infrastructure only).
 
-    Step j (paper's 1-based j = 2..n) finalises q_{j-1} and forms w_j with ONE
-    reduction [Q_{1:j-2}, w_{j-1}]^T [w_{j-1}, a_j]:
-      C = Q^T w_{j-1}, beta = w^T w, S = Q^T a_j, sigma = w^T a_j  (and a_j^T a_j,
-      kept only as the breakdown scale of the next step),
+    State: the final columns q_1..q_J in Q[:, :J] (stored values; q_{J+1} is written
+    into Q[:, J]), w = w_{j-1}, a = a_j, S_prev = S_{1:J, j-1}, rho = ||a_{j-1}||
+    (None at j = 2, where the breakdown scale is ||w_1|| = ||a_1||).  The one global
+    reduction of the step is [Q_{1:j-2}, w_{j-1}]^T [w_{j-1}, a_j]:
+      C = Q^T w, beta = w^T w, S = Q^T a, sigma = w^T a  (and gamma = a^T a, the
+      breakdown scale of the next step),
       alpha = sqrt(beta - C^T C)                   (Pythagorean trick, Sec. 3)
       q_{j-1} = (w_{j-1} - Q C) / alpha           (delayed reorthogonalisation)
       S_{j-1,j} = (sigma - C^T S) / alpha         (Stephen's trick, Sec. 3)
       w_j = a_j - Q_{1:j-1} S_{1:j-1,j}
       R_{1:j-2,j-1} = S_{1:j-2,j-1} + C,  R_{j-1,j-1} = alpha.
-    Last column: c = Q^T w_n; u = w_n - Q c; alpha = ||u||; two reductions.
+    Returns dict(status, C, beta, S, sigma, gamma, alpha, fallback, s_full, w, rcol);
+    on OK q_{j-1} is in Q[:, J].
+    """
+    Qk = _f64(Q[:, :J])
+    C = Qk.T @ w
+    beta = w @ w
+    S = Qk.T @ a
+    sigma = w @ a
+    gamma = a @ a
+    out = dict(status=OK, C=C, beta=beta, S=S, sigma=sigma, gamma=gamma, alpha=None,
+               fallback=False, s_full=None, w=None, rcol=None)
+    if not (np.all(np.isfinite(C)) and np.all(np.isfinite(S))
+            and np.isfinite(beta) and np.isfinite(sigma) and np.isfinite(gamma)):
+        out["status"] = NONFINITE
+        return out
+    if rho is None:
+        rho = np.sqrt(beta)                 # j = 2: ||a_1||
+    # --- delayed normalisation (Pythagorean trick) with the explicit fallback
+    d = beta - C @ C
+    if np.isfinite(d) and d > tau * beta:
+        alpha = np.sqrt(d)
+    else:
+        alpha = np.linalg.norm(w - Qk @ C)
+        out["fallback"] = True
+    out["alpha"] = alpha
+    if not np.isfinite(alpha):
+        out["status"] = NONFINITE
+        return out
+    out["rcol"] = np.concatenate([S_prev + C, [alpha]])
+    if alpha <= eta * rho:
+        out["status"] = BREAKDOWN
+        return out
+    # --- delayed reorthogonalisation of column j-1
+    Q[:, J] = (w - Qk @ C) / alpha
+    # --- projection of a_j, with Stephen's trick for q_{j-1}^T a_j
+    s_last = (sigma - C @ S) / alpha
+    out["s_full"] = np.concatenate([S, [s_last]])
+    out["w"] = a - _f64(Q[:, :J + 1]) @ out["s_full"]
+    return out
+
+
+def dcgs2_qr(B, tau=1e-8, eta=1e-12, qdtype=np.float64):
+    """Delayed CGS2 QR, Alg. qr, with the last column finished by CGS2 (end of Sec. 3).
+
+    Steps j = 2..n follow ``dcgs2_qr_step`` (one reduction each); the last column
+    is finished by CGS2: c = Q^T w_n; u = w_n - Q c; alpha = ||u||; two reductions.
 
     Readings where the paper is silent (both sides implement the same):
     * Pythagorean guard: if not (beta - C^T C > tau*beta), or it is not finite,
@@ -123,44 +170,17 @@ def dcgs2_qr(B, tau=1e-8, eta=1e-12, qdtype=np.float64):
 
     for j in range(2, n + 1):
         J = j - 2                           # columns q_1..q_{j-2} are final
-        a = B[:, j - 1]                     # a_j
-        Qk = _f64(Q[:, :J])
-        # --- the one global reduction of step j
-        C = Qk.T @ w
-        beta = w @ w
-        S = Qk.T @ a
-        sigma = w @ a
-        gamma = a @ a
-        red += 1
-        if not (np.all(np.isfinite(C)) and np.all(np.isfinite(S))
-                and np.isfinite(beta) and np.isfinite(sigma) and np.isfinite(gamma)):
-            return result(NONFINITE, J)
-        rho = np.sqrt(beta) if j == 2 else np.sqrt(gamma_prev)   # ||a_{j-1}||
-        # --- delayed normalisation (Pythagorean trick) with the explicit fallback
-        d = beta - C @ C
-        if np.isfinite(d) and d > tau * beta:
-            alpha = np.sqrt(d)
-        else:
-            alpha = np.linalg.norm(w - Qk @ C)
-            red += 1
-            fallbacks += 1
-        if not np.isfinite(alpha):
-            return result(NONFINITE, J)
-        if alpha <= eta * rho:
-            R[:J, J] = S_prev + C
-            R[J, J] = alpha
-            return result(BREAKDOWN, J)
-        # --- delayed reorthogonalisation of column j-1
-        Q[:, J] = (w - Qk @ C) / alpha
-        # --- projection of a_j, with Stephen's trick for q_{j-1}^T a_j
-        s_last = (sigma - C @ S) / alpha
-        S_full = np.concatenate([S, [s_last]])
-        w = a - _f64(Q[:, :J + 1]) @ S_full
-        # --- representation R_{:, j-1}
-        R[:J, J] = S_prev + C
-        R[J, J] = alpha
-        S_prev = S_full
-        gamma_prev = gamma
+        rho = None if j == 2 else np.sqrt(gamma_prev)
+        o = dcgs2_qr_step(Q, J, w, B[:, j - 1], S_prev, rho, tau, eta)
+        red += 2 if o["fallback"] else 1
+        fallbacks += 1 if o["fallback"] else 0
+        if o["rcol"] is not None:
+            R[:J + 1, J] = o["rcol"]
+        if o["status"] != OK:
+            return result(o["status"], J)
+        w = o["w"]
+        S_prev = o["s_full"]
+        gamma_prev = o["gamma"]
 
     # --- last column: CGS2 finish, two reductions (end of Sec. 3)
     J = n - 1

@@ -186,3 +186,95 @@ def test_krylov_schur_continuation_keeps_arnoldi_relation():
     assert representation_error(A, b.Q, b.H, p) <= 1e-14
     assert loss_of_orthogonality(b.Q) <= 1e-13
     assert b.matvecs == p - k
+
+
+def test_mgs_arnoldi_tiny_against_50_digit():
+    """MGS Arnoldi (Sec. 2) against the exact decomposition by 50-digit Gram-Schmidt:
+    a wrong index, sign or dropped projection in H or Q fails it."""
+    A = synth.rng(23).standard_normal((10, 10)) + 3 * np.eye(10)
+    r0 = synth.normal_vector(10, 24)
+    n = 7
+    Qx, Hx = _brute.arnoldi_exact(A, r0, n)
+    Qm, Hm, red = ar.mgs_arnoldi(lambda x: A @ x, r0, n)
+    assert np.max(np.abs(Hm - Hx)) / np.max(np.abs(Hx)) <= 1e-13
+    assert np.max(np.abs(Qm - Qx)) <= 1e-12
+    assert red == 1 + n * (n + 1) // 2 + n      # j projections + one norm at step j
+
+
+def test_mgs_arnoldi_relation_and_structure_config1():
+    """MGS Arnoldi on the 2-D 32x32 workload: the Arnoldi relation to O(eps) (it holds
+    for MGS whatever its orthogonality, Sec. 6.1), H upper Hessenberg with a positive
+    subdiagonal, and H equal to the CGS2 Hessenberg matrix to O(eps kappa)."""
+    prob, r0, n = synth.arnoldi_cd2d_32()
+    A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
+    mv = lambda x: A @ x
+    Qm, Hm, _ = ar.mgs_arnoldi(mv, r0, n)
+    Q2, H2, _ = ar.cgs2_arnoldi(mv, r0, n)
+    assert representation_error(A, Qm, Hm, n) <= 1e-15
+    assert np.all(np.tril(Hm, -2) == 0.0)
+    assert np.all(np.diag(Hm, -1) > 0.0)
+    assert np.allclose(Qm[:, 0], r0 / np.linalg.norm(r0), rtol=0, atol=1e-15)
+    colnorm = np.linalg.norm(H2, axis=0)
+    assert np.max(np.abs(Hm - H2) / colnorm[None, :]) <= 1e-9
+    # loss of orthogonality at the MGS rate O(eps) kappa, far above CGS2's O(eps)
+    assert 1e-13 < loss_of_orthogonality(Qm) < 1e-8
+
+
+def test_varcoef_constant_diffusion_is_the_kronecker_operator():
+    """xi = 0 gives D = 1: the flux-form assembly must equal the Kronecker-sum
+    convection-diffusion operator built independently (same grid, h and velocity)."""
+    from oracle.operators import varcoef_matrix
+    for n, vel in [(9, (10.0, 10.0)), (16, (3.0, -7.0))]:
+        p = synth.VarCoefProblem(n, (0.0,) * len(synth.KL_MODES), ((0.5, 0.5, 0.1, 1.0),) * 4,
+                                 vel)
+        A = varcoef_matrix(p)
+        B = ops.convection_diffusion((n, n), 1.0, vel)
+        assert abs(A - B).max() <= 1e-12 * abs(B).max()
+
+
+def test_varcoef_symmetric_without_convection():
+    """With v = 0 the face-centred diffusion stencil is symmetric for any D(x, y)."""
+    from oracle.operators import varcoef_matrix
+    p = synth.varcoef_instances(1, n=14, seed=9, vel=(0.0, 0.0))[0]
+    A = varcoef_matrix(p)
+    assert abs(A - A.T).max() <= 1e-13 * abs(A).max()
+    d = A.diagonal()
+    off = np.asarray(abs(A).sum(axis=1)).ravel() - np.abs(d)
+    assert np.all(d >= off * (1 - 1e-14))         # weakly diagonally dominant (M-matrix)
+
+
+def test_varcoef_second_order_manufactured_solution():
+    """The assembly approximates -div(D grad u) + v.grad u to second order: with
+    u = sin(pi x) sin(pi y) (zero on the boundary) the error of A u against the
+    analytic operator at the grid points falls by about 4 when h halves.  A misplaced
+    face, a swapped axis or a wrong sign leaves an O(1) error instead."""
+    from oracle.operators import varcoef_matrix
+    xi = synth.rng(31).standard_normal(len(synth.KL_MODES))
+    vel = (10.0, -4.0)
+    errs = []
+    for n in (15, 31, 63):
+        p = synth.VarCoefProblem(n, tuple(float(v) for v in xi), ((0.5, 0.5, 0.1, 1.0),) * 4,
+                                 vel)
+        h = 1.0 / (n + 1)
+        t = np.arange(1, n + 1) * h
+        X, Y = np.meshgrid(t, t, indexing="xy")       # x fastest
+        X, Y = X.ravel(), Y.ravel()
+        pi = np.pi
+        s = np.zeros_like(X)
+        sx = np.zeros_like(X)
+        sy = np.zeros_like(X)
+        for (pp, qq), z in zip(synth.KL_MODES, xi):
+            a = z / (pp * pp + qq * qq) * 2.0
+            s += a * np.sin(pp * pi * X) * np.sin(qq * pi * Y)
+            sx += a * pp * pi * np.cos(pp * pi * X) * np.sin(qq * pi * Y)
+            sy += a * qq * pi * np.sin(pp * pi * X) * np.cos(qq * pi * Y)
+        D = np.exp(s)
+        u = np.sin(pi * X) * np.sin(pi * Y)
+        ux = pi * np.cos(pi * X) * np.sin(pi * Y)
+        uy = pi * np.sin(pi * X) * np.cos(pi * Y)
+        lap = -2.0 * pi * pi * u
+        exact = -(D * sx * ux + D * sy * uy + D * lap) + vel[0] * ux + vel[1] * uy
+        Au = varcoef_matrix(p) @ u
+        errs.append(np.max(np.abs(Au - exact)) / np.max(np.abs(exact)))
+    assert errs[0] < 0.05
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5, errs
