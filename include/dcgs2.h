@@ -195,6 +195,55 @@ int dcgs2_qr_q32(dcgs2_ctx ctx, int64_t m, int32_t n, const double* B, int64_t l
 int dcgs2_arnoldi_q32(dcgs2_ctx ctx, const dcgs2_op* A, const double* r0, int32_t n,
                       float* Q, int64_t ldq, double* H_host, int32_t ldh, dcgs2_stats* st);
 
+/* Steps j0..j1 of Alg. arnoldi (Sec. 4) from a caller-given state, for checking
+ * the expansion one step at a time and for resuming it.  Step j is the matvec
+ * v = A w_{j-1}, the one global reduction [Q_{1:j-2}, w_{j-1}]^T [w_{j-1}, v], the
+ * scalar finalisation (Pythagorean alpha_{j-1}, T, the Hessenberg column j-2
+ * completed from K, then the new K column j-1) and the update that writes q_{j-1}
+ * and w_j, with the explicit-norm fallback of dcgs2_set_tolerances.  The
+ * last-column finish of dcgs2_arnoldi is not run.
+ *  j0, j1  : 2 <= j0 <= j1 <= min(m, DCGS2_MAX_N + 1).
+ *  Q       : device, m x (j1-1), ldq >= m; columns 1..j0-2 (1-based) are the
+ *            state's basis and are read; columns j0-1..j1-1 are written.
+ *  w       : device, m; in: w_{j0-1}, out: w_{j1} (valid when the return is OK).
+ *  H_host, K_host : host, ldh x (j1-1) each, ldh >= j1; in: H columns 1..j0-3
+ *            final and K column j0-2 partial (as dcgs2_arnoldi holds them after
+ *            step j0-1); out: H columns through j1-2 and K column j1-1.  Entries
+ *            outside the rows and columns a step writes come back unchanged.
+ *  rho     : breakdown scale of w_{j0-1} (sqrt(gamma_{j0-1}) / alpha_{j0-2}); not
+ *            used when j0 = 2 (the scale is then ||w_1||); finite, >= 0.
+ *  rec_host: host, optional (NULL), (j1-j0+1) records of 3 j1 + 1 doubles, record
+ *            r for step j = j0 + r: the 2j reduced values [Q^T w, w^T w, v^T w,
+ *            Q^T v, w^T v, v^T v], then T_{1:j-1}, alpha_{j-1} and the breakdown
+ *            scale of w_j; the rest of a record, and the records of steps that
+ *            did not run, are NaN.
+ * Returns as dcgs2_arnoldi (st->breakdown_step is the number of final H columns). */
+int dcgs2_arnoldi_steps(dcgs2_ctx ctx, const dcgs2_op* A, int32_t j0, int32_t j1, double* Q,
+                        int64_t ldq, double* w, double* H_host, double* K_host, int32_t ldh,
+                        double rho, double* rec_host, dcgs2_stats* st);
+
+/* Steps j0..j1 of Alg. qr (Sec. 3) from a caller-given state, under the context's
+ * pass schedule (dcgs2_set_qr_schedule: with the one-pass schedule the update of
+ * step j and the reduction of step j+1 share one pass for j0 <= j < j1).  Step j is
+ * the reduction [Q_{1:j-2}, w_{j-1}]^T [w_{j-1}, a_j], alpha_{j-1}, Stephen's trick
+ * for S_{j-1,j}, R column j-1, and the update that writes q_{j-1} and
+ * w_j = a_j - Q_{1:j-1} S_{1:j-1,j}.  The last-column finish is not run.
+ *  m, j0, j1 : 2 <= j0 <= j1 <= min(m, DCGS2_MAX_N).
+ *  B       : device, m x j1, ldb >= m; columns a_{j0}..a_{j1} are read.
+ *  Q       : device, m x (j1-1), ldq >= m; columns 1..j0-2 read, j0-1..j1-1 written.
+ *  w       : device, m; in: w_{j0-1}, out: w_{j1} (valid when the return is OK).
+ *  R_host  : host, ldr x (j1-1), ldr >= j1-1; columns j0-1..j1-1 (1-based) are
+ *            written, the others are left alone.
+ *  S_host  : host, j1-1 doubles; in: S_{1:j0-2, j0-1} (the first j0-2 entries),
+ *            out: S_{1:j1-1, j1}.
+ *  rho     : ||a_{j0-1}||, the breakdown scale of step j0 (not used when j0 = 2).
+ *  rec_host: optional, records as dcgs2_arnoldi_steps with the S column of step j
+ *            (S_{1:j-1,j}) in place of T and ||a_j|| as the next scale.
+ * Returns as dcgs2_qr. */
+int dcgs2_qr_steps(dcgs2_ctx ctx, int64_t m, int32_t j0, int32_t j1, const double* B, int64_t ldb,
+                   double* Q, int64_t ldq, double* w, double* R_host, int32_t ldr,
+                   double* S_host, double rho, double* rec_host, dcgs2_stats* st);
+
 /* Comparator: classical Gram-Schmidt with reorthogonalisation, Alg. cgs2 (Sec. 3):
  * per column S = Q^T a_j, w = a_j - Q S, C = Q^T w, u = w - Q C, alpha = ||u||,
  * q_j = u/alpha, R_{1:j-1,j} = S + C -- three global reductions and four passes

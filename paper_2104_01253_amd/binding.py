@@ -30,7 +30,7 @@ EXPORTS = ("dcgs2_create", "dcgs2_destroy", "dcgs2_set_tolerances", "dcgs2_qr", 
            "dcgs2_mlp_set_params", "dcgs2_mlp_get_params", "dcgs2_mlp_get_grads",
            "dcgs2_mlp_forward", "dcgs2_mlp_loss_grad", "dcgs2_mlp_adam",
            "dcgs2_guess_features", "dcgs2_guess_targets", "dcgs2_guess_prolong",
-           "dcgs2_guess_guard", "mgs_qr")
+           "dcgs2_guess_guard", "mgs_qr", "dcgs2_arnoldi_steps", "dcgs2_qr_steps")
 (TUNE_FUSED_WAVES, TUNE_REDUCE_GRID, TUNE_FUSED_MIN_J, TUNE_BATCH_REDUCE_ROWS,
  TUNE_FUSED_PAIR_SLOTS, TUNE_BATCH_DENSE) = 0, 1, 2, 3, 4, 5
 
@@ -96,6 +96,12 @@ def load(path: str = LIB_PATH):
                                          c_int32, c_double, c_int32, c_void_p, c_void_p,
                                          c_void_p, POINTER(KsInfo), c_int32]
     lib.dcgs2_apply.argtypes = [c_void_p, POINTER(Op), c_void_p, c_void_p]
+    lib.dcgs2_arnoldi_steps.argtypes = [c_void_p, POINTER(Op), c_int32, c_int32, c_void_p,
+                                        c_int64, c_void_p, c_void_p, c_void_p, c_int32, c_double,
+                                        c_void_p, POINTER(Stats)]
+    lib.dcgs2_qr_steps.argtypes = [c_void_p, c_int64, c_int32, c_int32, c_void_p, c_int64,
+                                   c_void_p, c_int64, c_void_p, c_void_p, c_int32, c_void_p,
+                                   c_double, c_void_p, POINTER(Stats)]
     lib.dcgs2_profile_enable.argtypes = [c_void_p, c_int]
     lib.dcgs2_set_qr_schedule.argtypes = [c_void_p, c_int]
     lib.dcgs2_set_basis_precision.argtypes = [c_void_p, c_int]
@@ -445,6 +451,51 @@ class Context:
         if rc < 0:
             raise DCGS2Error(rc, "dcgs2_arnoldi")
         return H, rc, st.as_dict()
+
+    def arnoldi_steps(self, op: Op, j0: int, j1: int, Q, w, H, K, rho: float, record=True):
+        """Steps j0..j1 of Alg. arnoldi from the state (Q columns, w, H, K, rho); Q and w
+        (device) and H, K (numpy float64, Fortran order, >= j1 rows, >= j1-1 columns) are
+        updated in place.  Returns (records (j1-j0+1, 3 j1 + 1) or None, status, stats)."""
+        pq, ldq = _colmajor_args(Q, "Q")
+        pw = _vec_ptr(w, "w", op.m)
+        for name, M in (("H", H), ("K", K)):
+            if (M.dtype != np.float64 or not M.flags.f_contiguous or M.shape[0] < j1
+                    or M.shape[1] < j1 - 1):
+                raise ValueError(f"{name} must be a Fortran float64 array of >= j1 x (j1-1)")
+        if H.shape[0] != K.shape[0]:
+            raise ValueError("H and K need the same leading dimension")
+        rec = np.empty((j1 - j0 + 1, 3 * j1 + 1)) if record else None
+        st = Stats()
+        rc = self._lib.dcgs2_arnoldi_steps(
+            self._h, ctypes.byref(op), j0, j1, pq, ldq, pw, H.ctypes.data_as(c_void_p),
+            K.ctypes.data_as(c_void_p), H.shape[0], float(rho),
+            rec.ctypes.data_as(c_void_p) if rec is not None else None, ctypes.byref(st))
+        if rc < 0:
+            raise DCGS2Error(rc, "dcgs2_arnoldi_steps")
+        return rec, rc, st.as_dict()
+
+    def qr_steps(self, B, j0: int, j1: int, Q, w, R, S, rho: float, record=True):
+        """Steps j0..j1 of Alg. qr from the state (Q columns, w, S_{1:j0-2,j0-1}, rho);
+        Q, w (device), R (numpy Fortran float64, >= j1-1 square) and S (numpy float64,
+        >= j1-1 entries) are updated in place.  Returns (records or None, status, stats)."""
+        m = B.shape[0]
+        pb, ldb = _colmajor_args(B, "B")
+        pq, ldq = _colmajor_args(Q, "Q")
+        pw = _vec_ptr(w, "w", m)
+        if (R.dtype != np.float64 or not R.flags.f_contiguous or R.shape[0] < j1 - 1
+                or R.shape[1] < j1 - 1):
+            raise ValueError("R must be a Fortran float64 array of >= (j1-1) x (j1-1)")
+        if S.dtype != np.float64 or not S.flags.c_contiguous or S.size < j1 - 1:
+            raise ValueError("S must be a contiguous float64 array of >= j1-1 entries")
+        rec = np.empty((j1 - j0 + 1, 3 * j1 + 1)) if record else None
+        st = Stats()
+        rc = self._lib.dcgs2_qr_steps(
+            self._h, m, j0, j1, pb, ldb, pq, ldq, pw, R.ctypes.data_as(c_void_p), R.shape[0],
+            S.ctypes.data_as(c_void_p), float(rho),
+            rec.ctypes.data_as(c_void_p) if rec is not None else None, ctypes.byref(st))
+        if rc < 0:
+            raise DCGS2Error(rc, "dcgs2_qr_steps")
+        return rec, rc, st.as_dict()
 
     def gmres(self, op: Op, b, x, restart=50, rtol=1e-8, max_iters=100000):
         """Restarted GMRES(restart); x holds x0 on entry and the solution on return."""

@@ -56,6 +56,8 @@ struct dcgs2_ctx_s {
   double *H = nullptr, *K = nullptr, *Rg = nullptr, *R = nullptr, *Z = nullptr;
   double *Sprev = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
   double *Qa = nullptr, *Qb = nullptr;    // internal bases (GMRES, Krylov-Schur)
+  double* rec = nullptr;                  // step records of the steps entry points
+  int64_t cap_rec = 0;
   int basis_q32 = 0;                         // internal bases stored in FP32
   Ctrl* ctrl = nullptr;
   Ctrl* ctrl_host = nullptr;       // pinned
@@ -271,6 +273,46 @@ double op_bytes(const OpDev& op) {
   return 16.0 * m;
 }
 
+// Device workspace of one expansion: the context's buffers, or views into other
+// device memory.
+struct Work {
+  double *w = nullptr, *v = nullptr, *r = nullptr;     // length-m vectors
+  double* P1 = nullptr;                                 // reduction partials
+  int ldp = 0;
+  double *coef = nullptr, *pend = nullptr;
+  double *H = nullptr, *K = nullptr, *Rg = nullptr, *R = nullptr;
+  double *Sprev = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
+  Ctrl* ctrl = nullptr;
+  Ctrl* ctrl_host = nullptr;                            // pinned read-back, or nullptr
+};
+
+Work ctx_work(dcgs2_ctx c) {
+  Work k;
+  k.w = c->w; k.v = c->v; k.r = c->r;
+  k.P1 = c->P1; k.ldp = LDP;
+  k.coef = c->coef; k.pend = c->pend;
+  k.H = c->H; k.K = c->K; k.Rg = c->Rg; k.R = c->R;
+  k.Sprev = c->Sprev; k.cs = c->cs; k.sn = c->sn; k.g = c->g;
+  k.ctrl = c->ctrl; k.ctrl_host = c->ctrl_host;
+  return k;
+}
+
+// Control block into *out: through the pinned buffer when there is one, else
+// straight into *out (pageable; the copy completes before the synchronisation).
+int read_ctrl(dcgs2_ctx c, const Work& k, Ctrl* out) {
+  if (!k.ctrl_host) {
+    CK(hipMemcpyAsync(out, k.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
+    CK(hipStreamSynchronize(c->stream));
+    if (c->prof) prof_resolve(c);
+    return DCGS2_OK;
+  }
+  CK(hipMemcpyAsync(k.ctrl_host, k.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c->stream));
+  CK(hipStreamSynchronize(c->stream));
+  *out = *k.ctrl_host;
+  if (c->prof) prof_resolve(c);
+  return DCGS2_OK;
+}
+
 // One expansion (QR or Arnoldi) over a basis Q.
 struct Expansion {
   dcgs2_ctx c;
@@ -286,17 +328,23 @@ struct Expansion {
   bool one_pass = false;        // QR: fuse update(j) with the reduction of step j+1
   int ldh = 0;                  // leading dimension of H/K/Rg (Arnoldi) or R (QR)
   GridRed gr{};
+  Work wk{};                    // device workspace (set by setup_expansion)
+  // step records (the steps entry points): step j writes rec + (j - rec_j0) rec_ld
+  double* rec = nullptr;
+  int rec_j0 = 0, rec_ld = 0;
 
   FinArgs fin(int kind, int j, int J) const {
     FinArgs f{};
     f.kind = kind; f.qr = qr; f.j = j; f.J = J; f.gmres = gmres; f.ldc = LDC;
-    f.ctrl = c->ctrl; f.coef = c->coef; f.pend = c->pend;
-    f.H = c->H; f.K = c->K; f.ldh = ldh;
-    f.R = c->R; f.ldr = ldh; f.Sprev = c->Sprev;
-    f.Rg = c->Rg; f.cs = c->cs; f.sn = c->sn; f.g = c->g;
+    f.ctrl = wk.ctrl; f.coef = wk.coef; f.pend = wk.pend;
+    f.H = wk.H; f.K = wk.K; f.ldh = ldh;
+    f.R = wk.R; f.ldr = ldh; f.Sprev = wk.Sprev;
+    f.Rg = wk.Rg; f.cs = wk.cs; f.sn = wk.sn; f.g = wk.g;
+    if (rec && (kind == FIN_STEP || kind == FIN_FALLBACK) && j >= rec_j0)
+      f.rec = rec + (int64_t)(j - rec_j0) * rec_ld;
     return f;
   }
-  const double* ycol(int j) const { return qr ? B + (int64_t)(j - 1) * ldb : c->v; }
+  const double* ycol(int j) const { return qr ? B + (int64_t)(j - 1) * ldb : wk.v; }
   double spmv_bytes() const { return op_bytes(op); }
 
   int enqueue_step(int j, int kind) {
@@ -304,11 +352,11 @@ struct Expansion {
     hipStream_t s = c->stream;
     const double vm = 8.0 * (double)m;
     const double qb = q32 ? 4.0 * (double)m : vm;      // bytes of one basis column
-    if (!qr) KL(K_SPMV, spmv_bytes(), launch_spmv(op, c->w, nullptr, c->v, c->ctrl, s));
+    if (!qr) KL(K_SPMV, spmv_bytes(), launch_spmv(op, wk.w, nullptr, wk.v, wk.ctrl, s));
     KL(K_REDUCE, qb * J + 2 * vm,
-       launch_reduce(Q, q32, ldq, J, c->w, ycol(j), m, gr, fin(kind, j, J), s, mid_));
+       launch_reduce(Q, q32, ldq, J, wk.w, ycol(j), m, gr, fin(kind, j, J), s, mid_));
     KL(K_UPDATE, qb * (J + 1) + 3 * vm,
-       launch_update(Q, q32, ldq, J, c->w, ycol(j), nullptr, m, c->coef, LDC, !qr, 0, c->ctrl, s));
+       launch_update(Q, q32, ldq, J, wk.w, ycol(j), nullptr, m, wk.coef, LDC, !qr, 0, wk.ctrl, s));
     return DCGS2_OK;
   }
   int enqueue_fallback(int j) {
@@ -317,9 +365,9 @@ struct Expansion {
     const double vm = 8.0 * (double)m;
     const double qb = q32 ? 4.0 * (double)m : vm;
     KL(K_PROJNORM, qb * J + 2 * vm,
-       launch_project_norm(Q, q32, ldq, J, c->w, c->r, m, gr, fin(FIN_FALLBACK, j, J), s, mid_));
+       launch_project_norm(Q, q32, ldq, J, wk.w, wk.r, m, gr, fin(FIN_FALLBACK, j, J), s, mid_));
     KL(K_UPDATE, qb * (J + 1) + 4 * vm,
-       launch_update(Q, q32, ldq, J, c->w, ycol(j), c->r, m, c->coef, LDC, !qr, 1, c->ctrl, s));
+       launch_update(Q, q32, ldq, J, wk.w, ycol(j), wk.r, m, wk.coef, LDC, !qr, 1, wk.ctrl, s));
     return DCGS2_OK;
   }
   // CGS2 finish of the last column: J final columns already in Q.
@@ -332,11 +380,11 @@ struct Expansion {
     // (rho_next keeps its initial 0)
     if (J > 0)
       KL(K_REDUCE, qb * J + vm,
-         launch_reduce(Q, q32, ldq, J, c->w, nullptr, m, gr, fin(FIN_LAST1, jvirt, J), s, mid_));
+         launch_reduce(Q, q32, ldq, J, wk.w, nullptr, m, gr, fin(FIN_LAST1, jvirt, J), s, mid_));
     KL(K_PROJNORM, qb * J + 2 * vm,
-       launch_project_norm(Q, q32, ldq, J, c->w, c->r, m, gr, fin(FIN_LAST2, jvirt, J), s, mid_));
+       launch_project_norm(Q, q32, ldq, J, wk.w, wk.r, m, gr, fin(FIN_LAST2, jvirt, J), s, mid_));
     KL(K_SCALE, vm + qb,
-       launch_scale_col(Q, q32, ldq, J, c->r, m, c->coef, LDC, c->ctrl, s));
+       launch_scale_col(Q, q32, ldq, J, wk.r, m, wk.coef, LDC, wk.ctrl, s));
     return DCGS2_OK;
   }
   // One-pass QR schedule for steps j0..j_to: reduce(j0), then fused(j) =
@@ -348,13 +396,13 @@ struct Expansion {
     if (j0 > j_to) return J_last >= 0 ? enqueue_last(J_last, j_to + 1) : DCGS2_OK;
     const double qb = q32 ? 4.0 * (double)m : vm;
     KL(K_REDUCE, qb * (j0 - 2) + 2 * vm,
-       launch_reduce(Q, q32, ldq, j0 - 2, c->w, ycol(j0), m, gr, fin(kind0, j0, j0 - 2), s, mid_));
+       launch_reduce(Q, q32, ldq, j0 - 2, wk.w, ycol(j0), m, gr, fin(kind0, j0, j0 - 2), s, mid_));
     for (int j = j0; j <= j_to; ++j) {
       const int J = j - 2;
       const bool last = (j == j_to);
       if (last && J_last < 0) {
         KL(K_UPDATE, qb * (J + 1) + 3 * vm,
-           launch_update(Q, q32, ldq, J, c->w, ycol(j), nullptr, m, c->coef, LDC, 0, 0, c->ctrl,
+           launch_update(Q, q32, ldq, J, wk.w, ycol(j), nullptr, m, wk.coef, LDC, 0, 0, wk.ctrl,
                          s));
         break;
       }
@@ -362,24 +410,24 @@ struct Expansion {
       if (J < c->tune_fused_min_j) {
         // a short basis: the separate passes stream better than the tiled fused pass
         KL(K_UPDATE, qb * (J + 1) + 3 * vm,
-           launch_update(Q, q32, ldq, J, c->w, ycol(j), nullptr, m, c->coef, LDC, 0, 0, c->ctrl,
+           launch_update(Q, q32, ldq, J, wk.w, ycol(j), nullptr, m, wk.coef, LDC, 0, 0, wk.ctrl,
                          s));
         KL(K_REDUCE, qb * (J + 1) + (last ? 1 : 2) * vm,
-           launch_reduce(Q, q32, ldq, J + 1, c->w, last ? nullptr : ycol(j + 1), m, gr, f, s, mid_));
+           launch_reduce(Q, q32, ldq, J + 1, wk.w, last ? nullptr : ycol(j + 1), m, gr, f, s, mid_));
         continue;
       }
       // bytes: Q_{0..J-1}, w, a_j, a_{j+1} read; q, w written (grid sized inside)
       KL(K_FUSED, qb * (J + 1) + vm * (last ? 3 : 4),
-         launch_fused_qr(Q, q32, ldq, J, c->w, ycol(j), last ? nullptr : ycol(j + 1), m,
-                         c->coef, LDC, last ? 1 : 0, c->tune_fused_waves,
+         launch_fused_qr(Q, q32, ldq, J, wk.w, ycol(j), last ? nullptr : ycol(j + 1), m,
+                         wk.coef, LDC, last ? 1 : 0, c->tune_fused_waves,
                          c->tune_reduce_gmax, c->tune_pair_max_ns, gr, f, s, mid_));
     }
     if (J_last >= 0) {
       KL(K_PROJNORM, qb * J_last + 2 * vm,
-         launch_project_norm(Q, q32, ldq, J_last, c->w, c->r, m, gr,
+         launch_project_norm(Q, q32, ldq, J_last, wk.w, wk.r, m, gr,
                              fin(FIN_LAST2, j_to + 1, J_last), s, mid_));
       KL(K_SCALE, vm + qb,
-         launch_scale_col(Q, q32, ldq, J_last, c->r, m, c->coef, LDC, c->ctrl, s));
+         launch_scale_col(Q, q32, ldq, J_last, wk.r, m, wk.coef, LDC, wk.ctrl, s));
     }
     return DCGS2_OK;
   }
@@ -392,7 +440,7 @@ struct Expansion {
     bool pending_fallback = false;
     for (;;) {
       if (pending_fallback) {
-        CKL(launch_set_state(c->ctrl, ST_RUNNING, c->stream));
+        CKL(launch_set_state(wk.ctrl, ST_RUNNING, c->stream));
         if ((rc = enqueue_fallback(j0))) return rc;
         ++j0;
         kind0 = FIN_STEP;
@@ -405,7 +453,7 @@ struct Expansion {
         }
         if (J_last >= 0 && (rc = enqueue_last(J_last, j_to + 1))) return rc;
       }
-      if ((rc = read_ctrl(c, out))) return rc;
+      if ((rc = read_ctrl(c, wk, out))) return rc;
       if (out->state != ST_FALLBACK) return DCGS2_OK;
       j0 = out->stop_step;
       pending_fallback = true;
@@ -413,12 +461,13 @@ struct Expansion {
   }
 };
 
-int setup_expansion(dcgs2_ctx c, Expansion& e, double thresh) {
+int setup_expansion(dcgs2_ctx c, Expansion& e, double thresh, double rho = 0.0) {
   e.c = c;
+  if (!e.wk.ctrl) e.wk = ctx_work(c);
   reduce_grid(e.m, c->tune_reduce_gmax, &e.gr.G);
-  e.gr.P1 = c->P1;
-  e.gr.ldp = LDP;
-  CK(launch_init_ctrl(c->ctrl, c->tau, c->eta, thresh, c->stream));
+  e.gr.P1 = e.wk.P1;
+  e.gr.ldp = e.wk.ldp;
+  CK(launch_init_ctrl(e.wk.ctrl, c->tau, c->eta, thresh, c->stream, rho));
   c->kernels += 1;
   return DCGS2_OK;
 }
@@ -485,7 +534,7 @@ int dcgs2_destroy(dcgs2_ctx c) {
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     double* bufs[] = {c->w, c->v, c->r, c->P1, c->coef, c->pend, c->H, c->K, c->Rg,
-                      c->R, c->Z, c->Sprev, c->cs, c->sn, c->g, c->Qa, c->Qb};
+                      c->R, c->Z, c->Sprev, c->cs, c->sn, c->g, c->Qa, c->Qb, c->rec};
     for (double* b : bufs) dfree(b);
     dfree(c->ctrl);
     prof_resolve(c);
@@ -664,6 +713,132 @@ int dcgs2_arnoldi(dcgs2_ctx c, const dcgs2_op* A, const double* r0, int32_t n, d
 int dcgs2_arnoldi_q32(dcgs2_ctx c, const dcgs2_op* A, const double* r0, int32_t n, float* Q,
                       int64_t ldq, double* H_host, int32_t ldh, dcgs2_stats* st) {
   return arnoldi_impl(c, A, r0, n, Q, 1, ldq, H_host, ldh, st);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Host block (rows x cols, leading dimension ldhost) into a zero-padded device block of
+// leading dimension ld.
+int put_small(dcgs2_ctx c, double* dev, int ld, int rows, int cols, const double* host,
+              int ldhost) {
+  std::vector<double> tmp((size_t)ld * cols, 0.0);
+  for (int jj = 0; jj < cols; ++jj)
+    for (int i = 0; i < rows; ++i) tmp[(size_t)jj * ld + i] = host[(size_t)jj * ldhost + i];
+  CK(hipMemcpyAsync(dev, tmp.data(), sizeof(double) * tmp.size(), hipMemcpyHostToDevice,
+                    c->stream));
+  CK(hipStreamSynchronize(c->stream));
+  return DCGS2_OK;
+}
+
+// Step records of steps j0..j1: one record of 3 j1 + 1 doubles per step (the largest,
+// step j1, has 2 j1 reduced values, j1 - 1 coefficients, alpha and rho), NaN-filled
+// so that a step that did not run is visible.
+int steps_records(dcgs2_ctx c, Expansion& e, int j0, int j1) {
+  const int ld = 3 * j1 + 1;
+  const int64_t need = (int64_t)(j1 - j0 + 1) * ld;
+  if (need > c->cap_rec) {
+    CK(hipStreamSynchronize(c->stream));
+    dfree(c->rec);
+    c->rec = nullptr;
+    c->cap_rec = 0;
+    const int rc = dalloc((void**)&c->rec, sizeof(double) * (size_t)need);
+    if (rc) return rc;
+    c->cap_rec = need;
+  }
+  CKL(launch_fill(c->rec, need, NAN, c->stream));
+  e.rec = c->rec;
+  e.rec_j0 = j0;
+  e.rec_ld = ld;
+  return DCGS2_OK;
+}
+
+int read_records(dcgs2_ctx c, int j0, int j1, double* rec_host) {
+  const size_t n = (size_t)(j1 - j0 + 1) * (3 * j1 + 1);
+  CK(hipMemcpyAsync(rec_host, c->rec, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  CK(hipStreamSynchronize(c->stream));
+  return DCGS2_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dcgs2_arnoldi_steps(dcgs2_ctx c, const dcgs2_op* A, int32_t j0, int32_t j1, double* Q,
+                        int64_t ldq, double* w, double* H_host, double* K_host, int32_t ldh,
+                        double rho, double* rec_host, dcgs2_stats* st) {
+  if (!c || !valid_op(A) || !Q || !w || !H_host || !K_host || j0 < 2 || j1 < j0 ||
+      j1 > DCGS2_MAX_N + 1 || (int64_t)j1 > A->m || ldq < A->m || ldh < j1 ||
+      !(rho >= 0.0) || !std::isfinite(rho))
+    return DCGS2_EINVAL;
+  int rc;
+  if ((rc = ctx_ready(c))) return rc;
+  const int64_t m = A->m;
+  if ((rc = ensure_vectors(c, m))) return rc;
+  c->kernels = 0;
+  Expansion e;
+  e.qr = false;
+  e.m = m;
+  e.Q = Q; e.q32 = 0; e.ldq = ldq;
+  e.op = to_dev(A);
+  e.ldh = j1;                                  // H, K rows 0..j1-2 and columns 0..j1-2
+  if (rec_host && (rc = steps_records(c, e, j0, j1))) return rc;
+  if ((rc = setup_expansion(c, e, 0.0, rho))) return rc;
+  if ((rc = put_small(c, c->H, j1, j1, j1 - 1, H_host, ldh))) return rc;
+  if ((rc = put_small(c, c->K, j1, j1, j1 - 1, K_host, ldh))) return rc;
+  CKL(launch_copy(c->w, w, m, c->stream));
+  Ctrl s{};
+  if ((rc = e.run(j0, j1, FIN_STEP, -1, &s))) return rc;
+  const int status = status_of(s);
+  if ((rc = copy_to_host(c, c->H, j1, j1, j1 - 1, H_host, ldh))) return rc;
+  if ((rc = copy_to_host(c, c->K, j1, j1, j1 - 1, K_host, ldh))) return rc;
+  CKL(launch_copy(w, c->w, m, c->stream));
+  CK(hipStreamSynchronize(c->stream));
+  if (rec_host && (rc = read_records(c, j0, j1, rec_host))) return rc;
+  fill_stats(st, s, c->kernels, status);
+  return status;
+}
+
+int dcgs2_qr_steps(dcgs2_ctx c, int64_t m, int32_t j0, int32_t j1, const double* B, int64_t ldb,
+                   double* Q, int64_t ldq, double* w, double* R_host, int32_t ldr,
+                   double* S_host, double rho, double* rec_host, dcgs2_stats* st) {
+  if (!c || m < 2 || j0 < 2 || j1 < j0 || j1 > DCGS2_MAX_N || (int64_t)j1 > m || !B || !Q ||
+      !w || !R_host || !S_host || ldb < m || ldq < m || ldr < j1 - 1 || !(rho >= 0.0) ||
+      !std::isfinite(rho))
+    return DCGS2_EINVAL;
+  int rc;
+  if ((rc = ctx_ready(c))) return rc;
+  if ((rc = ensure_vectors(c, m))) return rc;
+  c->kernels = 0;
+  Expansion e;
+  e.qr = true;
+  e.m = m;
+  e.Q = Q; e.q32 = 0; e.ldq = ldq; e.B = B; e.ldb = ldb;
+  e.ldh = j1;                                  // R rows 0..j1-2 and columns 0..j1-2
+  e.one_pass = c->qr_one_pass && j1 - 2 <= FUSED_QR_MAX_J && (double)m * 8.0 < 2147483648.0;
+  if (rec_host && (rc = steps_records(c, e, j0, j1))) return rc;
+  if ((rc = setup_expansion(c, e, 0.0, rho))) return rc;
+  CKL(launch_fill(c->R, (int64_t)j1 * j1, 0.0, c->stream));
+  if (j0 > 2) {
+    CK(hipMemcpyAsync(c->Sprev, S_host, sizeof(double) * (j0 - 2), hipMemcpyHostToDevice,
+                      c->stream));
+  }
+  CKL(launch_copy(c->w, w, m, c->stream));
+  Ctrl s{};
+  if ((rc = e.run(j0, j1, FIN_STEP, -1, &s))) return rc;
+  const int status = status_of(s);
+  std::vector<double> Rd((size_t)j1 * (j1 - 1));
+  if ((rc = copy_to_host(c, c->R, j1, j1, j1 - 1, Rd.data(), j1))) return rc;
+  for (int jj = j0 - 2; jj <= j1 - 2; ++jj)
+    for (int i = 0; i <= jj; ++i) R_host[(size_t)jj * ldr + i] = Rd[(size_t)jj * j1 + i];
+  CK(hipMemcpyAsync(S_host, c->Sprev, sizeof(double) * (j1 - 1), hipMemcpyDeviceToHost,
+                    c->stream));
+  CKL(launch_copy(w, c->w, m, c->stream));
+  CK(hipStreamSynchronize(c->stream));
+  if (rec_host && (rc = read_records(c, j0, j1, rec_host))) return rc;
+  fill_stats(st, s, c->kernels, status);
+  return status;
 }
 
 int cgs2_qr(dcgs2_ctx c, int64_t m, int32_t n, const double* B, int64_t ldb, double* Q,

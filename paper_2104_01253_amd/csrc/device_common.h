@@ -319,6 +319,14 @@ __device__ void step_tail(const FinArgs& f, const double* C, const double* S, do
   for (int i = threadIdx.x; i < J; i += (int)blockDim.x) T[i] = f.qr ? S[i] : S[i] / alpha;
   if (threadIdx.x == 0) T[J] = f.qr ? (sigma - csum) / alpha : (sigma - csum) / (alpha * alpha);
   __syncthreads();
+  if (f.rec) {                                    // step record: T, alpha, next rho
+    double* r = f.rec + 2 * (J + 2);
+    for (int i = threadIdx.x; i <= J; i += (int)blockDim.x) r[i] = T[i];
+    if (threadIdx.x == 0) {
+      r[J + 1] = alpha;
+      r[J + 2] = f.qr ? sqrt(gamma) : sqrt(gamma) / alpha;
+    }
+  }
   for (int i = threadIdx.x; i < J; i += (int)blockDim.x) f.coef[i] = C[i];
   for (int i = threadIdx.x; i <= J; i += (int)blockDim.x) f.coef[f.ldc + i] = T[i];
   if (threadIdx.x == 0) f.coef[2 * f.ldc] = alpha;
@@ -571,6 +579,8 @@ __device__ void finish_body(const GridRed& gr, int V, const FinArgs& fin, int J)
   // that the two memory latencies overlap (a stopped expansion still returns here)
   partial_sum(gr.P1, gr.ldp, gr.G, V, red, sp);
   if (fin.ctrl->state != ST_RUNNING) return;
+  if (fin.rec && fin.kind == FIN_STEP)
+    for (int v = threadIdx.x; v < V; v += (int)blockDim.x) fin.rec[v] = red[v];
   finalize(fin, red, T, scratch);
 }
 

@@ -61,6 +61,10 @@ struct FinArgs {
   double* H; double* K; int ldh;           // Arnoldi (device, column-major)
   double* R; int ldr; double* Sprev;       // QR     (device, column-major)
   double* Rg; double* cs; double* sn; double* g;   // GMRES Givens state
+  // Optional step record (nullptr: none).  A DCGS2 step (FIN_STEP, and its
+  // FIN_FALLBACK completion) writes its 2(J+2) reduced values, then T (or the S
+  // column in QR, J+1 values), alpha and the next breakdown scale.
+  double* rec;
 };
 
 // Deterministic grid reduction: each of the G workgroups of a streaming kernel
@@ -82,7 +86,9 @@ struct OpDev {
 
 // ---- launchers (kernels.hip) -------------------------------------------------------
 // Every launcher returns the hipError_t of its launch.
-hipError_t launch_init_ctrl(Ctrl* ctrl, double tau, double eta, double thresh, hipStream_t s);
+// rho: initial breakdown scale (rho_next) of the vector held in w.
+hipError_t launch_init_ctrl(Ctrl* ctrl, double tau, double eta, double thresh, hipStream_t s,
+                            double rho = 0.0);
 hipError_t launch_fill(double* p, int64_t n, double val, hipStream_t s);
 hipError_t launch_set_state(Ctrl* ctrl, int state, hipStream_t s);
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);

@@ -25,6 +25,7 @@
 
 #include "internal.h"
 
+
 namespace dcgs2 {
 namespace {
 
@@ -452,7 +453,7 @@ __global__ __launch_bounds__(BS) void tsgemm_kernel(const TQ* __restrict__ Q, in
   }
 }
 
-__global__ void init_ctrl_kernel(Ctrl* c, double tau, double eta, double thresh) {
+__global__ void init_ctrl_kernel(Ctrl* c, double tau, double eta, double thresh, double rho) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     c->state = ST_RUNNING;
     c->stop_step = -1;
@@ -460,7 +461,7 @@ __global__ void init_ctrl_kernel(Ctrl* c, double tau, double eta, double thresh)
     c->reductions = 0;
     c->fallbacks = 0;
     c->pad0 = 0;
-    c->rho_next = 0.0;
+    c->rho_next = rho;
     c->tau = tau;
     c->eta = eta;
     c->gmres_thresh = thresh;
@@ -517,8 +518,9 @@ void reduce_grid(int64_t m, int gmax, int* G) {
   *G = (int)g;
 }
 
-hipError_t launch_init_ctrl(Ctrl* ctrl, double tau, double eta, double thresh, hipStream_t s) {
-  init_ctrl_kernel<<<1, 64, 0, s>>>(ctrl, tau, eta, thresh);
+hipError_t launch_init_ctrl(Ctrl* ctrl, double tau, double eta, double thresh, hipStream_t s,
+                            double rho) {
+  init_ctrl_kernel<<<1, 64, 0, s>>>(ctrl, tau, eta, thresh, rho);
   return hipGetLastError();
 }
 

@@ -1,6 +1,10 @@
 """Fixed workloads for rocprofv3 runs, and the summariser for their output.
 
     python -m paper_2104_01253_amd.profile_run run --workload qr [--reps 2]
+
+Workloads: qr and qr32 (2,000,000 x 100 QR, FP64 or FP32-stored basis), qr2pass,
+arnoldi (128^3 stencil, n = 100), gmres and gmres32 (GMRES(50) at 128^3 to 1e-8,
+FP64 or FP32-stored basis), batched (128 Krylov-Schur instances).
     python -m paper_2104_01253_amd.profile_run summarize --fetch DIR --write DIR \\
         --trace DIR --out profiles/<name>
 
@@ -37,10 +41,10 @@ def run(workload: str, reps: int, tuning=None):
     for key, value in (tuning or {}).items():
         if value is not None:
             ctx.set_tuning(getattr(binding, key), value)
-    if workload == "qr":
+    if workload in ("qr", "qr32"):
         m, n = 2_000_000, 100
         B = binding.colmajor_from_numpy(synth.tall_skinny(m, n, 8.0))
-        Q = binding.colmajor_empty(m, n)
+        Q = binding.colmajor_empty(m, n, dtype=torch.float32 if workload == "qr32" else None)
         for _ in range(reps):
             _, rc, _ = ctx.qr(B, Q)
             assert rc == 0
@@ -60,7 +64,9 @@ def run(workload: str, reps: int, tuning=None):
         for _ in range(reps):
             _, rc, _ = ctx.arnoldi(op, bd, 100, Q)
             assert rc == 0
-    elif workload == "gmres":
+    elif workload in ("gmres", "gmres32"):
+        if workload == "gmres32":
+            ctx.set_basis_precision(32)
         prob, b = synth.gmres_cd3d(128)
         op = binding.stencil_op(prob.grid, prob.D, prob.vel)
         bd = torch.from_numpy(b).cuda()

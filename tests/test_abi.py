@@ -167,3 +167,46 @@ def test_varcoef_csr_matches_the_oracle_assembly():
         B = varcoef_matrix(p)
         assert abs(A - B).max() <= 1e-15 * abs(B).max()
         assert np.all(np.diff(ci.reshape(-1)[rp[0]:rp[1]]) > 0)
+
+
+def test_steps_argument_validation(ctx):
+    """dcgs2_arnoldi_steps / dcgs2_qr_steps reject bad step ranges and layouts."""
+    lib, h = ctx
+    E = binding.EINVAL
+    op = binding.stencil_op((8, 8), 1.0, (1.0, 1.0))
+    H = (ctypes.c_double * 4096)()
+    K = (ctypes.c_double * 4096)()
+    ok = (h, ctypes.byref(op), 3, 5, FAKE, 64, FAKE, H, K, 5, 1.0, None, None)
+
+    def arn(**kw):
+        a = list(ok)
+        for i, v in kw.items():
+            a[int(i[1:])] = v
+        return lib.dcgs2_arnoldi_steps(*a)
+    assert arn(a2=1) == E                        # j0 < 2
+    assert arn(a3=2) == E                        # j1 < j0
+    assert arn(a3=65) == E                       # j1 > m
+    assert arn(a5=63) == E                       # ldq < m
+    assert arn(a9=4) == E                        # ldh < j1
+    assert arn(a10=float("nan")) == E            # rho
+    assert arn(a10=-1.0) == E
+    assert arn(a6=None) == E                     # w
+    assert arn(a0=None) == E
+    S = (ctypes.c_double * 64)()
+    R = (ctypes.c_double * 4096)()
+    okq = [h, 100, 3, 5, FAKE, 100, FAKE, 100, FAKE, R, 4, S, 1.0, None, None]
+
+    def qr(**kw):
+        a = list(okq)
+        for i, v in kw.items():
+            a[int(i[1:])] = v
+        return lib.dcgs2_qr_steps(*a)
+    assert qr(a1=1) == E                         # m < 2
+    assert qr(a2=1) == E                         # j0 < 2
+    assert qr(a3=101) == E                       # j1 > m
+    assert qr(a5=99) == E                        # ldb < m
+    assert qr(a7=99) == E                        # ldq < m
+    assert qr(a10=3) == E                        # ldr < j1 - 1
+    assert qr(a11=None) == E                     # S
+    assert qr(a12=float("inf")) == E             # rho
+

@@ -3,9 +3,10 @@ GMRES option) against the oracle's FP32-basis variant.
 
 Both sides compute every q in FP64 and round it once to FP32; the FP64 values
 differ only by summation order (~1e-16 relative), so a stored entry differs by at
-most one FP32 ulp, rarely.  QR: R within 1e-10 relative, (dQ)R within 10 eps_32,
-raw Q within 4 eps_32 at low kappa.  Arnoldi: H within 20 eps_32 (a flip propagates
-through the matvec), plus the representation error and orthogonality.
+most one FP32 ulp, rarely.  QR: R element-wise within 1e-11 of its column's norm,
+(dQ)R within 10 eps_32,
+raw Q within 4 eps_32 at low kappa.  Arnoldi: H within 1.5e-7 relative (a flip
+propagates through the matvec), plus the representation error and orthogonality.
 """
 import numpy as np
 import pytest
@@ -16,7 +17,7 @@ from oracle import operators as ops
 from oracle.gmres import gmres_dcgs2
 from oracle.metrics import loss_of_orthogonality, representation_error
 from paper_2104_01253_amd import binding, synth
-from tests._gpu import dev_matrix, dev_vector, host, relnorm, say, torch_cuda
+from tests._gpu import colerr, dev_matrix, dev_vector, host, relnorm, say, torch_cuda
 
 pytestmark = pytest.mark.gpu
 EPS32 = float(np.finfo(np.float32).eps)
@@ -47,8 +48,10 @@ def test_qr_q32_parity(ctx, m, n, ce, one_pass):
     ref = gs.dcgs2_qr(B, qdtype=np.float32)
     Qh = host(Q).astype(np.float64)
     assert rc == 0 and st["reductions"] == n + 1
-    say("q32 R rel", relnorm(R, ref["R"]), "Q max", np.max(np.abs(Qh - ref["Q"])))
-    assert relnorm(R, ref["R"]) <= 1e-10
+    say("q32 R rel", relnorm(R, ref["R"]), "R colerr", colerr(R, ref["R"]),
+        "Q max", np.max(np.abs(Qh - ref["Q"])))
+    # measured colerr up to 6.9e-13 (300,001 x 100, kappa 1e8); the gate is 1e-11
+    assert colerr(R, ref["R"]) <= 1e-11
     Qr = ref["Q"].astype(np.float64)
     # a one-ulp difference in an early stored column is amplified by kappa(B_{1:j}) in
     # the later columns, so raw Q is compared only where kappa is small; (dQ) R is
@@ -68,11 +71,13 @@ def test_arnoldi_q32_parity(ctx):
     ref = ar.dcgs2_arnoldi(lambda x: A @ x, r0, n, qdtype=np.float32)
     assert rc == 0
     # The FP32-stored Arnoldi is defined only to O(eps_32): one rounding flip in an
-    # early column feeds every later column through the matvec (on the CPU oracle, a
-    # 1e-16 relative change of r0 moves H by 1.4e-8 relative).  Gate at 20 eps_32 and
-    # check the decomposition itself.
+    # early column feeds every later column through the matvec.  On the CPU oracle a
+    # 1e-16 relative change of r0 moves H by 1.4e-8 relative, and the GPU against the
+    # oracle measured 1.47e-8; the gate is ten times that, 1.5e-7, beside the
+    # decomposition itself.
     Qh = host(Q).astype(np.float64)
-    assert relnorm(H, ref["H"]) <= 20 * EPS32
+    say("q32 arnoldi H rel", relnorm(H, ref["H"]), "H colerr", colerr(H, ref["H"]))
+    assert relnorm(H, ref["H"]) <= 1.5e-7
     assert representation_error(A, Qh, H, n) <= EPS32
     assert loss_of_orthogonality(Qh) <= 60 * EPS32
 

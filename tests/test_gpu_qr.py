@@ -1,9 +1,10 @@
 """GPU parity of dcgs2_qr (Alg. qr) against the FP64 oracle, through the C ABI.
 
-Gate: 1e-12 relative, normwise on the quantities that are unique at the given
-conditioning -- R, (Q - Q_oracle) R_oracle / ||B||, and raw Q where kappa(B) is
-small (raw Q at kappa ~ 1e8 differs between any two correct implementations by
-~ eps * kappa).
+Gate: 1e-12 on the quantities that are unique at the given conditioning -- R
+element-wise against the norm of its own column (colerr), (Q - Q_oracle) R_oracle /
+||B|| normwise, and raw Q element-wise where kappa(B) is small (raw Q at kappa ~ 1e8
+differs between any two correct implementations by ~ eps * kappa(B_{1:j}) in
+column j).
 """
 import numpy as np
 import pytest
@@ -11,7 +12,7 @@ import pytest
 from oracle import gram_schmidt as gs
 from oracle.metrics import loss_of_orthogonality, qr_error
 from paper_2104_01253_amd import binding, synth
-from tests._gpu import dev_matrix, host, relnorm, say, torch_cuda
+from tests._gpu import colerr, dev_matrix, host, say, torch_cuda
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -33,8 +34,12 @@ def run_qr(ctx, B, ld=None):
 
 
 @pytest.mark.parametrize("one_pass", [True, False])
-@pytest.mark.parametrize("m,n,ce", [(1000, 1, 2), (1000, 2, 2), (1023, 3, 2), (4097, 17, 2),
-                                    (4097, 17, 8), (20011, 64, 8), (3000, 100, 4), (130, 120, 2)])
+# m = 1, 2, 63, 64 and 65: one partial tile of the one-pass kernel (64 rows with
+# one-row slots, 128 with two-row slots), odd and even
+@pytest.mark.parametrize("m,n,ce", [(1, 1, 2), (2, 2, 2), (63, 20, 2), (64, 17, 2), (65, 40, 2),
+                                    (64, 64, 1), (1000, 1, 2), (1000, 2, 2), (1023, 3, 2),
+                                    (4097, 17, 2), (4097, 17, 8), (20011, 64, 8), (3000, 100, 4),
+                                    (130, 120, 2)])
 def test_qr_parity_small(ctx, m, n, ce, one_pass):
     say(f"qr parity m={m} n={n} kappa=1e{ce} one_pass={one_pass}")
     B = synth.tall_skinny(m, n, ce, seed_g=100 + m, seed_v=7)
@@ -45,10 +50,10 @@ def test_qr_parity_small(ctx, m, n, ce, one_pass):
         ctx.set_qr_schedule(True)
     ref = gs.dcgs2_qr(B)
     assert rc == binding.OK and ref["status"] == 0
-    assert relnorm(R, ref["R"]) <= TOL
+    assert colerr(R, ref["R"]) <= TOL
     assert np.linalg.norm((Q - ref["Q"]) @ ref["R"]) / np.linalg.norm(B) <= TOL
-    if ce <= 2:
-        assert np.linalg.norm(Q - ref["Q"]) / np.sqrt(n) <= TOL
+    if np.linalg.cond(B) <= 1e3:
+        assert colerr(Q, ref["Q"]) <= TOL
     assert st["reductions"] == ref["reductions"] == (n + 1 if n > 1 else 1)
     assert loss_of_orthogonality(Q) <= 1e-13
     assert qr_error(B, Q, R) <= 1e-14
@@ -61,8 +66,8 @@ def test_qr_unaligned_leading_dimension(ctx):
     Q, R, rc, _ = run_qr(ctx, B, ld=5003)
     ref = gs.dcgs2_qr(B)
     assert rc == 0
-    assert relnorm(R, ref["R"]) <= TOL
-    assert np.linalg.norm(Q - ref["Q"]) / np.sqrt(n) <= TOL
+    assert colerr(R, ref["R"]) <= TOL
+    assert colerr(Q, ref["Q"]) <= TOL
 
 
 def test_qr_deterministic(ctx):
@@ -87,8 +92,8 @@ def test_qr_forced_fallback(ctx, one_pass):
     assert rc == 0
     assert st["pyth_fallbacks"] == ref["fallbacks"] == 14
     assert st["reductions"] == ref["reductions"]
-    assert relnorm(R, ref["R"]) <= TOL
-    assert np.linalg.norm(Q - ref["Q"]) / np.sqrt(15) <= TOL
+    assert colerr(R, ref["R"]) <= TOL
+    assert colerr(Q, ref["Q"]) <= TOL
 
 
 def test_qr_breakdown(ctx):
@@ -98,8 +103,8 @@ def test_qr_breakdown(ctx):
     ref = gs.dcgs2_qr(B)
     assert rc == binding.BREAKDOWN and ref["status"] == gs.BREAKDOWN
     assert st["breakdown_step"] == ref["k"] == 3
-    assert relnorm(R[:3, :4], ref["R"][:3, :4]) <= TOL
-    assert np.linalg.norm(Q[:, :3] - ref["Q"][:, :3]) <= TOL
+    assert colerr(R[:3, :4], ref["R"][:3, :4]) <= TOL
+    assert colerr(Q[:, :3], ref["Q"][:, :3]) <= TOL
 
 
 def test_qr_nonfinite(ctx):
@@ -128,7 +133,7 @@ def test_qr_full_size_kappa_1e8(ctx, full_size):
     say("gpu qr")
     Q, R, rc, st = run_qr(ctx, B)
     assert rc == 0 and st["reductions"] == n + 1
-    assert relnorm(R, ref["R"]) <= TOL
+    assert colerr(R, ref["R"]) <= TOL
     dq = np.linalg.norm((Q - ref["Q"]) @ ref["R"]) / np.linalg.norm(B)
     say("dQ R", dq)
     assert dq <= TOL
@@ -150,7 +155,7 @@ def test_qr_full_size_kappa_1e2(ctx):
     say("gpu qr")
     Q, R, rc, st = run_qr(ctx, B)
     assert rc == 0 and st["reductions"] == n + 1
-    assert relnorm(R, ref["R"]) <= TOL
+    assert colerr(R, ref["R"]) <= TOL
     dq = np.linalg.norm((Q - ref["Q"]) @ ref["R"]) / np.linalg.norm(B)
     loo = loss_of_orthogonality(Q)
     rre = np.linalg.norm(B - Q @ R) / np.linalg.norm(B)
@@ -175,9 +180,9 @@ def test_qr_full_size_every_tuned_shape(ctx, full_size):
             R, rc, st = ctx.qr(Bd, Qd)
             Q = host(Qd)
             dq = np.linalg.norm((Q - ref["Q"]) @ ref["R"]) / np.linalg.norm(B)
-            say("shape", dict(zip(keys, combo)), "R rel", relnorm(R, ref["R"]), "dQ R", dq)
+            say("shape", dict(zip(keys, combo)), "R colerr", colerr(R, ref["R"]), "dQ R", dq)
             assert rc == 0 and st["reductions"] == n + 1
-            assert relnorm(R, ref["R"]) <= TOL and dq <= TOL
+            assert colerr(R, ref["R"]) <= TOL and dq <= TOL
     finally:
         for k in keys:
             ctx.set_tuning(k, {binding.TUNE_FUSED_PAIR_SLOTS: 16}.get(k, 0))
@@ -192,7 +197,7 @@ def test_cgs2_comparator_parity(ctx, m, n, ce):
     R, rc, st = ctx.cgs2_qr(Bd, Qd)
     Qr, Rr, red = gs.cgs2_qr(B)
     assert rc == 0 and st["reductions"] == red == 3 * (n - 1) + 1
-    assert relnorm(R, Rr) <= TOL
+    assert colerr(R, Rr) <= TOL
     assert np.linalg.norm((host(Qd) - Qr) @ Rr) / np.linalg.norm(B) <= TOL
     assert loss_of_orthogonality(host(Qd)) <= 1e-13
 
@@ -209,10 +214,10 @@ def test_mgs_comparator_parity(ctx, m, n, ce):
     Qr, Rr, red = gs.mgs_qr(B)
     Q = host(Qd)
     assert rc == 0 and st["reductions"] == red == n * (n + 1) // 2
-    assert relnorm(R, Rr) <= (TOL if ce <= 2 else 1e-9)
+    assert colerr(R, Rr) <= (TOL if ce <= 2 else 1e-9)
     assert qr_error(B, Q, R) <= 1e-14
     if ce <= 2:
-        assert np.linalg.norm(Q - Qr) / np.sqrt(n) <= TOL
+        assert colerr(Q, Qr) <= TOL
     else:
         lo_gpu, lo_ref = loss_of_orthogonality(Q), loss_of_orthogonality(Qr)
         say("mgs LOO gpu", lo_gpu, "oracle", lo_ref)
@@ -237,11 +242,11 @@ def test_qr_hybrid_schedule_parity(ctx, m, n, ce, min_j):
         ctx.set_tolerances(1e-8, 1e-12)
         ctx.set_tuning(binding.TUNE_FUSED_MIN_J, 0)
     assert rc == 0 and st["reductions"] == ref["reductions"]
-    assert relnorm(R, ref["R"]) <= TOL
+    assert colerr(R, ref["R"]) <= TOL
     assert np.linalg.norm((Q - ref["Q"]) @ ref["R"]) / np.linalg.norm(B) <= TOL
     reff = gs.dcgs2_qr(B, tau=1.0)
     assert rcf == 0 and stf["pyth_fallbacks"] == reff["fallbacks"]
-    assert relnorm(Rf, reff["R"]) <= TOL
+    assert colerr(Rf, reff["R"]) <= TOL
 
 
 @pytest.mark.parametrize("one_pass", [True, False])
@@ -263,7 +268,7 @@ def test_qr_reduction_grid_parity(ctx, gmax, m, n, one_pass):
         ctx.set_tuning(binding.TUNE_REDUCE_GRID, 0)
         ctx.set_qr_schedule(True)
     assert rc == 0 and st["reductions"] == ref["reductions"]
-    assert relnorm(R, ref["R"]) <= TOL
+    assert colerr(R, ref["R"]) <= TOL
     assert np.linalg.norm((Q - ref["Q"]) @ ref["R"]) / np.linalg.norm(B) <= TOL
     assert np.array_equal(Q, Q2) and np.array_equal(R, R2)
 
@@ -278,7 +283,7 @@ def test_qr_one_pass_size_limits(ctx, m, n):
     ref = gs.dcgs2_qr(B)
     Q, R, rc, st = run_qr(ctx, B)
     assert rc == 0 and st["reductions"] == ref["reductions"] == n + 1
-    assert relnorm(R, ref["R"]) <= TOL
+    assert colerr(R, ref["R"]) <= TOL
     assert np.linalg.norm((Q - ref["Q"]) @ ref["R"]) / np.linalg.norm(B) <= TOL
     assert loss_of_orthogonality(Q) <= 1e-13
 
@@ -295,5 +300,5 @@ def test_qr_sixteen_wavefront_workgroups(ctx, m, n):
     finally:
         ctx.set_tuning(binding.TUNE_FUSED_WAVES, 8)
     assert rc == 0 and st["reductions"] == ref["reductions"]
-    assert relnorm(R, ref["R"]) <= TOL
+    assert colerr(R, ref["R"]) <= TOL
     assert np.linalg.norm((Q - ref["Q"]) @ ref["R"]) / np.linalg.norm(B) <= TOL
