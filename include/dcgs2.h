@@ -195,6 +195,21 @@ int dcgs2_qr_q32(dcgs2_ctx ctx, int64_t m, int32_t n, const double* B, int64_t l
 int dcgs2_arnoldi_q32(dcgs2_ctx ctx, const dcgs2_op* A, const double* r0, int32_t n,
                       float* Q, int64_t ldq, double* H_host, int32_t ldh, dcgs2_stats* st);
 
+/* dcgs2_qr for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * factorisation, kernels and results as dcgs2_qr, with every device buffer beyond
+ * B, Q and the outputs (the working vectors, reduction partials, coefficient and
+ * control blocks, R) in one fixed array of the library (about 36 MB, held by each
+ * GPU the library runs on until the process ends).  No hipMalloc, hipFree or other
+ * allocating routine is called, also not on a context's first use; kernel timing
+ * (dcgs2_profile_enable) is not recorded.  The array is shared by every call on the
+ * same GPU and keeps the last call's contents: calls that overlap on one GPU (from
+ * several threads or contexts) race and must be serialised by the caller.
+ * Limits: m <= 2,097,152 and n <= 128 (DCGS2_EINVAL beyond), otherwise the
+ * arguments, layouts, status codes and stats of dcgs2_qr. */
+int dcgs2_qr_noalloc(dcgs2_ctx ctx, int64_t m, int32_t n, const double* B, int64_t ldb,
+                     double* Q, int64_t ldq, double* R_host, int32_t ldr, dcgs2_stats* st);
+
 /* Steps j0..j1 of Alg. arnoldi (Sec. 4) from a caller-given state, for checking
  * the expansion one step at a time and for resuming it.  Step j is the matvec
  * v = A w_{j-1}, the one global reduction [Q_{1:j-2}, w_{j-1}]^T [w_{j-1}, v], the

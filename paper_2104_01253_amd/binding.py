@@ -30,7 +30,8 @@ EXPORTS = ("dcgs2_create", "dcgs2_destroy", "dcgs2_set_tolerances", "dcgs2_qr", 
            "dcgs2_mlp_set_params", "dcgs2_mlp_get_params", "dcgs2_mlp_get_grads",
            "dcgs2_mlp_forward", "dcgs2_mlp_loss_grad", "dcgs2_mlp_adam",
            "dcgs2_guess_features", "dcgs2_guess_targets", "dcgs2_guess_prolong",
-           "dcgs2_guess_guard", "mgs_qr", "dcgs2_arnoldi_steps", "dcgs2_qr_steps")
+           "dcgs2_guess_guard", "mgs_qr", "dcgs2_arnoldi_steps", "dcgs2_qr_steps",
+           "dcgs2_qr_noalloc")
 (TUNE_FUSED_WAVES, TUNE_REDUCE_GRID, TUNE_FUSED_MIN_J, TUNE_BATCH_REDUCE_ROWS,
  TUNE_FUSED_PAIR_SLOTS, TUNE_BATCH_DENSE) = 0, 1, 2, 3, 4, 5
 
@@ -108,6 +109,7 @@ def load(path: str = LIB_PATH):
     lib.dcgs2_qr_q32.argtypes = lib.dcgs2_qr.argtypes
     lib.cgs2_qr.argtypes = lib.dcgs2_qr.argtypes
     lib.mgs_qr.argtypes = lib.dcgs2_qr.argtypes
+    lib.dcgs2_qr_noalloc.argtypes = lib.dcgs2_qr.argtypes
     lib.dcgs2_set_tuning.argtypes = [c_void_p, c_int32, c_int32]
     lib.dcgs2_get_tuning.argtypes = [c_void_p, c_int32, POINTER(c_int32)]
     lib.dcgs2_arnoldi_q32.argtypes = lib.dcgs2_arnoldi.argtypes
@@ -404,6 +406,22 @@ class Context:
         rc = fn(self._h, m, n, pb, ldb, pq, ldq, R.ctypes.data_as(c_void_p), n, ctypes.byref(st))
         if rc < 0:
             raise DCGS2Error(rc, "dcgs2_qr")
+        return R, rc, st.as_dict()
+
+    def qr_noalloc(self, B, Q):
+        """dcgs2_qr through the allocation-free entry point (fixed library scratch;
+        m <= 2,097,152, n <= 128); returns (R, status, stats)."""
+        m, n = B.shape
+        pb, ldb = _colmajor_args(B, "B")
+        pq, ldq = _colmajor_args(Q, "Q")
+        if Q.shape != (m, n):
+            raise ValueError("Q must have B's shape")
+        R = np.zeros((n, n), order="F")
+        st = Stats()
+        rc = self._lib.dcgs2_qr_noalloc(self._h, m, n, pb, ldb, pq, ldq,
+                                        R.ctypes.data_as(c_void_p), n, ctypes.byref(st))
+        if rc < 0:
+            raise DCGS2Error(rc, "dcgs2_qr_noalloc")
         return R, rc, st.as_dict()
 
     def cgs2_qr(self, B, Q):

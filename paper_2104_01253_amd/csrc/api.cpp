@@ -273,8 +273,8 @@ double op_bytes(const OpDev& op) {
   return 16.0 * m;
 }
 
-// Device workspace of one expansion: the context's buffers, or views into other
-// device memory.
+// Device workspace of one expansion: the context's buffers, or views into the
+// library's fixed scratch array (dcgs2_qr_noalloc).
 struct Work {
   double *w = nullptr, *v = nullptr, *r = nullptr;     // length-m vectors
   double* P1 = nullptr;                                 // reduction partials
@@ -837,6 +837,58 @@ int dcgs2_qr_steps(dcgs2_ctx c, int64_t m, int32_t j0, int32_t j1, const double*
   CKL(launch_copy(w, c->w, m, c->stream));
   CK(hipStreamSynchronize(c->stream));
   if (rec_host && (rc = read_records(c, j0, j1, rec_host))) return rc;
+  fill_stats(st, s, c->kernels, status);
+  return status;
+}
+
+int dcgs2_qr_noalloc(dcgs2_ctx c, int64_t m, int32_t n, const double* B, int64_t ldb,
+                     double* Q, int64_t ldq, double* R_host, int32_t ldr, dcgs2_stats* st) {
+  if (!c || m < 1 || n < 1 || n > DCGS2_MAX_N || (int64_t)n > m || !B || !Q || !R_host ||
+      ldb < m || ldq < m || ldr < n)
+    return DCGS2_EINVAL;
+  if (m > NOALLOC_MAX_M || n > NOALLOC_MAX_N) return DCGS2_EINVAL;   // beyond the scratch
+  CK(hipSetDevice(c->device));
+  double* base = nullptr;
+  size_t cap = 0;
+  CK(noalloc_scratch(c->device, &base, &cap));
+  // views into the fixed scratch (the layout noalloc_scratch documents)
+  auto region = [](size_t d) { return (d + 63) / 64 * 64; };
+  Work k;
+  double* p = base;
+  k.w = p; p += region(NOALLOC_MAX_M);
+  k.r = p; p += region(NOALLOC_MAX_M);
+  k.P1 = p; p += region((size_t)REDUCE_GMAX * NOALLOC_LDP);
+  k.ldp = NOALLOC_LDP;
+  k.coef = p; p += region(NOALLOC_LDCOEF);
+  k.pend = p; p += region(NOALLOC_LDCOEF);
+  k.R = p; p += region((size_t)NOALLOC_MAX_N * NOALLOC_MAX_N);
+  k.Sprev = p; p += region(NOALLOC_MAX_N + 2);
+  k.ctrl = reinterpret_cast<Ctrl*>(p); p += region(sizeof(Ctrl) / 8 + 1);
+  if ((size_t)(p - base) > cap) return DCGS2_EDEVICE;      // layout and array disagree
+  // kernel timing records host events and is not used here
+  struct ProfOff {
+    dcgs2_ctx c; bool was;
+    ~ProfOff() { c->prof = was; }
+  } prof_off{c, c->prof};
+  c->prof = false;
+  c->kernels = 0;
+  Expansion e;
+  e.qr = true;
+  e.m = m;
+  e.Q = Q; e.q32 = 0; e.ldq = ldq; e.B = B; e.ldb = ldb;
+  e.ldh = n;
+  e.wk = k;
+  e.one_pass = c->qr_one_pass && n - 2 <= FUSED_QR_MAX_J && (double)m * 8.0 < 2147483648.0;
+  int rc;
+  if ((rc = setup_expansion(c, e, 0.0))) return rc;
+  CKL(launch_fill(k.R, (int64_t)n * n, 0.0, c->stream));
+  CKL(launch_copy(k.w, B, m, c->stream));                 // w_1 = a_1
+  Ctrl s{};
+  if ((rc = e.run(2, n, FIN_STEP, n - 1, &s))) return rc;
+  const int status = status_of(s);
+  CK(hipMemcpy2DAsync(R_host, sizeof(double) * (size_t)ldr, k.R, sizeof(double) * (size_t)n,
+                      sizeof(double) * (size_t)n, (size_t)n, hipMemcpyDeviceToHost, c->stream));
+  CK(hipStreamSynchronize(c->stream));
   fill_stats(st, s, c->kernels, status);
   return status;
 }

@@ -207,6 +207,19 @@ hipError_t launch_targets(int count, int n, int nc, const double* x, const doubl
 hipError_t launch_prolong(int count, int n, int nc, const float* y, const double* scale,
                           double gain, double* x0, hipStream_t s);
 
+// Fixed device scratch of dcgs2_qr_noalloc (kernels.hip): one array per device, sized
+// for m <= NOALLOC_MAX_M rows and n <= NOALLOC_MAX_N columns.  Layout in doubles, each
+// region starting on a 512-byte boundary: w and r (NOALLOC_MAX_M each), the reduction
+// partials (REDUCE_GMAX x NOALLOC_LDP), coef and pend (NOALLOC_LDCOEF each), R
+// (NOALLOC_MAX_N^2), S_prev (NOALLOC_MAX_N + 2) and the control block.
+constexpr int64_t NOALLOC_MAX_M = int64_t(1) << 21;
+constexpr int NOALLOC_MAX_N = 128;
+constexpr int NOALLOC_LDP = 2 * (NOALLOC_MAX_N + 2) + 8;
+constexpr int NOALLOC_LDCOEF = 2 * (DCGS2_MAX_N + 2) + 8;
+// Address of the current device's copy of the scratch array, looked up with
+// hipGetSymbolAddress on the first call for each device and cached (device < 64).
+hipError_t noalloc_scratch(int device, double** out, size_t* doubles);
+
 // Context access for the other host sources of the library: makes the context's
 // device current (allocating its workspace on first use) and returns its stream.
 int ctx_prepare(dcgs2_ctx c, hipStream_t* stream);

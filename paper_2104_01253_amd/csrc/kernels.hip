@@ -20,11 +20,26 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <mutex>
 #include <type_traits>
 #include <utility>
 
 #include "internal.h"
 
+// Fixed scratch of the allocation-free QR entry point (dcgs2_qr_noalloc): every GPU the
+// library runs on holds its own copy until the process ends.  Host code never passes
+// this name to a kernel (on the host it is only a stand-in for the symbol): it takes
+// the device address from dcgs2::noalloc_scratch.
+namespace {
+constexpr size_t noalloc_region(size_t doubles) { return (doubles + 63) / 64 * 64; }
+constexpr size_t NOALLOC_DOUBLES =
+    2 * noalloc_region(dcgs2::NOALLOC_MAX_M) +
+    noalloc_region((size_t)dcgs2::REDUCE_GMAX * dcgs2::NOALLOC_LDP) +
+    2 * noalloc_region(dcgs2::NOALLOC_LDCOEF) +
+    noalloc_region((size_t)dcgs2::NOALLOC_MAX_N * dcgs2::NOALLOC_MAX_N) +
+    noalloc_region(dcgs2::NOALLOC_MAX_N + 2) + noalloc_region(sizeof(dcgs2::Ctrl) / 8 + 1);
+}  // namespace
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
 
 namespace dcgs2 {
 namespace {
@@ -516,6 +531,28 @@ void reduce_grid(int64_t m, int gmax, int* G) {
   if (g > (gmax > 0 ? gmax : 256)) g = gmax > 0 ? gmax : 256;
   if (g > REDUCE_GMAX) g = REDUCE_GMAX;
   *G = (int)g;
+}
+
+hipError_t noalloc_scratch(int device, double** out, size_t* doubles) {
+  constexpr int MAXDEV = 64;
+  static std::mutex mu;
+  static double* addr[MAXDEV] = {};
+  if (device < 0 || device >= MAXDEV) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;   // the caller makes it current
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[device] = static_cast<double*>(p);
+  }
+  *out = addr[device];
+  *doubles = NOALLOC_DOUBLES;
+  return hipSuccess;
 }
 
 hipError_t launch_init_ctrl(Ctrl* ctrl, double tau, double eta, double thresh, hipStream_t s,

@@ -210,3 +210,15 @@ def test_steps_argument_validation(ctx):
     assert qr(a11=None) == E                     # S
     assert qr(a12=float("inf")) == E             # rho
 
+
+def test_qr_noalloc_argument_validation(ctx):
+    """The allocation-free QR rejects sizes beyond its fixed scratch before any device
+    call, as well as everything dcgs2_qr rejects."""
+    lib, h = ctx
+    E = binding.EINVAL
+    f = lib.dcgs2_qr_noalloc
+    assert f(h, 2 ** 21 + 1, 10, FAKE, 2 ** 21 + 1, FAKE, 2 ** 21 + 1, FAKE, 10, None) == E
+    assert f(h, 1000, 129, FAKE, 1000, FAKE, 1000, FAKE, 129, None) == E
+    assert f(h, 10, 20, FAKE, 10, FAKE, 10, FAKE, 20, None) == E                  # n > m
+    assert f(h, 100, 10, FAKE, 99, FAKE, 100, FAKE, 10, None) == E                # ldb < m
+    assert f(None, 100, 10, FAKE, 100, FAKE, 100, FAKE, 10, None) == E
