@@ -342,9 +342,10 @@ int dcgs2_profile_read(dcgs2_ctx ctx, dcgs2_kernel_stat* out, int32_t max_entrie
  *  v0          : device, the count start vectors concatenated in instance order.
  *  eig_re_host, eig_im_host : host, count x nev (instance-major).
  *  info_host   : host, count records (status per instance).
- * An instance whose Pythagorean guard fails stops with DCGS2_NOT_CONVERGED and
- * st.pyth_fallbacks = 1 (krylov_schur_eigs runs the fallback).  Returns DCGS2_OK
- * when every instance converged, DCGS2_NOT_CONVERGED otherwise, or an error. */
+ * When an instance's Pythagorean guard fails at a step, that step's explicit-norm
+ * fallback and the rest of the instance's cycle run through the single-instance
+ * schedule, as in krylov_schur_eigs (st.pyth_fallbacks counts them).  Returns
+ * DCGS2_OK when every instance converged, DCGS2_NOT_CONVERGED otherwise, or an error. */
 typedef struct {
   int32_t nx, ny;
   double c0, cxm, cxp, cym, cyp;
@@ -354,6 +355,59 @@ int krylov_schur_batched(dcgs2_ctx ctx, int32_t count, const dcgs2_stencil2d* op
                          int32_t nev, int32_t ncv, int32_t keep, double tol,
                          int32_t max_restarts, const double* v0, double* eig_re_host,
                          double* eig_im_host, dcgs2_ks_info* info_host, int32_t use_graph);
+
+/* Batched DCGS2 Arnoldi (Alg. arnoldi, Sec. 4) over `count` independent 2-D
+ * convection-diffusion operators (5-point stencils, grids of different sizes), each
+ * with its own number of steps n_b: every expansion step is ONE launch of each step
+ * kernel covering all instances (workgroups mapped to instances by prefix sums, a
+ * per-instance grid reduction and finaliser), an instance is idle after its own n_b
+ * steps, and each instance's last column is finished by CGS2 (two reductions) in
+ * launches shared by all.  The kernels and readings are those of
+ * krylov_schur_batched's expansion cycles; a failed Pythagorean guard runs the
+ * explicit-norm fallback as dcgs2_arnoldi does.
+ *  ops        : host, count descriptors (m_b = nx*ny >= 2).
+ *  n          : host, count step counts, 1 <= n_b <= min(m_b - 1, DCGS2_MAX_N).
+ *  r0         : device, the count start vectors concatenated (instance b at element
+ *               offset sum_{i<b} m_i); read only.
+ *  Q          : device output, 16-byte aligned: instance b's basis is m_b x (n_b+1),
+ *               column-major with leading dimension ld_b = m_b rounded up to a
+ *               multiple of 64, at element offset sum_{i<b} ld_i (n_i + 1).
+ *  H_host     : host output, the count (n_b+1) x n_b Hessenberg matrices, each
+ *               column-major with leading dimension n_b+1, concatenated (instance b
+ *               at offset sum_{i<b} (n_i+1) n_i).
+ *  status_host: host, count statuses (optional): DCGS2_OK, DCGS2_BREAKDOWN (the
+ *               first st.breakdown_step columns valid) or DCGS2_NONFINITE.
+ *  st_host    : host, count statistics records (optional).
+ * Returns DCGS2_NONFINITE if any instance saw a non-finite value, else
+ * DCGS2_BREAKDOWN if any broke down, else DCGS2_OK; or an error. */
+int dcgs2_arnoldi_batched(dcgs2_ctx ctx, int32_t count, const dcgs2_stencil2d* ops,
+                          const int32_t* n, const double* r0, double* Q, double* H_host,
+                          int32_t* status_host, dcgs2_stats* st_host);
+
+/* Batched restarted GMRES (Sec. 1) on the DCGS2 basis over `count` independent 2-D
+ * convection-diffusion systems A_b x_b = b_b (5-point stencils, grids of different
+ * sizes), each with its own restart length.  Every DCGS2 step of a restart cycle is
+ * ONE launch of each step kernel covering all instances (the batched expansion of
+ * dcgs2_arnoldi_batched, with each instance's Givens rotations and least-squares
+ * estimate in its finaliser); a cycle's launches are captured once into a HIP graph
+ * and replayed.  Between cycles one launch forms every residual b - A x, one grid
+ * reduction per instance its norm, and one launch adds Q_k y to every iterate (y from
+ * a back substitution on the host).  Each instance follows gmres_solve's readings:
+ * it stops when ||b - A x|| / ||b|| <= rtol (true residual) or after max_iters steps,
+ * a cycle ends early once its least-squares residual reaches rtol ||b||, b_b = 0 gives
+ * x_b = 0.
+ *  ops       : host, count descriptors (m_b = nx*ny >= 2).
+ *  restart   : host, count restart lengths, 1 <= restart_b <= min(m_b-1, DCGS2_MAX_N).
+ *  b         : device, the right-hand sides concatenated (instance b at element offset
+ *              sum_{i<b} m_i); read only.
+ *  x         : device, same layout; in: x0, out: the solutions.
+ *  info_host : host, count records (iterations, cycles, status, residuals).
+ * rtol > 0, max_iters >= 0.  Returns DCGS2_OK when every instance converged, else
+ * DCGS2_NONFINITE if any instance saw a non-finite value, else the first other
+ * status in instance order (DCGS2_NOT_CONVERGED, DCGS2_BREAKDOWN); or an error. */
+int gmres_batched(dcgs2_ctx ctx, int32_t count, const dcgs2_stencil2d* ops,
+                  const int32_t* restart, const double* b, double* x, double rtol,
+                  int32_t max_iters, dcgs2_gmres_info* info_host);
 
 /* ------------------------------------------------------------------------------------
  * Learned initial guess for GMRES (x0 of the minimisation over x0 + K_k, Sec. 1).

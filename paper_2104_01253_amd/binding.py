@@ -31,7 +31,8 @@ EXPORTS = ("dcgs2_create", "dcgs2_destroy", "dcgs2_set_tolerances", "dcgs2_qr", 
            "dcgs2_mlp_forward", "dcgs2_mlp_loss_grad", "dcgs2_mlp_adam",
            "dcgs2_guess_features", "dcgs2_guess_targets", "dcgs2_guess_prolong",
            "dcgs2_guess_guard", "mgs_qr", "dcgs2_arnoldi_steps", "dcgs2_qr_steps",
-           "dcgs2_qr_noalloc")
+           "dcgs2_qr_noalloc", "dcgs2_arnoldi_batched",
+           "gmres_batched")
 (TUNE_FUSED_WAVES, TUNE_REDUCE_GRID, TUNE_FUSED_MIN_J, TUNE_BATCH_REDUCE_ROWS,
  TUNE_FUSED_PAIR_SLOTS, TUNE_BATCH_DENSE) = 0, 1, 2, 3, 4, 5
 
@@ -97,6 +98,11 @@ def load(path: str = LIB_PATH):
                                          c_int32, c_double, c_int32, c_void_p, c_void_p,
                                          c_void_p, POINTER(KsInfo), c_int32]
     lib.dcgs2_apply.argtypes = [c_void_p, POINTER(Op), c_void_p, c_void_p]
+    lib.gmres_batched.argtypes = [c_void_p, c_int32, POINTER(Stencil2d), c_void_p, c_void_p,
+                                  c_void_p, c_double, c_int32, POINTER(GmresInfo)]
+    lib.dcgs2_arnoldi_batched.argtypes = [c_void_p, c_int32, POINTER(Stencil2d), c_void_p,
+                                          c_void_p, c_void_p, c_void_p, c_void_p,
+                                          POINTER(Stats)]
     lib.dcgs2_arnoldi_steps.argtypes = [c_void_p, POINTER(Op), c_int32, c_int32, c_void_p,
                                         c_int64, c_void_p, c_void_p, c_void_p, c_int32, c_double,
                                         c_void_p, POINTER(Stats)]
@@ -352,6 +358,16 @@ def csr_op(rowptr, colind, val) -> Op:
     return op
 
 
+def batched_basis_offsets(ops, n):
+    """Element offsets of the instance bases in dcgs2_arnoldi_batched's Q, and its size."""
+    offs, total = [], 0
+    for o, k in zip(ops, n):
+        ld = ((o.nx * o.ny + 63) // 64) * 64
+        offs.append(total)
+        total += ld * (int(k) + 1)
+    return offs, total
+
+
 # ---- context ----------------------------------------------------------------------
 class Context:
     """A libdcgs2 context bound to one device and one HIP stream."""
@@ -421,7 +437,8 @@ class Context:
         rc = self._lib.dcgs2_qr_noalloc(self._h, m, n, pb, ldb, pq, ldq,
                                         R.ctypes.data_as(c_void_p), n, ctypes.byref(st))
         if rc < 0:
-            raise DCGS2Error(rc, "dcgs2_qr_noalloc")
+            raise DCGS2Error(rc, "dcgs2_qr_noalloc", "dcgs2_arnoldi_batched",
+           "gmres_batched")
         return R, rc, st.as_dict()
 
     def cgs2_qr(self, B, Q):
@@ -542,6 +559,62 @@ class Context:
         out = {k: getattr(info, k) for k, _ in KsInfo._fields_ if k != "st"}
         out["stats"] = info.st.as_dict()
         return re + 1j * im, rc, out
+
+    def gmres_batched(self, ops, restart, b, x, rtol=1e-8, max_iters=100000):
+        """Batched GMRES over len(ops) stencil systems; b, x: device float64, concatenated
+        (x holds x0 on entry, the solutions on return); restart: per instance.  Returns
+        (status, list of per-instance info dicts)."""
+        count = len(ops)
+        arr = (Stencil2d * count)(*ops)
+        rs = np.ascontiguousarray(restart, dtype=np.int32)
+        total = int(sum(o.nx * o.ny for o in ops))
+        pb = _vec_ptr(b, "b", total)
+        px = _vec_ptr(x, "x", total)
+        infos = (GmresInfo * count)()
+        rc = self._lib.gmres_batched(self._h, count, arr, rs.ctypes.data_as(c_void_p), pb, px,
+                                     rtol, max_iters, infos)
+        if rc < 0:
+            raise DCGS2Error(rc, "gmres_batched")
+        out = []
+        for inf in infos:
+            d = {k: getattr(inf, k) for k, _ in GmresInfo._fields_ if k not in ("st", "pad")}
+            d["stats"] = inf.st.as_dict()
+            out.append(d)
+        return rc, out
+
+    def arnoldi_batched(self, ops, n, r0, Q=None):
+        """Batched DCGS2 Arnoldi: ops (Stencil2d list), n (steps per instance), r0 (device,
+        concatenated start vectors).  Q: device float64 buffer of
+        batched_basis_size(ops, n) elements (allocated when None).  Returns
+        (bases, H list, status, per-instance statuses, stats list); bases[b] is an
+        m_b x (n_b+1) column-major view into Q."""
+        import torch
+        count = len(ops)
+        arr = (Stencil2d * count)(*ops)
+        nn = np.ascontiguousarray(n, dtype=np.int32)
+        ms = [o.nx * o.ny for o in ops]
+        pr = _vec_ptr(r0, "r0", int(sum(ms)))
+        offs, total = batched_basis_offsets(ops, n)
+        if Q is None:
+            Q = torch.empty(total, dtype=torch.float64, device="cuda")
+        if Q.dtype != torch.float64 or not Q.is_cuda or Q.numel() < total or not Q.is_contiguous():
+            raise ValueError("Q must be a contiguous float64 device buffer of the batched size")
+        hsz = [(int(k) + 1) * int(k) for k in nn]
+        H = np.zeros(int(sum(hsz)))
+        stat = np.zeros(count, dtype=np.int32)
+        sts = (Stats * count)()
+        rc = self._lib.dcgs2_arnoldi_batched(self._h, count, arr, nn.ctypes.data_as(c_void_p), pr,
+                                             Q.data_ptr(), H.ctypes.data_as(c_void_p),
+                                             stat.ctypes.data_as(c_void_p), sts)
+        if rc < 0:
+            raise DCGS2Error(rc, "dcgs2_arnoldi_batched")
+        bases, Hs, h0 = [], [], 0
+        for b, (m, k) in enumerate(zip(ms, nn)):
+            ld = ((m + 63) // 64) * 64
+            bases.append(Q[offs[b]:offs[b] + ld * (k + 1)].view(int(k) + 1, ld).t()[:m])
+            Hs.append(H[h0:h0 + hsz[b]].reshape((int(k) + 1, int(k)), order="F"))
+            h0 += hsz[b]
+        return bases, Hs, rc, stat, [s.as_dict() for s in sts]
 
     def krylov_schur_batched(self, ops, v0, nev=10, ncv=60, keep=20, tol=1e-8,
                              max_restarts=500, use_graph=True):

@@ -279,6 +279,8 @@ struct Work {
   double *w = nullptr, *v = nullptr, *r = nullptr;     // length-m vectors
   double* P1 = nullptr;                                 // reduction partials
   int ldp = 0;
+  int G = 0;                                            // reduction workgroups (0: sized by m)
+  int ldc = 0;                                          // stride of the coefficient block
   double *coef = nullptr, *pend = nullptr;
   double *H = nullptr, *K = nullptr, *Rg = nullptr, *R = nullptr;
   double *Sprev = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
@@ -289,7 +291,7 @@ struct Work {
 Work ctx_work(dcgs2_ctx c) {
   Work k;
   k.w = c->w; k.v = c->v; k.r = c->r;
-  k.P1 = c->P1; k.ldp = LDP;
+  k.P1 = c->P1; k.ldp = LDP; k.ldc = LDC;
   k.coef = c->coef; k.pend = c->pend;
   k.H = c->H; k.K = c->K; k.Rg = c->Rg; k.R = c->R;
   k.Sprev = c->Sprev; k.cs = c->cs; k.sn = c->sn; k.g = c->g;
@@ -335,7 +337,7 @@ struct Expansion {
 
   FinArgs fin(int kind, int j, int J) const {
     FinArgs f{};
-    f.kind = kind; f.qr = qr; f.j = j; f.J = J; f.gmres = gmres; f.ldc = LDC;
+    f.kind = kind; f.qr = qr; f.j = j; f.J = J; f.gmres = gmres; f.ldc = wk.ldc;
     f.ctrl = wk.ctrl; f.coef = wk.coef; f.pend = wk.pend;
     f.H = wk.H; f.K = wk.K; f.ldh = ldh;
     f.R = wk.R; f.ldr = ldh; f.Sprev = wk.Sprev;
@@ -356,7 +358,7 @@ struct Expansion {
     KL(K_REDUCE, qb * J + 2 * vm,
        launch_reduce(Q, q32, ldq, J, wk.w, ycol(j), m, gr, fin(kind, j, J), s, mid_));
     KL(K_UPDATE, qb * (J + 1) + 3 * vm,
-       launch_update(Q, q32, ldq, J, wk.w, ycol(j), nullptr, m, wk.coef, LDC, !qr, 0, wk.ctrl, s));
+       launch_update(Q, q32, ldq, J, wk.w, ycol(j), nullptr, m, wk.coef, wk.ldc, !qr, 0, wk.ctrl, s));
     return DCGS2_OK;
   }
   int enqueue_fallback(int j) {
@@ -367,7 +369,7 @@ struct Expansion {
     KL(K_PROJNORM, qb * J + 2 * vm,
        launch_project_norm(Q, q32, ldq, J, wk.w, wk.r, m, gr, fin(FIN_FALLBACK, j, J), s, mid_));
     KL(K_UPDATE, qb * (J + 1) + 4 * vm,
-       launch_update(Q, q32, ldq, J, wk.w, ycol(j), wk.r, m, wk.coef, LDC, !qr, 1, wk.ctrl, s));
+       launch_update(Q, q32, ldq, J, wk.w, ycol(j), wk.r, m, wk.coef, wk.ldc, !qr, 1, wk.ctrl, s));
     return DCGS2_OK;
   }
   // CGS2 finish of the last column: J final columns already in Q.
@@ -384,7 +386,7 @@ struct Expansion {
     KL(K_PROJNORM, qb * J + 2 * vm,
        launch_project_norm(Q, q32, ldq, J, wk.w, wk.r, m, gr, fin(FIN_LAST2, jvirt, J), s, mid_));
     KL(K_SCALE, vm + qb,
-       launch_scale_col(Q, q32, ldq, J, wk.r, m, wk.coef, LDC, wk.ctrl, s));
+       launch_scale_col(Q, q32, ldq, J, wk.r, m, wk.coef, wk.ldc, wk.ctrl, s));
     return DCGS2_OK;
   }
   // One-pass QR schedule for steps j0..j_to: reduce(j0), then fused(j) =
@@ -402,7 +404,7 @@ struct Expansion {
       const bool last = (j == j_to);
       if (last && J_last < 0) {
         KL(K_UPDATE, qb * (J + 1) + 3 * vm,
-           launch_update(Q, q32, ldq, J, wk.w, ycol(j), nullptr, m, wk.coef, LDC, 0, 0, wk.ctrl,
+           launch_update(Q, q32, ldq, J, wk.w, ycol(j), nullptr, m, wk.coef, wk.ldc, 0, 0, wk.ctrl,
                          s));
         break;
       }
@@ -410,7 +412,7 @@ struct Expansion {
       if (J < c->tune_fused_min_j) {
         // a short basis: the separate passes stream better than the tiled fused pass
         KL(K_UPDATE, qb * (J + 1) + 3 * vm,
-           launch_update(Q, q32, ldq, J, wk.w, ycol(j), nullptr, m, wk.coef, LDC, 0, 0, wk.ctrl,
+           launch_update(Q, q32, ldq, J, wk.w, ycol(j), nullptr, m, wk.coef, wk.ldc, 0, 0, wk.ctrl,
                          s));
         KL(K_REDUCE, qb * (J + 1) + (last ? 1 : 2) * vm,
            launch_reduce(Q, q32, ldq, J + 1, wk.w, last ? nullptr : ycol(j + 1), m, gr, f, s, mid_));
@@ -419,7 +421,7 @@ struct Expansion {
       // bytes: Q_{0..J-1}, w, a_j, a_{j+1} read; q, w written (grid sized inside)
       KL(K_FUSED, qb * (J + 1) + vm * (last ? 3 : 4),
          launch_fused_qr(Q, q32, ldq, J, wk.w, ycol(j), last ? nullptr : ycol(j + 1), m,
-                         wk.coef, LDC, last ? 1 : 0, c->tune_fused_waves,
+                         wk.coef, wk.ldc, last ? 1 : 0, c->tune_fused_waves,
                          c->tune_reduce_gmax, c->tune_pair_max_ns, gr, f, s, mid_));
     }
     if (J_last >= 0) {
@@ -427,17 +429,20 @@ struct Expansion {
          launch_project_norm(Q, q32, ldq, J_last, wk.w, wk.r, m, gr,
                              fin(FIN_LAST2, j_to + 1, J_last), s, mid_));
       KL(K_SCALE, vm + qb,
-         launch_scale_col(Q, q32, ldq, J_last, wk.r, m, wk.coef, LDC, wk.ctrl, s));
+         launch_scale_col(Q, q32, ldq, J_last, wk.r, m, wk.coef, wk.ldc, wk.ctrl, s));
     }
     return DCGS2_OK;
   }
   // Steps j_from..j_to (the first one of kind first_kind), then the last-column
   // finish with J_last columns when J_last >= 0.  Resolves guard fallbacks.
-  int run(int j_from, int j_to, int first_kind, int J_last, Ctrl* out) {
+  // fallback_first: step j_from stopped at its Pythagorean guard (the control block
+  // says so); its explicit-norm fallback is enqueued first.
+  int run(int j_from, int j_to, int first_kind, int J_last, Ctrl* out,
+          bool fallback_first = false) {
     int rc;
     int j0 = j_from;
     int kind0 = first_kind;
-    bool pending_fallback = false;
+    bool pending_fallback = fallback_first;
     for (;;) {
       if (pending_fallback) {
         CKL(launch_set_state(wk.ctrl, ST_RUNNING, c->stream));
@@ -464,7 +469,10 @@ struct Expansion {
 int setup_expansion(dcgs2_ctx c, Expansion& e, double thresh, double rho = 0.0) {
   e.c = c;
   if (!e.wk.ctrl) e.wk = ctx_work(c);
-  reduce_grid(e.m, c->tune_reduce_gmax, &e.gr.G);
+  if (e.wk.G > 0)
+    e.gr.G = e.wk.G;
+  else
+    reduce_grid(e.m, c->tune_reduce_gmax, &e.gr.G);
   e.gr.P1 = e.wk.P1;
   e.gr.ldp = e.wk.ldp;
   CK(launch_init_ctrl(e.wk.ctrl, c->tau, c->eta, thresh, c->stream, rho));
@@ -859,6 +867,7 @@ int dcgs2_qr_noalloc(dcgs2_ctx c, int64_t m, int32_t n, const double* B, int64_t
   k.r = p; p += region(NOALLOC_MAX_M);
   k.P1 = p; p += region((size_t)REDUCE_GMAX * NOALLOC_LDP);
   k.ldp = NOALLOC_LDP;
+  k.ldc = LDC;
   k.coef = p; p += region(NOALLOC_LDCOEF);
   k.pend = p; p += region(NOALLOC_LDCOEF);
   k.R = p; p += region((size_t)NOALLOC_MAX_N * NOALLOC_MAX_N);
@@ -1222,6 +1231,7 @@ struct BatchedState {
   double *H = nullptr, *K = nullptr, *Z = nullptr, *P1 = nullptr;
   double *resid = nullptr, *ere = nullptr, *eim = nullptr;   // dense results on the GPU
   int* ires = nullptr;
+  double* gm = nullptr;          // batched GMRES: Rg, cs, sn, g and y of every instance
   Ctrl* ctrl = nullptr;
   hipStream_t s = nullptr;
   std::vector<std::pair<int, hipGraphExec_t>> graphs;
@@ -1230,7 +1240,7 @@ struct BatchedState {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
     for (auto& g : graph_defs) (void)hipGraphDestroy(g);
     void* bufs[] = {d_tab, d_pre_rows, d_pre_red, Qa, Qb, vec, coef, pend, H, K, Z, P1, ctrl,
-                    resid, ere, eim, ires};
+                    resid, ere, eim, ires, gm};
     for (void* b : bufs) if (b) (void)hipFree(b);
     if (s) (void)hipStreamDestroy(s);
   }
@@ -1286,6 +1296,40 @@ int batched_run_cycle(BatchedState& B, int jmin, double tau, double eta, bool us
 
 namespace {
 
+// Explicit-norm fallback of instance b of a batched cycle whose Pythagorean guard
+// failed at step ctrl->stop_step (the reading of Sec. 3 that the single-instance
+// solver and the oracle follow): that step's fallback, the instance's remaining steps
+// and its last-column finish run through the single-instance schedule on the
+// instance's own buffers (on the context's stream), and *out receives its control
+// block.  The batched launches of the cycle skipped the instance from that step on.
+int batched_fallback(dcgs2_ctx c, const BatchedState& B, int b, Ctrl* out) {
+  const dcgs2::BInst& I = B.tab[b];
+  Expansion e;
+  e.c = c;
+  e.qr = false;
+  e.m = I.m;
+  e.Q = I.Q; e.q32 = 0; e.ldq = I.ldq;
+  OpDev op{};
+  op.kind = DCGS2_OP_STENCIL5;
+  op.m = I.m;
+  op.nx = I.nx; op.ny = I.ny; op.nz = 1;
+  op.c0 = I.c0; op.cxm = I.cxm; op.cxp = I.cxp; op.cym = I.cym; op.cyp = I.cyp;
+  e.op = op;
+  e.ldh = B.ld;
+  Work k;
+  k.w = I.w; k.v = I.v; k.r = I.r;
+  k.P1 = I.P1; k.ldp = B.ldp; k.G = I.G; k.ldc = B.ldc;
+  k.coef = I.coef; k.pend = I.pend; k.H = I.H; k.K = I.K;
+  k.ctrl = I.ctrl;
+  if (I.gmres) {
+    k.Rg = I.Rg; k.cs = I.cs; k.sn = I.sn; k.g = I.g;
+    e.gmres = true;
+  }
+  e.wk = k;
+  e.gr.P1 = k.P1; e.gr.ldp = k.ldp; e.gr.G = k.G;
+  return e.run(out->stop_step, I.n + 1, FIN_STEP, I.n, out, true);
+}
+
 // One group of instances of the batched solver: its own stream, buffers, table
 // and graphs.  Two groups alternate so that the host dense work of one overlaps
 // the device cycle of the other.
@@ -1306,8 +1350,14 @@ struct BatchedGroup {
   std::chrono::steady_clock::time_point t_cycle;
 };
 
+// nsteps (indexed like ops; nullptr: ncv for every instance) gives each instance's
+// step count n_b <= ncv.  Qext, when given, holds the bases (instance b at element
+// offset sum of pad_ld(m_i) (n_i + 1) over the instances before it, leading dimension
+// pad_ld(m_b)); otherwise the group allocates two bases of ncv + 1 columns (the
+// Krylov-Schur truncation target).
 int group_setup(dcgs2_ctx c, BatchedGroup& g, const dcgs2_stencil2d* ops, const double* v0,
-                const std::vector<int64_t>& v0off, int ncv) {
+                const std::vector<int64_t>& v0off, int ncv, const int32_t* nsteps = nullptr,
+                double* Qext = nullptr, bool two_bases = true) {
   BatchedState& B = g.B;
   const int count = (int)g.gid.size();
   B.count = count;
@@ -1327,7 +1377,7 @@ int group_setup(dcgs2_ctx c, BatchedGroup& g, const dcgs2_stencil2d* ops, const 
     const int64_t mb = (int64_t)o.nx * o.ny;
     ldq[b] = pad_ld(mb);
     qoff[b] = qtot;
-    qtot += ldq[b] * (p + 1);
+    qtot += ldq[b] * ((nsteps ? nsteps[g.gid[b]] : p) + 1);
     voff[b] = vtot;
     vtot += 3 * ldq[b];
     const int64_t gg = ((mb + 1) / 2 + c->tune_batch_units - 1) / c->tune_batch_units;
@@ -1340,8 +1390,10 @@ int group_setup(dcgs2_ctx c, BatchedGroup& g, const dcgs2_stencil2d* ops, const 
   B.nb_rows = B.pre_rows[count];
   B.nb_red = B.pre_red[count];
   int rc;
-  if ((rc = dalloc((void**)&B.Qa, sizeof(double) * qtot))) return rc;
-  if ((rc = dalloc((void**)&B.Qb, sizeof(double) * qtot))) return rc;
+  if (!Qext) {
+    if ((rc = dalloc((void**)&B.Qa, sizeof(double) * qtot))) return rc;
+    if (two_bases && (rc = dalloc((void**)&B.Qb, sizeof(double) * qtot))) return rc;
+  }
   if ((rc = dalloc((void**)&B.vec, sizeof(double) * vtot))) return rc;
   if ((rc = dalloc((void**)&B.coef, sizeof(double) * (size_t)count * (2 * B.ldc + 8)))) return rc;
   if ((rc = dalloc((void**)&B.pend, sizeof(double) * (size_t)count * (2 * B.ldc + 8)))) return rc;
@@ -1361,8 +1413,8 @@ int group_setup(dcgs2_ctx c, BatchedGroup& g, const dcgs2_stencil2d* ops, const 
     std::memset(&I, 0, sizeof(I));
     I.m = (int64_t)o.nx * o.ny;
     I.ldq = ldq[b];
-    I.Q = B.Qa + qoff[b];
-    I.Qn = B.Qb + qoff[b];
+    I.Q = (Qext ? Qext : B.Qa) + qoff[b];
+    I.Qn = B.Qb ? B.Qb + qoff[b] : nullptr;
     I.w = B.vec + voff[b];
     I.v = I.w + ldq[b];
     I.r = I.v + ldq[b];
@@ -1380,6 +1432,7 @@ int group_setup(dcgs2_ctx c, BatchedGroup& g, const dcgs2_stencil2d* ops, const 
     I.first_j = 2;
     I.restart = 0;
     I.active = 1;
+    I.n = nsteps ? nsteps[g.gid[b]] : p;
     CK(hipMemcpyAsync(I.w, v0 + v0off[g.gid[b]], sizeof(double) * I.m, hipMemcpyDeviceToDevice,
                       B.s));
   }
@@ -1449,6 +1502,20 @@ int group_step(dcgs2_ctx c, BatchedGroup& g, int nev, int keep, double tol, int 
     c->acc[K_BATCH_CYCLE].ms +=
         std::chrono::duration<double, std::milli>(clk::now() - g.t_cycle).count();
   }
+  // Pythagorean-guard failures of this cycle: resolved instance by instance, after
+  // which their projected matrices are read again and their dense work runs on host
+  // threads (also in a group whose dense work otherwise runs on the GPU)
+  std::vector<char> repaired(count, 0);
+  for (int b = 0; b < count; ++b) {
+    if (!B.tab[b].active || g.hctrl[b].state != ST_FALLBACK) continue;
+    int rc = batched_fallback(c, B, b, &g.hctrl[b]);
+    if (rc) return rc;
+    repaired[b] = 1;
+    if (g.Hh.size() < (size_t)count * ld * ld) g.Hh.resize((size_t)count * ld * ld);
+    if (g.Zh.size() < (size_t)count * p * p) g.Zh.resize((size_t)count * p * p);
+    CK(hipMemcpy(g.Hh.data() + (size_t)b * ld * ld, B.tab[b].H, sizeof(double) * ld * ld,
+                 hipMemcpyDeviceToHost));
+  }
   const clk::time_point t_host = clk::now();
   const double CUT_GAP = BATCH_CUT_GAP;
   std::vector<std::thread> pool;
@@ -1457,7 +1524,7 @@ int group_step(dcgs2_ctx c, BatchedGroup& g, int nev, int keep, double tol, int 
     std::vector<double> T((size_t)p * p), Zm((size_t)p * p), ere(p), eim(p);
     for (int b = next++; b < count; b = next++) {
       dcgs2::BInst& I = B.tab[b];
-      if (!I.active) continue;
+      if (!I.active || (g.device_dense && !repaired[b])) continue;
       const int gb = g.gid[b];
       dcgs2_ks_info& inf = infos[gb];
       const Ctrl& hc = g.hctrl[b];
@@ -1466,11 +1533,12 @@ int group_step(dcgs2_ctx c, BatchedGroup& g, int nev, int keep, double tol, int 
       if (hc.state != ST_RUNNING) {
         inf.status = hc.state == ST_BREAKDOWN ? DCGS2_BREAKDOWN
                      : hc.state == ST_NONFINITE ? DCGS2_NONFINITE : DCGS2_NOT_CONVERGED;
-        if (hc.state == ST_FALLBACK) inf.st.pyth_fallbacks += 1;
+        inf.st.pyth_fallbacks += hc.fallbacks;
         inf.st.breakdown_step = hc.k;
         I.active = 0;
         continue;
       }
+      inf.st.pyth_fallbacks += hc.fallbacks;
       const double* Hb = g.Hh.data() + (size_t)b * ld * ld;
       const double h = Hb[(size_t)(p - 1) * ld + p];
       for (int jj = 0; jj < p; ++jj)
@@ -1517,7 +1585,7 @@ int group_step(dcgs2_ctx c, BatchedGroup& g, int nev, int keep, double tol, int 
   auto settle = [&]() {
     for (int b = 0; b < count; ++b) {
       dcgs2::BInst& I = B.tab[b];
-      if (!I.active) continue;
+      if (!I.active || repaired[b]) continue;
       const int gb = g.gid[b];
       dcgs2_ks_info& inf = infos[gb];
       const Ctrl& hc = g.hctrl[b];
@@ -1526,7 +1594,7 @@ int group_step(dcgs2_ctx c, BatchedGroup& g, int nev, int keep, double tol, int 
       if (hc.state != ST_RUNNING) {
         inf.status = hc.state == ST_BREAKDOWN ? DCGS2_BREAKDOWN
                      : hc.state == ST_NONFINITE ? DCGS2_NONFINITE : DCGS2_NOT_CONVERGED;
-        if (hc.state == ST_FALLBACK) inf.st.pyth_fallbacks += 1;
+        inf.st.pyth_fallbacks += hc.fallbacks;
         inf.st.breakdown_step = hc.k;
         I.active = 0;
         continue;
@@ -1554,9 +1622,10 @@ int group_step(dcgs2_ctx c, BatchedGroup& g, int nev, int keep, double tol, int 
       inf.matvecs += p - k;
     }
   };
-  if (g.device_dense) {
-    settle();
-  } else {
+  bool any_repaired = false;
+  for (int b = 0; b < count; ++b) any_repaired = any_repaired || repaired[b];
+  if (g.device_dense) settle();
+  if (!g.device_dense || any_repaired) {
     for (int t = 0; t < nthreads; ++t) pool.emplace_back(worker);
     for (auto& t : pool) t.join();
   }
@@ -1580,6 +1649,14 @@ int group_step(dcgs2_ctx c, BatchedGroup& g, int nev, int keep, double tol, int 
                       B.s));
     CK(hipMemcpyAsync(B.H, g.Hh.data(), sizeof(double) * g.Hh.size(), hipMemcpyHostToDevice,
                       B.s));
+  } else {                                // except for instances repaired on the host
+    for (int b = 0; b < count; ++b) {
+      if (!repaired[b] || !B.tab[b].active || !B.tab[b].truncate) continue;
+      CK(hipMemcpyAsync(B.tab[b].Z, g.Zh.data() + (size_t)b * p * p, sizeof(double) * p * p,
+                        hipMemcpyHostToDevice, B.s));
+      CK(hipMemcpyAsync(B.tab[b].H, g.Hh.data() + (size_t)b * ld * ld, sizeof(double) * ld * ld,
+                        hipMemcpyHostToDevice, B.s));
+    }
   }
   CK(launch_fill(B.K, (int64_t)count * ld * ld, 0.0, B.s));
   g.tab_trunc = B.tab;
@@ -1669,3 +1746,233 @@ extern "C" int krylov_schur_batched(dcgs2_ctx c, int32_t count, const dcgs2_sten
   }
   return overall;
 }
+
+extern "C" int dcgs2_arnoldi_batched(dcgs2_ctx c, int32_t count, const dcgs2_stencil2d* ops,
+                                     const int32_t* n, const double* r0, double* Q,
+                                     double* H_host, int32_t* status_host,
+                                     dcgs2_stats* st_host) {
+  if (!c || count < 1 || count > 65536 || !ops || !n || !r0 || !Q || !H_host ||
+      (reinterpret_cast<uintptr_t>(Q) & 15u) != 0)
+    return DCGS2_EINVAL;
+  int nmax = 0;
+  for (int b = 0; b < count; ++b) {
+    const int64_t mb = (int64_t)ops[b].nx * ops[b].ny;
+    if (ops[b].nx < 1 || ops[b].ny < 1 || mb < 2 || mb >= INT32_MAX || n[b] < 1 ||
+        n[b] > DCGS2_MAX_N || (int64_t)n[b] >= mb)
+      return DCGS2_EINVAL;
+    nmax = std::max(nmax, (int)n[b]);
+  }
+  int rc;
+  if ((rc = ctx_ready(c))) return rc;
+  CK(hipStreamSynchronize(c->stream));      // inputs produced on the caller's stream
+  std::vector<int64_t> v0off(count);
+  int64_t v0tot = 0;
+  for (int b = 0; b < count; ++b) {
+    v0off[b] = v0tot;
+    v0tot += (int64_t)ops[b].nx * ops[b].ny;
+  }
+  BatchedGroup g;
+  g.gid.resize(count);
+  for (int b = 0; b < count; ++b) g.gid[b] = b;
+  if ((rc = group_setup(c, g, ops, r0, v0off, nmax, n, Q))) return rc;
+  BatchedState& B = g.B;
+  int kernels = 0;
+  if ((rc = batched_run_cycle(B, 2, c->tau, c->eta, false, &kernels))) return rc;
+  const int ld = B.ld;
+  g.Hh.resize((size_t)count * ld * ld);
+  CK(hipMemcpyAsync(g.hctrl.data(), B.ctrl, sizeof(Ctrl) * count, hipMemcpyDeviceToHost, B.s));
+  CK(hipMemcpyAsync(g.Hh.data(), B.H, sizeof(double) * g.Hh.size(), hipMemcpyDeviceToHost, B.s));
+  CK(hipStreamSynchronize(B.s));
+  // Pythagorean-guard failures: the explicit-norm fallback and the rest of the
+  // instance's expansion through the single-instance schedule
+  for (int b = 0; b < count; ++b) {
+    if (g.hctrl[b].state != ST_FALLBACK) continue;
+    if ((rc = batched_fallback(c, B, b, &g.hctrl[b]))) return rc;
+    CK(hipMemcpy(g.Hh.data() + (size_t)b * ld * ld, B.tab[b].H, sizeof(double) * ld * ld,
+                 hipMemcpyDeviceToHost));
+  }
+  int overall = DCGS2_OK;
+  int64_t hoff = 0;
+  for (int b = 0; b < count; ++b) {
+    const Ctrl& hc = g.hctrl[b];
+    const int nb = n[b];
+    const int st = status_of(hc);
+    if (st == DCGS2_NONFINITE || (st == DCGS2_BREAKDOWN && overall == DCGS2_OK)) overall = st;
+    for (int jj = 0; jj < nb; ++jj)
+      for (int i = 0; i <= nb; ++i)
+        H_host[hoff + (int64_t)jj * (nb + 1) + i] = g.Hh[(size_t)b * ld * ld + (size_t)jj * ld + i];
+    hoff += (int64_t)(nb + 1) * nb;
+    if (status_host) status_host[b] = st;
+    if (st_host) fill_stats(&st_host[b], hc, kernels, st);
+  }
+  return overall;
+}
+
+extern "C" int gmres_batched(dcgs2_ctx c, int32_t count, const dcgs2_stencil2d* ops,
+                             const int32_t* restart, const double* b, double* x, double rtol,
+                             int32_t max_iters, dcgs2_gmres_info* info_host) {
+  if (!c || count < 1 || count > 65536 || !ops || !restart || !b || !x || !info_host ||
+      !(rtol > 0.0) || max_iters < 0)
+    return DCGS2_EINVAL;
+  int pmax = 0;
+  for (int i = 0; i < count; ++i) {
+    const int64_t mb = (int64_t)ops[i].nx * ops[i].ny;
+    if (ops[i].nx < 1 || ops[i].ny < 1 || mb < 2 || mb >= INT32_MAX || restart[i] < 1 ||
+        restart[i] > DCGS2_MAX_N || (int64_t)restart[i] >= mb)
+      return DCGS2_EINVAL;
+    pmax = std::max(pmax, (int)restart[i]);
+  }
+  int rc;
+  if ((rc = ctx_ready(c))) return rc;
+  CK(hipStreamSynchronize(c->stream));      // b and x0 produced on the caller's stream
+  std::vector<int64_t> off(count);
+  int64_t tot = 0;
+  for (int i = 0; i < count; ++i) {
+    off[i] = tot;
+    tot += (int64_t)ops[i].nx * ops[i].ny;
+  }
+  BatchedGroup g;
+  g.gid.resize(count);
+  for (int i = 0; i < count; ++i) g.gid[i] = i;
+  if ((rc = group_setup(c, g, ops, b, off, pmax, restart, nullptr, false))) return rc;
+  BatchedState& B = g.B;
+  const int p = B.p, ld = B.ld;
+  // Givens state and least-squares solution of every instance
+  const size_t per = (size_t)ld * ld + 3 * (size_t)(p + 2) + (size_t)(p + 1);
+  if ((rc = dalloc((void**)&B.gm, sizeof(double) * per * count))) return rc;
+  for (int i = 0; i < count; ++i) {
+    dcgs2::BInst& I = B.tab[i];
+    double* q = B.gm + per * i;
+    I.gmres = 1;
+    I.Rg = q; q += (size_t)ld * ld;
+    I.cs = q; q += p + 2;
+    I.sn = q; q += p + 2;
+    I.g = q; q += p + 2;
+    I.y = q;
+    I.bvec = b + off[i];
+    I.x = x + off[i];
+    I.ksol = 0;
+    I.thresh = 0.0;
+    std::memset(&info_host[i], 0, sizeof(info_host[i]));
+    info_host[i].st.breakdown_step = -1;
+  }
+  hipStream_t s = B.s;
+  auto upload_tab = [&]() -> int {
+    CK(hipMemcpyAsync(B.d_tab, B.tab.data(), sizeof(dcgs2::BInst) * count, hipMemcpyHostToDevice,
+                      s));
+    return DCGS2_OK;
+  };
+  auto read_ctrls = [&]() -> int {
+    CK(hipMemcpyAsync(g.hctrl.data(), B.ctrl, sizeof(Ctrl) * count, hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    return DCGS2_OK;
+  };
+  int kernels = 0;
+  // ||b|| of every instance
+  if ((rc = upload_tab())) return rc;
+  CK(launch_breset(B.d_tab, count, c->tau, c->eta, s));
+  CK(launch_bresidual(B.d_tab, B.d_pre_rows, count, B.nb_rows, 1, s));
+  CK(launch_bnorm(B.d_tab, B.d_pre_red, count, B.nb_red, B.ldp, B.ldc, ld, s));
+  kernels += 4;
+  if ((rc = read_ctrls())) return rc;
+  std::vector<double> bnorm(count), yh((size_t)count * (p + 1)), Rh((size_t)count * ld * ld),
+      gh((size_t)count * (p + 2));
+  for (int i = 0; i < count; ++i) {
+    dcgs2::BInst& I = B.tab[i];
+    bnorm[i] = std::sqrt(g.hctrl[i].norm2);
+    info_host[i].st.reductions += g.hctrl[i].reductions;
+    if (!std::isfinite(bnorm[i])) {
+      info_host[i].status = DCGS2_NONFINITE;
+      I.active = 0;
+    } else if (bnorm[i] == 0.0) {               // b = 0: x = 0
+      CK(launch_fill(I.x, I.m, 0.0, s));
+      info_host[i].status = DCGS2_OK;
+      I.active = 0;
+    }
+  }
+  for (;;) {
+    // r = b - A x and ||r|| for every active instance; decide who runs a cycle
+    if ((rc = upload_tab())) return rc;
+    CK(launch_breset(B.d_tab, count, c->tau, c->eta, s));
+    CK(launch_bresidual(B.d_tab, B.d_pre_rows, count, B.nb_rows, 0, s));
+    CK(launch_bnorm(B.d_tab, B.d_pre_red, count, B.nb_red, B.ldp, B.ldc, ld, s));
+    kernels += 4;
+    if ((rc = read_ctrls())) return rc;
+    int running = 0;
+    for (int i = 0; i < count; ++i) {
+      dcgs2::BInst& I = B.tab[i];
+      I.ksol = 0;
+      if (!I.active) continue;
+      dcgs2_gmres_info& inf = info_host[i];
+      inf.st.reductions += g.hctrl[i].reductions;
+      inf.relres_true = std::sqrt(g.hctrl[i].norm2) / bnorm[i];
+      if (!std::isfinite(inf.relres_true)) { inf.status = DCGS2_NONFINITE; I.active = 0; continue; }
+      if (inf.relres_true <= rtol) { inf.status = DCGS2_OK; I.active = 0; continue; }
+      if (inf.iters >= max_iters) { inf.status = DCGS2_NOT_CONVERGED; I.active = 0; continue; }
+      I.n = std::min((int)restart[i], max_iters - inf.iters);
+      I.thresh = rtol * bnorm[i];
+      inf.cycles += 1;
+      ++running;
+    }
+    if (running == 0) break;
+    if ((rc = upload_tab())) return rc;
+    CK(launch_fill(B.H, (int64_t)count * ld * ld, 0.0, s));
+    CK(launch_fill(B.K, (int64_t)count * ld * ld, 0.0, s));
+    CK(launch_fill(B.gm, (int64_t)(per * count), 0.0, s));
+    kernels += 3;
+    if ((rc = batched_run_cycle(B, 2, c->tau, c->eta, true, &kernels))) return rc;
+    CK(hipMemcpyAsync(g.hctrl.data(), B.ctrl, sizeof(Ctrl) * count, hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    for (int i = 0; i < count; ++i) {         // explicit-norm fallbacks, one instance at a time
+      if (!B.tab[i].active || g.hctrl[i].state != ST_FALLBACK) continue;
+      if ((rc = batched_fallback(c, B, i, &g.hctrl[i]))) return rc;
+    }
+    for (int i = 0; i < count; ++i) {
+      dcgs2::BInst& I = B.tab[i];
+      if (!I.active) continue;
+      CK(hipMemcpyAsync(Rh.data() + (size_t)i * ld * ld, I.Rg, sizeof(double) * ld * ld,
+                        hipMemcpyDeviceToHost, s));
+      CK(hipMemcpyAsync(gh.data() + (size_t)i * (p + 2), I.g, sizeof(double) * (p + 2),
+                        hipMemcpyDeviceToHost, s));
+    }
+    CK(hipStreamSynchronize(s));
+    for (int i = 0; i < count; ++i) {
+      dcgs2::BInst& I = B.tab[i];
+      if (!I.active) continue;
+      dcgs2_gmres_info& inf = info_host[i];
+      const Ctrl& hc = g.hctrl[i];
+      inf.st.reductions += hc.reductions;
+      inf.st.pyth_fallbacks += hc.fallbacks;
+      if (hc.state == ST_NONFINITE) { inf.status = DCGS2_NONFINITE; I.active = 0; continue; }
+      const int nc = I.n;
+      inf.iters += (hc.state == ST_RUNNING) ? nc : std::min(hc.stop_step - 1, nc);
+      inf.relres_est = hc.resid_est / bnorm[i];
+      const int k = hc.k;
+      if (k <= 0) { inf.status = DCGS2_BREAKDOWN; I.active = 0; continue; }
+      // y = R_k^{-1} g_{1:k} (back substitution on the rotated Hessenberg matrix)
+      const double* R = Rh.data() + (size_t)i * ld * ld;
+      const double* gg = gh.data() + (size_t)i * (p + 2);
+      double* y = yh.data() + (size_t)i * (p + 1);
+      for (int r = k - 1; r >= 0; --r) {
+        double sum = gg[r];
+        for (int jj = r + 1; jj < k; ++jj) sum -= R[(size_t)jj * ld + r] * y[jj];
+        y[r] = sum / R[(size_t)r * ld + r];
+      }
+      I.ksol = k;
+      CK(hipMemcpyAsync(I.y, y, sizeof(double) * k, hipMemcpyHostToDevice, s));
+    }
+    if ((rc = upload_tab())) return rc;
+    CK(launch_bxupdate(B.d_tab, B.d_pre_rows, count, B.nb_rows, s));
+    kernels += 1;
+  }
+  CK(hipStreamSynchronize(s));
+  int overall = DCGS2_OK;
+  for (int i = 0; i < count; ++i) {
+    info_host[i].st.kernels = kernels;
+    const int st = info_host[i].status;
+    if (st == DCGS2_NONFINITE) overall = DCGS2_NONFINITE;
+    else if (st != DCGS2_OK && overall == DCGS2_OK) overall = st;
+  }
+  return overall;
+}
+

@@ -70,17 +70,23 @@ __device__ __forceinline__ GridRed inst_grid(const BInst& I, int ldp) {
 __device__ __forceinline__ FinArgs inst_fin(const BInst& I, int kind, int j, int J, int ldc,
                                             int ldh) {
   FinArgs f{};
-  f.kind = kind; f.qr = 0; f.j = j; f.J = J; f.gmres = 0; f.ldc = ldc;
+  f.kind = kind; f.qr = 0; f.j = j; f.J = J; f.ldc = ldc;
   f.ctrl = I.ctrl; f.coef = I.coef; f.pend = I.pend;
   f.H = I.H; f.K = I.K; f.ldh = ldh;
   f.R = nullptr; f.ldr = 0; f.Sprev = nullptr;
-  f.Rg = nullptr; f.cs = nullptr; f.sn = nullptr; f.g = nullptr;
+  f.gmres = I.gmres;
+  f.Rg = I.Rg; f.cs = I.cs; f.sn = I.sn; f.g = I.g;
   return f;
 }
 
-// Does instance I take part in step j?
+// Does instance I take part in step j (its steps are first_j..n+1)?
 __device__ __forceinline__ bool inst_active(const BInst& I, int j) {
-  return I.active && j >= I.first_j && I.ctrl->state == ST_RUNNING;
+  return I.active && j >= I.first_j && j <= I.n + 1 && I.ctrl->state == ST_RUNNING;
+}
+
+// Does instance I take part in the last-column finish (over its own n columns)?
+__device__ __forceinline__ bool inst_running(const BInst& I) {
+  return I.active && I.ctrl->state == ST_RUNNING;
 }
 
 // v = A w (5-point stencil), 512 rows per workgroup (two per thread).
@@ -122,13 +128,16 @@ __global__ __launch_bounds__(BS) void breduce_kernel(const BInst* __restrict__ t
   int local;
   const int b = find_instance(pre, count, blockIdx.x, &local);
   const BInst I = load_inst(tab, b);
-  if (!inst_active(I, j)) return;
-  const int J = j - 2;
+  if (last ? !inst_running(I) : !inst_active(I, j)) return;
   const GridRed g = inst_grid(I, ldp);
-  if (last) {
-    reduce_body<2, false, double>(I.Q, I.ldq, J, I.w, nullptr, I.m, g,
-                                  inst_fin(I, FIN_LAST1, j, J, ldc, ldh), local);
+  if (last == 2) {                        // plain squared norm of w (batched GMRES)
+    reduce_body<2, false, double>(I.Q, I.ldq, 0, I.w, nullptr, I.m, g,
+                                  inst_fin(I, FIN_NORM, 0, 0, ldc, ldh), local);
+  } else if (last) {                      // over the instance's own n columns
+    reduce_body<2, false, double>(I.Q, I.ldq, I.n, I.w, nullptr, I.m, g,
+                                  inst_fin(I, FIN_LAST1, I.n + 2, I.n, ldc, ldh), local);
   } else {
+    const int J = j - 2;
     const int kind = (I.restart && j == I.first_j) ? FIN_RESTART : FIN_STEP;
     reduce_body<2, true, double>(I.Q, I.ldq, J, I.w, I.v, I.m, g,
                                  inst_fin(I, kind, j, J, ldc, ldh), local);
@@ -150,27 +159,27 @@ __global__ __launch_bounds__(BS) void bupdate_kernel(const BInst* __restrict__ t
 // Last column, reduction 2: u = w - Q c into r, alpha = ||u||, H column closed.
 __global__ __launch_bounds__(BS) void bproject_norm_kernel(const BInst* __restrict__ tab,
                                                            const int* __restrict__ pre,
-                                                           int count, int j, int ldp, int ldc,
+                                                           int count, int ldp, int ldc,
                                                            int ldh) {
   int local;
   const int b = find_instance(pre, count, blockIdx.x, &local);
   const BInst I = load_inst(tab, b);
-  if (!inst_active(I, j)) return;
-  const int J = j - 2;
+  if (!inst_running(I)) return;
+  const int J = I.n;
   project_norm_body<2, double>(I.Q, I.ldq, J, I.w, I.r, I.m, inst_grid(I, ldp),
-                               inst_fin(I, FIN_LAST2, j, J, ldc, ldh), local);
+                               inst_fin(I, FIN_LAST2, J + 2, J, ldc, ldh), local);
 }
 
-// q_{p+1} = u / alpha into column J of every active instance's basis.
+// q_{n+1} = u / alpha into column n of every active instance's basis.
 __global__ __launch_bounds__(BS) void bscale_kernel(const BInst* __restrict__ tab,
                                                     const int* __restrict__ pre, int count,
-                                                    int j, int ldc) {
+                                                    int ldc) {
   int local;
   const int b = find_instance(pre, count, blockIdx.x, &local);
   const BInst I = load_inst(tab, b);
-  if (!inst_active(I, j)) return;
+  if (!inst_running(I)) return;
   const double alpha = I.coef[2 * ldc];
-  const int J = j - 2;
+  const int J = I.n;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int64_t i = (int64_t)local * 2 * BS + h * BS + threadIdx.x;
@@ -221,21 +230,25 @@ __global__ __launch_bounds__(BS) void btruncate_kernel(const BInst* __restrict__
   }
 }
 
-// Second half of the reductions of step j, one workgroup per instance (see
-// finish_body): mode 0 the step's reduction, 1 and 2 the two reductions of the
-// last-column finish.
+// Second half of the reductions, one workgroup per instance (see finish_body):
+// mode 0 the reduction of step j, 1 and 2 the two reductions of the last-column
+// finish over the instance's own n columns.
 __global__ __launch_bounds__(FINISH_BS) void bfinish_kernel(const BInst* __restrict__ tab, int j,
                                                             int mode, int ldp, int ldc, int ldh) {
   const BInst I = load_inst(tab, blockIdx.x);
-  if (!inst_active(I, j)) return;
-  const int J = j - 2;
+  if (mode == 0 ? !inst_active(I, j) : !inst_running(I)) return;
+  const int J = mode == 0 ? j - 2 : mode == 3 ? 0 : I.n;
+  const int jj = mode == 0 ? j : mode == 3 ? 0 : I.n + 2;
   const int kind = mode == 1 ? FIN_LAST1
                  : mode == 2 ? FIN_LAST2
+                 : mode == 3 ? FIN_NORM
                  : (I.restart && j == I.first_j) ? FIN_RESTART : FIN_STEP;
-  const int V = mode == 1 ? J + 1 : mode == 2 ? 1 : 2 * (J + 2);
-  finish_body(inst_grid(I, ldp), V, inst_fin(I, kind, j, J, ldc, ldh), J);
+  const int V = mode == 1 ? J + 1 : (mode == 2 || mode == 3) ? 1 : 2 * (J + 2);
+  finish_body(inst_grid(I, ldp), V, inst_fin(I, kind, jj, J, ldc, ldh), J);
 }
 
+// LDS of bfinish_kernel for the largest J of the launch (j - 2 at step j; the largest
+// instance n, passed as j - 2, for the last-column modes).
 inline size_t bfinish_smem(int j, int mode) {
   const int J = j - 2;
   return finish_smem(mode == 1 ? J + 1 : mode == 2 ? 1 : 2 * (J + 2), J);
@@ -256,9 +269,62 @@ __global__ void breset_kernel(const BInst* __restrict__ tab, int count, double t
   c->rho_next = 0.0;
   c->tau = tau;
   c->eta = eta;
-  c->gmres_thresh = 0.0;
+  c->gmres_thresh = I.thresh;
   c->resid_est = 0.0;
   c->norm2 = 0.0;
+}
+
+// Batched GMRES residual: w = b - A x (copy_b: w = b), 512 rows per workgroup.
+__global__ __launch_bounds__(BS) void bresidual_kernel(const BInst* __restrict__ tab,
+                                                       const int* __restrict__ pre, int count,
+                                                       int copy_b) {
+  int local;
+  const int b = find_instance(pre, count, blockIdx.x, &local);
+  const BInst I = load_inst(tab, b);
+  if (!I.active) return;
+  const uint32_t nx = I.nx, ny = I.ny;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int64_t i = (int64_t)local * 2 * BS + h * BS + threadIdx.x;
+    if (i >= I.m) continue;
+    if (copy_b) {
+      I.w[i] = I.bvec[i];
+      continue;
+    }
+    const uint32_t ii = (uint32_t)i;
+    const uint32_t ix = ii % nx, iy = ii / nx;
+    const double* x = I.x;
+    const bool ym = iy > 0, yp = iy + 1 < ny, xm = ix > 0, xp = ix + 1 < nx;
+    const double vym = x[ym ? i - nx : i], vxm = x[xm ? i - 1 : i], vc = x[i];
+    const double vxp = x[xp ? i + 1 : i], vyp = x[yp ? i + nx : i];
+    double s = 0.0;
+    s = fma(ym ? I.cym : 0.0, vym, s);
+    s = fma(xm ? I.cxm : 0.0, vxm, s);
+    s = fma(I.c0, vc, s);
+    s = fma(xp ? I.cxp : 0.0, vxp, s);
+    s = fma(yp ? I.cyp : 0.0, vyp, s);
+    I.w[i] = I.bvec[i] - s;
+  }
+}
+
+// x += Q_{:,0..ksol) y for every active instance with a solution (y read through the
+// constant view: written by a host copy before the launch).
+__global__ __launch_bounds__(BS) void bxupdate_kernel(const BInst* __restrict__ tab,
+                                                      const int* __restrict__ pre, int count) {
+  int local;
+  const int b = find_instance(pre, count, blockIdx.x, &local);
+  const BInst I = load_inst(tab, b);
+  if (!I.active || I.ksol <= 0) return;
+  const ConstPtr<double> y = as_const(I.y);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int64_t i = (int64_t)local * 2 * BS + h * BS + threadIdx.x;
+    if (i >= I.m) continue;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int c = 0; c < I.ksol; ++c) acc = fma(I.Q[(int64_t)c * I.ldq + i], y[c], acc);
+    I.x[i] += acc;
+  }
 }
 
 inline unsigned bnb(int n) { return (unsigned)((n + BS - 1) / BS); }
@@ -793,7 +859,7 @@ hipError_t launch_bupdate(const BInst* tab, const int* pre_rows, int count, int 
 
 hipError_t launch_bproject_norm(const BInst* tab, const int* pre_red, int count, int nblocks,
                                 int j, int ldp, int ldc, int ldh, hipStream_t s) {
-  bproject_norm_kernel<<<nblocks, BS, sizeof(double) * NW, s>>>(tab, pre_red, count, j, ldp, ldc,
+  bproject_norm_kernel<<<nblocks, BS, sizeof(double) * NW, s>>>(tab, pre_red, count, ldp, ldc,
                                                                ldh);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -803,7 +869,8 @@ hipError_t launch_bproject_norm(const BInst* tab, const int* pre_red, int count,
 
 hipError_t launch_bscale(const BInst* tab, const int* pre_rows, int count, int nblocks, int j,
                          int ldc, hipStream_t s) {
-  bscale_kernel<<<nblocks, BS, 0, s>>>(tab, pre_rows, count, j, ldc);
+  (void)j;
+  bscale_kernel<<<nblocks, BS, 0, s>>>(tab, pre_rows, count, ldc);
   return hipGetLastError();
 }
 
@@ -822,6 +889,28 @@ hipError_t launch_bschur(const BInst* tab, int count, int p, int ld, int nev, in
   if (p < 2 || p > BSCHUR_MAX_P || nev < 1 || keep < 1) return hipErrorInvalidValue;
   bschur_kernel<<<count, SCHUR_THREADS, bschur_smem(p), s>>>(tab, p, ld, nev, keep, cut_gap, H, Z,
                                                              ires, resid, ere, eim);
+  return hipGetLastError();
+}
+
+hipError_t launch_bresidual(const BInst* tab, const int* pre_rows, int count, int nblocks,
+                            int copy_b, hipStream_t s) {
+  bresidual_kernel<<<nblocks, BS, 0, s>>>(tab, pre_rows, count, copy_b);
+  return hipGetLastError();
+}
+
+hipError_t launch_bnorm(const BInst* tab, const int* pre_red, int count, int nblocks, int ldp,
+                        int ldc, int ldh, hipStream_t s) {
+  breduce_kernel<<<nblocks, BS, sizeof(double) * NW * 2 * NT, s>>>(tab, pre_red, count, 0, 2,
+                                                                  ldp, ldc, ldh);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  bfinish_kernel<<<count, FINISH_BS, finish_smem(1, 0), s>>>(tab, 0, 3, ldp, ldc, ldh);
+  return hipGetLastError();
+}
+
+hipError_t launch_bxupdate(const BInst* tab, const int* pre_rows, int count, int nblocks,
+                           hipStream_t s) {
+  bxupdate_kernel<<<nblocks, BS, 0, s>>>(tab, pre_rows, count);
   return hipGetLastError();
 }
 

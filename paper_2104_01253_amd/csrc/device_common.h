@@ -746,7 +746,30 @@ __device__ __forceinline__ void project_norm_body(const TQ* __restrict__ Q, int6
   block_sum<1>(acc, shb, gr.P1 + (int64_t)bid * gr.ldp, 1);
 }
 
-// Update pass: q_{j-1} and w_j, one row unit per thread.
+// NC basis columns of one row unit into the update's two products: all NC loads are
+// issued before the first one is used (the coefficients are wavefront-uniform).
+template <int NC, int VW, typename TQ>
+__device__ __forceinline__ void update_group(const TQ* __restrict__ Q, int64_t ldq, int k0,
+                                             int64_t u, const double* __restrict__ C,
+                                             const double* __restrict__ T, RowVec<VW>& sc,
+                                             RowVec<VW>& st) {
+  RowVec<VW> q[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) q[c] = RowVec<VW>::load(Q + (int64_t)(k0 + c) * ldq, u);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double ck = C[k0 + c], tk = T[k0 + c];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+      sc.e[e] = fma(q[c].e[e], ck, sc.e[e]);
+      st.e[e] = fma(q[c].e[e], tk, st.e[e]);
+    }
+  }
+}
+
+// Update pass: q_{j-1} and w_j, one row unit per thread.  The basis columns are taken
+// in exact groups of 16, 8, 4, 2 and 1 (J = 16 q + the binary digits of the rest), so
+// that every load of a group is in flight together, as in the reduction sweeps.
 template <int VW, bool ARN, bool QCOL, typename TQ>
 __device__ __forceinline__ void update_body(TQ* __restrict__ Q, int64_t ldq, int J,
                                                     double* __restrict__ x,
@@ -764,16 +787,12 @@ __device__ __forceinline__ void update_body(TQ* __restrict__ Q, int64_t ldq, int
   TQ* qout = Q + (int64_t)J * ldq;
   if (u < units) {
     RowVec<VW> sc = RowVec<VW>::zero(), st = RowVec<VW>::zero();
-#pragma unroll 8
-    for (int k = 0; k < J; ++k) {
-      const RowVec<VW> q = RowVec<VW>::load(Q + (int64_t)k * ldq, u);
-      const double ck = C[k], tk = T[k];
-#pragma unroll
-      for (int e = 0; e < VW; ++e) {
-        sc.e[e] = fma(q.e[e], ck, sc.e[e]);
-        st.e[e] = fma(q.e[e], tk, st.e[e]);
-      }
-    }
+    int k0 = 0;
+    for (; k0 + 16 <= J; k0 += 16) update_group<16, VW, TQ>(Q, ldq, k0, u, C, T, sc, st);
+    if (k0 + 8 <= J) { update_group<8, VW, TQ>(Q, ldq, k0, u, C, T, sc, st); k0 += 8; }
+    if (k0 + 4 <= J) { update_group<4, VW, TQ>(Q, ldq, k0, u, C, T, sc, st); k0 += 4; }
+    if (k0 + 2 <= J) { update_group<2, VW, TQ>(Q, ldq, k0, u, C, T, sc, st); k0 += 2; }
+    if (k0 + 1 <= J) update_group<1, VW, TQ>(Q, ldq, k0, u, C, T, sc, st);
     const RowVec<VW> xv = RowVec<VW>::load(x, u);
     const RowVec<VW> yv = RowVec<VW>::load(y, u);
     RowVec<VW> qc = RowVec<VW>::zero();

@@ -161,7 +161,16 @@ struct BInst {
   int k;               // Schur vectors kept by the last truncation
   int active;          // 0: converged or stopped -- every batched kernel skips it
   int truncate;        // 1: btruncate acts on this instance
-  int pad;
+  int n;               // steps of a cycle: steps first_j..n+1, then the last-column
+                       // finish over n columns (Krylov-Schur: n = p for every instance)
+  // batched GMRES (gmres != 0): right-hand side, iterate, Givens state and the
+  // least-squares solution of the last cycle (ksol entries of y)
+  int gmres;
+  int ksol;
+  const double* bvec;
+  double* x;
+  double *Rg, *cs, *sn, *g, *y;
+  double thresh;       // rtol ||b||: a cycle ends once the least-squares residual is below
 };
 hipError_t launch_bstencil(const BInst* tab, const int* pre_rows, int count, int nblocks, int j,
                            hipStream_t s);
@@ -169,6 +178,8 @@ hipError_t launch_breduce(const BInst* tab, const int* pre_red, int count, int n
                           int last, int ldp, int ldc, int ldh, hipStream_t s);
 hipError_t launch_bupdate(const BInst* tab, const int* pre_rows, int count, int nblocks, int j,
                           int ldc, hipStream_t s);
+// The last-column launches work on each instance's own n columns; j = (largest n) + 2
+// sizes the finishing kernel's LDS.
 hipError_t launch_bproject_norm(const BInst* tab, const int* pre_red, int count, int nblocks,
                                 int j, int ldp, int ldc, int ldh, hipStream_t s);
 hipError_t launch_bscale(const BInst* tab, const int* pre_rows, int count, int nblocks, int j,
@@ -176,6 +187,15 @@ hipError_t launch_bscale(const BInst* tab, const int* pre_rows, int count, int n
 hipError_t launch_btruncate(const BInst* tab, const int* pre_rows, int count, int nblocks, int p,
                             hipStream_t s);
 hipError_t launch_breset(const BInst* tab, int count, double tau, double eta, hipStream_t s);
+// Batched GMRES: w = b - A x (or w = b when copy_b) for every active instance; the
+// squared norm of w into each instance's ctrl->norm2 (one grid reduction per
+// instance); x += Q_{:,0..ksol) y.
+hipError_t launch_bresidual(const BInst* tab, const int* pre_rows, int count, int nblocks,
+                            int copy_b, hipStream_t s);
+hipError_t launch_bnorm(const BInst* tab, const int* pre_red, int count, int nblocks, int ldp,
+                        int ldc, int ldh, hipStream_t s);
+hipError_t launch_bxupdate(const BInst* tab, const int* pre_rows, int count, int nblocks,
+                           hipStream_t s);
 // Dense restart work of every active, running instance on the GPU (one wavefront per
 // instance, T and Z in LDS): real Schur form of the p x p H, reordering by magnitude
 // for nev (Ritz values into ere/eim, residual estimate into resid) and then for keep

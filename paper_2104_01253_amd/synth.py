@@ -79,6 +79,23 @@ def ks_instances(count: int, seed: int = 4, nmin: int = 48, nmax: int = 256, vma
     return [CDProblem((int(n), int(n)), 1.0, (float(v[0]), float(v[1]))) for n, v in zip(nx, vel)]
 
 
+def gmres_batched_instances(count: int, seed: int = 6, nmin: int = 32, nmax: int = 128,
+                            vmax: float = 30.0, rmin: int = 20, rmax: int = 60):
+    """Batched GMRES family: 2-D grids n_x, n_y ~ U{nmin..nmax} (independently, so grids
+    are rectangular), v ~ U(0, vmax)^2, restart lengths ~ U{rmin..rmax}, b ~ U(0,1)
+    with seed 5000 + i.  Returns [(CDProblem, restart, b)]."""
+    g = rng(seed)
+    nx = g.integers(nmin, nmax + 1, size=count)
+    ny = g.integers(nmin, nmax + 1, size=count)
+    vel = g.uniform(0.0, vmax, size=(count, 2))
+    rs = g.integers(rmin, rmax + 1, size=count)
+    out = []
+    for i in range(count):
+        p = CDProblem((int(nx[i]), int(ny[i])), 1.0, (float(vel[i, 0]), float(vel[i, 1])))
+        out.append((p, int(rs[i]), uniform_vector(p.m, 5000 + i)))
+    return out
+
+
 # Named workloads ------------------------------------------------------------------
 def arnoldi_cd2d_32():
     """FP64 DCGS2 Arnoldi, 50 steps, 2-D convection-diffusion 32x32, v=(10,10), r0 ~ N(0,1) seed 0."""

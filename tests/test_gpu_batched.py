@@ -208,3 +208,32 @@ def test_batched_every_tuned_reduce_shape(ctx):
                     assert np.max(diff) <= bound, (rows, b, diff, bound)
     finally:
         ctx.set_tuning(key, default)
+
+
+def test_batched_ks_forced_fallback_vs_oracle(ctx):
+    """tau = 1 forces the explicit-norm fallback at every DCGS2 step of every cycle:
+    the batched solver resolves each through the single-instance schedule and
+    converges like the oracle run with the same reading (restart counts, Ritz values
+    within the Bauer-Fike bound), with one fallback per expansion step."""
+    cases = CASES[:2] + CASES[3:4]
+    descs, v0s, v0 = _batch(cases)
+    ctx.set_tolerances(1.0, 1e-12)
+    try:
+        ev, rc, infos = ctx.krylov_schur_batched(descs, v0, NEV, NCV, KEEP, TOL, 200)
+    finally:
+        ctx.set_tolerances(1e-8, 1e-12)
+    say("forced fallback", [(i["status"], i["restarts"], i["stats"]["pyth_fallbacks"])
+                            for i in infos])
+    assert rc == binding.OK
+    for b, (g, v, _) in enumerate(cases):
+        A = ops.convection_diffusion(g, 1.0, v)
+        ref, io = krylov_schur(A, v0s[b], nev=NEV, ncv=NCV, keep=KEEP, tol=TOL, tau=1.0)
+        assert infos[b]["status"] == binding.OK and infos[b]["resid"] <= TOL
+        assert abs(infos[b]["restarts"] - io["restarts"]) <= max(3, io["restarts"] // 4)
+        # every step but the continuation step of a restart takes the fallback
+        steps = infos[b]["matvecs"]
+        assert infos[b]["stats"]["pyth_fallbacks"] == steps - infos[b]["restarts"]
+        exact = ops.closed_form_eigenvalues(g, 1.0, v)[::-1][:NEV + 2]
+        bound = 2.0 * _eigvec_condition(g, v) * TOL * abs(exact[0]) + 1e-12 * abs(exact[0])
+        for th in _by_magnitude(ev[b]):
+            assert np.min(np.abs(exact - th)) <= bound, (b, th, bound)

@@ -72,18 +72,31 @@ def test_gmres_zero_rhs_warm_start_and_budget(ctx):
     assert rc == binding.NOT_CONVERGED and info["iters"] == 30 and info["cycles"] == 2
 
 
-def test_gmres_full_size_128cube(ctx):
-    """GMRES(50) to 1e-8 on 3-D 128^3 (m = 2,097,152), v = (10,10,10), b ~ U(0,1)."""
+@pytest.mark.parametrize("bits", [64, 32])
+def test_gmres_full_size_128cube(ctx, bits):
+    """GMRES(50) to 1e-8 on 3-D 128^3 (m = 2,097,152), v = (10,10,10), b ~ U(0,1), with
+    the basis in FP64 and in FP32: the iteration count within one of the oracle's and
+    the same cycle count (tests/golden/gmres50_128cube.json, written by a script that
+    runs only the oracle), and the true residual below 1e-8."""
+    import json
+    import os
     torch = torch_cuda()
+    golden = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                         "gmres50_128cube.json")))
+    ref = golden["fp64" if bits == 64 else "fp32_basis"]
     prob, b = synth.gmres_cd3d(128)
     A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
     op = binding.stencil_op(prob.grid, prob.D, prob.vel)
     x = torch.zeros(prob.m, dtype=torch.float64, device="cuda")
-    rc, info = ctx.gmres(op, dev_vector(b), x, restart=50, rtol=1e-8)
+    ctx.set_basis_precision(bits)
+    try:
+        rc, info = ctx.gmres(op, dev_vector(b), x, restart=50, rtol=1e-8)
+    finally:
+        ctx.set_basis_precision(64)
     relres = np.linalg.norm(b - A @ host(x)) / np.linalg.norm(b)
-    say("gmres 128^3", info, relres)
+    say("gmres 128^3", bits, info, relres, "oracle", ref)
     assert rc == 0 and relres <= 1e-8
-    assert 500 <= info["iters"] <= 800
+    assert abs(info["iters"] - ref["iters"]) <= 1 and info["cycles"] == ref["cycles"]
 
 
 def test_krylov_schur_closed_form(ctx):
