@@ -10,10 +10,11 @@ steps (columns) per second over the K timed factorisations.
 Also reported (not `value`): the DCGS2 Arnoldi expansion at m = 128^3 = 2,097,152
 with n = 100 (3-D convection-diffusion matvec), restarted GMRES(50) on the same
 operator to a 1e-8 true relative residual (time-to-solution, FP64 and FP32-stored
-basis), one Krylov-Schur solve, batched Krylov-Schur over 512 operators, GMRES
-from the learned initial guess against x0 = 0, the per-kernel roofline figures
-measured with HIP events around each launch, and the FP64 oracle timed on the
-host on the same matrix.
+basis), one Krylov-Schur solve, batched Krylov-Schur over 512 operators, batched
+GMRES over 128 systems against the single-instance solver, GMRES from the learned
+initial guess against x0 = 0, the per-kernel roofline figures measured with HIP
+events around each launch, and the FP64 oracle timed on the host (the whole QR
+factorisation, and a two-cycle sample of its GMRES).
 """
 from __future__ import annotations
 
@@ -32,6 +33,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published
 METRIC = "DCGS2 Arnoldi steps/s + HBM GB/s (m=2M,n=100); GMRES time-to-1e-8 vs FP64"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+TRAFFIC_FILE_Q32 = os.path.join(ROOT, "profiles", "traffic_q32.json")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2104_01253_amd", "csrc", f)
                for f in ("kernels.hip", "device_common.h")]
 
@@ -49,11 +51,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, record: str = TRAFFIC_FILE):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or None
     when the kernels changed since the counters were taken."""
     try:
-        t = json.load(open(TRAFFIC_FILE))
+        t = json.load(open(record))
     except (OSError, ValueError):
         return None
     if t.get("kernel_source_sha256_16") != kernel_source_hash():
@@ -73,14 +75,24 @@ def timed(torch, fn, steps):
     return e0.elapsed_time(e1) / 1000.0
 
 
-def roofline(prof, wall_s=None):
+def kernel_roof(st):
+    """Algorithmic GB/s of one kernel class (bytes per launch over its mean duration)."""
+    avg_ms = st["total_ms"] / max(st["launches"], 1)
+    bytes_per_launch = st["bytes"] / max(st["launches"], 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    return {"launches": st["launches"], "avg_launch_us": round(avg_ms * 1e3, 2),
+            "alg_bytes_per_launch": bytes_per_launch, "achieved": round(achieved, 1),
+            "frac": round(achieved / PEAK_HBM_GBS, 4)}
+
+
+def roofline(prof, record=TRAFFIC_FILE):
     kern = {k: v for k, v in prof.items() if not k.startswith("phase_")}
     dom = max(kern.items(), key=lambda kv: kv[1]["total_ms"])
     name, st = dom
     avg_ms = st["total_ms"] / max(st["launches"], 1)
     bytes_per_launch = st["bytes"] / max(st["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    tr = measured_traffic(name)
+    tr = measured_traffic(name, record)
     return name, {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
         "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": tr,
@@ -90,25 +102,58 @@ def roofline(prof, wall_s=None):
 
 
 def cpu_model() -> str:
-    """The host CPU's model name (Linux), for the CPU baseline's context."""
+    """The host CPU's model name, family/model/stepping numbers and logical CPU count
+    (Linux), for the CPU baseline's context (a virtual machine may report only the
+    product family as its name)."""
+    info = {}
     try:
         with open("/proc/cpuinfo") as fh:
             for line in fh:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if ":" in line:
+                    k, v = line.split(":", 1)
+                    info.setdefault(k.strip(), v.strip())
     except OSError:
         pass
-    return "unknown"
+    name = info.get("model name", "unknown")
+    fam = "/".join(info.get(k, "?") for k in ("cpu family", "model", "stepping"))
+    return f"{name} (family/model/stepping {fam}, {os.cpu_count()} logical CPUs)"
+
+
+def cpu_threads() -> int:
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def cpu_gmres_sample(cycles=2):
+    """The oracle's GMRES(50) (oracle.gmres.gmres_dcgs2, unmodified) on the 128^3 GMRES
+    workload for its first `cycles` restart cycles: iterations per second on the host,
+    and the time to 1e-8 projected from that rate and the oracle's own iteration count
+    (tests/golden/gmres50_128cube.json, written by a script that runs only the oracle;
+    every cycle sweeps the same basis sizes, so the first cycles' rate holds for all)."""
+    from oracle import operators as ops
+    from oracle.gmres import gmres_dcgs2
+    from paper_2104_01253_amd import synth
+    prob, b = synth.gmres_cd3d(128)
+    A = ops.convection_diffusion(prob.grid, prob.D, prob.vel)
+    t0 = time.perf_counter()
+    _, info = gmres_dcgs2(A, b, restart=50, rtol=1e-8, max_iters=50 * cycles)
+    dt = time.perf_counter() - t0
+    rate = info["iters"] / dt
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "gmres50_128cube.json")))
+    iters = golden["fp64"]["iters"]
+    return {"iters_per_s": round(rate, 2), "oracle_iters_to_1e-8": iters,
+            "projected_time_to_1e-8_s": round(iters / rate, 2), "cores": int(cpu_threads()),
+            "sample": f"the first {cycles} restart cycles ({info['iters']} iterations, "
+                      f"{dt:.1f} s) of the oracle's GMRES(50) at 128^3"}
 
 
 def cpu_baseline(B, n):
-    """The FP64 oracle (oracle.gram_schmidt.dcgs2_qr, unmodified) on the first rows of B."""
+    """The FP64 oracle (oracle.gram_schmidt.dcgs2_qr, unmodified) on the whole of B."""
     from oracle import gram_schmidt as gs
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count() or 1
+    cores = cpu_threads()
     m = B.shape[0]
     t0 = time.perf_counter()
     gs.dcgs2_qr(B)
@@ -162,13 +207,22 @@ def row_block_leg(torch, ctx, binding, B, n, rows=250_000, steps=20):
             "finish_and_gaps_ms": round(T * 1e3 - stream_ms, 3)}
 
 
-def batched_ks_leg(torch, ctx, binding, synth, count=512):
+def batched_ks_leg(torch, ctx, binding, synth, count=512, tune_count=64):
     """Batched Krylov-Schur: `count` 2-D convection-diffusion operators, n_x ~ U{48..256},
-    v ~ U(0,50)^2, 10 largest-magnitude eigenvalues, basis 60, keep 20, tol 1e-8."""
+    v ~ U(0,50)^2, 10 largest-magnitude eigenvalues, basis 60, keep 20, tol 1e-8.  The
+    rows per reduction workgroup are first autotuned on the first `tune_count`
+    instances (the restart's dense work stays on host threads)."""
+    from paper_2104_01253_amd import autotune
     probs = synth.ks_instances(count, seed=4)
     descs = [binding.stencil2d(p.grid, p.D, p.vel) for p in probs]
-    v0 = torch.from_numpy(np.concatenate([synth.normal_vector(p.m, 1000 + i)
-                                          for i, p in enumerate(probs)])).cuda()
+    v0s = [synth.normal_vector(p.m, 1000 + i) for i, p in enumerate(probs)]
+    v0 = torch.from_numpy(np.concatenate(v0s)).cuda()
+    vt = torch.from_numpy(np.concatenate(v0s[:tune_count])).cuda()
+    torch.cuda.synchronize()
+    key = binding.TUNE_BATCH_REDUCE_ROWS
+    best, _, _ = autotune.tune(
+        ctx, lambda: ctx.krylov_schur_batched(descs[:tune_count], vt, 10, 60, 20, 1e-8, 300),
+        reps=1, candidates={key: autotune.BATCHED_CANDIDATES[key]})
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, rc, infos = ctx.krylov_schur_batched(descs, v0, 10, 60, 20, 1e-8, 300, use_graph=True)
@@ -178,7 +232,56 @@ def batched_ks_leg(torch, ctx, binding, synth, count=512):
     return {"instances": count, "time_s": round(dt, 3), "converged": st.count(0),
             "restarts_max": max(rs), "restarts_mean": round(float(np.mean(rs)), 2),
             "matvecs_total": int(sum(i["matvecs"] for i in infos)),
-            "instances_per_s": round(count / dt, 2), "status": rc}
+            "instances_per_s": round(count / dt, 2), "status": rc,
+            "batch_reduce_rows": best[key]}
+
+
+def batched_gmres_leg(torch, ctx, binding, synth, count=128):
+    """Batched GMRES: `count` 2-D convection-diffusion systems of uneven size (grids
+    32..128 per side) and restart length (20..60), v ~ U(0,30)^2, b ~ U(0,1), to a 1e-8
+    true relative residual: time to solve them all in one batch (autotuned rows per
+    reduction workgroup), against the single-instance FP64 gmres_solve looping over the
+    same systems on the same GPU."""
+    from paper_2104_01253_amd import autotune
+    inst = synth.gmres_batched_instances(count)
+    descs = [binding.stencil2d(p.grid, p.D, p.vel) for p, _, _ in inst]
+    rs = [r for _, r, _ in inst]
+    bd = torch.from_numpy(np.concatenate([b for _, _, b in inst])).cuda()
+    x = torch.zeros_like(bd)
+
+    def batch():
+        x.zero_()
+        return ctx.gmres_batched(descs, rs, bd, x, rtol=1e-8)
+    key = binding.TUNE_BATCH_REDUCE_ROWS
+    default = ctx.get_tuning(key)
+    best, _, _ = autotune.tune(ctx, batch, reps=1,
+                               candidates={key: autotune.BATCHED_CANDIDATES[key]})
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, infos = batch()
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    ctx.set_tuning(key, default)
+    xs, off, t_single, it_single = [], 0, 0.0, 0
+    for (p, r, b), d in zip(inst, descs):
+        op = binding.stencil_op(p.grid, p.D, p.vel)
+        bi = bd[off:off + p.m]
+        xi = torch.zeros(p.m, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rci, ii = ctx.gmres(op, bi, xi, restart=r, rtol=1e-8)
+        t_single += time.perf_counter() - t1
+        it_single += ii["iters"]
+        off += p.m
+    its = [i["iters"] for i in infos]
+    return {"instances": count, "rows": int(sum(p.m for p, _, _ in inst)),
+            "time_to_1e-8_s": round(tb, 4), "single_instance_loop_s": round(t_single, 4),
+            "speedup_vs_single": round(t_single / tb, 2),
+            "converged": sum(i["status"] == 0 for i in infos),
+            "iters_total": int(sum(its)), "iters_max": int(max(its)),
+            "iters_total_single": int(it_single),
+            "max_relres_true": max(i["relres_true"] for i in infos),
+            "batch_reduce_rows": best[key], "status": rc}
 
 
 def learned_guess_leg(torch, ctx, binding, synth, count=16):
@@ -312,7 +415,15 @@ def main():
             assert rc == binding.OK, rc
         q32_once()
         T32 = timed(torch, q32_once, 3) / 3
-        out["qr_fp32_basis"] = {"steps_per_s": round(n / T32, 1), "ms": round(T32 * 1e3, 3)}
+        ctx.profile(True)
+        ctx.profile_read(reset=True)
+        q32_once()
+        p32 = {k: v for k, v in ctx.profile_read(reset=True).items() if v["launches"] > 0}
+        ctx.profile(False)
+        _, roof32 = roofline(p32, TRAFFIC_FILE_Q32)
+        b32 = sum(v["bytes"] for v in p32.values())
+        out["qr_fp32_basis"] = {"steps_per_s": round(n / T32, 1), "ms": round(T32 * 1e3, 3),
+                                "hbm_gbps": round(b32 / T32 / 1e9, 1), "roofline": roof32}
         del Q32
         log(f"[bench] cgs2 {out['cgs2_qr']}, mgs {out['mgs_qr']}, fp32 basis {out['qr_fp32_basis']}")
         out["qr_row_block_250k"] = row_block_leg(torch, ctx, binding, B, n)
@@ -337,8 +448,14 @@ def main():
         pa = ctx.profile_read(reset=True)
         ctx.profile(False)
         abytes = sum(v["bytes"] for v in pa.values())
-        out["arnoldi_128cube_n100"] = {"steps_per_s": round(n / Ta, 1), "ms": round(Ta * 1e3, 3),
-                                       "hbm_gbps": round(abytes / Ta / 1e9, 1)}
+        # per kernel, as the paper reports its two orthogonalisation kernels (MvTransMv,
+        # the reduction, and MvTimesMatAddMv, the update) separately (Sec. 7)
+        out["arnoldi_128cube_n100"] = {
+            "steps_per_s": round(n / Ta, 1), "ms": round(Ta * 1e3, 3),
+            "hbm_gbps": round(abytes / Ta / 1e9, 1),
+            "roofline_by_kernel": {"bound": "hbm", "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                   **{k: kernel_roof(v) for k, v in pa.items()
+                                      if v["launches"] > 0}}}
         del Qa
         x = torch.zeros(prob.m, dtype=torch.float64, device="cuda")
 
@@ -382,6 +499,8 @@ def main():
         log(f"[bench] legs: arnoldi {out['arnoldi_128cube_n100']}, gmres {out['gmres50_128cube_fp64']}")
         out["krylov_schur_batched_512"] = batched_ks_leg(torch, ctx, binding, synth)
         log(f"[bench] batched KS {out['krylov_schur_batched_512']}")
+        out["gmres_batched_128"] = batched_gmres_leg(torch, ctx, binding, synth)
+        log(f"[bench] batched GMRES {out['gmres_batched_128']}")
         out["gmres50_learned_guess_256sq"] = learned_guess_leg(torch, ctx, binding, synth)
         log(f"[bench] learned guess {out['gmres50_learned_guess_256sq']}")
 
@@ -390,6 +509,8 @@ def main():
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(B, n)
+        if not args.no_legs:
+            out["cpu_baseline"]["gmres50_128cube"] = cpu_gmres_sample()
     ctx.close()
     print(json.dumps(out), flush=True)
 

@@ -336,9 +336,9 @@ inline unsigned bnb(int n) { return (unsigned)((n + BS - 1) / BS); }
 //
 // The algorithms are those of the host implementation (schur.cpp): Householder
 // reduction to Hessenberg form, the implicit Francis double-shift QR step (Golub &
-// Van Loan, Alg. 7.5.1) with EISPACK's exceptional shifts, the 2x2 normal form of
-// LAPACK's lanv2, and adjacent block swaps through the Sylvester equation (Bai &
-// Demmel).  T and Z live in LDS.  Scalar decisions (deflation, shifts, reflectors,
+// Van Loan, Alg. 7.5.1) with EISPACK's exceptional shifts, the standard form of 2x2
+// blocks by a double-angle rotation, and adjacent block swaps through the Sylvester
+// equation (Bai & Demmel).  T and Z live in LDS.  Scalar decisions (deflation, shifts, reflectors,
 // rotations) are taken identically by every lane; each update of rows or columns
 // gives one row or column to a lane, with the per-element arithmetic of the host
 // code, so both paths agree up to the rounding of hypot.
@@ -421,63 +421,54 @@ __device__ void s_rot_cols(const LMat& A, int i, int r0, int r1, double cs, doub
 
 __device__ __forceinline__ void dswap(double& a, double& b) { const double t = a; a = b; b = t; }
 
-// Normal form of a real 2x2 block (scalar; see schur.cpp)
+// Standard form of a real 2x2 block (scalar), the same steps as std2x2 in schur.cpp:
+// a rotation through half the angle between the symmetric traceless part's vector
+// (t, s) and its target ((+-sqrt(delta), r) for real eigenvalues, (0, +-rho) for a
+// complex pair), M' = G^T M G formed explicitly, c' = 0 or a' = d' set exactly.
 __device__ void s_std2x2(double& a, double& b, double& c, double& d, double& cs, double& sn) {
-  if (c == 0.0) { cs = 1.0; sn = 0.0; return; }
-  if (b == 0.0) { cs = 0.0; sn = 1.0; dswap(a, d); b = -c; c = 0.0; return; }
-  if (a - d == 0.0 && signbit(b) != signbit(c)) { cs = 1.0; sn = 0.0; return; }
-  const double temp0 = a - d;
-  double p = 0.5 * temp0;
-  const double bcmax = fmax(fabs(b), fabs(c));
-  const double bcmis = fmin(fabs(b), fabs(c)) * copysign(1.0, b) * copysign(1.0, c);
-  const double scale = fmax(fabs(p), bcmax);
-  double z = (p / scale) * p + (bcmax / scale) * bcmis;
-  if (z >= 4.0 * SEPS) {
-    z = p + copysign(sqrt(scale) * sqrt(z), p);
-    a = d + z;
-    d = d - (bcmax / z) * bcmis;
-    const double tau = hypot(c, z);
-    cs = z / tau;
-    sn = c / tau;
-    b = b - c;
-    c = 0.0;
-    return;
-  }
-  const double sigma = b + c;
-  const double tau = hypot(sigma, temp0);
-  cs = sqrt(0.5 * (1.0 + fabs(sigma) / tau));
-  sn = -(p / (tau * cs)) * copysign(1.0, sigma);
-  const double aa = a * cs + b * sn, bb = -a * sn + b * cs;
-  const double cc = c * cs + d * sn, dd = -c * sn + d * cs;
-  a = aa * cs + cc * sn;
-  b = bb * cs + dd * sn;
-  c = -aa * sn + cc * cs;
-  d = -bb * sn + dd * cs;
-  const double mid = 0.5 * (a + d);
-  a = mid;
-  d = mid;
-  if (c != 0.0) {
-    if (b != 0.0) {
-      if (signbit(b) == signbit(c)) {
-        const double sab = sqrt(fabs(b)), sac = sqrt(fabs(c));
-        p = copysign(sab * sac, c);
-        const double t = 1.0 / sqrt(fabs(b + c));
-        a = mid + p;
-        d = mid - p;
-        b = b - c;
-        c = 0.0;
-        const double cs1 = sab * t, sn1 = sac * t;
-        const double ncs = cs * cs1 - sn * sn1;
-        sn = cs * sn1 + sn * cs1;
-        cs = ncs;
-      }
+  cs = 1.0;
+  sn = 0.0;
+  for (int pass = 0; pass < 2 && c != 0.0; ++pass) {
+    const double m = 0.5 * (a + d), t = 0.5 * (a - d);
+    const double s = 0.5 * (b + c), r = 0.5 * (b - c);
+    const double rho = hypot(t, s);
+    const double delta = t * t + b * c;
+    double tp, sp;
+    if (delta >= 0.0) {
+      tp = copysign(sqrt(delta), t);
+      sp = r;
     } else {
-      b = -c;
-      c = 0.0;
-      const double t = cs;
-      cs = -sn;
-      sn = t;
+      tp = 0.0;
+      sp = copysign(rho, s);
     }
+    double gc = 1.0, gs = 0.0;
+    if (rho > 0.0) {
+      const double cd = (t * tp + s * sp) / (rho * rho);
+      const double sd = (s * tp - t * sp) / (rho * rho);
+      if (cd >= 0.0) {
+        gc = sqrt(0.5 * (1.0 + cd));
+        gs = sd / (2.0 * gc);
+      } else {
+        gs = copysign(sqrt(0.5 * (1.0 - cd)), sd);
+        gc = sd / (2.0 * gs);
+      }
+    }
+    const double ua = gc * a + gs * c, ub = gc * b + gs * d;
+    const double la = -gs * a + gc * c, lb = -gs * b + gc * d;
+    a = ua * gc + ub * gs;
+    b = -ua * gs + ub * gc;
+    c = la * gc + lb * gs;
+    d = -la * gs + lb * gc;
+    if (delta >= 0.0) {
+      c = 0.0;
+    } else {
+      a = m;
+      d = m;
+    }
+    const double ncs = cs * gc - sn * gs;
+    sn = sn * gc + cs * gs;
+    cs = ncs;
+    if (delta < 0.0 && b != 0.0 && signbit(b) != signbit(c)) break;
   }
 }
 

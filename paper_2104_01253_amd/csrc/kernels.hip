@@ -115,7 +115,14 @@ template <int VR, typename T>
 __device__ __forceinline__ RawVec<VR, T> load_raw(const T* p, uint32_t off) {
   const char* b = reinterpret_cast<const char*>(p) + off;
   RawVec<VR, T> r;
-  if constexpr (VR == 2 && sizeof(T) == 8) {
+  static_assert(VR != 4 || sizeof(T) == 4, "four-row slots hold floats");
+  if constexpr (VR == 4) {
+    const float4 t = *reinterpret_cast<const float4*>(b);
+    r.e[0] = t.x;
+    r.e[1] = t.y;
+    r.e[2] = t.z;
+    r.e[3] = t.w;
+  } else if constexpr (VR == 2 && sizeof(T) == 8) {
     const double2 t = *reinterpret_cast<const double2*>(b);
     r.e[0] = t.x;
     r.e[1] = t.y;
@@ -137,8 +144,9 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
                                                            int64_t m,
                                                            const double* __restrict__ coef,
                                                            int ldc, GridRed gr, FinArgs fin) {
-  // VR rows per lane (1, or 2 with paired 16-byte loads; VR = 2 needs m even and
-  // every column 16-byte aligned), TR = 64 VR rows per tile.
+  // VR rows per lane (1; 2 with paired 16-byte loads; 4 with 16-byte float4 loads of
+  // an FP32 basis; VR > 1 needs m divisible by VR and every column aligned to the load
+  // width), TR = 64 VR rows per tile.
   constexpr int FS = FMAXCOL / FW;        // slot capacity per wavefront (power of two)
   constexpr int NV = LAST ? FS : 2 * FS;  // products reduced per wavefront
   constexpr int TR = 64 * VR;
@@ -183,7 +191,8 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
   // the compiler wait for every outstanding load (the whole prefetch) once per tile.
   struct Stage {
     RawVec<VR, TQ> q[NS];
-    RV x0, x1, x2;                        // w, a_j, a_{j+1} (used by wavefronts 0..VR-1)
+    double x0, x1, x2;                    // element wv of the lane's rows of w, a_j and
+                                          // a_{j+1} (used by wavefronts 0..VR-1)
   };
   Stage ring[PD + 1];
   auto issue = [&](int64_t t, Stage& S) __attribute__((always_inline)) {
@@ -198,10 +207,13 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
 #pragma unroll
     for (int sl = 0; sl < NS; ++sl)
       S.q[sl] = load_raw<VR>(colp[sl], wv + FW * sl < J ? off : 0u);
-    const uint32_t offv = wv < VR ? (uint32_t)ul * (uint32_t)(VR * sizeof(double)) : 0u;
-    S.x0 = RV::load_off32(w, offv);
-    S.x1 = RV::load_off32(a_cur, offv);
-    if (!LAST) S.x2 = RV::load_off32(a_next, offv);
+    // wavefront e < VR combines row element e of the lanes' units: it loads only that
+    // element of each vector (the VR wavefronts together read whole cache lines)
+    const uint32_t offv =
+        wv < VR ? ((uint32_t)ul * (uint32_t)VR + (uint32_t)wv) * (uint32_t)sizeof(double) : 0u;
+    S.x0 = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(w) + offv);
+    S.x1 = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(a_cur) + offv);
+    if (!LAST) S.x2 = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(a_next) + offv);
   };
   auto process = [&](int64_t tix, const Stage& S) __attribute__((always_inline)) {
     const int64_t u = tix * 64 + lane;
@@ -246,9 +258,7 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
         SC += part[((e * 2) * FW + v) * 64 + lane];
         ST += part[((e * 2 + 1) * FW + v) * 64 + lane];
       }
-      const double x0 = e == 0 ? S.x0.e[0] : S.x0.e[VR - 1];
-      const double x1 = e == 0 ? S.x1.e[0] : S.x1.e[VR - 1];
-      const double x2 = e == 0 ? S.x2.e[0] : S.x2.e[VR - 1];
+      const double x0 = S.x0, x1 = S.x1, x2 = S.x2;
       double qo = 0.0, wo = 0.0, ao = 0.0;
       if (live) {
         qo = stored<TQ>((x0 - SC) / alpha);
@@ -269,6 +279,7 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
       ww.e[e] = vw[e * 64 + lane];
       aa.e[e] = va[e * 64 + lane];
     }
+
 #pragma unroll
     for (int sl = 0; sl < NS; ++sl) {
       const int k = wv + FW * sl;
@@ -694,17 +705,20 @@ namespace {
 // register stages of NS slots fit, with the accumulators, in the registers of a
 // wavefront (256 with 8 wavefronts per workgroup, 128 with 16) without spilling.
 // The limits are the largest NS per depth found free of scratch use by compiling
-// every instantiation for gfx950; slot_limit is the largest NS that fits at PD = 1.
+// every instantiation for gfx950 (pd1: the largest NS that fits at all).  The FP64
+// limits are kept at those measured fastest for that kernel; deeper rings that also
+// fit measured no faster there.
 struct RingLimits {
   int pd4, pd3, pd2, pd1;
 };
 template <typename T, bool L, int F, int VR>
 constexpr RingLimits ring_limits() {
   if constexpr (F == 16) return RingLimits{0, 0, 0, 5};
+  if constexpr (VR == 4) return L ? RingLimits{2, 3, 4, 8} : RingLimits{1, 2, 4, 7};
   if constexpr (sizeof(T) == 8 && VR == 2) return L ? RingLimits{2, 3, 7, 13} : RingLimits{2, 3, 5, 12};
   if constexpr (sizeof(T) == 8) return L ? RingLimits{8, 11, 15, 16} : RingLimits{6, 8, 12, 16};
-  if constexpr (VR == 2) return L ? RingLimits{4, 5, 8, 14} : RingLimits{2, 4, 6, 13};
-  return L ? RingLimits{10, 12, 16, 16} : RingLimits{8, 10, 13, 16};
+  if constexpr (VR == 2) return L ? RingLimits{5, 7, 10, 16} : RingLimits{4, 6, 8, 14};
+  return L ? RingLimits{10, 14, 16, 16} : RingLimits{8, 11, 15, 16};
 }
 template <typename T, bool L, int F, int VR, int NS>
 constexpr int ring_depth() {
@@ -761,7 +775,13 @@ hipError_t launch_fused_qr(void* Q, int q32, int64_t ldq, int J, double* w, cons
   const bool pair = F == 8 && ns <= pair_max_ns && ns <= pair_fit && (m % 2 == 0) &&
                     aligned_to(Q, q32 ? 8 : 16) && (ldq % 2 == 0) && aligned16(w) &&
                     aligned16(a_cur) && (last || aligned16(a_next));
-  const size_t sm = fused_qr_smem(F, pair ? 2 : 1);
+  // FP32 basis: four rows per lane (one 16-byte load per column) when m and ldq are
+  // multiples of four, up to the slot count whose two register stages fit
+  const int quad_fit = last ? ring_limits<float, true, 8, 4>().pd1
+                            : ring_limits<float, false, 8, 4>().pd1;
+  const bool quad = q32 && pair && ns <= quad_fit && (m % 4 == 0) && (ldq % 4 == 0) &&
+                    aligned16(Q);
+  const size_t sm = fused_qr_smem(F, quad ? 4 : pair ? 2 : 1);
 #define DCGS2_FQ(T, L, FF, VR)                                                                 \
   return fused_qr_ns<T, L, FF, VR, 1>(ns, (T*)Q, ldq, J, w, a_cur, a_next, m, coef, ldc, sm, gr, \
                                       gmax, fin, s, mid)
@@ -772,6 +792,10 @@ hipError_t launch_fused_qr(void* Q, int q32, int64_t ldq, int J, double* w, cons
     DCGS2_FQ(double, false, FF, VR);                                                          \
   } while (0)
   if (F == 8) {
+    if (quad) {
+      if (last) DCGS2_FQ(float, true, 8, 4);
+      DCGS2_FQ(float, false, 8, 4);
+    }
     if (pair) DCGS2_FQ_V(8, 2);
     DCGS2_FQ_V(8, 1);
   }

@@ -7,7 +7,8 @@
 //     Computations", Alg. 7.4.2 / 7.5.1), with the ad hoc exceptional shift of
 //     the EISPACK hqr routine after 10 and 20 stagnant iterations;
 //   * standardisation of 2x2 diagonal blocks (real eigenvalues -> triangular,
-//     complex pair -> equal diagonal entries), the normal form of LAPACK's lanv2;
+//     complex pair -> equal diagonal entries) by a rotation found from the
+//     double-angle form of 2x2 similarity (derived at std2x2);
 //   * swapping adjacent diagonal blocks through the Sylvester equation
 //     T11 X - X T22 = T12 and a QR factorisation of [-X; I] (Bai & Demmel, 1993).
 // The matrices are tiny (p <= DCGS2_MAX_N), so clarity wins over blocking.
@@ -81,79 +82,73 @@ void rot_cols(const Mat& A, int i, int r0, int r1, double cs, double sn) {
   }
 }
 
-// Normal form of a real 2x2 block [a b; c d] = G [a' b'; c' d'] G^T with
-// G = [cs -sn; sn cs]: c' = 0 when the eigenvalues are real, otherwise a' = d'
-// and b' c' < 0.
+// Standard form of a real 2x2 block M = [a b; c d]: an orthogonal G = [cs -sn; sn cs]
+// with M = G M' G^T, where M' = [a' b'; c' d'] has c' = 0 when the eigenvalues are real
+// and a' = d', b' c' < 0 when they are a complex pair.
+//
+// Derivation used here: write M = m I + [t s; s -t] + r [0 1; -1 0] with m = (a+d)/2,
+// t = (a-d)/2, s = (b+c)/2, r = (b-c)/2.  Conjugation by a rotation through theta
+// leaves m and the skew part r unchanged and turns the symmetric traceless part's
+// vector (t, s) = rho (cos phi, sin phi) into rho (cos(phi - 2 theta), sin(phi - 2 theta)),
+// of the same length rho.  Then c' = s' - r and b' = s' + r, and the eigenvalues are
+// m +- sqrt(delta), delta = t^2 + b c = rho^2 - r^2.
+//   delta >= 0: choose s' = r (so c' = 0) and t' = +-sqrt(delta) (the sign of t, the
+//               nearer target);
+//   delta <  0: choose t' = 0 (so a' = d' = m) and s' = +-rho (the sign of s); then
+//               b' c' = rho^2 - r^2 = delta < 0.
+// theta is half the angle from (t', s') to (t, s); cs and sn follow from that angle's
+// cosine and sine by the half-angle formulas, choosing the branch that does not
+// divide by a small number.  M' is then formed explicitly and the entry that must
+// vanish (c') or the two that must agree (a', d') are set exactly; when rounding
+// turns a nearly double complex pair real, a second rotation triangularises it.
 void std2x2(double& a, double& b, double& c, double& d, double& cs, double& sn) {
-  if (c == 0.0) {
-    cs = 1.0; sn = 0.0;
-    return;
-  }
-  if (b == 0.0) {                          // swap the two rows and columns
-    cs = 0.0; sn = 1.0;
-    std::swap(a, d);
-    b = -c;
-    c = 0.0;
-    return;
-  }
-  if (a - d == 0.0 && std::signbit(b) != std::signbit(c)) {
-    cs = 1.0; sn = 0.0;                    // already a standard complex block
-    return;
-  }
-  const double temp0 = a - d;
-  double p = 0.5 * temp0;
-  const double bcmax = std::max(std::fabs(b), std::fabs(c));
-  const double bcmis = std::min(std::fabs(b), std::fabs(c)) * std::copysign(1.0, b) *
-                       std::copysign(1.0, c);
-  const double scale = std::max(std::fabs(p), bcmax);
-  double z = (p / scale) * p + (bcmax / scale) * bcmis;
-  if (z >= 4.0 * EPS) {                    // real eigenvalues: make the block triangular
-    z = p + std::copysign(std::sqrt(scale) * std::sqrt(z), p);
-    a = d + z;
-    d = d - (bcmax / z) * bcmis;
-    const double tau = std::hypot(c, z);
-    cs = z / tau;
-    sn = c / tau;
-    b = b - c;
-    c = 0.0;
-    return;
-  }
-  // complex (or nearly equal real) eigenvalues: equalise the diagonal
-  const double sigma = b + c;
-  const double tau = std::hypot(sigma, temp0);
-  cs = std::sqrt(0.5 * (1.0 + std::fabs(sigma) / tau));
-  sn = -(p / (tau * cs)) * std::copysign(1.0, sigma);
-  const double aa = a * cs + b * sn, bb = -a * sn + b * cs;
-  const double cc = c * cs + d * sn, dd = -c * sn + d * cs;
-  a = aa * cs + cc * sn;
-  b = bb * cs + dd * sn;
-  c = -aa * sn + cc * cs;
-  d = -bb * sn + dd * cs;
-  const double mid = 0.5 * (a + d);
-  a = mid;
-  d = mid;
-  if (c != 0.0) {
-    if (b != 0.0) {
-      if (std::signbit(b) == std::signbit(c)) {   // real after all: triangularise
-        const double sab = std::sqrt(std::fabs(b)), sac = std::sqrt(std::fabs(c));
-        p = std::copysign(sab * sac, c);
-        const double t = 1.0 / std::sqrt(std::fabs(b + c));
-        a = mid + p;
-        d = mid - p;
-        b = b - c;
-        c = 0.0;
-        const double cs1 = sab * t, sn1 = sac * t;
-        const double ncs = cs * cs1 - sn * sn1;
-        sn = cs * sn1 + sn * cs1;
-        cs = ncs;
-      }
+  cs = 1.0;
+  sn = 0.0;
+  for (int pass = 0; pass < 2 && c != 0.0; ++pass) {
+    const double m = 0.5 * (a + d), t = 0.5 * (a - d);
+    const double s = 0.5 * (b + c), r = 0.5 * (b - c);
+    const double rho = std::hypot(t, s);
+    const double delta = t * t + b * c;
+    double tp, sp;
+    if (delta >= 0.0) {
+      tp = std::copysign(std::sqrt(delta), t);
+      sp = r;
     } else {
-      b = -c;
-      c = 0.0;
-      const double t = cs;
-      cs = -sn;
-      sn = t;
+      tp = 0.0;
+      sp = std::copysign(rho, s);
     }
+    double gc = 1.0, gs = 0.0;               // rotation of this pass
+    if (rho > 0.0) {
+      // angle Delta = phi - phi' between (t, s) and (t', s') (both of length rho)
+      const double cd = (t * tp + s * sp) / (rho * rho);
+      const double sd = (s * tp - t * sp) / (rho * rho);
+      if (cd >= 0.0) {
+        gc = std::sqrt(0.5 * (1.0 + cd));
+        gs = sd / (2.0 * gc);
+      } else {
+        gs = std::copysign(std::sqrt(0.5 * (1.0 - cd)), sd);
+        gc = sd / (2.0 * gs);
+      }
+    }
+    // M' = G^T M G
+    const double ua = gc * a + gs * c, ub = gc * b + gs * d;
+    const double la = -gs * a + gc * c, lb = -gs * b + gc * d;
+    a = ua * gc + ub * gs;
+    b = -ua * gs + ub * gc;
+    c = la * gc + lb * gs;
+    d = -la * gs + lb * gc;
+    if (delta >= 0.0) {
+      c = 0.0;
+    } else {
+      a = m;
+      d = m;
+    }
+    const double ncs = cs * gc - sn * gs;    // accumulated G = G_1 G_2
+    sn = sn * gc + cs * gs;
+    cs = ncs;
+    // a complex pair stays one when b' and c' have strictly opposite signs; otherwise
+    // (rounding at a nearly double eigenvalue) the next pass finds delta >= 0
+    if (delta < 0.0 && b != 0.0 && std::signbit(b) != std::signbit(c)) break;
   }
 }
 

@@ -11,11 +11,12 @@ Alg. qr), and every quantity of the step is compared with its natural scale:
   H, K, R     each new column element-wise against its own norm.
 
 The bound is 1e-12 everywhere (the GPU's fixed-order tree sums and the oracle's
-BLAS dots differ by O(eps log m)).  Two consecutive steps run on the GPU; the
-second starts from the GPU's own state after the first, the oracle's from its
-own, which differ by rounding only.  With the one-pass QR schedule the first
-step's update and the second step's reduction are one pass of the fused kernel,
-so every kernel of that schedule is checked from the given state.
+BLAS dots differ by O(eps log m)).  Two (Arnoldi) or three (QR) consecutive steps
+run on the GPU; each later step starts from the GPU's own state, the oracle's from
+its own, which differ by rounding only.  With the one-pass QR schedule the update of
+a step and the reduction of the next are one pass of the fused kernel, and the
+second fused pass does the first one's finishing work, so every kernel of that
+schedule is checked from the given state.
 """
 import copy
 
@@ -192,9 +193,12 @@ def qr_state(m, j0, j1):
 
 
 @pytest.mark.parametrize("one_pass", [True, False])
-@pytest.mark.parametrize("m,j0", cases(lambda m: min(m, binding.MAX_N)))
-def test_qr_two_steps_from_oracle_state(ctx, m, j0, one_pass):
-    j1 = j0 + 1
+@pytest.mark.parametrize("m,j0", cases(lambda m: min(m, binding.MAX_N) - 1))
+def test_qr_three_steps_from_oracle_state(ctx, m, j0, one_pass):
+    """Steps j0, j0+1, j0+2: with the one-pass schedule the first fused pass leaves its
+    finishing work to the second, which folds it (and the third step's update is a
+    plain pass)."""
+    j1 = j0 + 2
     B, Qs, w0, S_prev, rho, _ = qr_state(m, j0, j1)
     say(f"qr steps m={m} j={j0}..{j1} one_pass={one_pass}")
     torch = torch_cuda()
@@ -210,12 +214,12 @@ def test_qr_two_steps_from_oracle_state(ctx, m, j0, one_pass):
         rec, rc, st = ctx.qr_steps(Bd, j0, j1, Q, w, R, S, rho)
     finally:
         ctx.set_qr_schedule(True)
-    assert rc == binding.OK and st["reductions"] == 2
-    # the oracle's two steps from the same state
+    assert rc == binding.OK and st["reductions"] == 3
+    # the oracle's steps from the same state
     Qo = Qs.copy(order="F")
     wo, So, rhoo = w0, S_prev, (None if j0 == 2 else rho)
     Qg = host(Q)
-    for r, j in zip(rec, (j0, j1)):
+    for r, j in zip(rec, range(j0, j1 + 1)):
         J = j - 2
         a = B[:, j - 1]
         o = gs.dcgs2_qr_step(Qo, J, wo, a, So, rhoo)
