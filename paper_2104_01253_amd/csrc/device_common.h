@@ -597,12 +597,17 @@ __device__ void finish_body(const GridRed& gr, int V, const FinArgs& fin, int J)
 // sweep forms x^T x, x^T y and y^T y.  Partial layout (V values per workgroup):
 //   [0, Jt)   = [Q, x, y]^T x,   [Jt, 2 Jt) = [Q, x, y]^T y   (HASY, Jt = J + 2)
 //   [0, Jt)   = [Q, x]^T x                                      (Jt = J + 1)
-template <int VW, bool HASY, int NC, typename TQ>
+//
+// XS: where x and y come from -- 0 the vectors, 1 the vectors, also copied into the
+// workgroup's LDS slab sx, sy (unit u at index u - u0), 2 that LDS copy.  Each thread
+// copies and later reads back the same units, so the copy needs no barrier.  x, y
+// themselves serve the odd last row.
+template <int VW, bool HASY, int NC, typename TQ, int XS>
 __device__ __forceinline__ void reduce_sweep(const TQ* __restrict__ Q, int64_t ldq, int k0,
                                              const double* __restrict__ x,
-                                             const double* __restrict__ y, int64_t u0,
-                                             int64_t u1, bool tail, int64_t m, double* shb,
-                                             double* P, int Jt) {
+                                             const double* __restrict__ y, double* sx,
+                                             double* sy, int64_t u0, int64_t u1, bool tail,
+                                             int64_t m, double* shb, double* P, int Jt) {
   constexpr int NA = HASY ? 2 * NC : NC;
   using RV = RowVec<VW>;
   double acc[NA];
@@ -610,8 +615,12 @@ __device__ __forceinline__ void reduce_sweep(const TQ* __restrict__ Q, int64_t l
   for (int c = 0; c < NA; ++c) acc[c] = 0.0;
   const TQ* __restrict__ qb = Q + (int64_t)k0 * ldq;
   for (int64_t u = u0 + threadIdx.x; u < u1; u += BS) {
-    const RV xv = RV::load(x, u);
-    const RV yv = HASY ? RV::load(y, u) : RV::zero();
+    const RV xv = XS == 2 ? RV::load(sx, u - u0) : RV::load(x, u);
+    const RV yv = !HASY ? RV::zero() : XS == 2 ? RV::load(sy, u - u0) : RV::load(y, u);
+    if (XS == 1) {
+      xv.store(sx, u - u0);
+      if (HASY) yv.store(sy, u - u0);
+    }
     RV q[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) q[c] = RV::load(qb + (int64_t)c * ldq, u);
@@ -634,19 +643,20 @@ __device__ __forceinline__ void reduce_sweep(const TQ* __restrict__ Q, int64_t l
   block_sum_t<NA, NC>(acc, shb, P + k0, NC, P + Jt + k0, HASY ? NC : 0);
 }
 
-template <int VW, bool HASY>
+template <int VW, bool HASY, bool LDSX>
 __device__ __forceinline__ void reduce_self(const double* __restrict__ x,
-                                            const double* __restrict__ y, int64_t u0, int64_t u1,
+                                            const double* __restrict__ y, const double* sx,
+                                            const double* sy, int64_t u0, int64_t u1,
                                             bool tail, int64_t m, double* shb, double* P, int J,
                                             int Jt) {
   using RV = RowVec<VW>;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};   // x.x, x.y, y.y, unused
 #pragma unroll 4
   for (int64_t u = u0 + threadIdx.x; u < u1; u += BS) {
-    const RV xv = RV::load(x, u);
+    const RV xv = LDSX ? RV::load(sx, u - u0) : RV::load(x, u);
     acc[0] += xv.dot(xv);
     if (HASY) {
-      const RV yv = RV::load(y, u);
+      const RV yv = LDSX ? RV::load(sy, u - u0) : RV::load(y, u);
       acc[1] += xv.dot(yv);
       acc[2] += yv.dot(yv);
     }
@@ -669,7 +679,14 @@ __device__ __forceinline__ void reduce_self(const double* __restrict__ x,
   }
 }
 
-template <int VW, bool HASY, typename TQ>
+// STAGED: the first column-group sweep also copies the workgroup's slab of x and y
+// into LDS (after the block-sum scratch), and the later sweeps and the final
+// x^T x, x^T y, y^T y read them there.  Read from HBM by every sweep, x and y are
+// fetched again each time: a slab is far larger than what stays in L2 while a sweep
+// streams its basis columns.
+constexpr int REDUCE_SCRATCH = NW * 2 * NT;   // doubles of block-sum scratch
+
+template <int VW, bool HASY, typename TQ, bool STAGED = false>
 __device__ __forceinline__ void reduce_body(const TQ* __restrict__ Q, int64_t ldq,
                                                     int J, const double* __restrict__ x,
                                                     const double* __restrict__ y, int64_t m,
@@ -677,30 +694,41 @@ __device__ __forceinline__ void reduce_body(const TQ* __restrict__ Q, int64_t ld
   extern __shared__ double smem[];
   if (fin.ctrl->state != ST_RUNNING) return;
   const int Jt = J + (HASY ? 2 : 1);
-  double* shb = smem;                       // NW * 2 * NT
+  double* shb = smem;                       // REDUCE_SCRATCH
   const int64_t units = m / VW;
   const int64_t per = (units + gr.G - 1) / gr.G;
   const int64_t u0 = (int64_t)bid * per;
   const int64_t u1 = min(units, u0 + per);
   const bool tail = (VW == 2) && (m & 1) && bid == gr.G - 1 && threadIdx.x == 0;
   double* P = gr.P1 + (int64_t)bid * gr.ldp;
+  double* sx = smem + REDUCE_SCRATCH;       // STAGED: per VW doubles of each vector
+  double* sy = sx + per * VW;
+  constexpr int XF = STAGED ? 1 : 0;        // the first sweep
+  constexpr int XN = STAGED ? 2 : 0;        // the later ones
+  // the groups in order 16 ... 16, 8, 4, 2, 1; the first one present copies the slab
   int k0 = 0;
-  for (; k0 + 16 <= J; k0 += 16)
-    reduce_sweep<VW, HASY, 16, TQ>(Q, ldq, k0, x, y, u0, u1, tail, m, shb, P, Jt);
-  if (k0 + 8 <= J) {
-    reduce_sweep<VW, HASY, 8, TQ>(Q, ldq, k0, x, y, u0, u1, tail, m, shb, P, Jt);
-    k0 += 8;
-  }
-  if (k0 + 4 <= J) {
-    reduce_sweep<VW, HASY, 4, TQ>(Q, ldq, k0, x, y, u0, u1, tail, m, shb, P, Jt);
-    k0 += 4;
-  }
-  if (k0 + 2 <= J) {
-    reduce_sweep<VW, HASY, 2, TQ>(Q, ldq, k0, x, y, u0, u1, tail, m, shb, P, Jt);
-    k0 += 2;
-  }
-  if (k0 + 1 <= J) reduce_sweep<VW, HASY, 1, TQ>(Q, ldq, k0, x, y, u0, u1, tail, m, shb, P, Jt);
-  reduce_self<VW, HASY>(x, y, u0, u1, tail, m, shb, P, J, Jt);
+  bool first = true;
+#define DCGS2_SWEEP(NC)                                                                  \
+  do {                                                                                   \
+    if (first)                                                                           \
+      reduce_sweep<VW, HASY, NC, TQ, XF>(Q, ldq, k0, x, y, sx, sy, u0, u1, tail, m, shb,  \
+                                         P, Jt);                                         \
+    else                                                                                 \
+      reduce_sweep<VW, HASY, NC, TQ, XN>(Q, ldq, k0, x, y, sx, sy, u0, u1, tail, m, shb,  \
+                                         P, Jt);                                         \
+    first = false;                                                                       \
+    k0 += NC;                                                                            \
+  } while (0)
+  while (k0 + 16 <= J) DCGS2_SWEEP(16);
+  if (k0 + 8 <= J) DCGS2_SWEEP(8);
+  if (k0 + 4 <= J) DCGS2_SWEEP(4);
+  if (k0 + 2 <= J) DCGS2_SWEEP(2);
+  if (k0 + 1 <= J) DCGS2_SWEEP(1);
+#undef DCGS2_SWEEP
+  if (STAGED && J > 0)
+    reduce_self<VW, HASY, true>(x, y, sx, sy, u0, u1, tail, m, shb, P, J, Jt);
+  else
+    reduce_self<VW, HASY, false>(x, y, sx, sy, u0, u1, tail, m, shb, P, J, Jt);
 }
 
 // u = x - Q_{0..J-1} C written to ubuf; ||u||^2 grid-reduced and finalised.

@@ -46,12 +46,12 @@ namespace {
 
 #include "device_common.h"
 
-template <int VW, bool HASY, typename TQ>
+template <int VW, bool HASY, typename TQ, bool STAGED>
 __global__ __launch_bounds__(BS) void reduce_kernel(const TQ* __restrict__ Q, int64_t ldq,
                                                     int J, const double* __restrict__ x,
                                                     const double* __restrict__ y, int64_t m,
                                                     GridRed gr, FinArgs fin) {
-  reduce_body<VW, HASY, TQ>(Q, ldq, J, x, y, m, gr, fin, blockIdx.x);
+  reduce_body<VW, HASY, TQ, STAGED>(Q, ldq, J, x, y, m, gr, fin, blockIdx.x);
 }
 
 template <int VW, typename TQ>
@@ -285,7 +285,12 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
       const int k = wv + FW * sl;
 #pragma unroll
       for (int e = 0; e < VR; ++e) {
-        const double val = (k < J) ? (double)S.q[sl].e[e]
+        // four-row slots: the basis element is widened to FP64 again here rather than
+        // kept widened across the tile's barriers (which would hold eight more registers
+        // per slot); the empty asm only hides the earlier conversion from the compiler
+        TQ qraw = S.q[sl].e[e];
+        if constexpr (VR == 4) asm volatile("" : "+v"(qraw));
+        const double val = (k < J) ? (double)qraw
                            : (k == J) ? qq.e[e]
                            : (k == J + 1) ? ww.e[e]
                            : (!LAST && k == J + 2) ? aa.e[e] : 0.0;
@@ -526,7 +531,23 @@ inline bool aligned_to(const void* p, unsigned a) {
   return (reinterpret_cast<uintptr_t>(p) & (uintptr_t)(a - 1)) == 0;
 }
 
-size_t reduce_smem() { return sizeof(double) * (size_t)(NW * 2 * NT); }
+size_t reduce_smem() { return sizeof(double) * (size_t)REDUCE_SCRATCH; }
+
+// LDS a reduction workgroup may use with its staged slab: the device's limit per
+// workgroup (queried once; 160 KiB on gfx950).
+size_t reduce_lds_cap() {
+  static size_t cap = 0;
+  if (cap == 0) {
+    int dev = 0, v = 0;
+    size_t c = 64 * 1024;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        v > 0)
+      c = (size_t)v;
+    cap = c;
+  }
+  return cap;
+}
 
 }  // namespace
 
@@ -625,15 +646,40 @@ hipError_t launch_finish(const GridRed& gr, int V, int J, const FinArgs& fin, hi
 }
 }  // namespace
 
+// A staged reduction may take more dynamic LDS than the default launch limit: raise the
+// limit of each staged instantiation to the cap once.
+template <int VW, bool HY, typename T>
+void allow_staged_lds() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&reduce_kernel<VW, HY, T, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)reduce_lds_cap());
+  });
+}
+
 hipError_t launch_reduce(const void* Q, int q32, int64_t ldq, int J, const double* x,
                          const double* y, int64_t m, const GridRed& gr, const FinArgs& fin,
                          hipStream_t s, hipEvent_t mid) {
   const bool vec = aligned_to(Q, q32 ? 8 : 16) && (ldq % 2 == 0) && aligned16(x) &&
                    (!y || aligned16(y));
-  const size_t sm = reduce_smem();
+  // stage the workgroup's slab of x (and y) in LDS when it fits: every sweep over a
+  // column group (and the final x^T x, x^T y, y^T y) then reads them there
+  const int64_t units = vec ? m / 2 : m;
+  const int64_t per = (units + gr.G - 1) / gr.G;
+  const size_t stage = sizeof(double) * (size_t)per * (vec ? 2 : 1) * (y ? 2 : 1);
+  const bool staged = J >= 1 && reduce_smem() + stage <= reduce_lds_cap();
+  const size_t sm = reduce_smem() + (staged ? stage : 0);
   const dim3 grid(gr.G), block(BS);
-#define DCGS2_RED(VW, HY, T) \
-  reduce_kernel<VW, HY, T><<<grid, block, sm, s>>>((const T*)Q, ldq, J, x, y, m, gr, fin)
+#define DCGS2_RED(VW, HY, T)                                                                  \
+  do {                                                                                        \
+    if (staged) {                                                                             \
+      allow_staged_lds<VW, HY, T>();                                                          \
+      reduce_kernel<VW, HY, T, true><<<grid, block, sm, s>>>((const T*)Q, ldq, J, x, y, m, gr, \
+                                                             fin);                            \
+    } else                                                                                    \
+      reduce_kernel<VW, HY, T, false><<<grid, block, sm, s>>>((const T*)Q, ldq, J, x, y, m,    \
+                                                              gr, fin);                       \
+  } while (0)
   if (q32) {
     if (y) { if (vec) DCGS2_RED(2, true, float); else DCGS2_RED(1, true, float); }
     else { if (vec) DCGS2_RED(2, false, float); else DCGS2_RED(1, false, float); }
@@ -714,7 +760,7 @@ struct RingLimits {
 template <typename T, bool L, int F, int VR>
 constexpr RingLimits ring_limits() {
   if constexpr (F == 16) return RingLimits{0, 0, 0, 5};
-  if constexpr (VR == 4) return L ? RingLimits{2, 3, 4, 8} : RingLimits{1, 2, 4, 7};
+  if constexpr (VR == 4) return L ? RingLimits{3, 4, 7, 13} : RingLimits{1, 3, 6, 11};
   if constexpr (sizeof(T) == 8 && VR == 2) return L ? RingLimits{2, 3, 7, 13} : RingLimits{2, 3, 5, 12};
   if constexpr (sizeof(T) == 8) return L ? RingLimits{8, 11, 15, 16} : RingLimits{6, 8, 12, 16};
   if constexpr (VR == 2) return L ? RingLimits{5, 7, 10, 16} : RingLimits{4, 6, 8, 14};
