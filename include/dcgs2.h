@@ -150,10 +150,21 @@ int dcgs2_set_qr_schedule(dcgs2_ctx ctx, int one_pass);
  *                           as the host work of one group of instances overlaps
  *                           the other group's expansion on the GPU).  Both follow
  *                           the same algorithms; results agree to rounding.
+ *  DCGS2_TUNE_MATVEC_FOLD : Arnoldi, GMRES and Krylov-Schur with a stencil operator:
+ *                           1 computes w = A q inside the step's reduction pass
+ *                           (x read once; needs m < 2^29, m even when the basis
+ *                           takes 16-byte row pairs, and LDS for a workgroup's
+ *                           slab of rows, else the separate matvec runs), 0 runs
+ *                           the matvec kernel first (default 1).  Bitwise the
+ *                           same results.
+ *  DCGS2_TUNE_UPDATE_GRID : upper bound on the workgroups of an update pass, each
+ *                           over a contiguous slab of rows, 1..65536, or 0 for
+ *                           automatic (default: one per CU with an FP64 basis,
+ *                           two with FP32).  Bitwise the same results.
  * Returns DCGS2_EINVAL for an unknown key or value. */
 enum { DCGS2_TUNE_FUSED_WAVES = 0, DCGS2_TUNE_REDUCE_GRID = 1, DCGS2_TUNE_FUSED_MIN_J = 2,
        DCGS2_TUNE_BATCH_REDUCE_ROWS = 3, DCGS2_TUNE_FUSED_PAIR_SLOTS = 4,
-       DCGS2_TUNE_BATCH_DENSE = 5 };
+       DCGS2_TUNE_BATCH_DENSE = 5, DCGS2_TUNE_MATVEC_FOLD = 6, DCGS2_TUNE_UPDATE_GRID = 7 };
 int dcgs2_set_tuning(dcgs2_ctx ctx, int32_t key, int32_t value);
 int dcgs2_get_tuning(dcgs2_ctx ctx, int32_t key, int32_t* value);
 

@@ -34,7 +34,7 @@ EXPORTS = ("dcgs2_create", "dcgs2_destroy", "dcgs2_set_tolerances", "dcgs2_qr", 
            "dcgs2_qr_noalloc", "dcgs2_arnoldi_batched",
            "gmres_batched")
 (TUNE_FUSED_WAVES, TUNE_REDUCE_GRID, TUNE_FUSED_MIN_J, TUNE_BATCH_REDUCE_ROWS,
- TUNE_FUSED_PAIR_SLOTS, TUNE_BATCH_DENSE) = 0, 1, 2, 3, 4, 5
+ TUNE_FUSED_PAIR_SLOTS, TUNE_BATCH_DENSE, TUNE_MATVEC_FOLD, TUNE_UPDATE_GRID) = range(8)
 
 
 class Stats(ctypes.Structure):

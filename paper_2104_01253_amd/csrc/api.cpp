@@ -48,6 +48,8 @@ struct dcgs2_ctx_s {
   int tune_batch_units = 1024;   // DCGS2_TUNE_BATCH_REDUCE_ROWS / 2
   int tune_pair_max_ns = 16;     // DCGS2_TUNE_FUSED_PAIR_SLOTS
   int tune_batch_host_dense = 1; // DCGS2_TUNE_BATCH_DENSE
+  int tune_matvec_fold = 1;      // DCGS2_TUNE_MATVEC_FOLD
+  int tune_update_grid = 0;      // DCGS2_TUNE_UPDATE_GRID (0: automatic)
   int64_t cap_m = 0;
   int64_t cap_qa = 0, cap_qb = 0;
   double *w = nullptr, *v = nullptr, *r = nullptr;
@@ -254,6 +256,16 @@ bool valid_op(const dcgs2_op* A) {
   }
 }
 
+DivMagic div_magic(uint32_t d) {
+  int l = 0;
+  while (l < 32 && ((uint64_t)1 << l) < d) ++l;
+  DivMagic g;
+  g.mul = (uint32_t)((((uint64_t)1 << 32) * (((uint64_t)1 << l) - d)) / d + 1);
+  g.sh1 = l < 1 ? l : 1;
+  g.sh2 = l > 1 ? l - 1 : 0;
+  return g;
+}
+
 OpDev to_dev(const dcgs2_op* A) {
   OpDev o;
   o.kind = A->kind;
@@ -262,6 +274,10 @@ OpDev to_dev(const dcgs2_op* A) {
   o.nx = A->nx; o.ny = A->ny; o.nz = A->kind == DCGS2_OP_STENCIL7 ? A->nz : 1;
   o.c0 = A->c0; o.cxm = A->cxm; o.cxp = A->cxp; o.cym = A->cym; o.cyp = A->cyp;
   o.czm = A->czm; o.czp = A->czp;
+  if (A->kind != DCGS2_OP_CSR) {
+    o.dx = div_magic((uint32_t)o.nx);
+    o.dy = div_magic((uint32_t)o.ny);
+  }
   return o;
 }
 
@@ -354,11 +370,18 @@ struct Expansion {
     hipStream_t s = c->stream;
     const double vm = 8.0 * (double)m;
     const double qb = q32 ? 4.0 * (double)m : vm;      // bytes of one basis column
-    if (!qr) KL(K_SPMV, spmv_bytes(), launch_spmv(op, wk.w, nullptr, wk.v, wk.ctrl, s));
-    KL(K_REDUCE, qb * J + 2 * vm,
-       launch_reduce(Q, q32, ldq, J, wk.w, ycol(j), m, gr, fin(kind, j, J), s, mid_));
+    if (!qr && c->tune_matvec_fold && reduce_mv_fits(Q, q32, ldq, wk.w, wk.v, m, op, gr)) {
+      // the matvec inside the reduction pass: x read once, y written (not read back)
+      KL(K_REDUCE, qb * J + 2 * vm,
+         launch_reduce_mv(Q, q32, ldq, J, wk.w, wk.v, m, op, gr, fin(kind, j, J), s, mid_));
+    } else {
+      if (!qr) KL(K_SPMV, spmv_bytes(), launch_spmv(op, wk.w, nullptr, wk.v, wk.ctrl, s));
+      KL(K_REDUCE, qb * J + 2 * vm,
+         launch_reduce(Q, q32, ldq, J, wk.w, ycol(j), m, gr, fin(kind, j, J), s, mid_));
+    }
     KL(K_UPDATE, qb * (J + 1) + 3 * vm,
-       launch_update(Q, q32, ldq, J, wk.w, ycol(j), nullptr, m, wk.coef, wk.ldc, !qr, 0, wk.ctrl, s));
+       launch_update(Q, q32, ldq, J, wk.w, ycol(j), nullptr, m, wk.coef, wk.ldc, !qr, 0, wk.ctrl, s,
+                     c->tune_update_grid));
     return DCGS2_OK;
   }
   int enqueue_fallback(int j) {
@@ -369,7 +392,8 @@ struct Expansion {
     KL(K_PROJNORM, qb * J + 2 * vm,
        launch_project_norm(Q, q32, ldq, J, wk.w, wk.r, m, gr, fin(FIN_FALLBACK, j, J), s, mid_));
     KL(K_UPDATE, qb * (J + 1) + 4 * vm,
-       launch_update(Q, q32, ldq, J, wk.w, ycol(j), wk.r, m, wk.coef, wk.ldc, !qr, 1, wk.ctrl, s));
+       launch_update(Q, q32, ldq, J, wk.w, ycol(j), wk.r, m, wk.coef, wk.ldc, !qr, 1, wk.ctrl, s,
+                     c->tune_update_grid));
     return DCGS2_OK;
   }
   // CGS2 finish of the last column: J final columns already in Q.
@@ -405,7 +429,7 @@ struct Expansion {
       if (last && J_last < 0) {
         KL(K_UPDATE, qb * (J + 1) + 3 * vm,
            launch_update(Q, q32, ldq, J, wk.w, ycol(j), nullptr, m, wk.coef, wk.ldc, 0, 0, wk.ctrl,
-                         s));
+                         s, c->tune_update_grid));
         break;
       }
       const FinArgs f = last ? fin(FIN_LAST1, j + 1, J + 1) : fin(FIN_STEP, j + 1, J + 1);
@@ -413,7 +437,7 @@ struct Expansion {
         // a short basis: the separate passes stream better than the tiled fused pass
         KL(K_UPDATE, qb * (J + 1) + 3 * vm,
            launch_update(Q, q32, ldq, J, wk.w, ycol(j), nullptr, m, wk.coef, wk.ldc, 0, 0, wk.ctrl,
-                         s));
+                         s, c->tune_update_grid));
         KL(K_REDUCE, qb * (J + 1) + (last ? 1 : 2) * vm,
            launch_reduce(Q, q32, ldq, J + 1, wk.w, last ? nullptr : ycol(j + 1), m, gr, f, s, mid_));
         continue;
@@ -588,6 +612,14 @@ int dcgs2_set_tuning(dcgs2_ctx c, int32_t key, int32_t value) {
       if (value != 0 && value != 1) return DCGS2_EINVAL;
       c->tune_batch_host_dense = value;
       return DCGS2_OK;
+    case DCGS2_TUNE_MATVEC_FOLD:
+      if (value != 0 && value != 1) return DCGS2_EINVAL;
+      c->tune_matvec_fold = value;
+      return DCGS2_OK;
+    case DCGS2_TUNE_UPDATE_GRID:
+      if (value < 0 || value > 65536) return DCGS2_EINVAL;
+      c->tune_update_grid = value;
+      return DCGS2_OK;
     default:
       return DCGS2_EINVAL;
   }
@@ -602,6 +634,8 @@ int dcgs2_get_tuning(dcgs2_ctx c, int32_t key, int32_t* value) {
     case DCGS2_TUNE_BATCH_REDUCE_ROWS: *value = 2 * c->tune_batch_units; return DCGS2_OK;
     case DCGS2_TUNE_FUSED_PAIR_SLOTS: *value = c->tune_pair_max_ns; return DCGS2_OK;
     case DCGS2_TUNE_BATCH_DENSE: *value = c->tune_batch_host_dense; return DCGS2_OK;
+    case DCGS2_TUNE_MATVEC_FOLD: *value = c->tune_matvec_fold; return DCGS2_OK;
+    case DCGS2_TUNE_UPDATE_GRID: *value = c->tune_update_grid; return DCGS2_OK;
     default: return DCGS2_EINVAL;
   }
 }
@@ -1314,6 +1348,8 @@ int batched_fallback(dcgs2_ctx c, const BatchedState& B, int b, Ctrl* out) {
   op.m = I.m;
   op.nx = I.nx; op.ny = I.ny; op.nz = 1;
   op.c0 = I.c0; op.cxm = I.cxm; op.cxp = I.cxp; op.cym = I.cym; op.cyp = I.cyp;
+  op.dx = div_magic((uint32_t)I.nx);
+  op.dy = div_magic((uint32_t)I.ny);
   e.op = op;
   e.ldh = B.ld;
   Work k;

@@ -679,14 +679,25 @@ __device__ __forceinline__ void reduce_self(const double* __restrict__ x,
   }
 }
 
-// STAGED: the first column-group sweep also copies the workgroup's slab of x and y
+// STAGE 1: the first column-group sweep also copies the workgroup's slab of x and y
 // into LDS (after the block-sum scratch), and the later sweeps and the final
 // x^T x, x^T y, y^T y read them there.  Read from HBM by every sweep, x and y are
 // fetched again each time: a slab is far larger than what stays in L2 while a sweep
-// streams its basis columns.
+// streams its basis columns.  STAGE 2: the slab is in LDS already (written there by
+// the same threads that read it back).  STAGE 0: every sweep reads x and y.
 constexpr int REDUCE_SCRATCH = NW * 2 * NT;   // doubles of block-sum scratch
 
-template <int VW, bool HASY, typename TQ, bool STAGED = false>
+// Rows [u0 VW, u1 VW) of workgroup bid of a reduction grid of G over m rows.
+template <int VW>
+__device__ __forceinline__ void reduce_slab(int64_t m, int G, int bid, int64_t* per,
+                                            int64_t* u0, int64_t* u1) {
+  const int64_t units = m / VW;
+  *per = (units + G - 1) / G;
+  *u0 = (int64_t)bid * *per;
+  *u1 = min(units, *u0 + *per);
+}
+
+template <int VW, bool HASY, typename TQ, int STAGE = 0>
 __device__ __forceinline__ void reduce_body(const TQ* __restrict__ Q, int64_t ldq,
                                                     int J, const double* __restrict__ x,
                                                     const double* __restrict__ y, int64_t m,
@@ -695,16 +706,14 @@ __device__ __forceinline__ void reduce_body(const TQ* __restrict__ Q, int64_t ld
   if (fin.ctrl->state != ST_RUNNING) return;
   const int Jt = J + (HASY ? 2 : 1);
   double* shb = smem;                       // REDUCE_SCRATCH
-  const int64_t units = m / VW;
-  const int64_t per = (units + gr.G - 1) / gr.G;
-  const int64_t u0 = (int64_t)bid * per;
-  const int64_t u1 = min(units, u0 + per);
+  int64_t per, u0, u1;
+  reduce_slab<VW>(m, gr.G, bid, &per, &u0, &u1);
   const bool tail = (VW == 2) && (m & 1) && bid == gr.G - 1 && threadIdx.x == 0;
   double* P = gr.P1 + (int64_t)bid * gr.ldp;
-  double* sx = smem + REDUCE_SCRATCH;       // STAGED: per VW doubles of each vector
+  double* sx = smem + REDUCE_SCRATCH;       // STAGE > 0: per VW doubles of each vector
   double* sy = sx + per * VW;
-  constexpr int XF = STAGED ? 1 : 0;        // the first sweep
-  constexpr int XN = STAGED ? 2 : 0;        // the later ones
+  constexpr int XF = STAGE;                 // the first sweep
+  constexpr int XN = STAGE > 0 ? 2 : 0;     // the later ones
   // the groups in order 16 ... 16, 8, 4, 2, 1; the first one present copies the slab
   int k0 = 0;
   bool first = true;
@@ -725,7 +734,7 @@ __device__ __forceinline__ void reduce_body(const TQ* __restrict__ Q, int64_t ld
   if (k0 + 2 <= J) DCGS2_SWEEP(2);
   if (k0 + 1 <= J) DCGS2_SWEEP(1);
 #undef DCGS2_SWEEP
-  if (STAGED && J > 0)
+  if (STAGE == 2 || (STAGE == 1 && J > 0))
     reduce_self<VW, HASY, true>(x, y, sx, sy, u0, u1, tail, m, shb, P, J, Jt);
   else
     reduce_self<VW, HASY, false>(x, y, sx, sy, u0, u1, tail, m, shb, P, J, Jt);
@@ -795,9 +804,64 @@ __device__ __forceinline__ void update_group(const TQ* __restrict__ Q, int64_t l
   }
 }
 
-// Update pass: q_{j-1} and w_j, one row unit per thread.  The basis columns are taken
-// in exact groups of 16, 8, 4, 2 and 1 (J = 16 q + the binary digits of the rest), so
-// that every load of a group is in flight together, as in the reduction sweeps.
+// Update of one row unit u: q_{j-1} and w_j.  The basis columns are taken in exact
+// groups of 16, 8, 4, 2 and 1 (J = 16 q + the binary digits of the rest), so that every
+// load of a group is in flight together, as in the reduction sweeps.
+template <int VW, bool ARN, bool QCOL, typename TQ>
+__device__ __forceinline__ void update_unit(const TQ* __restrict__ Q, int64_t ldq, int J,
+                                            double* __restrict__ x,
+                                            const double* __restrict__ y,
+                                            const double* __restrict__ ubuf,
+                                            const double* __restrict__ C,
+                                            const double* __restrict__ T, double alpha,
+                                            double tJ, TQ* __restrict__ qout, int64_t u) {
+  RowVec<VW> sc = RowVec<VW>::zero(), st = RowVec<VW>::zero();
+  int k0 = 0;
+  for (; k0 + 16 <= J; k0 += 16) update_group<16, VW, TQ>(Q, ldq, k0, u, C, T, sc, st);
+  if (k0 + 8 <= J) { update_group<8, VW, TQ>(Q, ldq, k0, u, C, T, sc, st); k0 += 8; }
+  if (k0 + 4 <= J) { update_group<4, VW, TQ>(Q, ldq, k0, u, C, T, sc, st); k0 += 4; }
+  if (k0 + 2 <= J) { update_group<2, VW, TQ>(Q, ldq, k0, u, C, T, sc, st); k0 += 2; }
+  if (k0 + 1 <= J) update_group<1, VW, TQ>(Q, ldq, k0, u, C, T, sc, st);
+  const RowVec<VW> xv = RowVec<VW>::load(x, u);
+  const RowVec<VW> yv = RowVec<VW>::load(y, u);
+  RowVec<VW> qc = RowVec<VW>::zero();
+  if (QCOL) qc = RowVec<VW>::load(ubuf, u);
+  RowVec<VW> qn, wn;
+#pragma unroll
+  for (int e = 0; e < VW; ++e) {
+    const double q = stored<TQ>(QCOL ? qc.e[e] / alpha : (xv.e[e] - sc.e[e]) / alpha);
+    const double yt = ARN ? yv.e[e] / alpha : yv.e[e];
+    qn.e[e] = q;
+    wn.e[e] = yt - fma(q, tJ, st.e[e]);
+  }
+  qn.store(qout, u);
+  wn.store(x, u);
+}
+
+// The odd last row of an update with two-row units.
+template <bool ARN, bool QCOL, typename TQ>
+__device__ __forceinline__ void update_last_row(const TQ* __restrict__ Q, int64_t ldq, int J,
+                                                double* __restrict__ x,
+                                                const double* __restrict__ y,
+                                                const double* __restrict__ ubuf, int64_t m,
+                                                const double* __restrict__ C,
+                                                const double* __restrict__ T, double alpha,
+                                                double tJ, TQ* __restrict__ qout) {
+  const int64_t r = m - 1;
+  double sc = 0.0, st = 0.0;
+  for (int k = 0; k < J; ++k) {
+    const double q = (double)Q[(int64_t)k * ldq + r];
+    sc = fma(q, C[k], sc);
+    st = fma(q, T[k], st);
+  }
+  const double q = stored<TQ>(QCOL ? ubuf[r] / alpha : (x[r] - sc) / alpha);
+  const double yt = ARN ? y[r] / alpha : y[r];
+  qout[r] = (TQ)q;
+  x[r] = yt - fma(q, tJ, st);
+}
+
+// Update pass: q_{j-1} and w_j, one row unit per thread of workgroup bid (the odd last
+// row with two-row units by the thread after the last unit).
 template <int VW, bool ARN, bool QCOL, typename TQ>
 __device__ __forceinline__ void update_body(TQ* __restrict__ Q, int64_t ldq, int J,
                                                     double* __restrict__ x,
@@ -813,40 +877,35 @@ __device__ __forceinline__ void update_body(TQ* __restrict__ Q, int64_t ldq, int
   const int64_t units = m / VW;
   const int64_t u = (int64_t)bid * BS + threadIdx.x;
   TQ* qout = Q + (int64_t)J * ldq;
-  if (u < units) {
-    RowVec<VW> sc = RowVec<VW>::zero(), st = RowVec<VW>::zero();
-    int k0 = 0;
-    for (; k0 + 16 <= J; k0 += 16) update_group<16, VW, TQ>(Q, ldq, k0, u, C, T, sc, st);
-    if (k0 + 8 <= J) { update_group<8, VW, TQ>(Q, ldq, k0, u, C, T, sc, st); k0 += 8; }
-    if (k0 + 4 <= J) { update_group<4, VW, TQ>(Q, ldq, k0, u, C, T, sc, st); k0 += 4; }
-    if (k0 + 2 <= J) { update_group<2, VW, TQ>(Q, ldq, k0, u, C, T, sc, st); k0 += 2; }
-    if (k0 + 1 <= J) update_group<1, VW, TQ>(Q, ldq, k0, u, C, T, sc, st);
-    const RowVec<VW> xv = RowVec<VW>::load(x, u);
-    const RowVec<VW> yv = RowVec<VW>::load(y, u);
-    RowVec<VW> qc = RowVec<VW>::zero();
-    if (QCOL) qc = RowVec<VW>::load(ubuf, u);
-    RowVec<VW> qn, wn;
-#pragma unroll
-    for (int e = 0; e < VW; ++e) {
-      const double q = stored<TQ>(QCOL ? qc.e[e] / alpha : (xv.e[e] - sc.e[e]) / alpha);
-      const double yt = ARN ? yv.e[e] / alpha : yv.e[e];
-      qn.e[e] = q;
-      wn.e[e] = yt - fma(q, tJ, st.e[e]);
-    }
-    qn.store(qout, u);
-    wn.store(x, u);
-  } else if (VW == 2 && (m & 1) && u == units) {
-    const int64_t r = m - 1;
-    double sc = 0.0, st = 0.0;
-    for (int k = 0; k < J; ++k) {
-      const double q = (double)Q[(int64_t)k * ldq + r];
-      sc = fma(q, C[k], sc);
-      st = fma(q, T[k], st);
-    }
-    const double q = stored<TQ>(QCOL ? ubuf[r] / alpha : (x[r] - sc) / alpha);
-    const double yt = ARN ? y[r] / alpha : y[r];
-    qout[r] = (TQ)q;
-    x[r] = yt - fma(q, tJ, st);
-  }
+  if (u < units)
+    update_unit<VW, ARN, QCOL, TQ>(Q, ldq, J, x, y, ubuf, C, T, alpha, tJ, qout, u);
+  else if (VW == 2 && (m & 1) && u == units)
+    update_last_row<ARN, QCOL, TQ>(Q, ldq, J, x, y, ubuf, m, C, T, alpha, tJ, qout);
+}
+
+// Update pass over slabs: workgroup bid of nb takes a contiguous slab of row units,
+// BS at a time (the odd last row by thread 0 of the last workgroup).
+template <int VW, bool ARN, bool QCOL, typename TQ>
+__device__ __forceinline__ void update_slab_body(TQ* __restrict__ Q, int64_t ldq, int J,
+                                                 double* __restrict__ x,
+                                                 const double* __restrict__ y,
+                                                 const double* __restrict__ ubuf, int64_t m,
+                                                 const double* __restrict__ coef, int ldc,
+                                                 const Ctrl* __restrict__ ctrl, int bid,
+                                                 int nb) {
+  if (ctrl->state != ST_RUNNING) return;
+  const double* __restrict__ C = coef;
+  const double* __restrict__ T = coef + ldc;
+  const double alpha = coef[2 * ldc];
+  const double tJ = T[J];
+  const int64_t units = m / VW;
+  const int64_t per = (units + nb - 1) / nb;
+  const int64_t u0 = (int64_t)bid * per;
+  const int64_t u1 = min(units, u0 + per);
+  TQ* qout = Q + (int64_t)J * ldq;
+  for (int64_t u = u0 + threadIdx.x; u < u1; u += BS)
+    update_unit<VW, ARN, QCOL, TQ>(Q, ldq, J, x, y, ubuf, C, T, alpha, tJ, qout, u);
+  if (VW == 2 && (m & 1) && bid == nb - 1 && threadIdx.x == 0)
+    update_last_row<ARN, QCOL, TQ>(Q, ldq, J, x, y, ubuf, m, C, T, alpha, tJ, qout);
 }
 

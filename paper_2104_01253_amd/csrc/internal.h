@@ -75,6 +75,17 @@ struct GridRed {
   int G, ldp;
 };
 
+// Unsigned 32-bit division by an invariant divisor d >= 1 as a multiply-high, two
+// shifts and two adds (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", PLDI 1994, unsigned case): with l = ceil(log2 d),
+// mul = floor(2^32 (2^l - d) / d) + 1, sh1 = min(l, 1), sh2 = max(l - 1, 0),
+// t = mulhi(mul, n) and n / d = (t + ((n - t) >> sh1)) >> sh2 for every n < 2^32.
+struct DivMagic {
+  uint32_t mul;
+  int sh1, sh2;
+};
+DivMagic div_magic(uint32_t d);
+
 struct OpDev {
   int kind;
   int64_t m;
@@ -82,6 +93,7 @@ struct OpDev {
   int64_t nnz;
   int nx, ny, nz;
   double c0, cxm, cxp, cym, cyp, czm, czp;
+  DivMagic dx, dy;              // stencils: division by nx and by ny
 };
 
 // ---- launchers (kernels.hip) -------------------------------------------------------
@@ -107,16 +119,28 @@ hipError_t launch_spmv(const OpDev& op, const double* x, const double* b, double
 hipError_t launch_reduce(const void* Q, int q32, int64_t ldq, int J, const double* x,
                          const double* y, int64_t m, const GridRed& gr, const FinArgs& fin,
                          hipStream_t s, hipEvent_t mid = nullptr);
+// The reduction of an Arnoldi step with the stencil matvec y = A x folded in: y is
+// written (as by launch_spmv with ctrl, b = nullptr) and the pass then reduces as
+// launch_reduce(.., x, y, ..), bitwise alike.  reduce_mv_fits tells whether the
+// operator (a stencil), the sizes (m < 2^29, no odd last row past 16-byte units) and
+// the LDS for the workgroup's slab allow it; launch_reduce_mv returns
+// hipErrorInvalidValue (nothing launched) when they do not.
+bool reduce_mv_fits(const void* Q, int q32, int64_t ldq, const double* x, const double* y,
+                    int64_t m, const OpDev& op, const GridRed& gr);
+hipError_t launch_reduce_mv(const void* Q, int q32, int64_t ldq, int J, const double* x,
+                            double* y, int64_t m, const OpDev& op, const GridRed& gr,
+                            const FinArgs& fin, hipStream_t s, hipEvent_t mid);
 // u = x - Q_{0..J-1} C written to ubuf; ||u||^2 grid-reduced and finalised.
 hipError_t launch_project_norm(const void* Q, int q32, int64_t ldq, int J, const double* x,
                                double* ubuf, int64_t m, const GridRed& gr, const FinArgs& fin,
                                hipStream_t s, hipEvent_t mid = nullptr);
 // q_{j-1} = (x - Q C)/alpha (or ubuf/alpha when qcol) into Q[:, J] (rounded to the
 // basis type), x <- yscale(y) - Q_{0..J-1} T - q T_J with the stored q,
-// yscale(y) = y/alpha (Arnoldi) or y (QR).
+// yscale(y) = y/alpha (Arnoldi) or y (QR).  At most `slabs` workgroups, each over a
+// contiguous slab of rows (0: automatic).
 hipError_t launch_update(void* Q, int q32, int64_t ldq, int J, double* x, const double* y,
                          const double* ubuf, int64_t m, const double* coef, int ldc, int arnoldi,
-                         int qcol, const Ctrl* ctrl, hipStream_t s);
+                         int qcol, const Ctrl* ctrl, hipStream_t s, int slabs = 0);
 // One-pass QR step: update of step j (q into Q[:, J], w <- w_j) fused with the
 // reduction of step j+1 over [Q_{0..J}, w_j, a_next]; last != 0 reduces only
 // [Q_{0..J}, w_j]^T w_j (a_next unused).  The launcher sizes the grid itself (one

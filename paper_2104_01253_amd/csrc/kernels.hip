@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
 #include <mutex>
 #include <type_traits>
 #include <utility>
@@ -51,7 +52,95 @@ __global__ __launch_bounds__(BS) void reduce_kernel(const TQ* __restrict__ Q, in
                                                     int J, const double* __restrict__ x,
                                                     const double* __restrict__ y, int64_t m,
                                                     GridRed gr, FinArgs fin) {
-  reduce_body<VW, HASY, TQ, STAGED>(Q, ldq, J, x, y, m, gr, fin, blockIdx.x);
+  reduce_body<VW, HASY, TQ, STAGED ? 1 : 0>(Q, ldq, J, x, y, m, gr, fin, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------------
+// Stencil rows (lexicographic grid, x fastest; out-of-grid neighbours are zero, as
+// for Dirichlet boundaries), shared by the matvec kernel and the reduction pass that
+// computes its own y = A x.
+
+__device__ __forceinline__ uint32_t div_by(uint32_t n, DivMagic g) {
+  const uint32_t t = __umulhi(g.mul, n);
+  return (t + ((n - t) >> g.sh1)) >> g.sh2;
+}
+
+// Loads the seven values of x that row i reads, in the order (z-, y-, x-, centre,
+// x+, y+, z+); an absent neighbour reads row i and is flagged false.  Grid
+// coordinates come from two divisions by the invariant nx and ny done as
+// multiplications.  OFF32: every byte offset into x fits 32 bits (m < 2^29), so the
+// loads take a 32-bit offset from one base register.
+template <bool OFF32>
+__device__ __forceinline__ void stencil_gather(const OpDev& op, const double* __restrict__ x,
+                                               uint32_t i, double (&v)[7], bool (&in)[7]) {
+  const uint32_t nx = op.nx, ny = op.ny, nz = op.nz;
+  const uint32_t sxy = nx * ny;
+  const uint32_t r = div_by(i, op.dx);            // i / nx
+  const uint32_t ix = i - r * nx;
+  const uint32_t iz = div_by(r, op.dy);           // i / (nx ny)
+  const uint32_t iy = r - iz * ny;
+  in[0] = nz > 1 && iz > 0;
+  in[1] = iy > 0;
+  in[2] = ix > 0;
+  in[3] = true;
+  in[4] = ix + 1 < nx;
+  in[5] = iy + 1 < ny;
+  in[6] = nz > 1 && iz + 1 < nz;
+  const uint32_t nb[7] = {i - sxy, i - nx, i - 1, i, i + 1, i + nx, i + sxy};
+#pragma unroll
+  for (int t = 0; t < 7; ++t) {
+    const uint32_t k = in[t] ? nb[t] : i;
+    if constexpr (OFF32)
+      v[t] = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(x) +
+                                              k * (uint32_t)sizeof(double));
+    else
+      v[t] = x[k];
+  }
+}
+
+// (A x)_i from the gathered values: terms in neighbour order, an absent term adds an
+// exact zero.
+__device__ __forceinline__ double stencil_sum(const OpDev& op, const double (&v)[7],
+                                              const bool (&in)[7]) {
+  const double c[7] = {op.czm, op.cym, op.cxm, op.c0, op.cxp, op.cyp, op.czp};
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t < 7; ++t) s = fma(in[t] ? c[t] : 0.0, v[t], s);
+  return s;
+}
+
+// Reduction pass of an Arnoldi step with the matvec folded in: y = A x for the
+// workgroup's slab (stored to y for the update pass and kept with x in LDS), then
+// [Q_{0..J-1}, x, y]^T [x, y] as reduce_kernel, every sweep reading x and y from LDS.
+// Needs a stencil operator, m < 2^29, no odd last row outside the units, and LDS for
+// the slab (checked by the launcher).  Bitwise the same y and partial sums as the
+// matvec kernel followed by reduce_kernel.
+template <int VW, typename TQ>
+__global__ __launch_bounds__(BS) void reduce_mv_kernel(const TQ* __restrict__ Q, int64_t ldq,
+                                                       int J, const double* __restrict__ x,
+                                                       double* __restrict__ y, int64_t m,
+                                                       OpDev op, GridRed gr, FinArgs fin) {
+  extern __shared__ double smem[];
+  if (fin.ctrl->state != ST_RUNNING) return;
+  int64_t per, u0, u1;
+  reduce_slab<VW>(m, gr.G, blockIdx.x, &per, &u0, &u1);
+  double* sx = smem + REDUCE_SCRATCH;
+  double* sy = sx + per * VW;
+  for (int64_t u = u0 + threadIdx.x; u < u1; u += BS) {
+    RowVec<VW> xv, yv;
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+      double v[7];
+      bool in[7];
+      stencil_gather<true>(op, x, (uint32_t)(u * VW + e), v, in);
+      xv.e[e] = v[3];
+      yv.e[e] = stencil_sum(op, v, in);
+    }
+    yv.store(y, u);
+    xv.store(sx, u - u0);
+    yv.store(sy, u - u0);
+  }
+  reduce_body<VW, true, TQ, 2>(Q, ldq, J, x, y, m, gr, fin, blockIdx.x);
 }
 
 template <int VW, typename TQ>
@@ -63,13 +152,15 @@ __global__ __launch_bounds__(BS) void project_norm_kernel(const TQ* __restrict__
 }
 
 template <int VW, bool ARN, bool QCOL, typename TQ>
-__global__ __launch_bounds__(BS) void update_kernel(TQ* __restrict__ Q, int64_t ldq, int J,
-                                                    double* __restrict__ x,
-                                                    const double* __restrict__ y,
-                                                    const double* __restrict__ ubuf, int64_t m,
-                                                    const double* __restrict__ coef, int ldc,
-                                                    const Ctrl* __restrict__ ctrl) {
-  update_body<VW, ARN, QCOL, TQ>(Q, ldq, J, x, y, ubuf, m, coef, ldc, ctrl, blockIdx.x);
+__global__ __launch_bounds__(BS) void update_slab_kernel(TQ* __restrict__ Q, int64_t ldq, int J,
+                                                         double* __restrict__ x,
+                                                         const double* __restrict__ y,
+                                                         const double* __restrict__ ubuf,
+                                                         int64_t m,
+                                                         const double* __restrict__ coef,
+                                                         int ldc, const Ctrl* __restrict__ ctrl) {
+  update_slab_body<VW, ARN, QCOL, TQ>(Q, ldq, J, x, y, ubuf, m, coef, ldc, ctrl, blockIdx.x,
+                                      gridDim.x);
 }
 
 // One-pass QR step (Alg. qr): the update of step j and the reduction of step j+1
@@ -395,48 +486,29 @@ __device__ __forceinline__ unsigned xcd_local_block() {
 // that fourteen loads are in flight per thread.
 constexpr int STENCIL_ROWS = 2;
 
+template <bool OFF32>
 __global__ __launch_bounds__(BS) void stencil_kernel(OpDev op, const double* __restrict__ x,
                                                      const double* __restrict__ b,
                                                      double* __restrict__ y,
                                                      const Ctrl* __restrict__ ctrl) {
-  const uint32_t nx = op.nx, ny = op.ny, nz = op.nz;
-  const int64_t sxy = (int64_t)nx * ny;
-  const int64_t base = (int64_t)xcd_local_block() * (BS * STENCIL_ROWS) + threadIdx.x;
+  const uint32_t m = (uint32_t)op.m;
+  const uint32_t base = xcd_local_block() * (BS * STENCIL_ROWS) + threadIdx.x;
   double v[STENCIL_ROWS][7];
   bool in[STENCIL_ROWS][7];
   // all loads first: an absent neighbour (or a row past m) reads a valid row
 #pragma unroll
   for (int h = 0; h < STENCIL_ROWS; ++h) {
-    const int64_t i0 = base + h * BS;
-    const int64_t i = i0 < op.m ? i0 : op.m - 1;
-    const uint32_t ii = (uint32_t)i;
-    const uint32_t ix = ii % nx;
-    const uint32_t r = ii / nx;
-    const uint32_t iy = r % ny;
-    const uint32_t iz = r / ny;
-    in[h][0] = nz > 1 && iz > 0;
-    in[h][1] = iy > 0;
-    in[h][2] = ix > 0;
-    in[h][3] = true;
-    in[h][4] = ix + 1 < nx;
-    in[h][5] = iy + 1 < ny;
-    in[h][6] = nz > 1 && iz + 1 < nz;
-    const int64_t off[7] = {-sxy, -(int64_t)nx, -1, 0, 1, (int64_t)nx, sxy};
-#pragma unroll
-    for (int t = 0; t < 7; ++t) v[h][t] = x[in[h][t] ? i + off[t] : i];
+    const uint32_t i0 = base + h * BS;
+    stencil_gather<OFF32>(op, x, i0 < m ? i0 : m - 1, v[h], in[h]);
   }
   // the control block is read while the loads are in flight; a stopped expansion
   // still exits before any store
   if (ctrl && ctrl->state != ST_RUNNING) return;
-  const double c[7] = {op.czm, op.cym, op.cxm, op.c0, op.cxp, op.cyp, op.czp};
 #pragma unroll
   for (int h = 0; h < STENCIL_ROWS; ++h) {
-    const int64_t i = base + h * BS;
-    if (i >= op.m) continue;
-    // terms in neighbour order; an absent term adds an exact zero
-    double s = 0.0;
-#pragma unroll
-    for (int t = 0; t < 7; ++t) s = fma(in[h][t] ? c[t] : 0.0, v[h][t], s);
+    const uint32_t i = base + h * BS;
+    if (i >= m) continue;
+    const double s = stencil_sum(op, v[h], in[h]);
     y[i] = b ? b[i] - s : s;
   }
 }
@@ -621,9 +693,18 @@ hipError_t launch_spmv(const OpDev& op, const double* x, const double* b, double
                        const Ctrl* ctrl, hipStream_t s) {
   if (op.kind == DCGS2_OP_CSR)
     csr_kernel<<<nblocks(op.m), BS, 0, s>>>(op, x, b, y, ctrl);
-  else
-    stencil_kernel<<<(unsigned)((op.m + BS * STENCIL_ROWS - 1) / (BS * STENCIL_ROWS)), BS, 0, s>>>(
-        op, x, b, y, ctrl);
+  else {
+    // row indices are 32-bit (m < 2^31, also past the last row of the grid), and the
+    // division constants must be set (mul >= 1 for every divisor)
+    const int64_t rows = BS * STENCIL_ROWS;
+    const int64_t nb = (op.m + rows - 1) / rows;
+    if (op.m < 1 || nb * rows >= ((int64_t)1 << 32) || op.dx.mul == 0 || op.dy.mul == 0)
+      return hipErrorInvalidValue;
+    if (op.m < ((int64_t)1 << 29))
+      stencil_kernel<true><<<(unsigned)nb, BS, 0, s>>>(op, x, b, y, ctrl);
+    else
+      stencil_kernel<false><<<(unsigned)nb, BS, 0, s>>>(op, x, b, y, ctrl);
+  }
   return hipGetLastError();
 }
 
@@ -646,6 +727,28 @@ hipError_t launch_finish(const GridRed& gr, int V, int J, const FinArgs& fin, hi
 }
 }  // namespace
 
+namespace {
+// Vector width of a reduction pass over these operands (2: 16-byte row units).
+int reduce_vw(const void* Q, int q32, int64_t ldq, const double* x, const double* y) {
+  return aligned_to(Q, q32 ? 8 : 16) && (ldq % 2 == 0) && aligned16(x) && (!y || aligned16(y))
+             ? 2 : 1;
+}
+
+size_t reduce_mv_smem(int vw, int64_t m, int G) {
+  const int64_t per = (m / vw + G - 1) / G;
+  return reduce_smem() + sizeof(double) * (size_t)per * vw * 2;
+}
+
+template <int VW, typename T>
+void allow_mv_lds() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&reduce_mv_kernel<VW, T>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)reduce_lds_cap());
+  });
+}
+}  // namespace
+
 // A staged reduction may take more dynamic LDS than the default launch limit: raise the
 // limit of each staged instantiation to the cap once.
 template <int VW, bool HY, typename T>
@@ -660,8 +763,7 @@ void allow_staged_lds() {
 hipError_t launch_reduce(const void* Q, int q32, int64_t ldq, int J, const double* x,
                          const double* y, int64_t m, const GridRed& gr, const FinArgs& fin,
                          hipStream_t s, hipEvent_t mid) {
-  const bool vec = aligned_to(Q, q32 ? 8 : 16) && (ldq % 2 == 0) && aligned16(x) &&
-                   (!y || aligned16(y));
+  const bool vec = reduce_vw(Q, q32, ldq, x, y) == 2;
   // stage the workgroup's slab of x (and y) in LDS when it fits: every sweep over a
   // column group (and the final x^T x, x^T y, y^T y) then reads them there
   const int64_t units = vec ? m / 2 : m;
@@ -692,6 +794,35 @@ hipError_t launch_reduce(const void* Q, int q32, int64_t ldq, int J, const doubl
   return launch_finish(gr, y ? 2 * Jt : Jt, J, fin, mid, s);
 }
 
+
+bool reduce_mv_fits(const void* Q, int q32, int64_t ldq, const double* x, const double* y,
+                    int64_t m, const OpDev& op, const GridRed& gr) {
+  if (op.kind == DCGS2_OP_CSR || op.m != m || m < 1 || m >= ((int64_t)1 << 29) ||
+      op.dx.mul == 0 || op.dy.mul == 0 || gr.G < 1)
+    return false;
+  const int vw = reduce_vw(Q, q32, ldq, x, y);
+  if (vw == 2 && (m & 1)) return false;       // no odd last row outside the units
+  return reduce_mv_smem(vw, m, gr.G) <= reduce_lds_cap();
+}
+
+hipError_t launch_reduce_mv(const void* Q, int q32, int64_t ldq, int J, const double* x,
+                            double* y, int64_t m, const OpDev& op, const GridRed& gr,
+                            const FinArgs& fin, hipStream_t s, hipEvent_t mid) {
+  if (!reduce_mv_fits(Q, q32, ldq, x, y, m, op, gr)) return hipErrorInvalidValue;
+  const int vw = reduce_vw(Q, q32, ldq, x, y);
+  const size_t sm = reduce_mv_smem(vw, m, gr.G);
+#define DCGS2_RMV(VW, T)                                                                     \
+  do {                                                                                       \
+    allow_mv_lds<VW, T>();                                                                   \
+    reduce_mv_kernel<VW, T><<<gr.G, BS, sm, s>>>((const T*)Q, ldq, J, x, y, m, op, gr, fin); \
+  } while (0)
+  if (q32) { if (vw == 2) DCGS2_RMV(2, float); else DCGS2_RMV(1, float); }
+  else { if (vw == 2) DCGS2_RMV(2, double); else DCGS2_RMV(1, double); }
+#undef DCGS2_RMV
+  const int Jt = J + 2;
+  return launch_finish(gr, 2 * Jt, J, fin, mid, s);
+}
+
 hipError_t launch_project_norm(const void* Q, int q32, int64_t ldq, int J, const double* x,
                                double* ubuf, int64_t m, const GridRed& gr, const FinArgs& fin,
                                hipStream_t s, hipEvent_t mid) {
@@ -708,13 +839,19 @@ hipError_t launch_project_norm(const void* Q, int q32, int64_t ldq, int J, const
 
 hipError_t launch_update(void* Q, int q32, int64_t ldq, int J, double* x, const double* y,
                          const double* ubuf, int64_t m, const double* coef, int ldc, int arnoldi,
-                         int qcol, const Ctrl* ctrl, hipStream_t s) {
+                         int qcol, const Ctrl* ctrl, hipStream_t s, int slabs) {
   const bool vec = aligned_to(Q, q32 ? 8 : 16) && (ldq % 2 == 0) && aligned16(x) &&
                    aligned16(y) && (!ubuf || aligned16(ubuf));
   const int64_t units = vec ? m / 2 : m;
-  const unsigned nb = nblocks(units + 1);
-#define DCGS2_UPD(VW, A, QC, T) \
-  update_kernel<VW, A, QC, T><<<nb, BS, 0, s>>>((T*)Q, ldq, J, x, y, ubuf, m, coef, ldc, ctrl)
+  // automatic: one slab per CU with an FP64 basis, two with an FP32 basis (half the
+  // bytes per load: more wavefronts keep as many bytes in flight); measured best at
+  // m = 2^21 among 256, 384, 512, 768, 1024, 2048 slabs and one row unit per thread
+  if (slabs == 0) slabs = device_cus() * (q32 ? 2 : 1);
+  const unsigned nb =
+      (unsigned)std::max<int64_t>(1, std::min<int64_t>(slabs, (units + BS - 1) / BS));
+#define DCGS2_UPD(VW, A, QC, T)                                                              \
+  update_slab_kernel<VW, A, QC, T><<<nb, BS, 0, s>>>((T*)Q, ldq, J, x, y, ubuf, m, coef, ldc, \
+                                                     ctrl)
 #define DCGS2_UPD_T(VW, T)                                                   \
   do {                                                                       \
     if (arnoldi) { if (qcol) DCGS2_UPD(VW, true, true, T); else DCGS2_UPD(VW, true, false, T); } \

@@ -103,14 +103,16 @@ def test_tuning_knobs(ctx):
                            (binding.TUNE_FUSED_MIN_J, (0, 16, 1024), (-1, 1025)),
                            (binding.TUNE_BATCH_REDUCE_ROWS, (512, 8192, 65536), (256, 3000, 131072)),
                            (binding.TUNE_FUSED_PAIR_SLOTS, (0, 5, 16), (-1, 17)),
-                           (binding.TUNE_BATCH_DENSE, (1, 0), (-1, 2))]:
+                           (binding.TUNE_BATCH_DENSE, (1, 0), (-1, 2)),
+                           (binding.TUNE_MATVEC_FOLD, (0, 1), (-1, 2)),
+                           (binding.TUNE_UPDATE_GRID, (0, 1, 512, 65536), (-1, 65537))]:
         for g in good:
             assert lib.dcgs2_set_tuning(h, key, g) == binding.OK
             assert lib.dcgs2_get_tuning(h, key, ctypes.byref(v)) == binding.OK and v.value == g
         for b in bad:
             assert lib.dcgs2_set_tuning(h, key, b) == E
-    assert lib.dcgs2_set_tuning(h, 6, 0) == E
-    assert lib.dcgs2_get_tuning(h, 6, ctypes.byref(v)) == E
+    assert lib.dcgs2_set_tuning(h, 8, 0) == E
+    assert lib.dcgs2_get_tuning(h, 8, ctypes.byref(v)) == E
 
 
 def test_tolerance_validation_and_status_strings(ctx):

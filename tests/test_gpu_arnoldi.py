@@ -32,7 +32,10 @@ def run_arnoldi(ctx, op, r0, n, ld=None):
 
 @pytest.mark.parametrize("grid,vel", [((32, 32), (10.0, 10.0)), ((31, 29), (3.0, 40.0)),
                                       ((7, 5, 3), (1.0, 2.0, 3.0)), ((40, 33, 17), (10., 10., 10.)),
-                                      ((1000, 1), (5.0, 0.0))])
+                                      ((1000, 1), (5.0, 0.0)), ((1, 1000), (0.0, 5.0)),
+                                      ((1, 1, 50), (0.0, 0.0, 2.0)), ((3, 1, 7), (1.0, 0.0, 4.0)),
+                                      ((129, 65, 9), (7.0, 3.0, 1.0)),
+                                      ((128, 128, 128), (10.0, 10.0, 10.0))])
 def test_matvec_parity(ctx, grid, vel):
     torch = torch_cuda()
     A = ops.convection_diffusion(grid, 1.0, vel)
@@ -190,3 +193,40 @@ def test_arnoldi_reduction_grid_parity(ctx, gmax):
     assert rc == 0 and st["reductions"] == n + 2
     assert colerr(H, ref["H"]) <= TOL
     assert colerr(Q, ref["Q"]) <= TOL
+
+
+@pytest.mark.parametrize("grid,vel", [((32, 32), (10.0, 10.0)), ((31, 29), (3.0, 40.0)),
+                                      ((40, 33, 17), (10.0, 10.0, 10.0)),
+                                      ((128, 128, 128), (10.0, 10.0, 10.0))])
+def test_matvec_fold_and_update_grid_bitwise(ctx, grid, vel):
+    """Launch shapes change no bit: the matvec inside the reduction pass against the
+    separate matvec kernel, and update passes over 1, 7, 256 and 65536 slabs, give
+    the same Q and H.  With an even m the folded pass runs (no matvec launches)."""
+    op = binding.stencil_op(grid, 1.0, vel)
+    m = op.m
+    n = 12 if m > 100000 else 30
+    r0 = synth.uniform_vector(m, 8)
+    runs = {}
+    for fold, ugrid in [(1, 0), (0, 0), (1, 1), (1, 7), (0, 256), (1, 65536)]:
+        say(f"arnoldi {grid} fold={fold} update_grid={ugrid}")
+        ctx.set_tuning(binding.TUNE_MATVEC_FOLD, fold)
+        ctx.set_tuning(binding.TUNE_UPDATE_GRID, ugrid)
+        try:
+            ctx.profile(True)
+            ctx.profile_read(reset=True)
+            Q, H, rc, st = run_arnoldi(ctx, op, r0, n)
+            prof = ctx.profile_read(reset=True)
+            ctx.profile(False)
+        finally:
+            ctx.set_tuning(binding.TUNE_MATVEC_FOLD, 1)
+            ctx.set_tuning(binding.TUNE_UPDATE_GRID, 0)
+        assert rc == 0 and st["reductions"] == n + 2
+        spmv = prof.get("spmv", {}).get("launches", 0)
+        if fold == 1 and m % 2 == 0:
+            assert spmv == 0
+        if fold == 0:
+            assert spmv >= n
+        runs[(fold, ugrid)] = (Q, H)
+    Q0, H0 = runs[(1, 0)]
+    for key, (Q, H) in runs.items():
+        assert np.array_equal(Q, Q0) and np.array_equal(H, H0), key
