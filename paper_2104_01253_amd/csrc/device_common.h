@@ -602,12 +602,19 @@ __device__ void finish_body(const GridRed& gr, int V, const FinArgs& fin, int J)
 // workgroup's LDS slab sx, sy (unit u at index u - u0), 2 that LDS copy.  Each thread
 // copies and later reads back the same units, so the copy needs no barrier.  x, y
 // themselves serve the odd last row.
-template <int VW, bool HASY, int NC, typename TQ, int XS>
+// A reduction without its own y (never called).
+struct NoY {
+  template <int VW>
+  __device__ void operator()(int64_t, RowVec<VW>&, RowVec<VW>&) const {}
+};
+
+template <int VW, bool HASY, int NC, typename TQ, int XS, class YF = NoY>
 __device__ __forceinline__ void reduce_sweep(const TQ* __restrict__ Q, int64_t ldq, int k0,
                                              const double* __restrict__ x,
                                              const double* __restrict__ y, double* sx,
                                              double* sy, int64_t u0, int64_t u1, bool tail,
-                                             int64_t m, double* shb, double* P, int Jt) {
+                                             int64_t m, double* shb, double* P, int Jt,
+                                             const YF& yf = YF{}) {
   constexpr int NA = HASY ? 2 * NC : NC;
   using RV = RowVec<VW>;
   double acc[NA];
@@ -615,9 +622,14 @@ __device__ __forceinline__ void reduce_sweep(const TQ* __restrict__ Q, int64_t l
   for (int c = 0; c < NA; ++c) acc[c] = 0.0;
   const TQ* __restrict__ qb = Q + (int64_t)k0 * ldq;
   for (int64_t u = u0 + threadIdx.x; u < u1; u += BS) {
-    const RV xv = XS == 2 ? RV::load(sx, u - u0) : RV::load(x, u);
-    const RV yv = !HASY ? RV::zero() : XS == 2 ? RV::load(sy, u - u0) : RV::load(y, u);
-    if (XS == 1) {
+    RV xv, yv;
+    if constexpr (XS == 3) {
+      yf(u, xv, yv);                       // x and y = A x of the unit (y stored by yf)
+    } else {
+      xv = XS == 2 ? RV::load(sx, u - u0) : RV::load(x, u);
+      yv = !HASY ? RV::zero() : XS == 2 ? RV::load(sy, u - u0) : RV::load(y, u);
+    }
+    if (XS == 1 || XS == 3) {
       xv.store(sx, u - u0);
       if (HASY) yv.store(sy, u - u0);
     }
@@ -684,7 +696,9 @@ __device__ __forceinline__ void reduce_self(const double* __restrict__ x,
 // x^T x, x^T y, y^T y read them there.  Read from HBM by every sweep, x and y are
 // fetched again each time: a slab is far larger than what stays in L2 while a sweep
 // streams its basis columns.  STAGE 2: the slab is in LDS already (written there by
-// the same threads that read it back).  STAGE 0: every sweep reads x and y.
+// the same threads that read it back).  STAGE 3: as STAGE 1, with x and y of each unit
+// given by yf (which computes y = A x and stores it), so that the matvec's loads
+// overlap the first sweep's.  STAGE 0: every sweep reads x and y.
 constexpr int REDUCE_SCRATCH = NW * 2 * NT;   // doubles of block-sum scratch
 
 // Rows [u0 VW, u1 VW) of workgroup bid of a reduction grid of G over m rows.
@@ -697,11 +711,12 @@ __device__ __forceinline__ void reduce_slab(int64_t m, int G, int bid, int64_t* 
   *u1 = min(units, *u0 + *per);
 }
 
-template <int VW, bool HASY, typename TQ, int STAGE = 0>
+template <int VW, bool HASY, typename TQ, int STAGE = 0, class YF = NoY>
 __device__ __forceinline__ void reduce_body(const TQ* __restrict__ Q, int64_t ldq,
                                                     int J, const double* __restrict__ x,
                                                     const double* __restrict__ y, int64_t m,
-                                                    const GridRed& gr, const FinArgs& fin, int bid) {
+                                                    const GridRed& gr, const FinArgs& fin, int bid,
+                                                    const YF& yf = YF{}) {
   extern __shared__ double smem[];
   if (fin.ctrl->state != ST_RUNNING) return;
   const int Jt = J + (HASY ? 2 : 1);
@@ -721,20 +736,28 @@ __device__ __forceinline__ void reduce_body(const TQ* __restrict__ Q, int64_t ld
   do {                                                                                   \
     if (first)                                                                           \
       reduce_sweep<VW, HASY, NC, TQ, XF>(Q, ldq, k0, x, y, sx, sy, u0, u1, tail, m, shb,  \
-                                         P, Jt);                                         \
+                                         P, Jt, yf);                                     \
     else                                                                                 \
       reduce_sweep<VW, HASY, NC, TQ, XN>(Q, ldq, k0, x, y, sx, sy, u0, u1, tail, m, shb,  \
-                                         P, Jt);                                         \
+                                         P, Jt, yf);                                     \
     first = false;                                                                       \
     k0 += NC;                                                                            \
   } while (0)
+  if (STAGE == 3 && J == 0) {               // no sweep: the slab is staged on its own
+    for (int64_t u = u0 + threadIdx.x; u < u1; u += BS) {
+      RowVec<VW> xv, yv;
+      yf(u, xv, yv);
+      xv.store(sx, u - u0);
+      yv.store(sy, u - u0);
+    }
+  }
   while (k0 + 16 <= J) DCGS2_SWEEP(16);
   if (k0 + 8 <= J) DCGS2_SWEEP(8);
   if (k0 + 4 <= J) DCGS2_SWEEP(4);
   if (k0 + 2 <= J) DCGS2_SWEEP(2);
   if (k0 + 1 <= J) DCGS2_SWEEP(1);
 #undef DCGS2_SWEEP
-  if (STAGE == 2 || (STAGE == 1 && J > 0))
+  if (STAGE >= 2 || (STAGE == 1 && J > 0))
     reduce_self<VW, HASY, true>(x, y, sx, sy, u0, u1, tail, m, shb, P, J, Jt);
   else
     reduce_self<VW, HASY, false>(x, y, sx, sy, u0, u1, tail, m, shb, P, J, Jt);

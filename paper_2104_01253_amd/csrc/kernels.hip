@@ -109,9 +109,10 @@ __device__ __forceinline__ double stencil_sum(const OpDev& op, const double (&v)
   return s;
 }
 
-// Reduction pass of an Arnoldi step with the matvec folded in: y = A x for the
-// workgroup's slab (stored to y for the update pass and kept with x in LDS), then
-// [Q_{0..J-1}, x, y]^T [x, y] as reduce_kernel, every sweep reading x and y from LDS.
+// Reduction pass of an Arnoldi step with the matvec folded in: [Q_{0..J-1}, x, y]^T
+// [x, y] as reduce_kernel, where y = A x is computed for the workgroup's slab (stored to
+// y for the update pass and kept with x in LDS for the sweeps) by the first column-group
+// sweep (FP64 basis) or before the sweeps (FP32 basis).
 // Needs a stencil operator, m < 2^29, no odd last row outside the units, and LDS for
 // the slab (checked by the launcher).  Bitwise the same y and partial sums as the
 // matvec kernel followed by reduce_kernel.
@@ -120,27 +121,37 @@ __global__ __launch_bounds__(BS) void reduce_mv_kernel(const TQ* __restrict__ Q,
                                                        int J, const double* __restrict__ x,
                                                        double* __restrict__ y, int64_t m,
                                                        OpDev op, GridRed gr, FinArgs fin) {
-  extern __shared__ double smem[];
-  if (fin.ctrl->state != ST_RUNNING) return;
-  int64_t per, u0, u1;
-  reduce_slab<VW>(m, gr.G, blockIdx.x, &per, &u0, &u1);
-  double* sx = smem + REDUCE_SCRATCH;
-  double* sy = sx + per * VW;
-  for (int64_t u = u0 + threadIdx.x; u < u1; u += BS) {
-    RowVec<VW> xv, yv;
+  auto yf = [&](int64_t u, RowVec<VW>& xv, RowVec<VW>& yv) __attribute__((always_inline)) {
+    double v[VW][7];
+    bool in[VW][7];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) stencil_gather<true>(op, x, (uint32_t)(u * VW + e), v[e], in[e]);
 #pragma unroll
     for (int e = 0; e < VW; ++e) {
-      double v[7];
-      bool in[7];
-      stencil_gather<true>(op, x, (uint32_t)(u * VW + e), v, in);
-      xv.e[e] = v[3];
-      yv.e[e] = stencil_sum(op, v, in);
+      xv.e[e] = v[e][3];
+      yv.e[e] = stencil_sum(op, v[e], in[e]);
     }
     yv.store(y, u);
-    xv.store(sx, u - u0);
-    yv.store(sy, u - u0);
+  };
+  if constexpr (sizeof(TQ) == 8) {
+    reduce_body<VW, true, TQ, 3>(Q, ldq, J, x, y, m, gr, fin, blockIdx.x, yf);
+  } else {
+    // FP32 basis: the matvec as a pass of its own over the slab before the sweeps
+    // (measured faster than inside the first sweep, unlike an FP64 basis)
+    extern __shared__ double smem[];
+    if (fin.ctrl->state != ST_RUNNING) return;
+    int64_t per, u0, u1;
+    reduce_slab<VW>(m, gr.G, blockIdx.x, &per, &u0, &u1);
+    double* sx = smem + REDUCE_SCRATCH;
+    double* sy = sx + per * VW;
+    for (int64_t u = u0 + threadIdx.x; u < u1; u += BS) {
+      RowVec<VW> xv, yv;
+      yf(u, xv, yv);
+      xv.store(sx, u - u0);
+      yv.store(sy, u - u0);
+    }
+    reduce_body<VW, true, TQ, 2>(Q, ldq, J, x, y, m, gr, fin, blockIdx.x);
   }
-  reduce_body<VW, true, TQ, 2>(Q, ldq, J, x, y, m, gr, fin, blockIdx.x);
 }
 
 template <int VW, typename TQ>

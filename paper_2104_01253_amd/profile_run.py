@@ -107,7 +107,8 @@ def _rows(d, pattern):
 
 
 # kernel name fragments -> the kernel classes of dcgs2_profile_read
-CLASSES = (("fused_qr_kernel", "fused_qr"), ("reduce_kernel", "reduce"), ("update_kernel", "update"),
+CLASSES = (("fused_qr_kernel", "fused_qr"), ("reduce_mv_kernel", "reduce"), ("reduce_kernel", "reduce"),
+           ("update_slab_kernel", "update"), ("update_kernel", "update"),
            ("project_norm_kernel", "project_norm"), ("scale_col_kernel", "scale"),
            ("stencil_kernel", "spmv"), ("csr_kernel", "spmv"), ("tsgemm_kernel", "tsgemm"),
            ("finish_kernel", "finish"), ("bschur_kernel", "dense_schur"),
