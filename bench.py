@@ -34,6 +34,7 @@ PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published
 METRIC = "DCGS2 Arnoldi steps/s + HBM GB/s (m=2M,n=100); GMRES time-to-1e-8 vs FP64"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 TRAFFIC_FILE_Q32 = os.path.join(ROOT, "profiles", "traffic_q32.json")
+TRAFFIC_FILE_ARNOLDI = os.path.join(ROOT, "profiles", "arnoldi_128cube_n100.json")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2104_01253_amd", "csrc", f)
                for f in ("kernels.hip", "device_common.h")]
 
@@ -75,14 +76,16 @@ def timed(torch, fn, steps):
     return e0.elapsed_time(e1) / 1000.0
 
 
-def kernel_roof(st):
-    """Algorithmic GB/s of one kernel class (bytes per launch over its mean duration)."""
+def kernel_roof(st, traffic=None):
+    """Algorithmic GB/s of one kernel class (bytes per launch over its mean duration),
+    with the counter-measured HBM bytes per launch when a record for these kernels
+    exists."""
     avg_ms = st["total_ms"] / max(st["launches"], 1)
     bytes_per_launch = st["bytes"] / max(st["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     return {"launches": st["launches"], "avg_launch_us": round(avg_ms * 1e3, 2),
             "alg_bytes_per_launch": bytes_per_launch, "achieved": round(achieved, 1),
-            "frac": round(achieved / PEAK_HBM_GBS, 4)}
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic}
 
 
 def roofline(prof, record=TRAFFIC_FILE):
@@ -454,8 +457,8 @@ def main():
             "steps_per_s": round(n / Ta, 1), "ms": round(Ta * 1e3, 3),
             "hbm_gbps": round(abytes / Ta / 1e9, 1),
             "roofline_by_kernel": {"bound": "hbm", "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                                   **{k: kernel_roof(v) for k, v in pa.items()
-                                      if v["launches"] > 0}}}
+                                   **{k: kernel_roof(v, measured_traffic(k, TRAFFIC_FILE_ARNOLDI))
+                                      for k, v in pa.items() if v["launches"] > 0}}}
         del Qa
         x = torch.zeros(prob.m, dtype=torch.float64, device="cuda")
 
