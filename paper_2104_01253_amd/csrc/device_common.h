@@ -209,6 +209,13 @@ __device__ void partial_sum(const double* __restrict__ P, int64_t ldp, int G, in
 
 __device__ __forceinline__ bool finite(double v) { return isfinite(v); }
 
+// Control-block fields that a finishing kernel reads before it writes any, loaded at
+// its start so that their latency overlaps that of the partial sums.
+struct CtrlSnap {
+  int state;
+  double rho_next, tau, eta;
+};
+
 // Deterministic dot product of two LDS/global vectors of length n by wavefront 0;
 // the result is broadcast through *out (LDS).  Call from all threads.
 __device__ void small_dot(const double* a, const double* b, int n, double* out) {
@@ -217,6 +224,31 @@ __device__ void small_dot(const double* a, const double* b, int n, double* out) 
     for (int i = threadIdx.x; i < n; i += 64) s = fma(a[i], b[i], s);
     s = wave_sum(s);
     if (threadIdx.x == 0) *out = s;
+  }
+  __syncthreads();
+}
+
+// The scalars of a DCGS2 step, by wavefront 0 in one pass: C^T C and C^T S (each
+// summed as small_dot sums it) and whether any of v[0..nv) is non-finite; broadcast
+// through out[0], out[1] and *flag (LDS).  Call from all threads.
+__device__ void step_scalars(const double* C, const double* S, int n, const double* v, int nv,
+                             double* out, int* flag) {
+  if (threadIdx.x < 64) {
+    double cc = 0.0, cs = 0.0;
+    for (int i = threadIdx.x; i < n; i += 64) {
+      cc = fma(C[i], C[i], cc);
+      cs = fma(C[i], S[i], cs);
+    }
+    int bad = 0;
+    for (int i = threadIdx.x; i < nv; i += 64) bad |= !finite(v[i]);
+    cc = wave_sum(cc);
+    cs = wave_sum(cs);
+    const bool any = __any(bad);
+    if (threadIdx.x == 0) {
+      out[0] = cc;
+      out[1] = cs;
+      *flag = any ? 1 : 0;
+    }
   }
   __syncthreads();
 }
@@ -290,18 +322,19 @@ __device__ void complete_h_column(const FinArgs& f, const double* C, int J, doub
 // -- H is completed before K is formed, as the derivation after eq. (52) requires;
 // or Alg. qr: R column and Stephen's trick).
 //   C, S : LDS vectors of length J; sigma, gamma, cs = C^T S; rho = breakdown scale.
-__device__ void step_tail(const FinArgs& f, const double* C, const double* S, double sigma,
-                          double gamma, double csum, double alpha, double rho, double* T,
-                          double* scratch) {
+//   sprev: S_prev (QR; an LDS copy in the finishing kernel)
+__device__ void step_tail(const FinArgs& f, const CtrlSnap& snap, const double* C, const double* S,
+                          double sigma, double gamma, double csum, double alpha, double rho,
+                          double* T, double* scratch, const double* sprev) {
   Ctrl* ctrl = f.ctrl;
   const int J = f.J, j = f.j;
   if (!finite(alpha)) {
     if (threadIdx.x == 0) { ctrl->state = ST_NONFINITE; ctrl->stop_step = j; }
     return;
   }
-  if (alpha <= ctrl->eta * rho) {                 // breakdown: close column j-2 and stop
+  if (alpha <= snap.eta * rho) {                  // breakdown: close column j-2 and stop
     if (f.qr) {
-      for (int i = threadIdx.x; i < J; i += (int)blockDim.x) f.R[(int64_t)J * f.ldr + i] = f.Sprev[i] + C[i];
+      for (int i = threadIdx.x; i < J; i += (int)blockDim.x) f.R[(int64_t)J * f.ldr + i] = sprev[i] + C[i];
       if (threadIdx.x == 0) f.R[(int64_t)J * f.ldr + J] = alpha;
       __syncthreads();
       if (threadIdx.x == 0) ctrl->k = J;
@@ -332,9 +365,8 @@ __device__ void step_tail(const FinArgs& f, const double* C, const double* S, do
   if (threadIdx.x == 0) f.coef[2 * f.ldc] = alpha;
   if (f.qr) {
     // R_{1:j-2, j-1} = S_{1:j-2, j-1} + C ; R_{j-1,j-1} = alpha ; keep S_{1:j-1, j}
-    for (int i = threadIdx.x; i < J; i += (int)blockDim.x) f.R[(int64_t)J * f.ldr + i] = f.Sprev[i] + C[i];
+    for (int i = threadIdx.x; i < J; i += (int)blockDim.x) f.R[(int64_t)J * f.ldr + i] = sprev[i] + C[i];
     if (threadIdx.x == 0) f.R[(int64_t)J * f.ldr + J] = alpha;
-    __syncthreads();
     for (int i = threadIdx.x; i <= J; i += (int)blockDim.x) f.Sprev[i] = T[i];
     if (threadIdx.x == 0) { ctrl->k = J + 1; ctrl->rho_next = sqrt(gamma); }
   } else {
@@ -344,6 +376,8 @@ __device__ void step_tail(const FinArgs& f, const double* C, const double* S, do
     // K_{1:j-1, j-1} = T - (1/alpha) H_{1:j-1, 1:j-2} C   (dense product).  Each row's
     // dot product is split over CH threads (column chunks, then the chunk partials
     // in order), so the chain of dependent global loads per thread stays short.
+    // (Chunks over every thread of the workgroup, with 16 loads in flight, measured
+    // slower.)
     {
       const int R = J + 1;
       const int cap = 3 * (J + 2) + 64;         // doubles of scratch
@@ -377,8 +411,11 @@ __device__ void step_tail(const FinArgs& f, const double* C, const double* S, do
   __syncthreads();
 }
 
-// The finalising workgroup: red[] holds the grid-reduced values of this kernel.
-__device__ void finalize(const FinArgs& f, double* red, double* T, double* scratch) {
+// The finalising workgroup: red[] holds the grid-reduced values of this kernel; snap
+// the control block as it was at the kernel's start; sprev: S_prev (QR steps and their
+// fallback completion; an LDS copy).
+__device__ void finalize(const FinArgs& f, const CtrlSnap& snap, double* red, double* T,
+                         double* scratch, const double* sprev) {
   Ctrl* ctrl = f.ctrl;
   const int J = f.J, j = f.j;
   __shared__ double s_dot[2];
@@ -421,14 +458,14 @@ __device__ void finalize(const FinArgs& f, double* red, double* T, double* scrat
       if (threadIdx.x == 0) {
         ctrl->reductions += 1;
         const double alpha = sqrt(red[0]);
-        const double rho = j == 0 ? alpha : ctrl->rho_next;
+        const double rho = j == 0 ? alpha : snap.rho_next;
         if (!finite(alpha)) {
           ctrl->state = ST_NONFINITE;
           ctrl->stop_step = j;
         } else {
           f.R[(int64_t)j * f.ldr + j] = alpha;
           f.coef[2 * f.ldc] = alpha;
-          if (alpha <= ctrl->eta * rho || alpha == 0.0) {
+          if (alpha <= snap.eta * rho || alpha == 0.0) {
             ctrl->state = ST_BREAKDOWN;
             ctrl->stop_step = j;
             ctrl->k = j;
@@ -459,7 +496,7 @@ __device__ void finalize(const FinArgs& f, double* red, double* T, double* scrat
       }
       for (int i = threadIdx.x; i < J; i += (int)blockDim.x) T[i] = c[i];   // c into LDS
       __syncthreads();
-      const bool brk = alpha <= ctrl->eta * ctrl->rho_next;
+      const bool brk = alpha <= snap.eta * snap.rho_next;
       if (f.qr) {
         for (int i = threadIdx.x; i < J; i += (int)blockDim.x) f.R[(int64_t)J * f.ldr + i] = f.Sprev[i] + T[i];
         if (threadIdx.x == 0) {
@@ -506,17 +543,15 @@ __device__ void finalize(const FinArgs& f, double* red, double* T, double* scrat
       const double* S = red + Jt;
       const double sigma = red[Jt + J];
       const double gamma = red[Jt + J + 1];
-      any_nonfinite(red, 2 * Jt, &s_flag);
+      step_scalars(C, S, J, red, 2 * Jt, s_dot, &s_flag);
       if (s_flag) {
         if (threadIdx.x == 0) { ctrl->state = ST_NONFINITE; ctrl->stop_step = j; ctrl->reductions += 1; }
         return;
       }
-      small_dot(C, C, J, &s_dot[0]);
-      small_dot(C, S, J, &s_dot[1]);
-      const double rho = (j == 2) ? sqrt(beta) : ctrl->rho_next;
+      const double rho = (j == 2) ? sqrt(beta) : snap.rho_next;
       const double d = beta - s_dot[0];
       if (threadIdx.x == 0) ctrl->reductions += 1;
-      if (!(finite(d) && d > ctrl->tau * beta)) {
+      if (!(finite(d) && d > snap.tau * beta)) {
         // hand the reduced step over to the explicit-norm fallback (run by the host)
         for (int i = threadIdx.x; i < J; i += (int)blockDim.x) {
           f.pend[i] = C[i];
@@ -532,7 +567,7 @@ __device__ void finalize(const FinArgs& f, double* red, double* T, double* scrat
         }
         return;
       }
-      step_tail(f, C, S, sigma, gamma, s_dot[1], sqrt(d), rho, T, scratch);
+      step_tail(f, snap, C, S, sigma, gamma, s_dot[1], sqrt(d), rho, T, scratch, sprev);
       return;
     }
     case FIN_FALLBACK: {
@@ -543,9 +578,9 @@ __device__ void finalize(const FinArgs& f, double* red, double* T, double* scrat
       __syncthreads();
       const double sigma = f.pend[2 * J], gamma = f.pend[2 * J + 1], beta = f.pend[2 * J + 2];
       small_dot(C, S, J, &s_dot[1]);
-      const double rho = (j == 2) ? sqrt(beta) : ctrl->rho_next;
+      const double rho = (j == 2) ? sqrt(beta) : snap.rho_next;
       if (threadIdx.x == 0) { ctrl->reductions += 1; ctrl->fallbacks += 1; }
-      step_tail(f, C, S, sigma, gamma, s_dot[1], alpha, rho, T, scratch + 2 * J);
+      step_tail(f, snap, C, S, sigma, gamma, s_dot[1], alpha, rho, T, scratch + 2 * J, sprev);
       return;
     }
   }
@@ -559,7 +594,7 @@ constexpr int FINISH_BS = 1024;
 // partial_sum (max(V, FINISH_BS)).
 __host__ __device__ inline size_t finish_smem(int V, int J) {
   const int Jp = J + 3;
-  return sizeof(double) * (size_t)(V + Jp + 5 * Jp + 64 + (V > FINISH_BS ? V : FINISH_BS));
+  return sizeof(double) * (size_t)(V + Jp + 5 * Jp + 64 + (V > FINISH_BS ? V : FINISH_BS) + Jp);
 }
 
 // Second half of every DCGS2 reduction, run by a single workgroup after the
@@ -574,14 +609,23 @@ __device__ void finish_body(const GridRed& gr, int V, const FinArgs& fin, int J)
   double* red = smem;                     // V
   double* T = red + V;                    // J + 3
   double* scratch = T + (J + 3);          // 5 (J + 3) + 64
-  double* sp = scratch + 5 * (J + 3) + 64;
-  // the sums only touch LDS: they are formed before the control block is read, so
-  // that the two memory latencies overlap (a stopped expansion still returns here)
-  partial_sum(gr.P1, gr.ldp, gr.G, V, red, sp);
-  if (fin.ctrl->state != ST_RUNNING) return;
+  double* sp = scratch + 5 * (J + 3) + 64;        // max(V, FINISH_BS)
+  double* sprev = sp + (V > FINISH_BS ? V : FINISH_BS);   // J + 3
+  // the control block and (QR) S_prev are read before the partials are summed, so
+  // that their memory latencies overlap (a stopped expansion still returns here)
+  CtrlSnap snap;
+  snap.state = fin.ctrl->state;
+  snap.rho_next = fin.ctrl->rho_next;
+  snap.tau = fin.ctrl->tau;
+  snap.eta = fin.ctrl->eta;
+  const bool qstep = fin.qr && (fin.kind == FIN_STEP || fin.kind == FIN_FALLBACK);
+  if (qstep)
+    for (int i = threadIdx.x; i < J; i += (int)blockDim.x) sprev[i] = fin.Sprev[i];
+  partial_sum(gr.P1, gr.ldp, gr.G, V, red, sp);   // ends with a barrier
+  if (snap.state != ST_RUNNING) return;
   if (fin.rec && fin.kind == FIN_STEP)
     for (int v = threadIdx.x; v < V; v += (int)blockDim.x) fin.rec[v] = red[v];
-  finalize(fin, red, T, scratch);
+  finalize(fin, snap, red, T, scratch, qstep ? sprev : fin.Sprev);
 }
 
 
@@ -599,9 +643,10 @@ __device__ void finish_body(const GridRed& gr, int V, const FinArgs& fin, int J)
 //   [0, Jt)   = [Q, x]^T x                                      (Jt = J + 1)
 //
 // XS: where x and y come from -- 0 the vectors, 1 the vectors, also copied into the
-// workgroup's LDS slab sx, sy (unit u at index u - u0), 2 that LDS copy.  Each thread
-// copies and later reads back the same units, so the copy needs no barrier.  x, y
-// themselves serve the odd last row.
+// workgroup's LDS slab sx, sy (unit u at index u - u0), 2 that LDS copy, 3 yf (x and
+// y = A x of the unit, y stored by yf), also copied into the slab.  Each thread copies
+// and later reads back the same units, so the copy needs no barrier.  x, y themselves
+// serve the odd last row.
 // A reduction without its own y (never called).
 struct NoY {
   template <int VW>

@@ -733,6 +733,15 @@ hipError_t launch_finish(const GridRed& gr, int V, int J, const FinArgs& fin, hi
   if (e != hipSuccess) return e;
   if (mid && (e = hipEventRecord(mid, s)) != hipSuccess) return e;
   const int Jf = J > fin.J ? J : fin.J;
+  // long bases need more than the default dynamic LDS limit (about 90 KB at
+  // J = DCGS2_MAX_N); a refusal is cleared here and shows as that launch's error
+  static std::once_flag once;
+  std::call_once(once, [] {
+    const int most = (int)finish_smem(2 * (DCGS2_MAX_N + 3), DCGS2_MAX_N + 1);
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&finish_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, most) != hipSuccess)
+      (void)hipGetLastError();
+  });
   finish_kernel<<<1, FINISH_BS, finish_smem(V, Jf), s>>>(gr, V, Jf, fin);
   return hipGetLastError();
 }
@@ -754,8 +763,10 @@ template <int VW, typename T>
 void allow_mv_lds() {
   static std::once_flag once;
   std::call_once(once, [] {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&reduce_mv_kernel<VW, T>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)reduce_lds_cap());
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&reduce_mv_kernel<VW, T>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)reduce_lds_cap()) !=
+        hipSuccess)
+      (void)hipGetLastError();            // shows as the launch's error instead
   });
 }
 }  // namespace
@@ -766,8 +777,10 @@ template <int VW, bool HY, typename T>
 void allow_staged_lds() {
   static std::once_flag once;
   std::call_once(once, [] {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&reduce_kernel<VW, HY, T, true>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)reduce_lds_cap());
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&reduce_kernel<VW, HY, T, true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)reduce_lds_cap()) !=
+        hipSuccess)
+      (void)hipGetLastError();            // shows as the launch's error instead
   });
 }
 
