@@ -17,6 +17,7 @@
 #include <math.h>
 
 #include "internal.h"
+#include "std2x2.h"
 
 namespace dcgs2 {
 namespace {
@@ -421,60 +422,9 @@ __device__ void s_rot_cols(const LMat& A, int i, int r0, int r1, double cs, doub
 
 __device__ __forceinline__ void dswap(double& a, double& b) { const double t = a; a = b; b = t; }
 
-// Standard form of a real 2x2 block (scalar), the same steps as std2x2 in schur.cpp:
-// a rotation through half the angle between the symmetric traceless part's vector
-// (t, s) and its target ((+-sqrt(delta), r) for real eigenvalues, (0, +-rho) for a
-// complex pair), M' = G^T M G formed explicitly, c' = 0 or a' = d' set exactly.
-__device__ void s_std2x2(double& a, double& b, double& c, double& d, double& cs, double& sn) {
-  cs = 1.0;
-  sn = 0.0;
-  for (int pass = 0; pass < 2 && c != 0.0; ++pass) {
-    const double m = 0.5 * (a + d), t = 0.5 * (a - d);
-    const double s = 0.5 * (b + c), r = 0.5 * (b - c);
-    const double rho = hypot(t, s);
-    const double delta = t * t + b * c;
-    double tp, sp;
-    if (delta >= 0.0) {
-      tp = copysign(sqrt(delta), t);
-      sp = r;
-    } else {
-      tp = 0.0;
-      sp = copysign(rho, s);
-    }
-    double gc = 1.0, gs = 0.0;
-    if (rho > 0.0) {
-      const double cd = (t * tp + s * sp) / (rho * rho);
-      const double sd = (s * tp - t * sp) / (rho * rho);
-      if (cd >= 0.0) {
-        gc = sqrt(0.5 * (1.0 + cd));
-        gs = sd / (2.0 * gc);
-      } else {
-        gs = copysign(sqrt(0.5 * (1.0 - cd)), sd);
-        gc = sd / (2.0 * gs);
-      }
-    }
-    const double ua = gc * a + gs * c, ub = gc * b + gs * d;
-    const double la = -gs * a + gc * c, lb = -gs * b + gc * d;
-    a = ua * gc + ub * gs;
-    b = -ua * gs + ub * gc;
-    c = la * gc + lb * gs;
-    d = -la * gs + lb * gc;
-    if (delta >= 0.0) {
-      c = 0.0;
-    } else {
-      a = m;
-      d = m;
-    }
-    const double ncs = cs * gc - sn * gs;
-    sn = sn * gc + cs * gs;
-    cs = ncs;
-    if (delta < 0.0 && b != 0.0 && signbit(b) != signbit(c)) break;
-  }
-}
-
 __device__ void s_standardize(int p, const LMat& T, const LMat& Z, int i) {
   double a = T(i, i), b = T(i, i + 1), c = T(i + 1, i), d = T(i + 1, i + 1), cs, sn;
-  s_std2x2(a, b, c, d, cs, sn);
+  std2x2(a, b, c, d, cs, sn);
   wsync();
   if (i + 2 <= p - 1) s_rot_rows(T, i, i + 2, p - 1, cs, sn);
   if (i >= 1) s_rot_cols(T, i, 0, i - 1, cs, sn);
