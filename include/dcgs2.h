@@ -131,7 +131,8 @@ int dcgs2_set_qr_schedule(dcgs2_ctx ctx, int one_pass);
  *  DCGS2_TUNE_FUSED_WAVES : wavefronts per workgroup of the one-pass QR kernel,
  *                           8 or 16 (default 8).
  *  DCGS2_TUNE_REDUCE_GRID : upper bound on the workgroups of a reduction pass,
- *                           1..1024, or 0 for automatic (default: at most 256).
+ *                           1..1024, or 0 for automatic (default: one per CU with
+ *                           an FP64 basis, two with FP32).
  *  DCGS2_TUNE_FUSED_MIN_J : one-pass QR schedule: steps whose basis has fewer
  *                           than this many columns run as a separate update and
  *                           reduction pass (same arithmetic per pass, another

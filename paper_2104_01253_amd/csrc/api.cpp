@@ -496,7 +496,7 @@ int setup_expansion(dcgs2_ctx c, Expansion& e, double thresh, double rho = 0.0) 
   if (e.wk.G > 0)
     e.gr.G = e.wk.G;
   else
-    reduce_grid(e.m, c->tune_reduce_gmax, &e.gr.G);
+    reduce_grid(e.m, c->tune_reduce_gmax, e.q32, &e.gr.G);
   e.gr.P1 = e.wk.P1;
   e.gr.ldp = e.wk.ldp;
   CK(launch_init_ctrl(e.wk.ctrl, c->tau, c->eta, thresh, c->stream, rho));

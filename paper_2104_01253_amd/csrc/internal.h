@@ -269,7 +269,7 @@ hipError_t noalloc_scratch(int device, double** out, size_t* doubles);
 int ctx_prepare(dcgs2_ctx c, hipStream_t* stream);
 
 // Grid sizing for the reductions (number of workgroups for m rows).
-void reduce_grid(int64_t m, int gmax, int* G);
+void reduce_grid(int64_t m, int gmax, int q32, int* G);
 constexpr int REDUCE_GMAX = 1024;
 constexpr int BATCH_GMAX = 32;            // reduction workgroups per batched instance
 

@@ -635,15 +635,17 @@ size_t reduce_lds_cap() {
 }  // namespace
 
 // ---------------------------------------------------------------------------------
-void reduce_grid(int64_t m, int gmax, int* G) {
+void reduce_grid(int64_t m, int gmax, int q32, int* G) {
   // one two-row unit per thread and sweep until the cap: short slabs keep the
   // latency chain of a sweep short when m is small
   const int64_t units = (m + 1) / 2;
   int64_t g = (units + (int64_t)BS - 1) / (int64_t)BS;
   if (g < 1) g = 1;
-  // default: at most 256 workgroups (one per CU); measured best for the
-  // 16-column sweeps at m = 2e6 (the tuning knob overrides it)
-  if (g > (gmax > 0 ? gmax : 256)) g = gmax > 0 ? gmax : 256;
+  // default: at most one workgroup per CU with an FP64 basis, two with an FP32 basis
+  // (half the bytes per load, so twice the wavefronts keep as many bytes in flight);
+  // measured best for the 16-column sweeps at m = 2^21 (the tuning knob overrides it)
+  const int cap = gmax > 0 ? gmax : device_cus() * (q32 ? 2 : 1);
+  if (g > cap) g = cap;
   if (g > REDUCE_GMAX) g = REDUCE_GMAX;
   *G = (int)g;
 }
