@@ -195,26 +195,37 @@ def test_arnoldi_reduction_grid_parity(ctx, gmax):
     assert colerr(Q, ref["Q"]) <= TOL
 
 
-@pytest.mark.parametrize("grid,vel", [((32, 32), (10.0, 10.0)), ((31, 29), (3.0, 40.0)),
-                                      ((40, 33, 17), (10.0, 10.0, 10.0)),
-                                      ((128, 128, 128), (10.0, 10.0, 10.0))])
-def test_matvec_fold_and_update_grid_bitwise(ctx, grid, vel):
+@pytest.mark.parametrize("grid,vel,bits,ld", [((32, 32), (10.0, 10.0), 64, None),
+                                              ((31, 29), (3.0, 40.0), 64, None),
+                                              ((40, 33, 17), (10.0, 10.0, 10.0), 64, None),
+                                              ((40, 33, 17), (10.0, 10.0, 10.0), 32, None),
+                                              ((36, 20), (5.0, 1.0), 64, 777),
+                                              ((36, 20), (5.0, 1.0), 32, 780),
+                                              ((128, 128, 128), (10.0, 10.0, 10.0), 64, None),
+                                              ((128, 128, 128), (10.0, 10.0, 10.0), 32, None)])
+def test_matvec_fold_and_update_grid_bitwise(ctx, grid, vel, bits, ld):
     """Launch shapes change no bit: the matvec inside the reduction pass against the
     separate matvec kernel, and update passes over 1, 7, 256 and 65536 slabs, give
-    the same Q and H.  With an even m the folded pass runs (no matvec launches)."""
+    the same Q and H, with an FP64 or FP32 basis and with a padded (odd) leading
+    dimension.  With an even m and an even leading dimension the folded pass runs (no
+    matvec launches)."""
+    torch = torch_cuda()
     op = binding.stencil_op(grid, 1.0, vel)
     m = op.m
     n = 12 if m > 100000 else 30
     r0 = synth.uniform_vector(m, 8)
     runs = {}
     for fold, ugrid in [(1, 0), (0, 0), (1, 1), (1, 7), (0, 256), (1, 65536)]:
-        say(f"arnoldi {grid} fold={fold} update_grid={ugrid}")
+        say(f"arnoldi {grid} bits={bits} ld={ld} fold={fold} update_grid={ugrid}")
         ctx.set_tuning(binding.TUNE_MATVEC_FOLD, fold)
         ctx.set_tuning(binding.TUNE_UPDATE_GRID, ugrid)
         try:
             ctx.profile(True)
             ctx.profile_read(reset=True)
-            Q, H, rc, st = run_arnoldi(ctx, op, r0, n)
+            Qd = binding.colmajor_empty(m, n + 1, ld,
+                                        dtype=torch.float32 if bits == 32 else None)
+            H, rc, st = ctx.arnoldi(op, dev_vector(r0), n, Qd)
+            Q = host(Qd)
             prof = ctx.profile_read(reset=True)
             ctx.profile(False)
         finally:
@@ -222,7 +233,7 @@ def test_matvec_fold_and_update_grid_bitwise(ctx, grid, vel):
             ctx.set_tuning(binding.TUNE_UPDATE_GRID, 0)
         assert rc == 0 and st["reductions"] == n + 2
         spmv = prof.get("spmv", {}).get("launches", 0)
-        if fold == 1 and m % 2 == 0:
+        if fold == 1 and m % 2 == 0 and (ld is None or ld % 2 == 0):
             assert spmv == 0
         if fold == 0:
             assert spmv >= n
