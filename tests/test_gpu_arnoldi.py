@@ -241,3 +241,26 @@ def test_matvec_fold_and_update_grid_bitwise(ctx, grid, vel, bits, ld):
     Q0, H0 = runs[(1, 0)]
     for key, (Q, H) in runs.items():
         assert np.array_equal(Q, Q0) and np.array_equal(H, H0), key
+
+
+def test_arnoldi_longest_basis(ctx):
+    """n = DCGS2_MAX_N (1024 steps) on a 48 x 48 grid (m = 2304): orthogonality and the
+    Arnoldi relation over the whole basis, and the first 64 columns element-wise
+    against the oracle (later columns of so long a Krylov basis are sensitive to
+    rounding far beyond the gate, in any two implementations)."""
+    grid, vel = (48, 48), (10.0, 10.0)
+    A = ops.convection_diffusion(grid, 1.0, vel)
+    op = binding.stencil_op(grid, 1.0, vel)
+    n = binding.MAX_N
+    r0 = synth.normal_vector(A.shape[0], 17)
+    say(f"arnoldi longest basis m={A.shape[0]} n={n}")
+    Q, H, rc, st = run_arnoldi(ctx, op, r0, n)
+    assert rc == 0 and st["reductions"] == n + 2
+    ref = ar.dcgs2_arnoldi(lambda x: A @ x, r0, 64)
+    assert colerr(H[:65, :64], ref["H"][:65, :64]) <= TOL
+    assert colerr(Q[:, :65], ref["Q"][:, :65]) <= TOL
+    loo = loss_of_orthogonality(Q)
+    rre = representation_error(A, Q, H, n)
+    say("loo", loo, "rre", rre)
+    assert loo <= 1e-12
+    assert rre <= 1e-15

@@ -302,3 +302,17 @@ def test_qr_sixteen_wavefront_workgroups(ctx, m, n):
     assert rc == 0 and st["reductions"] == ref["reductions"]
     assert colerr(R, ref["R"]) <= TOL
     assert np.linalg.norm((Q - ref["Q"]) @ ref["R"]) / np.linalg.norm(B) <= TOL
+
+
+def test_qr_longest_basis(ctx):
+    """n = DCGS2_MAX_N (1024 columns, two-pass schedule): the finishing kernel's LDS grows
+    with the basis (about 90 KB at this n)."""
+    m, n = 4000, binding.MAX_N
+    say(f"qr longest basis m={m} n={n}")
+    B = synth.tall_skinny(m, n, 4, seed_g=1100, seed_v=23)
+    ref = gs.dcgs2_qr(B)
+    Q, R, rc, st = run_qr(ctx, B)
+    assert rc == 0 and st["reductions"] == ref["reductions"] == n + 1
+    assert colerr(R, ref["R"]) <= TOL
+    assert np.linalg.norm((Q - ref["Q"]) @ ref["R"]) / np.linalg.norm(B) <= TOL
+    assert loss_of_orthogonality(Q) <= 1e-13
