@@ -666,6 +666,7 @@ __device__ __forceinline__ void reduce_sweep(const TQ* __restrict__ Q, int64_t l
 #pragma unroll
   for (int c = 0; c < NA; ++c) acc[c] = 0.0;
   const TQ* __restrict__ qb = Q + (int64_t)k0 * ldq;
+  // (two units a block width apart per iteration measured slower here, with either basis)
   for (int64_t u = u0 + threadIdx.x; u < u1; u += BS) {
     RV xv, yv;
     if constexpr (XS == 3) {
@@ -872,6 +873,29 @@ __device__ __forceinline__ void update_group(const TQ* __restrict__ Q, int64_t l
   }
 }
 
+// q_{j-1} and w_j of row unit u from its products sc = (Q C)_u and st = (Q T)_u.
+template <int VW, bool ARN, bool QCOL, typename TQ>
+__device__ __forceinline__ void update_finish_unit(double* __restrict__ x,
+                                                   const double* __restrict__ y,
+                                                   const double* __restrict__ ubuf, double alpha,
+                                                   double tJ, TQ* __restrict__ qout, int64_t u,
+                                                   const RowVec<VW>& sc, const RowVec<VW>& st) {
+  const RowVec<VW> xv = RowVec<VW>::load(x, u);
+  const RowVec<VW> yv = RowVec<VW>::load(y, u);
+  RowVec<VW> qc = RowVec<VW>::zero();
+  if (QCOL) qc = RowVec<VW>::load(ubuf, u);
+  RowVec<VW> qn, wn;
+#pragma unroll
+  for (int e = 0; e < VW; ++e) {
+    const double q = stored<TQ>(QCOL ? qc.e[e] / alpha : (xv.e[e] - sc.e[e]) / alpha);
+    const double yt = ARN ? yv.e[e] / alpha : yv.e[e];
+    qn.e[e] = q;
+    wn.e[e] = yt - fma(q, tJ, st.e[e]);
+  }
+  qn.store(qout, u);
+  wn.store(x, u);
+}
+
 // Update of one row unit u: q_{j-1} and w_j.  The basis columns are taken in exact
 // groups of 16, 8, 4, 2 and 1 (J = 16 q + the binary digits of the rest), so that every
 // load of a group is in flight together, as in the reduction sweeps.
@@ -890,20 +914,53 @@ __device__ __forceinline__ void update_unit(const TQ* __restrict__ Q, int64_t ld
   if (k0 + 4 <= J) { update_group<4, VW, TQ>(Q, ldq, k0, u, C, T, sc, st); k0 += 4; }
   if (k0 + 2 <= J) { update_group<2, VW, TQ>(Q, ldq, k0, u, C, T, sc, st); k0 += 2; }
   if (k0 + 1 <= J) update_group<1, VW, TQ>(Q, ldq, k0, u, C, T, sc, st);
-  const RowVec<VW> xv = RowVec<VW>::load(x, u);
-  const RowVec<VW> yv = RowVec<VW>::load(y, u);
-  RowVec<VW> qc = RowVec<VW>::zero();
-  if (QCOL) qc = RowVec<VW>::load(ubuf, u);
-  RowVec<VW> qn, wn;
+  update_finish_unit<VW, ARN, QCOL, TQ>(x, y, ubuf, alpha, tJ, qout, u, sc, st);
+}
+
+// update_group for two row units at once (all 2 NC loads issued before the first use).
+template <int NC, int VW, typename TQ>
+__device__ __forceinline__ void update_group2(const TQ* __restrict__ Q, int64_t ldq, int k0,
+                                              int64_t u, int64_t u2, const double* __restrict__ C,
+                                              const double* __restrict__ T, RowVec<VW>& sc,
+                                              RowVec<VW>& st, RowVec<VW>& sc2, RowVec<VW>& st2) {
+  RowVec<VW> q[NC], q2[NC];
 #pragma unroll
-  for (int e = 0; e < VW; ++e) {
-    const double q = stored<TQ>(QCOL ? qc.e[e] / alpha : (xv.e[e] - sc.e[e]) / alpha);
-    const double yt = ARN ? yv.e[e] / alpha : yv.e[e];
-    qn.e[e] = q;
-    wn.e[e] = yt - fma(q, tJ, st.e[e]);
+  for (int c = 0; c < NC; ++c) {
+    q[c] = RowVec<VW>::load(Q + (int64_t)(k0 + c) * ldq, u);
+    q2[c] = RowVec<VW>::load(Q + (int64_t)(k0 + c) * ldq, u2);
   }
-  qn.store(qout, u);
-  wn.store(x, u);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const double ck = C[k0 + c], tk = T[k0 + c];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+      sc.e[e] = fma(q[c].e[e], ck, sc.e[e]);
+      st.e[e] = fma(q[c].e[e], tk, st.e[e]);
+      sc2.e[e] = fma(q2[c].e[e], ck, sc2.e[e]);
+      st2.e[e] = fma(q2[c].e[e], tk, st2.e[e]);
+    }
+  }
+}
+
+template <int VW, bool ARN, bool QCOL, typename TQ>
+__device__ __forceinline__ void update_unit2(const TQ* __restrict__ Q, int64_t ldq, int J,
+                                             double* __restrict__ x,
+                                             const double* __restrict__ y,
+                                             const double* __restrict__ ubuf,
+                                             const double* __restrict__ C,
+                                             const double* __restrict__ T, double alpha,
+                                             double tJ, TQ* __restrict__ qout, int64_t u,
+                                             int64_t u2) {
+  RowVec<VW> sc = RowVec<VW>::zero(), st = RowVec<VW>::zero();
+  RowVec<VW> sc2 = RowVec<VW>::zero(), st2 = RowVec<VW>::zero();
+  int k0 = 0;
+  for (; k0 + 16 <= J; k0 += 16) update_group2<16, VW, TQ>(Q, ldq, k0, u, u2, C, T, sc, st, sc2, st2);
+  if (k0 + 8 <= J) { update_group2<8, VW, TQ>(Q, ldq, k0, u, u2, C, T, sc, st, sc2, st2); k0 += 8; }
+  if (k0 + 4 <= J) { update_group2<4, VW, TQ>(Q, ldq, k0, u, u2, C, T, sc, st, sc2, st2); k0 += 4; }
+  if (k0 + 2 <= J) { update_group2<2, VW, TQ>(Q, ldq, k0, u, u2, C, T, sc, st, sc2, st2); k0 += 2; }
+  if (k0 + 1 <= J) update_group2<1, VW, TQ>(Q, ldq, k0, u, u2, C, T, sc, st, sc2, st2);
+  update_finish_unit<VW, ARN, QCOL, TQ>(x, y, ubuf, alpha, tJ, qout, u, sc, st);
+  update_finish_unit<VW, ARN, QCOL, TQ>(x, y, ubuf, alpha, tJ, qout, u2, sc2, st2);
 }
 
 // The odd last row of an update with two-row units.
@@ -971,8 +1028,20 @@ __device__ __forceinline__ void update_slab_body(TQ* __restrict__ Q, int64_t ldq
   const int64_t u0 = (int64_t)bid * per;
   const int64_t u1 = min(units, u0 + per);
   TQ* qout = Q + (int64_t)J * ldq;
-  for (int64_t u = u0 + threadIdx.x; u < u1; u += BS)
-    update_unit<VW, ARN, QCOL, TQ>(Q, ldq, J, x, y, ubuf, C, T, alpha, tJ, qout, u);
+  if constexpr (sizeof(TQ) == 4) {
+    // FP32 basis: two row units per iteration, a block width apart, so that a
+    // wavefront has as many bytes in flight as with an FP64 basis (measured faster
+    // there, slower with FP64)
+    for (int64_t u = u0 + threadIdx.x; u < u1; u += 2 * BS) {
+      if (u + BS < u1)
+        update_unit2<VW, ARN, QCOL, TQ>(Q, ldq, J, x, y, ubuf, C, T, alpha, tJ, qout, u, u + BS);
+      else
+        update_unit<VW, ARN, QCOL, TQ>(Q, ldq, J, x, y, ubuf, C, T, alpha, tJ, qout, u);
+    }
+  } else {
+    for (int64_t u = u0 + threadIdx.x; u < u1; u += BS)
+      update_unit<VW, ARN, QCOL, TQ>(Q, ldq, J, x, y, ubuf, C, T, alpha, tJ, qout, u);
+  }
   if (VW == 2 && (m & 1) && bid == nb - 1 && threadIdx.x == 0)
     update_last_row<ARN, QCOL, TQ>(Q, ldq, J, x, y, ubuf, m, C, T, alpha, tJ, qout);
 }
