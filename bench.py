@@ -515,6 +515,9 @@ def main():
         log(f"[bench] learned guess {out['gmres50_learned_guess_256sq']}")
 
     out["roofline"]["achievable"] = calibration(torch)
+    # the dominant kernel against what a plain streaming read reaches on this device
+    out["roofline"]["frac_of_read"] = round(out["roofline"]["achieved"] /
+                                            out["roofline"]["achievable"]["read_gbps"], 4)
     log(f"[bench] calibration {out['roofline']['achievable']}")
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
