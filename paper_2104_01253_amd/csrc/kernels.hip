@@ -238,7 +238,10 @@ __device__ __forceinline__ RawVec<VR, T> load_raw(const T* p, uint32_t off) {
   return r;
 }
 
-template <typename TQ, bool LAST, int FW, int NS, int VR, int PD>
+// XV: the basis columns fit the NS slots but the vectors' products do not (J <= FW NS <
+// J + 3): wavefront 0 accumulates the products of the columns FW NS .. J + 2 (q, w' or
+// a_{j+1}) per lane in LDS and sums them over its lanes at the end.
+template <typename TQ, bool LAST, int FW, int NS, int VR, int PD, bool XV = false>
 __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, int64_t ldq,
                                                            int J, double* __restrict__ w,
                                                            const double* __restrict__ a_cur,
@@ -254,6 +257,7 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
   constexpr int TR = 64 * VR;
   static_assert(NS >= 1 && NS <= FS, "slot count");
   static_assert(PD >= 1, "prefetch depth");
+  static_assert(!XV || !LAST, "the vectors' products past the slots include a_{j+1}");
   using RV = RowVec<VR>;
   extern __shared__ double smem[];
   const int Jt = J + (LAST ? 2 : 3);
@@ -269,6 +273,8 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
   // (c_k, t_k) pairs and read per tile (one broadcast address per wavefront).
   constexpr bool CL = VR == 2 && NS > 11 && !LAST;
   double* cts = va + TR;                  // 2 FMAXCOL: (c_k, t_k), zero for k >= J
+  constexpr int XB = FW * NS;             // XV: first column past the slots
+  double* xacc = cts + 2 * FMAXCOL;       // XV: 6 x 64 lane sums of wavefront 0
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // per-slot column pointers and coefficients (uniform per wavefront; the
@@ -400,6 +406,25 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
         if constexpr (!LAST) ay[sl] = fma(val, aa.e[e], ay[sl]);
       }
     }
+    if constexpr (XV) {
+      if (wv == 0) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const int k = XB + i;
+          if (k < Jt) {                   // uniform; k >= J since J <= XB
+            double sx = xacc[(2 * i) * 64 + lane], sy = xacc[(2 * i + 1) * 64 + lane];
+#pragma unroll
+            for (int e = 0; e < VR; ++e) {
+              const double val = (k == J) ? qq.e[e] : (k == J + 1) ? ww.e[e] : aa.e[e];
+              sx = fma(val, ww.e[e], sx);
+              sy = fma(val, aa.e[e], sy);
+            }
+            xacc[(2 * i) * 64 + lane] = sx;
+            xacc[(2 * i + 1) * 64 + lane] = sy;
+          }
+        }
+      }
+    }
     // (the next tile's part writes follow the second barrier, and its vq writes
     // its first one, so two barriers per tile suffice)
   };
@@ -437,6 +462,12 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
       ts[sl] = k < J ? t : 0.0;
     }
   }
+  if constexpr (XV) {
+    if (wv == 0) {                        // read back by wavefront 0 alone: no barrier
+#pragma unroll
+      for (int i = 0; i < 6; ++i) xacc[i * 64 + lane] = 0.0;
+    }
+  }
   while (tix + (int64_t)PD * gr.G < ntiles) {
     static_for(std::make_integer_sequence<int, PD + 1>{}, [&](auto R) __attribute__((always_inline)) {
       constexpr int r = decltype(R)::value;
@@ -465,7 +496,23 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
     const int idx = transpose_index<NV>(lane);
     const int k = wv + FW * (idx % FS);
     const int rhs = idx / FS;
-    if (k < Jt) gr.P1[(int64_t)blockIdx.x * gr.ldp + rhs * Jt + k] = pv[0];
+    if (k < Jt && (!XV || k < XB)) gr.P1[(int64_t)blockIdx.x * gr.ldp + rhs * Jt + k] = pv[0];
+  }
+  if constexpr (XV) {
+    if (wv == 0) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const int k = XB + i;
+        if (k < Jt) {
+          const double sx = wave_sum(xacc[(2 * i) * 64 + lane]);
+          const double sy = wave_sum(xacc[(2 * i + 1) * 64 + lane]);
+          if (lane == 0) {
+            gr.P1[(int64_t)blockIdx.x * gr.ldp + k] = sx;
+            gr.P1[(int64_t)blockIdx.x * gr.ldp + Jt + k] = sy;
+          }
+        }
+      }
+    }
   }
 }
 
@@ -891,7 +938,7 @@ hipError_t launch_update(void* Q, int q32, int64_t ldq, int J, double* x, const 
 }
 
 size_t fused_qr_smem(int fw, int vr) {
-  return sizeof(double) * ((size_t)fw * 128 * vr + 3 * 64 * vr + 2 * FMAXCOL);
+  return sizeof(double) * ((size_t)fw * 128 * vr + 3 * 64 * vr + 2 * FMAXCOL + 6 * 64);
 }
 
 // Multiprocessors of the current device (cached).
@@ -981,9 +1028,9 @@ hipError_t launch_fused_qr(void* Q, int q32, int64_t ldq, int J, double* w, cons
                                    : ring_limits<float, false, 8, 2>().pd1)
                            : (last ? ring_limits<double, true, 8, 2>().pd1
                                    : ring_limits<double, false, 8, 2>().pd1);
-  const bool pair = F == 8 && ns <= pair_max_ns && ns <= pair_fit && (m % 2 == 0) &&
-                    aligned_to(Q, q32 ? 8 : 16) && (ldq % 2 == 0) && aligned16(w) &&
-                    aligned16(a_cur) && (last || aligned16(a_next));
+  const bool rows2 = (m % 2 == 0) && aligned_to(Q, q32 ? 8 : 16) && (ldq % 2 == 0) &&
+                     aligned16(w) && aligned16(a_cur) && (last || aligned16(a_next));
+  const bool pair = F == 8 && ns <= pair_max_ns && ns <= pair_fit && rows2;
   // FP32 basis: four rows per lane (one 16-byte load per column) when m and ldq are
   // multiples of four, up to the slot count whose two register stages fit
   const int quad_fit = last ? ring_limits<float, true, 8, 4>().pd1
@@ -1006,6 +1053,23 @@ hipError_t launch_fused_qr(void* Q, int q32, int64_t ldq, int J, double* w, cons
       DCGS2_FQ(float, false, 8, 4);
     }
     if (pair) DCGS2_FQ_V(8, 2);
+    // FP64, one slot beyond the two-row fit, the basis columns within it: the vectors'
+    // products past the slots by wavefront 0 (two-row slots instead of one-row ones)
+    constexpr int NSX = ring_limits<double, false, 8, 2>().pd1;
+    if (!q32 && !last && rows2 && ns == NSX + 1 && J <= 8 * NSX && pair_max_ns > NSX) {
+      const int64_t ntiles = (m / 2 + 63) / 64;
+      int64_t g = device_cus();
+      if (gmax > 0 && g > gmax) g = gmax;
+      if (g > REDUCE_GMAX) g = REDUCE_GMAX;
+      if (g > ntiles) g = ntiles;
+      GridRed gx = gr;
+      gx.G = (int)(g < 1 ? 1 : g);
+      constexpr int PDX = ring_depth<double, false, 8, 2, NSX>();
+      fused_qr_kernel<double, false, 8, NSX, 2, PDX, true>
+          <<<gx.G, 8 * 64, fused_qr_smem(8, 2), s>>>((double*)Q, ldq, J, w, a_cur, a_next, m,
+                                                    coef, ldc, gx, fin);
+      return launch_finish(gx, 2 * Jt, J, fin, mid, s);
+    }
     DCGS2_FQ_V(8, 1);
   }
   DCGS2_FQ_V(16, 1);

@@ -316,3 +316,16 @@ def test_qr_longest_basis(ctx):
     assert colerr(R, ref["R"]) <= TOL
     assert np.linalg.norm((Q - ref["Q"]) @ ref["R"]) / np.linalg.norm(B) <= TOL
     assert loss_of_orthogonality(Q) <= 1e-13
+
+
+@pytest.mark.parametrize("m", [20012, 4096])
+def test_qr_vector_products_past_the_slots(ctx, m):
+    """J = 94..96 at n = 100 (FP64, two-row slots): the basis fits twelve slots per
+    wavefront but q, w' and a_{j+1} do not; wavefront 0 forms their products."""
+    B = synth.tall_skinny(m, 100, 6, seed_g=1200 + m, seed_v=29)
+    ref = gs.dcgs2_qr(B)
+    Q, R, rc, st = run_qr(ctx, B)
+    assert rc == 0 and st["reductions"] == ref["reductions"]
+    assert colerr(R, ref["R"]) <= TOL
+    assert np.linalg.norm((Q - ref["Q"]) @ ref["R"]) / np.linalg.norm(B) <= TOL
+    assert loss_of_orthogonality(Q) <= 1e-13
