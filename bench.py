@@ -332,7 +332,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the path would shard by row blocks with one small all-reduce per step); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
