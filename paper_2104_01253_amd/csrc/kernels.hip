@@ -179,15 +179,18 @@ __global__ __launch_bounds__(BS) void update_slab_kernel(TQ* __restrict__ Q, int
 // rows of q_{j-1} and w_j produced by the update can be dotted at once:
 //   q = (w - Q C)/alpha,  w' = a_j - Q T_{1:J} - q T_J          (update, step j)
 //   [Q_{0..J-1}, q, w', a_{j+1}]^T [w', a_{j+1}]                 (reduction, step j+1)
-// A workgroup of FW wavefronts walks tiles of 64 rows (lane = row).  Column k of
-// [Q, q, w', a_{j+1}] belongs to wavefront k mod FW, slot k / FW; NS = the number
-// of slots in use is a template parameter, so the tile's loads of a wavefront are
-// unconditional (slots past the basis read a valid column and discard it) and are
-// all in flight together.  The wavefronts form partial Q C and Q T from their
-// slots, wavefronts 0..VR-1 combine them in a fixed order and publish q, w', a_{j+1}
-// of the tile through LDS, and every lane then accumulates its rows' products
-// for its slots in registers across all tiles; one transposed butterfly per
-// wavefront at the end yields the workgroup partials.
+// A workgroup of FW wavefronts walks tiles of 64 rows (lane = row).  Basis column k
+// belongs to wavefront k mod FW, slot k / FW; NS = ceil(J / FW) slots (at least one)
+// is a template parameter, so the tile's loads of a wavefront are unconditional and
+// all in flight together.  Every slot but the last of a wavefront holds a basis
+// column; the last one does when wv + FW (NS - 1) < J, and otherwise reads one
+// cache line and contributes zero.  The wavefronts form partial Q C and Q T from
+// their slots, wavefronts 0..VR-1 combine them in a fixed order and publish q, w',
+// a_{j+1} of the tile through LDS, and every lane then accumulates its rows'
+// products for its slots in registers across all tiles; wavefronts 0, 1 and 2 also
+// accumulate those of q, w' and a_{j+1} (one vector each).  One transposed butterfly
+// per wavefront (a plain wavefront sum for the vectors) at the end yields the
+// workgroup partials.
 // LAST: a_{j+1} does not exist (the CGS2 finish of the last column); only
 // [Q_{0..J-1}, q, w']^T w' is reduced.
 constexpr int FMAXCOL = 128;             // J + 3 <= FMAXCOL basis + vector columns
@@ -238,10 +241,7 @@ __device__ __forceinline__ RawVec<VR, T> load_raw(const T* p, uint32_t off) {
   return r;
 }
 
-// XV: the basis columns fit the NS slots but the vectors' products do not (J <= FW NS <
-// J + 3): wavefront 0 accumulates the products of the columns FW NS .. J + 2 (q, w' or
-// a_{j+1}) per lane in LDS and sums them over its lanes at the end.
-template <typename TQ, bool LAST, int FW, int NS, int VR, int PD, bool XV = false>
+template <typename TQ, bool LAST, int FW, int NS, int VR, int PD>
 __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, int64_t ldq,
                                                            int J, double* __restrict__ w,
                                                            const double* __restrict__ a_cur,
@@ -255,9 +255,10 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
   constexpr int FS = FMAXCOL / FW;        // slot capacity per wavefront (power of two)
   constexpr int NV = LAST ? FS : 2 * FS;  // products reduced per wavefront
   constexpr int TR = 64 * VR;
+  constexpr int NVEC = LAST ? 2 : 3;      // q, w' (, a_{j+1}): one per wavefront 0..NVEC-1
   static_assert(NS >= 1 && NS <= FS, "slot count");
   static_assert(PD >= 1, "prefetch depth");
-  static_assert(!XV || !LAST, "the vectors' products past the slots include a_{j+1}");
+  static_assert(FW >= NVEC && FW >= VR, "wavefronts");
   using RV = RowVec<VR>;
   extern __shared__ double smem[];
   const int Jt = J + (LAST ? 2 : 3);
@@ -266,17 +267,17 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
   // the partial (Q C for c = 0, Q T for c = 1) of row element e of the lane
   double* part = smem;                    // FW * TR * 2 partials
   double* vq = part + FW * TR * 2;        // q, w', a_{j+1} of the tile rows: [e 64 + lane]
-  double* vw = vq + TR;
+  double* vw = vq + TR;                   // (consecutive: vector i starts at vq + i TR)
   double* va = vw + TR;
   // With more than 11 two-row slots per wavefront (not the last column) the per-slot
   // coefficients do not fit in registers beside the ring: they are kept in LDS as
   // (c_k, t_k) pairs and read per tile (one broadcast address per wavefront).
   constexpr bool CL = VR == 2 && NS > 11 && !LAST;
   double* cts = va + TR;                  // 2 FMAXCOL: (c_k, t_k), zero for k >= J
-  constexpr int XB = FW * NS;             // XV: first column past the slots
-  double* xacc = cts + 2 * FMAXCOL;       // XV: 6 x 64 lane sums of wavefront 0
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // the wavefront's last slot holds a basis column (uniform)
+  const bool lastlive = wv + FW * (NS - 1) < J;
   // per-slot column pointers and coefficients (uniform per wavefront; the
   // coefficients are read once the first tiles' loads are in flight)
   const TQ* colp[NS];
@@ -292,6 +293,7 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
   double ax[NS], ay[NS];
 #pragma unroll
   for (int sl = 0; sl < NS; ++sl) { ax[sl] = 0.0; ay[sl] = 0.0; }
+  double bx = 0.0, by = 0.0;              // vector wv's products (wavefronts < NVEC)
 
   // Prefetch ring: PD + 1 register stages, tile t + PD G is loaded while tile t is
   // processed.  The ring is walked by a loop unrolled PD + 1 times, so each stage
@@ -310,11 +312,11 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
     const uint32_t off = (uint32_t)ul * (uint32_t)(VR * sizeof(TQ));
     // Every wavefront issues the same loads, so that all of them have the same
     // number in flight and the waits for a stage are exact.  Loads whose values are
-    // not used (slots past the basis, the vectors outside wavefronts 0..VR-1) read the
-    // first element of their array in every lane: one cache line, not a tile.
+    // not used (a last slot past the basis, the vectors outside wavefronts 0..VR-1)
+    // read the first element of their array in every lane: one cache line, not a tile.
 #pragma unroll
     for (int sl = 0; sl < NS; ++sl)
-      S.q[sl] = load_raw<VR>(colp[sl], wv + FW * sl < J ? off : 0u);
+      S.q[sl] = load_raw<VR>(colp[sl], (sl + 1 < NS || lastlive) ? off : 0u);
     // wavefront e < VR combines row element e of the lanes' units: it loads only that
     // element of each vector (the VR wavefronts together read whole cache lines)
     const uint32_t offv =
@@ -331,21 +333,21 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
     for (int e = 0; e < VR; ++e) { sc[e] = 0.0; st[e] = 0.0; }
 #pragma unroll
     for (int sl = 0; sl < NS; ++sl) {
-      if (wv + FW * sl < J) {             // uniform: a discarded slot may hold anything
-        double c, t;
-        if constexpr (CL) {
-          c = cts[2 * (wv + FW * sl)];
-          t = cts[2 * (wv + FW * sl) + 1];
-        } else {
-          c = cs[sl];
-          t = ts[sl];
-        }
+      double c, t;                        // zero past the basis
+      if constexpr (CL) {
+        c = cts[2 * (wv + FW * sl)];
+        t = cts[2 * (wv + FW * sl) + 1];
+      } else {
+        c = cs[sl];
+        t = ts[sl];
+      }
 #pragma unroll
-        for (int e = 0; e < VR; ++e) {
-          const double qx = (double)S.q[sl].e[e];
-          sc[e] = fma(qx, c, sc[e]);
-          st[e] = fma(qx, t, st[e]);
-        }
+      for (int e = 0; e < VR; ++e) {
+        double qx = (double)S.q[sl].e[e];
+        // a last slot past the basis holds whatever Q[0, .] holds: an exact zero instead
+        if (sl + 1 == NS) qx = lastlive ? qx : 0.0;
+        sc[e] = fma(qx, c, sc[e]);
+        st[e] = fma(qx, t, st[e]);
       }
     }
 #pragma unroll
@@ -380,49 +382,34 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
       va[r] = ao;
     }
     lds_barrier();
-    RV qq, ww, aa;
+    RV ww, aa;
 #pragma unroll
     for (int e = 0; e < VR; ++e) {
-      qq.e[e] = vq[e * 64 + lane];
       ww.e[e] = vw[e * 64 + lane];
-      aa.e[e] = va[e * 64 + lane];
+      aa.e[e] = LAST ? 0.0 : va[e * 64 + lane];
     }
 
 #pragma unroll
     for (int sl = 0; sl < NS; ++sl) {
-      const int k = wv + FW * sl;
 #pragma unroll
       for (int e = 0; e < VR; ++e) {
         // four-row slots: the basis element is widened to FP64 again here rather than
         // kept widened across the tile's barriers (which would hold eight more registers
-        // per slot); the empty asm only hides the earlier conversion from the compiler
+        // per slot); the empty asm only hides the earlier conversion from the compiler.
+        // (The products of a last slot past the basis are never stored.)
         TQ qraw = S.q[sl].e[e];
         if constexpr (VR == 4) asm volatile("" : "+v"(qraw));
-        const double val = (k < J) ? (double)qraw
-                           : (k == J) ? qq.e[e]
-                           : (k == J + 1) ? ww.e[e]
-                           : (!LAST && k == J + 2) ? aa.e[e] : 0.0;
+        const double val = (double)qraw;
         ax[sl] = fma(val, ww.e[e], ax[sl]);
         if constexpr (!LAST) ay[sl] = fma(val, aa.e[e], ay[sl]);
       }
     }
-    if constexpr (XV) {
-      if (wv == 0) {
+    if (wv < NVEC) {                      // uniform
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          const int k = XB + i;
-          if (k < Jt) {                   // uniform; k >= J since J <= XB
-            double sx = xacc[(2 * i) * 64 + lane], sy = xacc[(2 * i + 1) * 64 + lane];
-#pragma unroll
-            for (int e = 0; e < VR; ++e) {
-              const double val = (k == J) ? qq.e[e] : (k == J + 1) ? ww.e[e] : aa.e[e];
-              sx = fma(val, ww.e[e], sx);
-              sy = fma(val, aa.e[e], sy);
-            }
-            xacc[(2 * i) * 64 + lane] = sx;
-            xacc[(2 * i + 1) * 64 + lane] = sy;
-          }
-        }
+      for (int e = 0; e < VR; ++e) {
+        const double val = vq[wv * TR + e * 64 + lane];
+        bx = fma(val, ww.e[e], bx);
+        if constexpr (!LAST) by = fma(val, aa.e[e], by);
       }
     }
     // (the next tile's part writes follow the second barrier, and its vq writes
@@ -462,12 +449,6 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
       ts[sl] = k < J ? t : 0.0;
     }
   }
-  if constexpr (XV) {
-    if (wv == 0) {                        // read back by wavefront 0 alone: no barrier
-#pragma unroll
-      for (int i = 0; i < 6; ++i) xacc[i * 64 + lane] = 0.0;
-    }
-  }
   while (tix + (int64_t)PD * gr.G < ntiles) {
     static_for(std::make_integer_sequence<int, PD + 1>{}, [&](auto R) __attribute__((always_inline)) {
       constexpr int r = decltype(R)::value;
@@ -496,22 +477,14 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
     const int idx = transpose_index<NV>(lane);
     const int k = wv + FW * (idx % FS);
     const int rhs = idx / FS;
-    if (k < Jt && (!XV || k < XB)) gr.P1[(int64_t)blockIdx.x * gr.ldp + rhs * Jt + k] = pv[0];
+    if (k < J) gr.P1[(int64_t)blockIdx.x * gr.ldp + rhs * Jt + k] = pv[0];
   }
-  if constexpr (XV) {
-    if (wv == 0) {
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const int k = XB + i;
-        if (k < Jt) {
-          const double sx = wave_sum(xacc[(2 * i) * 64 + lane]);
-          const double sy = wave_sum(xacc[(2 * i + 1) * 64 + lane]);
-          if (lane == 0) {
-            gr.P1[(int64_t)blockIdx.x * gr.ldp + k] = sx;
-            gr.P1[(int64_t)blockIdx.x * gr.ldp + Jt + k] = sy;
-          }
-        }
-      }
+  if (wv < NVEC) {
+    const double sx = wave_sum(bx);
+    const double sy = LAST ? 0.0 : wave_sum(by);
+    if (lane == 0) {
+      gr.P1[(int64_t)blockIdx.x * gr.ldp + J + wv] = sx;
+      if (!LAST) gr.P1[(int64_t)blockIdx.x * gr.ldp + Jt + J + wv] = sy;
     }
   }
 }
@@ -938,7 +911,7 @@ hipError_t launch_update(void* Q, int q32, int64_t ldq, int J, double* x, const 
 }
 
 size_t fused_qr_smem(int fw, int vr) {
-  return sizeof(double) * ((size_t)fw * 128 * vr + 3 * 64 * vr + 2 * FMAXCOL + 6 * 64);
+  return sizeof(double) * ((size_t)fw * 128 * vr + 3 * 64 * vr + 2 * FMAXCOL);
 }
 
 // Multiprocessors of the current device (cached).
@@ -969,12 +942,12 @@ struct RingLimits {
 };
 template <typename T, bool L, int F, int VR>
 constexpr RingLimits ring_limits() {
-  if constexpr (F == 16) return RingLimits{0, 0, 0, 5};
-  if constexpr (VR == 4) return L ? RingLimits{3, 4, 7, 13} : RingLimits{1, 3, 6, 11};
-  if constexpr (sizeof(T) == 8 && VR == 2) return L ? RingLimits{2, 3, 7, 13} : RingLimits{2, 3, 5, 12};
-  if constexpr (sizeof(T) == 8) return L ? RingLimits{8, 11, 15, 16} : RingLimits{6, 8, 12, 16};
-  if constexpr (VR == 2) return L ? RingLimits{5, 7, 10, 16} : RingLimits{4, 6, 8, 14};
-  return L ? RingLimits{10, 14, 16, 16} : RingLimits{8, 11, 15, 16};
+  if constexpr (F == 16) return RingLimits{0, 0, 0, 8};
+  if constexpr (VR == 4) return L ? RingLimits{3, 5, 8, 14} : RingLimits{2, 4, 6, 11};
+  if constexpr (sizeof(T) == 8 && VR == 2) return L ? RingLimits{4, 6, 8, 15} : RingLimits{2, 3, 5, 12};
+  if constexpr (sizeof(T) == 8) return L ? RingLimits{8, 11, 16, 16} : RingLimits{7, 9, 13, 16};
+  if constexpr (VR == 2) return L ? RingLimits{5, 7, 10, 16} : RingLimits{4, 6, 9, 13};
+  return L ? RingLimits{11, 14, 16, 16} : RingLimits{9, 11, 16, 16};
 }
 template <typename T, bool L, int F, int VR, int NS>
 constexpr int ring_depth() {
@@ -982,7 +955,7 @@ constexpr int ring_depth() {
   return NS <= r.pd4 ? 4 : NS <= r.pd3 ? 3 : NS <= r.pd2 ? 2 : 1;
 }
 
-// Dispatch on the slot count NS = ceil(Jt / FW) (compile-time in the kernel).
+// Dispatch on the slot count NS = max(1, ceil(J / FW)) (compile-time in the kernel).
 // One workgroup per CU: measured faster at m = 2e6 than filling each CU to the
 // occupancy of the instantiation (several workgroups per CU for short bases).
 template <typename T, bool L, int F, int VR, int NS>
@@ -1015,10 +988,9 @@ hipError_t launch_fused_qr(void* Q, int q32, int64_t ldq, int J, double* w, cons
                            const double* a_next, int64_t m, const double* coef, int ldc, int last,
                            int fw, int gmax, int pair_max_ns, const GridRed& gr,
                            const FinArgs& fin, hipStream_t s, hipEvent_t mid) {
-  const int Jt = J + (last ? 2 : 3);
-  // 16-wavefront workgroups hold at most 5 slots per wavefront without spilling
-  const int F = (fw == 16 && (Jt + 15) / 16 <= ring_limits<double, false, 16, 1>().pd1) ? 16 : 8;
-  const int ns = (Jt + F - 1) / F;
+  // 16-wavefront workgroups (one-row slots, 128 registers) when the slots fit
+  const int F = (fw == 16 && (J + 15) / 16 <= ring_limits<double, false, 16, 1>().pd1) ? 16 : 8;
+  const int ns = J > 0 ? (J + F - 1) / F : 1;
   if (ns < 1 || ns > FMAXCOL / F) return hipErrorInvalidValue;
   if ((double)m * 8.0 >= 2147483648.0) return hipErrorInvalidValue;  // 32-bit offsets
   // paired rows: m even, every column start 16-byte aligned (8 for an FP32 basis);
@@ -1053,23 +1025,6 @@ hipError_t launch_fused_qr(void* Q, int q32, int64_t ldq, int J, double* w, cons
       DCGS2_FQ(float, false, 8, 4);
     }
     if (pair) DCGS2_FQ_V(8, 2);
-    // FP64, one slot beyond the two-row fit, the basis columns within it: the vectors'
-    // products past the slots by wavefront 0 (two-row slots instead of one-row ones)
-    constexpr int NSX = ring_limits<double, false, 8, 2>().pd1;
-    if (!q32 && !last && rows2 && ns == NSX + 1 && J <= 8 * NSX && pair_max_ns > NSX) {
-      const int64_t ntiles = (m / 2 + 63) / 64;
-      int64_t g = device_cus();
-      if (gmax > 0 && g > gmax) g = gmax;
-      if (g > REDUCE_GMAX) g = REDUCE_GMAX;
-      if (g > ntiles) g = ntiles;
-      GridRed gx = gr;
-      gx.G = (int)(g < 1 ? 1 : g);
-      constexpr int PDX = ring_depth<double, false, 8, 2, NSX>();
-      fused_qr_kernel<double, false, 8, NSX, 2, PDX, true>
-          <<<gx.G, 8 * 64, fused_qr_smem(8, 2), s>>>((double*)Q, ldq, J, w, a_cur, a_next, m,
-                                                    coef, ldc, gx, fin);
-      return launch_finish(gx, 2 * Jt, J, fin, mid, s);
-    }
     DCGS2_FQ_V(8, 1);
   }
   DCGS2_FQ_V(16, 1);
