@@ -414,6 +414,17 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
     }
     // (the next tile's part writes follow the second barrier, and its vq writes
     // its first one, so two barriers per tile suffice)
+    // Keep the stage's last uses above the next issue into the same stage: were the
+    // products sunk below it (towards their next use), the stage's old and new values
+    // would both be live there, the loads would land in other registers, and the
+    // copies back at the loop's back edge would wait for those loads (one tile in
+    // flight, not two).  The empty asm needs the products here, and its memory
+    // clobber keeps the next loads after it.
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+      if constexpr (LAST) asm volatile("" : "+v"(ax[sl]) : : "memory");
+      else asm volatile("" : "+v"(ax[sl]), "+v"(ay[sl]) : : "memory");
+    }
   };
   // Stage s holds tile tix + s G (s < PD) at the top of every round.  A round of
   // PD + 1 tiles runs only when all of them exist, so the loop body has no exits
@@ -934,20 +945,21 @@ namespace {
 // register stages of NS slots fit, with the accumulators, in the registers of a
 // wavefront (256 with 8 wavefronts per workgroup, 128 with 16) without spilling.
 // The limits are the largest NS per depth found free of scratch use by compiling
-// every instantiation for gfx950 (pd1: the largest NS that fits at all).  The FP64
-// limits are kept at those measured fastest for that kernel; deeper rings that also
-// fit measured no faster there.
+// every instantiation for gfx950 (pd1: the largest NS that fits at all), except for
+// the two-row FP64 and four-row FP32 slots of a non-last column: these use the
+// shallower rings measured fastest (the deepest ones that fit, up to PD 4 at seven
+// slots, were slower; shallower still was no faster).
 struct RingLimits {
   int pd4, pd3, pd2, pd1;
 };
 template <typename T, bool L, int F, int VR>
 constexpr RingLimits ring_limits() {
   if constexpr (F == 16) return RingLimits{0, 0, 0, 8};
-  if constexpr (VR == 4) return L ? RingLimits{3, 5, 8, 14} : RingLimits{2, 4, 6, 11};
-  if constexpr (sizeof(T) == 8 && VR == 2) return L ? RingLimits{4, 6, 8, 15} : RingLimits{2, 3, 5, 12};
-  if constexpr (sizeof(T) == 8) return L ? RingLimits{8, 11, 16, 16} : RingLimits{7, 9, 13, 16};
-  if constexpr (VR == 2) return L ? RingLimits{5, 7, 10, 16} : RingLimits{4, 6, 9, 13};
-  return L ? RingLimits{11, 14, 16, 16} : RingLimits{9, 11, 16, 16};
+  if constexpr (VR == 4) return L ? RingLimits{3, 5, 8, 16} : RingLimits{2, 4, 6, 16};
+  if constexpr (sizeof(T) == 8 && VR == 2) return L ? RingLimits{4, 6, 8, 16} : RingLimits{2, 3, 5, 16};
+  if constexpr (sizeof(T) == 8) return L ? RingLimits{15, 16, 16, 16} : RingLimits{12, 15, 16, 16};
+  if constexpr (VR == 2) return L ? RingLimits{13, 16, 16, 16} : RingLimits{10, 12, 14, 16};
+  return RingLimits{16, 16, 16, 16};
 }
 template <typename T, bool L, int F, int VR, int NS>
 constexpr int ring_depth() {
