@@ -32,9 +32,10 @@ def ctx():
 
 
 @pytest.mark.parametrize("one_pass", [True, False])
-# odd m: one-row slots throughout; m = 300,000 (even, aligned columns): two-row slots
+# odd m: one-row slots throughout; m = 300,000 and 6000 (multiples of four, aligned
+# columns): four-row slots, at n = 127 up to sixteen per wavefront (J = 125)
 @pytest.mark.parametrize("m,n,ce", [(1023, 3, 2), (20011, 64, 8), (300001, 100, 8),
-                                    (300000, 100, 8)])
+                                    (300000, 100, 8), (6000, 127, 4)])
 def test_qr_q32_parity(ctx, m, n, ce, one_pass):
     torch = torch_cuda()
     B = synth.tall_skinny(m, n, ce, seed_g=200 + m, seed_v=9)

@@ -275,8 +275,8 @@ def test_qr_reduction_grid_parity(ctx, gmax, m, n, one_pass):
 
 @pytest.mark.parametrize("m,n", [(6000, 126), (6000, 127), (3001, 127), (6000, 128), (2600, 200)])
 def test_qr_one_pass_size_limits(ctx, m, n):
-    """Around the one-pass limit: n = 127 fills all 16 slots of every wavefront (J + 3 =
-    128 columns, one-row slots where two-row ones would spill; odd m), n >= 128 runs the
+    """Around the one-pass limit: n = 127 takes J up to 125, sixteen basis slots per
+    wavefront (two-row slots for even m, one-row slots for odd m); n >= 128 runs the
     two-pass schedule."""
     say(f"qr size limits m={m} n={n}")
     B = synth.tall_skinny(m, n, 4, seed_g=700 + n, seed_v=13)
@@ -290,8 +290,8 @@ def test_qr_one_pass_size_limits(ctx, m, n):
 
 @pytest.mark.parametrize("m,n", [(20011, 40), (20011, 100), (4097, 17)])
 def test_qr_sixteen_wavefront_workgroups(ctx, m, n):
-    """FUSED_WAVES = 16: 16-wavefront workgroups while every wavefront holds at most five
-    slots (J + 3 <= 80), 8-wavefront ones beyond."""
+    """FUSED_WAVES = 16: 16-wavefront workgroups with one-row slots (at most eight basis
+    slots per wavefront)."""
     B = synth.tall_skinny(m, n, 6, seed_g=800 + n, seed_v=17)
     ref = gs.dcgs2_qr(B)
     ctx.set_tuning(binding.TUNE_FUSED_WAVES, 16)
@@ -319,9 +319,10 @@ def test_qr_longest_basis(ctx):
 
 
 @pytest.mark.parametrize("m", [20012, 4096])
-def test_qr_vector_products_past_the_slots(ctx, m):
-    """J = 94..96 at n = 100 (FP64, two-row slots): the basis fits twelve slots per
-    wavefront but q, w' and a_{j+1} do not; wavefront 0 forms their products."""
+def test_qr_last_slot_past_the_basis(ctx, m):
+    """n = 100 (FP64, two-row slots): for J not a multiple of eight a wavefront's last slot
+    lies past the basis and must contribute exactly zero; wavefronts 0, 1 and 2 form the
+    products of q, w' and a_{j+1}; J = 89..97 hold twelve and thirteen slots."""
     B = synth.tall_skinny(m, 100, 6, seed_g=1200 + m, seed_v=29)
     ref = gs.dcgs2_qr(B)
     Q, R, rc, st = run_qr(ctx, B)
