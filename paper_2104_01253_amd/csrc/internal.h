@@ -153,7 +153,7 @@ hipError_t launch_fused_qr(void* Q, int q32, int64_t ldq, int J, double* w, cons
 // fw: wavefronts per workgroup (8 or 16); two-row slots are used (when the data
 // allow them) only while the slot count NS <= pair_max_ns.
 int device_cus();                         // multiprocessors of the current device
-constexpr int FUSED_QR_MAX_J = 125;       // J + 3 basis and vector columns <= 128
+constexpr int FUSED_QR_MAX_J = 125;       // one-pass QR for n <= 127 (J <= 125 basis columns)
 // Q[:, J] = ubuf / alpha (coef[2 ldc]) when ctrl->state == RUNNING.
 hipError_t launch_scale_col(void* Q, int q32, int64_t ldq, int J, const double* ubuf, int64_t m,
                             const double* coef, int ldc, const Ctrl* ctrl, hipStream_t s);

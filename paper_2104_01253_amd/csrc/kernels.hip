@@ -193,7 +193,7 @@ __global__ __launch_bounds__(BS) void update_slab_kernel(TQ* __restrict__ Q, int
 // workgroup partials.
 // LAST: a_{j+1} does not exist (the CGS2 finish of the last column); only
 // [Q_{0..J-1}, q, w']^T w' is reduced.
-constexpr int FMAXCOL = 128;             // J + 3 <= FMAXCOL basis + vector columns
+constexpr int FMAXCOL = 128;             // basis columns per workgroup: FW x (FMAXCOL / FW) slots
 
 // Workgroup barrier for LDS hand-offs only: waits for this wavefront's LDS
 // traffic, not for its outstanding global loads, so the next tile's prefetch
