@@ -270,8 +270,8 @@ __global__ __launch_bounds__(FW * 64) void fused_qr_kernel(TQ* __restrict__ Q, i
   double* vw = vq + TR;                   // (consecutive: vector i starts at vq + i TR)
   double* va = vw + TR;
   // With more than 11 two-row slots per wavefront (not the last column) the per-slot
-  // coefficients do not fit in registers beside the ring: they are kept in LDS as
-  // (c_k, t_k) pairs and read per tile (one broadcast address per wavefront).
+  // coefficients are kept in LDS as (c_k, t_k) pairs and read per tile (one broadcast
+  // address per wavefront), which leaves the scalar and vector registers to the ring.
   constexpr bool CL = VR == 2 && NS > 11 && !LAST;
   double* cts = va + TR;                  // 2 FMAXCOL: (c_k, t_k), zero for k >= J
   const int lane = threadIdx.x & 63;
