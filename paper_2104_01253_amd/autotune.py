@@ -18,7 +18,7 @@ from . import binding
 
 CANDIDATES = {
     binding.TUNE_REDUCE_GRID: (0, 512, 1024),
-    binding.TUNE_FUSED_MIN_J: (0, 8, 16, 24),
+    binding.TUNE_FUSED_MIN_J: (0, 4, 8, 16),
     binding.TUNE_FUSED_PAIR_SLOTS: (16, 8, 5, 0),
 }
 
