@@ -43,9 +43,13 @@ def _time(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def tune(ctx: "binding.Context", fn, reps: int = 2, candidates=None, verbose=False):
+def tune(ctx: "binding.Context", fn, reps: int = 2, candidates=None, verbose=False,
+         refine: int = 0, refine_reps: int = 5):
     """Try every combination of the knobs, leave the fastest set on ctx and return
-    (settings dict, best ms, all timings)."""
+    (settings dict, best ms, all timings).  With refine > 1 the `refine` fastest
+    combinations of the sweep are timed again over `refine_reps` calls each and the
+    fastest of those is kept, so that run-to-run noise of a short sweep does not pick
+    the setting."""
     import torch
     cands = candidates or CANDIDATES
     keys = list(cands)
@@ -57,7 +61,17 @@ def tune(ctx: "binding.Context", fn, reps: int = 2, candidates=None, verbose=Fal
         timings.append((dict(zip(keys, combo)), ms))
         if verbose:
             print("autotune", dict(zip(keys, combo)), f"{ms:.3f} ms", flush=True)
-    best, best_ms = min(timings, key=lambda t: t[1])
+    ranked = sorted(timings, key=lambda t: t[1])
+    best, best_ms = ranked[0]
+    if refine > 1:
+        finals = []
+        for settings, _ in ranked[:refine]:
+            for k, v in settings.items():
+                ctx.set_tuning(k, v)
+            finals.append((settings, _time(torch, fn, refine_reps)))
+            if verbose:
+                print("autotune refine", settings, f"{finals[-1][1]:.3f} ms", flush=True)
+        best, best_ms = min(finals, key=lambda t: t[1])
     for k, v in best.items():
         ctx.set_tuning(k, v)
     return best, best_ms, timings
