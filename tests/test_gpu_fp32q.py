@@ -33,9 +33,11 @@ def ctx():
 
 @pytest.mark.parametrize("one_pass", [True, False])
 # odd m: one-row slots throughout; m = 300,000 and 6000 (multiples of four, aligned
-# columns): four-row slots, at n = 127 up to sixteen per wavefront (J = 125)
+# columns): four-row slots, at n = 127 up to sixteen per wavefront (J = 125); m = 64 and
+# 260: four-row slots on a single partial tile, and on a full tile plus one live lane
 @pytest.mark.parametrize("m,n,ce", [(1023, 3, 2), (20011, 64, 8), (300001, 100, 8),
-                                    (300000, 100, 8), (6000, 127, 4)])
+                                    (300000, 100, 8), (6000, 127, 4), (64, 20, 2),
+                                    (260, 30, 2)])
 def test_qr_q32_parity(ctx, m, n, ce, one_pass):
     torch = torch_cuda()
     B = synth.tall_skinny(m, n, ce, seed_g=200 + m, seed_v=9)
